@@ -1,0 +1,971 @@
+/*
+ * FP64 CPU oracle for the per-pixel hot path of DDGI resampling
+ * (Majercik, Mueller, Keller, Nowrouzezahrai, McGuire: "Dynamic Diffuse
+ * Global Illumination Resampling", EGSR 2021).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the HIP implementation; the only
+ * thing both sides see is the seeded input arrays (scene, camera, probe grid)
+ * and the published Philox4x32-10 definition, which each side implements on
+ * its own.
+ *
+ * Style: plain, single-threaded, double precision, no blocking or fusion.
+ * Every pass is written per pixel in the order of the method so that it can
+ * be checked against the paper by eye.  Pixels can be evaluated one by one
+ * (pixel lists) so that full-size frames can be checked on samples.
+ *
+ * Record layouts (all double):
+ *   G-buffer pixel  [14]: pos[3] nrm[3] albedo[3] emit[3] view_depth prim
+ *   reservoir       [14]: y[3] n_y[3] L[3] wsum W M tag prim
+ *   probe textures : irr[P][(Ni+2)^2][3] (E/pi), dep[P][(Nd+2)^2][2] (mean, mean^2)
+ * A reservoir whose sample left the scene stores the direction in y and a
+ * zero normal in n_y.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+
+#define O_MISS 0xFFFFFFFFu
+#define O_PI 3.14159265358979323846
+#define O_INF (1.0 / 0.0)
+
+/* ---------------------------------------------------------------------------
+ * Inputs
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t n_prims;
+    int32_t has_room;
+    const double *prims;            /* n_prims x 16 records (see scene generator) */
+    double room_lo[3], room_hi[3];
+    double wall_albedo[3], wall_emit[3];
+    double sky[3];
+    double eps;                     /* ray-origin offset along the surface normal */
+} o_scene;
+
+typedef struct {
+    double eye[3], fwd[3], right[3], up[3];
+    double tan_half_fovy;
+    int32_t width, height;
+} o_camera;
+
+typedef struct {
+    int32_t dims[3];
+    int32_t irr_res, dep_res;
+    double lo[3], spacing[3];
+    double bias_dist;               /* view-path bias distance d */
+    double var_floor;               /* Chebyshev variance floor */
+    double d_max;                   /* depth clamp for probe rays */
+    const double *irr;
+    const double *dep;
+} o_probes;
+
+typedef struct {
+    int32_t M;                      /* candidates per pixel */
+    int32_t k;                      /* spatial neighbours */
+    int32_t unbiased;               /* 1: 1/Z with visibility; 0: 1/M */
+    int32_t pad;
+    double radius;                  /* spatial radius in pixels */
+    double g_max;                   /* geometry-term bound */
+    double cos_n;                   /* reuse normal threshold */
+    double depth_rel;               /* reuse relative depth threshold */
+    double m_cap;                   /* temporal history cap (multiple of current M) */
+} o_params;
+
+enum { GB_POS = 0, GB_NRM = 3, GB_ALB = 6, GB_EMIT = 9, GB_DEPTH = 12, GB_PRIM = 13, GB_N = 14 };
+enum { R_Y = 0, R_NY = 3, R_L = 6, R_WSUM = 9, R_W = 10, R_M = 11, R_TAG = 12, R_PRIM = 13, R_N = 14 };
+
+/* ---------------------------------------------------------------------------
+ * Small vector helpers
+ * ------------------------------------------------------------------------- */
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static double lum(const double *c) { return 0.2126 * c[0] + 0.7152 * c[1] + 0.0722 * c[2]; }
+static void normalize3(double *v)
+{
+    double l = sqrt(dot3(v, v));
+    v[0] /= l; v[1] /= l; v[2] /= l;
+}
+static double sgn(double v) { return v >= 0.0 ? 1.0 : -1.0; }
+
+/* ---------------------------------------------------------------------------
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+ * multiplications whose high and low halves are crossed and xored with the
+ * key; the key advances by the Weyl constants between rounds.
+ * Counter layout of this method: (pixel or probe, frame, pass, block);
+ * key = (seed low word, seed high word).
+ * ------------------------------------------------------------------------- */
+void o_philox(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out)
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* uniform in [0,1) from the top 24 bits: exactly representable in f32 and f64 */
+static double u01(uint32_t v) { return (double)(v >> 8) * (1.0 / 16777216.0); }
+
+static void rand4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, double *u)
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3}, out[4];
+    o_philox((uint32_t)seed, (uint32_t)(seed >> 32), ctr, out);
+    for (int i = 0; i < 4; ++i) u[i] = u01(out[i]);
+}
+
+enum { PASS_INITIAL = 0, PASS_TEMPORAL = 1, PASS_SPATIAL0 = 2, PASS_PROBE = 9 };
+
+/* ---------------------------------------------------------------------------
+ * Sampling
+ * ------------------------------------------------------------------------- */
+/* Cosine-weighted direction about n (the Lambertian BSDF sampling of step 1,
+ * Sec. 3.1): disk point (sqrt(u1) cos 2pi u0, sqrt(u1) sin 2pi u0), lifted to
+ * the hemisphere, expressed in the orthonormal basis of Duff et al. 2017. */
+void o_cosine_dir(const double *n, double u0, double u1, double *w)
+{
+    double phi = 2.0 * O_PI * u0, r = sqrt(u1);
+    double lx = r * cos(phi), ly = r * sin(phi), lz = sqrt(fmax(0.0, 1.0 - u1));
+    double s = n[2] >= 0.0 ? 1.0 : -1.0;
+    double a = -1.0 / (s + n[2]);
+    double b = n[0] * n[1] * a;
+    double t[3] = {1.0 + s * n[0] * n[0] * a, s * b, -s * n[0]};
+    double bt[3] = {b, s + n[1] * n[1] * a, -n[1]};
+    for (int i = 0; i < 3; ++i) w[i] = lx * t[i] + ly * bt[i] + lz * n[i];
+}
+
+/* Uniform direction on the unit sphere (probe-update rays). */
+void o_sphere_dir(double u0, double u1, double *w)
+{
+    double z = 1.0 - 2.0 * u0, phi = 2.0 * O_PI * u1;
+    double r = sqrt(fmax(0.0, 1.0 - z * z));
+    w[0] = r * cos(phi); w[1] = r * sin(phi); w[2] = z;
+}
+
+/* ---------------------------------------------------------------------------
+ * Ray casting against the analytic scene (brute force, index order).
+ * Hit rule: smallest t > 0 (and < tmax); equal t goes to the lower index;
+ * the room walls follow the primitives with indices n + 2*axis + (hi side).
+ * Normals are geometric and turned to face the incoming ray.
+ * ------------------------------------------------------------------------- */
+typedef struct { double t; uint32_t prim; double n[3]; } o_hit;
+
+static int hit_sphere(const double *rec, const double *o, const double *d, double *t, double *n)
+{
+    double oc[3] = {o[0] - rec[0], o[1] - rec[1], o[2] - rec[2]};
+    double r = rec[4];
+    double b = dot3(oc, d);
+    double c = dot3(oc, oc) - r * r;
+    double disc = b * b - c;
+    if (disc < 0.0) return 0;
+    double s = sqrt(disc);
+    double t0 = -b - s, t1 = -b + s, th;
+    if (t0 > 0.0) th = t0;
+    else if (t1 > 0.0) th = t1;
+    else return 0;
+    *t = th;
+    for (int i = 0; i < 3; ++i) n[i] = (o[i] + th * d[i] - rec[i]) / r;
+    if (dot3(n, d) > 0.0) for (int i = 0; i < 3; ++i) n[i] = -n[i];
+    return 1;
+}
+
+static int hit_box(const double *rec, const double *o, const double *d, double *t, double *n)
+{
+    double tn = -O_INF, tf = O_INF;
+    int an = 0, af = 0;
+    for (int a = 0; a < 3; ++a) {
+        double inv = 1.0 / d[a];
+        double t1 = (rec[a] - rec[4 + a] - o[a]) * inv;
+        double t2 = (rec[a] + rec[4 + a] - o[a]) * inv;
+        double lo = fmin(t1, t2), hi = fmax(t1, t2);
+        if (lo > tn) { tn = lo; an = a; }
+        if (hi < tf) { tf = hi; af = a; }
+    }
+    if (tn > tf) return 0;
+    int axis;
+    if (tn > 0.0) { *t = tn; axis = an; }
+    else if (tf > 0.0) { *t = tf; axis = af; }
+    else return 0;
+    n[0] = n[1] = n[2] = 0.0;
+    n[axis] = -sgn(d[axis]);
+    return 1;
+}
+
+static int hit_room(const o_scene *sc, const double *o, const double *d, double *t, double *n, uint32_t *wall)
+{
+    double best = O_INF;
+    int ba = -1;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) continue;
+        double ta = ((d[a] > 0.0 ? sc->room_hi[a] : sc->room_lo[a]) - o[a]) / d[a];
+        if (ta > 0.0 && ta < best) { best = ta; ba = a; }
+    }
+    if (ba < 0) return 0;
+    *t = best;
+    n[0] = n[1] = n[2] = 0.0;
+    n[ba] = -sgn(d[ba]);
+    *wall = (uint32_t)sc->n_prims + 2u * (uint32_t)ba + (d[ba] > 0.0 ? 1u : 0u);
+    return 1;
+}
+
+static int closest_hit(const o_scene *sc, const double *o, const double *d, double tmax, o_hit *h)
+{
+    h->t = tmax;
+    h->prim = O_MISS;
+    for (int i = 0; i < sc->n_prims; ++i) {
+        const double *rec = sc->prims + 16 * i;
+        uint32_t type = (uint32_t)rec[3];      /* 0 sphere, 1 box */
+        double t, n[3];
+        int ok = type == 0 ? hit_sphere(rec, o, d, &t, n) : hit_box(rec, o, d, &t, n);
+        if (ok && t < h->t) {
+            h->t = t; h->prim = (uint32_t)i;
+            h->n[0] = n[0]; h->n[1] = n[1]; h->n[2] = n[2];
+        }
+    }
+    if (sc->has_room) {
+        double t, n[3];
+        uint32_t wall;
+        if (hit_room(sc, o, d, &t, n, &wall) && t < h->t) {
+            h->t = t; h->prim = wall;
+            h->n[0] = n[0]; h->n[1] = n[1]; h->n[2] = n[2];
+        }
+    }
+    return h->prim != O_MISS;
+}
+
+int o_closest_hit(const o_scene *sc, const double *o, const double *d, double tmax, double *out)
+{
+    o_hit h;
+    int r = closest_hit(sc, o, d, tmax, &h);
+    out[0] = h.t; out[1] = (double)h.prim;
+    out[2] = h.n[0]; out[3] = h.n[1]; out[4] = h.n[2];
+    return r;
+}
+
+static void material(const o_scene *sc, uint32_t prim, double *alb, double *emit)
+{
+    if (prim < (uint32_t)sc->n_prims) {
+        const double *rec = sc->prims + 16 * (size_t)prim;
+        for (int i = 0; i < 3; ++i) { alb[i] = rec[8 + i]; emit[i] = rec[12 + i]; }
+    } else {
+        for (int i = 0; i < 3; ++i) { alb[i] = sc->wall_albedo[i]; emit[i] = sc->wall_emit[i]; }
+    }
+}
+
+/* Mutual visibility V(a, b) of two surface points (each lifted by eps along its
+ * normal), or of a surface point a and the sky in direction b when b_is_dir. */
+int o_visible(const o_scene *sc, const double *a, const double *na, const double *b,
+              const double *nb, int b_is_dir)
+{
+    double o[3], d[3], tmax;
+    for (int i = 0; i < 3; ++i) o[i] = a[i] + sc->eps * na[i];
+    if (b_is_dir) {
+        for (int i = 0; i < 3; ++i) d[i] = b[i];
+        tmax = O_INF;
+    } else {
+        for (int i = 0; i < 3; ++i) d[i] = b[i] + sc->eps * nb[i] - o[i];
+        tmax = sqrt(dot3(d, d));
+        for (int i = 0; i < 3; ++i) d[i] /= tmax;
+    }
+    o_hit h;
+    return !closest_hit(sc, o, d, tmax, &h);
+}
+
+/* ---------------------------------------------------------------------------
+ * Primary vertices (step 1's starting point, Sec. 3.1): one pinhole ray
+ * through each pixel centre; pixel (i, j) has index j*W + i, row 0 at the top.
+ * ------------------------------------------------------------------------- */
+static void camera_ray(const o_camera *c, int i, int j, double *d)
+{
+    double aspect = (double)c->width / (double)c->height;
+    double sx = (2.0 * (i + 0.5) / c->width - 1.0) * c->tan_half_fovy * aspect;
+    double sy = (1.0 - 2.0 * (j + 0.5) / c->height) * c->tan_half_fovy;
+    for (int a = 0; a < 3; ++a) d[a] = c->fwd[a] + sx * c->right[a] + sy * c->up[a];
+    normalize3(d);
+}
+
+void o_gbuffer(const o_scene *sc, const o_camera *cam, const int32_t *pix, int64_t npix, double *gb)
+{
+    int64_t total = (int64_t)cam->width * cam->height;
+    int64_t n = pix ? npix : total;
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        int i = (int)(p % cam->width), j = (int)(p / cam->width);
+        double d[3];
+        camera_ray(cam, i, j, d);
+        double *g = gb + GB_N * p;
+        o_hit h;
+        memset(g, 0, sizeof(double) * GB_N);
+        if (!closest_hit(sc, cam->eye, d, O_INF, &h)) {
+            for (int a = 0; a < 3; ++a) g[GB_EMIT + a] = sc->sky[a];
+            g[GB_PRIM] = (double)O_MISS;
+            continue;
+        }
+        for (int a = 0; a < 3; ++a) {
+            g[GB_POS + a] = cam->eye[a] + h.t * d[a];
+            g[GB_NRM + a] = h.n[a];
+        }
+        material(sc, h.prim, g + GB_ALB, g + GB_EMIT);
+        g[GB_DEPTH] = h.t * dot3(d, cam->fwd);
+        g[GB_PRIM] = (double)h.prim;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Octahedral parameterisation (Cigolle et al. 2014) of gutter-padded square
+ * tiles: N x N interior texels, one gutter texel on every side.
+ * ------------------------------------------------------------------------- */
+void o_oct_encode(const double *v, double *uv)
+{
+    double l1 = fabs(v[0]) + fabs(v[1]) + fabs(v[2]);
+    double px = v[0] / l1, py = v[1] / l1;
+    if (v[2] < 0.0) {
+        double fx = (1.0 - fabs(py)) * sgn(px);
+        double fy = (1.0 - fabs(px)) * sgn(py);
+        px = fx; py = fy;
+    }
+    uv[0] = 0.5 * (px + 1.0);
+    uv[1] = 0.5 * (py + 1.0);
+}
+
+void o_oct_decode(const double *uv, double *v)
+{
+    double px = 2.0 * uv[0] - 1.0, py = 2.0 * uv[1] - 1.0;
+    double z = 1.0 - fabs(px) - fabs(py);
+    if (z < 0.0) {
+        double fx = (1.0 - fabs(py)) * sgn(px);
+        double fy = (1.0 - fabs(px)) * sgn(py);
+        px = fx; py = fy;
+    }
+    v[0] = px; v[1] = py; v[2] = z;
+    normalize3(v);
+}
+
+/* bilinear fetch of a padded tile with C channels at the direction v */
+static void tile_fetch(const double *tile, int N, int C, const double *v, double *out)
+{
+    double uv[2];
+    o_oct_encode(v, uv);
+    int P = N + 2;
+    double fx = uv[0] * N + 0.5, fy = uv[1] * N + 0.5;
+    int x0 = (int)floor(fx), y0 = (int)floor(fy);
+    double ax = fx - x0, ay = fy - y0;
+    for (int c = 0; c < C; ++c) out[c] = 0.0;
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+            double w = (dx ? ax : 1.0 - ax) * (dy ? ay : 1.0 - ay);
+            const double *t = tile + C * ((size_t)(y0 + dy) * P + (x0 + dx));
+            for (int c = 0; c < C; ++c) out[c] += w * t[c];
+        }
+}
+
+void o_tile_fetch(const double *tile, int N, int C, const double *v, double *out)
+{
+    tile_fetch(tile, N, C, v, out);
+}
+
+/* Gutter fill: a border texel repeats the interior texel mirrored along its
+ * edge; a corner repeats the diagonally opposite interior corner.  This makes
+ * bilinear filtering continuous across the octahedral folds. */
+static void fill_gutter(double *tile, int N, int C)
+{
+    int P = N + 2;
+#define T(x, y) (tile + C * ((size_t)(y) * P + (x)))
+    for (int x = 1; x <= N; ++x) {
+        memcpy(T(x, 0), T(N + 1 - x, 1), sizeof(double) * C);
+        memcpy(T(x, N + 1), T(N + 1 - x, N), sizeof(double) * C);
+    }
+    for (int y = 1; y <= N; ++y) {
+        memcpy(T(0, y), T(1, N + 1 - y), sizeof(double) * C);
+        memcpy(T(N + 1, y), T(N, N + 1 - y), sizeof(double) * C);
+    }
+    memcpy(T(0, 0), T(N, N), sizeof(double) * C);
+    memcpy(T(N + 1, 0), T(1, N), sizeof(double) * C);
+    memcpy(T(0, N + 1), T(N, 1), sizeof(double) * C);
+    memcpy(T(N + 1, N + 1), T(1, 1), sizeof(double) * C);
+#undef T
+}
+
+void o_fill_gutter(double *tile, int N, int C) { fill_gutter(tile, N, C); }
+
+/* ---------------------------------------------------------------------------
+ * Probe query Q(p, n) = E(p, n) / pi, the DDGI irradiance cache the paper
+ * builds on (Sec. 2 and Eq. 4): blend of the 8 probes of p's grid cell with
+ * weight = trilinear x smooth backface x Chebyshev visibility from the probe's
+ * depth moments (mean visibility distance, Sec. 3.2), normalised.
+ * flags bit 0 disables the backface term, bit 1 the visibility term.
+ * ------------------------------------------------------------------------- */
+static void probe_pos(const o_probes *pr, const int *idx, double *P)
+{
+    for (int a = 0; a < 3; ++a) P[a] = pr->lo[a] + (idx[a] + 0.5) * pr->spacing[a];
+}
+
+static void probe_query(const o_probes *pr, const double *p, const double *n, int flags, double *out)
+{
+    int base[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        double g = (p[a] - pr->lo[a]) / pr->spacing[a] - 0.5;
+        g = fmin(fmax(g, 0.0), (double)(pr->dims[a] - 1));
+        int b = (int)floor(g);
+        if (b > pr->dims[a] - 2) b = pr->dims[a] - 2;
+        if (b < 0) b = 0;
+        base[a] = b;
+        f[a] = pr->dims[a] >= 2 ? g - b : 0.0;
+    }
+    int Ni = pr->irr_res, Nd = pr->dep_res;
+    size_t irr_tile = (size_t)(Ni + 2) * (Ni + 2) * 3, dep_tile = (size_t)(Nd + 2) * (Nd + 2) * 2;
+    double sum[3] = {0, 0, 0}, wsum = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        int off[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1}, idx[3];
+        double tri = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            idx[a] = base[a] + off[a];
+            if (idx[a] > pr->dims[a] - 1) idx[a] = pr->dims[a] - 1;
+            tri *= off[a] ? f[a] : 1.0 - f[a];
+        }
+        size_t pi = (size_t)idx[0] + (size_t)pr->dims[0] * ((size_t)idx[1] + (size_t)pr->dims[1] * idx[2]);
+        double P[3];
+        probe_pos(pr, idx, P);
+        double to_probe[3] = {P[0] - p[0], P[1] - p[1], P[2] - p[2]};
+        double r = sqrt(dot3(to_probe, to_probe));
+        double back = 0.45, vis = 1.0;
+        if (r > 0.0) {
+            double w[3] = {to_probe[0] / r, to_probe[1] / r, to_probe[2] / r};
+            double h = 0.5 * (1.0 + dot3(n, w));
+            back = h * h + 0.2;
+            double from_probe[3] = {-w[0], -w[1], -w[2]}, mom[2];
+            tile_fetch(pr->dep + pi * dep_tile, Nd, 2, from_probe, mom);
+            if (r > mom[0]) {
+                double var = fmax(mom[1] - mom[0] * mom[0], pr->var_floor);
+                double dd = r - mom[0];
+                double cheb = var / (var + dd * dd);
+                vis = cheb * cheb * cheb;
+            }
+        }
+        if (flags & 1) back = 1.0;
+        if (flags & 2) vis = 1.0;
+        double w = tri * fmax(back * vis, 1e-6);
+        double irr[3];
+        tile_fetch(pr->irr + pi * irr_tile, Ni, 3, n, irr);
+        for (int a = 0; a < 3; ++a) sum[a] += w * irr[a];
+        wsum += w;
+    }
+    for (int a = 0; a < 3; ++a) out[a] = sum[a] / wsum;
+}
+
+void o_probe_query(const o_probes *pr, int64_t n, const double *p, const double *nrm, int flags, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) probe_query(pr, p + 3 * i, nrm + 3 * i, flags, out + 3 * i);
+}
+
+/* View-path self-shadow bias (Sec. 3.4): the query point for a surface point
+ * y reached from x is moved back along the path toward x by min(d, |x-y|/2),
+ * so it never crosses a surface. */
+void o_view_bias(const double *y, const double *x, double d, double *out)
+{
+    double v[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+    double dist = sqrt(dot3(v, v));
+    double s = fmin(d, 0.5 * dist);
+    for (int a = 0; a < 3; ++a) out[a] = y[a] + s * v[a] / dist;
+}
+
+/* Radiance leaving surface point y toward x: L_e(y) + rho_y * Q(y_b, n_y),
+ * i.e. L_DDGI+ of Eq. 4/5 with the diffuse term rho/pi * E = rho * Q. */
+static void radiance_toward(const o_scene *sc, const o_probes *pr, uint32_t prim, const double *y,
+                            const double *ny, const double *x, double *L)
+{
+    double alb[3], emit[3];
+    material(sc, prim, alb, emit);
+    for (int a = 0; a < 3; ++a) L[a] = emit[a];
+    if (alb[0] == 0.0 && alb[1] == 0.0 && alb[2] == 0.0) return;
+    double pb[3], q[3];
+    o_view_bias(y, x, pr->bias_dist, pb);
+    probe_query(pr, pb, ny, 0, q);
+    for (int a = 0; a < 3; ++a) L[a] += alb[a] * q[a];
+}
+
+/* ---------------------------------------------------------------------------
+ * Probe update (Eq. 5, Sec. 3.2): each probe traces R uniform-sphere rays;
+ * a ray that hits h brings L_e(h) + rho_h Q_prev(h_b, n_h) (single-bounce
+ * recursion, emission not diffused), a ray that leaves brings the sky.
+ * Irradiance texel with centre direction n_t takes the cosine-weighted mean
+ * sum max(0, n_t.w) L / sum max(0, n_t.w), which estimates E/pi; depth texel
+ * takes the max(0, n_t.w)^sharpness weighted mean of (d, d^2), d = min(t, d_max).
+ * Stored = hysteresis * old + (1 - hysteresis) * new; then gutters.
+ * Q_prev is read from the input textures only.
+ * ------------------------------------------------------------------------- */
+void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, double *dep_out,
+                    int rays, double hysteresis, double sharpness, uint64_t seed, uint32_t frame,
+                    const int32_t *plist, int64_t nlist)
+{
+    int Ni = in->irr_res, Nd = in->dep_res;
+    int64_t P = (int64_t)in->dims[0] * in->dims[1] * in->dims[2];
+    size_t irr_tile = (size_t)(Ni + 2) * (Ni + 2) * 3, dep_tile = (size_t)(Nd + 2) * (Nd + 2) * 2;
+    int64_t n = plist ? nlist : P;
+    double dirs[4096][3], Ls[4096][3], ds[4096];
+    if (rays > 4096) rays = 4096;
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t pi = plist ? plist[q] : q;
+        int idx[3] = {(int)(pi % in->dims[0]), (int)((pi / in->dims[0]) % in->dims[1]),
+                      (int)(pi / ((int64_t)in->dims[0] * in->dims[1]))};
+        double Pp[3];
+        probe_pos(in, idx, Pp);
+        for (int r = 0; r < rays; ++r) {
+            double u[4];
+            rand4(seed, (uint32_t)pi, frame, PASS_PROBE, (uint32_t)r, u);
+            o_sphere_dir(u[0], u[1], dirs[r]);
+            o_hit h;
+            if (closest_hit(sc, Pp, dirs[r], O_INF, &h)) {
+                double hp[3], alb[3], emit[3];
+                for (int a = 0; a < 3; ++a) hp[a] = Pp[a] + h.t * dirs[r][a];
+                material(sc, h.prim, alb, emit);
+                for (int a = 0; a < 3; ++a) Ls[r][a] = emit[a];
+                if (alb[0] != 0.0 || alb[1] != 0.0 || alb[2] != 0.0) {
+                    double hb[3], qv[3];
+                    o_view_bias(hp, Pp, in->bias_dist, hb);
+                    probe_query(in, hb, h.n, 0, qv);
+                    for (int a = 0; a < 3; ++a) Ls[r][a] += alb[a] * qv[a];
+                }
+                ds[r] = fmin(h.t, in->d_max);
+            } else {
+                for (int a = 0; a < 3; ++a) Ls[r][a] = sc->sky[a];
+                ds[r] = in->d_max;
+            }
+        }
+        const double *iold = in->irr + pi * irr_tile;
+        const double *dold = in->dep + pi * dep_tile;
+        double *inew = irr_out + pi * irr_tile;
+        double *dnew = dep_out + pi * dep_tile;
+        for (int ty = 0; ty < Ni; ++ty)
+            for (int tx = 0; tx < Ni; ++tx) {
+                double uv[2] = {(tx + 0.5) / Ni, (ty + 0.5) / Ni}, nt[3];
+                o_oct_decode(uv, nt);
+                double num[3] = {0, 0, 0}, den = 0.0;
+                for (int r = 0; r < rays; ++r) {
+                    double w = fmax(0.0, dot3(nt, dirs[r]));
+                    for (int a = 0; a < 3; ++a) num[a] += w * Ls[r][a];
+                    den += w;
+                }
+                size_t o = 3 * ((size_t)(ty + 1) * (Ni + 2) + (tx + 1));
+                for (int a = 0; a < 3; ++a) {
+                    double nv = den > 0.0 ? num[a] / den : iold[o + a];
+                    inew[o + a] = hysteresis * iold[o + a] + (1.0 - hysteresis) * nv;
+                }
+            }
+        for (int ty = 0; ty < Nd; ++ty)
+            for (int tx = 0; tx < Nd; ++tx) {
+                double uv[2] = {(tx + 0.5) / Nd, (ty + 0.5) / Nd}, nt[3];
+                o_oct_decode(uv, nt);
+                double m1 = 0.0, m2 = 0.0, den = 0.0;
+                for (int r = 0; r < rays; ++r) {
+                    double w = pow(fmax(0.0, dot3(nt, dirs[r])), sharpness);
+                    m1 += w * ds[r];
+                    m2 += w * ds[r] * ds[r];
+                    den += w;
+                }
+                size_t o = 2 * ((size_t)(ty + 1) * (Nd + 2) + (tx + 1));
+                double n1 = den > 0.0 ? m1 / den : dold[o];
+                double n2 = den > 0.0 ? m2 / den : dold[o + 1];
+                dnew[o] = hysteresis * dold[o] + (1.0 - hysteresis) * n1;
+                dnew[o + 1] = hysteresis * dold[o + 1] + (1.0 - hysteresis) * n2;
+            }
+        fill_gutter(inew, Ni, 3);
+        fill_gutter(dnew, Nd, 2);
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Target function and reuse helpers
+ * ------------------------------------------------------------------------- */
+/* p_hat at shading point (x, n_x, rho_x) for a reservoir sample: the
+ * luminance of the bounded-geometry contribution rho_x/pi * L(y) * min(G, G_max)
+ * (Sec. 3.1 step 2 and Sec. 3.5), using the sample's cached radiance
+ * (query caching, Sec. 3.6).  Sky samples (zero n_y) use G := cos(theta_x). */
+static double target(const double *x, const double *nx, const double *rho, const double *y,
+                     const double *ny, const double *L, double g_max)
+{
+    double f[3] = {rho[0] / O_PI * L[0], rho[1] / O_PI * L[1], rho[2] / O_PI * L[2]};
+    if (ny[0] == 0.0 && ny[1] == 0.0 && ny[2] == 0.0) {
+        double cx = dot3(nx, y);
+        return cx > 0.0 ? lum(f) * cx : 0.0;
+    }
+    double v[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+    double d2 = dot3(v, v), d = sqrt(d2);
+    double w[3] = {v[0] / d, v[1] / d, v[2] / d};
+    double cx = dot3(nx, w), cy = -dot3(ny, w);
+    if (cx <= 0.0 || cy <= 0.0) return 0.0;
+    double G = cx * cy / d2;
+    return lum(f) * fmin(G, g_max);
+}
+
+static double res_target(const double *g, const double *r, double g_max)
+{
+    return target(g + GB_POS, g + GB_NRM, g + GB_ALB, r + R_Y, r + R_NY, r + R_L, g_max);
+}
+
+static int res_is_sky(const double *r)
+{
+    return r[R_NY] == 0.0 && r[R_NY + 1] == 0.0 && r[R_NY + 2] == 0.0;
+}
+
+static int pixel_active(const double *g)
+{
+    return (uint32_t)g[GB_PRIM] != O_MISS &&
+           (g[GB_ALB] != 0.0 || g[GB_ALB + 1] != 0.0 || g[GB_ALB + 2] != 0.0);
+}
+
+static void res_empty(double *r, double M)
+{
+    memset(r, 0, sizeof(double) * R_N);
+    r[R_M] = M;
+    r[R_TAG] = (double)0xFFFFFFFFu;
+    r[R_PRIM] = (double)O_MISS;
+}
+
+static double make_tag(int64_t pixel, int cand, uint32_t frame)
+{
+    uint32_t t = ((uint32_t)(pixel & 0x7FFFFF) << 9) | ((uint32_t)(cand & 31) << 4) | (frame & 15u);
+    return (double)t;
+}
+
+/* geometric similarity test used by temporal and spatial reuse */
+static int similar(const double *g, const double *gq, const o_params *pp)
+{
+    if ((uint32_t)gq[GB_PRIM] == O_MISS) return 0;
+    if (dot3(g + GB_NRM, gq + GB_NRM) < pp->cos_n) return 0;
+    if (fabs(g[GB_DEPTH] - gq[GB_DEPTH]) > pp->depth_rel * g[GB_DEPTH]) return 0;
+    return 1;
+}
+
+/* ---------------------------------------------------------------------------
+ * Initial resampling (Sec. 3.1 steps 1-2, Fig. 2; Sec. 3.5; Sec. 3.6):
+ * M cosine-sampled candidates y_i, converted to area measure, streamed
+ * through a weighted reservoir with w_i = p_hat(y_i) / p_A(y_i), where
+ * p_A = cos(theta_x)/pi * cos(theta_y)/|x-y|^2.  The reservoir keeps the
+ * sample's radiance L(y) (the cached query).  The residual transport with
+ * the unbounded part max(0, G - G_max) is estimated from candidate 0 (the
+ * auxiliary BSDF sample of Sec. 3.5, Eq. 9).
+ * Replacement rule: candidate i replaces the current sample iff
+ * u_2 * wsum < w_i after wsum has been increased by w_i.
+ * ------------------------------------------------------------------------- */
+void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *gb, const o_probes *pr,
+                        const o_params *pp, uint64_t seed, uint32_t frame, const int32_t *pix,
+                        int64_t npix, double *res, double *resid)
+{
+    int64_t n = pix ? npix : (int64_t)W * H;
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        const double *g = gb + GB_N * p;
+        double *r = res + R_N * p, *rs = resid + 3 * p;
+        rs[0] = rs[1] = rs[2] = 0.0;
+        if (!pixel_active(g)) { res_empty(r, 0.0); continue; }
+        const double *x = g + GB_POS, *nx = g + GB_NRM, *rho = g + GB_ALB;
+        double o[3];
+        for (int a = 0; a < 3; ++a) o[a] = x[a] + sc->eps * nx[a];
+        double wsum = 0.0, p_sel = 0.0;
+        int have = 0;
+        res_empty(r, 0.0);
+        for (int i = 0; i < pp->M; ++i) {
+            double u[4], w[3];
+            rand4(seed, (uint32_t)p, frame, PASS_INITIAL, (uint32_t)i, u);
+            o_cosine_dir(nx, u[0], u[1], w);
+            o_hit h;
+            double y[3], ny[3] = {0, 0, 0}, L[3], phat = 0.0, wi = 0.0;
+            uint32_t prim = O_MISS;
+            if (closest_hit(sc, o, w, O_INF, &h)) {
+                for (int a = 0; a < 3; ++a) { y[a] = o[a] + h.t * w[a]; ny[a] = h.n[a]; }
+                prim = h.prim;
+                double v[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+                double d2 = dot3(v, v), d = sqrt(d2);
+                double wv[3] = {v[0] / d, v[1] / d, v[2] / d};
+                double cx = dot3(nx, wv), cy = -dot3(ny, wv);
+                if (cx > 0.0 && cy > 0.0) {
+                    radiance_toward(sc, pr, prim, y, ny, x, L);
+                    double G = cx * cy / d2;
+                    double f[3] = {rho[0] / O_PI * L[0], rho[1] / O_PI * L[1], rho[2] / O_PI * L[2]};
+                    phat = lum(f) * fmin(G, pp->g_max);
+                    double pA = cx / O_PI * cy / d2;
+                    wi = phat / pA;
+                    if (i == 0 && G > pp->g_max)
+                        for (int a = 0; a < 3; ++a) rs[a] = rho[a] * L[a] * (1.0 - pp->g_max / G);
+                }
+            } else {
+                for (int a = 0; a < 3; ++a) { y[a] = w[a]; L[a] = sc->sky[a]; }
+                double cx = dot3(nx, w);
+                if (cx > 0.0) {
+                    double f[3] = {rho[0] / O_PI * L[0], rho[1] / O_PI * L[1], rho[2] / O_PI * L[2]};
+                    phat = lum(f) * cx;
+                    wi = phat / (cx / O_PI);
+                }
+            }
+            wsum += wi;
+            if (u[2] * wsum < wi) {
+                have = 1;
+                p_sel = phat;
+                for (int a = 0; a < 3; ++a) { r[R_Y + a] = y[a]; r[R_NY + a] = ny[a]; r[R_L + a] = L[a]; }
+                r[R_TAG] = make_tag(p, i, frame);
+                r[R_PRIM] = (double)prim;
+            }
+        }
+        r[R_WSUM] = wsum;
+        r[R_M] = (double)pp->M;
+        r[R_W] = (have && p_sel > 0.0) ? wsum / (pp->M * p_sel) : 0.0;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Reservoir merge shared by temporal and spatial reuse (Sec. 3.1 step 2):
+ * candidate reservoir q enters with weight p_hat_x(y_q) * W_q * M_q and
+ * replaces the sample iff u * wsum < w_q.  The normalisation either counts
+ * the M_q of every merged domain whose own target supports the chosen y and
+ * sees it (V traced from x_q), or (biased) all of them.  In the unbiased form
+ * a chosen sample that x itself cannot see is dropped (W = 0, M kept).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double wsum, Msum;
+    const double *sel;
+} merge_state;
+
+static void merge_in(merge_state *s, const double *g, const double *rq, double Mq, double u, double g_max)
+{
+    double w = 0.0;
+    if (rq[R_W] > 0.0 && Mq > 0.0) w = res_target(g, rq, g_max) * rq[R_W] * Mq;
+    s->wsum += w;
+    s->Msum += Mq;
+    if (u * s->wsum < w) s->sel = rq;
+}
+
+static void finish_merge(const o_scene *sc, const merge_state *s, const double *g, int ndom,
+                         const double *const *gdom, const double *Mdom, const o_params *pp, double *out)
+{
+    double tmp[R_N];
+    if (!s->sel) {
+        res_empty(tmp, s->Msum);
+        tmp[R_WSUM] = s->wsum;
+        memcpy(out, tmp, sizeof tmp);
+        return;
+    }
+    memcpy(tmp, s->sel, sizeof tmp);
+    double ph = res_target(g, tmp, pp->g_max);
+    double Z;
+    int keep = 1;
+    if (pp->unbiased) {
+        /* domain 0 is the pixel itself; a sample it cannot see is dropped so
+         * that every reservoir only holds samples visible from its own pixel,
+         * which is the support the next pass's normalisation assumes */
+        int sky = res_is_sky(tmp);
+        int vis_x = o_visible(sc, g + GB_POS, g + GB_NRM, tmp + R_Y, tmp + R_NY, sky);
+        keep = vis_x;
+        Z = 0.0;
+        for (int j = 0; j < ndom; ++j) {
+            const double *gq = gdom[j];
+            if (Mdom[j] <= 0.0) continue;
+            if (res_target(gq, tmp, pp->g_max) <= 0.0) continue;
+            int v = j == 0 ? vis_x : o_visible(sc, gq + GB_POS, gq + GB_NRM, tmp + R_Y, tmp + R_NY, sky);
+            if (!v) continue;
+            Z += Mdom[j];
+        }
+    } else {
+        Z = s->Msum;
+    }
+    tmp[R_WSUM] = s->wsum;
+    tmp[R_M] = s->Msum;
+    tmp[R_W] = (keep && Z > 0.0 && ph > 0.0) ? s->wsum / (Z * ph) : 0.0;
+    memcpy(out, tmp, sizeof tmp);
+}
+
+/* Reprojection of x into a camera: continuous pixel coordinates, floor.
+ * Returns the pixel index or -1 when x is behind the camera or off-screen. */
+int64_t o_reproject(const o_camera *c, const double *x)
+{
+    double v[3] = {x[0] - c->eye[0], x[1] - c->eye[1], x[2] - c->eye[2]};
+    double z = dot3(v, c->fwd);
+    if (z <= 0.0) return -1;
+    double aspect = (double)c->width / (double)c->height;
+    double sx = dot3(v, c->right) / (z * c->tan_half_fovy * aspect);
+    double sy = dot3(v, c->up) / (z * c->tan_half_fovy);
+    double px = (sx + 1.0) * 0.5 * c->width, py = (1.0 - sy) * 0.5 * c->height;
+    double fx = floor(px), fy = floor(py);
+    if (fx < 0.0 || fy < 0.0 || fx >= c->width || fy >= c->height) return -1;
+    return (int64_t)fy * c->width + (int64_t)fx;
+}
+
+/* ---------------------------------------------------------------------------
+ * Temporal reuse (Sec. 3.1 step 2, "among previous frames"; Sec. 3.6 for the
+ * cached radiance): merge the current reservoir with the history reservoir
+ * of the pixel x lands on in the previous camera, if that pixel passes the
+ * normal/depth test; the history's M is capped at m_cap x the current M.
+ * ------------------------------------------------------------------------- */
+void o_resample_temporal(const o_scene *sc, int32_t W, int32_t H, const double *gb, const double *gb_prev,
+                         const o_camera *cam_prev, const double *cur, const double *hist,
+                         const o_params *pp, uint64_t seed, uint32_t frame, const int32_t *pix,
+                         int64_t npix, double *out)
+{
+    int64_t n = pix ? npix : (int64_t)W * H;
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        const double *g = gb + GB_N * p;
+        const double *rc = cur + R_N * p;
+        if (!pixel_active(g)) { memcpy(out + R_N * p, rc, sizeof(double) * R_N); continue; }
+        merge_state s = {0.0, 0.0, NULL};
+        const double *gdom[2];
+        double Mdom[2];
+        int nd = 0;
+        merge_in(&s, g, rc, rc[R_M], 0.0, pp->g_max);
+        gdom[nd] = g; Mdom[nd] = rc[R_M]; ++nd;
+        int64_t pp_idx = o_reproject(cam_prev, g + GB_POS);
+        if (pp_idx >= 0 && similar(g, gb_prev + GB_N * pp_idx, pp)) {
+            const double *rh = hist + R_N * pp_idx;
+            double Mh = fmin(rh[R_M], pp->m_cap * rc[R_M]);
+            double u[4];
+            rand4(seed, (uint32_t)p, frame, PASS_TEMPORAL, 0u, u);
+            merge_in(&s, g, rh, Mh, u[0], pp->g_max);
+            gdom[nd] = gb_prev + GB_N * pp_idx; Mdom[nd] = Mh; ++nd;
+        }
+        finish_merge(sc, &s, g, nd, gdom, Mdom, pp, out + R_N * p);
+    }
+}
+
+/* Neighbour candidate j of pixel p in spatial pass s (before validation):
+ * uniform point in the disk of the given radius, rounded half up. */
+int64_t o_spatial_candidate(int32_t W, int32_t H, int64_t p, int j, double radius, uint64_t seed,
+                            uint32_t frame, int pass, double *u2)
+{
+    double u[4];
+    rand4(seed, (uint32_t)p, frame, (uint32_t)(PASS_SPATIAL0 + pass), (uint32_t)j, u);
+    double rad = radius * sqrt(u[0]), ang = 2.0 * O_PI * u[1];
+    int64_t px = p % W, py = p / W;
+    int64_t qx = px + (int64_t)floor(rad * cos(ang) + 0.5);
+    int64_t qy = py + (int64_t)floor(rad * sin(ang) + 0.5);
+    if (u2) *u2 = u[2];
+    if (qx < 0 || qy < 0 || qx >= W || qy >= H) return -1;
+    if (qx == px && qy == py) return -1;
+    return qy * W + qx;
+}
+
+/* ---------------------------------------------------------------------------
+ * Spatial reuse (Sec. 3.1 step 2, "among neighboring pixels"; Sec. 3.6):
+ * merge the pixel's own reservoir, then k neighbours from a disk that pass
+ * the normal/depth test.  Rejected neighbours are neither counted nor retried.
+ * ------------------------------------------------------------------------- */
+void o_resample_spatial(const o_scene *sc, int32_t W, int32_t H, const double *gb, const double *in,
+                        const o_params *pp, int pass, uint64_t seed, uint32_t frame, const int32_t *pix,
+                        int64_t npix, double *out)
+{
+    int64_t n = pix ? npix : (int64_t)W * H;
+    const double *gdom[16];
+    double Mdom[16];
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        const double *g = gb + GB_N * p;
+        const double *rc = in + R_N * p;
+        if (!pixel_active(g)) { memcpy(out + R_N * p, rc, sizeof(double) * R_N); continue; }
+        merge_state s = {0.0, 0.0, NULL};
+        int nd = 0;
+        merge_in(&s, g, rc, rc[R_M], 0.0, pp->g_max);
+        gdom[nd] = g; Mdom[nd] = rc[R_M]; ++nd;
+        for (int j = 0; j < pp->k && j < 15; ++j) {
+            double u2;
+            int64_t qq = o_spatial_candidate(W, H, p, j, pp->radius, seed, frame, pass, &u2);
+            if (qq < 0) continue;
+            const double *gq = gb + GB_N * qq;
+            if (!similar(g, gq, pp)) continue;
+            const double *rq = in + R_N * qq;
+            merge_in(&s, g, rq, rq[R_M], u2, pp->g_max);
+            gdom[nd] = gq; Mdom[nd] = rq[R_M]; ++nd;
+        }
+        finish_merge(sc, &s, g, nd, gdom, Mdom, pp, out + R_N * p);
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Shading (Sec. 3.1 steps 3-4; Eq. 9): L_o = L_e(x) + bounded term + residual,
+ * bounded term = rho_x/pi * L(y; x) * min(G, G_max) * V(x, y) * W with a fresh
+ * radiance query biased toward this x (the per-vertex query of Sec. 3.6) and
+ * one shadow ray.  A primary ray that left the scene shows the sky.
+ * ------------------------------------------------------------------------- */
+void o_shade(const o_scene *sc, int32_t W, int32_t H, const double *gb, const o_probes *pr,
+             const double *res, const double *resid, const o_params *pp, const int32_t *pix,
+             int64_t npix, double *img)
+{
+    int64_t n = pix ? npix : (int64_t)W * H;
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        const double *g = gb + GB_N * p;
+        const double *r = res + R_N * p;
+        double *o = img + 3 * p;
+        for (int a = 0; a < 3; ++a) o[a] = g[GB_EMIT + a];
+        if ((uint32_t)g[GB_PRIM] == O_MISS) continue;
+        for (int a = 0; a < 3; ++a) o[a] += resid[3 * p + a];
+        if (!(r[R_W] > 0.0)) continue;
+        const double *x = g + GB_POS, *nx = g + GB_NRM, *rho = g + GB_ALB;
+        double L[3], geo;
+        if (res_is_sky(r)) {
+            geo = dot3(nx, r + R_Y);
+            if (geo <= 0.0) continue;
+            if (!o_visible(sc, x, nx, r + R_Y, r + R_NY, 1)) continue;
+            for (int a = 0; a < 3; ++a) L[a] = sc->sky[a];
+        } else {
+            const double *y = r + R_Y, *ny = r + R_NY;
+            double v[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+            double d2 = dot3(v, v), d = sqrt(d2);
+            double w[3] = {v[0] / d, v[1] / d, v[2] / d};
+            double cx = dot3(nx, w), cy = -dot3(ny, w);
+            if (cx <= 0.0 || cy <= 0.0) continue;
+            geo = fmin(cx * cy / d2, pp->g_max);
+            if (!o_visible(sc, x, nx, y, ny, 0)) continue;
+            radiance_toward(sc, pr, (uint32_t)r[R_PRIM], y, ny, x, L);
+        }
+        for (int a = 0; a < 3; ++a) o[a] += rho[a] / O_PI * L[a] * geo * r[R_W];
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Brute-force reference of what one pixel's estimate converges to:
+ * L_e(x) + integral over the hemisphere of rho_x/pi * L(y; x) cos(theta_x),
+ * by plain Monte Carlo with uniform hemisphere directions (a uniform sphere
+ * direction mirrored into n_x's hemisphere, pdf 1/(2 pi)).  No resampling,
+ * no bounding: a check of the whole resampled estimator (Eq. 9 is unbiased
+ * for this integral).  Random stream: counter (sample, pixel, 99, 0).
+ * ------------------------------------------------------------------------- */
+void o_brute_force(const o_scene *sc, const o_probes *pr, const double *gb, int32_t W, int32_t H,
+                   const int32_t *pix, int64_t npix, int64_t nsamples, uint64_t seed, double *out)
+{
+    for (int64_t q = 0; q < npix; ++q) {
+        int64_t p = pix[q];
+        const double *g = gb + GB_N * p;
+        double *o = out + 3 * q;
+        for (int a = 0; a < 3; ++a) o[a] = g[GB_EMIT + a];
+        if (!pixel_active(g)) continue;
+        const double *x = g + GB_POS, *nx = g + GB_NRM, *rho = g + GB_ALB;
+        double org[3], acc[3] = {0, 0, 0};
+        for (int a = 0; a < 3; ++a) org[a] = x[a] + sc->eps * nx[a];
+        for (int64_t s = 0; s < nsamples; ++s) {
+            double u[4], w[3], L[3];
+            rand4(seed, (uint32_t)s, (uint32_t)p, 99u, 0u, u);
+            o_sphere_dir(u[0], u[1], w);
+            double c = dot3(nx, w);
+            if (c < 0.0) { w[0] = -w[0]; w[1] = -w[1]; w[2] = -w[2]; c = -c; }
+            o_hit h;
+            if (closest_hit(sc, org, w, O_INF, &h)) {
+                double y[3];
+                for (int a = 0; a < 3; ++a) y[a] = org[a] + h.t * w[a];
+                if (-dot3(h.n, w) <= 0.0) continue;
+                radiance_toward(sc, pr, h.prim, y, h.n, x, L);
+            } else {
+                for (int a = 0; a < 3; ++a) L[a] = sc->sky[a];
+            }
+            for (int a = 0; a < 3; ++a) acc[a] += 2.0 * rho[a] * L[a] * c;
+        }
+        for (int a = 0; a < 3; ++a) o[a] += acc[a] / (double)nsamples;
+    }
+}

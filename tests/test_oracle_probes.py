@@ -1,0 +1,342 @@
+"""Pins of the oracle's probe volume: octahedral map, gutters, query, update.
+
+* octahedral encode/decode round trip; texel centres; bilinear fetch at a
+  texel centre returns the texel;
+* gutters make the fetch continuous across the octahedral folds (a smooth
+  function sampled at texel centres is reproduced everywhere, edges included);
+* with the backface and visibility terms switched off and a constant value
+  per probe, the query equals scipy's trilinear RegularGridInterpolator;
+* constant textures give a constant query whatever the weights;
+* visibility limits (probe fully visible / fully hidden);
+* update: empty space under sky L gives E/pi = L and depth = (d_max, d_max^2)
+  exactly; the Lambertian plane of albedo 1 under sky L is a fixed point with
+  E = pi L on the plane; hysteresis follows a^k; a texel converges to the
+  analytic irradiance of a probe above a black plane.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.interpolate import RegularGridInterpolator
+
+import oracle as o
+from paper_2108_05263_amd import scenegen as g
+
+
+def _dirs(n, seed=0):
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=(n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def test_octahedral_round_trip():
+    for v in _dirs(500):
+        uv = o.oct_encode(v)
+        assert 0.0 <= uv[0] <= 1.0 and 0.0 <= uv[1] <= 1.0
+        assert np.allclose(o.oct_decode(uv), v, atol=1e-12)
+    for v in ([0, 0, 1.0], [0, 0, -1.0], [1.0, 0, 0], [0, -1.0, 0]):
+        assert np.allclose(o.oct_decode(o.oct_encode(v)), v, atol=1e-12)
+
+
+def _smooth(v):
+    return np.array([1.0 + 0.5 * v[0], 2.0 + 0.3 * v[1] - 0.2 * v[2], 0.5 + 0.4 * v[2] ** 2])
+
+
+def _tile_from(fn, N):
+    P = N + 2
+    tile = np.zeros((P * P, 3))
+    for ty in range(N):
+        for tx in range(N):
+            d = o.oct_decode([(tx + 0.5) / N, (ty + 0.5) / N])
+            tile[(ty + 1) * P + tx + 1] = fn(d)
+    return o.fill_gutter(tile, N)
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_fetch_at_texel_centres(N):
+    tile = _tile_from(_smooth, N)
+    for ty in range(N):
+        for tx in range(N):
+            d = o.oct_decode([(tx + 0.5) / N, (ty + 0.5) / N])
+            assert np.allclose(o.tile_fetch(tile, N, d), tile[(ty + 1) * (N + 2) + tx + 1], atol=1e-12)
+
+
+def test_gutters_make_fetch_continuous():
+    N = 16
+    tile = _tile_from(_smooth, N)
+    # directions next to the equator and the -z pole (where the folds are),
+    # and both sides of every fold, must reproduce the smooth function
+    worst = 0.0
+    for v in _dirs(3000, 4):
+        if abs(v[2]) > 0.15 and v[2] > -0.85:
+            continue
+        worst = max(worst, np.abs(o.tile_fetch(tile, N, v) - _smooth(v)).max())
+    assert worst < 0.05
+    # a pure fold test: mirrored directions across the z=0 edge agree
+    for v in _dirs(500, 5):
+        v = np.array([v[0], v[1], 1e-9])
+        v /= np.linalg.norm(v)
+        w = np.array([v[0], v[1], -1e-9])
+        w /= np.linalg.norm(w)
+        assert np.allclose(o.tile_fetch(tile, N, v), o.tile_fetch(tile, N, w), atol=1e-6)
+
+
+def _grid(dims=(4, 3, 5), spacing=1.5):
+    return g.probe_grid(dims, (0.0, 0.0, 0.0), spacing)
+
+
+def test_query_equals_trilinear_when_weights_off():
+    grid = _grid()
+    P = grid.count
+    rng = np.random.default_rng(8)
+    vals = rng.uniform(0.1, 3.0, (P, 3))
+    irr = np.repeat(vals[:, None, :], (grid.irr_res + 2) ** 2, axis=1)
+    dep = rng.uniform(0.0, 2.0, (P, (grid.dep_res + 2) ** 2, 2))
+    nx, ny, nz = grid.dims
+    s = float(grid.spacing[0])
+    axes = [(np.arange(n) + 0.5) * s for n in (nx, ny, nz)]
+    grid_vals = vals.reshape(nz, ny, nx, 3).transpose(2, 1, 0, 3)
+    interp = RegularGridInterpolator(axes, grid_vals)
+    pts = np.stack([rng.uniform(a[0], a[-1], 400) for a in axes], axis=1)
+    nrm = _dirs(400, 9)
+    q = o.probe_query(grid, irr, dep, pts, nrm, flags=3)
+    assert np.allclose(q, interp(pts), atol=1e-12, rtol=1e-12)
+    # outside the probe box the grid coordinate clamps to the border probes
+    out = np.array([[-5.0, 1.0, 2.0]])
+    q_out = o.probe_query(grid, irr, dep, out, nrm[:1], flags=3)
+    clamp = np.array([[axes[0][0], 1.0, 2.0]])
+    assert np.allclose(q_out, interp(clamp), atol=1e-12)
+
+
+def test_query_constant_textures_give_constant():
+    grid = _grid()
+    P = grid.count
+    rng = np.random.default_rng(10)
+    irr = np.zeros((P, (grid.irr_res + 2) ** 2, 3)) + np.array([0.7, 1.1, 2.3])
+    dep = rng.uniform(0.0, 2.5, (P, (grid.dep_res + 2) ** 2, 1))
+    dep = np.concatenate([dep, dep ** 2 + rng.uniform(0, 0.5, dep.shape)], axis=2)
+    pts = rng.uniform(0.0, 7.0, (300, 3))
+    q = o.probe_query(grid, irr, dep, pts, _dirs(300, 3))
+    assert np.allclose(q, [0.7, 1.1, 2.3], atol=1e-12)
+
+
+def test_query_visibility_limits():
+    grid = _grid((2, 2, 2), 2.0)
+    P = grid.count
+    vals = np.arange(P, dtype=np.float64)[:, None] * np.ones(3) + 1.0
+    irr = np.repeat(vals[:, None, :], (grid.irr_res + 2) ** 2, axis=1)
+    nd = (grid.dep_res + 2) ** 2
+    far = np.zeros((P, nd, 2))
+    far[..., 0], far[..., 1] = 100.0, 100.0 ** 2
+    pts = np.random.default_rng(2).uniform(1.0, 3.0, (100, 3))
+    nrm = _dirs(100, 6)
+    # every probe sees farther than the query point: visibility 1
+    assert np.allclose(o.probe_query(grid, irr, far, pts, nrm, 0),
+                       o.probe_query(grid, irr, far, pts, nrm, 2), atol=1e-12)
+    # probe 0 is hidden (mean distance 0, variance at the floor): with the
+    # backface term off its weight collapses to ~1e-6 x trilinear and the query
+    # becomes the trilinear blend of the seven others, renormalised
+    hidden = far.copy()
+    hidden[0] = 0.0
+    q = o.probe_query(grid, irr, hidden, pts, nrm, flags=1)
+    f = (pts - 1.0) / 2.0
+    num = np.zeros(len(pts))
+    den = np.zeros(len(pts))
+    for c in range(1, 8):
+        ox, oy, oz = c & 1, (c >> 1) & 1, (c >> 2) & 1
+        t = ((f[:, 0] if ox else 1 - f[:, 0]) * (f[:, 1] if oy else 1 - f[:, 1])
+             * (f[:, 2] if oz else 1 - f[:, 2]))
+        num += t * vals[c, 0]
+        den += t
+    assert np.allclose(q[:, 0], num / den, rtol=1e-5)
+
+
+# --------------------------------------------------------------------------
+# probe update
+# --------------------------------------------------------------------------
+def _open_scene(prims=None, sky=(1.5, 0.5, 2.0)):
+    if prims is None:
+        prims = np.zeros((0, 16), np.float32)
+    return g.Scene(prims=prims, has_room=False, room_lo=np.zeros(3, np.float32),
+                   room_hi=np.zeros(3, np.float32), wall_albedo=np.zeros(3, np.float32),
+                   sky=np.asarray(sky, np.float32), eps=1e-3)
+
+
+def test_update_empty_space_under_sky():
+    sky = np.array([1.5, 0.5, 2.0], np.float32)
+    sc = _open_scene(sky=sky)
+    grid = _grid((2, 2, 2), 1.0)
+    irr, dep = g.empty_probe_textures(grid)
+    i2, d2 = o.probe_update(sc, grid, irr, dep, rays=128, hysteresis=0.0, sharpness=50.0, seed=3,
+                            frame=0)
+    assert np.allclose(i2, sky.astype(np.float64), rtol=1e-14, atol=0)
+    assert np.allclose(d2[..., 0], grid.d_max, rtol=1e-14)
+    assert np.allclose(d2[..., 1], grid.d_max ** 2, rtol=1e-13)
+
+
+def test_update_plane_fixed_point_gives_pi_L():
+    L = np.array([0.8, 1.3, 2.1], np.float32)
+    plane = g.prim_records([1], [[0.0, -1.0, 0.0]], [[1000.0, 1.0, 1000.0]], [[1.0, 1.0, 1.0]],
+                           [[0, 0, 0]])
+    sc = _open_scene(plane, sky=L)
+    grid = g.probe_grid((3, 3, 3), (-1.5, 0.0, -1.5), 1.0)
+    irr, dep = g.empty_probe_textures(grid)
+    irr[..., :3] = L
+    dep[..., 0], dep[..., 1] = 1.0, 1.0
+    i2, d2 = o.probe_update(sc, grid, irr, dep, rays=64, hysteresis=0.0, sharpness=50.0, seed=1,
+                            frame=0)
+    assert np.allclose(i2, L.astype(np.float64), rtol=1e-12)
+    # query on the plane: Q = E/pi = L, i.e. E = pi L
+    pts = np.array([[0.1, 0.0, 0.2], [-0.7, 0.0, 0.4]])
+    q = o.probe_query(grid, i2, d2, pts, [[0, 1.0, 0]] * 2)
+    assert np.allclose(math.pi * q, math.pi * L.astype(np.float64), rtol=1e-12)
+
+
+def test_update_hysteresis_geometric():
+    sky = np.array([2.0, 2.0, 2.0], np.float32)
+    sc = _open_scene(sky=sky)
+    grid = _grid((2, 2, 2), 1.0)
+    irr, dep = g.empty_probe_textures(grid)
+    irr = irr[..., :3].astype(np.float64) + 0.5
+    dep = dep.astype(np.float64)
+    a = 0.9
+    for k in range(1, 6):
+        irr, dep = o.probe_update(sc, grid, irr, dep, 64, a, 50.0, 1, k)
+        expect = a ** k * 0.5 + (1 - a ** k) * 2.0
+        assert np.allclose(irr, expect, rtol=1e-12)
+
+
+def test_update_texel_converges_to_analytic_irradiance():
+    # probe above an infinite black plane under sky L: a texel with direction n
+    # at angle theta from +y sees E/pi = L (1 + cos theta) / 2
+    L = 1.0
+    plane = g.prim_records([1], [[0.0, -1.0, 0.0]], [[1000.0, 1.0, 1000.0]], [[0, 0, 0]],
+                           [[0, 0, 0]])
+    sc = _open_scene(plane, sky=(L, L, L))
+    grid = g.probe_grid((1, 1, 1), (-0.5, 0.0, -0.5), 1.0)
+    irr, dep = g.empty_probe_textures(grid)
+    i2, _ = o.probe_update(sc, grid, irr, dep, 4096, 0.0, 50.0, 5, 0)
+    N = grid.irr_res
+    errs = []
+    for ty in range(N):
+        for tx in range(N):
+            n = o.oct_decode([(tx + 0.5) / N, (ty + 0.5) / N])
+            got = i2[0, (ty + 1) * (N + 2) + tx + 1, 0]
+            errs.append(got - L * (1 + n[1]) / 2)
+    assert np.max(np.abs(errs)) < 0.03
+    assert abs(np.mean(errs)) < 0.006
+
+
+def _random_tile(N, C, seed):
+    P = N + 2
+    rng = np.random.default_rng(seed)
+    tile = np.zeros((P * P, C))
+    for ty in range(N):
+        for tx in range(N):
+            tile[(ty + 1) * P + tx + 1] = rng.uniform(0, 1, C)
+    return o.fill_gutter(tile, N)
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_fetch_continuous_across_border_folds(N):
+    """The outer border of the octahedral square is a fold: directions just on
+    either side of the planes x=0 and y=0 (lower hemisphere) map to mirrored
+    points of the same border.  With correct gutters the bilinear fetch agrees
+    on both sides for ANY texel values; near -z all four corners meet."""
+    tile = _random_tile(N, 3, N)
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        a, z = rng.uniform(-1, 1), -rng.uniform(0.05, 1.0)
+        for axis in (0, 1):
+            vp = np.zeros(3)
+            vp[1 - axis], vp[2] = a, z
+            vm = vp.copy()
+            vp[axis], vm[axis] = 1e-10, -1e-10
+            vp /= np.linalg.norm(vp)
+            vm /= np.linalg.norm(vm)
+            assert np.allclose(o.tile_fetch(tile, N, vp), o.tile_fetch(tile, N, vm), atol=1e-7)
+    corner = [o.tile_fetch(tile, N, np.array([sx * 1e-9, sy * 1e-9, -1.0]))
+              for sx in (-1, 1) for sy in (-1, 1)]
+    for c in corner[1:]:
+        assert np.allclose(c, corner[0], atol=1e-7)
+
+
+def test_update_depth_clamped_and_probe_centred():
+    # one probe at the centre of a 6^3 room: texels that face a wall read
+    # a depth mean close to 3 (the cos^50 lobe is narrow); all depths <= d_max
+    sc = g.Scene(prims=np.zeros((0, 16), np.float32), has_room=True,
+                 room_lo=np.zeros(3, np.float32), room_hi=np.full(3, 6.0, np.float32),
+                 wall_albedo=np.zeros(3, np.float32), sky=np.zeros(3, np.float32), eps=1e-3)
+    grid = g.probe_grid((1, 1, 1), (0, 0, 0), 6.0)
+    grid.d_max = 100.0
+    irr, dep = g.empty_probe_textures(grid)
+    _, d2 = o.probe_update(sc, grid, irr, dep, 4096, 0.0, 50.0, 2, 0)
+    N = grid.dep_res
+    for ty in range(N):
+        for tx in range(N):
+            n = o.oct_decode([(tx + 0.5) / N, (ty + 0.5) / N])
+            if np.max(np.abs(n)) > 0.97:
+                m = d2[0, (ty + 1) * (N + 2) + tx + 1, 0]
+                assert 3.0 <= m < 3.3, (n, m)
+    grid.d_max = 2.0
+    _, d3 = o.probe_update(sc, grid, irr, dep, 256, 0.0, 50.0, 2, 0)
+    assert np.all(d3[..., 0] <= 2.0 + 1e-12) and np.all(d3[..., 1] <= 4.0 + 1e-12)
+
+
+def test_update_emission_enters_undiffused():
+    # a probe enclosed by an emissive sphere of radiance Le (albedo 0): every
+    # probe ray returns Le itself, so every texel stores E/pi = Le (Eq. 5)
+    le = np.array([3.0, 5.0, 7.0], np.float32)
+    prims = g.prim_records([0], [[0.5, 0.5, 0.5]], [[2.0, 0, 0]], [[0, 0, 0]], [le])
+    sc = g.Scene(prims=prims, has_room=False, room_lo=np.zeros(3, np.float32),
+                 room_hi=np.zeros(3, np.float32), wall_albedo=np.zeros(3, np.float32),
+                 sky=np.zeros(3, np.float32), eps=1e-3)
+    grid = g.probe_grid((1, 1, 1), (0, 0, 0), 1.0)
+    irr, dep = g.empty_probe_textures(grid)
+    i2, d2 = o.probe_update(sc, grid, irr, dep, 128, 0.0, 50.0, 2, 0)
+    assert np.allclose(i2, le.astype(np.float64), rtol=1e-13)
+
+
+def test_query_backface_prefers_probes_in_front():
+    # query at the centre of a cubic cell, normal pointing at probe c: the
+    # eight weights are ((1 + cos)/2)^2 + 0.2 with cos in {1, 1/3, -1/3, -1}
+    grid = _grid((2, 2, 2), 2.0)
+    P = grid.count
+    nd = (grid.dep_res + 2) ** 2
+    far = np.zeros((P, nd, 2))
+    far[..., 0], far[..., 1] = 100.0, 100.0 ** 2
+    p = np.array([[2.0, 2.0, 2.0]])
+    for c in range(8):
+        vals = np.zeros(P)
+        vals[c] = 1.0
+        irr = np.repeat((vals[:, None] * np.ones(3))[:, None, :], (grid.irr_res + 2) ** 2, axis=1)
+        corner = np.array([c & 1, (c >> 1) & 1, (c >> 2) & 1]) * 2.0 + 1.0
+        n = (corner - p[0]) / np.linalg.norm(corner - p[0])
+        q = o.probe_query(grid, irr, far, p, n[None], 0)[0, 0]
+        w = [((1 + cs) / 2) ** 2 + 0.2 for cs in (1, 1 / 3, 1 / 3, 1 / 3, -1 / 3, -1 / 3, -1 / 3, -1)]
+        assert q == pytest.approx(w[0] / sum(w), rel=1e-12)
+        q_back = o.probe_query(grid, irr, far, p, -n[None], 0)[0, 0]
+        assert q_back == pytest.approx(w[-1] / sum(w), rel=1e-12)
+
+
+def test_query_chebyshev_weight():
+    # two probes along x; probe 0 stores depth moments (mu, mu^2 + s2) in every
+    # texel, probe 1 sees far.  The query's value recovers probe 0's
+    # visibility weight, which must be the cubed one-sided Chebyshev bound
+    # s2 / (s2 + (r - mu)^2) when r > mu, and 1 when r <= mu.
+    grid = g.probe_grid((2, 1, 1), (0, 0, 0), 2.0)
+    nd = (grid.dep_res + 2) ** 2
+    irr = np.zeros((2, (grid.irr_res + 2) ** 2, 3))
+    irr[1] = 1.0
+    for mu, s2, xq in [(0.3, 0.04, 1.6), (0.5, 0.01, 2.2), (0.2, 0.2, 1.4), (1.0, 0.05, 1.5)]:
+        dep = np.zeros((2, nd, 2))
+        dep[0, :, 0], dep[0, :, 1] = mu, mu * mu + s2
+        dep[1, :, 0], dep[1, :, 1] = 100.0, 1e4
+        p = np.array([[xq, 1.0, 1.0]])
+        q = o.probe_query(grid, irr, dep, p, [[0, 1.0, 0]], flags=1)[0, 0]
+        t1 = (xq - 1.0) / 2.0
+        t0 = 1.0 - t1
+        v0 = t1 * (1.0 - q) / (t0 * q)
+        r = xq - 1.0
+        cheb = 1.0 if r <= mu else (s2 / (s2 + (r - mu) ** 2)) ** 3
+        assert v0 == pytest.approx(max(cheb, 1e-6), rel=1e-9), (mu, s2, xq)
