@@ -1,0 +1,184 @@
+"""Benchmark of the DDGI-resampling hot path on one MI355X.
+
+A step is one frame of the 1920x1080 workload (room with 128 spheres + 128
+boxes, 32x8x32 probes, M=32 candidates, temporal reuse, two spatial passes
+with k=5 and radius 30 px): G-buffer, initial resampling, temporal reuse,
+two spatial passes and shading, with all inputs resident in HBM.  The probe
+volume is filled before the timed region (the workload updates it only
+before frame 0).
+
+Prints one JSON line: resampled pixels per second over whole frames, the
+per-kernel HIP-event times, the roofline of the dominant kernel and the FP64
+oracle's rate on a bounded crop of the same frame (CPU baseline).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per pixel each pass must move through HBM with this
+# layout (16-byte G-buffer and reservoir records; padding lanes excluded):
+#   gbuffer  writes pos+depth 16, normal+prim 16, albedo 12, emit 12 = 56
+#   initial  reads x, n, rho (12+12+12 = 36); writes reservoir 56 + resid 12 = 104
+#   temporal reads G-buffer 40 + current reservoir 56 + history 56 + prev G-buffer 28
+#            = 180 (+ writes 56) = 236
+#   spatial  reads G-buffer 40 + own reservoir 56; writes 56 = 152 (neighbour
+#            records are re-reads of the same buffer)
+#   shade    reads G-buffer 52 + reservoir 56 + resid 12; writes 12 = 132
+ALGO_BYTES = {"gbuffer": 56, "initial": 104, "temporal": 236, "spatial": 152, "shade": 132}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="hd")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--cpu-crop", type=int, nargs=2, default=(160, 90))
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, crop):
+    """FP64 oracle, single thread, on a centred crop of the same frame: two
+    frames (the second with temporal reuse), the second one timed."""
+    import numpy as np
+    import oracle as o
+    from paper_2108_05263_amd import scenegen as sg
+
+    sc = sg.make_scene(cfg)
+    grid = sg.make_probe_grid(cfg)
+    upd = sg.ProbeUpdate(rays=32, fill_passes=1, fill_rays=32)
+    irr, dep = o.fill_probes(sc, grid, upd, seed=1)
+    W, H = cfg.width, cfg.height
+    cw, ch = crop
+    x0, y0 = (W - cw) // 2, (H - ch) // 2
+    pix = np.array([(y0 + j) * W + x0 + i for j in range(ch) for i in range(cw)], np.int32)
+    pr = cfg.params
+    n = W * H
+    gb_prev = hist = None
+    cam_prev = None
+    t_frame = 0.0
+    for f in range(2):
+        cam = sg.make_camera(cfg, f)
+        t0 = time.perf_counter()
+        gb = o.gbuffer(sc, cam, pixels=pix, out=np.zeros((n, 14)))
+        res, resid = o.resample_initial(sc, W, H, gb, grid, irr, dep, pr, 1, f, pixels=pix)
+        if hist is not None:
+            res = o.resample_temporal(sc, W, H, gb, gb_prev, cam_prev, res, hist, pr, 1, f, pixels=pix)
+        for sp in range(pr.n_spatial):
+            res = o.resample_spatial(sc, W, H, gb, res, pr, sp, 1, f, pixels=pix)
+        o.shade(sc, W, H, gb, grid, irr, dep, res, resid, pr, pixels=pix)
+        t_frame = time.perf_counter() - t0
+        gb_prev, hist, cam_prev = gb, res, cam
+    return {"value": len(pix) / t_frame, "unit": "pixels/s", "cores": 1, "kind": "oracle",
+            "sample": f"{cw}x{ch} centre crop of the {W}x{H} frame, second frame (with temporal "
+                      f"reuse), {t_frame:.1f} s single-threaded FP64"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the path shards by screen "
+                                   "bands (see DESIGN.md), which is not built"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2108_05263_amd import build as libbuild
+    if not os.path.exists(libbuild.LIB):
+        libbuild.build()
+    from paper_2108_05263_amd import gi
+    from paper_2108_05263_amd import scenegen as sg
+
+    cfg = sg.CONFIGS[args.config]
+    torch.cuda.set_device(0)
+    r = gi.Renderer(cfg, seed=1)
+    r.fill_probes()
+    stream = torch.cuda.current_stream()
+    names = ["gbuffer", "initial", "temporal", "spatial0", "spatial1", "shade"]
+
+    # wrap the entry points with HIP events recorded on the launch stream
+    times = {k: [] for k in names}
+    orig = {k: getattr(gi, k) for k in ("trace_gbuffer", "resample_initial", "resample_temporal",
+                                        "resample_spatial", "shade")}
+    pending = []
+
+    def timed(key_fn, fn):
+        def wrapper(*a, **kw):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn(*a, **kw)
+            e1.record(stream)
+            pending.append((key_fn(a), e0, e1))
+        return wrapper
+
+    gi.trace_gbuffer = timed(lambda a: "gbuffer", orig["trace_gbuffer"])
+    gi.resample_initial = timed(lambda a: "initial", orig["resample_initial"])
+    gi.resample_temporal = timed(lambda a: "temporal", orig["resample_temporal"])
+    gi.resample_spatial = timed(lambda a: f"spatial{a[4]}", orig["resample_spatial"])
+    gi.shade = timed(lambda a: "shade", orig["shade"])
+
+    for f in range(args.warmup):
+        r.frame(f)
+    torch.cuda.synchronize()
+    pending.clear()
+    t0 = time.perf_counter()
+    for f in range(args.warmup, args.warmup + args.steps):
+        r.frame(f)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for key, e0, e1 in pending:
+        times[key].append(e0.elapsed_time(e1))
+    for k, v in orig.items():
+        setattr(gi, k, v)
+
+    W, H = r.W, r.H
+    npx = W * H
+    ms_step = elapsed * 1e3 / args.steps
+    avg = {k: (sum(v) / len(v) if v else 0.0) for k, v in times.items()}
+    resampling_ms = avg["initial"] + avg["temporal"] + avg["spatial0"] + avg["spatial1"] + avg["shade"]
+    dom = max(avg, key=avg.get)
+    dom_key = "spatial" if dom.startswith("spatial") else dom
+    bytes_launch = ALGO_BYTES[dom_key] * npx
+    achieved = bytes_launch / (avg[dom] * 1e-3) / 1e9
+    path_bytes = sum(ALGO_BYTES[k if not k.startswith("spatial") else "spatial"] for k in names) * npx
+    line = {
+        "metric": "resampled pixels/s (1080p, M=32, 2xk=5)",
+        "value": npx * args.steps / elapsed,
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {W}x{H} room, {cfg.n_spheres}+{cfg.n_boxes} primitives, "
+                               f"{cfg.probe_dims[0]}x{cfg.probe_dims[1]}x{cfg.probe_dims[2]} probes, "
+                               f"M={cfg.params.M}, temporal, {cfg.params.n_spatial}x k={cfg.params.k} "
+                               f"r={cfg.params.radius:g}",
+                   "width": W, "height": H, "M": cfg.params.M, "k": cfg.params.k,
+                   "spatial_passes": cfg.params.n_spatial, "temporal": cfg.params.temporal},
+        "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
+        "resampling_only_pixels_per_s": npx / (resampling_ms * 1e-3),
+        "path_hbm_frac": path_bytes / ((sum(avg.values())) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "roofline": {"kernel": f"k_{dom_key}", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(cfg, tuple(args.cpu_crop))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,558 @@
+// Device-side primitives of the DDGI-resampling path for gfx950 (wave64).
+//
+// Everything here is FP32 and inlined into the kernels of gi_kernels.hip:
+// Philox4x32-10, samplers, ray casting against the analytic scene (brute
+// force or a uniform grid walked with a 3D-DDA), the octahedral probe
+// fetch and the DDGI probe query, and the reservoir target function.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gi.h"
+
+namespace gi {
+
+constexpr float kPi = 3.14159265358979f;
+constexpr float kInvPi = 0.318309886183791f;
+constexpr float kInf = __builtin_huge_valf();
+
+// Hardware reciprocal, square root and reciprocal square root (about 1 ulp);
+// used instead of the IEEE-exact division/sqrt expansions, which cost ~10
+// instructions each.  The path's tolerance against the FP64 oracle is far
+// above these errors.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// --------------------------------------------------------------------------
+// small vector type
+// --------------------------------------------------------------------------
+struct V3 {
+    float x, y, z;
+};
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 operator-(V3 a) { return v3(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ V3 operator*(V3 a, V3 b) { return v3(a.x * b.x, a.y * b.y, a.z * b.z); }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 madd(V3 o, float t, V3 d) { return v3(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z)); }
+__device__ __forceinline__ float lum(V3 c) { return 0.2126f * c.x + 0.7152f * c.y + 0.0722f * c.z; }
+__device__ __forceinline__ bool is_zero(V3 a) { return a.x == 0.0f && a.y == 0.0f && a.z == 0.0f; }
+__device__ __forceinline__ V3 xyz(float4 a) { return v3(a.x, a.y, a.z); }
+__device__ __forceinline__ V3 ld3(const float *a) { return v3(a[0], a[1], a[2]); }
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds; each round multiplies
+// words 0 and 2 by the two round constants, crosses the high halves (xored
+// with the neighbour word and the key) and the low halves; the key advances
+// by the two Weyl constants between rounds.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3)
+{
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// 24-bit uniform in [0, 1): exact in FP32
+__device__ __forceinline__ float u01(uint32_t v) { return (float)(v >> 8) * 5.9604644775390625e-08f; }
+
+enum : uint32_t { kPassInitial = 0, kPassTemporal = 1, kPassSpatial0 = 2, kPassProbe = 9 };
+
+// --------------------------------------------------------------------------
+// samplers
+// --------------------------------------------------------------------------
+// sin(2 pi u), cos(2 pi u) for u in [0, 1): the hardware sine/cosine take
+// their argument in revolutions
+__device__ __forceinline__ float sin_rev(float u) { return __builtin_amdgcn_sinf(u); }
+__device__ __forceinline__ float cos_rev(float u) { return __builtin_amdgcn_cosf(u); }
+
+// cosine-weighted hemisphere about n in the branch-free basis of
+// Duff et al. 2017 ("Building an Orthonormal Basis, Revisited")
+__device__ __forceinline__ V3 cosine_dir(V3 n, float u0, float u1)
+{
+    float s_ = sin_rev(u0), c_ = cos_rev(u0);
+    float r = fsqrt(u1);
+    float lx = r * c_, ly = r * s_, lz = fsqrt(fmaxf(0.0f, 1.0f - u1));
+    float sg = n.z >= 0.0f ? 1.0f : -1.0f;
+    float a = -rcp(sg + n.z);
+    float b = n.x * n.y * a;
+    V3 t = v3(1.0f + sg * n.x * n.x * a, sg * b, -sg * n.x);
+    V3 bt = v3(b, sg + n.y * n.y * a, -n.y);
+    return v3(lx * t.x + ly * bt.x + lz * n.x, lx * t.y + ly * bt.y + lz * n.y, lx * t.z + ly * bt.z + lz * n.z);
+}
+
+__device__ __forceinline__ V3 sphere_dir(float u0, float u1)
+{
+    float z = 1.0f - 2.0f * u0;
+    float s_ = sin_rev(u1), c_ = cos_rev(u1);
+    float r = fsqrt(fmaxf(0.0f, 1.0f - z * z));
+    return v3(r * c_, r * s_, z);
+}
+
+// --------------------------------------------------------------------------
+// ray casting
+// --------------------------------------------------------------------------
+struct Hit {
+    float t;
+    uint32_t prim;
+    int axis;        // box / wall face axis; -1 for spheres
+};
+
+// nearest t > 0 of a sphere, in the cancellation-free form of Haines et al.
+// 2019 ("Precision Improvements for Ray/Sphere Intersection")
+__device__ __forceinline__ float isect_sphere(V3 o, V3 d, V3 c, float r)
+{
+    V3 f = o - c;
+    float b = dot(f, d);
+    V3 l = madd(f, -b, d);
+    float disc = r * r - dot(l, l);
+    if (disc < 0.0f) return kInf;
+    float q = -(b + copysignf(fsqrt(disc), b));
+    float cc = dot(f, f) - r * r;
+    if (q == 0.0f) return kInf;
+    float t0 = cc * rcp(q), t1 = q;
+    float tn = fminf(t0, t1), tf = fmaxf(t0, t1);
+    if (tn > 0.0f) return tn;
+    if (tf > 0.0f) return tf;
+    return kInf;
+}
+
+// slab test; on a hit returns t and the face axis
+__device__ __forceinline__ float isect_box(V3 o, V3 inv, V3 c, V3 h, int &axis)
+{
+    float ax = (c.x - h.x - o.x) * inv.x, bx = (c.x + h.x - o.x) * inv.x;
+    float ay = (c.y - h.y - o.y) * inv.y, by = (c.y + h.y - o.y) * inv.y;
+    float az = (c.z - h.z - o.z) * inv.z, bz = (c.z + h.z - o.z) * inv.z;
+    float lx = fminf(ax, bx), hx = fmaxf(ax, bx);
+    float ly = fminf(ay, by), hy = fmaxf(ay, by);
+    float lz = fminf(az, bz), hz = fmaxf(az, bz);
+    int an = 0;
+    float tn = lx;
+    if (ly > tn) { tn = ly; an = 1; }
+    if (lz > tn) { tn = lz; an = 2; }
+    int af = 0;
+    float tf = hx;
+    if (hy < tf) { tf = hy; af = 1; }
+    if (hz < tf) { tf = hz; af = 2; }
+    if (tn > tf) return kInf;
+    if (tn > 0.0f) { axis = an; return tn; }
+    if (tf > 0.0f) { axis = af; return tf; }
+    return kInf;
+}
+
+__device__ __forceinline__ float comp(V3 v, int a) { return a == 0 ? v.x : (a == 1 ? v.y : v.z); }
+
+// exit of the room box from inside
+__device__ __forceinline__ float isect_room(const gi_scene &sc, V3 o, V3 d, int &axis, uint32_t &wall)
+{
+    float best = kInf;
+    int ba = -1;
+    float dv[3] = {d.x, d.y, d.z}, ov[3] = {o.x, o.y, o.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (dv[a] == 0.0f) continue;
+        float ta = ((dv[a] > 0.0f ? sc.room_hi[a] : sc.room_lo[a]) - ov[a]) * rcp(dv[a]);
+        if (ta > 0.0f && ta < best) { best = ta; ba = a; }
+    }
+    if (ba < 0) return kInf;
+    axis = ba;
+    wall = sc.n_prims + 2u * (uint32_t)ba + (dv[ba] > 0.0f ? 1u : 0u);
+    return best;
+}
+
+struct PrimGeo {
+    V3 c;
+    uint32_t type;
+    V3 s;
+};
+
+__device__ __forceinline__ PrimGeo load_geo(const gi_prim *prims, uint32_t i)
+{
+    const float4 *p = reinterpret_cast<const float4 *>(prims + i);
+    float4 a = p[0], b = p[1];
+    return PrimGeo{v3(a.x, a.y, a.z), __float_as_uint(a.w), v3(b.x, b.y, b.z)};
+}
+
+// test one primitive; keep the lexicographically smallest (t, id)
+__device__ __forceinline__ void test_prim(const gi_prim *prims, uint32_t i, V3 o, V3 d, V3 inv, Hit &h)
+{
+    PrimGeo g = load_geo(prims, i);
+    int axis = -1;
+    float t = g.type == 0u ? isect_sphere(o, d, g.c, g.s.x) : isect_box(o, inv, g.c, g.s, axis);
+    // equal distances go to the lower id; a miss (t = inf) never counts,
+    // even when the running best is still the initial tmax = inf
+    if (t < h.t || (t == h.t && t < kInf && i < h.prim)) {
+        h.t = t;
+        h.prim = i;
+        h.axis = g.type == 0u ? -1 : axis;
+    }
+}
+
+// any surface crossing of a primitive in (0, tmax)?
+__device__ __forceinline__ bool occludes_prim(const gi_prim *prims, uint32_t i, V3 o, V3 d, V3 inv, float tmax)
+{
+    PrimGeo g = load_geo(prims, i);
+    int axis;
+    float t = g.type == 0u ? isect_sphere(o, d, g.c, g.s.x) : isect_box(o, inv, g.c, g.s, axis);
+    return t < tmax;
+}
+
+__device__ __forceinline__ float safe_inv(float v) { return v == 0.0f ? kInf : 1.0f / v; }
+
+// Ray cast: closest hit (ANY = false) or any hit (ANY = true) with t in (0, tmax).
+// Walls are tested first; the grid (if present) is walked with a 3D-DDA and
+// stops once the best hit lies before the current cell's exit.  Primitive
+// boxes are padded when binned, so the grid walk returns the same hit as the
+// brute-force loop.
+template <bool ANY>
+__device__ __forceinline__ bool cast(const gi_scene &sc, V3 o, V3 d, float tmax, Hit &h)
+{
+    h.t = tmax;
+    h.prim = GI_MISS;
+    h.axis = -1;
+    V3 inv = v3(rcp(d.x), rcp(d.y), rcp(d.z));
+    if (!ANY && sc.has_room) {
+        int axis;
+        uint32_t wall;
+        float tw = isect_room(sc, o, d, axis, wall);
+        if (tw < h.t) { h.t = tw; h.prim = wall; h.axis = axis; }
+    }
+    if (sc.cell_start == nullptr) {
+        for (uint32_t i = 0; i < sc.n_prims; ++i) {
+            if (ANY) {
+                if (occludes_prim(sc.prims, i, o, d, inv, tmax)) { h.prim = i; return true; }
+            } else {
+                test_prim(sc.prims, i, o, d, inv, h);
+            }
+        }
+        return h.prim != GI_MISS;
+    }
+    // clip to the grid box
+    float t0 = 0.0f, t1 = h.t;
+    {
+        float ax = (sc.grid_lo[0] - o.x) * inv.x, bx = (sc.grid_hi[0] - o.x) * inv.x;
+        float ay = (sc.grid_lo[1] - o.y) * inv.y, by = (sc.grid_hi[1] - o.y) * inv.y;
+        float az = (sc.grid_lo[2] - o.z) * inv.z, bz = (sc.grid_hi[2] - o.z) * inv.z;
+        t0 = fmaxf(t0, fmaxf(fminf(ax, bx), fmaxf(fminf(ay, by), fminf(az, bz))));
+        t1 = fminf(t1, fminf(fmaxf(ax, bx), fminf(fmaxf(ay, by), fmaxf(az, bz))));
+    }
+    if (!(t0 <= t1)) return h.prim != GI_MISS;
+    const int rx = (int)sc.grid_res[0], ry = (int)sc.grid_res[1], rz = (int)sc.grid_res[2];
+    const float cxs = (sc.grid_hi[0] - sc.grid_lo[0]) / rx;
+    const float cys = (sc.grid_hi[1] - sc.grid_lo[1]) / ry;
+    const float czs = (sc.grid_hi[2] - sc.grid_lo[2]) / rz;
+    V3 ps = madd(o, t0, d);
+    int ix = min(max((int)floorf((ps.x - sc.grid_lo[0]) * ((float)rx / (sc.grid_hi[0] - sc.grid_lo[0]))), 0), rx - 1);
+    int iy = min(max((int)floorf((ps.y - sc.grid_lo[1]) * ((float)ry / (sc.grid_hi[1] - sc.grid_lo[1]))), 0), ry - 1);
+    int iz = min(max((int)floorf((ps.z - sc.grid_lo[2]) * ((float)rz / (sc.grid_hi[2] - sc.grid_lo[2]))), 0), rz - 1);
+    const int sx = d.x >= 0.0f ? 1 : -1, sy = d.y >= 0.0f ? 1 : -1, sz = d.z >= 0.0f ? 1 : -1;
+    const int max_steps = rx + ry + rz + 3;
+    for (int step = 0; step < max_steps; ++step) {
+        uint32_t cell = (uint32_t)(ix + rx * (iy + ry * iz));
+        uint32_t b = sc.cell_start[cell], e = sc.cell_start[cell + 1];
+        for (uint32_t j = b; j < e; ++j) {
+            uint32_t i = sc.cell_items[j];
+            if (ANY) {
+                if (occludes_prim(sc.prims, i, o, d, inv, tmax)) { h.prim = i; return true; }
+            } else {
+                test_prim(sc.prims, i, o, d, inv, h);
+            }
+        }
+        float nx = d.x == 0.0f ? kInf : (sc.grid_lo[0] + (float)(ix + (sx > 0)) * cxs - o.x) * inv.x;
+        float ny = d.y == 0.0f ? kInf : (sc.grid_lo[1] + (float)(iy + (sy > 0)) * cys - o.y) * inv.y;
+        float nz = d.z == 0.0f ? kInf : (sc.grid_lo[2] + (float)(iz + (sz > 0)) * czs - o.z) * inv.z;
+        float texit = fminf(nx, fminf(ny, nz));
+        if (texit >= fminf(t1, h.t)) break;
+        if (nx <= ny && nx <= nz) {
+            ix += sx;
+            if (ix < 0 || ix >= rx) break;
+        } else if (ny <= nz) {
+            iy += sy;
+            if (iy < 0 || iy >= ry) break;
+        } else {
+            iz += sz;
+            if (iz < 0 || iz >= rz) break;
+        }
+    }
+    return h.prim != GI_MISS;
+}
+
+// facing geometric normal of a closest hit
+__device__ __forceinline__ V3 hit_normal(const gi_scene &sc, V3 o, V3 d, const Hit &h)
+{
+    V3 n;
+    if (h.prim >= sc.n_prims || h.axis >= 0) {
+        float s = comp(d, h.axis) > 0.0f ? -1.0f : 1.0f;
+        n = v3(h.axis == 0 ? s : 0.0f, h.axis == 1 ? s : 0.0f, h.axis == 2 ? s : 0.0f);
+    } else {
+        PrimGeo g = load_geo(sc.prims, h.prim);
+        V3 p = madd(o, h.t, d);
+        float ir = rcp(g.s.x);
+        n = ir * (p - g.c);
+        if (dot(n, d) > 0.0f) n = -n;
+    }
+    return n;
+}
+
+__device__ __forceinline__ void material(const gi_scene &sc, uint32_t prim, V3 &alb, V3 &emit)
+{
+    if (prim < sc.n_prims) {
+        const float4 *p = reinterpret_cast<const float4 *>(sc.prims + prim);
+        alb = xyz(p[2]);
+        emit = xyz(p[3]);
+    } else {
+        alb = ld3(sc.wall_albedo);
+        emit = ld3(sc.wall_emit);
+    }
+}
+
+// mutual visibility of two surface points (eps-lifted), or of a point and
+// the sky in direction b when b_is_dir
+__device__ __forceinline__ bool visible(const gi_scene &sc, V3 a, V3 na, V3 b, V3 nb, bool b_is_dir)
+{
+    V3 o = madd(a, sc.eps, na);
+    Hit h;
+    if (b_is_dir) return !cast<true>(sc, o, b, kInf, h) && !(sc.has_room);
+    V3 e = madd(b, sc.eps, nb);
+    V3 v = e - o;
+    float dist = fsqrt(dot(v, v));
+    V3 d = rcp(dist) * v;
+    if (cast<true>(sc, o, d, dist, h)) return false;
+    if (sc.has_room) {
+        int axis;
+        uint32_t wall;
+        if (isect_room(sc, o, d, axis, wall) < dist) return false;
+    }
+    return true;
+}
+
+// --------------------------------------------------------------------------
+// octahedral tiles and the probe query
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float sgnf(float v) { return v >= 0.0f ? 1.0f : -1.0f; }
+
+__device__ __forceinline__ void oct_encode(V3 v, float &u, float &w)
+{
+    float l1 = fabsf(v.x) + fabsf(v.y) + fabsf(v.z);
+    float il = rcp(l1);
+    float px = v.x * il, py = v.y * il;
+    if (v.z < 0.0f) {
+        float fx = (1.0f - fabsf(py)) * sgnf(px);
+        float fy = (1.0f - fabsf(px)) * sgnf(py);
+        px = fx;
+        py = fy;
+    }
+    u = 0.5f * (px + 1.0f);
+    w = 0.5f * (py + 1.0f);
+}
+
+__device__ __forceinline__ V3 oct_decode(float u, float w)
+{
+    float px = 2.0f * u - 1.0f, py = 2.0f * w - 1.0f;
+    float z = 1.0f - fabsf(px) - fabsf(py);
+    if (z < 0.0f) {
+        float fx = (1.0f - fabsf(py)) * sgnf(px);
+        float fy = (1.0f - fabsf(px)) * sgnf(py);
+        px = fx;
+        py = fy;
+    }
+    float il = frsq(px * px + py * py + z * z);
+    return v3(px * il, py * il, z * il);
+}
+
+struct Bilin {
+    int i00;        // index of the top-left texel in the padded tile
+    float ax, ay;   // fractional weights toward +x, +y
+};
+
+__device__ __forceinline__ Bilin bilin(V3 dir, int N)
+{
+    float u, w;
+    oct_encode(dir, u, w);
+    float fx = u * (float)N + 0.5f, fy = w * (float)N + 0.5f;
+    float x0 = floorf(fx), y0 = floorf(fy);
+    Bilin b;
+    // u, w lie in [0, 1] so x0, y0 lie in [0, N]; the clamp only guards
+    // against a degenerate (zero or NaN) direction
+    int ix = min(max((int)x0, 0), N), iy = min(max((int)y0, 0), N);
+    b.i00 = iy * (N + 2) + ix;
+    b.ax = fx - x0;
+    b.ay = fy - y0;
+    return b;
+}
+
+__device__ __forceinline__ V3 fetch_irr(const float4 *tile, const Bilin &b)
+{
+    float4 t00 = tile[b.i00], t10 = tile[b.i00 + 1], t01 = tile[b.i00 + 10], t11 = tile[b.i00 + 11];
+    float w00 = (1.0f - b.ax) * (1.0f - b.ay), w10 = b.ax * (1.0f - b.ay);
+    float w01 = (1.0f - b.ax) * b.ay, w11 = b.ax * b.ay;
+    return v3(w00 * t00.x + w10 * t10.x + w01 * t01.x + w11 * t11.x,
+              w00 * t00.y + w10 * t10.y + w01 * t01.y + w11 * t11.y,
+              w00 * t00.z + w10 * t10.z + w01 * t01.z + w11 * t11.z);
+}
+
+__device__ __forceinline__ float2 fetch_dep(const float2 *tile, V3 dir)
+{
+    Bilin b = bilin(dir, 16);
+    float2 t00 = tile[b.i00], t10 = tile[b.i00 + 1], t01 = tile[b.i00 + 18], t11 = tile[b.i00 + 19];
+    float w00 = (1.0f - b.ax) * (1.0f - b.ay), w10 = b.ax * (1.0f - b.ay);
+    float w01 = (1.0f - b.ax) * b.ay, w11 = b.ax * b.ay;
+    return make_float2(w00 * t00.x + w10 * t10.x + w01 * t01.x + w11 * t11.x,
+                       w00 * t00.y + w10 * t10.y + w01 * t01.y + w11 * t11.y);
+}
+
+constexpr int kIrrTexels = 10 * 10;
+constexpr int kDepTexels = 18 * 18;
+
+// Q(p, n) = E(p, n)/pi: blend of the 8 probes of p's cell
+__device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
+{
+    const float4 *irr = reinterpret_cast<const float4 *>(pr.irr);
+    const float2 *dep = reinterpret_cast<const float2 *>(pr.dep);
+    float pv[3] = {p.x, p.y, p.z};
+    int base[3];
+    float fr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int na = (int)pr.dims[a];
+        float g = (pv[a] - pr.lo[a]) / pr.spacing[a] - 0.5f;
+        g = fminf(fmaxf(g, 0.0f), (float)(na - 1));
+        int b = min(max((int)floorf(g), 0), max(na - 2, 0));
+        base[a] = b;
+        fr[a] = na >= 2 ? g - (float)b : 0.0f;
+    }
+    V3 sum = v3(0.0f, 0.0f, 0.0f);
+    float wsum = 0.0f;
+    const Bilin bn = bilin(n, 8);     // the irradiance direction is the same for all 8 probes
+#ifndef GI_QUERY_UNROLL
+#define GI_QUERY_UNROLL 1
+#endif
+#pragma unroll GI_QUERY_UNROLL
+    for (int c = 0; c < 8; ++c) {
+        int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
+        int ix = min(base[0] + ox, (int)pr.dims[0] - 1);
+        int iy = min(base[1] + oy, (int)pr.dims[1] - 1);
+        int iz = min(base[2] + oz, (int)pr.dims[2] - 1);
+        float tri = (ox ? fr[0] : 1.0f - fr[0]) * (oy ? fr[1] : 1.0f - fr[1]) * (oz ? fr[2] : 1.0f - fr[2]);
+        uint32_t pi = (uint32_t)ix + pr.dims[0] * ((uint32_t)iy + pr.dims[1] * (uint32_t)iz);
+        V3 P = v3(pr.lo[0] + ((float)ix + 0.5f) * pr.spacing[0], pr.lo[1] + ((float)iy + 0.5f) * pr.spacing[1],
+                  pr.lo[2] + ((float)iz + 0.5f) * pr.spacing[2]);
+        V3 tp = P - p;
+        float r2 = dot(tp, tp);
+        float back = 0.45f, vis = 1.0f;
+        if (r2 > 0.0f) {
+            float ir = frsq(r2);
+            float r = r2 * ir;
+            V3 w = ir * tp;
+            float hh = 0.5f * (1.0f + dot(n, w));
+            back = hh * hh + 0.2f;
+            float2 m = fetch_dep(dep + (size_t)pi * kDepTexels, -w);
+            if (r > m.x) {
+                float var = fmaxf(fmaf(-m.x, m.x, m.y), pr.var_floor);
+                float dd = r - m.x;
+                float cheb = var * rcp(fmaf(dd, dd, var));
+                vis = cheb * cheb * cheb;
+            }
+        }
+        float wgt = tri * fmaxf(back * vis, 1e-6f);
+        V3 e = fetch_irr(irr + (size_t)pi * kIrrTexels, bn);
+        sum = madd(sum, wgt, e);
+        wsum += wgt;
+    }
+    return rcp(wsum) * sum;
+}
+
+// view-path bias: move y toward x by min(d, |x - y|/2)
+__device__ __forceinline__ V3 view_bias(V3 y, V3 x, float d)
+{
+    V3 v = x - y;
+    float d2 = dot(v, v);
+    float id = frsq(d2);
+    float s = fminf(d, 0.5f * d2 * id);
+    return madd(y, s * id, v);
+}
+
+// L_e(y) + rho_y Q(y_b, n_y), y_b biased toward x
+__device__ __forceinline__ V3 radiance_toward(const gi_scene &sc, const gi_probes &pr, uint32_t prim, V3 y, V3 ny, V3 x)
+{
+    V3 alb, emit;
+    material(sc, prim, alb, emit);
+    if (is_zero(alb)) return emit;
+    V3 q = probe_query(pr, view_bias(y, x, pr.bias_dist), ny);
+    return v3(fmaf(alb.x, q.x, emit.x), fmaf(alb.y, q.y, emit.y), fmaf(alb.z, q.z, emit.z));
+}
+
+// --------------------------------------------------------------------------
+// reservoirs
+// --------------------------------------------------------------------------
+struct Res {
+    V3 y;
+    float W;
+    V3 n;
+    float wsum;
+    V3 L;
+    uint32_t M;
+    uint32_t tag, prim;
+};
+
+__device__ __forceinline__ Res load_res(const gi_reservoirs &r, uint32_t p)
+{
+    float4 a = reinterpret_cast<const float4 *>(r.y_W)[p];
+    float4 b = reinterpret_cast<const float4 *>(r.n_wsum)[p];
+    float4 c = reinterpret_cast<const float4 *>(r.L_M)[p];
+    uint2 d = reinterpret_cast<const uint2 *>(r.tag_prim)[p];
+    return Res{xyz(a), a.w, xyz(b), b.w, xyz(c), __float_as_uint(c.w), d.x, d.y};
+}
+
+__device__ __forceinline__ void store_res(const gi_reservoirs &r, uint32_t p, const Res &s)
+{
+    reinterpret_cast<float4 *>(r.y_W)[p] = make_float4(s.y.x, s.y.y, s.y.z, s.W);
+    reinterpret_cast<float4 *>(r.n_wsum)[p] = make_float4(s.n.x, s.n.y, s.n.z, s.wsum);
+    reinterpret_cast<float4 *>(r.L_M)[p] = make_float4(s.L.x, s.L.y, s.L.z, __uint_as_float(s.M));
+    reinterpret_cast<uint2 *>(r.tag_prim)[p] = make_uint2(s.tag, s.prim);
+}
+
+__device__ __forceinline__ Res empty_res(uint32_t M)
+{
+    Res r;
+    r.y = r.n = r.L = v3(0.0f, 0.0f, 0.0f);
+    r.W = r.wsum = 0.0f;
+    r.M = M;
+    r.tag = GI_EMPTY_TAG;
+    r.prim = GI_MISS;
+    return r;
+}
+
+// target p_hat at (x, n_x, rho_x) for a sample with cached radiance L
+__device__ __forceinline__ float target(V3 x, V3 nx, V3 rho, V3 y, V3 ny, V3 L, float g_max)
+{
+    float fl = kInvPi * lum(rho * L);
+    if (is_zero(ny)) {
+        float cx = dot(nx, y);
+        return cx > 0.0f ? fl * cx : 0.0f;
+    }
+    V3 v = y - x;
+    float d2 = dot(v, v);
+    V3 w = frsq(d2) * v;
+    float cx = dot(nx, w), cy = -dot(ny, w);
+    if (cx <= 0.0f || cy <= 0.0f) return 0.0f;
+    float G = cx * cy * rcp(d2);
+    return fl * fminf(G, g_max);
+}
+
+}  // namespace gi

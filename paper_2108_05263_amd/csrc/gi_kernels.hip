@@ -1,0 +1,792 @@
+// HIP kernels and C-ABI launchers of the DDGI-resampling path (gfx950).
+//
+// Per-pixel kernels use 256-thread workgroups over 16x16 pixel tiles, each
+// wave64 covering an 8x8 sub-tile, so SoA float4 plane accesses of a wave
+// fill whole 128-byte lines and neighbouring pixels share cache lines of the
+// grid, probes and reservoirs.  One kernel per C-ABI entry point; all state
+// lives in caller-owned buffers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "gi.h"
+#include "gi_device.hpp"
+
+using namespace gi;
+
+namespace {
+
+constexpr int kTile = 16;
+constexpr int kBlock = 256;
+
+// Workgroups are dealt round-robin to the chip's 8 XCDs (each with its own
+// L2).  Workgroup L runs on XCD L % 8; it is given tile (L % 8) * chunk +
+// L / 8 of the row-major tile order, so every XCD works through one
+// contiguous band of the image and its L2 sees the scene and probes that
+// band's rays reach, instead of rays from the whole frame.
+#ifndef GI_XCD_BANDS
+#define GI_XCD_BANDS 0
+#endif
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ bool tile_pixel(uint32_t W, uint32_t H, uint32_t &px, uint32_t &py)
+{
+    uint32_t t = threadIdx.x, w = t >> 6, l = t & 63u;
+    uint32_t tx, ty;
+#if GI_XCD_BANDS
+    uint32_t tiles_x = (W + kTile - 1) / kTile, tiles = tiles_x * ((H + kTile - 1) / kTile);
+    uint32_t chunk = (tiles + kXcds - 1) / kXcds;
+    uint32_t tile = (blockIdx.x % kXcds) * chunk + blockIdx.x / kXcds;
+    if (tile >= tiles) return false;
+    tx = tile % tiles_x;
+    ty = tile / tiles_x;
+#else
+    tx = blockIdx.x;
+    ty = blockIdx.y;
+#endif
+    px = tx * kTile + (w & 1u) * 8u + (l & 7u);
+    py = ty * kTile + (w >> 1) * 8u + (l >> 3);
+    return px < W && py < H;
+}
+
+dim3 tile_grid(uint32_t W, uint32_t H)
+{
+    uint32_t tx = (W + kTile - 1) / kTile, ty = (H + kTile - 1) / kTile;
+#if GI_XCD_BANDS
+    uint32_t chunk = (tx * ty + kXcds - 1) / kXcds;
+    return dim3(chunk * kXcds);
+#else
+    return dim3(tx, ty);
+#endif
+}
+
+struct GB {
+    V3 pos;
+    float depth;
+    V3 n;
+    uint32_t prim;
+    V3 alb;
+};
+
+__device__ __forceinline__ GB load_gb(const gi_gbuffer &g, uint32_t p)
+{
+    float4 a = reinterpret_cast<const float4 *>(g.pos_depth)[p];
+    float4 b = reinterpret_cast<const float4 *>(g.nrm_prim)[p];
+    float4 c = reinterpret_cast<const float4 *>(g.albedo)[p];
+    return GB{xyz(a), a.w, xyz(b), __float_as_uint(b.w), xyz(c)};
+}
+
+__device__ __forceinline__ bool active(const GB &g) { return g.prim != GI_MISS && !is_zero(g.alb); }
+
+__device__ __forceinline__ bool similar(const GB &g, const GB &q, const gi_params &pp)
+{
+    if (q.prim == GI_MISS) return false;
+    if (dot(g.n, q.n) < pp.cos_n) return false;
+    if (fabsf(g.depth - q.depth) > pp.depth_rel * g.depth) return false;
+    return true;
+}
+
+__device__ __forceinline__ float res_target(const GB &g, const Res &r, float g_max)
+{
+    return target(g.pos, g.n, g.alb, r.y, r.n, r.L, g_max);
+}
+
+// --------------------------------------------------------------------------
+// primary vertices
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_gbuffer(gi_scene sc, gi_camera cam, gi_gbuffer gb)
+{
+    uint32_t px, py;
+    if (!tile_pixel(cam.width, cam.height, px, py)) return;
+    uint32_t p = py * cam.width + px;
+    float aspect = (float)cam.width / (float)cam.height;
+    float sx = (2.0f * ((float)px + 0.5f) / (float)cam.width - 1.0f) * cam.tan_half_fovy * aspect;
+    float sy = (1.0f - 2.0f * ((float)py + 0.5f) / (float)cam.height) * cam.tan_half_fovy;
+    V3 d = ld3(cam.fwd) + sx * ld3(cam.right) + sy * ld3(cam.up);
+    d = rsqrtf(dot(d, d)) * d;
+    V3 o = ld3(cam.eye);
+    Hit h;
+    float4 *pd = reinterpret_cast<float4 *>(gb.pos_depth);
+    float4 *np = reinterpret_cast<float4 *>(gb.nrm_prim);
+    float4 *al = reinterpret_cast<float4 *>(gb.albedo);
+    float4 *em = reinterpret_cast<float4 *>(gb.emit);
+    if (!cast<false>(sc, o, d, kInf, h)) {
+        pd[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        np[p] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(GI_MISS));
+        al[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        em[p] = make_float4(sc.sky[0], sc.sky[1], sc.sky[2], 0.0f);
+        return;
+    }
+    V3 x = madd(o, h.t, d);
+    V3 n = hit_normal(sc, o, d, h);
+    V3 alb, emit;
+    material(sc, h.prim, alb, emit);
+    pd[p] = make_float4(x.x, x.y, x.z, h.t * dot(d, ld3(cam.fwd)));
+    np[p] = make_float4(n.x, n.y, n.z, __uint_as_float(h.prim));
+    al[p] = make_float4(alb.x, alb.y, alb.z, 0.0f);
+    em[p] = make_float4(emit.x, emit.y, emit.z, 0.0f);
+}
+
+// --------------------------------------------------------------------------
+// probe update: one workgroup per probe
+// --------------------------------------------------------------------------
+constexpr int kProbeBlock = 256;
+
+// Interior texel (row-major index into the N x N interior) that padded texel
+// (x, y) shows: the interior itself, or for a gutter texel the interior texel
+// mirrored along the tile edge (applied first across rows, then across
+// columns, which maps a corner to the diagonally opposite interior corner).
+__device__ __forceinline__ int gutter_source(int x, int y, int N)
+{
+    int sx = x, sy = y;
+    if (sy == 0 || sy == N + 1) { sx = N + 1 - sx; sy = sy == 0 ? 1 : N; }
+    if (sx == 0 || sx == N + 1) { sy = N + 1 - sy; sx = sx == 0 ? 1 : N; }
+    return (sy - 1) * N + (sx - 1);
+}
+
+__global__ void __launch_bounds__(kProbeBlock)
+    k_probe_update(gi_scene sc, gi_probes in, gi_probes out, gi_probe_params pp, uint64_t seed, uint32_t frame)
+{
+    __shared__ float s_dir[GI_MAX_PROBE_RAYS][3];
+    __shared__ float s_L[GI_MAX_PROBE_RAYS][3];
+    __shared__ float s_d[GI_MAX_PROBE_RAYS];
+    __shared__ float s_irr[8 * 8][3];
+    __shared__ float s_dep[16 * 16][2];
+    const uint32_t pi = blockIdx.x;
+    const uint32_t ix = pi % in.dims[0], iy = (pi / in.dims[0]) % in.dims[1], iz = pi / (in.dims[0] * in.dims[1]);
+    const V3 P = v3(in.lo[0] + ((float)ix + 0.5f) * in.spacing[0], in.lo[1] + ((float)iy + 0.5f) * in.spacing[1],
+                    in.lo[2] + ((float)iz + 0.5f) * in.spacing[2]);
+    const uint32_t R = pp.rays;
+    for (uint32_t r = threadIdx.x; r < R; r += kProbeBlock) {
+        uint4 rn = philox(seed, pi, frame, kPassProbe, r);
+        V3 w = sphere_dir(u01(rn.x), u01(rn.y));
+        Hit h;
+        V3 L;
+        float dist;
+        if (cast<false>(sc, P, w, kInf, h)) {
+            V3 hp = madd(P, h.t, w);
+            V3 n = hit_normal(sc, P, w, h);
+            V3 alb, emit;
+            material(sc, h.prim, alb, emit);
+            L = emit;
+            if (!is_zero(alb)) {
+                V3 q = probe_query(in, view_bias(hp, P, in.bias_dist), n);
+                L = v3(fmaf(alb.x, q.x, emit.x), fmaf(alb.y, q.y, emit.y), fmaf(alb.z, q.z, emit.z));
+            }
+            dist = fminf(h.t, in.d_max);
+        } else {
+            L = ld3(sc.sky);
+            dist = in.d_max;
+        }
+        s_dir[r][0] = w.x;
+        s_dir[r][1] = w.y;
+        s_dir[r][2] = w.z;
+        s_L[r][0] = L.x;
+        s_L[r][1] = L.y;
+        s_L[r][2] = L.z;
+        s_d[r] = dist;
+    }
+    __syncthreads();
+    const float4 *iold = reinterpret_cast<const float4 *>(in.irr) + (size_t)pi * kIrrTexels;
+    const float2 *dold = reinterpret_cast<const float2 *>(in.dep) + (size_t)pi * kDepTexels;
+    const float hy = pp.hysteresis;
+    {   // depth texel t (16x16)
+        uint32_t t = threadIdx.x;
+        uint32_t tx = t & 15u, ty = t >> 4;
+        V3 nt = oct_decode(((float)tx + 0.5f) / 16.0f, ((float)ty + 0.5f) / 16.0f);
+        float m1 = 0.0f, m2 = 0.0f, den = 0.0f;
+        for (uint32_t r = 0; r < R; ++r) {
+            float c = nt.x * s_dir[r][0] + nt.y * s_dir[r][1] + nt.z * s_dir[r][2];
+            if (c > 0.0f) {
+                float w = exp2f(pp.sharpness * __log2f(c));
+                float d = s_d[r];
+                m1 = fmaf(w, d, m1);
+                m2 = fmaf(w, d * d, m2);
+                den += w;
+            }
+        }
+        float2 old = dold[(ty + 1) * 18 + tx + 1];
+        float n1 = den > 0.0f ? m1 / den : old.x;
+        float n2 = den > 0.0f ? m2 / den : old.y;
+        s_dep[t][0] = hy * old.x + (1.0f - hy) * n1;
+        s_dep[t][1] = hy * old.y + (1.0f - hy) * n2;
+    }
+    if (threadIdx.x < 64) {   // irradiance texel t (8x8)
+        uint32_t t = threadIdx.x;
+        uint32_t tx = t & 7u, ty = t >> 3;
+        V3 nt = oct_decode(((float)tx + 0.5f) / 8.0f, ((float)ty + 0.5f) / 8.0f);
+        V3 num = v3(0.0f, 0.0f, 0.0f);
+        float den = 0.0f;
+        for (uint32_t r = 0; r < R; ++r) {
+            float c = nt.x * s_dir[r][0] + nt.y * s_dir[r][1] + nt.z * s_dir[r][2];
+            if (c > 0.0f) {
+                num = v3(fmaf(c, s_L[r][0], num.x), fmaf(c, s_L[r][1], num.y), fmaf(c, s_L[r][2], num.z));
+                den += c;
+            }
+        }
+        float4 old = iold[(ty + 1) * 10 + tx + 1];
+        float id = 1.0f / den;
+        V3 nv = den > 0.0f ? id * num : xyz(old);
+        s_irr[t][0] = hy * old.x + (1.0f - hy) * nv.x;
+        s_irr[t][1] = hy * old.y + (1.0f - hy) * nv.y;
+        s_irr[t][2] = hy * old.z + (1.0f - hy) * nv.z;
+    }
+    __syncthreads();
+    // write padded tiles: an interior texel or the interior texel a gutter mirrors
+    float4 *iout = reinterpret_cast<float4 *>(out.irr) + (size_t)pi * kIrrTexels;
+    float2 *dout = reinterpret_cast<float2 *>(out.dep) + (size_t)pi * kDepTexels;
+    for (uint32_t t = threadIdx.x; t < (uint32_t)kDepTexels; t += kProbeBlock) {
+        int s = gutter_source((int)(t % 18u), (int)(t / 18u), 16);
+        dout[t] = make_float2(s_dep[s][0], s_dep[s][1]);
+    }
+    for (uint32_t t = threadIdx.x; t < (uint32_t)kIrrTexels; t += kProbeBlock) {
+        int s = gutter_source((int)(t % 10u), (int)(t / 10u), 8);
+        iout[t] = make_float4(s_irr[s][0], s_irr[s][1], s_irr[s][2], 0.0f);
+    }
+}
+
+__global__ void k_probe_query(gi_probes pr, uint32_t n, const float *p, const float *nrm, float *out)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    V3 q = probe_query(pr, ld3(p + 3 * i), ld3(nrm + 3 * i));
+    out[3 * i] = q.x;
+    out[3 * i + 1] = q.y;
+    out[3 * i + 2] = q.z;
+}
+
+// --------------------------------------------------------------------------
+// initial resampling
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+    k_initial(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_params pp, gi_reservoirs out, float4 *resid,
+              uint64_t seed, uint32_t frame)
+{
+    uint32_t px, py;
+    if (!tile_pixel(gb.width, gb.height, px, py)) return;
+    const uint32_t p = py * gb.width + px;
+    const GB g = load_gb(gb, p);
+    V3 rs = v3(0.0f, 0.0f, 0.0f);
+    if (!active(g)) {
+        store_res(out, p, empty_res(0));
+        resid[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
+    }
+    const V3 o = madd(g.pos, sc.eps, g.n);
+    const V3 rho_pi = kInvPi * g.alb;
+    Res r = empty_res(pp.M);
+    float wsum = 0.0f, p_sel = 0.0f;
+    bool have = false;
+    for (uint32_t i = 0; i < pp.M; ++i) {
+        uint4 rn = philox(seed, p, frame, kPassInitial, i);
+        V3 w = cosine_dir(g.n, u01(rn.x), u01(rn.y));
+        float u2 = u01(rn.z);
+        Hit h;
+        V3 y, ny = v3(0.0f, 0.0f, 0.0f), L = v3(0.0f, 0.0f, 0.0f);
+        float phat = 0.0f, wi = 0.0f;
+        uint32_t prim = GI_MISS;
+        if (cast<false>(sc, o, w, kInf, h)) {
+            y = madd(o, h.t, w);
+            ny = hit_normal(sc, o, w, h);
+            prim = h.prim;
+            V3 v = y - g.pos;
+            float d2 = dot(v, v);
+            V3 wv = frsq(d2) * v;
+            float cx = dot(g.n, wv), cy = -dot(ny, wv);
+            if (cx > 0.0f && cy > 0.0f) {
+                L = radiance_toward(sc, pr, prim, y, ny, g.pos);
+                float G = cx * cy * rcp(d2);
+                float fl = lum(rho_pi * L);
+                float iG = rcp(G);
+                phat = fl * fminf(G, pp.g_max);
+                wi = kPi * phat * iG;   // p_hat / p_A with p_A = G / pi
+                if (i == 0 && G > pp.g_max) rs = (1.0f - pp.g_max * iG) * (g.alb * L);
+            }
+        } else {
+            y = w;
+            L = ld3(sc.sky);
+            float cx = dot(g.n, w);
+            if (cx > 0.0f) {
+                phat = lum(rho_pi * L) * cx;
+                wi = kPi * phat * rcp(cx);
+            }
+        }
+        wsum += wi;
+        if (u2 * wsum < wi) {
+            have = true;
+            p_sel = phat;
+            r.y = y;
+            r.n = ny;
+            r.L = L;
+            r.tag = ((p & 0x7FFFFFu) << 9) | ((i & 31u) << 4) | (frame & 15u);
+            r.prim = prim;
+        }
+    }
+    r.wsum = wsum;
+    r.W = (have && p_sel > 0.0f) ? wsum * rcp((float)pp.M * p_sel) : 0.0f;
+    store_res(out, p, r);
+    resid[p] = make_float4(rs.x, rs.y, rs.z, 0.0f);
+}
+
+// --------------------------------------------------------------------------
+// reservoir merging (temporal and spatial reuse)
+// --------------------------------------------------------------------------
+struct Merge {
+    float wsum;
+    uint32_t Msum;
+    bool have;
+    Res sel;
+};
+
+__device__ __forceinline__ void merge_in(Merge &m, const GB &g, const Res &q, uint32_t Mq, float u, float g_max)
+{
+    float w = 0.0f;
+    if (q.W > 0.0f && Mq > 0u) w = res_target(g, q, g_max) * q.W * (float)Mq;
+    m.wsum += w;
+    m.Msum += Mq;
+    if (u * m.wsum < w) {
+        m.have = true;
+        m.sel = q;
+    }
+}
+
+constexpr int kMaxDom = GI_MAX_K + 1;
+
+// Normalise the merged reservoir.  Domain slot j holds M_j (0 = slot unused:
+// a neighbour that was rejected or never drawn) and is loaded by dom(j);
+// slot 0 is the pixel itself.  Slots are static so that the unrolled loop
+// keeps everything in registers.
+template <int ND, class DomFn>
+__device__ __forceinline__ Res finish(const gi_scene &sc, const Merge &m, const GB &g, const uint32_t (&Mdom)[ND],
+                                      DomFn dom, const gi_params &pp)
+{
+    if (!m.have) {
+        Res e = empty_res(m.Msum);
+        e.wsum = m.wsum;
+        return e;
+    }
+    Res r = m.sel;
+    float ph = res_target(g, r, pp.g_max);
+    float Z;
+    bool keep = true;
+    if (pp.unbiased) {
+        bool sky = is_zero(r.n);
+        bool vis_x = visible(sc, g.pos, g.n, r.y, r.n, sky);
+        keep = vis_x;
+        uint32_t z = vis_x ? Mdom[0] : 0u;     // the target at x supports y (it was chosen)
+#pragma unroll
+        for (int j = 1; j < ND; ++j) {
+            if (Mdom[j] == 0u) continue;
+            GB q = dom(j);
+            if (res_target(q, r, pp.g_max) <= 0.0f) continue;
+            if (visible(sc, q.pos, q.n, r.y, r.n, sky)) z += Mdom[j];
+        }
+        Z = (float)z;
+    } else {
+        Z = (float)m.Msum;
+    }
+    r.wsum = m.wsum;
+    r.M = m.Msum;
+    r.W = (keep && Z > 0.0f && ph > 0.0f) ? m.wsum * rcp(Z * ph) : 0.0f;
+    return r;
+}
+
+__device__ __forceinline__ int reproject(const gi_camera &c, V3 x)
+{
+    V3 v = x - ld3(c.eye);
+    float z = dot(v, ld3(c.fwd));
+    if (z <= 0.0f) return -1;
+    float aspect = (float)c.width / (float)c.height;
+    float sx = dot(v, ld3(c.right)) / (z * c.tan_half_fovy * aspect);
+    float sy = dot(v, ld3(c.up)) / (z * c.tan_half_fovy);
+    float fx = floorf((sx + 1.0f) * 0.5f * (float)c.width);
+    float fy = floorf((1.0f - sy) * 0.5f * (float)c.height);
+    if (!(fx >= 0.0f && fy >= 0.0f && fx < (float)c.width && fy < (float)c.height)) return -1;
+    return (int)fy * (int)c.width + (int)fx;
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_temporal(gi_scene sc, gi_gbuffer gb, gi_gbuffer gbp, gi_camera cam_prev, gi_reservoirs cur,
+               gi_reservoirs hist, gi_params pp, gi_reservoirs out, uint64_t seed, uint32_t frame)
+{
+    uint32_t px, py;
+    if (!tile_pixel(gb.width, gb.height, px, py)) return;
+    const uint32_t p = py * gb.width + px;
+    const GB g = load_gb(gb, p);
+    const Res rc = load_res(cur, p);
+    if (!active(g)) {
+        store_res(out, p, rc);
+        return;
+    }
+    Merge m{0.0f, 0u, false, rc};
+    uint32_t Mdom[2] = {rc.M, 0u};
+    uint32_t qprev = 0u;
+    merge_in(m, g, rc, rc.M, 0.0f, pp.g_max);
+    int q = reproject(cam_prev, g.pos);
+    if (q >= 0) {
+        GB gq = load_gb(gbp, (uint32_t)q);
+        if (similar(g, gq, pp)) {
+            Res rh = load_res(hist, (uint32_t)q);
+            float cap = pp.m_cap * (float)rc.M;
+            uint32_t Mh = (float)rh.M > cap ? (uint32_t)cap : rh.M;
+            uint4 rn = philox(seed, p, frame, kPassTemporal, 0u);
+            merge_in(m, g, rh, Mh, u01(rn.x), pp.g_max);
+            Mdom[1] = Mh;
+            qprev = (uint32_t)q;
+        }
+    }
+    store_res(out, p, finish(sc, m, g, Mdom, [&](int) { return load_gb(gbp, qprev); }, pp));
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_spatial(gi_scene sc, gi_gbuffer gb, gi_reservoirs in, gi_params pp, uint32_t pass, gi_reservoirs out,
+              uint64_t seed, uint32_t frame)
+{
+    uint32_t px, py;
+    if (!tile_pixel(gb.width, gb.height, px, py)) return;
+    const uint32_t W = gb.width, H = gb.height;
+    const uint32_t p = py * W + px;
+    const GB g = load_gb(gb, p);
+    const Res rc = load_res(in, p);
+    if (!active(g)) {
+        store_res(out, p, rc);
+        return;
+    }
+    Merge m{0.0f, 0u, false, rc};
+    uint32_t Mdom[kMaxDom], qidx[kMaxDom];
+    Mdom[0] = rc.M;
+    qidx[0] = p;
+    merge_in(m, g, rc, rc.M, 0.0f, pp.g_max);
+#pragma unroll
+    for (uint32_t j = 0; j < GI_MAX_K; ++j) {
+        Mdom[j + 1] = 0u;
+        qidx[j + 1] = p;
+        if (j >= pp.k) continue;
+        uint4 rn = philox(seed, p, frame, kPassSpatial0 + pass, j);
+        float rad = pp.radius * fsqrt(u01(rn.x));
+        float s_ = sin_rev(u01(rn.y)), c_ = cos_rev(u01(rn.y));
+        int qx = (int)px + (int)floorf(rad * c_ + 0.5f);
+        int qy = (int)py + (int)floorf(rad * s_ + 0.5f);
+        if (qx < 0 || qy < 0 || qx >= (int)W || qy >= (int)H) continue;
+        if (qx == (int)px && qy == (int)py) continue;
+        uint32_t q = (uint32_t)qy * W + (uint32_t)qx;
+        GB gq = load_gb(gb, q);
+        if (!similar(g, gq, pp)) continue;
+        Res rq = load_res(in, q);
+        merge_in(m, g, rq, rq.M, u01(rn.z), pp.g_max);
+        Mdom[j + 1] = rq.M;
+        qidx[j + 1] = q;
+    }
+    store_res(out, p, finish(sc, m, g, Mdom, [&](int j) { return load_gb(gb, qidx[j]); }, pp));
+}
+
+// --------------------------------------------------------------------------
+// shading
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+    k_shade(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_reservoirs res, const float4 *resid, gi_params pp,
+            float4 *img)
+{
+    uint32_t px, py;
+    if (!tile_pixel(gb.width, gb.height, px, py)) return;
+    const uint32_t p = py * gb.width + px;
+    const GB g = load_gb(gb, p);
+    float4 e = reinterpret_cast<const float4 *>(gb.emit)[p];
+    V3 o = xyz(e);
+    if (g.prim != GI_MISS) {
+        o = o + xyz(resid[p]);
+        Res r = load_res(res, p);
+        if (r.W > 0.0f) {
+            V3 L;
+            float geo = 0.0f;
+            bool ok = false;
+            if (is_zero(r.n)) {
+                geo = dot(g.n, r.y);
+                if (geo > 0.0f && visible(sc, g.pos, g.n, r.y, r.n, true)) {
+                    L = ld3(sc.sky);
+                    ok = true;
+                }
+            } else {
+                V3 v = r.y - g.pos;
+                float d2 = dot(v, v);
+                V3 w = frsq(d2) * v;
+                float cx = dot(g.n, w), cy = -dot(r.n, w);
+                if (cx > 0.0f && cy > 0.0f) {
+                    geo = fminf(cx * cy * rcp(d2), pp.g_max);
+                    if (visible(sc, g.pos, g.n, r.y, r.n, false)) {
+                        L = radiance_toward(sc, pr, r.prim, r.y, r.n, g.pos);
+                        ok = true;
+                    }
+                }
+            }
+            if (ok) o = o + (kInvPi * geo * r.W) * (g.alb * L);
+        }
+    }
+    img[p] = make_float4(o.x, o.y, o.z, 1.0f);
+}
+
+// --------------------------------------------------------------------------
+// test hooks
+// --------------------------------------------------------------------------
+__global__ void k_philox(uint64_t seed, uint32_t n, const uint4 *ctr, uint4 *out)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint4 c = ctr[i];
+    out[i] = philox(seed, c.x, c.y, c.z, c.w);
+}
+
+__global__ void k_trace(gi_scene sc, uint32_t n, const float *org, const float *dir, float4 *out, uint32_t *prim)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    V3 o = ld3(org + 3 * i), d = ld3(dir + 3 * i);
+    Hit h;
+    if (cast<false>(sc, o, d, kInf, h)) {
+        V3 nn = hit_normal(sc, o, d, h);
+        out[i] = make_float4(h.t, nn.x, nn.y, nn.z);
+        prim[i] = h.prim;
+    } else {
+        out[i] = make_float4(kInf, 0.0f, 0.0f, 0.0f);
+        prim[i] = GI_MISS;
+    }
+}
+
+// --------------------------------------------------------------------------
+// host-side validation
+// --------------------------------------------------------------------------
+gi_status launched()
+{
+    return hipGetLastError() == hipSuccess ? GI_OK : GI_ERR_LAUNCH;
+}
+
+gi_status check_scene(const gi_scene *sc)
+{
+    if (!sc) return GI_ERR_NULL;
+    if (sc->n_prims > 0 && !sc->prims) return GI_ERR_NULL;
+    if (!(sc->eps >= 0.0f)) return GI_ERR_PARAM;
+    if (sc->cell_start) {
+        if (!sc->cell_items) return GI_ERR_NULL;
+        if (sc->grid_res[0] == 0 || sc->grid_res[1] == 0 || sc->grid_res[2] == 0) return GI_ERR_SHAPE;
+        if ((uint64_t)sc->grid_res[0] * sc->grid_res[1] * sc->grid_res[2] > (1u << 26)) return GI_ERR_SHAPE;
+        for (int a = 0; a < 3; ++a)
+            if (!(sc->grid_hi[a] > sc->grid_lo[a])) return GI_ERR_PARAM;
+    }
+    return GI_OK;
+}
+
+gi_status check_gb(const gi_gbuffer *g, uint32_t W, uint32_t H)
+{
+    if (!g || !g->pos_depth || !g->nrm_prim || !g->albedo || !g->emit) return GI_ERR_NULL;
+    if (g->width != W || g->height != H) return GI_ERR_SHAPE;
+    return GI_OK;
+}
+
+gi_status check_res(const gi_reservoirs *r, uint32_t W, uint32_t H)
+{
+    if (!r || !r->y_W || !r->n_wsum || !r->L_M || !r->tag_prim) return GI_ERR_NULL;
+    if (r->width != W || r->height != H) return GI_ERR_SHAPE;
+    return GI_OK;
+}
+
+bool res_alias(const gi_reservoirs *a, const gi_reservoirs *b)
+{
+    const void *pa[4] = {a->y_W, a->n_wsum, a->L_M, a->tag_prim};
+    const void *pb[4] = {b->y_W, b->n_wsum, b->L_M, b->tag_prim};
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            if (pa[i] == pb[j]) return true;
+    return false;
+}
+
+gi_status check_probes(const gi_probes *p)
+{
+    if (!p || !p->irr || !p->dep) return GI_ERR_NULL;
+    if (p->irr_res != 8 || p->dep_res != 16) return GI_ERR_SHAPE;
+    if (p->dims[0] == 0 || p->dims[1] == 0 || p->dims[2] == 0) return GI_ERR_SHAPE;
+    if ((uint64_t)p->dims[0] * p->dims[1] * p->dims[2] > (1u << 24)) return GI_ERR_SHAPE;
+    for (int a = 0; a < 3; ++a)
+        if (!(p->spacing[a] > 0.0f)) return GI_ERR_PARAM;
+    return GI_OK;
+}
+
+gi_status check_params(const gi_params *pp)
+{
+    if (!pp) return GI_ERR_NULL;
+    if (pp->M < 1 || pp->M > GI_MAX_M || pp->k > GI_MAX_K) return GI_ERR_PARAM;
+    if (!(pp->radius >= 0.0f) || !(pp->g_max > 0.0f) || !(pp->m_cap >= 0.0f) || !(pp->depth_rel >= 0.0f))
+        return GI_ERR_PARAM;
+    return GI_OK;
+}
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+const char *gi_status_string(gi_status s)
+{
+    switch (s) {
+    case GI_OK: return "ok";
+    case GI_ERR_NULL: return "null pointer";
+    case GI_ERR_SHAPE: return "shape mismatch or size limit";
+    case GI_ERR_PARAM: return "parameter out of range";
+    case GI_ERR_ALIAS: return "output aliases an input";
+    case GI_ERR_LAUNCH: return "kernel launch failed";
+    case GI_ERR_DEVICE: return "no usable HIP device";
+    }
+    return "unknown status";
+}
+
+int gi_device(void)
+{
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess) return -1;
+    return d;
+}
+
+gi_status gi_trace_gbuffer(const gi_scene *scene, const gi_camera *cam, gi_gbuffer *out, void *stream)
+{
+    gi_status s;
+    if (!cam || !out) return GI_ERR_NULL;
+    if ((s = check_scene(scene)) != GI_OK) return s;
+    if (cam->width == 0 || cam->height == 0) return GI_ERR_SHAPE;
+    if ((s = check_gb(out, cam->width, cam->height)) != GI_OK) return s;
+    k_gbuffer<<<tile_grid(cam->width, cam->height), kBlock, 0, S(stream)>>>(*scene, *cam, *out);
+    return launched();
+}
+
+gi_status gi_probe_update(const gi_scene *scene, const gi_probes *in, gi_probes *out, const gi_probe_params *pp,
+                          uint64_t seed, uint32_t frame, void *stream)
+{
+    gi_status s;
+    if (!pp || !out) return GI_ERR_NULL;
+    if ((s = check_scene(scene)) != GI_OK) return s;
+    if ((s = check_probes(in)) != GI_OK) return s;
+    if ((s = check_probes(out)) != GI_OK) return s;
+    for (int a = 0; a < 3; ++a)
+        if (in->dims[a] != out->dims[a]) return GI_ERR_SHAPE;
+    if (in->irr == out->irr || in->dep == out->dep || in->irr == out->dep || in->dep == out->irr)
+        return GI_ERR_ALIAS;
+    if (pp->rays < 1 || pp->rays > GI_MAX_PROBE_RAYS) return GI_ERR_PARAM;
+    if (!(pp->hysteresis >= 0.0f && pp->hysteresis <= 1.0f) || !(pp->sharpness > 0.0f)) return GI_ERR_PARAM;
+    uint32_t P = in->dims[0] * in->dims[1] * in->dims[2];
+    k_probe_update<<<P, kProbeBlock, 0, S(stream)>>>(*scene, *in, *out, *pp, seed, frame);
+    return launched();
+}
+
+gi_status gi_probe_query(const gi_probes *probes, uint32_t n, const float *p, const float *nrm, float *out,
+                         void *stream)
+{
+    gi_status s;
+    if ((s = check_probes(probes)) != GI_OK) return s;
+    if (n == 0) return GI_OK;
+    if (!p || !nrm || !out) return GI_ERR_NULL;
+    k_probe_query<<<(n + 255) / 256, 256, 0, S(stream)>>>(*probes, n, p, nrm, out);
+    return launched();
+}
+
+gi_status gi_resample_initial(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes,
+                              const gi_params *params, gi_reservoirs *out, float *resid, uint64_t seed,
+                              uint32_t frame, void *stream)
+{
+    gi_status s;
+    if (!gb || !out || !resid) return GI_ERR_NULL;
+    if ((s = check_scene(scene)) != GI_OK) return s;
+    if ((s = check_gb(gb, gb->width, gb->height)) != GI_OK) return s;
+    if ((s = check_probes(probes)) != GI_OK) return s;
+    if ((s = check_params(params)) != GI_OK) return s;
+    if ((s = check_res(out, gb->width, gb->height)) != GI_OK) return s;
+    if ((uint64_t)gb->width * gb->height > (1u << 23)) return GI_ERR_SHAPE;   // 23-bit tag origin
+    if (gb->width == 0 || gb->height == 0) return GI_OK;
+    k_initial<<<tile_grid(gb->width, gb->height), kBlock, 0, S(stream)>>>(
+        *scene, *gb, *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame);
+    return launched();
+}
+
+gi_status gi_resample_temporal(const gi_scene *scene, const gi_gbuffer *gb, const gi_gbuffer *gb_prev,
+                               const gi_camera *prev_cam, const gi_reservoirs *cur_in,
+                               const gi_reservoirs *history, const gi_params *params, gi_reservoirs *out,
+                               uint64_t seed, uint32_t frame, void *stream)
+{
+    gi_status s;
+    if (!gb || !gb_prev || !prev_cam || !cur_in || !history || !out) return GI_ERR_NULL;
+    uint32_t W = gb->width, H = gb->height;
+    if ((s = check_scene(scene)) != GI_OK) return s;
+    if ((s = check_gb(gb, W, H)) != GI_OK) return s;
+    if ((s = check_gb(gb_prev, W, H)) != GI_OK) return s;
+    if (prev_cam->width != W || prev_cam->height != H) return GI_ERR_SHAPE;
+    if ((s = check_params(params)) != GI_OK) return s;
+    if ((s = check_res(cur_in, W, H)) != GI_OK) return s;
+    if ((s = check_res(history, W, H)) != GI_OK) return s;
+    if ((s = check_res(out, W, H)) != GI_OK) return s;
+    if (res_alias(out, cur_in) || res_alias(out, history)) return GI_ERR_ALIAS;
+    if (W == 0 || H == 0) return GI_OK;
+    k_temporal<<<tile_grid(W, H), kBlock, 0, S(stream)>>>(*scene, *gb, *gb_prev, *prev_cam, *cur_in, *history,
+                                                         *params, *out, seed, frame);
+    return launched();
+}
+
+gi_status gi_resample_spatial(const gi_scene *scene, const gi_gbuffer *gb, const gi_reservoirs *in,
+                              const gi_params *params, uint32_t pass, gi_reservoirs *out, uint64_t seed,
+                              uint32_t frame, void *stream)
+{
+    gi_status s;
+    if (!gb || !in || !out) return GI_ERR_NULL;
+    uint32_t W = gb->width, H = gb->height;
+    if ((s = check_scene(scene)) != GI_OK) return s;
+    if ((s = check_gb(gb, W, H)) != GI_OK) return s;
+    if ((s = check_params(params)) != GI_OK) return s;
+    if ((s = check_res(in, W, H)) != GI_OK) return s;
+    if ((s = check_res(out, W, H)) != GI_OK) return s;
+    if (res_alias(out, in)) return GI_ERR_ALIAS;
+    if (pass > 5) return GI_ERR_PARAM;
+    if (W == 0 || H == 0) return GI_OK;
+    k_spatial<<<tile_grid(W, H), kBlock, 0, S(stream)>>>(*scene, *gb, *in, *params, pass, *out, seed, frame);
+    return launched();
+}
+
+gi_status gi_shade(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes, const gi_reservoirs *res,
+                   const float *resid, const gi_params *params, float *out_rgba, void *stream)
+{
+    gi_status s;
+    if (!gb || !res || !resid || !out_rgba) return GI_ERR_NULL;
+    uint32_t W = gb->width, H = gb->height;
+    if ((s = check_scene(scene)) != GI_OK) return s;
+    if ((s = check_gb(gb, W, H)) != GI_OK) return s;
+    if ((s = check_probes(probes)) != GI_OK) return s;
+    if ((s = check_params(params)) != GI_OK) return s;
+    if ((s = check_res(res, W, H)) != GI_OK) return s;
+    if (W == 0 || H == 0) return GI_OK;
+    k_shade<<<tile_grid(W, H), kBlock, 0, S(stream)>>>(*scene, *gb, *probes, *res,
+                                                      reinterpret_cast<const float4 *>(resid), *params,
+                                                      reinterpret_cast<float4 *>(out_rgba));
+    return launched();
+}
+
+gi_status gi_philox(uint64_t seed, uint32_t n, const uint32_t *ctr, uint32_t *out, void *stream)
+{
+    if (n == 0) return GI_OK;
+    if (!ctr || !out) return GI_ERR_NULL;
+    k_philox<<<(n + 255) / 256, 256, 0, S(stream)>>>(seed, n, reinterpret_cast<const uint4 *>(ctr),
+                                                    reinterpret_cast<uint4 *>(out));
+    return launched();
+}
+
+gi_status gi_trace_rays(const gi_scene *scene, uint32_t n, const float *org, const float *dir, float *out,
+                        uint32_t *prim, void *stream)
+{
+    gi_status s;
+    if ((s = check_scene(scene)) != GI_OK) return s;
+    if (n == 0) return GI_OK;
+    if (!org || !dir || !out || !prim) return GI_ERR_NULL;
+    k_trace<<<(n + 255) / 256, 256, 0, S(stream)>>>(*scene, n, org, dir, reinterpret_cast<float4 *>(out), prim);
+    return launched();
+}
+
+}  // extern "C"

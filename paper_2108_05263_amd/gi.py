@@ -1,0 +1,461 @@
+"""Python binding of libgi.so (argument marshalling only).
+
+Every step of the method runs in the library's HIP kernels; this module
+allocates caller-owned device buffers with torch, fills the C structs of
+include/gi.h and forwards the current torch stream.  There is no fallback:
+if libgi.so cannot be loaded, or a call returns an error, it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+from . import scenegen as sg
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgi.so")
+MISS = 0xFFFFFFFF
+EMPTY_TAG = 0xFFFFFFFF
+
+_lib = None
+
+# every symbol include/gi.h declares
+EXPORTS = ["gi_status_string", "gi_device", "gi_trace_gbuffer", "gi_probe_update", "gi_probe_query",
+           "gi_resample_initial", "gi_resample_temporal", "gi_resample_spatial", "gi_shade",
+           "gi_accel_build_host", "gi_philox", "gi_trace_rays"]
+
+
+class GiError(RuntimeError):
+    pass
+
+
+# --------------------------------------------------------------------------
+# C structs (layouts of include/gi.h)
+# --------------------------------------------------------------------------
+F3 = C.c_float * 3
+U3 = C.c_uint32 * 3
+
+
+class GiScene(C.Structure):
+    _fields_ = [("prims", C.c_void_p), ("n_prims", C.c_uint32), ("has_room", C.c_uint32),
+                ("room_lo", F3), ("room_hi", F3), ("wall_albedo", F3), ("wall_emit", F3), ("sky", F3),
+                ("eps", C.c_float), ("grid_res", U3), ("grid_lo", F3), ("grid_hi", F3),
+                ("cell_start", C.c_void_p), ("cell_items", C.c_void_p)]
+
+
+class GiCamera(C.Structure):
+    _fields_ = [("eye", F3), ("fwd", F3), ("right", F3), ("up", F3), ("tan_half_fovy", C.c_float),
+                ("width", C.c_uint32), ("height", C.c_uint32)]
+
+
+class GiGBuffer(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("pos_depth", C.c_void_p),
+                ("nrm_prim", C.c_void_p), ("albedo", C.c_void_p), ("emit", C.c_void_p)]
+
+
+class GiProbes(C.Structure):
+    _fields_ = [("dims", U3), ("irr_res", C.c_uint32), ("dep_res", C.c_uint32), ("lo", F3),
+                ("spacing", F3), ("bias_dist", C.c_float), ("var_floor", C.c_float),
+                ("d_max", C.c_float), ("irr", C.c_void_p), ("dep", C.c_void_p)]
+
+
+class GiReservoirs(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("y_W", C.c_void_p),
+                ("n_wsum", C.c_void_p), ("L_M", C.c_void_p), ("tag_prim", C.c_void_p)]
+
+
+class GiParams(C.Structure):
+    _fields_ = [("M", C.c_uint32), ("k", C.c_uint32), ("radius", C.c_float), ("g_max", C.c_float),
+                ("cos_n", C.c_float), ("depth_rel", C.c_float), ("m_cap", C.c_float),
+                ("unbiased", C.c_uint32)]
+
+
+class GiProbeParams(C.Structure):
+    _fields_ = [("rays", C.c_uint32), ("hysteresis", C.c_float), ("sharpness", C.c_float)]
+
+
+_P = C.c_void_p
+
+
+def load():
+    """Load libgi.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GiError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                      "python paper_2108_05263_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    L.gi_status_string.restype = C.c_char_p
+    L.gi_status_string.argtypes = [C.c_int]
+    L.gi_device.restype = C.c_int
+    for name, args in {
+        "gi_trace_gbuffer": [_P, _P, _P, _P],
+        "gi_probe_update": [_P, _P, _P, _P, C.c_uint64, C.c_uint32, _P],
+        "gi_probe_query": [_P, C.c_uint32, _P, _P, _P, _P],
+        "gi_resample_initial": [_P, _P, _P, _P, _P, _P, C.c_uint64, C.c_uint32, _P],
+        "gi_resample_temporal": [_P, _P, _P, _P, _P, _P, _P, _P, C.c_uint64, C.c_uint32, _P],
+        "gi_resample_spatial": [_P, _P, _P, _P, C.c_uint32, _P, C.c_uint64, C.c_uint32, _P],
+        "gi_shade": [_P, _P, _P, _P, _P, _P, _P, _P],
+        "gi_accel_build_host": [_P, C.c_uint32, _P, _P, _P, _P, _P, C.c_uint32, _P],
+        "gi_philox": [C.c_uint64, C.c_uint32, _P, _P, _P],
+        "gi_trace_rays": [_P, C.c_uint32, _P, _P, _P, _P, _P],
+    }.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(status: int, what: str):
+    if status != 0:
+        msg = load().gi_status_string(status).decode()
+        raise GiError(f"{what}: {msg} (status {status})")
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+def _f3(v):
+    return F3(*[float(x) for x in np.asarray(v, np.float32).reshape(3)])
+
+
+# --------------------------------------------------------------------------
+# device-side objects
+# --------------------------------------------------------------------------
+class DeviceScene:
+    """Primitive records (and the optional grid accelerator) on the device."""
+
+    def __init__(self, scene: sg.Scene, grid_res=None, device="cuda"):
+        self.scene = scene
+        rec = np.ascontiguousarray(scene.prims.astype(np.float32))
+        self.prims = torch.from_numpy(rec.copy()).to(device)
+        s = GiScene()
+        s.prims = self.prims.data_ptr() if len(rec) else None
+        s.n_prims = len(rec)
+        s.has_room = 1 if scene.has_room else 0
+        s.room_lo, s.room_hi = _f3(scene.room_lo), _f3(scene.room_hi)
+        s.wall_albedo, s.wall_emit = _f3(scene.wall_albedo), _f3(scene.wall_emit)
+        s.sky = _f3(scene.sky)
+        s.eps = float(scene.eps)
+        self.cell_start = self.cell_items = None
+        if grid_res is not None:
+            lo, hi = scene.bounds()
+            res = (C.c_uint32 * 3)(*[int(v) for v in grid_res])
+            lo_c, hi_c = _f3(lo), _f3(hi)
+            ncell = int(grid_res[0]) * int(grid_res[1]) * int(grid_res[2])
+            start = np.zeros(ncell + 1, np.uint32)
+            n_items = C.c_uint32()
+            L = load()
+            st = L.gi_accel_build_host(rec.ctypes.data_as(_P), len(rec), lo_c, hi_c, res,
+                                       start.ctypes.data_as(_P), None, 0, C.byref(n_items))
+            items = np.zeros(max(int(n_items.value), 1), np.uint32)
+            st = L.gi_accel_build_host(rec.ctypes.data_as(_P), len(rec), lo_c, hi_c, res,
+                                       start.ctypes.data_as(_P), items.ctypes.data_as(_P),
+                                       len(items), C.byref(n_items))
+            check(st, "gi_accel_build_host")
+            self.cell_start = torch.from_numpy(start.view(np.int32).copy()).to(device)
+            self.cell_items = torch.from_numpy(items.view(np.int32).copy()).to(device)
+            s.grid_res = res
+            s.grid_lo, s.grid_hi = lo_c, hi_c
+            s.cell_start = self.cell_start.data_ptr()
+            s.cell_items = self.cell_items.data_ptr()
+            self.n_items = int(n_items.value)
+        self.c = s
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+
+def camera_struct(cam: sg.Camera) -> GiCamera:
+    c = GiCamera()
+    c.eye, c.fwd, c.right, c.up = _f3(cam.eye), _f3(cam.fwd), _f3(cam.right), _f3(cam.up)
+    c.tan_half_fovy = float(cam.tan_half_fovy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+class GBuffer:
+    def __init__(self, W, H, device="cuda"):
+        self.W, self.H = W, H
+        n = W * H
+        self.pos_depth = torch.zeros(n, 4, dtype=torch.float32, device=device)
+        self.nrm_prim = torch.zeros(n, 4, dtype=torch.float32, device=device)
+        self.albedo = torch.zeros(n, 4, dtype=torch.float32, device=device)
+        self.emit = torch.zeros(n, 4, dtype=torch.float32, device=device)
+        g = GiGBuffer()
+        g.width, g.height = W, H
+        g.pos_depth, g.nrm_prim = self.pos_depth.data_ptr(), self.nrm_prim.data_ptr()
+        g.albedo, g.emit = self.albedo.data_ptr(), self.emit.data_ptr()
+        self.c = g
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+    def to_records(self) -> np.ndarray:
+        """(W*H, 14) float64 records in the oracle's G-buffer layout."""
+        pd, npm = self.pos_depth.cpu().numpy(), self.nrm_prim.cpu().numpy()
+        al, em = self.albedo.cpu().numpy(), self.emit.cpu().numpy()
+        rec = np.zeros((self.W * self.H, 14))
+        rec[:, 0:3], rec[:, 3:6] = pd[:, 0:3], npm[:, 0:3]
+        rec[:, 6:9], rec[:, 9:12] = al[:, 0:3], em[:, 0:3]
+        rec[:, 12] = pd[:, 3]
+        rec[:, 13] = npm[:, 3].view(np.uint32)
+        return rec
+
+    def load_records(self, rec):
+        """Fill from (W*H, 14) oracle-layout records (rounded to float32)."""
+        rec = np.asarray(rec, np.float64)
+        n = self.W * self.H
+        pd = np.zeros((n, 4), np.float32)
+        npm = np.zeros((n, 4), np.float32)
+        al = np.zeros((n, 4), np.float32)
+        em = np.zeros((n, 4), np.float32)
+        pd[:, 0:3], pd[:, 3] = rec[:, 0:3], rec[:, 12]
+        npm[:, 0:3] = rec[:, 3:6]
+        npm.view(np.uint32)[:, 3] = rec[:, 13].astype(np.uint64).astype(np.uint32)
+        al[:, 0:3], em[:, 0:3] = rec[:, 6:9], rec[:, 9:12]
+        for t, a in ((self.pos_depth, pd), (self.nrm_prim, npm), (self.albedo, al), (self.emit, em)):
+            t.copy_(torch.from_numpy(a))
+
+
+class Reservoirs:
+    def __init__(self, W, H, device="cuda"):
+        self.W, self.H = W, H
+        n = W * H
+        self.y_W = torch.zeros(n, 4, dtype=torch.float32, device=device)
+        self.n_wsum = torch.zeros(n, 4, dtype=torch.float32, device=device)
+        self.L_M = torch.zeros(n, 4, dtype=torch.float32, device=device)
+        self.tag_prim = torch.zeros(n, 2, dtype=torch.int32, device=device)
+        r = GiReservoirs()
+        r.width, r.height = W, H
+        r.y_W, r.n_wsum = self.y_W.data_ptr(), self.n_wsum.data_ptr()
+        r.L_M, r.tag_prim = self.L_M.data_ptr(), self.tag_prim.data_ptr()
+        self.c = r
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+    def to_records(self) -> np.ndarray:
+        """(W*H, 14) float64 records in the oracle's reservoir layout."""
+        a, b = self.y_W.cpu().numpy(), self.n_wsum.cpu().numpy()
+        c, d = self.L_M.cpu().numpy(), self.tag_prim.cpu().numpy().view(np.uint32)
+        rec = np.zeros((self.W * self.H, 14))
+        rec[:, 0:3], rec[:, 10] = a[:, 0:3], a[:, 3]
+        rec[:, 3:6], rec[:, 9] = b[:, 0:3], b[:, 3]
+        rec[:, 6:9], rec[:, 11] = c[:, 0:3], c[:, 3].view(np.uint32)
+        rec[:, 12], rec[:, 13] = d[:, 0], d[:, 1]
+        return rec
+
+    def load_records(self, rec):
+        rec = np.asarray(rec, np.float64)
+        n = self.W * self.H
+        a = np.zeros((n, 4), np.float32)
+        b = np.zeros((n, 4), np.float32)
+        c = np.zeros((n, 4), np.float32)
+        d = np.zeros((n, 2), np.uint32)
+        a[:, 0:3], a[:, 3] = rec[:, 0:3], rec[:, 10]
+        b[:, 0:3], b[:, 3] = rec[:, 3:6], rec[:, 9]
+        c[:, 0:3] = rec[:, 6:9]
+        c.view(np.uint32)[:, 3] = rec[:, 11].astype(np.uint32)
+        d[:, 0], d[:, 1] = rec[:, 12].astype(np.uint64), rec[:, 13].astype(np.uint64)
+        for t, arr in ((self.y_W, a), (self.n_wsum, b), (self.L_M, c)):
+            t.copy_(torch.from_numpy(arr))
+        self.tag_prim.copy_(torch.from_numpy(d.view(np.int32)))
+
+
+class Probes:
+    def __init__(self, grid: sg.ProbeGrid, device="cuda"):
+        self.grid = grid
+        P = grid.count
+        self.irr = torch.zeros(P, (grid.irr_res + 2) ** 2, 4, dtype=torch.float32, device=device)
+        self.dep = torch.zeros(P, (grid.dep_res + 2) ** 2, 2, dtype=torch.float32, device=device)
+        p = GiProbes()
+        p.dims = (C.c_uint32 * 3)(*grid.dims)
+        p.irr_res, p.dep_res = grid.irr_res, grid.dep_res
+        p.lo, p.spacing = _f3(grid.lo), _f3(grid.spacing)
+        p.bias_dist, p.var_floor, p.d_max = grid.bias_dist, grid.var_floor, grid.d_max
+        p.irr, p.dep = self.irr.data_ptr(), self.dep.data_ptr()
+        self.c = p
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+    def load(self, irr, dep):
+        irr = np.asarray(irr)
+        a = np.zeros(tuple(self.irr.shape), np.float32)
+        a[..., :3] = irr[..., :3]
+        self.irr.copy_(torch.from_numpy(a))
+        self.dep.copy_(torch.from_numpy(np.asarray(dep, np.float32)[..., :2].copy()))
+
+
+def params_struct(p: sg.Params) -> GiParams:
+    g = GiParams()
+    g.M, g.k, g.radius, g.g_max = int(p.M), int(p.k), float(p.radius), float(p.g_max)
+    g.cos_n, g.depth_rel, g.m_cap = float(p.cos_n), float(p.depth_rel), float(p.m_cap)
+    g.unbiased = int(p.unbiased)
+    return g
+
+
+# --------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# --------------------------------------------------------------------------
+def trace_gbuffer(scene: DeviceScene, cam, gb: GBuffer, stream=None):
+    c = camera_struct(cam)
+    check(load().gi_trace_gbuffer(scene.ref, C.byref(c), gb.ref, _stream(stream)), "gi_trace_gbuffer")
+
+
+def probe_update(scene: DeviceScene, pin: Probes, pout: Probes, rays, hysteresis, sharpness, seed,
+                 frame, stream=None):
+    pp = GiProbeParams(int(rays), float(hysteresis), float(sharpness))
+    check(load().gi_probe_update(scene.ref, pin.ref, pout.ref, C.byref(pp), int(seed),
+                                 int(frame) & 0xFFFFFFFF, _stream(stream)), "gi_probe_update")
+
+
+def probe_query(probes: Probes, p: torch.Tensor, n: torch.Tensor, stream=None) -> torch.Tensor:
+    p, n = p.contiguous().float(), n.contiguous().float()
+    out = torch.empty_like(p)
+    check(load().gi_probe_query(probes.ref, p.shape[0], _ptr(p), _ptr(n), _ptr(out), _stream(stream)),
+          "gi_probe_query")
+    return out
+
+
+def resample_initial(scene, gb, probes, params, out: Reservoirs, resid: torch.Tensor, seed, frame,
+                     stream=None):
+    pp = params_struct(params)
+    check(load().gi_resample_initial(scene.ref, gb.ref, probes.ref, C.byref(pp), out.ref, _ptr(resid),
+                                     int(seed), int(frame) & 0xFFFFFFFF, _stream(stream)),
+          "gi_resample_initial")
+
+
+def resample_temporal(scene, gb, gb_prev, cam_prev, cur, hist, params, out, seed, frame, stream=None):
+    pp = params_struct(params)
+    c = camera_struct(cam_prev)
+    check(load().gi_resample_temporal(scene.ref, gb.ref, gb_prev.ref, C.byref(c), cur.ref, hist.ref,
+                                      C.byref(pp), out.ref, int(seed), int(frame) & 0xFFFFFFFF,
+                                      _stream(stream)), "gi_resample_temporal")
+
+
+def resample_spatial(scene, gb, res_in, params, spass, out, seed, frame, stream=None):
+    pp = params_struct(params)
+    check(load().gi_resample_spatial(scene.ref, gb.ref, res_in.ref, C.byref(pp), int(spass), out.ref,
+                                     int(seed), int(frame) & 0xFFFFFFFF, _stream(stream)),
+          "gi_resample_spatial")
+
+
+def shade(scene, gb, probes, res, resid, params, out_rgba: torch.Tensor, stream=None):
+    pp = params_struct(params)
+    check(load().gi_shade(scene.ref, gb.ref, probes.ref, res.ref, _ptr(resid), C.byref(pp),
+                          _ptr(out_rgba), _stream(stream)), "gi_shade")
+
+
+def philox(seed: int, ctr: torch.Tensor, stream=None) -> torch.Tensor:
+    ctr = ctr.contiguous()
+    out = torch.empty_like(ctr)
+    check(load().gi_philox(int(seed), ctr.shape[0], _ptr(ctr), _ptr(out), _stream(stream)), "gi_philox")
+    return out
+
+
+def trace_rays(scene: DeviceScene, org: torch.Tensor, d: torch.Tensor, stream=None):
+    org, d = org.contiguous().float(), d.contiguous().float()
+    n = org.shape[0]
+    out = torch.empty(n, 4, dtype=torch.float32, device=org.device)
+    prim = torch.empty(n, dtype=torch.int32, device=org.device)
+    check(load().gi_trace_rays(scene.ref, n, _ptr(org), _ptr(d), _ptr(out), _ptr(prim),
+                               _stream(stream)), "gi_trace_rays")
+    return out, prim
+
+
+# --------------------------------------------------------------------------
+# frame driver
+# --------------------------------------------------------------------------
+FILL_FRAME_BASE = 0xF0000000
+
+
+class Renderer:
+    """Runs the path frame after frame on the device: G-buffer, (probe
+    update), initial RIS, temporal reuse against the last frame's final
+    reservoirs, spatial passes (ping-pong) and shading."""
+
+    def __init__(self, cfg: sg.Config, seed: int = 1, width=None, height=None, use_grid=True,
+                 device="cuda", scene=None, params=None):
+        self.cfg = cfg
+        self.seed = seed
+        self.W, self.H = int(width or cfg.width), int(height or cfg.height)
+        self.scene = scene if scene is not None else sg.make_scene(cfg)
+        self.dscene = DeviceScene(self.scene, cfg.grid_res if use_grid else None, device)
+        self.grid = sg.make_probe_grid(cfg)
+        self.params = params if params is not None else cfg.params
+        self.probes = [Probes(self.grid, device), Probes(self.grid, device)]
+        self.cur_probe = 0
+        self.gb = [GBuffer(self.W, self.H, device), GBuffer(self.W, self.H, device)]
+        self.res = [Reservoirs(self.W, self.H, device) for _ in range(4)]
+        self.resid = torch.zeros(self.W * self.H, 4, dtype=torch.float32, device=device)
+        self.img = torch.zeros(self.W * self.H, 4, dtype=torch.float32, device=device)
+        self.hist = None
+        self.cam_prev = None
+        self.frame_index = 0
+
+    @property
+    def probe(self) -> Probes:
+        return self.probes[self.cur_probe]
+
+    def update_probes(self, rays, hysteresis, frame, stream=None):
+        src, dst = self.probes[self.cur_probe], self.probes[1 - self.cur_probe]
+        probe_update(self.dscene, src, dst, rays, hysteresis, self.cfg.probe_update.sharpness,
+                     self.seed, frame, stream)
+        self.cur_probe = 1 - self.cur_probe
+
+    def fill_probes(self, stream=None):
+        u = self.cfg.probe_update
+        for k in range(u.fill_passes):
+            self.update_probes(u.fill_rays, 0.0, FILL_FRAME_BASE + k, stream)
+
+    def camera(self, f):
+        return sg.make_camera(self.cfg, f, self.W, self.H)
+
+    def frame(self, f=None, stream=None, cam=None):
+        """Render frame f; returns the final reservoirs object (history)."""
+        f = self.frame_index if f is None else f
+        cam = cam if cam is not None else self.camera(f)
+        pr = self.params
+        gb, gb_prev = self.gb[f & 1], self.gb[(f & 1) ^ 1]
+        if self.cfg.probe_update.per_frame:
+            u = self.cfg.probe_update
+            self.update_probes(u.rays, u.hysteresis, f, stream)
+        trace_gbuffer(self.dscene, cam, gb, stream)
+        bufs = [r for r in self.res if r is not self.hist]
+        a = bufs[0]
+        resample_initial(self.dscene, gb, self.probe, pr, a, self.resid, self.seed, f, stream)
+        cur = a
+        spare = bufs[1:]
+        if pr.temporal and self.hist is not None:
+            t = spare[0]
+            resample_temporal(self.dscene, gb, gb_prev, self.cam_prev, cur, self.hist, pr, t, self.seed,
+                              f, stream)
+            cur = t
+        pool = [b for b in self.res if b is not cur and b is not self.hist] + \
+            ([self.hist] if self.hist is not None else [])
+        for sp in range(pr.n_spatial):
+            dst = next(b for b in pool if b is not cur)
+            resample_spatial(self.dscene, gb, cur, pr, sp, dst, self.seed, f, stream)
+            cur = dst
+        shade(self.dscene, gb, self.probe, cur, self.resid, pr, self.img, stream)
+        self.hist = cur
+        self.cam_prev = cam
+        self.frame_index = f + 1
+        return cur

@@ -1,0 +1,121 @@
+"""The C-ABI library loads, exports every symbol include/gi.h declares, and
+rejects bad arguments on the host before launching anything (no GPU needed:
+validation never touches the device)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2108_05263_amd import build as libbuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def gi():
+    if libbuild.is_stale():
+        libbuild.build()
+    from paper_2108_05263_amd import gi as m
+    m.load()
+    return m
+
+
+def test_exports_every_declared_symbol(gi):
+    hdr = open(os.path.join(ROOT, "include", "gi.h")).read()
+    declared = set(re.findall(r"^\w[\w\s\*]*?\b(gi_\w+)\s*\(", hdr, re.M))
+    assert declared >= {"gi_trace_gbuffer", "gi_probe_update", "gi_resample_initial",
+                        "gi_resample_temporal", "gi_resample_spatial", "gi_shade"}
+    lib = gi.load()
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(gi.EXPORTS)
+
+
+def test_status_strings(gi):
+    lib = gi.load()
+    for s in range(7):
+        assert lib.gi_status_string(s)
+    assert lib.gi_status_string(99) == b"unknown status"
+
+
+def _null():
+    return C.c_void_p(0)
+
+
+def test_validation_rejects_before_launch(gi):
+    lib = gi.load()
+    s = gi.GiScene()
+    cam = gi.GiCamera()
+    cam.width, cam.height = 4, 4
+    g = gi.GiGBuffer()
+    g.width, g.height = 4, 4
+    # null pointers
+    assert lib.gi_trace_gbuffer(None, C.byref(cam), C.byref(g), None) == 1
+    assert lib.gi_trace_gbuffer(C.byref(s), C.byref(cam), C.byref(g), None) == 1
+    # shape mismatch
+    g.pos_depth = g.nrm_prim = g.albedo = g.emit = 16
+    g.width = 5
+    assert lib.gi_trace_gbuffer(C.byref(s), C.byref(cam), C.byref(g), None) == 2
+    # parameters out of range
+    r = gi.GiReservoirs()
+    r.width, r.height = 4, 4
+    r.y_W, r.n_wsum, r.L_M, r.tag_prim = 16, 32, 48, 64
+    g.width = 4
+    pr = gi.GiProbes()
+    pr.dims = (C.c_uint32 * 3)(2, 2, 2)
+    pr.irr_res, pr.dep_res = 8, 16
+    pr.spacing = gi.F3(1.0, 1.0, 1.0)
+    pr.irr, pr.dep = 80, 96
+    pp = gi.GiParams()
+    pp.M, pp.k, pp.radius, pp.g_max, pp.m_cap = 33, 1, 1.0, 1.0, 20.0
+    resid = C.c_void_p(112)
+    assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r),
+                                   resid, 1, 0, None) == 3
+    pp.M = 8
+    pr.irr_res = 4
+    assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r),
+                                   resid, 1, 0, None) == 2
+    pr.irr_res = 8
+    # aliasing output and input reservoirs
+    assert lib.gi_resample_spatial(C.byref(s), C.byref(g), C.byref(r), C.byref(pp), 0, C.byref(r),
+                                   1, 0, None) == 4
+    # probe update: rays out of range, aliasing
+    pu = gi.GiProbeParams(0, 0.5, 50.0)
+    pr2 = gi.GiProbes()
+    C.pointer(pr2)[0] = pr
+    pr2.irr, pr2.dep = 128, 144
+    assert lib.gi_probe_update(C.byref(s), C.byref(pr), C.byref(pr2), C.byref(pu), 1, 0, None) == 3
+    pu.rays = 64
+    assert lib.gi_probe_update(C.byref(s), C.byref(pr), C.byref(pr), C.byref(pu), 1, 0, None) == 4
+
+
+def test_accel_builder_lists_overlapping_cells(gi):
+    from paper_2108_05263_amd import scenegen as sg
+    cfg = sg.CONFIGS["hd"]
+    sc = sg.make_scene(cfg)
+    lib = gi.load()
+    lo, hi = sc.bounds()
+    res = (C.c_uint32 * 3)(*cfg.grid_res)
+    ncell = int(np.prod(cfg.grid_res))
+    start = np.zeros(ncell + 1, np.uint32)
+    n = C.c_uint32()
+    rec = np.ascontiguousarray(sc.prims)
+    st = lib.gi_accel_build_host(rec.ctypes.data_as(C.c_void_p), len(rec), gi._f3(lo), gi._f3(hi), res,
+                                 start.ctypes.data_as(C.c_void_p), None, 0, C.byref(n))
+    assert st == 2 and n.value > len(rec)
+    items = np.zeros(n.value, np.uint32)
+    st = lib.gi_accel_build_host(rec.ctypes.data_as(C.c_void_p), len(rec), gi._f3(lo), gi._f3(hi), res,
+                                 start.ctypes.data_as(C.c_void_p), items.ctypes.data_as(C.c_void_p),
+                                 len(items), C.byref(n))
+    assert st == 0 and start[-1] == n.value
+    # every primitive appears in the cell that contains its centre, ids increase per cell
+    cs = (hi - lo) / np.array(cfg.grid_res)
+    for i in range(len(rec)):
+        c = np.clip(((rec[i, 0:3] - lo) / cs).astype(int), 0, np.array(cfg.grid_res) - 1)
+        cell = c[0] + cfg.grid_res[0] * (c[1] + cfg.grid_res[1] * c[2])
+        assert i in items[start[cell]:start[cell + 1]]
+    for c in range(ncell):
+        seg = items[start[c]:start[c + 1]]
+        assert np.all(np.diff(seg.astype(np.int64)) > 0)
