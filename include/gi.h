@@ -81,7 +81,11 @@ typedef struct gi_scene {
     float grid_lo[3], grid_hi[3];
     const uint32_t *cell_start;      /* grid_res[0]*grid_res[1]*grid_res[2] + 1 entries */
     const uint32_t *cell_items;
+    uint32_t n_items;                /* entries of cell_items (= cell_start[last]) */
+    uint32_t options;                /* GI_OPT_* bits */
 } gi_scene;
+
+#define GI_OPT_NO_LDS 1u             /* trace from global memory even when the scene fits LDS */
 
 /* Pinhole camera: the ray through pixel (i, j) has direction
  * normalize(fwd + sx*right + sy*up), sx = (2(i+.5)/W - 1) tan_half_fovy W/H,
@@ -105,10 +109,16 @@ typedef struct gi_gbuffer {
 } gi_gbuffer;
 
 /* DDGI probe volume.  Probe (i, j, k), index i + dims[0]*(j + dims[1]*k),
- * sits at lo + (idx + 0.5) * spacing.  Per probe:
- *   irr: (irr_res+2)^2 float4 texels (r, g, b, 0) of E/pi, row-major, with a
- *        one-texel octahedral gutter;
- *   dep: (dep_res+2)^2 float2 texels (mean, mean^2) of the hit distance.
+ * sits at lo + (idx + 0.5) * spacing.  Each probe owns an octahedral
+ * irradiance tile (irr_res^2 texels of E/pi, RGB) and depth tile (dep_res^2
+ * texels of the mean and mean square hit distance), each with a one-texel
+ * gutter that mirrors the interior along the tile edge (corners take the
+ * diagonally opposite interior texel).  They are stored as bilinear quads:
+ *   irr: per probe (irr_res+1)^2 records of 12 floats; record cy*(irr_res+1)+cx
+ *        holds the RGB of padded texels (cx,cy), (cx+1,cy), (cx,cy+1),
+ *        (cx+1,cy+1) in that order (3888 bytes per probe);
+ *   dep: per probe (dep_res+1)^2 records of 8 floats, (mean, mean^2) of the
+ *        same four padded texels (9248 bytes per probe).
  * irr_res must be 8 and dep_res 16.  bias_dist is the view-path bias d,
  * var_floor the Chebyshev variance floor, d_max the probe-ray depth clamp. */
 typedef struct gi_probes {

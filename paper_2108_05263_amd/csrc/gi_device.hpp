@@ -181,17 +181,77 @@ struct PrimGeo {
     V3 s;
 };
 
-__device__ __forceinline__ PrimGeo load_geo(const gi_prim *prims, uint32_t i)
+__device__ __forceinline__ PrimGeo geo_of(float4 a, float4 b)
 {
-    const float4 *p = reinterpret_cast<const float4 *>(prims + i);
-    float4 a = p[0], b = p[1];
     return PrimGeo{v3(a.x, a.y, a.z), __float_as_uint(a.w), v3(b.x, b.y, b.z)};
 }
 
-// test one primitive; keep the lexicographically smallest (t, id)
-__device__ __forceinline__ void test_prim(const gi_prim *prims, uint32_t i, V3 o, V3 d, V3 inv, Hit &h)
+__device__ __forceinline__ PrimGeo load_geo(const gi_prim *prims, uint32_t i)
 {
-    PrimGeo g = load_geo(prims, i);
+    const float4 *p = reinterpret_cast<const float4 *>(prims + i);
+    return geo_of(p[0], p[1]);
+}
+
+// Scene access through the caller's device buffers.
+struct GeoGlobal {
+    const gi_prim *prims;
+    const uint32_t *cells;
+    const uint32_t *items;
+    __device__ __forceinline__ explicit GeoGlobal(const gi_scene &sc)
+        : prims(sc.prims), cells(sc.cell_start), items(sc.cell_items) {}
+    __device__ __forceinline__ PrimGeo geo(uint32_t i) const { return load_geo(prims, i); }
+    __device__ __forceinline__ uint32_t cell(uint32_t c) const { return cells[c]; }
+    __device__ __forceinline__ uint32_t item(uint32_t j) const { return items[j]; }
+    __device__ __forceinline__ bool has_grid() const { return cells != nullptr; }
+};
+
+// Scene access through a workgroup-local copy in LDS (see stage_scene):
+// [2 float4 of geometry per primitive][cell_start: ncells+1][items]
+extern __shared__ float4 gi_lds[];
+
+struct GeoLds {
+    uint32_t n_prims, n_cells;
+    __device__ __forceinline__ explicit GeoLds(const gi_scene &sc)
+        : n_prims(sc.n_prims), n_cells(sc.grid_res[0] * sc.grid_res[1] * sc.grid_res[2]) {}
+    __device__ __forceinline__ PrimGeo geo(uint32_t i) const { return geo_of(gi_lds[2 * i], gi_lds[2 * i + 1]); }
+    __device__ __forceinline__ uint32_t cell(uint32_t c) const
+    {
+        return reinterpret_cast<const uint32_t *>(gi_lds + 2 * n_prims)[c];
+    }
+    __device__ __forceinline__ uint32_t item(uint32_t j) const
+    {
+        return reinterpret_cast<const uint32_t *>(gi_lds + 2 * n_prims)[n_cells + 1 + j];
+    }
+    __device__ __forceinline__ bool has_grid() const { return true; }
+};
+
+// Bytes of LDS the staged scene needs (host and device agree on this layout).
+__host__ __device__ __forceinline__ uint32_t lds_scene_bytes(const gi_scene &sc)
+{
+    uint32_t nc = sc.grid_res[0] * sc.grid_res[1] * sc.grid_res[2];
+    uint32_t words = nc + 1 + sc.n_items;
+    return 32u * sc.n_prims + ((4u * words + 15u) & ~15u);
+}
+
+// Cooperative copy of primitive geometry and the grid into LDS; every
+// thread of the workgroup must call it (it ends with a barrier).
+__device__ __forceinline__ void stage_scene(const gi_scene &sc)
+{
+    const float4 *src = reinterpret_cast<const float4 *>(sc.prims);
+    const uint32_t n2 = 2u * sc.n_prims, bs = blockDim.x;
+    for (uint32_t i = threadIdx.x; i < n2; i += bs) gi_lds[i] = src[(i >> 1) * 4u + (i & 1u)];
+    uint32_t *w = reinterpret_cast<uint32_t *>(gi_lds + n2);
+    const uint32_t nc = sc.grid_res[0] * sc.grid_res[1] * sc.grid_res[2] + 1u;
+    for (uint32_t i = threadIdx.x; i < nc; i += bs) w[i] = sc.cell_start[i];
+    for (uint32_t i = threadIdx.x; i < sc.n_items; i += bs) w[nc + i] = sc.cell_items[i];
+    __syncthreads();
+}
+
+// test one primitive; keep the lexicographically smallest (t, id)
+template <class G>
+__device__ __forceinline__ void test_prim(const G &acc, uint32_t i, V3 o, V3 d, V3 inv, Hit &h)
+{
+    PrimGeo g = acc.geo(i);
     int axis = -1;
     float t = g.type == 0u ? isect_sphere(o, d, g.c, g.s.x) : isect_box(o, inv, g.c, g.s, axis);
     // equal distances go to the lower id; a miss (t = inf) never counts,
@@ -204,23 +264,22 @@ __device__ __forceinline__ void test_prim(const gi_prim *prims, uint32_t i, V3 o
 }
 
 // any surface crossing of a primitive in (0, tmax)?
-__device__ __forceinline__ bool occludes_prim(const gi_prim *prims, uint32_t i, V3 o, V3 d, V3 inv, float tmax)
+template <class G>
+__device__ __forceinline__ bool occludes_prim(const G &acc, uint32_t i, V3 o, V3 d, V3 inv, float tmax)
 {
-    PrimGeo g = load_geo(prims, i);
+    PrimGeo g = acc.geo(i);
     int axis;
     float t = g.type == 0u ? isect_sphere(o, d, g.c, g.s.x) : isect_box(o, inv, g.c, g.s, axis);
     return t < tmax;
 }
-
-__device__ __forceinline__ float safe_inv(float v) { return v == 0.0f ? kInf : 1.0f / v; }
 
 // Ray cast: closest hit (ANY = false) or any hit (ANY = true) with t in (0, tmax).
 // Walls are tested first; the grid (if present) is walked with a 3D-DDA and
 // stops once the best hit lies before the current cell's exit.  Primitive
 // boxes are padded when binned, so the grid walk returns the same hit as the
 // brute-force loop.
-template <bool ANY>
-__device__ __forceinline__ bool cast(const gi_scene &sc, V3 o, V3 d, float tmax, Hit &h)
+template <bool ANY, class G>
+__device__ __forceinline__ bool cast(const gi_scene &sc, const G &acc, V3 o, V3 d, float tmax, Hit &h)
 {
     h.t = tmax;
     h.prim = GI_MISS;
@@ -232,12 +291,12 @@ __device__ __forceinline__ bool cast(const gi_scene &sc, V3 o, V3 d, float tmax,
         float tw = isect_room(sc, o, d, axis, wall);
         if (tw < h.t) { h.t = tw; h.prim = wall; h.axis = axis; }
     }
-    if (sc.cell_start == nullptr) {
+    if (!acc.has_grid()) {
         for (uint32_t i = 0; i < sc.n_prims; ++i) {
             if (ANY) {
-                if (occludes_prim(sc.prims, i, o, d, inv, tmax)) { h.prim = i; return true; }
+                if (occludes_prim(acc, i, o, d, inv, tmax)) { h.prim = i; return true; }
             } else {
-                test_prim(sc.prims, i, o, d, inv, h);
+                test_prim(acc, i, o, d, inv, h);
             }
         }
         return h.prim != GI_MISS;
@@ -264,13 +323,13 @@ __device__ __forceinline__ bool cast(const gi_scene &sc, V3 o, V3 d, float tmax,
     const int max_steps = rx + ry + rz + 3;
     for (int step = 0; step < max_steps; ++step) {
         uint32_t cell = (uint32_t)(ix + rx * (iy + ry * iz));
-        uint32_t b = sc.cell_start[cell], e = sc.cell_start[cell + 1];
+        uint32_t b = acc.cell(cell), e = acc.cell(cell + 1);
         for (uint32_t j = b; j < e; ++j) {
-            uint32_t i = sc.cell_items[j];
+            uint32_t i = acc.item(j);
             if (ANY) {
-                if (occludes_prim(sc.prims, i, o, d, inv, tmax)) { h.prim = i; return true; }
+                if (occludes_prim(acc, i, o, d, inv, tmax)) { h.prim = i; return true; }
             } else {
-                test_prim(sc.prims, i, o, d, inv, h);
+                test_prim(acc, i, o, d, inv, h);
             }
         }
         float nx = d.x == 0.0f ? kInf : (sc.grid_lo[0] + (float)(ix + (sx > 0)) * cxs - o.x) * inv.x;
@@ -293,14 +352,15 @@ __device__ __forceinline__ bool cast(const gi_scene &sc, V3 o, V3 d, float tmax,
 }
 
 // facing geometric normal of a closest hit
-__device__ __forceinline__ V3 hit_normal(const gi_scene &sc, V3 o, V3 d, const Hit &h)
+template <class G>
+__device__ __forceinline__ V3 hit_normal(const gi_scene &sc, const G &acc, V3 o, V3 d, const Hit &h)
 {
     V3 n;
     if (h.prim >= sc.n_prims || h.axis >= 0) {
         float s = comp(d, h.axis) > 0.0f ? -1.0f : 1.0f;
         n = v3(h.axis == 0 ? s : 0.0f, h.axis == 1 ? s : 0.0f, h.axis == 2 ? s : 0.0f);
     } else {
-        PrimGeo g = load_geo(sc.prims, h.prim);
+        PrimGeo g = acc.geo(h.prim);
         V3 p = madd(o, h.t, d);
         float ir = rcp(g.s.x);
         n = ir * (p - g.c);
@@ -323,16 +383,17 @@ __device__ __forceinline__ void material(const gi_scene &sc, uint32_t prim, V3 &
 
 // mutual visibility of two surface points (eps-lifted), or of a point and
 // the sky in direction b when b_is_dir
-__device__ __forceinline__ bool visible(const gi_scene &sc, V3 a, V3 na, V3 b, V3 nb, bool b_is_dir)
+template <class G>
+__device__ __forceinline__ bool visible(const gi_scene &sc, const G &acc, V3 a, V3 na, V3 b, V3 nb, bool b_is_dir)
 {
     V3 o = madd(a, sc.eps, na);
     Hit h;
-    if (b_is_dir) return !cast<true>(sc, o, b, kInf, h) && !(sc.has_room);
+    if (b_is_dir) return !sc.has_room && !cast<true>(sc, acc, o, b, kInf, h);
     V3 e = madd(b, sc.eps, nb);
     V3 v = e - o;
     float dist = fsqrt(dot(v, v));
     V3 d = rcp(dist) * v;
-    if (cast<true>(sc, o, d, dist, h)) return false;
+    if (cast<true>(sc, acc, o, d, dist, h)) return false;
     if (sc.has_room) {
         int axis;
         uint32_t wall;
@@ -375,8 +436,19 @@ __device__ __forceinline__ V3 oct_decode(float u, float w)
     return v3(px * il, py * il, z * il);
 }
 
+// Probe textures are stored as bilinear quads: record (cx, cy), cx, cy in
+// [0, N], holds the four gutter-padded texels (cx, cy), (cx+1, cy),
+// (cx, cy+1), (cx+1, cy+1) that a bilinear fetch between them needs, so one
+// fetch is a single 48-byte (irradiance RGB) or 32-byte (depth moments)
+// record: 3 or 2 16-byte loads instead of 4 scattered texel loads.
+constexpr int kIrrN = 8, kDepN = 16;
+constexpr int kIrrQuads = (kIrrN + 1) * (kIrrN + 1);      // 81 records of 12 floats
+constexpr int kDepQuads = (kDepN + 1) * (kDepN + 1);      // 289 records of 8 floats
+constexpr int kIrrProbeF4 = kIrrQuads * 3;                 // float4 per probe
+constexpr int kDepProbeF4 = kDepQuads * 2;
+
 struct Bilin {
-    int i00;        // index of the top-left texel in the padded tile
+    int q;          // quad record index cy * (N + 1) + cx
     float ax, ay;   // fractional weights toward +x, +y
 };
 
@@ -390,40 +462,39 @@ __device__ __forceinline__ Bilin bilin(V3 dir, int N)
     // u, w lie in [0, 1] so x0, y0 lie in [0, N]; the clamp only guards
     // against a degenerate (zero or NaN) direction
     int ix = min(max((int)x0, 0), N), iy = min(max((int)y0, 0), N);
-    b.i00 = iy * (N + 2) + ix;
+    b.q = iy * (N + 1) + ix;
     b.ax = fx - x0;
     b.ay = fy - y0;
     return b;
 }
 
-__device__ __forceinline__ V3 fetch_irr(const float4 *tile, const Bilin &b)
+__device__ __forceinline__ V3 fetch_irr(const float4 *probe, const Bilin &b)
 {
-    float4 t00 = tile[b.i00], t10 = tile[b.i00 + 1], t01 = tile[b.i00 + 10], t11 = tile[b.i00 + 11];
+    const float4 *r = probe + 3 * b.q;
+    float4 a = r[0], c = r[1], d = r[2];
     float w00 = (1.0f - b.ax) * (1.0f - b.ay), w10 = b.ax * (1.0f - b.ay);
     float w01 = (1.0f - b.ax) * b.ay, w11 = b.ax * b.ay;
-    return v3(w00 * t00.x + w10 * t10.x + w01 * t01.x + w11 * t11.x,
-              w00 * t00.y + w10 * t10.y + w01 * t01.y + w11 * t11.y,
-              w00 * t00.z + w10 * t10.z + w01 * t01.z + w11 * t11.z);
+    return v3(w00 * a.x + w10 * a.w + w01 * c.z + w11 * d.y,
+              w00 * a.y + w10 * c.x + w01 * c.w + w11 * d.z,
+              w00 * a.z + w10 * c.y + w01 * d.x + w11 * d.w);
 }
 
-__device__ __forceinline__ float2 fetch_dep(const float2 *tile, V3 dir)
+__device__ __forceinline__ float2 fetch_dep(const float4 *probe, V3 dir)
 {
-    Bilin b = bilin(dir, 16);
-    float2 t00 = tile[b.i00], t10 = tile[b.i00 + 1], t01 = tile[b.i00 + 18], t11 = tile[b.i00 + 19];
+    Bilin b = bilin(dir, kDepN);
+    const float4 *r = probe + 2 * b.q;
+    float4 a = r[0], c = r[1];
     float w00 = (1.0f - b.ax) * (1.0f - b.ay), w10 = b.ax * (1.0f - b.ay);
     float w01 = (1.0f - b.ax) * b.ay, w11 = b.ax * b.ay;
-    return make_float2(w00 * t00.x + w10 * t10.x + w01 * t01.x + w11 * t11.x,
-                       w00 * t00.y + w10 * t10.y + w01 * t01.y + w11 * t11.y);
+    return make_float2(w00 * a.x + w10 * a.z + w01 * c.x + w11 * c.z,
+                       w00 * a.y + w10 * a.w + w01 * c.y + w11 * c.w);
 }
-
-constexpr int kIrrTexels = 10 * 10;
-constexpr int kDepTexels = 18 * 18;
 
 // Q(p, n) = E(p, n)/pi: blend of the 8 probes of p's cell
 __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
 {
     const float4 *irr = reinterpret_cast<const float4 *>(pr.irr);
-    const float2 *dep = reinterpret_cast<const float2 *>(pr.dep);
+    const float4 *dep = reinterpret_cast<const float4 *>(pr.dep);
     float pv[3] = {p.x, p.y, p.z};
     int base[3];
     float fr[3];
@@ -438,7 +509,7 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
     }
     V3 sum = v3(0.0f, 0.0f, 0.0f);
     float wsum = 0.0f;
-    const Bilin bn = bilin(n, 8);     // the irradiance direction is the same for all 8 probes
+    const Bilin bn = bilin(n, kIrrN);   // the irradiance direction is the same for all 8 probes
 #ifndef GI_QUERY_UNROLL
 #define GI_QUERY_UNROLL 1
 #endif
@@ -461,7 +532,7 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
             V3 w = ir * tp;
             float hh = 0.5f * (1.0f + dot(n, w));
             back = hh * hh + 0.2f;
-            float2 m = fetch_dep(dep + (size_t)pi * kDepTexels, -w);
+            float2 m = fetch_dep(dep + (size_t)pi * kDepProbeF4, -w);
             if (r > m.x) {
                 float var = fmaxf(fmaf(-m.x, m.x, m.y), pr.var_floor);
                 float dd = r - m.x;
@@ -470,7 +541,7 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
             }
         }
         float wgt = tri * fmaxf(back * vis, 1e-6f);
-        V3 e = fetch_irr(irr + (size_t)pi * kIrrTexels, bn);
+        V3 e = fetch_irr(irr + (size_t)pi * kIrrProbeF4, bn);
         sum = madd(sum, wgt, e);
         wsum += wgt;
     }

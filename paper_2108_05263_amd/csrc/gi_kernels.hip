@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "gi.h"
 #include "gi_device.hpp"
@@ -107,11 +108,12 @@ __global__ void __launch_bounds__(kBlock) k_gbuffer(gi_scene sc, gi_camera cam, 
     d = rsqrtf(dot(d, d)) * d;
     V3 o = ld3(cam.eye);
     Hit h;
+    const GeoGlobal acc(sc);
     float4 *pd = reinterpret_cast<float4 *>(gb.pos_depth);
     float4 *np = reinterpret_cast<float4 *>(gb.nrm_prim);
     float4 *al = reinterpret_cast<float4 *>(gb.albedo);
     float4 *em = reinterpret_cast<float4 *>(gb.emit);
-    if (!cast<false>(sc, o, d, kInf, h)) {
+    if (!cast<false>(sc, acc, o, d, kInf, h)) {
         pd[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         np[p] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(GI_MISS));
         al[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -119,7 +121,7 @@ __global__ void __launch_bounds__(kBlock) k_gbuffer(gi_scene sc, gi_camera cam, 
         return;
     }
     V3 x = madd(o, h.t, d);
-    V3 n = hit_normal(sc, o, d, h);
+    V3 n = hit_normal(sc, acc, o, d, h);
     V3 alb, emit;
     material(sc, h.prim, alb, emit);
     pd[p] = make_float4(x.x, x.y, x.z, h.t * dot(d, ld3(cam.fwd)));
@@ -145,9 +147,13 @@ __device__ __forceinline__ int gutter_source(int x, int y, int N)
     return (sy - 1) * N + (sx - 1);
 }
 
+template <bool LDS>
 __global__ void __launch_bounds__(kProbeBlock)
     k_probe_update(gi_scene sc, gi_probes in, gi_probes out, gi_probe_params pp, uint64_t seed, uint32_t frame)
 {
+    using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
+    if (LDS) stage_scene(sc);
+    const Acc acc(sc);
     __shared__ float s_dir[GI_MAX_PROBE_RAYS][3];
     __shared__ float s_L[GI_MAX_PROBE_RAYS][3];
     __shared__ float s_d[GI_MAX_PROBE_RAYS];
@@ -164,9 +170,9 @@ __global__ void __launch_bounds__(kProbeBlock)
         Hit h;
         V3 L;
         float dist;
-        if (cast<false>(sc, P, w, kInf, h)) {
+        if (cast<false>(sc, acc, P, w, kInf, h)) {
             V3 hp = madd(P, h.t, w);
-            V3 n = hit_normal(sc, P, w, h);
+            V3 n = hit_normal(sc, acc, P, w, h);
             V3 alb, emit;
             material(sc, h.prim, alb, emit);
             L = emit;
@@ -188,8 +194,9 @@ __global__ void __launch_bounds__(kProbeBlock)
         s_d[r] = dist;
     }
     __syncthreads();
-    const float4 *iold = reinterpret_cast<const float4 *>(in.irr) + (size_t)pi * kIrrTexels;
-    const float2 *dold = reinterpret_cast<const float2 *>(in.dep) + (size_t)pi * kDepTexels;
+    // old interior texel (i, j) = first texel of quad record (i+1, j+1)
+    const float4 *iold = reinterpret_cast<const float4 *>(in.irr) + (size_t)pi * kIrrProbeF4;
+    const float4 *dold = reinterpret_cast<const float4 *>(in.dep) + (size_t)pi * kDepProbeF4;
     const float hy = pp.hysteresis;
     {   // depth texel t (16x16)
         uint32_t t = threadIdx.x;
@@ -206,7 +213,7 @@ __global__ void __launch_bounds__(kProbeBlock)
                 den += w;
             }
         }
-        float2 old = dold[(ty + 1) * 18 + tx + 1];
+        float4 old = dold[2 * ((ty + 1) * 17 + tx + 1)];
         float n1 = den > 0.0f ? m1 / den : old.x;
         float n2 = den > 0.0f ? m2 / den : old.y;
         s_dep[t][0] = hy * old.x + (1.0f - hy) * n1;
@@ -225,7 +232,7 @@ __global__ void __launch_bounds__(kProbeBlock)
                 den += c;
             }
         }
-        float4 old = iold[(ty + 1) * 10 + tx + 1];
+        float4 old = iold[3 * ((ty + 1) * 9 + tx + 1)];
         float id = 1.0f / den;
         V3 nv = den > 0.0f ? id * num : xyz(old);
         s_irr[t][0] = hy * old.x + (1.0f - hy) * nv.x;
@@ -233,16 +240,24 @@ __global__ void __launch_bounds__(kProbeBlock)
         s_irr[t][2] = hy * old.z + (1.0f - hy) * nv.z;
     }
     __syncthreads();
-    // write padded tiles: an interior texel or the interior texel a gutter mirrors
-    float4 *iout = reinterpret_cast<float4 *>(out.irr) + (size_t)pi * kIrrTexels;
-    float2 *dout = reinterpret_cast<float2 *>(out.dep) + (size_t)pi * kDepTexels;
-    for (uint32_t t = threadIdx.x; t < (uint32_t)kDepTexels; t += kProbeBlock) {
-        int s = gutter_source((int)(t % 18u), (int)(t / 18u), 16);
-        dout[t] = make_float2(s_dep[s][0], s_dep[s][1]);
+    // write quad records: each corner is an interior texel or the interior
+    // texel its gutter position mirrors
+    float4 *iout = reinterpret_cast<float4 *>(out.irr) + (size_t)pi * kIrrProbeF4;
+    float4 *dout = reinterpret_cast<float4 *>(out.dep) + (size_t)pi * kDepProbeF4;
+    for (uint32_t q = threadIdx.x; q < (uint32_t)kDepQuads; q += kProbeBlock) {
+        int cx = (int)(q % 17u), cy = (int)(q / 17u);
+        int s0 = gutter_source(cx, cy, kDepN), s1 = gutter_source(cx + 1, cy, kDepN);
+        int s2 = gutter_source(cx, cy + 1, kDepN), s3 = gutter_source(cx + 1, cy + 1, kDepN);
+        dout[2 * q] = make_float4(s_dep[s0][0], s_dep[s0][1], s_dep[s1][0], s_dep[s1][1]);
+        dout[2 * q + 1] = make_float4(s_dep[s2][0], s_dep[s2][1], s_dep[s3][0], s_dep[s3][1]);
     }
-    for (uint32_t t = threadIdx.x; t < (uint32_t)kIrrTexels; t += kProbeBlock) {
-        int s = gutter_source((int)(t % 10u), (int)(t / 10u), 8);
-        iout[t] = make_float4(s_irr[s][0], s_irr[s][1], s_irr[s][2], 0.0f);
+    for (uint32_t q = threadIdx.x; q < (uint32_t)kIrrQuads; q += kProbeBlock) {
+        int cx = (int)(q % 9u), cy = (int)(q / 9u);
+        int s0 = gutter_source(cx, cy, kIrrN), s1 = gutter_source(cx + 1, cy, kIrrN);
+        int s2 = gutter_source(cx, cy + 1, kIrrN), s3 = gutter_source(cx + 1, cy + 1, kIrrN);
+        iout[3 * q] = make_float4(s_irr[s0][0], s_irr[s0][1], s_irr[s0][2], s_irr[s1][0]);
+        iout[3 * q + 1] = make_float4(s_irr[s1][1], s_irr[s1][2], s_irr[s2][0], s_irr[s2][1]);
+        iout[3 * q + 2] = make_float4(s_irr[s2][2], s_irr[s3][0], s_irr[s3][1], s_irr[s3][2]);
     }
 }
 
@@ -259,12 +274,17 @@ __global__ void k_probe_query(gi_probes pr, uint32_t n, const float *p, const fl
 // --------------------------------------------------------------------------
 // initial resampling
 // --------------------------------------------------------------------------
+template <bool LDS>
 __global__ void __launch_bounds__(kBlock)
     k_initial(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_params pp, gi_reservoirs out, float4 *resid,
               uint64_t seed, uint32_t frame)
 {
+    using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
     uint32_t px, py;
-    if (!tile_pixel(gb.width, gb.height, px, py)) return;
+    const bool inside = tile_pixel(gb.width, gb.height, px, py);
+    if (LDS) stage_scene(sc);
+    if (!inside) return;
+    const Acc acc(sc);
     const uint32_t p = py * gb.width + px;
     const GB g = load_gb(gb, p);
     V3 rs = v3(0.0f, 0.0f, 0.0f);
@@ -286,9 +306,9 @@ __global__ void __launch_bounds__(kBlock)
         V3 y, ny = v3(0.0f, 0.0f, 0.0f), L = v3(0.0f, 0.0f, 0.0f);
         float phat = 0.0f, wi = 0.0f;
         uint32_t prim = GI_MISS;
-        if (cast<false>(sc, o, w, kInf, h)) {
+        if (cast<false>(sc, acc, o, w, kInf, h)) {
             y = madd(o, h.t, w);
-            ny = hit_normal(sc, o, w, h);
+            ny = hit_normal(sc, acc, o, w, h);
             prim = h.prim;
             V3 v = y - g.pos;
             float d2 = dot(v, v);
@@ -357,9 +377,9 @@ constexpr int kMaxDom = GI_MAX_K + 1;
 // a neighbour that was rejected or never drawn) and is loaded by dom(j);
 // slot 0 is the pixel itself.  Slots are static so that the unrolled loop
 // keeps everything in registers.
-template <int ND, class DomFn>
-__device__ __forceinline__ Res finish(const gi_scene &sc, const Merge &m, const GB &g, const uint32_t (&Mdom)[ND],
-                                      DomFn dom, const gi_params &pp)
+template <int ND, class DomFn, class G>
+__device__ __forceinline__ Res finish(const gi_scene &sc, const G &acc, const Merge &m, const GB &g,
+                                      const uint32_t (&Mdom)[ND], DomFn dom, const gi_params &pp)
 {
     if (!m.have) {
         Res e = empty_res(m.Msum);
@@ -372,7 +392,7 @@ __device__ __forceinline__ Res finish(const gi_scene &sc, const Merge &m, const 
     bool keep = true;
     if (pp.unbiased) {
         bool sky = is_zero(r.n);
-        bool vis_x = visible(sc, g.pos, g.n, r.y, r.n, sky);
+        bool vis_x = visible(sc, acc, g.pos, g.n, r.y, r.n, sky);
         keep = vis_x;
         uint32_t z = vis_x ? Mdom[0] : 0u;     // the target at x supports y (it was chosen)
 #pragma unroll
@@ -380,7 +400,7 @@ __device__ __forceinline__ Res finish(const gi_scene &sc, const Merge &m, const 
             if (Mdom[j] == 0u) continue;
             GB q = dom(j);
             if (res_target(q, r, pp.g_max) <= 0.0f) continue;
-            if (visible(sc, q.pos, q.n, r.y, r.n, sky)) z += Mdom[j];
+            if (visible(sc, acc, q.pos, q.n, r.y, r.n, sky)) z += Mdom[j];
         }
         Z = (float)z;
     } else {
@@ -406,12 +426,17 @@ __device__ __forceinline__ int reproject(const gi_camera &c, V3 x)
     return (int)fy * (int)c.width + (int)fx;
 }
 
+template <bool LDS>
 __global__ void __launch_bounds__(kBlock)
     k_temporal(gi_scene sc, gi_gbuffer gb, gi_gbuffer gbp, gi_camera cam_prev, gi_reservoirs cur,
                gi_reservoirs hist, gi_params pp, gi_reservoirs out, uint64_t seed, uint32_t frame)
 {
+    using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
     uint32_t px, py;
-    if (!tile_pixel(gb.width, gb.height, px, py)) return;
+    const bool inside = tile_pixel(gb.width, gb.height, px, py);
+    if (LDS) stage_scene(sc);
+    if (!inside) return;
+    const Acc acc(sc);
     const uint32_t p = py * gb.width + px;
     const GB g = load_gb(gb, p);
     const Res rc = load_res(cur, p);
@@ -436,15 +461,20 @@ __global__ void __launch_bounds__(kBlock)
             qprev = (uint32_t)q;
         }
     }
-    store_res(out, p, finish(sc, m, g, Mdom, [&](int) { return load_gb(gbp, qprev); }, pp));
+    store_res(out, p, finish(sc, acc, m, g, Mdom, [&](int) { return load_gb(gbp, qprev); }, pp));
 }
 
+template <bool LDS>
 __global__ void __launch_bounds__(kBlock)
     k_spatial(gi_scene sc, gi_gbuffer gb, gi_reservoirs in, gi_params pp, uint32_t pass, gi_reservoirs out,
               uint64_t seed, uint32_t frame)
 {
+    using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
     uint32_t px, py;
-    if (!tile_pixel(gb.width, gb.height, px, py)) return;
+    const bool inside = tile_pixel(gb.width, gb.height, px, py);
+    if (LDS) stage_scene(sc);
+    if (!inside) return;
+    const Acc acc(sc);
     const uint32_t W = gb.width, H = gb.height;
     const uint32_t p = py * W + px;
     const GB g = load_gb(gb, p);
@@ -478,18 +508,23 @@ __global__ void __launch_bounds__(kBlock)
         Mdom[j + 1] = rq.M;
         qidx[j + 1] = q;
     }
-    store_res(out, p, finish(sc, m, g, Mdom, [&](int j) { return load_gb(gb, qidx[j]); }, pp));
+    store_res(out, p, finish(sc, acc, m, g, Mdom, [&](int j) { return load_gb(gb, qidx[j]); }, pp));
 }
 
 // --------------------------------------------------------------------------
 // shading
 // --------------------------------------------------------------------------
+template <bool LDS>
 __global__ void __launch_bounds__(kBlock)
     k_shade(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_reservoirs res, const float4 *resid, gi_params pp,
             float4 *img)
 {
+    using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
     uint32_t px, py;
-    if (!tile_pixel(gb.width, gb.height, px, py)) return;
+    const bool inside = tile_pixel(gb.width, gb.height, px, py);
+    if (LDS) stage_scene(sc);
+    if (!inside) return;
+    const Acc acc(sc);
     const uint32_t p = py * gb.width + px;
     const GB g = load_gb(gb, p);
     float4 e = reinterpret_cast<const float4 *>(gb.emit)[p];
@@ -503,7 +538,7 @@ __global__ void __launch_bounds__(kBlock)
             bool ok = false;
             if (is_zero(r.n)) {
                 geo = dot(g.n, r.y);
-                if (geo > 0.0f && visible(sc, g.pos, g.n, r.y, r.n, true)) {
+                if (geo > 0.0f && visible(sc, acc, g.pos, g.n, r.y, r.n, true)) {
                     L = ld3(sc.sky);
                     ok = true;
                 }
@@ -514,7 +549,7 @@ __global__ void __launch_bounds__(kBlock)
                 float cx = dot(g.n, w), cy = -dot(r.n, w);
                 if (cx > 0.0f && cy > 0.0f) {
                     geo = fminf(cx * cy * rcp(d2), pp.g_max);
-                    if (visible(sc, g.pos, g.n, r.y, r.n, false)) {
+                    if (visible(sc, acc, g.pos, g.n, r.y, r.n, false)) {
                         L = radiance_toward(sc, pr, r.prim, r.y, r.n, g.pos);
                         ok = true;
                     }
@@ -543,8 +578,9 @@ __global__ void k_trace(gi_scene sc, uint32_t n, const float *org, const float *
     if (i >= n) return;
     V3 o = ld3(org + 3 * i), d = ld3(dir + 3 * i);
     Hit h;
-    if (cast<false>(sc, o, d, kInf, h)) {
-        V3 nn = hit_normal(sc, o, d, h);
+    const GeoGlobal acc(sc);
+    if (cast<false>(sc, acc, o, d, kInf, h)) {
+        V3 nn = hit_normal(sc, acc, o, d, h);
         out[i] = make_float4(h.t, nn.x, nn.y, nn.z);
         prim[i] = h.prim;
     } else {
@@ -567,7 +603,7 @@ gi_status check_scene(const gi_scene *sc)
     if (sc->n_prims > 0 && !sc->prims) return GI_ERR_NULL;
     if (!(sc->eps >= 0.0f)) return GI_ERR_PARAM;
     if (sc->cell_start) {
-        if (!sc->cell_items) return GI_ERR_NULL;
+        if (!sc->cell_items && sc->n_items) return GI_ERR_NULL;
         if (sc->grid_res[0] == 0 || sc->grid_res[1] == 0 || sc->grid_res[2] == 0) return GI_ERR_SHAPE;
         if ((uint64_t)sc->grid_res[0] * sc->grid_res[1] * sc->grid_res[2] > (1u << 26)) return GI_ERR_SHAPE;
         for (int a = 0; a < 3; ++a)
@@ -621,6 +657,26 @@ gi_status check_params(const gi_params *pp)
 }
 
 hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Dynamic LDS a tracing kernel needs to stage the scene, or 0 to read it from
+// global memory (no grid, staging switched off, or over budget: 40 KB keeps
+// four 256-thread workgroups per CU; a kernel with static LDS stays within
+// 64 KB in total).
+constexpr uint32_t kLdsScene = 40u * 1024u;
+constexpr uint32_t kLdsTotal = 64u * 1024u;
+uint32_t scene_lds(const gi_scene *sc, uint32_t static_lds = 0)
+{
+    if (!sc->cell_start || sc->n_items == 0 || (sc->options & GI_OPT_NO_LDS)) return 0;
+    uint32_t b = lds_scene_bytes(*sc);
+    if (static_lds == 0) return b <= kLdsScene ? b : 0u;
+    return b + static_lds <= kLdsTotal ? b : 0u;
+}
+
+#define GI_LAUNCH_LDS(kernel, grid, block, lds, stream, ...)                                   \
+    do {                                                                                      \
+        if (lds) kernel<true><<<(grid), (block), (lds), (stream)>>>(__VA_ARGS__);             \
+        else kernel<false><<<(grid), (block), 0, (stream)>>>(__VA_ARGS__);                   \
+    } while (0)
 
 }  // namespace
 
@@ -676,7 +732,8 @@ gi_status gi_probe_update(const gi_scene *scene, const gi_probes *in, gi_probes 
     if (pp->rays < 1 || pp->rays > GI_MAX_PROBE_RAYS) return GI_ERR_PARAM;
     if (!(pp->hysteresis >= 0.0f && pp->hysteresis <= 1.0f) || !(pp->sharpness > 0.0f)) return GI_ERR_PARAM;
     uint32_t P = in->dims[0] * in->dims[1] * in->dims[2];
-    k_probe_update<<<P, kProbeBlock, 0, S(stream)>>>(*scene, *in, *out, *pp, seed, frame);
+    uint32_t lds = scene_lds(scene, (uint32_t)sizeof(float) * (7u * GI_MAX_PROBE_RAYS + 64u * 3u + 256u * 2u));
+    GI_LAUNCH_LDS(k_probe_update, P, kProbeBlock, lds, S(stream), *scene, *in, *out, *pp, seed, frame);
     return launched();
 }
 
@@ -704,8 +761,8 @@ gi_status gi_resample_initial(const gi_scene *scene, const gi_gbuffer *gb, const
     if ((s = check_res(out, gb->width, gb->height)) != GI_OK) return s;
     if ((uint64_t)gb->width * gb->height > (1u << 23)) return GI_ERR_SHAPE;   // 23-bit tag origin
     if (gb->width == 0 || gb->height == 0) return GI_OK;
-    k_initial<<<tile_grid(gb->width, gb->height), kBlock, 0, S(stream)>>>(
-        *scene, *gb, *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame);
+    GI_LAUNCH_LDS(k_initial, tile_grid(gb->width, gb->height), kBlock, scene_lds(scene), S(stream), *scene, *gb,
+                  *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame);
     return launched();
 }
 
@@ -727,8 +784,8 @@ gi_status gi_resample_temporal(const gi_scene *scene, const gi_gbuffer *gb, cons
     if ((s = check_res(out, W, H)) != GI_OK) return s;
     if (res_alias(out, cur_in) || res_alias(out, history)) return GI_ERR_ALIAS;
     if (W == 0 || H == 0) return GI_OK;
-    k_temporal<<<tile_grid(W, H), kBlock, 0, S(stream)>>>(*scene, *gb, *gb_prev, *prev_cam, *cur_in, *history,
-                                                         *params, *out, seed, frame);
+    GI_LAUNCH_LDS(k_temporal, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *gb_prev,
+                  *prev_cam, *cur_in, *history, *params, *out, seed, frame);
     return launched();
 }
 
@@ -747,7 +804,8 @@ gi_status gi_resample_spatial(const gi_scene *scene, const gi_gbuffer *gb, const
     if (res_alias(out, in)) return GI_ERR_ALIAS;
     if (pass > 5) return GI_ERR_PARAM;
     if (W == 0 || H == 0) return GI_OK;
-    k_spatial<<<tile_grid(W, H), kBlock, 0, S(stream)>>>(*scene, *gb, *in, *params, pass, *out, seed, frame);
+    GI_LAUNCH_LDS(k_spatial, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *in, *params,
+                  pass, *out, seed, frame);
     return launched();
 }
 
@@ -763,9 +821,8 @@ gi_status gi_shade(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes 
     if ((s = check_params(params)) != GI_OK) return s;
     if ((s = check_res(res, W, H)) != GI_OK) return s;
     if (W == 0 || H == 0) return GI_OK;
-    k_shade<<<tile_grid(W, H), kBlock, 0, S(stream)>>>(*scene, *gb, *probes, *res,
-                                                      reinterpret_cast<const float4 *>(resid), *params,
-                                                      reinterpret_cast<float4 *>(out_rgba));
+    GI_LAUNCH_LDS(k_shade, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *probes, *res,
+                  reinterpret_cast<const float4 *>(resid), *params, reinterpret_cast<float4 *>(out_rgba));
     return launched();
 }
 

@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgi.so")
 MISS = 0xFFFFFFFF
 EMPTY_TAG = 0xFFFFFFFF
+OPT_NO_LDS = 1
 
 _lib = None
 
@@ -43,7 +44,8 @@ class GiScene(C.Structure):
     _fields_ = [("prims", C.c_void_p), ("n_prims", C.c_uint32), ("has_room", C.c_uint32),
                 ("room_lo", F3), ("room_hi", F3), ("wall_albedo", F3), ("wall_emit", F3), ("sky", F3),
                 ("eps", C.c_float), ("grid_res", U3), ("grid_lo", F3), ("grid_hi", F3),
-                ("cell_start", C.c_void_p), ("cell_items", C.c_void_p)]
+                ("cell_start", C.c_void_p), ("cell_items", C.c_void_p), ("n_items", C.c_uint32),
+                ("options", C.c_uint32)]
 
 
 class GiCamera(C.Structure):
@@ -136,7 +138,7 @@ def _f3(v):
 class DeviceScene:
     """Primitive records (and the optional grid accelerator) on the device."""
 
-    def __init__(self, scene: sg.Scene, grid_res=None, device="cuda"):
+    def __init__(self, scene: sg.Scene, grid_res=None, device="cuda", lds=True):
         self.scene = scene
         rec = np.ascontiguousarray(scene.prims.astype(np.float32))
         self.prims = torch.from_numpy(rec.copy()).to(device)
@@ -148,6 +150,7 @@ class DeviceScene:
         s.wall_albedo, s.wall_emit = _f3(scene.wall_albedo), _f3(scene.wall_emit)
         s.sky = _f3(scene.sky)
         s.eps = float(scene.eps)
+        s.options = 0 if lds else OPT_NO_LDS
         self.cell_start = self.cell_items = None
         if grid_res is not None:
             lo, hi = scene.bounds()
@@ -170,6 +173,7 @@ class DeviceScene:
             s.grid_lo, s.grid_hi = lo_c, hi_c
             s.cell_start = self.cell_start.data_ptr()
             s.cell_items = self.cell_items.data_ptr()
+            s.n_items = int(n_items.value)
             self.n_items = int(n_items.value)
         self.c = s
 
@@ -277,12 +281,38 @@ class Reservoirs:
         self.tag_prim.copy_(torch.from_numpy(d.view(np.int32)))
 
 
+def tiles_to_quads(tiles, N):
+    """Gutter-padded tiles (P, (N+2)^2, C) -> bilinear quad records
+    (P, (N+1)^2, 4C): record (cx, cy) = texels (cx,cy), (cx+1,cy), (cx,cy+1),
+    (cx+1,cy+1)."""
+    t = np.asarray(tiles)
+    P, C_ = t.shape[0], t.shape[-1]
+    T = t.reshape(P, N + 2, N + 2, C_)
+    q = np.stack([T[:, :N + 1, :N + 1], T[:, :N + 1, 1:], T[:, 1:, :N + 1], T[:, 1:, 1:]], axis=3)
+    return q.reshape(P, (N + 1) ** 2, 4 * C_)
+
+
+def quads_to_tiles(quads, N, C_):
+    """Inverse of tiles_to_quads."""
+    q = np.asarray(quads)
+    P = q.shape[0]
+    Q = q.reshape(P, N + 1, N + 1, 4, C_)
+    T = np.zeros((P, N + 2, N + 2, C_), q.dtype)
+    T[:, :N + 1, :N + 1] = Q[:, :, :, 0]
+    T[:, :N + 1, N + 1] = Q[:, :, N, 1]
+    T[:, N + 1, :N + 1] = Q[:, N, :, 2]
+    T[:, N + 1, N + 1] = Q[:, N, N, 3]
+    return T.reshape(P, (N + 2) ** 2, C_)
+
+
 class Probes:
+    """Probe textures in the library's quad-record layout (see gi.h)."""
+
     def __init__(self, grid: sg.ProbeGrid, device="cuda"):
         self.grid = grid
         P = grid.count
-        self.irr = torch.zeros(P, (grid.irr_res + 2) ** 2, 4, dtype=torch.float32, device=device)
-        self.dep = torch.zeros(P, (grid.dep_res + 2) ** 2, 2, dtype=torch.float32, device=device)
+        self.irr = torch.zeros(P, (grid.irr_res + 1) ** 2, 12, dtype=torch.float32, device=device)
+        self.dep = torch.zeros(P, (grid.dep_res + 1) ** 2, 8, dtype=torch.float32, device=device)
         p = GiProbes()
         p.dims = (C.c_uint32 * 3)(*grid.dims)
         p.irr_res, p.dep_res = grid.irr_res, grid.dep_res
@@ -296,11 +326,18 @@ class Probes:
         return C.byref(self.c)
 
     def load(self, irr, dep):
-        irr = np.asarray(irr)
-        a = np.zeros(tuple(self.irr.shape), np.float32)
-        a[..., :3] = irr[..., :3]
-        self.irr.copy_(torch.from_numpy(a))
-        self.dep.copy_(torch.from_numpy(np.asarray(dep, np.float32)[..., :2].copy()))
+        """Fill from gutter-padded tiles: irr (P, (N+2)^2, >=3), dep (P, (Nd+2)^2, 2)."""
+        g = self.grid
+        qi = tiles_to_quads(np.asarray(irr, np.float32)[..., :3], g.irr_res)
+        qd = tiles_to_quads(np.asarray(dep, np.float32)[..., :2], g.dep_res)
+        self.irr.copy_(torch.from_numpy(np.ascontiguousarray(qi)))
+        self.dep.copy_(torch.from_numpy(np.ascontiguousarray(qd)))
+
+    def tiles(self):
+        """(irr (P, (N+2)^2, 3), dep (P, (Nd+2)^2, 2)) as gutter-padded tiles."""
+        g = self.grid
+        return (quads_to_tiles(self.irr.cpu().numpy(), g.irr_res, 3),
+                quads_to_tiles(self.dep.cpu().numpy(), g.dep_res, 2))
 
 
 def params_struct(p: sg.Params) -> GiParams:
@@ -392,12 +429,12 @@ class Renderer:
     reservoirs, spatial passes (ping-pong) and shading."""
 
     def __init__(self, cfg: sg.Config, seed: int = 1, width=None, height=None, use_grid=True,
-                 device="cuda", scene=None, params=None):
+                 device="cuda", scene=None, params=None, lds=True):
         self.cfg = cfg
         self.seed = seed
         self.W, self.H = int(width or cfg.width), int(height or cfg.height)
         self.scene = scene if scene is not None else sg.make_scene(cfg)
-        self.dscene = DeviceScene(self.scene, cfg.grid_res if use_grid else None, device)
+        self.dscene = DeviceScene(self.scene, cfg.grid_res if use_grid else None, device, lds=lds)
         self.grid = sg.make_probe_grid(cfg)
         self.params = params if params is not None else cfg.params
         self.probes = [Probes(self.grid, device), Probes(self.grid, device)]

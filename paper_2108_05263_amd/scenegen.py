@@ -174,7 +174,7 @@ CONFIGS = {
         pan=0.05, probe_dims=(32, 8, 32), probe_spacing=1.0,
         params=Params(M=32, k=5, n_spatial=2, radius=30.0, temporal=True),
         probe_update=ProbeUpdate(rays=256, hysteresis=0.0, fill_passes=4, fill_rays=256),
-        frames=8, grid_res=(32, 8, 32)),
+        frames=8, grid_res=(16, 4, 16)),
     # 3840x2160, same room with 512 + 512 primitives, 64x16x64 probes updated every
     # frame with 256 rays at hysteresis 0.97.
     "uhd": Config(
@@ -185,7 +185,7 @@ CONFIGS = {
         params=Params(M=32, k=5, n_spatial=2, radius=30.0, temporal=True),
         probe_update=ProbeUpdate(rays=256, hysteresis=0.97, fill_passes=4, fill_rays=256,
                                  per_frame=True),
-        frames=16, grid_res=(64, 16, 64)),
+        frames=16, grid_res=(12, 3, 12)),
 }
 
 

@@ -119,3 +119,15 @@ def test_accel_builder_lists_overlapping_cells(gi):
     for c in range(ncell):
         seg = items[start[c]:start[c + 1]]
         assert np.all(np.diff(seg.astype(np.int64)) > 0)
+
+
+def test_quad_layout_round_trip(gi):
+    rng = np.random.default_rng(0)
+    for N, C_ in ((8, 3), (16, 2)):
+        t = rng.random((5, (N + 2) ** 2, C_)).astype(np.float32)
+        q = gi.tiles_to_quads(t, N)
+        assert q.shape == (5, (N + 1) ** 2, 4 * C_)
+        assert np.array_equal(gi.quads_to_tiles(q, N, C_), t)
+        # record (cx, cy) corner 3 is padded texel (cx+1, cy+1)
+        T = t.reshape(5, N + 2, N + 2, C_)
+        assert np.array_equal(q.reshape(5, N + 1, N + 1, 4, C_)[:, 2, 5, 3], T[:, 3, 6])

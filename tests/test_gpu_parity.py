@@ -163,8 +163,10 @@ def test_probe_update(gi, tiny):
     pin.load(i2, d2)
     for hyst in (0.0, 0.97):
         gi.probe_update(ds, pin, pout, 64, hyst, 50.0, 1, 5)
-        gi_irr = pout.irr.cpu().numpy()[..., :3]
-        gi_dep = pout.dep.cpu().numpy()
+        gi_irr, gi_dep = pout.tiles()
+        # every quad record agrees with the padded tile it encodes (gutters included)
+        assert np.array_equal(pout.irr.cpu().numpy(), gi.tiles_to_quads(gi_irr, grid.irr_res))
+        assert np.array_equal(pout.dep.cpu().numpy(), gi.tiles_to_quads(gi_dep, grid.dep_res))
         ri, rd = o.probe_update(sc, grid, i2, d2, 64, hyst, 50.0, 1, 5)
         ei, ed = rel_err(gi_irr, ri), rel_err(gi_dep, rd)
         log(f"probe update h={hyst}: irr mean {ei.mean():.2e} max {ei.max():.2e}; "
@@ -264,6 +266,23 @@ def test_free_running(gi, request, which, frames):
         m = compare_images(gimg, oimg, same, tol=1e-4, label=f"{which} frame {f}")
         log(f"free-running {which} frame {f}: flips {flips:.2e}, mean rel image err (unflipped) {m:.2e}")
         assert flips <= 1e-3
+
+
+@pytest.mark.parametrize("which", ["tiny", "hd_small"])
+def test_lds_staging_matches_global(gi, request, which):
+    """Tracing from the LDS copy of the scene gives bit-identical frames."""
+    cfg, sc, grid, irr, dep = request.getfixturevalue(which)
+    W, H = (64, 64) if which == "tiny" else (250, 141)
+    out = []
+    for lds in (True, False):
+        r = gi.Renderer(cfg, seed=2, width=W, height=H, scene=sc, lds=lds)
+        r.probe.load(irr, dep)
+        for f in range(2):
+            r.frame(f)
+        torch.cuda.synchronize()
+        out.append((r.img.cpu().numpy().copy(), r.hist.to_records()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
 
 
 def test_determinism(gi, tiny):
