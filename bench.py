@@ -42,8 +42,38 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="hd")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
-    ap.add_argument("--cpu-crop", type=int, nargs=2, default=(160, 90))
+    ap.add_argument("--cpu-crop", type=int, nargs=2, default=(320, 180))
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="after the timed region, copy 1 GiB device-to-device once (a known-size "
+                         "reference for the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ["paper_2108_05263_amd/csrc/gi_kernels.hip", "paper_2108_05263_amd/csrc/gi_device.hpp",
+                  "include/gi.h"]
+
+
+def source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs (profiles/<kernel>_hd_traffic.json), if they were taken on the
+    current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_hd_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha") != source_sha():
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def cpu_baseline(cfg, crop):
@@ -138,6 +168,12 @@ def main():
         times[key].append(e0.elapsed_time(e1))
     for k, v in orig.items():
         setattr(gi, k, v)
+    if args.profile_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     W, H = r.W, r.H
     npx = W * H
@@ -172,8 +208,10 @@ def main():
         "resampling_only_pixels_per_s": npx / (resampling_ms * 1e-3),
         "path_hbm_frac": path_bytes / ((sum(avg.values())) * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"kernel": f"k_{dom_key}", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"k_{dom_key}"),
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "kernel_source_sha": source_sha()},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg, tuple(args.cpu_crop))
