@@ -969,3 +969,43 @@ void o_brute_force(const o_scene *sc, const o_probes *pr, const double *gb, int3
         for (int a = 0; a < 3; ++a) o[a] += acc[a] / (double)nsamples;
     }
 }
+
+/* ---------------------------------------------------------------------------
+ * Training samples of the learned cache (the MLP that can stand in for the
+ * probe query; caches are interchangeable, Sec. 2 and Sec. 5).  Sample j
+ * (counter (j, frame, 10, 0)) picks pixel p = floor(u0 W H) and takes the
+ * surface sample y, n_y of that pixel's initial reservoir; its label is a
+ * one-sample estimate of E(y, n_y)/pi: the radiance arriving along a
+ * cosine-distributed direction (u1, u2) about n_y, L_e(z) + rho_z Q(z_b, n_z)
+ * from the hit z (z_b biased toward y), or the sky.  Samples whose pixel has
+ * no surface sample get valid = 0.
+ * ------------------------------------------------------------------------- */
+void o_mlp_batch(const o_scene *sc, const o_probes *pr, int32_t W, int32_t H, const double *gb,
+                 const double *res, int64_t B, uint64_t seed, uint32_t frame, double *pos, double *nrm,
+                 double *target, int32_t *valid)
+{
+    for (int64_t j = 0; j < B; ++j) {
+        double u[4];
+        rand4(seed, (uint32_t)j, frame, 10u, 0u, u);
+        int64_t p = (int64_t)floor(u[0] * (double)W * (double)H);
+        const double *g = gb + GB_N * p;
+        const double *r = res + R_N * p;
+        valid[j] = 0;
+        for (int a = 0; a < 3; ++a) { pos[3 * j + a] = 0.0; nrm[3 * j + a] = 0.0; target[3 * j + a] = 0.0; }
+        if (!pixel_active(g) || !(r[R_W] > 0.0) || res_is_sky(r)) continue;
+        const double *y = r + R_Y, *ny = r + R_NY;
+        double w[3], o[3], L[3];
+        o_cosine_dir(ny, u[1], u[2], w);
+        for (int a = 0; a < 3; ++a) o[a] = y[a] + sc->eps * ny[a];
+        o_hit h;
+        if (closest_hit(sc, o, w, O_INF, &h)) {
+            double z[3];
+            for (int a = 0; a < 3; ++a) z[a] = o[a] + h.t * w[a];
+            radiance_toward(sc, pr, h.prim, z, h.n, y, L);
+        } else {
+            for (int a = 0; a < 3; ++a) L[a] = sc->sky[a];
+        }
+        valid[j] = 1;
+        for (int a = 0; a < 3; ++a) { pos[3 * j + a] = y[a]; nrm[3 * j + a] = ny[a]; target[3 * j + a] = L[a]; }
+    }
+}

@@ -1,0 +1,244 @@
+"""Pins of the learned-cache oracle (oracle/mlp_ref.py) against independent
+implementations:
+
+* BF16 / FP8-E4M3FN rounding == torch's casts;
+* encoding identities (sin^2 + cos^2 = 1, frequency doubling, raw value);
+* FP64 forward == torch Linear/ReLU stack; backward == torch autograd of the
+  relative-L2 loss with a stop-gradient denominator; central finite
+  differences agree with the backward;
+* BF16 forward/backward == torch autograd where every GEMM operand (and
+  back-propagated gradient) passes through a BF16 rounding function;
+* FP8 forward == torch float8_e4m3fn casts with per-layer scales;
+* Adam == torch.optim.Adam (float64);
+* training labels in a closed form: in a room whose walls emit L and whose
+  probes are empty, every label equals L exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as o
+from oracle import mlp_ref as M
+from paper_2108_05263_amd import scenegen as sg
+
+torch.set_default_dtype(torch.float64)
+
+
+def _batch(n=64, seed=0):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, 8.0, (n, 3))
+    nrm = rng.normal(size=(n, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return M.encode(pos, nrm, np.zeros(3), np.full(3, 8.0))
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.normal(0, 10, 5000), rng.normal(0, 1e-3, 1000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.005859375, 3.0e38, -1e-30]])
+    # exact ties: values halfway between two bf16 numbers
+    b = rng.integers(0x3C00, 0x4300, 200).astype(np.uint32)       # bf16 patterns in [2^-7, 2^7)
+    ties = ((b << 16) | 0x8000).view(np.float32).astype(np.float64)
+    x = np.concatenate([x, ties])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(M.round_bf16(x), ref)
+
+
+def test_fp8_rounding_matches_torch():
+    rng = np.random.default_rng(2)
+    x = np.concatenate([rng.normal(0, 50, 5000), rng.normal(0, 0.01, 2000),
+                        np.arange(-64, 64) / 32.0 + 1.0 / 64.0,      # ties at various exponents
+                        [0.0, 448.0, -448.0, 2.0 ** -9, 2.0 ** -10, 3 * 2.0 ** -11]])
+    x = np.clip(x, -448, 448)
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(M.round_fp8_e4m3(x), ref)
+    assert np.all(np.abs(M.round_fp8_e4m3([1000.0, -900.0])) == 448.0)
+
+
+def test_encoding_identities():
+    rng = np.random.default_rng(3)
+    pos = rng.uniform(0, 8, (50, 3))
+    nrm = rng.normal(size=(50, 3))
+    lo, hi = np.zeros(3), np.full(3, 8.0)
+    X = M.encode(pos, nrm, lo, hi)
+    assert X.shape == (50, 78) and M.N_ENC == 78
+    v = np.concatenate([pos / 8.0, nrm], axis=1)
+    for i in range(6):
+        assert np.allclose(X[:, 13 * i], v[:, i], rtol=0, atol=1e-15)
+        for j in range(6):
+            s, c = X[:, 13 * i + 1 + 2 * j], X[:, 13 * i + 2 + 2 * j]
+            assert np.allclose(s * s + c * c, 1.0, atol=1e-12)
+            if j > 0:
+                sp, cp = X[:, 13 * i + 2 * j - 1], X[:, 13 * i + 2 * j]
+                assert np.allclose(s, 2 * sp * cp, atol=1e-12)
+        # j = 0 is sin(pi v): zero at v = 0 and v = 1
+    z = M.encode(np.zeros((1, 3)), np.zeros((1, 3)), lo, hi)
+    assert np.allclose(z[0, 1::13][:6], 0.0) and np.allclose(z[0, 2::13][:6], 1.0)
+
+
+def _torch_net(params):
+    layers = []
+    for (W, b), (i, n) in zip(M.split(params), M.LAYERS):
+        lin = torch.nn.Linear(i, n)
+        lin.weight.data = torch.tensor(W)
+        lin.bias.data = torch.tensor(b)
+        layers.append(lin)
+    return layers
+
+
+def _torch_forward(layers, X, rnd=None):
+    h = X
+    for li, lin in enumerate(layers):
+        if rnd is not None:
+            h = rnd(h) @ rnd(lin.weight).T + lin.bias
+        else:
+            h = lin(h)
+        if li < len(layers) - 1:
+            h = torch.relu(h)
+    return h
+
+
+def _torch_loss(out, target, valid):
+    w = torch.tensor(valid, dtype=torch.float64)[:, None]
+    den = out.detach() ** 2 + 0.01
+    return (((out - target) ** 2 / den) * w).sum() / (max(valid.sum(), 1) * 3)
+
+
+def test_fp64_forward_backward_match_torch_and_fd():
+    params = M.init_params(7)
+    assert params.size == M.N_PARAMS == 17731
+    X = _batch(48)
+    rng = np.random.default_rng(4)
+    target = rng.uniform(0, 2, (48, 3))
+    valid = rng.random(48) > 0.2
+    out, cache = M.forward(params, X)
+    layers = _torch_net(params)
+    tout = _torch_forward(layers, torch.tensor(X))
+    assert np.allclose(out, tout.detach().numpy(), rtol=1e-12, atol=1e-12)
+    loss, g = M.loss_and_grad_out(out, target, valid)
+    tl = _torch_loss(tout, torch.tensor(target), valid)
+    assert loss == pytest.approx(float(tl), rel=1e-12)
+    grad = M.backward(params, cache, g)
+    tl.backward()
+    tg = np.concatenate([np.concatenate([l.weight.grad.numpy().ravel(), l.bias.grad.numpy()]) for l in layers])
+    assert np.allclose(grad, tg, rtol=1e-10, atol=1e-14)
+    # central finite differences of the loss with the denominator frozen
+    den_fixed = out * out + 0.01
+
+    def loss_frozen(p):
+        o_, _ = M.forward(p, X)
+        w = valid.astype(np.float64)[:, None]
+        return float((((o_ - target) ** 2 / den_fixed) * w).sum() / (valid.sum() * 3))
+    for idx in rng.choice(M.N_PARAMS, 25, replace=False):
+        h = 1e-6
+        pp, pm = params.copy(), params.copy()
+        pp[idx] += h
+        pm[idx] -= h
+        fd = (loss_frozen(pp) - loss_frozen(pm)) / (2 * h)
+        assert fd == pytest.approx(grad[idx], rel=1e-5, abs=1e-10)
+
+
+class _RoundFwd(torch.autograd.Function):
+    """BF16 rounding of a GEMM operand (forward only)."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return x.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+class _RoundGradIn(torch.autograd.Function):
+    """Identity forward; BF16 rounding of the gradient that enters the GEMM
+    backward products (dW = g^T x and dx = g W take g in BF16)."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return x
+
+    @staticmethod
+    def backward(ctx, g):
+        return g.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+def test_bf16_training_semantics_match_torch():
+    params = M.init_params(8)
+    X = _batch(40, 5)
+    rng = np.random.default_rng(6)
+    target = rng.uniform(0, 2, (40, 3))
+    valid = np.ones(40, bool)
+    out, cache = M.forward(params, X, prec="bf16")
+    loss, g = M.loss_and_grad_out(out, target, valid)
+    grad = M.backward(params, cache, g, prec="bf16")
+    layers = _torch_net(params)
+    h = torch.tensor(X)
+    for li, lin in enumerate(layers):
+        z = _RoundGradIn.apply(_RoundFwd.apply(h) @ _RoundFwd.apply(lin.weight).T) + lin.bias
+        h = torch.relu(z) if li < len(layers) - 1 else z
+    assert np.allclose(out, h.detach().numpy(), rtol=1e-12, atol=1e-12)
+    tl = _torch_loss(h, torch.tensor(target), valid)
+    tl.backward()
+    tg = np.concatenate([np.concatenate([l.weight.grad.numpy().ravel(), l.bias.grad.numpy()]) for l in layers])
+    assert np.allclose(grad, tg, rtol=1e-9, atol=1e-13)
+    # BF16 output stays close to FP64
+    ref, _ = M.forward(params, X)
+    assert np.max(np.abs(out - ref)) < 0.05 * (np.max(np.abs(ref)) + 1e-3)
+
+
+def test_fp8_forward_matches_torch_casts():
+    params = M.init_params(9)
+    X = _batch(40, 7)
+    amax = M.act_amax(params, X)
+    sa = [a / 448.0 for a in amax]
+    out, _ = M.forward(params, X, prec="fp8", act_scales=sa)
+    h = torch.tensor(X)
+    f8 = torch.float8_e4m3fn
+    for li, (W, b) in enumerate(M.split(params)):
+        sw = float(np.max(np.abs(W))) / 448.0
+        a8 = (h / sa[li]).clamp(-448, 448).to(torch.float32).to(f8).to(torch.float64)
+        w8 = (torch.tensor(W) / sw).to(torch.float32).to(f8).to(torch.float64)
+        h = (a8 @ w8.T) * (sw * sa[li]) + torch.tensor(b)
+        if li < 4:
+            h = torch.relu(h)
+    assert np.allclose(out, h.numpy(), rtol=1e-12, atol=1e-12)
+    ref, _ = M.forward(params, X)
+    assert np.max(np.abs(out - ref)) < 0.2 * (np.max(np.abs(ref)) + 1e-3)
+
+
+def test_adam_matches_torch():
+    rng = np.random.default_rng(10)
+    p = rng.normal(size=300)
+    m, v = np.zeros(300), np.zeros(300)
+    tp = torch.tensor(p.copy(), requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=1e-2, betas=(0.9, 0.99), eps=1e-8)
+    for t in range(1, 8):
+        g = rng.normal(size=300) * (0.1 * t)
+        p, m, v = M.adam_step(p, m, v, g, t)
+        tp.grad = torch.tensor(g)
+        opt.step()
+        assert np.allclose(p, tp.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+def test_batch_labels_closed_form():
+    # walls emit L and have albedo 0.5, probes empty: a label is the radiance
+    # arriving from another wall point, L_e + rho * Q = L exactly
+    L = np.array([0.7, 1.1, 1.9], np.float32)
+    sc = sg.Scene(prims=np.zeros((0, 16), np.float32), has_room=True, room_lo=np.zeros(3, np.float32),
+                  room_hi=np.full(3, 8.0, np.float32), wall_albedo=np.full(3, 0.5, np.float32),
+                  sky=np.zeros(3, np.float32), eps=8e-4, wall_emit=L)
+    cfg = sg.CONFIGS["tiny"]
+    cam = sg.make_camera(cfg, 0, 24, 24)
+    grid = sg.probe_grid((2, 2, 2), (0, 0, 0), 4.0)
+    irr, dep = sg.empty_probe_textures(grid)
+    gb = o.gbuffer(sc, cam)
+    res, _ = o.resample_initial(sc, 24, 24, gb, grid, irr, dep, sg.Params(M=4), 1, 0)
+    pos, nrm, tgt, valid = o.mlp_batch(sc, 24, 24, gb, res, grid, irr, dep, 300, 5, 0)
+    assert valid.mean() > 0.9
+    assert np.array_equal(tgt[valid], np.broadcast_to(L.astype(np.float64), tgt[valid].shape))
+    # inputs are the reservoirs' surface samples, on the walls
+    on_wall = np.min(np.minimum(pos[valid], 8.0 - pos[valid]), axis=1)
+    assert np.all(on_wall < 1e-6)
