@@ -59,6 +59,11 @@ typedef struct {
     double d_max;                   /* depth clamp for probe rays */
     const double *irr;
     const double *dep;
+    /* learned cache used as the target instead of the probe query (NULL: probes) */
+    const double *mlp;              /* 17731 parameters, layout of oracle/mlp_ref.py */
+    int32_t mlp_prec;               /* 0: FP64, 1: BF16 operands */
+    int32_t mlp_pad;
+    double mlp_lo[3], mlp_hi[3];    /* position normalisation box */
 } o_probes;
 
 typedef struct {
@@ -478,19 +483,88 @@ void o_view_bias(const double *y, const double *x, double d, double *out)
     for (int a = 0; a < 3; ++a) out[a] = y[a] + s * v[a] / dist;
 }
 
-/* Radiance leaving surface point y toward x: L_e(y) + rho_y * Q(y_b, n_y),
- * i.e. L_DDGI+ of Eq. 4/5 with the diffuse term rho/pi * E = rho * Q. */
-static void radiance_toward(const o_scene *sc, const o_probes *pr, uint32_t prim, const double *y,
-                            const double *ny, const double *x, double *L)
+/* ---------------------------------------------------------------------------
+ * Learned cache: the MLP of oracle/mlp_ref.py written out in plain loops
+ * (encoding, 78-64-64-64-64-3 with ReLU).  prec 1 rounds every GEMM operand
+ * (encoded input, weights, hidden activations) to BF16 through FP32, nearest
+ * even.  The output approximates E/pi like the probe query.
+ * ------------------------------------------------------------------------- */
+static double bf16r(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+void o_mlp_forward(const double *params, int prec, const double *lo, const double *hi, const double *pos,
+                   const double *nrm, double *out)
+{
+    static const int dims[6] = {78, 64, 64, 64, 64, 3};
+    double a[80], b[80];
+    double v[6];
+    for (int i = 0; i < 3; ++i) {
+        v[i] = (pos[i] - lo[i]) / (hi[i] - lo[i]);
+        v[3 + i] = nrm[i];
+    }
+    for (int i = 0; i < 6; ++i) {
+        a[13 * i] = v[i];
+        for (int j = 0; j < 6; ++j) {
+            double f = ldexp(1.0, j) * O_PI * v[i];
+            a[13 * i + 1 + 2 * j] = sin(f);
+            a[13 * i + 2 + 2 * j] = cos(f);
+        }
+    }
+    const double *w = params;
+    for (int l = 0; l < 5; ++l) {
+        int ni = dims[l], no = dims[l + 1];
+        const double *W = w, *bias = w + ni * no;
+        for (int o = 0; o < no; ++o) {
+            double acc = 0.0;
+            for (int k = 0; k < ni; ++k) {
+                double x = prec ? bf16r(a[k]) : a[k];
+                double wk = prec ? bf16r(W[o * ni + k]) : W[o * ni + k];
+                acc += x * wk;
+            }
+            acc += bias[o];
+            b[o] = (l < 4 && acc < 0.0) ? 0.0 : acc;
+        }
+        memcpy(a, b, sizeof(double) * no);
+        w += ni * no + no;
+    }
+    for (int c = 0; c < 3; ++c) out[c] = a[c];
+}
+
+/* Radiance leaving surface point y toward x: L_e(y) + rho_y * C(y), the
+ * radiance L_DDGI+ of Eq. 4/5 (diffuse term rho/pi * E = rho * E/pi).  C is
+ * the probe query Q(y_b, n_y) at the view-path-biased point, or, when a
+ * learned cache is set and allowed, its output max(0, MLP(y, n_y)) at y
+ * itself (the bias only guards the probes' visibility test). */
+static void radiance_toward_ex(const o_scene *sc, const o_probes *pr, uint32_t prim, const double *y,
+                               const double *ny, const double *x, int allow_mlp, double *L)
 {
     double alb[3], emit[3];
     material(sc, prim, alb, emit);
     for (int a = 0; a < 3; ++a) L[a] = emit[a];
     if (alb[0] == 0.0 && alb[1] == 0.0 && alb[2] == 0.0) return;
-    double pb[3], q[3];
-    o_view_bias(y, x, pr->bias_dist, pb);
-    probe_query(pr, pb, ny, 0, q);
+    double q[3];
+    if (allow_mlp && pr->mlp) {
+        o_mlp_forward(pr->mlp, pr->mlp_prec, pr->mlp_lo, pr->mlp_hi, y, ny, q);
+        for (int a = 0; a < 3; ++a) q[a] = fmax(q[a], 0.0);
+    } else {
+        double pb[3];
+        o_view_bias(y, x, pr->bias_dist, pb);
+        probe_query(pr, pb, ny, 0, q);
+    }
     for (int a = 0; a < 3; ++a) L[a] += alb[a] * q[a];
+}
+
+static void radiance_toward(const o_scene *sc, const o_probes *pr, uint32_t prim, const double *y,
+                            const double *ny, const double *x, double *L)
+{
+    radiance_toward_ex(sc, pr, prim, y, ny, x, 1, L);
 }
 
 /* ---------------------------------------------------------------------------
@@ -1001,7 +1075,7 @@ void o_mlp_batch(const o_scene *sc, const o_probes *pr, int32_t W, int32_t H, co
         if (closest_hit(sc, o, w, O_INF, &h)) {
             double z[3];
             for (int a = 0; a < 3; ++a) z[a] = o[a] + h.t * w[a];
-            radiance_toward(sc, pr, h.prim, z, h.n, y, L);
+            radiance_toward_ex(sc, pr, h.prim, z, h.n, y, 0, L);
         } else {
             for (int a = 0; a < 3; ++a) L[a] = sc->sky[a];
         }

@@ -49,7 +49,9 @@ class OProbes(C.Structure):
     _fields_ = [("dims", C.c_int32 * 3), ("irr_res", C.c_int32), ("dep_res", C.c_int32),
                 ("lo", C.c_double * 3), ("spacing", C.c_double * 3), ("bias_dist", C.c_double),
                 ("var_floor", C.c_double), ("d_max", C.c_double),
-                ("irr", C.c_void_p), ("dep", C.c_void_p)]
+                ("irr", C.c_void_p), ("dep", C.c_void_p), ("mlp", C.c_void_p),
+                ("mlp_prec", C.c_int32), ("mlp_pad", C.c_int32),
+                ("mlp_lo", C.c_double * 3), ("mlp_hi", C.c_double * 3)]
 
 
 class OParams(C.Structure):
@@ -145,8 +147,19 @@ def _camera(cam) -> OCamera:
     return c
 
 
+class MlpTarget:
+    """A learned cache used as the target: flat FP64 parameters, precision
+    ('f64' or 'bf16') and the position normalisation box."""
+
+    def __init__(self, params, lo, hi, prec="bf16"):
+        self.params = _f64(params)
+        self.lo, self.hi = [float(v) for v in np.asarray(lo, np.float32)], \
+            [float(v) for v in np.asarray(hi, np.float32)]
+        self.prec = 1 if prec == "bf16" else 0
+
+
 class _Probes:
-    def __init__(self, grid, irr, dep):
+    def __init__(self, grid, irr, dep, mlp: "MlpTarget" = None):
         self.irr = _f64(np.asarray(irr)[..., :3])
         self.dep = _f64(np.asarray(dep)[..., :2])
         p = OProbes()
@@ -159,6 +172,11 @@ class _Probes:
         p.d_max = float(np.float32(grid.d_max))
         p.irr = self.irr.ctypes.data
         p.dep = self.dep.ctypes.data
+        self.mlp = mlp
+        if mlp is not None:
+            p.mlp = mlp.params.ctypes.data
+            p.mlp_prec = mlp.prec
+            p.mlp_lo[:], p.mlp_hi[:] = mlp.lo, mlp.hi
         self.p = p
 
     @property
@@ -288,8 +306,8 @@ def fill_probes(scene, grid, upd, seed, irr=None, dep=None):
 
 
 def resample_initial(scene, W, H, gb, grid, irr, dep, params, seed, frame, pixels=None,
-                     res=None, resid=None):
-    s, pr, pp = _scene(scene), _Probes(grid, irr, dep), _params(params)
+                     res=None, resid=None, mlp=None):
+    s, pr, pp = _scene(scene), _Probes(grid, irr, dep, mlp), _params(params)
     gb = _f64(gb)
     res = np.zeros((W * H, R_N)) if res is None else res
     resid = np.zeros((W * H, 3)) if resid is None else resid
@@ -340,8 +358,8 @@ def resample_spatial(scene, W, H, gb, res_in, params, spass, seed, frame, pixels
     return out
 
 
-def shade(scene, W, H, gb, grid, irr, dep, res, resid, params, pixels=None, out=None):
-    s, pr, pp = _scene(scene), _Probes(grid, irr, dep), _params(params)
+def shade(scene, W, H, gb, grid, irr, dep, res, resid, params, pixels=None, out=None, mlp=None):
+    s, pr, pp = _scene(scene), _Probes(grid, irr, dep, mlp), _params(params)
     gb, res, resid = _f64(gb), _f64(res), _f64(resid)
     out = np.zeros((W * H, 3)) if out is None else out
     arr, n, px = _pix(pixels)
@@ -357,16 +375,16 @@ class Sequence:
     """Runs the method frame after frame on full images, keeping the history
     (last spatial output) and the previous G-buffer/camera."""
 
-    def __init__(self, scene, grid, irr, dep, params, seed):
+    def __init__(self, scene, grid, irr, dep, params, seed, mlp=None):
         self.scene, self.grid, self.irr, self.dep = scene, grid, irr, dep
-        self.params, self.seed = params, seed
+        self.params, self.seed, self.mlp = params, seed, mlp
         self.hist = self.gb_prev = self.cam_prev = None
 
     def frame(self, cam, frame):
         W, H, pr = cam.width, cam.height, self.params
         gb = gbuffer(self.scene, cam)
         res, resid = resample_initial(self.scene, W, H, gb, self.grid, self.irr, self.dep, pr,
-                                      self.seed, frame)
+                                      self.seed, frame, mlp=self.mlp)
         stages = {"gbuffer": gb, "initial": res, "resid": resid}
         if pr.temporal and self.hist is not None:
             res = resample_temporal(self.scene, W, H, gb, self.gb_prev, self.cam_prev, res,
@@ -375,7 +393,7 @@ class Sequence:
         for sp in range(pr.n_spatial):
             res = resample_spatial(self.scene, W, H, gb, res, pr, sp, self.seed, frame)
             stages[f"spatial{sp}"] = res
-        img = shade(self.scene, W, H, gb, self.grid, self.irr, self.dep, res, resid, pr)
+        img = shade(self.scene, W, H, gb, self.grid, self.irr, self.dep, res, resid, pr, mlp=self.mlp)
         stages["image"] = img
         self.hist, self.gb_prev, self.cam_prev = res, gb, cam
         return img, stages
@@ -417,3 +435,17 @@ def mlp_batch(scene, W, H, gb, res, grid, irr, dep, B, seed, frame):
     L.o_mlp_batch(s.ref, pr.ref, W, H, _ptr(gb), _ptr(res), int(B), int(seed), int(frame) & 0xFFFFFFFF,
                   _ptr(pos), _ptr(nrm), _ptr(tgt), _ptr(valid))
     return pos, nrm, tgt, valid.astype(bool)
+
+
+def mlp_forward(params, prec, lo, hi, pos, nrm) -> np.ndarray:
+    """The C oracle's MLP forward (prec 'f64' or 'bf16') for n points."""
+    p = _f64(params)
+    pos, nrm = _f64(pos).reshape(-1, 3), _f64(nrm).reshape(-1, 3)
+    lo_, hi_ = _f64(np.asarray(lo, np.float32)), _f64(np.asarray(hi, np.float32))
+    out = np.zeros((len(pos), 3))
+    L = lib()
+    L.o_mlp_forward.argtypes = [_P, C.c_int, _P, _P, _P, _P, _P]
+    for i in range(len(pos)):
+        L.o_mlp_forward(_ptr(p), 1 if prec == "bf16" else 0, _ptr(lo_), _ptr(hi_), _ptr(pos[i]),
+                        _ptr(nrm[i]), out[i].ctypes.data_as(C.c_void_p))
+    return out

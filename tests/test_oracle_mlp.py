@@ -242,3 +242,48 @@ def test_batch_labels_closed_form():
     # inputs are the reservoirs' surface samples, on the walls
     on_wall = np.min(np.minimum(pos[valid], 8.0 - pos[valid]), axis=1)
     assert np.all(on_wall < 1e-6)
+
+
+def test_c_forward_matches_numpy_oracle():
+    """The C oracle's MLP (used as the resampling target) == the numpy oracle."""
+    params = M.init_params(11)
+    rng = np.random.default_rng(12)
+    pos = rng.uniform(0, 8, (30, 3))
+    nrm = rng.normal(size=(30, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    lo, hi = np.zeros(3, np.float32), np.full(3, 8.0, np.float32)
+    X = M.encode(pos, nrm, lo, hi)
+    for prec in ("f64", "bf16"):
+        ref, _ = M.forward(params, X, prec=prec)
+        got = o.mlp_forward(params, prec, lo, hi, pos, nrm)
+        assert np.allclose(got, ref, rtol=1e-12, atol=1e-12), prec
+
+
+def test_constant_mlp_target_equals_constant_probes():
+    """A network with zero weights outputs its last bias c everywhere; as a
+    target it must give the same reservoirs and image as probes whose
+    irradiance texels all hold c (the probe query's normalised blend of a
+    constant is that constant)."""
+    cfg = sg.CONFIGS["tiny"]
+    sc = sg.make_scene(cfg)
+    W, H = 32, 24
+    cam = sg.make_camera(cfg, 0, W, H)
+    grid = sg.make_probe_grid(cfg)
+    c = np.array([0.3, 0.55, 0.8], np.float32).astype(np.float64)   # exact in the FP32 texels
+    params = np.zeros(M.N_PARAMS)
+    params[-3:] = c
+    lo, hi = sc.bounds()
+    mlp = o.MlpTarget(params, lo, hi, prec="f64")
+    irr, dep = sg.empty_probe_textures(grid)
+    irr[..., :3] = c.astype(np.float32)
+    dep[..., 0], dep[..., 1] = 1.0, 1.0
+    gb = o.gbuffer(sc, cam)
+    pr = sg.Params(M=8)
+    r_mlp, d_mlp = o.resample_initial(sc, W, H, gb, grid, irr * 0, dep, pr, 3, 0, mlp=mlp)
+    r_prb, d_prb = o.resample_initial(sc, W, H, gb, grid, irr, dep, pr, 3, 0)
+    assert np.allclose(r_mlp, r_prb, rtol=1e-9, atol=1e-12)
+    assert np.allclose(d_mlp, d_prb, rtol=1e-9, atol=1e-12)
+    i_mlp = o.shade(sc, W, H, gb, grid, irr * 0, dep, r_mlp, d_mlp, pr, mlp=mlp)
+    i_prb = o.shade(sc, W, H, gb, grid, irr, dep, r_prb, d_prb, pr)
+    assert np.allclose(i_mlp, i_prb, rtol=1e-9, atol=1e-12)
+    assert np.abs(i_mlp).max() > 0.1
