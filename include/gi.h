@@ -234,6 +234,149 @@ gi_status gi_shade(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes 
                    const gi_reservoirs *res, const float *resid, const gi_params *params,
                    float *out_rgba, void *stream);
 
+/* ==========================================================================
+ * Learned radiance cache (the paper treats the irradiance cache as
+ * interchangeable: Sec. 2 and Sec. 5 name neural radiance caching as an
+ * alternative).  A small MLP C(y, n) ~ E(y, n)/pi replaces the probe query in
+ * the target; the probe query stays the fallback.
+ *
+ * Network: inputs y normalised to [0,1]^3 by [pos_lo, pos_hi] and the raw
+ * normal n; each of the 6 values v is encoded as [v, sin(2^j pi v),
+ * cos(2^j pi v), j = 0..5] (feature 13*i + e, 78 in all); layers 78 -> 64 ->
+ * 64 -> 64 -> 64 -> 3, ReLU on the hidden layers, linear output (used as
+ * max(0, C)).  Parameters (FP32 master copy, GI_MLP_N_PARAMS floats): W1
+ * (64x78 row-major, out x in), b1, W2 (64x64), b2, W3, b3, W4, b4, W5 (3x64),
+ * b5.
+ *
+ * Precision: BF16 inference rounds every GEMM operand (encoded input,
+ * weights, hidden activations) to BF16, nearest even, and accumulates in
+ * FP32 (biases FP32).  FP8 inference stores operands as OCP E4M3FN values
+ * x/s, with s = amax|W_l|/448 per weight matrix and s = (activation scale of
+ * layer l) per layer input, saturating at +-448; products accumulate in FP32
+ * and are scaled back by s_w*s_a.  Training is BF16 (gradients that enter a
+ * product are rounded to BF16 too) with FP32 master weights and Adam moments.
+ * ========================================================================== */
+#define GI_MLP_N_PARAMS 17731u
+#define GI_MLP_WEIGHT_BYTES 38912u   /* 38 MFMA fragments x 64 lanes x 16 B */
+#define GI_MLP_MAX_BATCH (1u << 20)  /* largest training batch per call */
+
+typedef enum gi_mlp_precision { GI_MLP_BF16 = 0, GI_MLP_FP8 = 1 } gi_mlp_precision;
+
+/* When the resampling entry points use the cache. */
+typedef enum gi_mlp_mode {
+    GI_MLP_AUTO = 0,     /* when state[GI_MLP_STATE_USABLE] != 0 (decided on the device) */
+    GI_MLP_ALWAYS = 1,   /* always the cache */
+    GI_MLP_NEVER = 2     /* always the probe query */
+} gi_mlp_mode;
+
+/* Words of gi_mlp.state (uint32; FP32 values stored as their bits). */
+#define GI_MLP_STATE_USABLE 0     /* 1 when AUTO mode uses the cache */
+#define GI_MLP_STATE_STEPS 1      /* Adam steps taken */
+#define GI_MLP_STATE_NONFINITE 2  /* non-finite outputs in the last training batch */
+#define GI_MLP_STATE_EMA_ERR 3    /* EMA of the relative error vs the probe query (float) */
+#define GI_MLP_STATE_LOSS 4       /* loss of the last training batch (float) */
+#define GI_MLP_STATE_VALID 5      /* valid samples in the last training batch */
+#define GI_MLP_STATE_BATCH_ERR 6  /* relative error of the last batch (float) */
+#define GI_MLP_STATE_WORDS 16
+
+typedef struct gi_mlp {
+    float *params;        /* GI_MLP_N_PARAMS FP32 master parameters */
+    float *adam_m;        /* GI_MLP_N_PARAMS Adam first moments (zero at start) */
+    float *adam_v;        /* GI_MLP_N_PARAMS Adam second moments (zero at start) */
+    void *weights;        /* GI_MLP_WEIGHT_BYTES inference operands, written by gi_mlp_prepare */
+    float *scales;        /* 16 floats: [0..4] FP8 weight scales (gi_mlp_prepare), [5..9] FP8
+                             activation scales of the layer inputs (gi_mlp_grad or the caller) */
+    uint32_t *state;      /* GI_MLP_STATE_WORDS words, zero at start */
+    float pos_lo[3];      /* position normalisation box */
+    float pos_hi[3];
+    uint32_t precision;   /* gi_mlp_precision of inference */
+    uint32_t mode;        /* gi_mlp_mode */
+    uint32_t warmup_steps;/* AUTO: Adam steps before the cache may be used */
+    float max_rel_err;    /* AUTO: largest EMA relative error vs the probe query, > 0 */
+} gi_mlp;
+
+/* Initialise the master parameters: He-uniform weights, W[o][i] = (2u - 1)
+ * sqrt(6 / fan_in) with u from counter (parameter index, 0, 12, 0) (first
+ * word), zero biases; Adam moments and state are zeroed, then
+ * gi_mlp_prepare runs. */
+gi_status gi_mlp_init(const gi_mlp *mlp, uint64_t seed, void *stream);
+
+/* Convert the master parameters into the inference operands (BF16 or FP8
+ * MFMA fragments per `precision`; FP8 also writes the weight scales).  Must
+ * run after any change of params or precision, before inference. */
+gi_status gi_mlp_prepare(const gi_mlp *mlp, void *stream);
+
+/* Cache output C(y, n) for n points: pos4, nrm4 are float4 planes (xyz used),
+ * out4 receives (C_r, C_g, C_b, 0).  Runs whatever the mode (the state is
+ * not consulted). */
+gi_status gi_mlp_infer(const gi_mlp *mlp, uint32_t n, const float *pos4, const float *nrm4, float *out4,
+                       void *stream);
+
+/* Training samples drawn from the resampler's own reservoirs.  Sample j
+ * (counter (j, frame, 10, 0)) takes pixel p = floor(u0 W H) and the surface
+ * sample (y, n_y) of res at p; its label is the radiance arriving along a
+ * cosine-distributed direction (u1, u2) about n_y, L_e(z) + rho_z Q(z_b, n_z)
+ * at the hit z with z_b biased toward y (a one-bounce gather past the probes,
+ * Sec. 3.2), or the sky.  Outputs (float4 planes of n): pos4 (y, 0), nrm4
+ * (n_y, 0), target4 (label, valid 1/0), qprobe4 (Q(y_b, n_y) with y_b biased
+ * toward the pixel's x: the probe value the cache replaces, 0).  A sample
+ * whose pixel holds no surface sample is invalid (all zero). */
+gi_status gi_mlp_make_batch(const gi_scene *scene, const gi_gbuffer *gb, const gi_reservoirs *res,
+                            const gi_probes *probes, uint32_t n, uint64_t seed, uint32_t frame,
+                            float *pos4, float *nrm4, float *target4, float *qprobe4, void *stream);
+
+/* Device workspace bytes gi_mlp_grad / gi_mlp_train_step need for n samples. */
+uint64_t gi_mlp_train_workspace_bytes(uint32_t n);
+
+/* Gradient of the relative-L2 loss, mean over valid samples and channels of
+ * (C - t)^2 / (sg(C)^2 + 0.01), with BF16 operands as above; writes grad
+ * (GI_MLP_N_PARAMS floats, caller-owned) and, into state, LOSS, VALID,
+ * NONFINITE and BATCH_ERR = sum |max(0,C) - q| / sum (q + 0.01) over valid
+ * samples and channels (q from qprobe4, which may be NULL: error 0); writes
+ * the activation amax/448 of every layer input into scales[5..9].  The sums
+ * are reduced in a fixed order (deterministic). */
+gi_status gi_mlp_grad(const gi_mlp *mlp, uint32_t n, const float *pos4, const float *nrm4,
+                      const float *target4, const float *qprobe4, float *grad, void *workspace,
+                      uint64_t workspace_bytes, void *stream);
+
+/* One Adam step (beta 0.9, 0.99, eps 1e-8, bias-corrected with step t >= 1)
+ * on the master parameters with gradient grad, then gi_mlp_prepare.  Updates
+ * state: STEPS = t, EMA_ERR (0.9 old + 0.1 BATCH_ERR, or BATCH_ERR at t = 1)
+ * and USABLE = (t >= warmup_steps && NONFINITE == 0 && EMA_ERR <=
+ * max_rel_err && every parameter finite). */
+gi_status gi_mlp_adam(const gi_mlp *mlp, const float *grad, uint32_t t, float lr, void *stream);
+
+/* gi_mlp_grad followed by gi_mlp_adam, the gradient kept in the workspace. */
+gi_status gi_mlp_train_step(const gi_mlp *mlp, uint32_t n, const float *pos4, const float *nrm4,
+                            const float *target4, const float *qprobe4, uint32_t t, float lr,
+                            void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Device workspace bytes of gi_resample_initial_mlp: 48 bytes per candidate. */
+uint64_t gi_initial_mlp_workspace_bytes(uint32_t width, uint32_t height, uint32_t M);
+
+/* gi_resample_initial with the learned cache as the target: the candidates
+ * are traced (counter (pixel, frame, 0, i), as in gi_resample_initial), the
+ * cache is evaluated for all of them, and the resampling uses
+ * L(y) = L_e(y) + rho_y max(0, C(y, n_y)).  When the mode or the device state
+ * rules the cache out, the same candidates take the probe query and the
+ * result is bit-identical to gi_resample_initial. */
+gi_status gi_resample_initial_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes,
+                                  const gi_mlp *mlp, const gi_params *params, gi_reservoirs *out,
+                                  float *resid, void *workspace, uint64_t workspace_bytes, uint64_t seed,
+                                  uint32_t frame, void *stream);
+
+/* Device workspace bytes of gi_shade_mlp: 16 bytes per pixel. */
+uint64_t gi_shade_mlp_workspace_bytes(uint32_t width, uint32_t height);
+
+/* gi_shade with the learned cache for the fresh radiance query at each
+ * reservoir's sample (the cache needs no view-path bias); probe query when
+ * the mode or the device state rules the cache out (then bit-identical to
+ * gi_shade). */
+gi_status gi_shade_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes,
+                       const gi_mlp *mlp, const gi_reservoirs *res, const float *resid,
+                       const gi_params *params, float *out_rgba, void *workspace, uint64_t workspace_bytes,
+                       void *stream);
+
 /* Host-side builder of the optional uniform-grid accelerator.  prims: HOST
  * array of n records.  Cells cover [lo, hi] with res cells per axis; a
  * primitive is listed in every cell its bounding box (padded by 1e-3 cell)

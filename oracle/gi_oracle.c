@@ -1051,12 +1051,13 @@ void o_brute_force(const o_scene *sc, const o_probes *pr, const double *gb, int3
  * surface sample y, n_y of that pixel's initial reservoir; its label is a
  * one-sample estimate of E(y, n_y)/pi: the radiance arriving along a
  * cosine-distributed direction (u1, u2) about n_y, L_e(z) + rho_z Q(z_b, n_z)
- * from the hit z (z_b biased toward y), or the sky.  Samples whose pixel has
- * no surface sample get valid = 0.
+ * from the hit z (z_b biased toward y), or the sky.  qprobe receives
+ * Q(y_b, n_y) with y_b biased toward the pixel's x, the probe value the cache
+ * stands in for.  Samples whose pixel has no surface sample get valid = 0.
  * ------------------------------------------------------------------------- */
 void o_mlp_batch(const o_scene *sc, const o_probes *pr, int32_t W, int32_t H, const double *gb,
                  const double *res, int64_t B, uint64_t seed, uint32_t frame, double *pos, double *nrm,
-                 double *target, int32_t *valid)
+                 double *target, int32_t *valid, double *qprobe)
 {
     for (int64_t j = 0; j < B; ++j) {
         double u[4];
@@ -1065,7 +1066,9 @@ void o_mlp_batch(const o_scene *sc, const o_probes *pr, int32_t W, int32_t H, co
         const double *g = gb + GB_N * p;
         const double *r = res + R_N * p;
         valid[j] = 0;
-        for (int a = 0; a < 3; ++a) { pos[3 * j + a] = 0.0; nrm[3 * j + a] = 0.0; target[3 * j + a] = 0.0; }
+        for (int a = 0; a < 3; ++a) {
+            pos[3 * j + a] = 0.0; nrm[3 * j + a] = 0.0; target[3 * j + a] = 0.0; qprobe[3 * j + a] = 0.0;
+        }
         if (!pixel_active(g) || !(r[R_W] > 0.0) || res_is_sky(r)) continue;
         const double *y = r + R_Y, *ny = r + R_NY;
         double w[3], o[3], L[3];
@@ -1079,7 +1082,13 @@ void o_mlp_batch(const o_scene *sc, const o_probes *pr, int32_t W, int32_t H, co
         } else {
             for (int a = 0; a < 3; ++a) L[a] = sc->sky[a];
         }
+        /* the probe value the cache replaces at y, biased toward the pixel's x */
+        double yb[3], q[3];
+        o_view_bias(y, g + GB_POS, pr->bias_dist, yb);
+        probe_query(pr, yb, ny, 0, q);
         valid[j] = 1;
-        for (int a = 0; a < 3; ++a) { pos[3 * j + a] = y[a]; nrm[3 * j + a] = ny[a]; target[3 * j + a] = L[a]; }
+        for (int a = 0; a < 3; ++a) {
+            pos[3 * j + a] = y[a]; nrm[3 * j + a] = ny[a]; target[3 * j + a] = L[a]; qprobe[3 * j + a] = q[a];
+        }
     }
 }

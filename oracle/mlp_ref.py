@@ -101,6 +101,23 @@ def init_params(seed) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32).astype(np.float64)
 
 
+def init_params_philox(seed) -> np.ndarray:
+    """Initial parameters drawn from Philox: weight p of a layer with fan-in
+    F is (2u - 1) * sqrt(6/F) in FP32 arithmetic (each step rounded to FP32),
+    u = (x >> 8) 2^-24 from the first word of counter (p, 0, 12, 0); biases
+    zero."""
+    from . import ref
+    out = np.zeros(N_PARAMS, np.float32)
+    o = 0
+    for i, n in LAYERS:
+        bound = np.sqrt(np.float32(6.0) / np.float32(i), dtype=np.float32)
+        for q in range(o, o + i * n):
+            u = np.float32((int(ref.philox(seed, [q, 0, 12, 0])[0]) >> 8) * 2.0 ** -24)
+            out[q] = (np.float32(2.0) * u - np.float32(1.0)) * bound
+        o += i * n + n
+    return out.astype(np.float64)
+
+
 # --------------------------------------------------------------------------
 # encoding and network
 # --------------------------------------------------------------------------
@@ -119,7 +136,8 @@ def encode(pos, nrm, lo, hi) -> np.ndarray:
 
 
 def fp8_weight_scales(params):
-    return [float(np.max(np.abs(W))) / 448.0 for W, _ in split(params)]
+    """amax|W| / 448 per layer (1 for an all-zero matrix, which has no range)."""
+    return [float(np.max(np.abs(W))) / 448.0 or 1.0 for W, _ in split(params)]
 
 
 def forward(params, X, prec="f64", act_scales=None):

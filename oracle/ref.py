@@ -424,17 +424,17 @@ def brute_force(scene, W, H, gb, grid, irr, dep, pixels, nsamples, seed=12345) -
 
 def mlp_batch(scene, W, H, gb, res, grid, irr, dep, B, seed, frame):
     """Training samples of the learned cache (see o_mlp_batch): returns
-    (pos (B,3), nrm (B,3), target (B,3), valid (B,))."""
+    (pos (B,3), nrm (B,3), target (B,3), valid (B,), qprobe (B,3))."""
     s, pr = _scene(scene), _Probes(grid, irr, dep)
     gb, res = _f64(gb), _f64(res)
-    pos, nrm, tgt = np.zeros((B, 3)), np.zeros((B, 3)), np.zeros((B, 3))
+    pos, nrm, tgt, qp = np.zeros((B, 3)), np.zeros((B, 3)), np.zeros((B, 3)), np.zeros((B, 3))
     valid = np.zeros(B, np.int32)
     L = lib()
     L.o_mlp_batch.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P, C.c_int64, C.c_uint64, C.c_uint32,
-                              _P, _P, _P, _P]
+                              _P, _P, _P, _P, _P]
     L.o_mlp_batch(s.ref, pr.ref, W, H, _ptr(gb), _ptr(res), int(B), int(seed), int(frame) & 0xFFFFFFFF,
-                  _ptr(pos), _ptr(nrm), _ptr(tgt), _ptr(valid))
-    return pos, nrm, tgt, valid.astype(bool)
+                  _ptr(pos), _ptr(nrm), _ptr(tgt), _ptr(valid), _ptr(qp))
+    return pos, nrm, tgt, valid.astype(bool), qp
 
 
 def mlp_forward(params, prec, lo, hi, pos, nrm) -> np.ndarray:

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgi.so")
-SOURCES = [os.path.join(CSRC, "gi_kernels.hip"), os.path.join(CSRC, "gi_accel.cpp")]
+SOURCES = [os.path.join(CSRC, "gi_kernels.hip"), os.path.join(CSRC, "gi_mlp.hip"), os.path.join(CSRC, "gi_accel.cpp")]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))] + \
     [os.path.join(INCLUDE, "gi.h")]
 

@@ -71,7 +71,7 @@ __device__ __forceinline__ uint4 philox(uint64_t seed, uint32_t c0, uint32_t c1,
 // 24-bit uniform in [0, 1): exact in FP32
 __device__ __forceinline__ float u01(uint32_t v) { return (float)(v >> 8) * 5.9604644775390625e-08f; }
 
-enum : uint32_t { kPassInitial = 0, kPassTemporal = 1, kPassSpatial0 = 2, kPassProbe = 9 };
+enum : uint32_t { kPassInitial = 0, kPassTemporal = 1, kPassSpatial0 = 2, kPassProbe = 9, kPassTrainBatch = 10 };
 
 // --------------------------------------------------------------------------
 // samplers
@@ -566,6 +566,17 @@ __device__ __forceinline__ V3 radiance_toward(const gi_scene &sc, const gi_probe
     if (is_zero(alb)) return emit;
     V3 q = probe_query(pr, view_bias(y, x, pr.bias_dist), ny);
     return v3(fmaf(alb.x, q.x, emit.x), fmaf(alb.y, q.y, emit.y), fmaf(alb.z, q.z, emit.z));
+}
+
+// L_e(y) + rho_y max(0, C) with a cache value C already evaluated at y (the
+// learned cache needs no view-path bias); a non-finite C counts as 0
+__device__ __forceinline__ V3 radiance_cached(const gi_scene &sc, uint32_t prim, float4 c)
+{
+    V3 alb, emit;
+    material(sc, prim, alb, emit);
+    if (is_zero(alb)) return emit;
+    return v3(fmaf(alb.x, fmaxf(c.x, 0.0f), emit.x), fmaf(alb.y, fmaxf(c.y, 0.0f), emit.y),
+              fmaf(alb.z, fmaxf(c.z, 0.0f), emit.z));
 }
 
 // --------------------------------------------------------------------------

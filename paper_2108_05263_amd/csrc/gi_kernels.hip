@@ -13,6 +13,7 @@
 
 #include "gi.h"
 #include "gi_device.hpp"
+#include "gi_mlp.hpp"
 
 using namespace gi;
 
@@ -274,10 +275,64 @@ __global__ void k_probe_query(gi_probes pr, uint32_t n, const float *p, const fl
 // --------------------------------------------------------------------------
 // initial resampling
 // --------------------------------------------------------------------------
+// Candidate planes of the learned-cache form of the initial pass: candidate
+// i of pixel p at i*W*H + p; pos = (y or the miss direction, prim bits),
+// nrm = (n_y, 0), q = cache value at (y, n_y).
+struct CandWs {
+    float4 *pos;
+    float4 *nrm;
+    float4 *q;
+};
+
+// Traces the M candidates of every pixel into the candidate planes (the
+// directions and hits k_initial computes itself in the probe form).
 template <bool LDS>
 __global__ void __launch_bounds__(kBlock)
+    k_cand(gi_scene sc, gi_gbuffer gb, gi_params pp, CandWs ws, uint64_t seed, uint32_t frame)
+{
+    using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
+    uint32_t px, py;
+    const bool inside = tile_pixel(gb.width, gb.height, px, py);
+    if (LDS) stage_scene(sc);
+    if (!inside) return;
+    const Acc acc(sc);
+    const uint32_t p = py * gb.width + px;
+    const size_t npx = (size_t)gb.width * gb.height;
+    const GB g = load_gb(gb, p);
+    const float miss = __uint_as_float(GI_MISS);
+    if (!active(g)) {
+        for (uint32_t i = 0; i < pp.M; ++i) {
+            ws.pos[i * npx + p] = make_float4(0.0f, 0.0f, 0.0f, miss);
+            ws.nrm[i * npx + p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        return;
+    }
+    const V3 o = madd(g.pos, sc.eps, g.n);
+    for (uint32_t i = 0; i < pp.M; ++i) {
+        uint4 rn = philox(seed, p, frame, kPassInitial, i);
+        V3 w = cosine_dir(g.n, u01(rn.x), u01(rn.y));
+        Hit h;
+        float4 a, b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (cast<false>(sc, acc, o, w, kInf, h)) {
+            V3 y = madd(o, h.t, w), ny = hit_normal(sc, acc, o, w, h);
+            a = make_float4(y.x, y.y, y.z, __uint_as_float(h.prim));
+            b = make_float4(ny.x, ny.y, ny.z, 0.0f);
+        } else {
+            a = make_float4(w.x, w.y, w.z, miss);
+        }
+        ws.pos[i * npx + p] = a;
+        ws.nrm[i * npx + p] = b;
+    }
+}
+
+// Initial resampling.  WS = false: traces its candidates and queries the
+// probes.  WS = true: takes the candidates from the planes k_cand wrote and,
+// when the cache is selected, their cache values; otherwise the probe query
+// of the same candidates, through the same arithmetic as WS = false.
+template <bool LDS, bool WS>
+__global__ void __launch_bounds__(kBlock)
     k_initial(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_params pp, gi_reservoirs out, float4 *resid,
-              uint64_t seed, uint32_t frame)
+              uint64_t seed, uint32_t frame, CandWs ws, gi_mlp mlp)
 {
     using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
     uint32_t px, py;
@@ -295,27 +350,45 @@ __global__ void __launch_bounds__(kBlock)
     }
     const V3 o = madd(g.pos, sc.eps, g.n);
     const V3 rho_pi = kInvPi * g.alb;
+    const bool use_cache = WS && mlp_selected(mlp);
+    const size_t npx = (size_t)gb.width * gb.height;
     Res r = empty_res(pp.M);
     float wsum = 0.0f, p_sel = 0.0f;
     bool have = false;
     for (uint32_t i = 0; i < pp.M; ++i) {
         uint4 rn = philox(seed, p, frame, kPassInitial, i);
-        V3 w = cosine_dir(g.n, u01(rn.x), u01(rn.y));
         float u2 = u01(rn.z);
-        Hit h;
-        V3 y, ny = v3(0.0f, 0.0f, 0.0f), L = v3(0.0f, 0.0f, 0.0f);
+        V3 w, y, ny = v3(0.0f, 0.0f, 0.0f), L = v3(0.0f, 0.0f, 0.0f);
         float phat = 0.0f, wi = 0.0f;
         uint32_t prim = GI_MISS;
-        if (cast<false>(sc, acc, o, w, kInf, h)) {
-            y = madd(o, h.t, w);
-            ny = hit_normal(sc, acc, o, w, h);
-            prim = h.prim;
+        bool hit;
+        if constexpr (WS) {
+            const float4 a = ws.pos[i * npx + p];
+            w = xyz(a);
+            hit = __float_as_uint(a.w) != GI_MISS;
+            if (hit) {
+                y = w;
+                ny = xyz(ws.nrm[i * npx + p]);
+                prim = __float_as_uint(a.w);
+            }
+        } else {
+            w = cosine_dir(g.n, u01(rn.x), u01(rn.y));
+            Hit h;
+            hit = cast<false>(sc, acc, o, w, kInf, h);
+            if (hit) {
+                y = madd(o, h.t, w);
+                ny = hit_normal(sc, acc, o, w, h);
+                prim = h.prim;
+            }
+        }
+        if (hit) {
             V3 v = y - g.pos;
             float d2 = dot(v, v);
             V3 wv = frsq(d2) * v;
             float cx = dot(g.n, wv), cy = -dot(ny, wv);
             if (cx > 0.0f && cy > 0.0f) {
-                L = radiance_toward(sc, pr, prim, y, ny, g.pos);
+                L = use_cache ? radiance_cached(sc, prim, ws.q[i * npx + p])
+                              : radiance_toward(sc, pr, prim, y, ny, g.pos);
                 float G = cx * cy * rcp(d2);
                 float fl = lum(rho_pi * L);
                 float iG = rcp(G);
@@ -514,10 +587,12 @@ __global__ void __launch_bounds__(kBlock)
 // --------------------------------------------------------------------------
 // shading
 // --------------------------------------------------------------------------
-template <bool LDS>
+// WS = true: the fresh query is the cache value q[p] evaluated at the
+// reservoir's sample when the cache is selected (probe query otherwise).
+template <bool LDS, bool WS>
 __global__ void __launch_bounds__(kBlock)
     k_shade(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_reservoirs res, const float4 *resid, gi_params pp,
-            float4 *img)
+            float4 *img, const float4 *q, gi_mlp mlp)
 {
     using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
     uint32_t px, py;
@@ -550,7 +625,8 @@ __global__ void __launch_bounds__(kBlock)
                 if (cx > 0.0f && cy > 0.0f) {
                     geo = fminf(cx * cy * rcp(d2), pp.g_max);
                     if (visible(sc, acc, g.pos, g.n, r.y, r.n, false)) {
-                        L = radiance_toward(sc, pr, r.prim, r.y, r.n, g.pos);
+                        L = (WS && mlp_selected(mlp)) ? radiance_cached(sc, r.prim, q[p])
+                                                       : radiance_toward(sc, pr, r.prim, r.y, r.n, g.pos);
                         ok = true;
                     }
                 }
@@ -559,6 +635,50 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
     img[p] = make_float4(o.x, o.y, o.z, 1.0f);
+}
+
+// --------------------------------------------------------------------------
+// training samples of the learned cache
+// --------------------------------------------------------------------------
+template <bool LDS>
+__global__ void __launch_bounds__(kBlock)
+    k_mlp_batch(gi_scene sc, gi_gbuffer gb, gi_reservoirs res, gi_probes pr, uint32_t n, uint64_t seed,
+                uint32_t frame, float4 *pos, float4 *nrm, float4 *tgt, float4 *qp)
+{
+    using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
+    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (LDS) stage_scene(sc);
+    if (j >= n) return;
+    const Acc acc(sc);
+    const uint4 rn = philox(seed, j, frame, kPassTrainBatch, 0u);
+    // p = floor(u0 W H), exactly: u0 = (x >> 8) 2^-24
+    const uint64_t npx = (uint64_t)gb.width * gb.height;
+    const uint32_t p = (uint32_t)(((uint64_t)(rn.x >> 8) * npx) >> 24);
+    const GB g = load_gb(gb, p);
+    const Res r = load_res(res, p);
+    const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (!active(g) || !(r.W > 0.0f) || is_zero(r.n)) {
+        pos[j] = zero;
+        nrm[j] = zero;
+        tgt[j] = zero;
+        qp[j] = zero;
+        return;
+    }
+    const V3 w = cosine_dir(r.n, u01(rn.y), u01(rn.z));
+    const V3 o = madd(r.y, sc.eps, r.n);
+    Hit h;
+    V3 L;
+    if (cast<false>(sc, acc, o, w, kInf, h)) {
+        const V3 z = madd(o, h.t, w);
+        L = radiance_toward(sc, pr, h.prim, z, hit_normal(sc, acc, o, w, h), r.y);
+    } else {
+        L = ld3(sc.sky);
+    }
+    const V3 q = probe_query(pr, view_bias(r.y, g.pos, pr.bias_dist), r.n);
+    pos[j] = make_float4(r.y.x, r.y.y, r.y.z, 0.0f);
+    nrm[j] = make_float4(r.n.x, r.n.y, r.n.z, 0.0f);
+    tgt[j] = make_float4(L.x, L.y, L.z, 1.0f);
+    qp[j] = make_float4(q.x, q.y, q.z, 0.0f);
 }
 
 // --------------------------------------------------------------------------
@@ -677,6 +797,11 @@ uint32_t scene_lds(const gi_scene *sc, uint32_t static_lds = 0)
         if (lds) kernel<true><<<(grid), (block), (lds), (stream)>>>(__VA_ARGS__);             \
         else kernel<false><<<(grid), (block), 0, (stream)>>>(__VA_ARGS__);                   \
     } while (0)
+#define GI_LAUNCH_LDS2(kernel, T2, grid, block, lds, stream, ...)                             \
+    do {                                                                                      \
+        if (lds) kernel<true, T2><<<(grid), (block), (lds), (stream)>>>(__VA_ARGS__);         \
+        else kernel<false, T2><<<(grid), (block), 0, (stream)>>>(__VA_ARGS__);               \
+    } while (0)
 
 }  // namespace
 
@@ -761,8 +886,9 @@ gi_status gi_resample_initial(const gi_scene *scene, const gi_gbuffer *gb, const
     if ((s = check_res(out, gb->width, gb->height)) != GI_OK) return s;
     if ((uint64_t)gb->width * gb->height > (1u << 23)) return GI_ERR_SHAPE;   // 23-bit tag origin
     if (gb->width == 0 || gb->height == 0) return GI_OK;
-    GI_LAUNCH_LDS(k_initial, tile_grid(gb->width, gb->height), kBlock, scene_lds(scene), S(stream), *scene, *gb,
-                  *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame);
+    GI_LAUNCH_LDS2(k_initial, false, tile_grid(gb->width, gb->height), kBlock, scene_lds(scene), S(stream),
+                   *scene, *gb, *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame, CandWs{},
+                   gi_mlp{});
     return launched();
 }
 
@@ -821,8 +947,92 @@ gi_status gi_shade(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes 
     if ((s = check_params(params)) != GI_OK) return s;
     if ((s = check_res(res, W, H)) != GI_OK) return s;
     if (W == 0 || H == 0) return GI_OK;
-    GI_LAUNCH_LDS(k_shade, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *probes, *res,
-                  reinterpret_cast<const float4 *>(resid), *params, reinterpret_cast<float4 *>(out_rgba));
+    GI_LAUNCH_LDS2(k_shade, false, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *probes,
+                   *res, reinterpret_cast<const float4 *>(resid), *params, reinterpret_cast<float4 *>(out_rgba),
+                   nullptr, gi_mlp{});
+    return launched();
+}
+
+gi_status gi_mlp_make_batch(const gi_scene *scene, const gi_gbuffer *gb, const gi_reservoirs *res,
+                            const gi_probes *probes, uint32_t n, uint64_t seed, uint32_t frame, float *pos4,
+                            float *nrm4, float *target4, float *qprobe4, void *stream)
+{
+    gi_status s;
+    if (!gb || !res) return GI_ERR_NULL;
+    uint32_t W = gb->width, H = gb->height;
+    if ((s = check_scene(scene)) != GI_OK) return s;
+    if ((s = check_gb(gb, W, H)) != GI_OK) return s;
+    if ((s = check_res(res, W, H)) != GI_OK) return s;
+    if ((s = check_probes(probes)) != GI_OK) return s;
+    if (n > GI_MLP_MAX_BATCH) return GI_ERR_SHAPE;
+    if (n == 0) return GI_OK;
+    if (!pos4 || !nrm4 || !target4 || !qprobe4) return GI_ERR_NULL;
+    if (W == 0 || H == 0) return GI_ERR_SHAPE;
+    GI_LAUNCH_LDS(k_mlp_batch, (n + kBlock - 1) / kBlock, kBlock, scene_lds(scene), S(stream), *scene, *gb, *res,
+                  *probes, n, seed, frame, reinterpret_cast<float4 *>(pos4), reinterpret_cast<float4 *>(nrm4),
+                  reinterpret_cast<float4 *>(target4), reinterpret_cast<float4 *>(qprobe4));
+    return launched();
+}
+
+uint64_t gi_initial_mlp_workspace_bytes(uint32_t width, uint32_t height, uint32_t M)
+{
+    return 48ull * width * height * M;
+}
+
+gi_status gi_resample_initial_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes,
+                                  const gi_mlp *mlp, const gi_params *params, gi_reservoirs *out, float *resid,
+                                  void *workspace, uint64_t workspace_bytes, uint64_t seed, uint32_t frame,
+                                  void *stream)
+{
+    gi_status s;
+    if (!gb || !out || !resid || !workspace) return GI_ERR_NULL;
+    uint32_t W = gb->width, H = gb->height;
+    if ((s = check_scene(scene)) != GI_OK) return s;
+    if ((s = check_gb(gb, W, H)) != GI_OK) return s;
+    if ((s = check_probes(probes)) != GI_OK) return s;
+    if ((s = check_mlp(mlp)) != GI_OK) return s;
+    if ((s = check_params(params)) != GI_OK) return s;
+    if ((s = check_res(out, W, H)) != GI_OK) return s;
+    const uint64_t ncand = (uint64_t)W * H * params->M;
+    if (ncand >= (1ull << 31)) return GI_ERR_SHAPE;
+    if (workspace_bytes < gi_initial_mlp_workspace_bytes(W, H, params->M)) return GI_ERR_SHAPE;
+    if (W == 0 || H == 0) return GI_OK;
+    float4 *base = reinterpret_cast<float4 *>(workspace);
+    CandWs ws{base, base + ncand, base + 2 * ncand};
+    GI_LAUNCH_LDS(k_cand, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *params, ws, seed,
+                  frame);
+    if ((s = launched()) != GI_OK) return s;
+    if ((s = mlp_infer_launch(*mlp, (uint32_t)ncand, ws.pos, ws.nrm, ws.q, true, S(stream))) != GI_OK) return s;
+    k_initial<false, true><<<tile_grid(W, H), kBlock, 0, S(stream)>>>(*scene, *gb, *probes, *params, *out,
+                                                                        reinterpret_cast<float4 *>(resid), seed,
+                                                                        frame, ws, *mlp);
+    return launched();
+}
+
+uint64_t gi_shade_mlp_workspace_bytes(uint32_t width, uint32_t height) { return 16ull * width * height; }
+
+gi_status gi_shade_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes, const gi_mlp *mlp,
+                       const gi_reservoirs *res, const float *resid, const gi_params *params, float *out_rgba,
+                       void *workspace, uint64_t workspace_bytes, void *stream)
+{
+    gi_status s;
+    if (!gb || !res || !resid || !out_rgba || !workspace) return GI_ERR_NULL;
+    uint32_t W = gb->width, H = gb->height;
+    if ((s = check_scene(scene)) != GI_OK) return s;
+    if ((s = check_gb(gb, W, H)) != GI_OK) return s;
+    if ((s = check_probes(probes)) != GI_OK) return s;
+    if ((s = check_mlp(mlp)) != GI_OK) return s;
+    if ((s = check_params(params)) != GI_OK) return s;
+    if ((s = check_res(res, W, H)) != GI_OK) return s;
+    if (workspace_bytes < gi_shade_mlp_workspace_bytes(W, H)) return GI_ERR_SHAPE;
+    if (W == 0 || H == 0) return GI_OK;
+    float4 *q = reinterpret_cast<float4 *>(workspace);
+    if ((s = mlp_infer_launch(*mlp, W * H, reinterpret_cast<const float4 *>(res->y_W),
+                              reinterpret_cast<const float4 *>(res->n_wsum), q, true, S(stream))) != GI_OK)
+        return s;
+    GI_LAUNCH_LDS2(k_shade, true, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *probes, *res,
+                   reinterpret_cast<const float4 *>(resid), *params, reinterpret_cast<float4 *>(out_rgba), q,
+                   *mlp);
     return launched();
 }
 

@@ -26,7 +26,18 @@ _lib = None
 # every symbol include/gi.h declares
 EXPORTS = ["gi_status_string", "gi_device", "gi_trace_gbuffer", "gi_probe_update", "gi_probe_query",
            "gi_resample_initial", "gi_resample_temporal", "gi_resample_spatial", "gi_shade",
-           "gi_accel_build_host", "gi_philox", "gi_trace_rays"]
+           "gi_accel_build_host", "gi_philox", "gi_trace_rays",
+           "gi_mlp_init", "gi_mlp_prepare", "gi_mlp_infer", "gi_mlp_make_batch", "gi_mlp_train_workspace_bytes",
+           "gi_mlp_grad", "gi_mlp_adam", "gi_mlp_train_step", "gi_initial_mlp_workspace_bytes",
+           "gi_resample_initial_mlp", "gi_shade_mlp_workspace_bytes", "gi_shade_mlp"]
+
+MLP_N_PARAMS = 17731
+MLP_WEIGHT_BYTES = 38912
+MLP_MAX_BATCH = 1 << 20
+MLP_PRECISION = {"bf16": 0, "fp8": 1}
+MLP_MODE = {"auto": 0, "always": 1, "never": 2}
+# words of the device state (GI_MLP_STATE_*)
+MLP_STATE = {"usable": 0, "steps": 1, "nonfinite": 2, "ema_err": 3, "loss": 4, "valid": 5, "batch_err": 6}
 
 
 class GiError(RuntimeError):
@@ -79,6 +90,13 @@ class GiProbeParams(C.Structure):
     _fields_ = [("rays", C.c_uint32), ("hysteresis", C.c_float), ("sharpness", C.c_float)]
 
 
+class GiMlp(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p),
+                ("weights", C.c_void_p), ("scales", C.c_void_p), ("state", C.c_void_p), ("pos_lo", F3),
+                ("pos_hi", F3), ("precision", C.c_uint32), ("mode", C.c_uint32),
+                ("warmup_steps", C.c_uint32), ("max_rel_err", C.c_float)]
+
+
 _P = C.c_void_p
 
 
@@ -105,10 +123,25 @@ def load():
         "gi_accel_build_host": [_P, C.c_uint32, _P, _P, _P, _P, _P, C.c_uint32, _P],
         "gi_philox": [C.c_uint64, C.c_uint32, _P, _P, _P],
         "gi_trace_rays": [_P, C.c_uint32, _P, _P, _P, _P, _P],
+        "gi_mlp_init": [_P, C.c_uint64, _P],
+        "gi_mlp_prepare": [_P, _P],
+        "gi_mlp_infer": [_P, C.c_uint32, _P, _P, _P, _P],
+        "gi_mlp_make_batch": [_P, _P, _P, _P, C.c_uint32, C.c_uint64, C.c_uint32, _P, _P, _P, _P, _P],
+        "gi_mlp_grad": [_P, C.c_uint32, _P, _P, _P, _P, _P, _P, C.c_uint64, _P],
+        "gi_mlp_adam": [_P, _P, C.c_uint32, C.c_float, _P],
+        "gi_mlp_train_step": [_P, C.c_uint32, _P, _P, _P, _P, C.c_uint32, C.c_float, _P, C.c_uint64, _P],
+        "gi_resample_initial_mlp": [_P, _P, _P, _P, _P, _P, _P, _P, C.c_uint64, C.c_uint64, C.c_uint32, _P],
+        "gi_shade_mlp": [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_uint64, _P],
     }.items():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = C.c_int
+    for name, args in {"gi_mlp_train_workspace_bytes": [C.c_uint32],
+                       "gi_initial_mlp_workspace_bytes": [C.c_uint32, C.c_uint32, C.c_uint32],
+                       "gi_shade_mlp_workspace_bytes": [C.c_uint32, C.c_uint32]}.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_uint64
     _lib = L
     return L
 
@@ -418,6 +451,141 @@ def trace_rays(scene: DeviceScene, org: torch.Tensor, d: torch.Tensor, stream=No
 
 
 # --------------------------------------------------------------------------
+# learned radiance cache
+# --------------------------------------------------------------------------
+class Mlp:
+    """Device state of the learned cache: FP32 master parameters, Adam
+    moments, inference operands, FP8 scales and the usability state words."""
+
+    def __init__(self, lo, hi, precision="bf16", mode="auto", warmup_steps=16, max_rel_err=0.5,
+                 device="cuda"):
+        f32 = dict(dtype=torch.float32, device=device)
+        self.params = torch.zeros(MLP_N_PARAMS, **f32)
+        self.adam_m = torch.zeros(MLP_N_PARAMS, **f32)
+        self.adam_v = torch.zeros(MLP_N_PARAMS, **f32)
+        self.weights = torch.zeros(MLP_WEIGHT_BYTES, dtype=torch.uint8, device=device)
+        self.scales = torch.ones(16, **f32)
+        self.state = torch.zeros(16, dtype=torch.int32, device=device)
+        self.step = 0
+        m = GiMlp()
+        m.params, m.adam_m, m.adam_v = self.params.data_ptr(), self.adam_m.data_ptr(), self.adam_v.data_ptr()
+        m.weights, m.scales, m.state = self.weights.data_ptr(), self.scales.data_ptr(), self.state.data_ptr()
+        m.pos_lo, m.pos_hi = _f3(lo), _f3(hi)
+        m.precision = MLP_PRECISION[precision]
+        m.mode = MLP_MODE[mode]
+        m.warmup_steps = int(warmup_steps)
+        m.max_rel_err = float(max_rel_err)
+        self.c = m
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+    @property
+    def precision(self):
+        return {v: k for k, v in MLP_PRECISION.items()}[self.c.precision]
+
+    def set_precision(self, precision, stream=None):
+        self.c.precision = MLP_PRECISION[precision]
+        self.prepare(stream)
+
+    def set_mode(self, mode):
+        self.c.mode = MLP_MODE[mode]
+
+    def init(self, seed, stream=None):
+        check(load().gi_mlp_init(self.ref, int(seed), _stream(stream)), "gi_mlp_init")
+        self.step = 0
+
+    def prepare(self, stream=None):
+        check(load().gi_mlp_prepare(self.ref, _stream(stream)), "gi_mlp_prepare")
+
+    def load_params(self, flat, stream=None):
+        """Set the master parameters (rounded to FP32) and prepare."""
+        self.params.copy_(torch.from_numpy(np.asarray(flat, np.float32)))
+        self.prepare(stream)
+
+    def state_words(self) -> dict:
+        w = self.state.cpu().numpy().view(np.uint32)
+        out = {}
+        for k, i in MLP_STATE.items():
+            out[k] = float(w[i:i + 1].view(np.float32)[0]) if k in ("ema_err", "loss", "batch_err") else int(w[i])
+        return out
+
+
+def mlp_infer(mlp: Mlp, pos4: torch.Tensor, nrm4: torch.Tensor, stream=None) -> torch.Tensor:
+    pos4, nrm4 = pos4.contiguous().float(), nrm4.contiguous().float()
+    out = torch.empty(pos4.shape[0], 4, dtype=torch.float32, device=pos4.device)
+    check(load().gi_mlp_infer(mlp.ref, pos4.shape[0], _ptr(pos4), _ptr(nrm4), _ptr(out), _stream(stream)),
+          "gi_mlp_infer")
+    return out
+
+
+class MlpBatch:
+    """Training samples (float4 planes)."""
+
+    def __init__(self, n, device="cuda"):
+        self.n = n
+        self.pos = torch.zeros(n, 4, dtype=torch.float32, device=device)
+        self.nrm = torch.zeros(n, 4, dtype=torch.float32, device=device)
+        self.target = torch.zeros(n, 4, dtype=torch.float32, device=device)
+        self.qprobe = torch.zeros(n, 4, dtype=torch.float32, device=device)
+
+    def slice(self, a, b):
+        s = MlpBatch.__new__(MlpBatch)
+        s.n = b - a
+        s.pos, s.nrm, s.target, s.qprobe = self.pos[a:b], self.nrm[a:b], self.target[a:b], self.qprobe[a:b]
+        return s
+
+
+def mlp_make_batch(scene, gb, res, probes, batch: MlpBatch, seed, frame, stream=None):
+    check(load().gi_mlp_make_batch(scene.ref, gb.ref, res.ref, probes.ref, batch.n, int(seed),
+                                   int(frame) & 0xFFFFFFFF, _ptr(batch.pos), _ptr(batch.nrm),
+                                   _ptr(batch.target), _ptr(batch.qprobe), _stream(stream)), "gi_mlp_make_batch")
+
+
+def train_workspace(n, device="cuda") -> torch.Tensor:
+    return torch.empty(int(load().gi_mlp_train_workspace_bytes(n)), dtype=torch.uint8, device=device)
+
+
+def mlp_grad(mlp: Mlp, batch: MlpBatch, grad: torch.Tensor, ws: torch.Tensor, stream=None, qprobe=True):
+    check(load().gi_mlp_grad(mlp.ref, batch.n, _ptr(batch.pos), _ptr(batch.nrm), _ptr(batch.target),
+                             _ptr(batch.qprobe) if qprobe else None, _ptr(grad), _ptr(ws), ws.numel(),
+                             _stream(stream)), "gi_mlp_grad")
+
+
+def mlp_adam(mlp: Mlp, grad: torch.Tensor, t, lr=1e-2, stream=None):
+    check(load().gi_mlp_adam(mlp.ref, _ptr(grad), int(t), float(lr), _stream(stream)), "gi_mlp_adam")
+
+
+def mlp_train_step(mlp: Mlp, batch: MlpBatch, t, lr, ws: torch.Tensor, stream=None):
+    check(load().gi_mlp_train_step(mlp.ref, batch.n, _ptr(batch.pos), _ptr(batch.nrm), _ptr(batch.target),
+                                   _ptr(batch.qprobe), int(t), float(lr), _ptr(ws), ws.numel(),
+                                   _stream(stream)), "gi_mlp_train_step")
+
+
+def initial_mlp_workspace(W, H, M, device="cuda") -> torch.Tensor:
+    return torch.empty(int(load().gi_initial_mlp_workspace_bytes(W, H, M)), dtype=torch.uint8, device=device)
+
+
+def shade_mlp_workspace(W, H, device="cuda") -> torch.Tensor:
+    return torch.empty(int(load().gi_shade_mlp_workspace_bytes(W, H)), dtype=torch.uint8, device=device)
+
+
+def resample_initial_mlp(scene, gb, probes, mlp: Mlp, params, out: Reservoirs, resid, ws, seed, frame,
+                         stream=None):
+    pp = params_struct(params)
+    check(load().gi_resample_initial_mlp(scene.ref, gb.ref, probes.ref, mlp.ref, C.byref(pp), out.ref,
+                                         _ptr(resid), _ptr(ws), ws.numel(), int(seed), int(frame) & 0xFFFFFFFF,
+                                         _stream(stream)), "gi_resample_initial_mlp")
+
+
+def shade_mlp(scene, gb, probes, mlp: Mlp, res, resid, params, out_rgba, ws, stream=None):
+    pp = params_struct(params)
+    check(load().gi_shade_mlp(scene.ref, gb.ref, probes.ref, mlp.ref, res.ref, _ptr(resid), C.byref(pp),
+                              _ptr(out_rgba), _ptr(ws), ws.numel(), _stream(stream)), "gi_shade_mlp")
+
+
+# --------------------------------------------------------------------------
 # frame driver
 # --------------------------------------------------------------------------
 FILL_FRAME_BASE = 0xF0000000
@@ -429,7 +597,8 @@ class Renderer:
     reservoirs, spatial passes (ping-pong) and shading."""
 
     def __init__(self, cfg: sg.Config, seed: int = 1, width=None, height=None, use_grid=True,
-                 device="cuda", scene=None, params=None, lds=True):
+                 device="cuda", scene=None, params=None, lds=True, mlp=None, mlp_mode="auto",
+                 mlp_batch=1 << 16, mlp_steps=4, mlp_lr=1e-2, mlp_warmup=16, mlp_seed=7, train=True):
         self.cfg = cfg
         self.seed = seed
         self.W, self.H = int(width or cfg.width), int(height or cfg.height)
@@ -446,6 +615,20 @@ class Renderer:
         self.hist = None
         self.cam_prev = None
         self.frame_index = 0
+        # learned cache (mlp = 'bf16' or 'fp8'): the target of the initial pass
+        # and of shading; trained after every frame on samples of the frame's
+        # initial reservoirs, mlp_steps Adam steps of mlp_batch/mlp_steps samples
+        self.mlp = None
+        if mlp is not None:
+            lo, hi = self.scene.bounds()
+            self.mlp = Mlp(lo, hi, precision=mlp, mode=mlp_mode, warmup_steps=mlp_warmup, device=device)
+            self.mlp.init(mlp_seed)
+            self.train = train
+            self.mlp_steps, self.mlp_lr = int(mlp_steps), float(mlp_lr)
+            self.batch = MlpBatch(int(mlp_batch), device)
+            self.ws_init = initial_mlp_workspace(self.W, self.H, self.params.M, device)
+            self.ws_shade = shade_mlp_workspace(self.W, self.H, device)
+            self.ws_train = train_workspace(int(mlp_batch) // self.mlp_steps, device)
 
     @property
     def probe(self) -> Probes:
@@ -477,7 +660,13 @@ class Renderer:
         trace_gbuffer(self.dscene, cam, gb, stream)
         bufs = [r for r in self.res if r is not self.hist]
         a = bufs[0]
-        resample_initial(self.dscene, gb, self.probe, pr, a, self.resid, self.seed, f, stream)
+        if self.mlp is not None:
+            resample_initial_mlp(self.dscene, gb, self.probe, self.mlp, pr, a, self.resid, self.ws_init,
+                                 self.seed, f, stream)
+            if self.train:
+                mlp_make_batch(self.dscene, gb, a, self.probe, self.batch, self.seed, f, stream)
+        else:
+            resample_initial(self.dscene, gb, self.probe, pr, a, self.resid, self.seed, f, stream)
         cur = a
         spare = bufs[1:]
         if pr.temporal and self.hist is not None:
@@ -491,8 +680,21 @@ class Renderer:
             dst = next(b for b in pool if b is not cur)
             resample_spatial(self.dscene, gb, cur, pr, sp, dst, self.seed, f, stream)
             cur = dst
-        shade(self.dscene, gb, self.probe, cur, self.resid, pr, self.img, stream)
+        if self.mlp is not None:
+            shade_mlp(self.dscene, gb, self.probe, self.mlp, cur, self.resid, pr, self.img, self.ws_shade, stream)
+            if self.train:
+                self.train_mlp(stream)
+        else:
+            shade(self.dscene, gb, self.probe, cur, self.resid, pr, self.img, stream)
         self.hist = cur
         self.cam_prev = cam
         self.frame_index = f + 1
         return cur
+
+    def train_mlp(self, stream=None):
+        """mlp_steps Adam steps on consecutive slices of the current batch."""
+        n = self.batch.n // self.mlp_steps
+        for k in range(self.mlp_steps):
+            self.mlp.step += 1
+            mlp_train_step(self.mlp, self.batch.slice(k * n, (k + 1) * n), self.mlp.step, self.mlp_lr,
+                           self.ws_train, stream)

@@ -22,7 +22,7 @@ def compare_reservoirs(gpu, ref, active=None, tol_mean=1e-4, tol_flip=1e-3, labe
     tg, tr = tags(gpu), tags(ref)
     same = (tg == tr) & act
     flips = np.mean(tg[act] != tr[act]) if act.any() else 0.0
-    out = {"flips": float(flips), "n": int(act.sum())}
+    out = {"flips": float(flips), "count": int(act.sum())}
     # integer fields exact on unflipped pixels
     assert np.array_equal(gpu[same, 11], ref[same, 11]), f"{label} M differs"
     assert np.array_equal(gpu[same, 13], ref[same, 13]), f"{label} prim differs"

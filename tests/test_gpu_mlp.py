@@ -1,0 +1,354 @@
+"""GPU parity of the learned radiance cache against the oracle (through the C ABI).
+
+* initialisation: bit-exact against the oracle's Philox initialisation;
+* inference: BF16 and FP8 MFMA kernels vs the oracle's BF16 / FP8 forward
+  (same operand rounding; FP32 vs FP64 accumulation and the hardware sine of
+  the encoding can move an operand across a rounding boundary now and then,
+  so the bound is statistical: mean and maximum error relative to the mean
+  output magnitude);
+* training: gradient, loss and statistics of one batch vs the oracle's BF16
+  backward on identical parameters and samples; Adam vs the oracle's step;
+* batch generation and the cache-target resampling passes vs the oracle on
+  the oracle's own inputs; the probe fallback is bit-identical to the probe
+  path;
+* the trained network's loss on a held-out batch drops well below the
+  untrained network's.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as o
+from oracle import mlp_ref as M
+from paper_2108_05263_amd import scenegen as sg
+
+from helpers import compare_reservoirs, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gi():
+    from paper_2108_05263_amd import gi as m
+    m.load()
+    assert torch.cuda.is_available()
+    return m
+
+
+BOX_LO, BOX_HI = np.zeros(3, np.float32), np.array([8.0, 8.0, 8.0], np.float32)
+
+
+def _points(n, seed):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, 8.0, (n, 3)).astype(np.float32)
+    nrm = rng.normal(size=(n, 3))
+    nrm = (nrm / np.linalg.norm(nrm, axis=1, keepdims=True)).astype(np.float32)
+    return pos, nrm
+
+
+def _params(seed):
+    """He-uniform weights with non-zero biases (the biases must reach the output)."""
+    p = M.init_params(seed)
+    rng = np.random.default_rng(seed + 1000)
+    for W, b in M.split(p):
+        b[:] = rng.uniform(-0.2, 0.2, b.shape)
+    return p.astype(np.float32).astype(np.float64)
+
+
+def _f4(a):
+    a = np.asarray(a, np.float32)
+    return torch.from_numpy(np.concatenate([a, np.zeros((len(a), 1), np.float32)], 1)).cuda()
+
+
+def _mlp(gi, params, precision="bf16", mode="always", lo=BOX_LO, hi=BOX_HI):
+    m = gi.Mlp(lo, hi, precision=precision, mode=mode)
+    m.load_params(params)
+    return m
+
+
+def _err_stats(gpu, ref):
+    scale = float(np.mean(np.abs(ref))) + 1e-6
+    e = np.abs(gpu - ref) / scale
+    return float(e.mean()), float(np.percentile(e, 99)), float(e.max())
+
+
+# --------------------------------------------------------------------------
+# initialisation and inference
+# --------------------------------------------------------------------------
+def test_mlp_init_bit_exact(gi):
+    m = gi.Mlp(BOX_LO, BOX_HI)
+    m.init(3)
+    torch.cuda.synchronize()
+    got = m.params.cpu().numpy()
+    ref = M.init_params_philox(3).astype(np.float32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    assert np.all(m.adam_m.cpu().numpy() == 0) and np.all(m.state.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("n", [1000, 32 * 4096 + 5])
+def test_mlp_infer_bf16(gi, n):
+    """Inference on n points (ragged last tile) vs the oracle's BF16 forward;
+    the FP64 forward's distance is reported (precision statement)."""
+    params = _params(11)
+    pos, nrm = _points(n, 12)
+    m = _mlp(gi, params, "bf16")
+    out = gi.mlp_infer(m, _f4(pos), _f4(nrm)).cpu().numpy()
+    assert np.all(out[:, 3] == 0)
+    sel = np.arange(n) if n <= 4096 else np.random.default_rng(0).choice(n, 4096, replace=False)
+    X = M.encode(pos[sel].astype(np.float64), nrm[sel].astype(np.float64), BOX_LO, BOX_HI)
+    ref, _ = M.forward(params, X, prec="bf16")
+    ref64, _ = M.forward(params, X, prec="f64")
+    mean, p99, mx = _err_stats(out[sel, :3], ref)
+    m64 = _err_stats(out[sel, :3], ref64)
+    log(f"bf16 n={n}: vs oracle bf16 mean {mean:.2e} p99 {p99:.2e} max {mx:.2e}; vs fp64 {m64}")
+    assert mean <= 2e-4 and p99 <= 5e-3 and mx <= 3e-2
+
+
+def test_mlp_infer_fp8(gi):
+    params = _params(21)
+    n = 4000
+    pos, nrm = _points(n, 22)
+    X = M.encode(pos.astype(np.float64), nrm.astype(np.float64), BOX_LO, BOX_HI)
+    amax = M.act_amax(params, X)
+    m = _mlp(gi, params, "fp8")
+    m.scales[5:10] = torch.tensor([a / 448.0 for a in amax], dtype=torch.float32)
+    out = gi.mlp_infer(m, _f4(pos), _f4(nrm)).cpu().numpy()[:, :3]
+    wsc = m.scales[:5].cpu().numpy()
+    assert np.allclose(wsc, M.fp8_weight_scales(params), rtol=1e-6)
+    # the oracle with the activation scales as stored (float32)
+    sa = [float(v) for v in m.scales[5:10].cpu().numpy()]
+    ref, _ = M.forward(params, X, prec="fp8", act_scales=sa)
+    ref64, _ = M.forward(params, X, prec="f64")
+    mean, p99, mx = _err_stats(out, ref)
+    m64 = _err_stats(out, ref64)
+    log(f"fp8: vs oracle fp8 mean {mean:.2e} p99 {p99:.2e} max {mx:.2e}; vs fp64 {m64}")
+    assert mean <= 2e-3 and p99 <= 5e-2 and mx <= 0.2
+
+
+# --------------------------------------------------------------------------
+# training
+# --------------------------------------------------------------------------
+def _batch(gi, n, seed, valid_frac=0.85):
+    rng = np.random.default_rng(seed)
+    pos, nrm = _points(n, seed)
+    tgt = rng.uniform(0.0, 2.0, (n, 3)).astype(np.float32)
+    q = rng.uniform(0.0, 1.5, (n, 3)).astype(np.float32)
+    valid = rng.random(n) < valid_frac
+    tgt[~valid] = 0
+    b = gi.MlpBatch(n)
+    b.pos.copy_(_f4(pos))
+    b.nrm.copy_(_f4(nrm))
+    t4 = np.concatenate([tgt, valid[:, None].astype(np.float32)], 1)
+    b.target.copy_(torch.from_numpy(t4))
+    b.qprobe.copy_(_f4(q))
+    return b, pos.astype(np.float64), nrm.astype(np.float64), tgt.astype(np.float64), valid, q.astype(np.float64)
+
+
+@pytest.mark.parametrize("n", [200, 16384])
+def test_mlp_grad(gi, n):
+    params = _params(31)
+    m = _mlp(gi, params, "bf16")
+    b, pos, nrm, tgt, valid, q = _batch(gi, n, 32)
+    grad = torch.zeros(gi.MLP_N_PARAMS, device="cuda")
+    ws = gi.train_workspace(n)
+    gi.mlp_grad(m, b, grad, ws)
+    g = grad.cpu().numpy().astype(np.float64)
+    st = m.state_words()
+    X = M.encode(pos, nrm, BOX_LO, BOX_HI)
+    out, cache = M.forward(params, X, prec="bf16")
+    loss, gout = M.loss_and_grad_out(out, tgt, valid)
+    ref = M.backward(params, cache, gout, prec="bf16")
+    # per-tensor relative error of the gradient
+    o_ = 0
+    worst = 0.0
+    for (i, nn) in M.LAYERS:
+        for size in (i * nn, nn):
+            gr, rr = g[o_:o_ + size], ref[o_:o_ + size]
+            e = np.linalg.norm(gr - rr) / (np.linalg.norm(rr) + 1e-30)
+            worst = max(worst, e)
+            o_ += size
+    log(f"grad n={n}: worst tensor rel err {worst:.2e}; loss {st['loss']:.6f} vs {loss:.6f}")
+    assert worst <= 1e-2
+    assert st["valid"] == int(valid.sum())
+    assert st["loss"] == pytest.approx(loss, rel=2e-3)
+    assert st["nonfinite"] == 0
+    relu_out = np.maximum(out, 0.0)
+    be = np.abs(relu_out - q)[valid].sum() / (q[valid] + 0.01).sum()
+    assert st["batch_err"] == pytest.approx(be, rel=2e-3)
+    # activation amax of every layer input (valid samples), FP8 scales
+    amax = M.act_amax(params, X[valid])
+    sa = m.scales[5:10].cpu().numpy() * 448.0
+    assert np.allclose(sa, amax, rtol=2e-2), (sa, amax)
+
+
+def test_mlp_adam(gi):
+    rng = np.random.default_rng(40)
+    params = _params(41)
+    m0 = rng.normal(0, 1e-2, M.N_PARAMS).astype(np.float32).astype(np.float64)
+    v0 = rng.uniform(0, 1e-3, M.N_PARAMS).astype(np.float32).astype(np.float64)
+    g = rng.normal(0, 1e-2, M.N_PARAMS).astype(np.float32).astype(np.float64)
+    m = _mlp(gi, params, "bf16")
+    m.adam_m.copy_(torch.from_numpy(m0.astype(np.float32)))
+    m.adam_v.copy_(torch.from_numpy(v0.astype(np.float32)))
+    grad = torch.from_numpy(g.astype(np.float32)).cuda()
+    gi.mlp_adam(m, grad, 3, 1e-2)
+    p_ref, m_ref, v_ref = M.adam_step(params, m0, v0, g, 3)
+    assert np.allclose(m.adam_m.cpu().numpy(), m_ref, rtol=1e-5, atol=1e-9)
+    assert np.allclose(m.adam_v.cpu().numpy(), v_ref, rtol=1e-5, atol=1e-12)
+    assert np.allclose(m.params.cpu().numpy(), p_ref, rtol=1e-5, atol=1e-6)
+    st = m.state_words()
+    assert st["steps"] == 3
+
+
+# --------------------------------------------------------------------------
+# batch generation and the cache-target passes on the oracle's inputs
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def tiny():
+    cfg = sg.CONFIGS["tiny"]
+    sc = sg.make_scene(cfg)
+    grid = sg.make_probe_grid(cfg)
+    irr, dep = o.fill_probes(sc, grid, cfg.probe_update, seed=1)
+    W, H = 64, 48
+    cam = sg.make_camera(cfg, 0, W, H)
+    gb = o.gbuffer(sc, cam)
+    res, resid = o.resample_initial(sc, W, H, gb, grid, irr, dep, cfg.params, 1, 0)
+    return cfg, sc, grid, irr, dep, W, H, gb, res, resid
+
+
+def test_mlp_make_batch(gi, tiny):
+    cfg, sc, grid, irr, dep, W, H, gb, res, _ = tiny
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    probes = gi.Probes(grid)
+    probes.load(irr, dep)
+    g, r = gi.GBuffer(W, H), gi.Reservoirs(W, H)
+    g.load_records(gb)
+    r.load_records(res)
+    n = 3000
+    b = gi.MlpBatch(n)
+    gi.mlp_make_batch(ds, g, r, probes, b, 5, 2)
+    pos, nrm, tgt, valid, qp = o.mlp_batch(sc, W, H, gb, res, grid, irr, dep, n, 5, 2)
+    t4 = b.target.cpu().numpy()
+    gvalid = t4[:, 3] != 0
+    assert np.array_equal(gvalid, valid)
+    assert valid.mean() > 0.8
+    assert np.array_equal(b.pos.cpu().numpy()[:, :3], pos.astype(np.float32))
+    assert np.array_equal(b.nrm.cpu().numpy()[:, :3], nrm.astype(np.float32))
+    et = rel_err(t4[valid, :3], tgt[valid], 1e-2)
+    eq = rel_err(b.qprobe.cpu().numpy()[valid, :3], qp[valid], 1e-2)
+    # a label ray may hit another primitive near a silhouette: count those apart
+    far = et.max(1) > 1e-2
+    log(f"batch: label rel err mean {et[~far].mean():.2e} (far {far.mean():.2e}), qprobe {eq.mean():.2e}")
+    assert far.mean() <= 2e-3
+    assert et[~far].mean() <= 1e-4 and eq.mean() <= 1e-4
+
+
+def _cache_setup(gi, tiny, precision="bf16", mode="always"):
+    cfg, sc, grid, irr, dep, W, H, gb, res, resid = tiny
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    probes = gi.Probes(grid)
+    probes.load(irr, dep)
+    g = gi.GBuffer(W, H)
+    g.load_records(gb)
+    lo, hi = sc.bounds()
+    params = _params(51)
+    m = _mlp(gi, params, precision, mode, lo, hi)
+    return ds, probes, g, m, params, lo, hi
+
+
+def test_initial_and_shade_with_cache(gi, tiny):
+    cfg, sc, grid, irr, dep, W, H, gb, res, resid = tiny
+    ds, probes, g, m, params, lo, hi = _cache_setup(gi, tiny)
+    pr = cfg.params
+    out = gi.Reservoirs(W, H)
+    gresid = torch.zeros(W * H, 4, device="cuda")
+    ws = gi.initial_mlp_workspace(W, H, pr.M)
+    gi.resample_initial_mlp(ds, g, probes, m, pr, out, gresid, ws, 1, 0)
+    target = o.MlpTarget(params, lo, hi, prec="bf16")
+    r_ref, d_ref = o.resample_initial(sc, W, H, gb, grid, irr, dep, pr, 1, 0, mlp=target)
+    active = (gb[:, 13] != o.MISS) & (gb[:, 6:9].max(1) > 0)
+    stats, same = compare_reservoirs(out.to_records(), r_ref, active, tol_mean=1e-3, tol_flip=3e-3,
+                                     label="initial cache")
+    er = rel_err(gresid.cpu().numpy()[:, :3], d_ref)
+    log(f"initial with cache: {stats}; resid {er.mean():.2e}")
+    assert er.mean() < 1e-3
+    # shading with the cache, on the oracle's reservoirs
+    rin = gi.Reservoirs(W, H)
+    rin.load_records(r_ref)
+    gresid.copy_(torch.from_numpy(np.concatenate([d_ref, np.zeros((W * H, 1))], 1).astype(np.float32)))
+    img = torch.zeros(W * H, 4, device="cuda")
+    wss = gi.shade_mlp_workspace(W, H)
+    gi.shade_mlp(ds, g, probes, m, rin, gresid, pr, img, wss)
+    ref_img = o.shade(sc, W, H, gb, grid, irr, dep, r_ref, d_ref, pr, mlp=target)
+    e = rel_err(img.cpu().numpy()[:, :3], ref_img, 1e-2)
+    log(f"shade with cache: mean rel err {e.mean():.2e} max {e.max():.2e}")
+    assert e.mean() < 1e-3
+
+
+@pytest.mark.parametrize("how", ["never", "auto_unusable", "nan_weights"])
+def test_probe_fallback_bit_identical(gi, tiny, how):
+    """When the mode or the device state rules the cache out, the cache entry
+    points give exactly the probe path's reservoirs and image."""
+    cfg, sc, grid, irr, dep, W, H, gb, res, resid = tiny
+    ds, probes, g, m, params, lo, hi = _cache_setup(gi, tiny, mode="never" if how == "never" else "auto")
+    if how == "nan_weights":
+        # a NaN output bias: every output is NaN; a training step leaves the
+        # state unusable
+        m.params[M.N_PARAMS - 3] = float("nan")
+        m.prepare()
+        b, *_ = _batch(gi, 256, 60)
+        ws = gi.train_workspace(256)
+        m.c.warmup_steps = 0
+        gi.mlp_train_step(m, b, 1, 1e-2, ws)
+        st = m.state_words()
+        assert st["usable"] == 0 and st["nonfinite"] > 0
+    pr = cfg.params
+    a, bres = gi.Reservoirs(W, H), gi.Reservoirs(W, H)
+    ra, rb = torch.zeros(W * H, 4, device="cuda"), torch.zeros(W * H, 4, device="cuda")
+    gi.resample_initial(ds, g, probes, pr, a, ra, 1, 0)
+    gi.resample_initial_mlp(ds, g, probes, m, pr, bres, rb, gi.initial_mlp_workspace(W, H, pr.M), 1, 0)
+    for x, y in ((a.y_W, bres.y_W), (a.n_wsum, bres.n_wsum), (a.L_M, bres.L_M), (a.tag_prim, bres.tag_prim),
+                 (ra, rb)):
+        assert torch.equal(x, y)
+    ia, ib = torch.zeros(W * H, 4, device="cuda"), torch.zeros(W * H, 4, device="cuda")
+    gi.shade(ds, g, probes, a, ra, pr, ia)
+    gi.shade_mlp(ds, g, probes, m, a, ra, pr, ib, gi.shade_mlp_workspace(W, H))
+    assert torch.equal(ia, ib)
+
+
+# --------------------------------------------------------------------------
+# online training
+# --------------------------------------------------------------------------
+def test_training_lowers_heldout_loss(gi):
+    """Renderer in cache mode on the small room: after 24 frames of online
+    training the relative-L2 loss on a held-out batch (drawn from a later
+    frame) is far below the untrained network's on the same batch."""
+    cfg = sg.CONFIGS["tiny"]
+    r = gi.Renderer(cfg, seed=1, width=96, height=96, mlp="bf16", mlp_batch=1 << 14, mlp_warmup=8)
+    r.fill_probes()
+    untrained = r.mlp.params.clone()
+    for f in range(24):
+        r.frame(f)
+    torch.cuda.synchronize()
+    st = r.mlp.state_words()
+    log(f"after 24 frames: {st}")
+    assert st["steps"] == 96 and st["nonfinite"] == 0 and st["usable"] == 1
+    held = gi.MlpBatch(1 << 14)
+    gi.mlp_make_batch(r.dscene, r.gb[1], r.hist, r.probe, held, 99, 1000)
+    grad = torch.zeros(gi.MLP_N_PARAMS, device="cuda")
+    ws = gi.train_workspace(held.n)
+    gi.mlp_grad(r.mlp, held, grad, ws)
+    trained_loss = r.mlp.state_words()["loss"]
+    r.mlp.params.copy_(untrained)
+    r.mlp.prepare()
+    gi.mlp_grad(r.mlp, held, grad, ws)
+    untrained_loss = r.mlp.state_words()["loss"]
+    log(f"held-out loss: untrained {untrained_loss:.4f} trained {trained_loss:.4f}")
+    assert trained_loss < 0.25 * untrained_loss

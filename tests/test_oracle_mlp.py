@@ -224,9 +224,11 @@ def test_adam_matches_torch():
 
 
 def test_batch_labels_closed_form():
-    # walls emit L and have albedo 0.5, probes empty: a label is the radiance
-    # arriving from another wall point, L_e + rho * Q = L exactly
+    # walls emit L and have albedo 0.5; every probe texel holds irradiance/pi
+    # c: a label is the radiance arriving from another wall point, L_e + rho c
+    # = L + c/2 exactly, and the probe value at the sample is c
     L = np.array([0.7, 1.1, 1.9], np.float32)
+    c = np.array([0.25, 0.5, 1.5], np.float32)
     sc = sg.Scene(prims=np.zeros((0, 16), np.float32), has_room=True, room_lo=np.zeros(3, np.float32),
                   room_hi=np.full(3, 8.0, np.float32), wall_albedo=np.full(3, 0.5, np.float32),
                   sky=np.zeros(3, np.float32), eps=8e-4, wall_emit=L)
@@ -234,14 +236,20 @@ def test_batch_labels_closed_form():
     cam = sg.make_camera(cfg, 0, 24, 24)
     grid = sg.probe_grid((2, 2, 2), (0, 0, 0), 4.0)
     irr, dep = sg.empty_probe_textures(grid)
+    irr[..., :3] = c
+    dep[..., 0], dep[..., 1] = 1.0, 1.0
     gb = o.gbuffer(sc, cam)
     res, _ = o.resample_initial(sc, 24, 24, gb, grid, irr, dep, sg.Params(M=4), 1, 0)
-    pos, nrm, tgt, valid = o.mlp_batch(sc, 24, 24, gb, res, grid, irr, dep, 300, 5, 0)
+    pos, nrm, tgt, valid, qp = o.mlp_batch(sc, 24, 24, gb, res, grid, irr, dep, 300, 5, 0)
     assert valid.mean() > 0.9
-    assert np.array_equal(tgt[valid], np.broadcast_to(L.astype(np.float64), tgt[valid].shape))
-    # inputs are the reservoirs' surface samples, on the walls
+    want = L.astype(np.float64) + 0.5 * c.astype(np.float64)
+    assert np.allclose(tgt[valid], want, rtol=1e-14, atol=0)
+    assert np.allclose(qp[valid], c.astype(np.float64), rtol=1e-14, atol=0)
+    assert np.all(tgt[~valid] == 0) and np.all(qp[~valid] == 0)
+    # inputs are the reservoirs' surface samples, on the walls, with unit normals
     on_wall = np.min(np.minimum(pos[valid], 8.0 - pos[valid]), axis=1)
     assert np.all(on_wall < 1e-6)
+    assert np.allclose(np.linalg.norm(nrm[valid], axis=1), 1.0)
 
 
 def test_c_forward_matches_numpy_oracle():
@@ -287,3 +295,19 @@ def test_constant_mlp_target_equals_constant_probes():
     i_prb = o.shade(sc, W, H, gb, grid, irr, dep, r_prb, d_prb, pr)
     assert np.allclose(i_mlp, i_prb, rtol=1e-9, atol=1e-12)
     assert np.abs(i_mlp).max() > 0.1
+
+
+def test_philox_init_distribution():
+    """He-uniform initialisation: every weight in [-b, b) with b = sqrt(6/fan_in),
+    zero biases, per-layer mean ~ 0 and variance ~ b^2/3 (uniform law)."""
+    p = M.init_params_philox(5)
+    for (W, b), (i, n) in zip(M.split(p), M.LAYERS):
+        bound = math.sqrt(6.0 / i)
+        assert np.all(b == 0)
+        assert np.all(np.abs(W) <= bound * (1 + 1e-6))
+        k = W.size
+        assert abs(W.mean()) < 5 * bound / math.sqrt(3 * k)
+        assert W.var() == pytest.approx(bound ** 2 / 3, rel=8 * math.sqrt(0.8 / k) + 0.01)
+    # two seeds differ, one seed repeats
+    assert not np.array_equal(p, M.init_params_philox(6))
+    assert np.array_equal(p, M.init_params_philox(5))
