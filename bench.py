@@ -8,8 +8,11 @@ volume is filled before the timed region (the workload updates it only
 before frame 0).
 
 Prints one JSON line: resampled pixels per second over whole frames, the
-per-kernel HIP-event times, the roofline of the dominant kernel and the FP64
-oracle's rate on a bounded crop of the same frame (CPU baseline).
+per-kernel HIP-event times, the roofline of the dominant kernel, the same
+frame with the learned cache as the target (BF16 and FP8 inference, online
+BF16 training; speed ratio to the probe form and the MFMA roofline of the
+inference kernel) and the FP64 oracle's rate on a bounded crop of the same
+frame (CPU baseline).
 """
 import argparse
 import json
@@ -43,6 +46,15 @@ def parse():
     ap.add_argument("--config", default="hd")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-crop", type=int, nargs=2, default=(320, 180))
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-cache forms")
+    ap.add_argument("--mlp-only", choices=["bf16", "fp8"], default=None,
+                    help="time only this learned-cache form (for profiling)")
+    ap.add_argument("--quality", action="store_true",
+                    help="instead of timing: image MSE of the probe and learned-cache forms against "
+                         "path-traced references (prints one JSON line)")
+    ap.add_argument("--quality-frames", type=int, default=32)
+    ap.add_argument("--quality-eval", type=int, default=8, help="last frames scored")
+    ap.add_argument("--ref-spp", type=int, default=512)
     ap.add_argument("--profile-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device-to-device once (a known-size "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -113,6 +125,150 @@ def cpu_baseline(cfg, crop):
                       f"reuse), {t_frame:.1f} s single-threaded FP64"}
 
 
+# Algorithmic FLOP of one network evaluation: 2 * (78*64 + 3*64*64 + 64*3)
+MLP_FLOP = 34944
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0}
+
+
+def mlp_form(gi, sg, torch, cfg, precision, steps, warmup):
+    """Frames of the learned-cache form (cache target in the initial pass and
+    in shading, online training after each frame), timed like the probe form,
+    plus the inference kernel alone on one frame's candidates."""
+    # the cache is always the target here (the usability test could hand
+    # frames back to the probe query and leave the inference untimed)
+    r = gi.Renderer(cfg, seed=1, mlp=precision, mlp_mode="always")
+    r.fill_probes()
+    stream = torch.cuda.current_stream()
+    keys = {"trace_gbuffer": "gbuffer", "resample_initial_mlp": "initial", "resample_temporal": "temporal",
+            "shade_mlp": "shade", "mlp_make_batch": "batch"}
+    orig = {k: getattr(gi, k) for k in list(keys) + ["resample_spatial"]}
+    pending = []
+
+    def timed(key_fn, fn):
+        def wrapper(*a, **kw):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn(*a, **kw)
+            e1.record(stream)
+            pending.append((key_fn(a), e0, e1))
+        return wrapper
+
+    for k, name in keys.items():
+        setattr(gi, k, timed(lambda a, name=name: name, orig[k]))
+    gi.resample_spatial = timed(lambda a: f"spatial{a[4]}", orig["resample_spatial"])
+    orig_train = r.train_mlp
+    r.train_mlp = timed(lambda a: "train", orig_train)
+    try:
+        for f in range(warmup):
+            r.frame(f)
+        torch.cuda.synchronize()
+        pending.clear()
+        t0 = time.perf_counter()
+        for f in range(warmup, warmup + steps):
+            r.frame(f)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+    finally:
+        for k, v in orig.items():
+            setattr(gi, k, v)
+    times = {}
+    for key, e0, e1 in pending:
+        times.setdefault(key, []).append(e0.elapsed_time(e1))
+    avg = {k: sum(v) / len(v) for k, v in times.items()}
+    st = r.mlp.state_words()
+    # inference alone on the last frame's candidate points (M per pixel)
+    n = r.W * r.H * r.params.M
+    ws = r.ws_init.view(torch.float32).view(-1, 4)
+    pos, nrm = ws[:n], ws[n:2 * n]
+    out = torch.empty(n, 4, dtype=torch.float32, device="cuda")
+    lib = gi.load()
+    import ctypes as C
+
+    def infer():
+        gi.check(lib.gi_mlp_infer(r.mlp.ref, n, C.c_void_p(pos.data_ptr()), C.c_void_p(nrm.data_ptr()),
+                                  C.c_void_p(out.data_ptr()), C.c_void_p(stream.cuda_stream)), "gi_mlp_infer")
+    infer()
+    torch.cuda.synchronize()
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        infer()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_inf = e0.elapsed_time(e1) / reps
+    tflops = n * MLP_FLOP / (t_inf * 1e-3) / 1e12
+    npx = r.W * r.H
+    res_ms = sum(v for k, v in avg.items() if k not in ("gbuffer", "batch", "train"))
+    return {
+        "ms_per_step": elapsed * 1e3 / steps,
+        "pixels_per_s": npx * steps / elapsed,
+        "resampling_only_pixels_per_s": npx / (res_ms * 1e-3),
+        "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
+        "train": {"samples_per_frame": r.batch.n, "adam_steps_per_frame": r.mlp_steps,
+                  "loss": st["loss"], "ema_rel_err_vs_probe": st["ema_err"], "usable": st["usable"]},
+        "infer_kernel": {"samples": n, "ms": t_inf, "bound": "mfma", "achieved": tflops,
+                         "peak": MFMA_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+                         "frac": tflops / MFMA_PEAK_TFLOPS[precision], "flop_per_sample": MLP_FLOP},
+    }
+
+
+def reference_image(gi, torch, r, gb, spp, seed, chunk=32):
+    """Mean of spp path-traced samples per pixel, in launches of `chunk` samples."""
+    acc = torch.zeros(r.W * r.H, 4, dtype=torch.float32, device="cuda")
+    tmp = torch.empty_like(acc)
+    s0 = 0
+    while s0 < spp:
+        n = min(chunk, spp - s0)
+        gi.path_trace(r.dscene, gb, n, seed, s0, tmp)
+        acc += tmp * n
+        s0 += n
+    return acc[:, :3] / spp
+
+
+def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp):
+    """Frames 0..frames-1 of each form (probe target; learned cache in BF16 /
+    FP8, always the target, trained online from frame 0); the last n_eval
+    frames are scored against path-traced references of the same camera:
+    MSE over pixels and channels, and the relative MSE (err^2 / (ref^2 +
+    0.01)).  The reference's own noise is estimated from two independent
+    halves (MSE(a, b) / 4 is the expected squared error of their mean)."""
+    eval_frames = list(range(frames - n_eval, frames))
+    base = gi.Renderer(cfg, seed=1)
+    refs, noise = {}, []
+    half = ref_spp // 2
+    for f in eval_frames:
+        gi.trace_gbuffer(base.dscene, base.camera(f), base.gb[0])
+        a = reference_image(gi, torch, base, base.gb[0], half, 777)
+        b = reference_image(gi, torch, base, base.gb[0], half, 778)
+        refs[f] = (a + b) * 0.5
+        noise.append(float(((a - b) ** 2).mean()) / 4.0)
+        print(f"reference frame {f} done", file=sys.stderr, flush=True)
+    del base
+    out = {"config": cfg.name, "frames": frames, "eval_frames": eval_frames, "ref_spp": ref_spp,
+           "ref_noise_mse": sum(noise) / len(noise), "forms": {}}
+    for form in ("probe", "bf16", "fp8"):
+        r = gi.Renderer(cfg, seed=1, mlp=None if form == "probe" else form, mlp_mode="always")
+        r.fill_probes()
+        mse, rel = [], []
+        for f in range(frames):
+            r.frame(f)
+            if f in refs:
+                img = r.img[:, :3]
+                d = (img - refs[f]) ** 2
+                mse.append(float(d.mean()))
+                rel.append(float((d / (refs[f] ** 2 + 1e-2)).mean()))
+        rec = {"mse": sum(mse) / len(mse), "relmse": sum(rel) / len(rel)}
+        if r.mlp is not None:
+            st = r.mlp.state_words()
+            rec.update({"loss": st["loss"], "ema_rel_err_vs_probe": st["ema_err"]})
+        out["forms"][form] = rec
+        print(f"form {form}: {rec}", file=sys.stderr, flush=True)
+        del r
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -129,6 +285,14 @@ def main():
 
     cfg = sg.CONFIGS[args.config]
     torch.cuda.set_device(0)
+    if args.quality:
+        print(json.dumps({"quality": quality(gi, sg, torch, cfg, args.quality_frames, args.quality_eval,
+                                             args.ref_spp)}), flush=True)
+        return
+    if args.mlp_only:
+        print(json.dumps({"mlp_form": args.mlp_only,
+                          **mlp_form(gi, sg, torch, cfg, args.mlp_only, args.steps, args.warmup)}), flush=True)
+        return
     r = gi.Renderer(cfg, seed=1)
     r.fill_probes()
     stream = torch.cuda.current_stream()
@@ -213,6 +377,16 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "kernel_source_sha": source_sha()},
     }
+    if not args.no_mlp:
+        del r
+        torch.cuda.empty_cache()
+        forms = {}
+        for prec in ("bf16", "fp8"):
+            f = mlp_form(gi, sg, torch, cfg, prec, args.steps, args.warmup)
+            f["speed_ratio_vs_probe"] = ms_step / f["ms_per_step"]
+            forms[prec] = f
+            torch.cuda.empty_cache()
+        line["mlp_forms"] = forms
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg, tuple(args.cpu_crop))
     print(json.dumps(line), flush=True)

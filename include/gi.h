@@ -312,18 +312,21 @@ gi_status gi_mlp_prepare(const gi_mlp *mlp, void *stream);
 gi_status gi_mlp_infer(const gi_mlp *mlp, uint32_t n, const float *pos4, const float *nrm4, float *out4,
                        void *stream);
 
-/* Training samples drawn from the resampler's own reservoirs.  Sample j
- * (counter (j, frame, 10, 0)) takes pixel p = floor(u0 W H) and the surface
- * sample (y, n_y) of res at p; its label is the radiance arriving along a
- * cosine-distributed direction (u1, u2) about n_y, L_e(z) + rho_z Q(z_b, n_z)
- * at the hit z with z_b biased toward y (a one-bounce gather past the probes,
- * Sec. 3.2), or the sky.  Outputs (float4 planes of n): pos4 (y, 0), nrm4
- * (n_y, 0), target4 (label, valid 1/0), qprobe4 (Q(y_b, n_y) with y_b biased
- * toward the pixel's x: the probe value the cache replaces, 0).  A sample
- * whose pixel holds no surface sample is invalid (all zero). */
-gi_status gi_mlp_make_batch(const gi_scene *scene, const gi_gbuffer *gb, const gi_reservoirs *res,
-                            const gi_probes *probes, uint32_t n, uint64_t seed, uint32_t frame,
-                            float *pos4, float *nrm4, float *target4, float *qprobe4, void *stream);
+/* Training samples: the cache is queried at the initial pass's candidates,
+ * so it is trained on them.  Sample j (counter (j, frame, 10, 0)) takes pixel
+ * p = floor(u0 W H) and candidate i = floor(u1 M) of the initial pass
+ * (counter (p, frame, 0, i), traced as gi_resample_initial traces it); its
+ * label is the radiance arriving along a cosine-distributed direction (u2,
+ * u3) about n_y, L_e(z) + rho_z Q(z_b, n_z) at the hit z with z_b biased
+ * toward y (a one-bounce gather past the probes, Sec. 3.2), or the sky.
+ * Outputs (float4 planes of n): pos4 (y, 0), nrm4 (n_y, 0), target4 (label,
+ * valid 1/0), qprobe4 (Q(y_b, n_y) with y_b biased toward the pixel's x: the
+ * probe value the cache replaces, 0).  A sample whose pixel has no surface,
+ * whose candidate misses or lands on a zero-albedo surface is invalid (all
+ * zero).  M in 1..GI_MAX_M (the initial pass's candidate count). */
+gi_status gi_mlp_make_batch(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes, uint32_t M,
+                            uint32_t n, uint64_t seed, uint32_t frame, float *pos4, float *nrm4,
+                            float *target4, float *qprobe4, void *stream);
 
 /* Device workspace bytes gi_mlp_grad / gi_mlp_train_step need for n samples. */
 uint64_t gi_mlp_train_workspace_bytes(uint32_t n);
@@ -376,6 +379,18 @@ gi_status gi_shade_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_pro
                        const gi_mlp *mlp, const gi_reservoirs *res, const float *resid,
                        const gi_params *params, float *out_rgba, void *workspace, uint64_t workspace_bytes,
                        void *stream);
+
+/* Reference path tracer (converged images the estimators are compared with;
+ * the paper evaluates against an unbiased path tracer, Sec. 4).  From each
+ * pixel's primary vertex in gb: L = L_e(x) plus, per bounce b = 1..32, the
+ * throughput times the emission hit (or the sky on a miss, which ends the
+ * path); each bounce samples a cosine direction about the normal (throughput
+ * *= albedo); from bounce 4 a path survives with probability P = min(1, max
+ * throughput component), throughput /= P; zero albedo ends a path.  Sample
+ * s, bounce b: counter (pixel, sample0 + s, 13, b).  out_rgba (float4 plane)
+ * receives the mean over the spp samples (rgb, 1).  spp in 1..65536. */
+gi_status gi_path_trace(const gi_scene *scene, const gi_gbuffer *gb, uint32_t spp, uint32_t sample0,
+                        uint64_t seed, float *out_rgba, void *stream);
 
 /* Host-side builder of the optional uniform-grid accelerator.  prims: HOST
  * array of n records.  Cells cover [lo, hi] with res cells per axis; a

@@ -1045,46 +1045,130 @@ void o_brute_force(const o_scene *sc, const o_probes *pr, const double *gb, int3
 }
 
 /* ---------------------------------------------------------------------------
- * Training samples of the learned cache (the MLP that can stand in for the
- * probe query; caches are interchangeable, Sec. 2 and Sec. 5).  Sample j
- * (counter (j, frame, 10, 0)) picks pixel p = floor(u0 W H) and takes the
- * surface sample y, n_y of that pixel's initial reservoir; its label is a
- * one-sample estimate of E(y, n_y)/pi: the radiance arriving along a
- * cosine-distributed direction (u1, u2) about n_y, L_e(z) + rho_z Q(z_b, n_z)
- * from the hit z (z_b biased toward y), or the sky.  qprobe receives
- * Q(y_b, n_y) with y_b biased toward the pixel's x, the probe value the cache
- * stands in for.  Samples whose pixel has no surface sample get valid = 0.
+ * Reference path tracer: the converged images the estimators are judged
+ * against (the paper's evaluation compares with an unbiased path tracer,
+ * Sec. 4).  A path starts at the pixel's primary vertex x (G-buffer) with
+ * L = L_e(x).  Bounce b = 1, 2, ...: leaving a surface of albedo rho, a
+ * cosine-distributed direction about its normal multiplies the throughput by
+ * rho (the Lambertian BSDF times the cosine over the density); from bounce 4
+ * on the path survives with probability P = min(1, max throughput component)
+ * and its throughput is divided by P (Russian roulette); the ray from the
+ * surface (offset eps along the normal) adds throughput x L_e of what it hits,
+ * or throughput x sky on a miss, which ends the path; a surface of zero
+ * albedo ends it too; at most 32 bounces.  Sample s, bounce b draws from
+ * counter (pixel, s, 13, b): u0, u1 for the direction, u2 for the roulette.
+ * out[q] = mean over samples s0 .. s0+spp-1.
  * ------------------------------------------------------------------------- */
-void o_mlp_batch(const o_scene *sc, const o_probes *pr, int32_t W, int32_t H, const double *gb,
-                 const double *res, int64_t B, uint64_t seed, uint32_t frame, double *pos, double *nrm,
-                 double *target, int32_t *valid, double *qprobe)
+void o_path_trace(const o_scene *sc, const double *gb, const int32_t *pix, int64_t npix, int32_t spp,
+                  uint32_t s0, uint64_t seed, double *out)
+{
+    for (int64_t q = 0; q < npix; ++q) {
+        const int64_t p = pix[q];
+        const double *g = gb + GB_N * p;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int32_t s = 0; s < spp; ++s) {
+            double x[3], n[3], rho[3], L[3], thr[3] = {1.0, 1.0, 1.0};
+            for (int a = 0; a < 3; ++a) {
+                x[a] = g[GB_POS + a];
+                n[a] = g[GB_NRM + a];
+                rho[a] = g[GB_ALB + a];
+                L[a] = g[GB_EMIT + a];
+            }
+            for (uint32_t b = 1; b <= 32; ++b) {
+                if (rho[0] == 0.0 && rho[1] == 0.0 && rho[2] == 0.0) break;
+                double u[4];
+                rand4(seed, (uint32_t)p, s0 + (uint32_t)s, 13u, b, u);
+                for (int a = 0; a < 3; ++a) thr[a] *= rho[a];
+                if (b >= 4) {
+                    double P = fmin(1.0, fmax(thr[0], fmax(thr[1], thr[2])));
+                    if (!(u[2] < P)) break;
+                    for (int a = 0; a < 3; ++a) thr[a] /= P;
+                }
+                double w[3], o[3];
+                o_cosine_dir(n, u[0], u[1], w);
+                for (int a = 0; a < 3; ++a) o[a] = x[a] + sc->eps * n[a];
+                o_hit h;
+                if (!closest_hit(sc, o, w, O_INF, &h)) {
+                    for (int a = 0; a < 3; ++a) L[a] += thr[a] * sc->sky[a];
+                    break;
+                }
+                double emit[3];
+                for (int a = 0; a < 3; ++a) {
+                    x[a] = o[a] + h.t * w[a];
+                    n[a] = h.n[a];
+                }
+                material(sc, h.prim, rho, emit);
+                for (int a = 0; a < 3; ++a) L[a] += thr[a] * emit[a];
+            }
+            for (int a = 0; a < 3; ++a) acc[a] += L[a];
+        }
+        for (int a = 0; a < 3; ++a) out[3 * q + a] = acc[a] / (double)spp;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Training samples of the learned cache (the MLP that can stand in for the
+ * probe query; caches are interchangeable, Sec. 2 and Sec. 5).  The cache is
+ * queried at the initial pass's candidates, so it is trained on them: sample
+ * j (counter (j, frame, 10, 0)) takes pixel p = floor(u0 W H) and candidate
+ * i = floor(u1 M) of that pixel, regenerated from the initial pass's own
+ * counter (p, frame, 0, i) (direction u0, u1 about n_x from x + eps n_x).
+ * Candidates that miss, land on a zero-albedo surface (where the cache is
+ * never used) or belong to a pixel without a surface are invalid (all zero).
+ * The label at the candidate y is a one-sample estimate of E(y, n_y)/pi: the
+ * radiance arriving along a cosine-distributed direction (u2, u3) about n_y
+ * from y + eps n_y, L_e(z) + rho_z Q(z_b, n_z) at the hit z with z_b biased
+ * toward y (a gather past the probes, Sec. 3.2), or the sky.  qprobe receives
+ * Q(y_b, n_y) with y_b biased toward x, the probe value the cache replaces.
+ * (Selected reservoir samples would not do as training inputs: selection
+ * follows the target, which contains the cache, so a region the cache
+ * predicts dark would never be selected and never corrected.)
+ * ------------------------------------------------------------------------- */
+void o_mlp_batch(const o_scene *sc, const o_probes *pr, int32_t W, int32_t H, const double *gb, int32_t M,
+                 int64_t B, uint64_t seed, uint32_t frame, double *pos, double *nrm, double *target,
+                 int32_t *valid, double *qprobe)
 {
     for (int64_t j = 0; j < B; ++j) {
-        double u[4];
+        double u[4], c[4];
         rand4(seed, (uint32_t)j, frame, 10u, 0u, u);
         int64_t p = (int64_t)floor(u[0] * (double)W * (double)H);
+        uint32_t i = (uint32_t)floor(u[1] * (double)M);
         const double *g = gb + GB_N * p;
-        const double *r = res + R_N * p;
         valid[j] = 0;
         for (int a = 0; a < 3; ++a) {
             pos[3 * j + a] = 0.0; nrm[3 * j + a] = 0.0; target[3 * j + a] = 0.0; qprobe[3 * j + a] = 0.0;
         }
-        if (!pixel_active(g) || !(r[R_W] > 0.0) || res_is_sky(r)) continue;
-        const double *y = r + R_Y, *ny = r + R_NY;
-        double w[3], o[3], L[3];
-        o_cosine_dir(ny, u[1], u[2], w);
-        for (int a = 0; a < 3; ++a) o[a] = y[a] + sc->eps * ny[a];
+        if (!pixel_active(g)) continue;
+        const double *x = g + GB_POS, *nx = g + GB_NRM;
+        /* the candidate */
+        double w[3], o[3];
+        rand4(seed, (uint32_t)p, frame, 0u, i, c);
+        o_cosine_dir(nx, c[0], c[1], w);
+        for (int a = 0; a < 3; ++a) o[a] = x[a] + sc->eps * nx[a];
+        o_hit hy;
+        if (!closest_hit(sc, o, w, O_INF, &hy)) continue;
+        double y[3], ny[3], alb[3], emit[3];
+        for (int a = 0; a < 3; ++a) {
+            y[a] = o[a] + hy.t * w[a];
+            ny[a] = hy.n[a];
+        }
+        material(sc, hy.prim, alb, emit);
+        if (alb[0] == 0.0 && alb[1] == 0.0 && alb[2] == 0.0) continue;
+        /* its label */
+        double wl[3], ol[3], L[3];
+        o_cosine_dir(ny, u[2], u[3], wl);
+        for (int a = 0; a < 3; ++a) ol[a] = y[a] + sc->eps * ny[a];
         o_hit h;
-        if (closest_hit(sc, o, w, O_INF, &h)) {
+        if (closest_hit(sc, ol, wl, O_INF, &h)) {
             double z[3];
-            for (int a = 0; a < 3; ++a) z[a] = o[a] + h.t * w[a];
+            for (int a = 0; a < 3; ++a) z[a] = ol[a] + h.t * wl[a];
             radiance_toward_ex(sc, pr, h.prim, z, h.n, y, 0, L);
         } else {
             for (int a = 0; a < 3; ++a) L[a] = sc->sky[a];
         }
-        /* the probe value the cache replaces at y, biased toward the pixel's x */
+        /* the probe value the cache replaces at y, biased toward x */
         double yb[3], q[3];
-        o_view_bias(y, g + GB_POS, pr->bias_dist, yb);
+        o_view_bias(y, x, pr->bias_dist, yb);
         probe_query(pr, yb, ny, 0, q);
         valid[j] = 1;
         for (int a = 0; a < 3; ++a) {

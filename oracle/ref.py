@@ -422,17 +422,17 @@ def brute_force(scene, W, H, gb, grid, irr, dep, pixels, nsamples, seed=12345) -
     return out
 
 
-def mlp_batch(scene, W, H, gb, res, grid, irr, dep, B, seed, frame):
+def mlp_batch(scene, W, H, gb, grid, irr, dep, M, B, seed, frame):
     """Training samples of the learned cache (see o_mlp_batch): returns
     (pos (B,3), nrm (B,3), target (B,3), valid (B,), qprobe (B,3))."""
     s, pr = _scene(scene), _Probes(grid, irr, dep)
-    gb, res = _f64(gb), _f64(res)
+    gb = _f64(gb)
     pos, nrm, tgt, qp = np.zeros((B, 3)), np.zeros((B, 3)), np.zeros((B, 3)), np.zeros((B, 3))
     valid = np.zeros(B, np.int32)
     L = lib()
-    L.o_mlp_batch.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, _P, C.c_int64, C.c_uint64, C.c_uint32,
+    L.o_mlp_batch.argtypes = [_P, _P, C.c_int32, C.c_int32, _P, C.c_int32, C.c_int64, C.c_uint64, C.c_uint32,
                               _P, _P, _P, _P, _P]
-    L.o_mlp_batch(s.ref, pr.ref, W, H, _ptr(gb), _ptr(res), int(B), int(seed), int(frame) & 0xFFFFFFFF,
+    L.o_mlp_batch(s.ref, pr.ref, W, H, _ptr(gb), int(M), int(B), int(seed), int(frame) & 0xFFFFFFFF,
                   _ptr(pos), _ptr(nrm), _ptr(tgt), _ptr(valid), _ptr(qp))
     return pos, nrm, tgt, valid.astype(bool), qp
 
@@ -448,4 +448,16 @@ def mlp_forward(params, prec, lo, hi, pos, nrm) -> np.ndarray:
     for i in range(len(pos)):
         L.o_mlp_forward(_ptr(p), 1 if prec == "bf16" else 0, _ptr(lo_), _ptr(hi_), _ptr(pos[i]),
                         _ptr(nrm[i]), out[i].ctypes.data_as(C.c_void_p))
+    return out
+
+
+def path_trace(scene, gb, pixels, spp, seed, s0=0) -> np.ndarray:
+    """Reference path tracer (o_path_trace) for the listed pixels: (n, 3)."""
+    s = _scene(scene)
+    gb = _f64(gb)
+    pix = np.ascontiguousarray(np.asarray(pixels, np.int32))
+    out = np.zeros((len(pix), 3))
+    L = lib()
+    L.o_path_trace.argtypes = [_P, _P, _P, C.c_int64, C.c_int32, C.c_uint32, C.c_uint64, _P]
+    L.o_path_trace(s.ref, _ptr(gb), _ptr(pix), len(pix), int(spp), int(s0) & 0xFFFFFFFF, int(seed), _ptr(out))
     return out

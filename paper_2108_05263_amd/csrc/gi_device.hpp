@@ -71,7 +71,8 @@ __device__ __forceinline__ uint4 philox(uint64_t seed, uint32_t c0, uint32_t c1,
 // 24-bit uniform in [0, 1): exact in FP32
 __device__ __forceinline__ float u01(uint32_t v) { return (float)(v >> 8) * 5.9604644775390625e-08f; }
 
-enum : uint32_t { kPassInitial = 0, kPassTemporal = 1, kPassSpatial0 = 2, kPassProbe = 9, kPassTrainBatch = 10 };
+enum : uint32_t { kPassInitial = 0, kPassTemporal = 1, kPassSpatial0 = 2, kPassProbe = 9, kPassTrainBatch = 10,
+                   kPassReference = 13 };
 
 // --------------------------------------------------------------------------
 // samplers

@@ -640,10 +640,12 @@ __global__ void __launch_bounds__(kBlock)
 // --------------------------------------------------------------------------
 // training samples of the learned cache
 // --------------------------------------------------------------------------
+// Sample j: pixel p = floor(u0 W H), candidate i = floor(u1 M) of the
+// initial pass (its own counter), label gathered along (u2, u3) about n_y.
 template <bool LDS>
 __global__ void __launch_bounds__(kBlock)
-    k_mlp_batch(gi_scene sc, gi_gbuffer gb, gi_reservoirs res, gi_probes pr, uint32_t n, uint64_t seed,
-                uint32_t frame, float4 *pos, float4 *nrm, float4 *tgt, float4 *qp)
+    k_mlp_batch(gi_scene sc, gi_gbuffer gb, gi_probes pr, uint32_t M, uint32_t n, uint64_t seed, uint32_t frame,
+                float4 *pos, float4 *nrm, float4 *tgt, float4 *qp)
 {
     using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
     const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
@@ -651,34 +653,90 @@ __global__ void __launch_bounds__(kBlock)
     if (j >= n) return;
     const Acc acc(sc);
     const uint4 rn = philox(seed, j, frame, kPassTrainBatch, 0u);
-    // p = floor(u0 W H), exactly: u0 = (x >> 8) 2^-24
+    // floor(u W H) and floor(u M) exactly: u = (x >> 8) 2^-24
     const uint64_t npx = (uint64_t)gb.width * gb.height;
     const uint32_t p = (uint32_t)(((uint64_t)(rn.x >> 8) * npx) >> 24);
-    const GB g = load_gb(gb, p);
-    const Res r = load_res(res, p);
+    const uint32_t i = (uint32_t)(((uint64_t)(rn.y >> 8) * M) >> 24);
     const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (!active(g) || !(r.W > 0.0f) || is_zero(r.n)) {
-        pos[j] = zero;
-        nrm[j] = zero;
-        tgt[j] = zero;
-        qp[j] = zero;
-        return;
-    }
-    const V3 w = cosine_dir(r.n, u01(rn.y), u01(rn.z));
-    const V3 o = madd(r.y, sc.eps, r.n);
+    pos[j] = zero;
+    nrm[j] = zero;
+    tgt[j] = zero;
+    qp[j] = zero;
+    const GB g = load_gb(gb, p);
+    if (!active(g)) return;
+    // the candidate, as the initial pass traces it
+    const uint4 rc = philox(seed, p, frame, kPassInitial, i);
+    const V3 w = cosine_dir(g.n, u01(rc.x), u01(rc.y));
+    const V3 o = madd(g.pos, sc.eps, g.n);
+    Hit hy;
+    if (!cast<false>(sc, acc, o, w, kInf, hy)) return;
+    const V3 y = madd(o, hy.t, w), ny = hit_normal(sc, acc, o, w, hy);
+    V3 alb, emit;
+    material(sc, hy.prim, alb, emit);
+    if (is_zero(alb)) return;
+    // its label
+    const V3 wl = cosine_dir(ny, u01(rn.z), u01(rn.w));
+    const V3 ol = madd(y, sc.eps, ny);
     Hit h;
     V3 L;
-    if (cast<false>(sc, acc, o, w, kInf, h)) {
-        const V3 z = madd(o, h.t, w);
-        L = radiance_toward(sc, pr, h.prim, z, hit_normal(sc, acc, o, w, h), r.y);
+    if (cast<false>(sc, acc, ol, wl, kInf, h)) {
+        const V3 z = madd(ol, h.t, wl);
+        L = radiance_toward(sc, pr, h.prim, z, hit_normal(sc, acc, ol, wl, h), y);
     } else {
         L = ld3(sc.sky);
     }
-    const V3 q = probe_query(pr, view_bias(r.y, g.pos, pr.bias_dist), r.n);
-    pos[j] = make_float4(r.y.x, r.y.y, r.y.z, 0.0f);
-    nrm[j] = make_float4(r.n.x, r.n.y, r.n.z, 0.0f);
+    const V3 q = probe_query(pr, view_bias(y, g.pos, pr.bias_dist), ny);
+    pos[j] = make_float4(y.x, y.y, y.z, 0.0f);
+    nrm[j] = make_float4(ny.x, ny.y, ny.z, 0.0f);
     tgt[j] = make_float4(L.x, L.y, L.z, 1.0f);
     qp[j] = make_float4(q.x, q.y, q.z, 0.0f);
+}
+
+// --------------------------------------------------------------------------
+// reference path tracer (converged images for the error statements)
+// --------------------------------------------------------------------------
+template <bool LDS>
+__global__ void __launch_bounds__(kBlock)
+    k_path_trace(gi_scene sc, gi_gbuffer gb, uint32_t spp, uint32_t s0, uint64_t seed, float4 *out)
+{
+    using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
+    uint32_t px, py;
+    const bool inside = tile_pixel(gb.width, gb.height, px, py);
+    if (LDS) stage_scene(sc);
+    if (!inside) return;
+    const Acc acc(sc);
+    const uint32_t p = py * gb.width + px;
+    const GB g = load_gb(gb, p);
+    const V3 e0 = xyz(reinterpret_cast<const float4 *>(gb.emit)[p]);
+    V3 sum = v3(0.0f, 0.0f, 0.0f);
+    for (uint32_t s = 0; s < spp; ++s) {
+        V3 x = g.pos, n = g.n, rho = g.alb, L = e0, thr = v3(1.0f, 1.0f, 1.0f);
+        for (uint32_t b = 1; b <= 32; ++b) {
+            if (is_zero(rho)) break;
+            const uint4 rn = philox(seed, p, s0 + s, kPassReference, b);
+            thr = thr * rho;
+            if (b >= 4) {
+                const float P = fminf(1.0f, fmaxf(thr.x, fmaxf(thr.y, thr.z)));
+                if (!(u01(rn.z) < P)) break;
+                thr = v3(thr.x / P, thr.y / P, thr.z / P);
+            }
+            const V3 w = cosine_dir(n, u01(rn.x), u01(rn.y));
+            const V3 o = madd(x, sc.eps, n);
+            Hit h;
+            if (!cast<false>(sc, acc, o, w, kInf, h)) {
+                L = L + thr * ld3(sc.sky);
+                break;
+            }
+            x = madd(o, h.t, w);
+            n = hit_normal(sc, acc, o, w, h);
+            V3 emit;
+            material(sc, h.prim, rho, emit);
+            L = L + thr * emit;
+        }
+        sum = sum + L;
+    }
+    const float inv = 1.0f / (float)spp;
+    out[p] = make_float4(sum.x * inv, sum.y * inv, sum.z * inv, 1.0f);
 }
 
 // --------------------------------------------------------------------------
@@ -953,23 +1011,23 @@ gi_status gi_shade(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes 
     return launched();
 }
 
-gi_status gi_mlp_make_batch(const gi_scene *scene, const gi_gbuffer *gb, const gi_reservoirs *res,
-                            const gi_probes *probes, uint32_t n, uint64_t seed, uint32_t frame, float *pos4,
-                            float *nrm4, float *target4, float *qprobe4, void *stream)
+gi_status gi_mlp_make_batch(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes, uint32_t M,
+                            uint32_t n, uint64_t seed, uint32_t frame, float *pos4, float *nrm4, float *target4,
+                            float *qprobe4, void *stream)
 {
     gi_status s;
-    if (!gb || !res) return GI_ERR_NULL;
+    if (!gb) return GI_ERR_NULL;
     uint32_t W = gb->width, H = gb->height;
     if ((s = check_scene(scene)) != GI_OK) return s;
     if ((s = check_gb(gb, W, H)) != GI_OK) return s;
-    if ((s = check_res(res, W, H)) != GI_OK) return s;
     if ((s = check_probes(probes)) != GI_OK) return s;
+    if (M < 1 || M > GI_MAX_M) return GI_ERR_PARAM;
     if (n > GI_MLP_MAX_BATCH) return GI_ERR_SHAPE;
     if (n == 0) return GI_OK;
     if (!pos4 || !nrm4 || !target4 || !qprobe4) return GI_ERR_NULL;
     if (W == 0 || H == 0) return GI_ERR_SHAPE;
-    GI_LAUNCH_LDS(k_mlp_batch, (n + kBlock - 1) / kBlock, kBlock, scene_lds(scene), S(stream), *scene, *gb, *res,
-                  *probes, n, seed, frame, reinterpret_cast<float4 *>(pos4), reinterpret_cast<float4 *>(nrm4),
+    GI_LAUNCH_LDS(k_mlp_batch, (n + kBlock - 1) / kBlock, kBlock, scene_lds(scene), S(stream), *scene, *gb, *probes,
+                  M, n, seed, frame, reinterpret_cast<float4 *>(pos4), reinterpret_cast<float4 *>(nrm4),
                   reinterpret_cast<float4 *>(target4), reinterpret_cast<float4 *>(qprobe4));
     return launched();
 }
@@ -1033,6 +1091,21 @@ gi_status gi_shade_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_pro
     GI_LAUNCH_LDS2(k_shade, true, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *probes, *res,
                    reinterpret_cast<const float4 *>(resid), *params, reinterpret_cast<float4 *>(out_rgba), q,
                    *mlp);
+    return launched();
+}
+
+gi_status gi_path_trace(const gi_scene *scene, const gi_gbuffer *gb, uint32_t spp, uint32_t sample0, uint64_t seed,
+                        float *out_rgba, void *stream)
+{
+    gi_status s;
+    if (!gb || !out_rgba) return GI_ERR_NULL;
+    uint32_t W = gb->width, H = gb->height;
+    if ((s = check_scene(scene)) != GI_OK) return s;
+    if ((s = check_gb(gb, W, H)) != GI_OK) return s;
+    if (spp < 1 || spp > 65536) return GI_ERR_PARAM;
+    if (W == 0 || H == 0) return GI_OK;
+    GI_LAUNCH_LDS(k_path_trace, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, spp, sample0, seed,
+                  reinterpret_cast<float4 *>(out_rgba));
     return launched();
 }
 

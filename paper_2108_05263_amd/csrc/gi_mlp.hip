@@ -11,8 +11,9 @@
 // Training (2^14..2^16 samples per step, ~0.6 GFLOP) runs on the vector ALUs
 // with the operands in LDS: one workgroup per 32 samples computes the
 // forward pass, the loss gradient and the backward pass, and writes its
-// partial gradient; a second kernel sums the partials in workgroup order, so
-// the result does not depend on scheduling.
+// partial gradient; two more kernels sum the partials in a fixed order
+// (groups of 16 workgroups, then the groups), so the result does not depend
+// on scheduling.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -547,16 +548,41 @@ __global__ void __launch_bounds__(kTrainBlock) k_mlp_fwdbwd(gi_mlp m, uint32_t n
     }
 }
 
-// ordered sum of the per-workgroup partials; statistics into state / scales
+// First level of the ordered reduction: rows g*kGroup .. g*kGroup+kGroup-1
+// of the partials are summed in order (max for the amax slots) into row
+// g*kGroup; each thread owns one column, so the in-place write is private.
+constexpr uint32_t kGroup = 16;
+
+__device__ __forceinline__ bool stat_is_max(int p)
+{
+    const int j = p - kParams;
+    return j >= kStAmax0 && j < kStAmax0 + kLayers;
+}
+
+__global__ void __launch_bounds__(256) k_mlp_reduce1(uint32_t nwg, float *part)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= kParams + kStats) return;
+    const uint32_t w0 = blockIdx.y * kGroup, w1 = min(w0 + kGroup, nwg);
+    const bool is_max = stat_is_max(p);
+    float acc = 0.0f;
+    for (uint32_t w = w0; w < w1; ++w) {
+        const float x = part[(size_t)w * kPartStride + p];
+        acc = is_max ? fmaxf(acc, x) : acc + x;
+    }
+    part[(size_t)w0 * kPartStride + p] = acc;
+}
+
+// second level: the group sums in group order; statistics into state / scales
 __global__ void __launch_bounds__(256) k_mlp_reduce(gi_mlp m, uint32_t nwg, const float *part, float *grad,
                                                     const uint32_t *hdr)
 {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= kParams + kStats) return;
     const int j = p - kParams;
-    const bool is_max = j >= kStAmax0 && j < kStAmax0 + kLayers;
+    const bool is_max = stat_is_max(p);
     float acc = 0.0f;
-    for (uint32_t w = 0; w < nwg; ++w) {
+    for (uint32_t w = 0; w < nwg; w += kGroup) {
         const float x = part[(size_t)w * kPartStride + p];
         acc = is_max ? fmaxf(acc, x) : acc + x;
     }
@@ -571,7 +597,7 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(gi_mlp m, uint32_t nwg, cons
         m.state[GI_MLP_STATE_VALID] = valid;
     } else if (j == kStErrNum) {
         float den = 0.0f;
-        for (uint32_t w = 0; w < nwg; ++w) den += part[(size_t)w * kPartStride + kParams + kStErrDen];
+        for (uint32_t w = 0; w < nwg; w += kGroup) den += part[(size_t)w * kPartStride + kParams + kStErrDen];
         m.state[GI_MLP_STATE_BATCH_ERR] = __float_as_uint(den > 0.0f ? acc / den : 0.0f);
     } else if (j == kStNonFinite) {
         m.state[GI_MLP_STATE_NONFINITE] = (uint32_t)acc;
@@ -652,7 +678,9 @@ gi_status grad_launch(const gi_mlp &m, uint32_t n, const float *pos4, const floa
                                                   reinterpret_cast<const float4 *>(nrm4),
                                                   reinterpret_cast<const float4 *>(target4),
                                                   reinterpret_cast<const float4 *>(qprobe4), hdr, part);
-    k_mlp_reduce<<<(kParams + kStats + 255) / 256, 256, 0, st>>>(m, nwg, part, grad, hdr);
+    const uint32_t cols = (kParams + kStats + 255) / 256;
+    if (nwg) k_mlp_reduce1<<<dim3(cols, (nwg + kGroup - 1) / kGroup), 256, 0, st>>>(nwg, part);
+    k_mlp_reduce<<<cols, 256, 0, st>>>(m, nwg, part, grad, hdr);
     return launched_mlp();
 }
 

@@ -29,7 +29,7 @@ EXPORTS = ["gi_status_string", "gi_device", "gi_trace_gbuffer", "gi_probe_update
            "gi_accel_build_host", "gi_philox", "gi_trace_rays",
            "gi_mlp_init", "gi_mlp_prepare", "gi_mlp_infer", "gi_mlp_make_batch", "gi_mlp_train_workspace_bytes",
            "gi_mlp_grad", "gi_mlp_adam", "gi_mlp_train_step", "gi_initial_mlp_workspace_bytes",
-           "gi_resample_initial_mlp", "gi_shade_mlp_workspace_bytes", "gi_shade_mlp"]
+           "gi_resample_initial_mlp", "gi_shade_mlp_workspace_bytes", "gi_shade_mlp", "gi_path_trace"]
 
 MLP_N_PARAMS = 17731
 MLP_WEIGHT_BYTES = 38912
@@ -126,12 +126,13 @@ def load():
         "gi_mlp_init": [_P, C.c_uint64, _P],
         "gi_mlp_prepare": [_P, _P],
         "gi_mlp_infer": [_P, C.c_uint32, _P, _P, _P, _P],
-        "gi_mlp_make_batch": [_P, _P, _P, _P, C.c_uint32, C.c_uint64, C.c_uint32, _P, _P, _P, _P, _P],
+        "gi_mlp_make_batch": [_P, _P, _P, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32, _P, _P, _P, _P, _P],
         "gi_mlp_grad": [_P, C.c_uint32, _P, _P, _P, _P, _P, _P, C.c_uint64, _P],
         "gi_mlp_adam": [_P, _P, C.c_uint32, C.c_float, _P],
         "gi_mlp_train_step": [_P, C.c_uint32, _P, _P, _P, _P, C.c_uint32, C.c_float, _P, C.c_uint64, _P],
         "gi_resample_initial_mlp": [_P, _P, _P, _P, _P, _P, _P, _P, C.c_uint64, C.c_uint64, C.c_uint32, _P],
         "gi_shade_mlp": [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_uint64, _P],
+        "gi_path_trace": [_P, _P, C.c_uint32, C.c_uint32, C.c_uint64, _P, _P],
     }.items():
         fn = getattr(L, name)
         fn.argtypes = args
@@ -433,6 +434,15 @@ def shade(scene, gb, probes, res, resid, params, out_rgba: torch.Tensor, stream=
                           _ptr(out_rgba), _stream(stream)), "gi_shade")
 
 
+def path_trace(scene: DeviceScene, gb: GBuffer, spp, seed, sample0=0, out_rgba=None, stream=None):
+    """Reference path tracer: mean of spp samples per pixel (float4 plane)."""
+    if out_rgba is None:
+        out_rgba = torch.zeros(gb.W * gb.H, 4, dtype=torch.float32, device=gb.pos_depth.device)
+    check(load().gi_path_trace(scene.ref, gb.ref, int(spp), int(sample0) & 0xFFFFFFFF, int(seed),
+                               _ptr(out_rgba), _stream(stream)), "gi_path_trace")
+    return out_rgba
+
+
 def philox(seed: int, ctr: torch.Tensor, stream=None) -> torch.Tensor:
     ctr = ctr.contiguous()
     out = torch.empty_like(ctr)
@@ -537,8 +547,8 @@ class MlpBatch:
         return s
 
 
-def mlp_make_batch(scene, gb, res, probes, batch: MlpBatch, seed, frame, stream=None):
-    check(load().gi_mlp_make_batch(scene.ref, gb.ref, res.ref, probes.ref, batch.n, int(seed),
+def mlp_make_batch(scene, gb, probes, M, batch: MlpBatch, seed, frame, stream=None):
+    check(load().gi_mlp_make_batch(scene.ref, gb.ref, probes.ref, int(M), batch.n, int(seed),
                                    int(frame) & 0xFFFFFFFF, _ptr(batch.pos), _ptr(batch.nrm),
                                    _ptr(batch.target), _ptr(batch.qprobe), _stream(stream)), "gi_mlp_make_batch")
 
@@ -616,8 +626,8 @@ class Renderer:
         self.cam_prev = None
         self.frame_index = 0
         # learned cache (mlp = 'bf16' or 'fp8'): the target of the initial pass
-        # and of shading; trained after every frame on samples of the frame's
-        # initial reservoirs, mlp_steps Adam steps of mlp_batch/mlp_steps samples
+        # and of shading; trained after every frame on the frame's candidates,
+        # mlp_steps Adam steps of mlp_batch/mlp_steps samples
         self.mlp = None
         if mlp is not None:
             lo, hi = self.scene.bounds()
@@ -664,7 +674,7 @@ class Renderer:
             resample_initial_mlp(self.dscene, gb, self.probe, self.mlp, pr, a, self.resid, self.ws_init,
                                  self.seed, f, stream)
             if self.train:
-                mlp_make_batch(self.dscene, gb, a, self.probe, self.batch, self.seed, f, stream)
+                mlp_make_batch(self.dscene, gb, self.probe, pr.M, self.batch, self.seed, f, stream)
         else:
             resample_initial(self.dscene, gb, self.probe, pr, a, self.resid, self.seed, f, stream)
         cur = a

@@ -228,19 +228,26 @@ def test_mlp_make_batch(gi, tiny):
     ds = gi.DeviceScene(sc, cfg.grid_res)
     probes = gi.Probes(grid)
     probes.load(irr, dep)
-    g, r = gi.GBuffer(W, H), gi.Reservoirs(W, H)
+    g = gi.GBuffer(W, H)
     g.load_records(gb)
-    r.load_records(res)
     n = 3000
     b = gi.MlpBatch(n)
-    gi.mlp_make_batch(ds, g, r, probes, b, 5, 2)
-    pos, nrm, tgt, valid, qp = o.mlp_batch(sc, W, H, gb, res, grid, irr, dep, n, 5, 2)
+    gi.mlp_make_batch(ds, g, probes, cfg.params.M, b, 5, 2)
+    pos, nrm, tgt, valid, qp = o.mlp_batch(sc, W, H, gb, grid, irr, dep, cfg.params.M, n, 5, 2)
     t4 = b.target.cpu().numpy()
     gvalid = t4[:, 3] != 0
-    assert np.array_equal(gvalid, valid)
+    # the candidate ray may reach another surface near a silhouette: count apart
+    both = gvalid & valid
+    assert np.mean(gvalid != valid) <= 2e-3
     assert valid.mean() > 0.8
-    assert np.array_equal(b.pos.cpu().numpy()[:, :3], pos.astype(np.float32))
-    assert np.array_equal(b.nrm.cpu().numpy()[:, :3], nrm.astype(np.float32))
+    ep = np.abs(b.pos.cpu().numpy()[both, :3] - pos[both]).max(1)
+    moved = ep > 1e-3
+    assert moved.mean() <= 2e-3
+    keep = np.nonzero(both)[0][~moved]
+    assert np.abs(b.pos.cpu().numpy()[keep, :3] - pos[keep]).max() < 1e-4
+    assert np.abs(b.nrm.cpu().numpy()[keep, :3] - nrm[keep]).max() < 1e-4
+    valid = np.zeros_like(valid)
+    valid[keep] = True
     et = rel_err(t4[valid, :3], tgt[valid], 1e-2)
     eq = rel_err(b.qprobe.cpu().numpy()[valid, :3], qp[valid], 1e-2)
     # a label ray may hit another primitive near a silhouette: count those apart
@@ -341,7 +348,7 @@ def test_training_lowers_heldout_loss(gi):
     log(f"after 24 frames: {st}")
     assert st["steps"] == 96 and st["nonfinite"] == 0 and st["usable"] == 1
     held = gi.MlpBatch(1 << 14)
-    gi.mlp_make_batch(r.dscene, r.gb[1], r.hist, r.probe, held, 99, 1000)
+    gi.mlp_make_batch(r.dscene, r.gb[1], r.probe, cfg.params.M, held, 99, 1000)
     grad = torch.zeros(gi.MLP_N_PARAMS, device="cuda")
     ws = gi.train_workspace(held.n)
     gi.mlp_grad(r.mlp, held, grad, ws)

@@ -239,14 +239,13 @@ def test_batch_labels_closed_form():
     irr[..., :3] = c
     dep[..., 0], dep[..., 1] = 1.0, 1.0
     gb = o.gbuffer(sc, cam)
-    res, _ = o.resample_initial(sc, 24, 24, gb, grid, irr, dep, sg.Params(M=4), 1, 0)
-    pos, nrm, tgt, valid, qp = o.mlp_batch(sc, 24, 24, gb, res, grid, irr, dep, 300, 5, 0)
+    pos, nrm, tgt, valid, qp = o.mlp_batch(sc, 24, 24, gb, grid, irr, dep, 4, 300, 5, 0)
     assert valid.mean() > 0.9
     want = L.astype(np.float64) + 0.5 * c.astype(np.float64)
     assert np.allclose(tgt[valid], want, rtol=1e-14, atol=0)
     assert np.allclose(qp[valid], c.astype(np.float64), rtol=1e-14, atol=0)
     assert np.all(tgt[~valid] == 0) and np.all(qp[~valid] == 0)
-    # inputs are the reservoirs' surface samples, on the walls, with unit normals
+    # inputs are candidates of the initial pass, on the walls, with unit normals
     on_wall = np.min(np.minimum(pos[valid], 8.0 - pos[valid]), axis=1)
     assert np.all(on_wall < 1e-6)
     assert np.allclose(np.linalg.norm(nrm[valid], axis=1), 1.0)
@@ -311,3 +310,25 @@ def test_philox_init_distribution():
     # two seeds differ, one seed repeats
     assert not np.array_equal(p, M.init_params_philox(6))
     assert np.array_equal(p, M.init_params_philox(5))
+
+
+def test_batch_inputs_are_initial_candidates():
+    """A training input is candidate i = floor(u1 M) of pixel p = floor(u0 W H)
+    of the initial pass: with M = 1 the initial reservoir holds exactly that
+    candidate, so the sample's position equals the reservoir's y."""
+    cfg = sg.CONFIGS["tiny"]
+    sc = sg.make_scene(cfg)
+    grid = sg.make_probe_grid(cfg)
+    irr, dep = sg.empty_probe_textures(grid)
+    irr[..., :3] = 0.5      # every candidate on a lit surface gets a positive weight
+    dep[..., 0], dep[..., 1] = 1.0, 1.0
+    W, H = 20, 16
+    gb = o.gbuffer(sc, sg.make_camera(cfg, 0, W, H))
+    res, _ = o.resample_initial(sc, W, H, gb, grid, irr, dep, sg.Params(M=1), 3, 2)
+    pos, nrm, tgt, valid, qp = o.mlp_batch(sc, W, H, gb, grid, irr, dep, 1, 400, 3, 2)
+    assert valid.mean() > 0.5
+    for j in np.nonzero(valid)[0]:
+        u = o.philox(3, [j, 2, 10, 0])
+        p = int(((int(u[0]) >> 8) * W * H) >> 24)
+        assert np.allclose(pos[j], res[p, 0:3], rtol=0, atol=1e-12)
+        assert np.allclose(nrm[j], res[p, 3:6], rtol=0, atol=1e-12)
