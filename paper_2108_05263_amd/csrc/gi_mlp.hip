@@ -28,7 +28,6 @@ using namespace gi::mlp;
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -155,22 +154,48 @@ __device__ __forceinline__ f32x16 mfma(long a, long b, f32x16 c)
     return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ bf16x8 to_bf16(f32x8 x) { return __builtin_convertvector(x, bf16x8); }
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-// ReLU on BF16 bit patterns: as signed 16-bit integers every negative value
-// (sign bit set) is below zero, so max(x, 0) clears exactly those; rounding
-// and ReLU commute.
-__device__ __forceinline__ bf16x8 relu_bf16(bf16x8 a)
+// two floats -> one register of two BF16 (one v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b)
 {
-    s16x8 s = __builtin_bit_cast(s16x8, a);
-    s = __builtin_elementwise_max(s, (s16x8)0);
-    return __builtin_bit_cast(bf16x8, s);
+    bf16x2 p = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, p);
 }
 
+// ReLU on two BF16 bit patterns: as signed 16-bit integers every negative
+// value (sign bit set) is below zero, so max(x, 0) clears exactly those;
+// rounding and ReLU commute.  Written as the instruction itself (an ALU
+// operation, no memory access): expressed as a vector max, the compiler
+// splits the preceding pair conversion into two conversions and a permute.
+__device__ __forceinline__ uint32_t relu_pk(uint32_t u)
+{
+    uint32_t r;
+    asm("v_pk_max_i16 %0, %1, 0" : "=v"(r) : "v"(u));
+    return r;
+}
+
+__device__ __forceinline__ bf16x8 to_bf16(f32x8 x)
+{
+    u32x4 r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] = pk_bf16(x[2 * i], x[2 * i + 1]);
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+// accumulators 8*part .. 8*part+7 as a BF16 operand, with ReLU
+__device__ __forceinline__ bf16x8 relu_operand(const f32x16 &a, int part)
+{
+    u32x4 r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] = relu_pk(pk_bf16(a[8 * part + 2 * i], a[8 * part + 2 * i + 1]));
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+// eight floats already within +-448 -> eight E4M3FN bytes
 __device__ __forceinline__ long to_fp8(f32x8 x)
 {
-#pragma unroll
-    for (int v = 0; v < 8; ++v) x[v] = fminf(fmaxf(x[v], -kFp8Max), kFp8Max);
     int lo = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
     lo = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], lo, true);
     int hi = __builtin_amdgcn_cvt_pk_fp8_f32(x[4], x[5], 0, false);
@@ -200,35 +225,55 @@ __device__ __forceinline__ f32x16 bias_tile(const float *b, int h)
 }
 
 template <int P>
-__global__ void __launch_bounds__(kInferBlock) k_mlp_infer(gi_mlp m, uint32_t n, const float4 *pos,
+__global__ void __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(P == GI_MLP_BF16 ? 2 : 1, 2)))
+k_mlp_infer(gi_mlp m, uint32_t n, const float4 *pos,
                                                            const float4 *nrm, float4 *out, int gate)
 {
     using FT = typename Frag<P>::T;
     if (gate && !mlp_selected(m)) return;   // uniform over the grid
-    // biases: layers 0-3 at 64 L, layer 4 at 256 padded to 32 rows
+    // FP8 scales (a non-positive or non-finite activation scale counts as 1):
+    // layer L's accumulator holds sum a8 w8 = z / (s_w s_a); its bias enters
+    // as b / (s_w s_a) and the next layer's operand is acc * (s_w s_a / s_a')
+    float kq[kLayers - 1];
+    float smul4 = 1.0f, in0 = 1.0f;
+    if (P == GI_MLP_FP8) {
+        float sa[kLayers];
+#pragma unroll
+        for (int L = 0; L < kLayers; ++L) {
+            sa[L] = m.scales[5 + L];
+            if (!(sa[L] > 0.0f && sa[L] < kInf)) sa[L] = 1.0f;
+        }
+#pragma unroll
+        for (int L = 0; L + 1 < kLayers; ++L) kq[L] = m.scales[L] * sa[L] / sa[L + 1];
+        in0 = 1.0f / sa[0];
+        smul4 = m.scales[4] * sa[4];
+    }
+    // biases (accumulator units): layers 0-3 at 64 L, layer 4 at 256 padded to 32 rows
     __shared__ __attribute__((aligned(16))) float sb[4 * 64 + 32];
     for (int i = threadIdx.x; i < 4 * 64 + 32; i += kInferBlock) {
         int L = i < 256 ? i >> 6 : 4, u = i < 256 ? (i & 63) : i - 256;
-        sb[i] = u < kOut[L] ? m.params[kOffB[L] + u] : 0.0f;
-    }
-    __syncthreads();
-    const int l = threadIdx.x & 63, s = l & 31, h = l >> 5;
-    FT wf[kFrags];
-    const FT *wsrc = reinterpret_cast<const FT *>(m.weights);
-#pragma unroll
-    for (int f = 0; f < kFrags; ++f) wf[f] = wsrc[f * 64 + l];
-
-    // FP8 scales (a non-positive or non-finite activation scale counts as 1)
-    float smul[kLayers], sinv[kLayers];
-    if (P == GI_MLP_FP8) {
-#pragma unroll
-        for (int L = 0; L < kLayers; ++L) {
+        float b = u < kOut[L] ? m.params[kOffB[L] + u] : 0.0f;
+        if (P == GI_MLP_FP8) {
             float sa = m.scales[5 + L];
             if (!(sa > 0.0f && sa < kInf)) sa = 1.0f;
-            smul[L] = m.scales[L] * sa;
-            sinv[L] = 1.0f / sa;
+            b = b / (m.scales[L] * sa);
         }
+        sb[i] = b;
     }
+    // the fragments of layers 0 and 1 (18) stay in LDS and are re-read per
+    // tile; the other 20 live in registers for the whole kernel (two waves
+    // per SIMD without spills)
+    constexpr int kLdsFrags = 18, kRegFrags = kFrags - kLdsFrags;
+    __shared__ FT wls[kLdsFrags * 64];
+    const FT *wsrc = reinterpret_cast<const FT *>(m.weights);
+    for (int i = threadIdx.x; i < kLdsFrags * 64; i += kInferBlock) wls[i] = wsrc[i];
+    __syncthreads();
+    const int l = threadIdx.x & 63, s = l & 31, h = l >> 5;
+    FT wf[kRegFrags];
+#pragma unroll
+    for (int f = 0; f < kRegFrags; ++f) wf[f] = wsrc[(kLdsFrags + f) * 64 + l];
+    auto frag = [&](int f) -> FT { return f < kLdsFrags ? wls[f * 64 + l] : wf[f - kLdsFrags]; };
+
     // lanes 0-31 encode the normalised position, lanes 32-63 the normal
     float lo[3], ext[3];
 #pragma unroll
@@ -261,24 +306,22 @@ __global__ void __launch_bounds__(kInferBlock) k_mlp_infer(gi_mlp m, uint32_t n,
         feat[39] = 0.0f;
 
         // layer 0: K = 80 (5 k-steps), two output tiles
-        f32x16 acc0, acc1;
-        if (P == GI_MLP_BF16) {
-            acc0 = bias_tile(sb, h);
-            acc1 = bias_tile(sb + 32, h);
-        } else {
-            acc0 = (f32x16)0.0f;
-            acc1 = (f32x16)0.0f;
-        }
+        f32x16 acc0 = bias_tile(sb, h), acc1 = bias_tile(sb + 32, h);
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             f32x8 x;
 #pragma unroll
             for (int v = 0; v < 8; ++v) x[v] = feat[8 * c + v];
             FT b;
-            if constexpr (P == GI_MLP_BF16) b = to_bf16(x);
-            else b = to_fp8(x * sinv[0]);
-            acc0 = mfma(wf[c], b, acc0);
-            acc1 = mfma(wf[5 + c], b, acc1);
+            if constexpr (P == GI_MLP_BF16) {
+                b = to_bf16(x);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) x[v] = __builtin_amdgcn_fmed3f(x[v] * in0, -kFp8Max, kFp8Max);
+                b = to_fp8(x);
+            }
+            acc0 = mfma(frag(c), b, acc0);
+            acc1 = mfma(frag(5 + c), b, acc1);
         }
         // hidden layers 1-3 and the output layer 4
 #pragma unroll
@@ -286,50 +329,34 @@ __global__ void __launch_bounds__(kInferBlock) k_mlp_infer(gi_mlp m, uint32_t n,
             FT bop[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                f32x8 x = half_of(c >> 1 ? acc1 : acc0, c & 1);
                 if constexpr (P == GI_MLP_BF16) {
-                    bop[c] = relu_bf16(to_bf16(x));
+                    bop[c] = relu_operand(c >> 1 ? acc1 : acc0, c & 1);
                 } else {
-                    // slot v is accumulator 4a + b with a = 2(c&1) + (v>>2), b = v&3 of
-                    // tile c>>1: unit 32(c>>1) + 16(c&1) + 8(v>>2) + 4h + (v&3)
-                    const float *bb = sb + 64 * (L - 1) + 32 * (c >> 1) + 16 * (c & 1) + 4 * h;
+                    f32x8 x = half_of(c >> 1 ? acc1 : acc0, c & 1);
+                    // ReLU, rescale to the next layer's input scale, saturate
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) {
-                        const float bias = bb[8 * (v >> 2) + (v & 3)];
-                        x[v] = fmaxf(fmaf(x[v], smul[L - 1], bias), 0.0f) * sinv[L];
-                    }
+                    for (int v = 0; v < 8; ++v) x[v] = __builtin_amdgcn_fmed3f(x[v] * kq[L - 1], 0.0f, kFp8Max);
                     bop[c] = to_fp8(x);
                 }
             }
             const int f0 = kFrag0[L];
             if (L < kLayers - 1) {
-                if (P == GI_MLP_BF16) {
-                    acc0 = bias_tile(sb + 64 * L, h);
-                    acc1 = bias_tile(sb + 64 * L + 32, h);
-                } else {
-                    acc0 = (f32x16)0.0f;
-                    acc1 = (f32x16)0.0f;
-                }
+                acc0 = bias_tile(sb + 64 * L, h);
+                acc1 = bias_tile(sb + 64 * L + 32, h);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    acc0 = mfma(wf[f0 + c], bop[c], acc0);
-                    acc1 = mfma(wf[f0 + 4 + c], bop[c], acc1);
+                    acc0 = mfma(frag(f0 + c), bop[c], acc0);
+                    acc1 = mfma(frag(f0 + 4 + c), bop[c], acc1);
                 }
             } else {
-                acc0 = P == GI_MLP_BF16 ? bias_tile(sb + 256, h) : (f32x16)0.0f;
+                acc0 = bias_tile(sb + 256, h);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc0 = mfma(wf[f0 + c], bop[c], acc0);
+                for (int c = 0; c < 4; ++c) acc0 = mfma(frag(f0 + c), bop[c], acc0);
             }
         }
         // output rows 0..2 sit in accumulators 0..2 of the lower half-wave
         if (ok && h == 0) {
-            float o0 = acc0[0], o1 = acc0[1], o2 = acc0[2];
-            if (P == GI_MLP_FP8) {
-                o0 = fmaf(o0, smul[4], sb[256]);
-                o1 = fmaf(o1, smul[4], sb[257]);
-                o2 = fmaf(o2, smul[4], sb[258]);
-            }
-            out[idx] = make_float4(o0, o1, o2, 0.0f);
+            out[idx] = make_float4(acc0[0] * smul4, acc0[1] * smul4, acc0[2] * smul4, 0.0f);
         }
     }
 }
