@@ -52,9 +52,10 @@ def parse():
     ap.add_argument("--quality", action="store_true",
                     help="instead of timing: image MSE of the probe and learned-cache forms against "
                          "path-traced references (prints one JSON line)")
-    ap.add_argument("--quality-frames", type=int, default=32)
-    ap.add_argument("--quality-eval", type=int, default=8, help="last frames scored")
-    ap.add_argument("--ref-spp", type=int, default=512)
+    ap.add_argument("--quality-frames", type=int, default=64)
+    ap.add_argument("--quality-eval", type=int, default=32, help="last frames scored")
+    ap.add_argument("--quality-seeds", type=int, default=2, help="render seeds averaged")
+    ap.add_argument("--ref-spp", type=int, default=2048)
     ap.add_argument("--profile-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device-to-device once (a known-size "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -62,7 +63,7 @@ def parse():
 
 
 KERNEL_SOURCES = ["paper_2108_05263_amd/csrc/gi_kernels.hip", "paper_2108_05263_amd/csrc/gi_device.hpp",
-                  "include/gi.h"]
+                  "paper_2108_05263_amd/csrc/gi_mlp.hip", "paper_2108_05263_amd/csrc/gi_mlp.hpp", "include/gi.h"]
 
 
 def source_sha():
@@ -226,13 +227,15 @@ def reference_image(gi, torch, r, gb, spp, seed, chunk=32):
     return acc[:, :3] / spp
 
 
-def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp):
+def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
     """Frames 0..frames-1 of each form (probe target; learned cache in BF16 /
-    FP8, always the target, trained online from frame 0); the last n_eval
-    frames are scored against path-traced references of the same camera:
-    MSE over pixels and channels, and the relative MSE (err^2 / (ref^2 +
-    0.01)).  The reference's own noise is estimated from two independent
-    halves (MSE(a, b) / 4 is the expected squared error of their mean)."""
+    FP8, always the target, trained online from frame 0) for render seeds
+    1..n_seeds; the last n_eval frames are scored against path-traced
+    references of the same camera: MSE over pixels and channels, relative
+    MSE (err^2 / (ref^2 + 0.01)) and MAPE (|err| / (ref + 0.01)), averaged
+    over frames and seeds.  The reference's own noise is estimated from two
+    independent halves (MSE(a, b) / 4 is the expected squared error of their
+    mean); it adds the same amount to every form's MSE."""
     eval_frames = list(range(frames - n_eval, frames))
     base = gi.Renderer(cfg, seed=1)
     refs, noise = {}, []
@@ -245,27 +248,31 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp):
         noise.append(float(((a - b) ** 2).mean()) / 4.0)
         print(f"reference frame {f} done", file=sys.stderr, flush=True)
     del base
-    out = {"config": cfg.name, "frames": frames, "eval_frames": eval_frames, "ref_spp": ref_spp,
-           "ref_noise_mse": sum(noise) / len(noise), "forms": {}}
+    out = {"config": cfg.name, "frames": frames, "eval_frames": [eval_frames[0], eval_frames[-1]],
+           "seeds": n_seeds, "ref_spp": ref_spp, "ref_noise_mse": sum(noise) / len(noise), "forms": {}}
     for form in ("probe", "bf16", "fp8"):
-        r = gi.Renderer(cfg, seed=1, mlp=None if form == "probe" else form, mlp_mode="always")
-        r.fill_probes()
-        mse, rel = [], []
-        for f in range(frames):
-            r.frame(f)
-            if f in refs:
-                img = r.img[:, :3]
-                d = (img - refs[f]) ** 2
-                mse.append(float(d.mean()))
-                rel.append(float((d / (refs[f] ** 2 + 1e-2)).mean()))
-        rec = {"mse": sum(mse) / len(mse), "relmse": sum(rel) / len(rel)}
-        if r.mlp is not None:
-            st = r.mlp.state_words()
-            rec.update({"loss": st["loss"], "ema_rel_err_vs_probe": st["ema_err"]})
+        acc = {"mse": [], "relmse": [], "mape": []}
+        per_seed = []
+        for seed in range(1, n_seeds + 1):
+            r = gi.Renderer(cfg, seed=seed, mlp=None if form == "probe" else form, mlp_mode="always")
+            r.fill_probes()
+            m = {"mse": 0.0, "relmse": 0.0, "mape": 0.0}
+            for f in range(frames):
+                r.frame(f)
+                if f in refs:
+                    d = r.img[:, :3] - refs[f]
+                    m["mse"] += float((d * d).mean()) / n_eval
+                    m["relmse"] += float((d * d / (refs[f] ** 2 + 1e-2)).mean()) / n_eval
+                    m["mape"] += float((d.abs() / (refs[f] + 1e-2)).mean()) / n_eval
+            for k in acc:
+                acc[k].append(m[k])
+            per_seed.append(m["mse"])
+            del r
+            torch.cuda.empty_cache()
+        rec = {k: sum(v) / len(v) for k, v in acc.items()}
+        rec["mse_per_seed"] = per_seed
         out["forms"][form] = rec
         print(f"form {form}: {rec}", file=sys.stderr, flush=True)
-        del r
-        torch.cuda.empty_cache()
     return out
 
 
@@ -287,11 +294,15 @@ def main():
     torch.cuda.set_device(0)
     if args.quality:
         print(json.dumps({"quality": quality(gi, sg, torch, cfg, args.quality_frames, args.quality_eval,
-                                             args.ref_spp)}), flush=True)
+                                             args.ref_spp, args.quality_seeds)}), flush=True)
         return
     if args.mlp_only:
         print(json.dumps({"mlp_form": args.mlp_only,
                           **mlp_form(gi, sg, torch, cfg, args.mlp_only, args.steps, args.warmup)}), flush=True)
+        if args.profile_copy:
+            src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
         return
     r = gi.Renderer(cfg, seed=1)
     r.fill_probes()

@@ -257,7 +257,7 @@ gi_status gi_shade(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes 
  * product are rounded to BF16 too) with FP32 master weights and Adam moments.
  * ========================================================================== */
 #define GI_MLP_N_PARAMS 17731u
-#define GI_MLP_WEIGHT_BYTES 38912u   /* 38 MFMA fragments x 64 lanes x 16 B */
+#define GI_MLP_WEIGHT_BYTES 40064u   /* 38 MFMA fragments x 64 lanes x 16 B + 288 FP32 biases */
 #define GI_MLP_MAX_BATCH (1u << 20)  /* largest training batch per call */
 
 typedef enum gi_mlp_precision { GI_MLP_BF16 = 0, GI_MLP_FP8 = 1 } gi_mlp_precision;
@@ -283,6 +283,9 @@ typedef struct gi_mlp {
     float *params;        /* GI_MLP_N_PARAMS FP32 master parameters */
     float *adam_m;        /* GI_MLP_N_PARAMS Adam first moments (zero at start) */
     float *adam_v;        /* GI_MLP_N_PARAMS Adam second moments (zero at start) */
+    float *ema;           /* GI_MLP_N_PARAMS exponential moving average of the parameters, or
+                             NULL; when set (and after the first Adam step) inference uses the
+                             bias-corrected average ema / (1 - ema_decay^t) */
     void *weights;        /* GI_MLP_WEIGHT_BYTES inference operands, written by gi_mlp_prepare */
     float *scales;        /* 16 floats: [0..4] FP8 weight scales (gi_mlp_prepare), [5..9] FP8
                              activation scales of the layer inputs (gi_mlp_grad or the caller) */
@@ -293,17 +296,21 @@ typedef struct gi_mlp {
     uint32_t mode;        /* gi_mlp_mode */
     uint32_t warmup_steps;/* AUTO: Adam steps before the cache may be used */
     float max_rel_err;    /* AUTO: largest EMA relative error vs the probe query, > 0 */
+    float ema_decay;      /* decay of the parameter average, in [0, 1) */
+    uint32_t pad;
 } gi_mlp;
 
 /* Initialise the master parameters: He-uniform weights, W[o][i] = (2u - 1)
  * sqrt(6 / fan_in) with u from counter (parameter index, 0, 12, 0) (first
- * word), zero biases; Adam moments and state are zeroed, then
- * gi_mlp_prepare runs. */
+ * word), zero biases; Adam moments, the parameter average and the state are
+ * zeroed, then gi_mlp_prepare runs. */
 gi_status gi_mlp_init(const gi_mlp *mlp, uint64_t seed, void *stream);
 
-/* Convert the master parameters into the inference operands (BF16 or FP8
- * MFMA fragments per `precision`; FP8 also writes the weight scales).  Must
- * run after any change of params or precision, before inference. */
+/* Convert the inference parameters (the bias-corrected average when `ema`
+ * is set and state STEPS > 0, else the master parameters) into the inference
+ * operands: BF16 or FP8 MFMA fragments per `precision` and FP32 biases; FP8
+ * also writes the weight scales.  Must run after any change of params, ema
+ * or precision, before inference. */
 gi_status gi_mlp_prepare(const gi_mlp *mlp, void *stream);
 
 /* Cache output C(y, n) for n points: pos4, nrm4 are float4 planes (xyz used),
@@ -343,7 +350,8 @@ gi_status gi_mlp_grad(const gi_mlp *mlp, uint32_t n, const float *pos4, const fl
                       uint64_t workspace_bytes, void *stream);
 
 /* One Adam step (beta 0.9, 0.99, eps 1e-8, bias-corrected with step t >= 1)
- * on the master parameters with gradient grad, then gi_mlp_prepare.  Updates
+ * on the master parameters with gradient grad; when `ema` is set, ema =
+ * ema_decay * ema + (1 - ema_decay) * params afterwards; then gi_mlp_prepare.  Updates
  * state: STEPS = t, EMA_ERR (0.9 old + 0.1 BATCH_ERR, or BATCH_ERR at t = 1)
  * and USABLE = (t >= warmup_steps && NONFINITE == 0 && EMA_ERR <=
  * max_rel_err && every parameter finite). */

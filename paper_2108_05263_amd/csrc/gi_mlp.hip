@@ -79,19 +79,43 @@ __global__ void __launch_bounds__(256) k_mlp_init(gi_mlp m, uint64_t seed)
     m.params[p] = val;
     m.adam_m[p] = 0.0f;
     m.adam_v[p] = 0.0f;
+    if (m.ema) m.ema[p] = 0.0f;
+}
+
+// the parameters inference uses: the bias-corrected average when present
+struct InferSrc {
+    const float *p;
+    float scale;
+};
+
+__device__ __forceinline__ InferSrc infer_src(const gi_mlp &m)
+{
+    const uint32_t t = m.state[GI_MLP_STATE_STEPS];
+    if (m.ema && t > 0u) return InferSrc{m.ema, 1.0f / (1.0f - powf(m.ema_decay, (float)t))};
+    return InferSrc{m.params, 1.0f};
+}
+
+// FP32 biases after the fragments (one thread per slot)
+__device__ __forceinline__ void write_bias(const gi_mlp &m, const InferSrc &src, int i)
+{
+    const int L = i < 256 ? i >> 6 : 4, u = i < 256 ? (i & 63) : i - 256;
+    const float b = u < kOut[L] ? src.p[kOffB[L] + u] * src.scale : 0.0f;
+    reinterpret_cast<float *>(reinterpret_cast<uint8_t *>(m.weights) + kBiasOff)[i] = b;
 }
 
 // BF16 fragments: element i = (f * 64 + lane) * 8 + v
 __global__ void __launch_bounds__(256) k_mlp_prepare_bf16(gi_mlp m)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
+    const InferSrc src = infer_src(m);
+    if (i < kBiasSlots) write_bias(m, src, i);
     if (i >= kFrags * 64 * 8) return;
     const int f = i >> 9, l = (i >> 3) & 63, v = i & 7;
     const int L = layer_of_frag(f), r = f - kFrag0[L];
     const int t = r / kSteps[L], c = r % kSteps[L];
     const int row = 32 * t + (l & 31), k = frag_column(L, c, l >> 5, v);
     float w = 0.0f;
-    if (row < kOut[L] && k >= 0 && k < kIn[L]) w = m.params[kOffW[L] + row * kIn[L] + k];
+    if (row < kOut[L] && k >= 0 && k < kIn[L]) w = src.p[kOffW[L] + row * kIn[L] + k] * src.scale;
     reinterpret_cast<__bf16 *>(m.weights)[i] = (__bf16)w;
 }
 
@@ -100,8 +124,9 @@ __global__ void __launch_bounds__(256) k_mlp_wscale(gi_mlp m)
 {
     __shared__ float red[256];
     const int L = blockIdx.x, t = threadIdx.x, cnt = kIn[L] * kOut[L];
+    const InferSrc src = infer_src(m);
     float a = 0.0f;
-    for (int i = t; i < cnt; i += 256) a = fmaxf(a, fabsf(m.params[kOffW[L] + i]));
+    for (int i = t; i < cnt; i += 256) a = fmaxf(a, fabsf(src.p[kOffW[L] + i] * src.scale));
     red[t] = a;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -121,13 +146,15 @@ __device__ __forceinline__ uint32_t fp8_byte(float x)
 __global__ void __launch_bounds__(256) k_mlp_prepare_fp8(gi_mlp m)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
+    const InferSrc src = infer_src(m);
+    if (i < kBiasSlots) write_bias(m, src, i);
     if (i >= kFrags * 64 * 8) return;
     const int f = i >> 9, l = (i >> 3) & 63, v = i & 7;
     const int L = layer_of_frag(f), r = f - kFrag0[L];
     const int t = r / kSteps[L], c = r % kSteps[L];
     const int row = 32 * t + (l & 31), k = frag_column(L, c, l >> 5, v);
     float w = 0.0f;
-    if (row < kOut[L] && k >= 0 && k < kIn[L]) w = m.params[kOffW[L] + row * kIn[L] + k] / m.scales[L];
+    if (row < kOut[L] && k >= 0 && k < kIn[L]) w = src.p[kOffW[L] + row * kIn[L] + k] * src.scale / m.scales[L];
     reinterpret_cast<uint8_t *>(m.weights)[i] = (uint8_t)fp8_byte(w);
 }
 
@@ -249,10 +276,11 @@ k_mlp_infer(gi_mlp m, uint32_t n, const float4 *pos,
         smul4 = m.scales[4] * sa[4];
     }
     // biases (accumulator units): layers 0-3 at 64 L, layer 4 at 256 padded to 32 rows
-    __shared__ __attribute__((aligned(16))) float sb[4 * 64 + 32];
-    for (int i = threadIdx.x; i < 4 * 64 + 32; i += kInferBlock) {
-        int L = i < 256 ? i >> 6 : 4, u = i < 256 ? (i & 63) : i - 256;
-        float b = u < kOut[L] ? m.params[kOffB[L] + u] : 0.0f;
+    __shared__ __attribute__((aligned(16))) float sb[kBiasSlots];
+    const float *bias = reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(m.weights) + kBiasOff);
+    for (int i = threadIdx.x; i < kBiasSlots; i += kInferBlock) {
+        const int L = i < 256 ? i >> 6 : 4;
+        float b = bias[i];
         if (P == GI_MLP_FP8) {
             float sa = m.scales[5 + L];
             if (!(sa > 0.0f && sa < kInf)) sa = 1.0f;
@@ -642,7 +670,9 @@ __global__ void __launch_bounds__(256) k_mlp_adam(gi_mlp m, const float *grad, f
     const float vv = 0.99f * m.adam_v[p] + 0.01f * g * g;
     m.adam_m[p] = mm;
     m.adam_v[p] = vv;
-    m.params[p] -= lr * (mm * c1) / (sqrtf(vv * c2) + 1e-8f);
+    const float np = m.params[p] - lr * (mm * c1) / (sqrtf(vv * c2) + 1e-8f);
+    m.params[p] = np;
+    if (m.ema) m.ema[p] = m.ema_decay * m.ema[p] + (1.0f - m.ema_decay) * np;
 }
 
 // usability after step t (one workgroup)
@@ -734,6 +764,7 @@ gi_status check_mlp(const gi_mlp *m)
     for (int a = 0; a < 3; ++a)
         if (!(m->pos_hi[a] > m->pos_lo[a])) return GI_ERR_PARAM;
     if (!(m->max_rel_err > 0.0f)) return GI_ERR_PARAM;
+    if (!(m->ema_decay >= 0.0f && m->ema_decay < 1.0f)) return GI_ERR_PARAM;
     return GI_OK;
 }
 

@@ -25,7 +25,10 @@ constexpr int kTiles[kLayers] = {2, 2, 2, 2, 1};
 constexpr int kSteps[kLayers] = {5, 4, 4, 4, 4};
 constexpr int kFrag0[kLayers] = {0, 10, 18, 26, 34};
 constexpr int kFrags = 38;
-static_assert(kFrags * 64 * 16 == GI_MLP_WEIGHT_BYTES, "fragment bytes");
+// after the fragments: FP32 biases, layers 0-3 at 64 L, layer 4 at 256 (32 rows, 3 used)
+constexpr int kBiasOff = kFrags * 64 * 16;
+constexpr int kBiasSlots = 4 * 64 + 32;
+static_assert(kBiasOff + kBiasSlots * 4 == GI_MLP_WEIGHT_BYTES, "weight buffer bytes");
 
 // The encoded input is split between the two half-waves: lanes 0-31 hold
 // the 39 features of the three position values, lanes 32-63 those of the

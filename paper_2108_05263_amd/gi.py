@@ -32,7 +32,7 @@ EXPORTS = ["gi_status_string", "gi_device", "gi_trace_gbuffer", "gi_probe_update
            "gi_resample_initial_mlp", "gi_shade_mlp_workspace_bytes", "gi_shade_mlp", "gi_path_trace"]
 
 MLP_N_PARAMS = 17731
-MLP_WEIGHT_BYTES = 38912
+MLP_WEIGHT_BYTES = 40064
 MLP_MAX_BATCH = 1 << 20
 MLP_PRECISION = {"bf16": 0, "fp8": 1}
 MLP_MODE = {"auto": 0, "always": 1, "never": 2}
@@ -92,9 +92,10 @@ class GiProbeParams(C.Structure):
 
 class GiMlp(C.Structure):
     _fields_ = [("params", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p),
-                ("weights", C.c_void_p), ("scales", C.c_void_p), ("state", C.c_void_p), ("pos_lo", F3),
-                ("pos_hi", F3), ("precision", C.c_uint32), ("mode", C.c_uint32),
-                ("warmup_steps", C.c_uint32), ("max_rel_err", C.c_float)]
+                ("ema", C.c_void_p), ("weights", C.c_void_p), ("scales", C.c_void_p), ("state", C.c_void_p),
+                ("pos_lo", F3), ("pos_hi", F3), ("precision", C.c_uint32), ("mode", C.c_uint32),
+                ("warmup_steps", C.c_uint32), ("max_rel_err", C.c_float), ("ema_decay", C.c_float),
+                ("pad", C.c_uint32)]
 
 
 _P = C.c_void_p
@@ -468,7 +469,7 @@ class Mlp:
     moments, inference operands, FP8 scales and the usability state words."""
 
     def __init__(self, lo, hi, precision="bf16", mode="auto", warmup_steps=16, max_rel_err=0.5,
-                 device="cuda"):
+                 ema_decay=None, device="cuda"):
         f32 = dict(dtype=torch.float32, device=device)
         self.params = torch.zeros(MLP_N_PARAMS, **f32)
         self.adam_m = torch.zeros(MLP_N_PARAMS, **f32)
@@ -476,10 +477,13 @@ class Mlp:
         self.weights = torch.zeros(MLP_WEIGHT_BYTES, dtype=torch.uint8, device=device)
         self.scales = torch.ones(16, **f32)
         self.state = torch.zeros(16, dtype=torch.int32, device=device)
+        self.ema = torch.zeros(MLP_N_PARAMS, **f32) if ema_decay is not None else None
         self.step = 0
         m = GiMlp()
         m.params, m.adam_m, m.adam_v = self.params.data_ptr(), self.adam_m.data_ptr(), self.adam_v.data_ptr()
         m.weights, m.scales, m.state = self.weights.data_ptr(), self.scales.data_ptr(), self.state.data_ptr()
+        m.ema = self.ema.data_ptr() if self.ema is not None else None
+        m.ema_decay = float(ema_decay or 0.0)
         m.pos_lo, m.pos_hi = _f3(lo), _f3(hi)
         m.precision = MLP_PRECISION[precision]
         m.mode = MLP_MODE[mode]
@@ -608,7 +612,8 @@ class Renderer:
 
     def __init__(self, cfg: sg.Config, seed: int = 1, width=None, height=None, use_grid=True,
                  device="cuda", scene=None, params=None, lds=True, mlp=None, mlp_mode="auto",
-                 mlp_batch=1 << 16, mlp_steps=4, mlp_lr=1e-2, mlp_warmup=16, mlp_seed=7, train=True):
+                 mlp_batch=1 << 16, mlp_steps=4, mlp_lr=1e-2, mlp_warmup=16, mlp_seed=7, mlp_ema=0.99,
+                 train=True):
         self.cfg = cfg
         self.seed = seed
         self.W, self.H = int(width or cfg.width), int(height or cfg.height)
@@ -627,11 +632,13 @@ class Renderer:
         self.frame_index = 0
         # learned cache (mlp = 'bf16' or 'fp8'): the target of the initial pass
         # and of shading; trained after every frame on the frame's candidates,
-        # mlp_steps Adam steps of mlp_batch/mlp_steps samples
+        # mlp_steps Adam steps of mlp_batch/mlp_steps samples; inference uses
+        # the average of the parameters (decay mlp_ema; None: the parameters)
         self.mlp = None
         if mlp is not None:
             lo, hi = self.scene.bounds()
-            self.mlp = Mlp(lo, hi, precision=mlp, mode=mlp_mode, warmup_steps=mlp_warmup, device=device)
+            self.mlp = Mlp(lo, hi, precision=mlp, mode=mlp_mode, warmup_steps=mlp_warmup, ema_decay=mlp_ema,
+                           device=device)
             self.mlp.init(mlp_seed)
             self.train = train
             self.mlp_steps, self.mlp_lr = int(mlp_steps), float(mlp_lr)

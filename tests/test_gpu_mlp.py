@@ -359,3 +359,29 @@ def test_training_lowers_heldout_loss(gi):
     untrained_loss = r.mlp.state_words()["loss"]
     log(f"held-out loss: untrained {untrained_loss:.4f} trained {trained_loss:.4f}")
     assert trained_loss < 0.25 * untrained_loss
+
+
+def test_parameter_average_for_inference(gi):
+    """With a parameter average, two Adam steps leave ema_t = d ema_{t-1} +
+    (1 - d) p_t (from 0), and inference uses ema_t / (1 - d^t)."""
+    rng = np.random.default_rng(70)
+    params = _params(71)
+    d = 0.9
+    m = gi.Mlp(BOX_LO, BOX_HI, precision="bf16", mode="always", ema_decay=d)
+    m.load_params(params)
+    p, mm, vv = params.copy(), np.zeros(M.N_PARAMS), np.zeros(M.N_PARAMS)
+    ema = np.zeros(M.N_PARAMS)
+    for t in (1, 2):
+        g = rng.normal(0, 1e-2, M.N_PARAMS).astype(np.float32).astype(np.float64)
+        gi.mlp_adam(m, torch.from_numpy(g.astype(np.float32)).cuda(), t, 1e-2)
+        p, mm, vv = M.adam_step(p, mm, vv, g, t)
+        ema = d * ema + (1 - d) * p
+    assert np.allclose(m.ema.cpu().numpy(), ema, rtol=1e-5, atol=1e-7)
+    avg = ema / (1 - d ** 2)
+    pos, nrm = _points(2000, 72)
+    out = gi.mlp_infer(m, _f4(pos), _f4(nrm)).cpu().numpy()[:, :3]
+    X = M.encode(pos.astype(np.float64), nrm.astype(np.float64), BOX_LO, BOX_HI)
+    ref, _ = M.forward(avg.astype(np.float32).astype(np.float64), X, prec="bf16")
+    mean, p99, mx = _err_stats(out, ref)
+    log(f"averaged parameters: mean {mean:.2e} max {mx:.2e}")
+    assert mean <= 2e-4 and mx <= 3e-2
