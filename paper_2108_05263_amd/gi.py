@@ -254,10 +254,12 @@ class GBuffer:
         rec[:, 13] = npm[:, 3].view(np.uint32)
         return rec
 
-    def load_records(self, rec):
-        """Fill from (W*H, 14) oracle-layout records (rounded to float32)."""
+    def load_records(self, rec, pixels=None):
+        """Fill from (W*H, 14) oracle-layout records (rounded to float32); with
+        `pixels`, rec holds one record per listed pixel and only those rows
+        are written."""
         rec = np.asarray(rec, np.float64)
-        n = self.W * self.H
+        n = len(rec) if pixels is not None else self.W * self.H
         pd = np.zeros((n, 4), np.float32)
         npm = np.zeros((n, 4), np.float32)
         al = np.zeros((n, 4), np.float32)
@@ -266,8 +268,12 @@ class GBuffer:
         npm[:, 0:3] = rec[:, 3:6]
         npm.view(np.uint32)[:, 3] = rec[:, 13].astype(np.uint64).astype(np.uint32)
         al[:, 0:3], em[:, 0:3] = rec[:, 6:9], rec[:, 9:12]
+        idx = None if pixels is None else torch.as_tensor(np.asarray(pixels, np.int64), device=self.pos_depth.device)
         for t, a in ((self.pos_depth, pd), (self.nrm_prim, npm), (self.albedo, al), (self.emit, em)):
-            t.copy_(torch.from_numpy(a))
+            if idx is None:
+                t.copy_(torch.from_numpy(a))
+            else:
+                t[idx] = torch.from_numpy(a).to(t.device)
 
 
 class Reservoirs:
@@ -299,9 +305,10 @@ class Reservoirs:
         rec[:, 12], rec[:, 13] = d[:, 0], d[:, 1]
         return rec
 
-    def load_records(self, rec):
+    def load_records(self, rec, pixels=None):
+        """Fill from oracle-layout records; with `pixels`, only those rows."""
         rec = np.asarray(rec, np.float64)
-        n = self.W * self.H
+        n = len(rec) if pixels is not None else self.W * self.H
         a = np.zeros((n, 4), np.float32)
         b = np.zeros((n, 4), np.float32)
         c = np.zeros((n, 4), np.float32)
@@ -311,9 +318,12 @@ class Reservoirs:
         c[:, 0:3] = rec[:, 6:9]
         c.view(np.uint32)[:, 3] = rec[:, 11].astype(np.uint32)
         d[:, 0], d[:, 1] = rec[:, 12].astype(np.uint64), rec[:, 13].astype(np.uint64)
-        for t, arr in ((self.y_W, a), (self.n_wsum, b), (self.L_M, c)):
-            t.copy_(torch.from_numpy(arr))
-        self.tag_prim.copy_(torch.from_numpy(d.view(np.int32)))
+        idx = None if pixels is None else torch.as_tensor(np.asarray(pixels, np.int64), device=self.y_W.device)
+        for t, arr in ((self.y_W, a), (self.n_wsum, b), (self.L_M, c), (self.tag_prim, d.view(np.int32))):
+            if idx is None:
+                t.copy_(torch.from_numpy(arr))
+            else:
+                t[idx] = torch.from_numpy(arr).to(t.device)
 
 
 def tiles_to_quads(tiles, N):

@@ -279,6 +279,23 @@ def empty_probe_textures(grid: ProbeGrid):
     return irr, dep
 
 
+def random_probe_textures(grid: ProbeGrid, seed: int):
+    """Seeded stand-in probe textures for parity tests at full size (both
+    sides read the same arrays): irradiance texels U[0, 2), depth means
+    U[0.05, d_max) with second moments mean^2 + U[0, 0.05) spacing^2.
+    Plain random numbers, gutters included."""
+    rng = np.random.default_rng(seed)
+    P = grid.count
+    irr = np.zeros((P, (grid.irr_res + 2) ** 2, 4), np.float32)
+    irr[..., :3] = rng.uniform(0.0, 2.0, (P, (grid.irr_res + 2) ** 2, 3))
+    dep = np.zeros((P, (grid.dep_res + 2) ** 2, 2), np.float32)
+    m = rng.uniform(0.05, grid.d_max, (P, (grid.dep_res + 2) ** 2))
+    s = float(min(grid.spacing))
+    dep[..., 0] = m
+    dep[..., 1] = m * m + rng.uniform(0.0, 0.05, m.shape) * s * s
+    return irr, dep
+
+
 # --------------------------------------------------------------------------
 # closed-form test scenes
 # --------------------------------------------------------------------------
