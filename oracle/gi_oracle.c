@@ -70,7 +70,7 @@ typedef struct {
     int32_t M;                      /* candidates per pixel */
     int32_t k;                      /* spatial neighbours */
     int32_t unbiased;               /* 1: 1/Z with visibility; 0: 1/M */
-    int32_t pad;
+    int32_t M_light;                /* emitter-sampled candidates per pixel */
     double radius;                  /* spatial radius in pixels */
     double g_max;                   /* geometry-term bound */
     double cos_n;                   /* reuse normal threshold */
@@ -730,11 +730,46 @@ static int similar(const double *g, const double *gq, const o_params *pp)
  * auxiliary BSDF sample of Sec. 3.5, Eq. 9).
  * Replacement rule: candidate i replaces the current sample iff
  * u_2 * wsum < w_i after wsum has been increased by w_i.
+ * Emitter samples (Sec. 3.1 step 1 draws candidates from the BSDF and from
+ * the emitters; Fig. 2 selects them in proportion to L_e + L_DDGI): M_light
+ * more candidates i = M .. M+M_light-1, each a point uniform in the area of
+ * an emissive sphere chosen uniformly (u0 the sphere, u1, u2 the point, u3
+ * the reservoir decision).  With both techniques every candidate's weight is
+ * p_hat over the balance-heuristic mixture density (M p_bsdf + M_light
+ * p_light) / (M + M_light) in area measure, and the reservoir counts all
+ * M + M_light candidates; with M_light = 0 this is the weight above.  The
+ * density of cosine sampling is taken without visibility: a light sample
+ * that x cannot see has zero contribution, so its weight does not matter.
  * ------------------------------------------------------------------------- */
+/* Emitters for light sampling: the emissive spheres, in index order. */
+static int emitter_list(const o_scene *sc, int32_t *out, int cap)
+{
+    int n = 0;
+    for (int32_t i = 0; i < sc->n_prims; ++i) {
+        const double *rec = sc->prims + 16 * i;
+        if ((int)rec[3] == 0 && (rec[12] > 0.0 || rec[13] > 0.0 || rec[14] > 0.0) && n < cap) out[n++] = i;
+    }
+    return n;
+}
+
+/* area-measure density of the emitter technique at a point of primitive prim */
+static double light_pdf(const o_scene *sc, const int32_t *em, int n_em, uint32_t prim)
+{
+    for (int e = 0; e < n_em; ++e)
+        if ((uint32_t)em[e] == prim) {
+            double r = sc->prims[16 * em[e] + 4];
+            return 1.0 / ((double)n_em * 4.0 * O_PI * r * r);
+        }
+    return 0.0;
+}
+
 void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *gb, const o_probes *pr,
                         const o_params *pp, uint64_t seed, uint32_t frame, const int32_t *pix,
                         int64_t npix, double *res, double *resid)
 {
+    int32_t em[256];
+    const int n_em = pp->M_light > 0 ? emitter_list(sc, em, 256) : 0;
+    const int Mb = pp->M, Ml = pp->M_light, Mt = Mb + Ml;
     int64_t n = pix ? npix : (int64_t)W * H;
     for (int64_t q = 0; q < n; ++q) {
         int64_t p = pix ? pix[q] : q;
@@ -748,16 +783,36 @@ void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *g
         double wsum = 0.0, p_sel = 0.0;
         int have = 0;
         res_empty(r, 0.0);
-        for (int i = 0; i < pp->M; ++i) {
+        for (int i = 0; i < Mt; ++i) {
             double u[4], w[3];
             rand4(seed, (uint32_t)p, frame, PASS_INITIAL, (uint32_t)i, u);
-            o_cosine_dir(nx, u[0], u[1], w);
-            o_hit h;
             double y[3], ny[3] = {0, 0, 0}, L[3], phat = 0.0, wi = 0.0;
             uint32_t prim = O_MISS;
-            if (closest_hit(sc, o, w, O_INF, &h)) {
-                for (int a = 0; a < 3; ++a) { y[a] = o[a] + h.t * w[a]; ny[a] = h.n[a]; }
-                prim = h.prim;
+            int surface = 0;
+            double u_dec = u[2];
+            if (i < Mb) {
+                /* BSDF (cosine) candidate: the first surface along the ray */
+                o_cosine_dir(nx, u[0], u[1], w);
+                o_hit h;
+                if (closest_hit(sc, o, w, O_INF, &h)) {
+                    for (int a = 0; a < 3; ++a) { y[a] = o[a] + h.t * w[a]; ny[a] = h.n[a]; }
+                    prim = h.prim;
+                    surface = 1;
+                }
+            } else {
+                /* emitter candidate: an emitter chosen uniformly, a point uniform in its area */
+                u_dec = u[3];
+                if (n_em > 0) {
+                    int e = (int)floor(u[0] * (double)n_em);
+                    const double *rec = sc->prims + 16 * em[e];
+                    double d[3];
+                    o_sphere_dir(u[1], u[2], d);
+                    for (int a = 0; a < 3; ++a) { y[a] = rec[a] + rec[4] * d[a]; ny[a] = d[a]; }
+                    prim = (uint32_t)em[e];
+                    surface = 1;
+                }
+            }
+            if (surface) {
                 double v[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
                 double d2 = dot3(v, v), d = sqrt(d2);
                 double wv[3] = {v[0] / d, v[1] / d, v[2] / d};
@@ -767,22 +822,25 @@ void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *g
                     double G = cx * cy / d2;
                     double f[3] = {rho[0] / O_PI * L[0], rho[1] / O_PI * L[1], rho[2] / O_PI * L[2]};
                     phat = lum(f) * fmin(G, pp->g_max);
+                    /* balance heuristic: p_hat over the candidates' mixture density
+                     * (Mb p_bsdf + Ml p_light) / Mt, area measure */
                     double pA = cx / O_PI * cy / d2;
-                    wi = phat / pA;
+                    if (Ml == 0) wi = phat / pA;
+                    else wi = phat * Mt / (Mb * pA + Ml * light_pdf(sc, em, n_em, prim));
                     if (i == 0 && G > pp->g_max)
                         for (int a = 0; a < 3; ++a) rs[a] = rho[a] * L[a] * (1.0 - pp->g_max / G);
                 }
-            } else {
+            } else if (i < Mb) {
                 for (int a = 0; a < 3; ++a) { y[a] = w[a]; L[a] = sc->sky[a]; }
                 double cx = dot3(nx, w);
                 if (cx > 0.0) {
                     double f[3] = {rho[0] / O_PI * L[0], rho[1] / O_PI * L[1], rho[2] / O_PI * L[2]};
                     phat = lum(f) * cx;
-                    wi = phat / (cx / O_PI);
+                    wi = phat / (cx / O_PI) * ((double)Mt / Mb);
                 }
             }
             wsum += wi;
-            if (u[2] * wsum < wi) {
+            if (u_dec * wsum < wi) {
                 have = 1;
                 p_sel = phat;
                 for (int a = 0; a < 3; ++a) { r[R_Y + a] = y[a]; r[R_NY + a] = ny[a]; r[R_L + a] = L[a]; }
@@ -791,8 +849,8 @@ void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *g
             }
         }
         r[R_WSUM] = wsum;
-        r[R_M] = (double)pp->M;
-        r[R_W] = (have && p_sel > 0.0) ? wsum / (pp->M * p_sel) : 0.0;
+        r[R_M] = (double)Mt;
+        r[R_W] = (have && p_sel > 0.0) ? wsum / (Mt * p_sel) : 0.0;
     }
 }
 

@@ -55,7 +55,7 @@ class OProbes(C.Structure):
 
 
 class OParams(C.Structure):
-    _fields_ = [("M", C.c_int32), ("k", C.c_int32), ("unbiased", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("M", C.c_int32), ("k", C.c_int32), ("unbiased", C.c_int32), ("M_light", C.c_int32),
                 ("radius", C.c_double), ("g_max", C.c_double), ("cos_n", C.c_double),
                 ("depth_rel", C.c_double), ("m_cap", C.c_double)]
 
@@ -187,6 +187,7 @@ class _Probes:
 def _params(pr) -> OParams:
     o = OParams()
     o.M, o.k, o.unbiased = int(pr.M), int(pr.k), int(pr.unbiased)
+    o.M_light = int(getattr(pr, "M_light", 0))
     o.radius = float(np.float32(pr.radius))
     o.g_max = float(np.float32(pr.g_max))
     o.cos_n = float(np.float32(pr.cos_n))

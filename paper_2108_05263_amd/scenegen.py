@@ -111,6 +111,7 @@ class Params:
     m_cap: int = 20                   # temporal history cap, multiple of the current M
     unbiased: int = 1                 # 1: 1/Z normalisation with visibility, 0: 1/M
     temporal: bool = True
+    M_light: int = 0                  # emitter-sampled candidates per pixel (M + M_light <= 32)
 
 
 @dataclasses.dataclass

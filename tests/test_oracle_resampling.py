@@ -22,6 +22,7 @@ from scipy import stats
 
 import oracle as o
 from paper_2108_05263_amd import scenegen as g
+from paper_2108_05263_amd import scenegen as sg
 
 
 def _params(**kw):
@@ -195,3 +196,65 @@ def test_mape_hand_values():
     r = np.array([1.0, 0.01, 1.0, 0.99])
     expect = (0.0 + 0.01 / 0.02 + 1.0 / 1.01 + 0.49 / 1.0) / 4
     assert o.mape(v, r) == pytest.approx(expect, rel=1e-14)
+
+
+def _sphere_over_plane():
+    """A Lambertian plane (top face y = 0) under a black sky, lit only by an
+    emissive sphere wholly above it; a camera looking down at the plane."""
+    rho = np.array([0.6, 0.5, 0.4], np.float32)
+    Le = np.array([[30.0, 20.0, 10.0], [200.0, 300.0, 400.0]], np.float32)
+    r = np.array([0.8, 1.5])
+    c = np.array([[0.3, 2.4, 0.8], [25.0, 3.0, 0.8]])
+    # the far sphere stays above the horizon and out of the near one's shadow
+    # for every plane point the camera sees
+    prims = sg.prim_records([sg.PRIM_BOX, sg.PRIM_SPHERE, sg.PRIM_SPHERE], [[0.0, -1.0, 0.0], c[0], c[1]],
+                            [[50.0, 1.0, 50.0], [r[0], 0, 0], [r[1], 0, 0]], [rho, [0, 0, 0], [0, 0, 0]],
+                            [[0, 0, 0], Le[0], Le[1]])
+    sc = sg.Scene(prims=prims, has_room=False, room_lo=np.zeros(3, np.float32), room_hi=np.zeros(3, np.float32),
+                  wall_albedo=np.zeros(3, np.float32), sky=np.zeros(3, np.float32), eps=float(np.float32(1e-3)))
+    eye, look = np.array([0.3, 3.0, -2.5]), np.array([0.3, 0.0, 1.0])
+    f = (look - eye) / np.linalg.norm(look - eye)
+    rt = np.cross(f, [0.0, 1.0, 0.0])
+    rt /= np.linalg.norm(rt)
+    cam = sg.Camera(eye=eye.astype(np.float32), fwd=f.astype(np.float32), right=rt.astype(np.float32),
+                    up=np.cross(rt, f).astype(np.float32),
+                    tan_half_fovy=float(np.float32(math.tan(math.radians(25.0)))), width=12, height=10)
+    return sc, cam, rho.astype(np.float64), Le.astype(np.float64), r, c
+
+
+def test_emitter_candidates_unbiased_closed_form():
+    """Emitter-sampled candidates with balance-heuristic weights: a sphere of
+    radiance L_e and radius r wholly above a plane gives irradiance
+    pi L_e (r/d)^2 cos(theta) (a classic closed form), so each plane pixel
+    converges to rho sum_e L_e (r_e/d_e)^2 cos(theta_e) for two unoccluded
+    emissive spheres.  Per-pixel z-test over seeds; the emitter candidates
+    must also cut the variance."""
+    sc, cam, rho, Le, r, c = _sphere_over_plane()
+    W, H = cam.width, cam.height
+    gb = o.gbuffer(sc, cam)
+    grid = sg.probe_grid((2, 2, 2), (-8.0, -1.0, -8.0), 8.0)
+    irr, dep = sg.empty_probe_textures(grid)
+    plane = (gb[:, 13] == 0) & (np.abs(gb[:, 4] - 1.0) < 1e-12)
+    assert plane.sum() > 60
+    x = gb[plane, 0:3]
+    exact = np.zeros((len(x), 3))
+    for e in range(2):
+        v = c[e] - x
+        d = np.linalg.norm(v, axis=1)
+        exact += rho[None, :] * Le[e][None, :] * ((r[e] / d) ** 2 * (v[:, 1] / d))[:, None]
+    S = 300
+    var = {}
+    for M, ml in ((4, 0), (4, 4), (2, 8)):
+        pr = sg.Params(M=M, M_light=ml, k=0, n_spatial=0, temporal=False)
+        vals = np.zeros((S, int(plane.sum()), 3))
+        for s in range(S):
+            res, resid = o.resample_initial(sc, W, H, gb, grid, irr, dep, pr, 1000 + s, 0)
+            vals[s] = o.shade(sc, W, H, gb, grid, irr, dep, res, resid, pr)[plane]
+        mean, sd = vals.mean(0), vals.std(0, ddof=1)
+        var[ml] = float((sd ** 2).mean())
+        if ml == 0:
+            continue    # cosine candidates alone almost never reach the far sphere: no z-test
+        z = (mean - exact) / (sd / math.sqrt(S) + 1e-12)
+        # Bonferroni over the plane pixels and channels at family-wise 1e-3
+        assert np.abs(z).max() < 5.0, (M, ml, np.abs(z).max())
+    assert var[4] < 0.5 * var[0], var
