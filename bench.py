@@ -361,7 +361,8 @@ def main():
     achieved = bytes_launch / (avg[dom] * 1e-3) / 1e9
     path_bytes = sum(ALGO_BYTES[k if not k.startswith("spatial") else "spatial"] for k in names) * npx
     line = {
-        "metric": "resampled pixels/s (1080p, M=32, 2xk=5)",
+        "metric": ("resampled pixels/s (1080p, M=32, 2xk=5)" if (W, H) == (1920, 1080) else
+                   f"resampled pixels/s ({W}x{H}, M={cfg.params.M}, {cfg.params.n_spatial}xk={cfg.params.k})"),
         "value": npx * args.steps / elapsed,
         "unit": "pixels/s",
         "n_gpus": 1,

@@ -83,7 +83,11 @@ typedef struct gi_scene {
     const uint32_t *cell_items;
     uint32_t n_items;                /* entries of cell_items (= cell_start[last]) */
     uint32_t options;                /* GI_OPT_* bits */
+    uint32_t n_emitters;             /* emissive spheres light sampling draws from, <= GI_MAX_EMITTERS */
+    uint32_t emitters[32];           /* their primitive ids (each a sphere with emission) */
 } gi_scene;
+
+#define GI_MAX_EMITTERS 32u
 
 #define GI_OPT_NO_LDS 1u             /* trace from global memory even when the scene fits LDS */
 
@@ -155,6 +159,7 @@ typedef struct gi_params {
     float depth_rel;     /* reuse relative depth threshold */
     float m_cap;         /* temporal history cap, multiple of the current M */
     uint32_t unbiased;   /* 1: visibility-tested 1/Z normalisation, 0: 1/M */
+    uint32_t M_light;    /* emitter-sampled candidates per pixel; M + M_light <= GI_MAX_M */
 } gi_params;
 
 /* Probe-update parameters. */
@@ -198,9 +203,15 @@ gi_status gi_probe_query(const gi_probes *probes, uint32_t n, const float *p, co
  * traced, its radiance L(y_i) = L_e + rho Q(view-path-biased y_i, n_y)
  * evaluated, weighted w = p_hat/p_A with p_hat = lum(rho_x/pi L) min(G, g_max)
  * and streamed through a weighted reservoir (replace iff u*wsum < w); W =
- * wsum/(M p_hat(y)).  resid (float4 plane, rgb used) receives the residual
- * transport rho_x L(y_0) max(0, 1 - g_max/G_0) of candidate 0 (Eq. 9).
- * Pixels that miss or have zero albedo get an empty reservoir with M = 0. */
+ * wsum/(M p_hat(y)).  With M_light > 0 (Sec. 3.1 step 1 samples the emitters
+ * too), candidates i = M .. M+M_light-1 are points uniform in the area of an
+ * emitter chosen uniformly from scene->emitters (u0 the emitter, u1, u2 the
+ * point, u3 the decision); every candidate's weight is then p_hat over the
+ * balance-heuristic mixture density (M p_A + M_light p_light)/(M + M_light)
+ * and M + M_light candidates are counted.  resid (float4 plane, rgb used)
+ * receives the residual transport rho_x L(y_0) max(0, 1 - g_max/G_0) of
+ * candidate 0 (Eq. 9).  Pixels that miss or have zero albedo get an empty
+ * reservoir with M = 0. */
 gi_status gi_resample_initial(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes,
                               const gi_params *params, gi_reservoirs *out, float *resid,
                               uint64_t seed, uint32_t frame, void *stream);

@@ -94,6 +94,18 @@ __device__ __forceinline__ float res_target(const GB &g, const Res &r, float g_m
     return target(g.pos, g.n, g.alb, r.y, r.n, r.L, g_max);
 }
 
+// area density of emitter sampling at a point of primitive prim: 1/(n 4 pi r^2)
+// on a listed emitter, else 0
+__device__ __forceinline__ float light_pdf(const gi_scene &sc, uint32_t prim)
+{
+    for (uint32_t e = 0; e < sc.n_emitters; ++e)
+        if (sc.emitters[e] == prim) {
+            const float rad = reinterpret_cast<const float4 *>(sc.prims)[4 * prim + 1].x;
+            return rcp((float)sc.n_emitters * 4.0f * kPi * rad * rad);
+        }
+    return 0.0f;
+}
+
 // --------------------------------------------------------------------------
 // primary vertices
 // --------------------------------------------------------------------------
@@ -329,7 +341,9 @@ __global__ void __launch_bounds__(kBlock)
 // probes.  WS = true: takes the candidates from the planes k_cand wrote and,
 // when the cache is selected, their cache values; otherwise the probe query
 // of the same candidates, through the same arithmetic as WS = false.
-template <bool LDS, bool WS>
+// LIGHT: emitter candidates present (M_light > 0); without them the loop
+// compiles to the plain cosine-candidate form.
+template <bool LDS, bool WS, bool LIGHT>
 __global__ void __launch_bounds__(kBlock)
     k_initial(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_params pp, gi_reservoirs out, float4 *resid,
               uint64_t seed, uint32_t frame, CandWs ws, gi_mlp mlp)
@@ -352,17 +366,33 @@ __global__ void __launch_bounds__(kBlock)
     const V3 rho_pi = kInvPi * g.alb;
     const bool use_cache = WS && mlp_selected(mlp);
     const size_t npx = (size_t)gb.width * gb.height;
-    Res r = empty_res(pp.M);
+    const uint32_t Mt = LIGHT ? pp.M + pp.M_light : pp.M;
+    // balance heuristic: weights divide by the mixture density (M p_A + M_light p_light) / Mt
+    const float mixb = (float)pp.M / (float)Mt, mixl = (float)pp.M_light / (float)Mt;
+    Res r = empty_res(Mt);
     float wsum = 0.0f, p_sel = 0.0f;
     bool have = false;
-    for (uint32_t i = 0; i < pp.M; ++i) {
+    for (uint32_t i = 0; i < Mt; ++i) {
         uint4 rn = philox(seed, p, frame, kPassInitial, i);
         float u2 = u01(rn.z);
         V3 w, y, ny = v3(0.0f, 0.0f, 0.0f), L = v3(0.0f, 0.0f, 0.0f);
         float phat = 0.0f, wi = 0.0f;
         uint32_t prim = GI_MISS;
         bool hit;
-        if constexpr (WS) {
+        if (LIGHT && i >= pp.M) {
+            // emitter candidate: a point uniform in the area of a uniformly chosen emitter
+            u2 = u01(rn.w);
+            hit = sc.n_emitters > 0u;
+            if (hit) {
+                const uint32_t e = min((uint32_t)(u01(rn.x) * (float)sc.n_emitters), sc.n_emitters - 1u);
+                prim = sc.emitters[e];
+                const float4 c = reinterpret_cast<const float4 *>(sc.prims)[4 * prim];
+                const float rad = reinterpret_cast<const float4 *>(sc.prims)[4 * prim + 1].x;
+                const V3 d = sphere_dir(u01(rn.y), u01(rn.z));
+                y = madd(xyz(c), rad, d);
+                ny = d;
+            }
+        } else if constexpr (WS) {
             const float4 a = ws.pos[i * npx + p];
             w = xyz(a);
             hit = __float_as_uint(a.w) != GI_MISS;
@@ -387,22 +417,26 @@ __global__ void __launch_bounds__(kBlock)
             V3 wv = frsq(d2) * v;
             float cx = dot(g.n, wv), cy = -dot(ny, wv);
             if (cx > 0.0f && cy > 0.0f) {
-                L = use_cache ? radiance_cached(sc, prim, ws.q[i * npx + p])
-                              : radiance_toward(sc, pr, prim, y, ny, g.pos);
+                L = (use_cache && i < pp.M) ? radiance_cached(sc, prim, ws.q[i * npx + p])
+                                            : radiance_toward(sc, pr, prim, y, ny, g.pos);
                 float G = cx * cy * rcp(d2);
                 float fl = lum(rho_pi * L);
                 float iG = rcp(G);
                 phat = fl * fminf(G, pp.g_max);
-                wi = kPi * phat * iG;   // p_hat / p_A with p_A = G / pi
+                if (!LIGHT)
+                    wi = kPi * phat * iG;   // p_hat / p_A with p_A = G / pi
+                else
+                    wi = phat * rcp(mixb * kInvPi * G + mixl * light_pdf(sc, prim));
                 if (i == 0 && G > pp.g_max) rs = (1.0f - pp.g_max * iG) * (g.alb * L);
             }
-        } else {
+        } else if (!LIGHT || i < pp.M) {
             y = w;
             L = ld3(sc.sky);
             float cx = dot(g.n, w);
             if (cx > 0.0f) {
                 phat = lum(rho_pi * L) * cx;
                 wi = kPi * phat * rcp(cx);
+                if (LIGHT) wi *= rcp(mixb);
             }
         }
         wsum += wi;
@@ -417,7 +451,7 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
     r.wsum = wsum;
-    r.W = (have && p_sel > 0.0f) ? wsum * rcp((float)pp.M * p_sel) : 0.0f;
+    r.W = (have && p_sel > 0.0f) ? wsum * rcp((float)Mt * p_sel) : 0.0f;
     store_res(out, p, r);
     resid[p] = make_float4(rs.x, rs.y, rs.z, 0.0f);
 }
@@ -779,6 +813,9 @@ gi_status check_scene(const gi_scene *sc)
 {
     if (!sc) return GI_ERR_NULL;
     if (sc->n_prims > 0 && !sc->prims) return GI_ERR_NULL;
+    if (sc->n_emitters > GI_MAX_EMITTERS) return GI_ERR_SHAPE;
+    for (uint32_t e = 0; e < sc->n_emitters; ++e)
+        if (sc->emitters[e] >= sc->n_prims) return GI_ERR_PARAM;
     if (!(sc->eps >= 0.0f)) return GI_ERR_PARAM;
     if (sc->cell_start) {
         if (!sc->cell_items && sc->n_items) return GI_ERR_NULL;
@@ -829,6 +866,7 @@ gi_status check_params(const gi_params *pp)
 {
     if (!pp) return GI_ERR_NULL;
     if (pp->M < 1 || pp->M > GI_MAX_M || pp->k > GI_MAX_K) return GI_ERR_PARAM;
+    if (pp->M_light > GI_MAX_M - pp->M) return GI_ERR_PARAM;
     if (!(pp->radius >= 0.0f) || !(pp->g_max > 0.0f) || !(pp->m_cap >= 0.0f) || !(pp->depth_rel >= 0.0f))
         return GI_ERR_PARAM;
     return GI_OK;
@@ -855,6 +893,19 @@ uint32_t scene_lds(const gi_scene *sc, uint32_t static_lds = 0)
         if (lds) kernel<true><<<(grid), (block), (lds), (stream)>>>(__VA_ARGS__);             \
         else kernel<false><<<(grid), (block), 0, (stream)>>>(__VA_ARGS__);                   \
     } while (0)
+// k_initial with the scene staging (lds bytes, 0: none) and emitter candidates chosen at run time
+template <bool WS, class... A>
+void launch_initial(bool light, uint32_t lds, dim3 grid, hipStream_t st, A... a)
+{
+    if (light) {
+        if (lds) k_initial<true, WS, true><<<grid, kBlock, lds, st>>>(a...);
+        else k_initial<false, WS, true><<<grid, kBlock, 0, st>>>(a...);
+    } else {
+        if (lds) k_initial<true, WS, false><<<grid, kBlock, lds, st>>>(a...);
+        else k_initial<false, WS, false><<<grid, kBlock, 0, st>>>(a...);
+    }
+}
+
 #define GI_LAUNCH_LDS2(kernel, T2, grid, block, lds, stream, ...)                             \
     do {                                                                                      \
         if (lds) kernel<true, T2><<<(grid), (block), (lds), (stream)>>>(__VA_ARGS__);         \
@@ -944,9 +995,9 @@ gi_status gi_resample_initial(const gi_scene *scene, const gi_gbuffer *gb, const
     if ((s = check_res(out, gb->width, gb->height)) != GI_OK) return s;
     if ((uint64_t)gb->width * gb->height > (1u << 23)) return GI_ERR_SHAPE;   // 23-bit tag origin
     if (gb->width == 0 || gb->height == 0) return GI_OK;
-    GI_LAUNCH_LDS2(k_initial, false, tile_grid(gb->width, gb->height), kBlock, scene_lds(scene), S(stream),
-                   *scene, *gb, *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame, CandWs{},
-                   gi_mlp{});
+    launch_initial<false>(params->M_light > 0, scene_lds(scene), tile_grid(gb->width, gb->height), S(stream),
+                          *scene, *gb, *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame,
+                          CandWs{}, gi_mlp{});
     return launched();
 }
 
@@ -1061,9 +1112,8 @@ gi_status gi_resample_initial_mlp(const gi_scene *scene, const gi_gbuffer *gb, c
                   frame);
     if ((s = launched()) != GI_OK) return s;
     if ((s = mlp_infer_launch(*mlp, (uint32_t)ncand, ws.pos, ws.nrm, ws.q, true, S(stream))) != GI_OK) return s;
-    k_initial<false, true><<<tile_grid(W, H), kBlock, 0, S(stream)>>>(*scene, *gb, *probes, *params, *out,
-                                                                        reinterpret_cast<float4 *>(resid), seed,
-                                                                        frame, ws, *mlp);
+    launch_initial<true>(params->M_light > 0, 0u, tile_grid(W, H), S(stream), *scene, *gb, *probes, *params, *out,
+                         reinterpret_cast<float4 *>(resid), seed, frame, ws, *mlp);
     return launched();
 }
 

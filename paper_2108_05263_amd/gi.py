@@ -56,7 +56,7 @@ class GiScene(C.Structure):
                 ("room_lo", F3), ("room_hi", F3), ("wall_albedo", F3), ("wall_emit", F3), ("sky", F3),
                 ("eps", C.c_float), ("grid_res", U3), ("grid_lo", F3), ("grid_hi", F3),
                 ("cell_start", C.c_void_p), ("cell_items", C.c_void_p), ("n_items", C.c_uint32),
-                ("options", C.c_uint32)]
+                ("options", C.c_uint32), ("n_emitters", C.c_uint32), ("emitters", C.c_uint32 * 32)]
 
 
 class GiCamera(C.Structure):
@@ -83,7 +83,7 @@ class GiReservoirs(C.Structure):
 class GiParams(C.Structure):
     _fields_ = [("M", C.c_uint32), ("k", C.c_uint32), ("radius", C.c_float), ("g_max", C.c_float),
                 ("cos_n", C.c_float), ("depth_rel", C.c_float), ("m_cap", C.c_float),
-                ("unbiased", C.c_uint32)]
+                ("unbiased", C.c_uint32), ("M_light", C.c_uint32)]
 
 
 class GiProbeParams(C.Structure):
@@ -186,6 +186,13 @@ class DeviceScene:
         s.sky = _f3(scene.sky)
         s.eps = float(scene.eps)
         s.options = 0 if lds else OPT_NO_LDS
+        # emitters light sampling draws from: the emissive spheres, in index order
+        em = [i for i in range(len(rec)) if rec.view(np.uint32)[i, 3] == sg.PRIM_SPHERE and np.any(rec[i, 12:15] > 0)]
+        if len(em) > 32:
+            raise GiError("more than 32 emissive spheres")
+        s.n_emitters = len(em)
+        for j, e in enumerate(em):
+            s.emitters[j] = e
         self.cell_start = self.cell_items = None
         if grid_res is not None:
             lo, hi = scene.bounds()
@@ -390,6 +397,7 @@ def params_struct(p: sg.Params) -> GiParams:
     g.M, g.k, g.radius, g.g_max = int(p.M), int(p.k), float(p.radius), float(p.g_max)
     g.cos_n, g.depth_rel, g.m_cap = float(p.cos_n), float(p.depth_rel), float(p.m_cap)
     g.unbiased = int(p.unbiased)
+    g.M_light = int(getattr(p, "M_light", 0))
     return g
 
 

@@ -14,6 +14,7 @@
 * the trained network's loss on a held-out batch drops well below the
   untrained network's.
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -270,10 +271,11 @@ def _cache_setup(gi, tiny, precision="bf16", mode="always"):
     return ds, probes, g, m, params, lo, hi
 
 
-def test_initial_and_shade_with_cache(gi, tiny):
+@pytest.mark.parametrize("m_light", [0, 3])
+def test_initial_and_shade_with_cache(gi, tiny, m_light):
     cfg, sc, grid, irr, dep, W, H, gb, res, resid = tiny
     ds, probes, g, m, params, lo, hi = _cache_setup(gi, tiny)
-    pr = cfg.params
+    pr = dataclasses.replace(cfg.params, M_light=m_light)
     out = gi.Reservoirs(W, H)
     gresid = torch.zeros(W * H, 4, device="cuda")
     ws = gi.initial_mlp_workspace(W, H, pr.M)

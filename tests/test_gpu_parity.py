@@ -7,6 +7,7 @@ own chain.  Tolerances: bit-exact for Philox, tags, M and primitive ids;
 relative error (floor 1e-3) of the float fields <= 1e-4 on average over
 pixels whose selection agrees; selection flips <= 1e-3 of pixels.
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -349,3 +350,77 @@ def test_initial_full_hd_sampled(gi):
     active = (ogb[pix, 13] != o.MISS) & (ogb[pix, 6:9].max(1) > 0) & (gb_g[pix, 13] == ogb[pix, 13])
     res, _ = compare_reservoirs(g, ref, active, tol_flip=5e-3, label="1080p initial sampled")
     log(f"1080p initial (sampled): {res}")
+
+
+# --------------------------------------------------------------------------
+# emitter-sampled candidates
+# --------------------------------------------------------------------------
+def test_emitter_candidates_shared_inputs(gi, tiny):
+    """M cosine + M_light emitter candidates (balance heuristic) on the
+    oracle's G-buffer and probes: reservoirs and image against the oracle."""
+    cfg, sc, grid, irr, dep = tiny
+    W, H = 64, 64
+    pr = dataclasses.replace(cfg.params, M=6, M_light=4)
+    cam = sg.make_camera(cfg, 0, W, H)
+    ogb = o.gbuffer(sc, cam)
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    assert ds.c.n_emitters == 1
+    probes = gi.Probes(grid)
+    probes.load(irr, dep)
+    gb = gi.GBuffer(W, H)
+    gb.load_records(ogb)
+    out = gi.Reservoirs(W, H)
+    resid = torch.zeros(W * H, 4, device="cuda")
+    gi.resample_initial(ds, gb, probes, pr, out, resid, 1, 0)
+    ores, oresid = o.resample_initial(sc, W, H, ogb, grid, irr, dep, pr, 1, 0)
+    active = (ogb[:, 13] != o.MISS) & (ogb[:, 6:9].max(1) > 0)
+    st, _ = compare_reservoirs(out.to_records(), ores, active, label="emitter candidates")
+    assert np.all(out.to_records()[active, 11] == 10)
+    # some reservoirs hold an emitter sample drawn by light sampling (candidate index >= M)
+    cand = (tags(ores[active]) >> 4) & 31
+    assert np.mean(cand >= 6) > 0.05
+    er = rel_err(resid.cpu().numpy()[:, :3], oresid)
+    log(f"emitter candidates: {st}; resid {er.mean():.2e}")
+    assert er.mean() < 1e-4
+    img = torch.zeros(W * H, 4, device="cuda")
+    gi.shade(ds, gb, probes, out, resid, pr, img)
+    oimg = o.shade(sc, W, H, ogb, grid, irr, dep, ores, oresid, pr)
+    e = rel_err(img.cpu().numpy()[:, :3], oimg, 1e-2)
+    log(f"emitter candidates shade: mean rel err {e.mean():.2e}")
+    assert e.mean() < 1e-4
+
+
+def test_emitter_candidates_closed_form(gi):
+    """The two-sphere closed form of the oracle's pin, on the device: each
+    plane pixel's mean over seeds is rho sum_e L_e (r_e/d_e)^2 cos(theta_e)."""
+    sys.path.insert(0, __import__("os").path.dirname(__file__))
+    from test_oracle_resampling import _sphere_over_plane
+    sc, cam, rho, Le, r, c = _sphere_over_plane()
+    W, H = cam.width, cam.height
+    ogb = o.gbuffer(sc, cam)
+    plane = (ogb[:, 13] == 0) & (np.abs(ogb[:, 4] - 1.0) < 1e-12)
+    x = ogb[plane, 0:3]
+    exact = np.zeros((len(x), 3))
+    for e in range(2):
+        v = c[e] - x
+        d = np.linalg.norm(v, axis=1)
+        exact += rho[None, :] * Le[e][None, :] * ((r[e] / d) ** 2 * (v[:, 1] / d))[:, None]
+    grid = sg.probe_grid((2, 2, 2), (-8.0, -1.0, -8.0), 8.0)
+    ds = gi.DeviceScene(sc, None)
+    probes = gi.Probes(grid)
+    gb = gi.GBuffer(W, H)
+    gb.load_records(ogb)
+    pr = sg.Params(M=2, M_light=8, k=0, n_spatial=0, temporal=False)
+    out = gi.Reservoirs(W, H)
+    resid = torch.zeros(W * H, 4, device="cuda")
+    img = torch.zeros(W * H, 4, device="cuda")
+    S = 400
+    vals = np.zeros((S, int(plane.sum()), 3))
+    for s in range(S):
+        gi.resample_initial(ds, gb, probes, pr, out, resid, 2000 + s, 0)
+        gi.shade(ds, gb, probes, out, resid, pr, img)
+        vals[s] = img.cpu().numpy()[plane, :3]
+    mean, sd = vals.mean(0), vals.std(0, ddof=1)
+    z = (mean - exact) / (sd / np.sqrt(S) + 1e-12)
+    log(f"emitter closed form on the device: max |z| {np.abs(z).max():.2f}")
+    assert np.abs(z).max() < 5.0
