@@ -578,8 +578,8 @@ static void radiance_toward(const o_scene *sc, const o_probes *pr, uint32_t prim
  * Q_prev is read from the input textures only.
  * ------------------------------------------------------------------------- */
 void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, double *dep_out,
-                    int rays, double hysteresis, double sharpness, uint64_t seed, uint32_t frame,
-                    const int32_t *plist, int64_t nlist)
+                    int rays, double hysteresis, double sharpness, double slider, uint64_t seed,
+                    uint32_t frame, const int32_t *plist, int64_t nlist)
 {
     int Ni = in->irr_res, Nd = in->dep_res;
     int64_t P = (int64_t)in->dims[0] * in->dims[1] * in->dims[2];
@@ -602,6 +602,22 @@ void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, doub
                 double hp[3], alb[3], emit[3];
                 for (int a = 0; a < 3; ++a) hp[a] = Pp[a] + h.t * dirs[r][a];
                 material(sc, h.prim, alb, emit);
+                if (slider > 0.0 && (emit[0] != 0.0 || emit[1] != 0.0 || emit[2] != 0.0)) {
+                    /* distance heuristic (Sec. 3.2): the surfaces this probe shades lie
+                     * behind it; their distance to the light is estimated as the ray
+                     * length t plus the probe's own mean depth in the backward
+                     * direction, clipped to the probe's cell; emission is scaled by the
+                     * inverse square of that total relative to t, with the backward
+                     * part weighted by the per-scene slider */
+                    double back[3] = {-dirs[r][0], -dirs[r][1], -dirs[r][2]}, mom[2];
+                    tile_fetch(in->dep + pi * dep_tile, Nd, 2, back, mom);
+                    double clip = O_INF;
+                    for (int a = 0; a < 3; ++a)
+                        if (back[a] != 0.0) clip = fmin(clip, 0.5 * in->spacing[a] / fabs(back[a]));
+                    double db = fmin(fmax(mom[0], 0.0), clip);
+                    double ratio = h.t / (h.t + slider * db);
+                    for (int a = 0; a < 3; ++a) emit[a] *= ratio * ratio;
+                }
                 for (int a = 0; a < 3; ++a) Ls[r][a] = emit[a];
                 if (alb[0] != 0.0 || alb[1] != 0.0 || alb[2] != 0.0) {
                     double hb[3], qv[3];

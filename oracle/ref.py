@@ -77,7 +77,7 @@ def _setup(L):
     L.o_tile_fetch.argtypes = [_P, C.c_int, C.c_int, _P, _P]
     L.o_fill_gutter.argtypes = [_P, C.c_int, C.c_int]
     L.o_probe_query.argtypes = [_P, C.c_int64, _P, _P, C.c_int, _P]
-    L.o_probe_update.argtypes = [_P, _P, _P, _P, C.c_int, C.c_double, C.c_double, C.c_uint64,
+    L.o_probe_update.argtypes = [_P, _P, _P, _P, C.c_int, C.c_double, C.c_double, C.c_double, C.c_uint64,
                                  C.c_uint32, _P, C.c_int64]
     L.o_resample_initial.argtypes = [_P, C.c_int32, C.c_int32, _P, _P, _P, C.c_uint64, C.c_uint32,
                                      _P, C.c_int64, _P, _P]
@@ -284,13 +284,13 @@ def probe_query(grid, irr, dep, p, n, flags=0) -> np.ndarray:
     return out
 
 
-def probe_update(scene, grid, irr, dep, rays, hysteresis, sharpness, seed, frame, probes=None):
+def probe_update(scene, grid, irr, dep, rays, hysteresis, sharpness, seed, frame, probes=None, slider=0.0):
     s = _scene(scene)
     pr = _Probes(grid, irr, dep)
     irr_out, dep_out = pr.irr.copy(), pr.dep.copy()
     arr, n, pp = _pix(probes)
     lib().o_probe_update(s.ref, pr.ref, _ptr(irr_out), _ptr(dep_out), int(rays), float(hysteresis),
-                         float(sharpness), int(seed), int(frame) & 0xFFFFFFFF, pp, n)
+                         float(sharpness), float(np.float32(slider)), int(seed), int(frame) & 0xFFFFFFFF, pp, n)
     return irr_out, dep_out
 
 
@@ -302,7 +302,7 @@ def fill_probes(scene, grid, upd, seed, irr=None, dep=None):
         dep = np.zeros((P, (grid.dep_res + 2) ** 2, 2))
     for k in range(upd.fill_passes):
         irr, dep = probe_update(scene, grid, irr, dep, upd.fill_rays, 0.0, upd.sharpness, seed,
-                                FILL_FRAME_BASE + k)
+                                FILL_FRAME_BASE + k, slider=getattr(upd, "distance_slider", 0.0))
     return irr, dep
 
 

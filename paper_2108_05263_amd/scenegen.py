@@ -122,6 +122,7 @@ class ProbeUpdate:
     fill_passes: int = 4              # passes at hysteresis 0 before frame 0
     fill_rays: int = 256
     per_frame: bool = False           # update every frame (4K workload)
+    distance_slider: float = 0.0      # weight of the backward distance in the emission heuristic (0: off)
 
 
 @dataclasses.dataclass

@@ -340,3 +340,76 @@ def test_query_chebyshev_weight():
         r = xq - 1.0
         cheb = 1.0 if r <= mu else (s2 / (s2 + (r - mu) ** 2)) ** 3
         assert v0 == pytest.approx(max(cheb, 1e-6), rel=1e-9), (mu, s2, xq)
+
+
+def test_distance_heuristic_single_ray():
+    """Emission heuristic of the probe update (Sec. 3.2): a probe at the
+    centre of a cube room whose walls emit L and reflect nothing, one update
+    ray of length t: every irradiance texel facing the ray holds L (t / (t +
+    s d_b))^2, with d_b the probe's backward mean depth clipped to its cell.
+    Here the cell is the room, so a backward depth beyond the walls clips to
+    t and the factor is 1/(1+s)^2 whatever the direction; slider 0 leaves L."""
+    L = np.array([0.7, 1.1, 1.9], np.float32)
+    sc = g.Scene(prims=np.zeros((0, 16), np.float32), has_room=True, room_lo=np.zeros(3, np.float32),
+                 room_hi=np.full(3, 8.0, np.float32), wall_albedo=np.zeros(3, np.float32),
+                 sky=np.zeros(3, np.float32), eps=8e-4, wall_emit=L)
+    grid = g.probe_grid((1, 1, 1), (0.0, 0.0, 0.0), 8.0)
+    N = grid.irr_res
+    Ld = L.astype(np.float64)
+    for frame in range(6):
+        u = o.philox(3, [0, frame, 9, 0])
+        w = o.sphere_dir(float(u[0] >> 8) * 2.0 ** -24, float(u[1] >> 8) * 2.0 ** -24)
+        t = float(np.min(4.0 / np.abs(w)))
+        for mu_b, s, factor in ((100.0, 0.7, 1.0 / 1.7 ** 2), (1.5, 0.7, (t / (t + 0.7 * 1.5)) ** 2),
+                                (1.5, 0.0, 1.0)):
+            irr, dep = g.empty_probe_textures(grid)
+            dep[..., 0], dep[..., 1] = mu_b, mu_b * mu_b
+            i2, _ = o.probe_update(sc, grid, irr, dep, 1, 0.0, 50.0, 3, frame, slider=s)
+            T = i2.reshape(N + 2, N + 2, 3)[1:N + 1, 1:N + 1]
+            facing, checked = 0, 0
+            for ty in range(N):
+                for tx in range(N):
+                    nt = o.oct_decode([(tx + 0.5) / N, (ty + 0.5) / N])
+                    if np.dot(nt, w) > 1e-9:
+                        assert np.allclose(T[ty, tx], Ld * factor, rtol=1e-12), (frame, mu_b, s)
+                        facing += 1
+                    elif np.dot(nt, w) < -1e-9:
+                        assert np.all(T[ty, tx] == 0.0)
+                    checked += 1
+            assert facing > 10
+
+
+def test_distance_heuristic_reads_the_backward_direction():
+    """Same room; the probe's depth tile says 'far' (beyond the cell) for
+    directions with z > 0 and 1.5 for z < 0, so the factor tells which
+    direction was read: the backward one, -w."""
+    L = np.array([1.0, 2.0, 3.0], np.float32)
+    sc = g.Scene(prims=np.zeros((0, 16), np.float32), has_room=True, room_lo=np.zeros(3, np.float32),
+                 room_hi=np.full(3, 8.0, np.float32), wall_albedo=np.zeros(3, np.float32),
+                 sky=np.zeros(3, np.float32), eps=8e-4, wall_emit=L)
+    grid = g.probe_grid((1, 1, 1), (0.0, 0.0, 0.0), 8.0)
+    N, Nd = grid.irr_res, grid.dep_res
+    irr, dep = g.empty_probe_textures(grid)
+    tile = np.zeros((Nd + 2, Nd + 2, 2))
+    for ty in range(Nd):
+        for tx in range(Nd):
+            d = o.oct_decode([(tx + 0.5) / Nd, (ty + 0.5) / Nd])
+            mu = 100.0 if d[2] > 0 else 1.5
+            tile[ty + 1, tx + 1] = (mu, mu * mu)
+    dep[0] = o.fill_gutter(tile.reshape(-1, 2), Nd).reshape(-1, 2)
+    s, seen = 0.5, {True: 0, False: 0}
+    for frame in range(40):
+        u = o.philox(7, [0, frame, 9, 0])
+        w = o.sphere_dir(float(u[0] >> 8) * 2.0 ** -24, float(u[1] >> 8) * 2.0 ** -24)
+        if abs(w[2]) < 0.4:
+            continue
+        t = float(np.min(4.0 / np.abs(w)))
+        far = -w[2] > 0
+        factor = 1.0 / (1.0 + s) ** 2 if far else (t / (t + s * 1.5)) ** 2
+        i2, _ = o.probe_update(sc, grid, irr, dep, 1, 0.0, 50.0, 7, frame, slider=s)
+        T = i2.reshape(N + 2, N + 2, 3)[1:N + 1, 1:N + 1]
+        best = max(((ty, tx) for ty in range(N) for tx in range(N)),
+                   key=lambda c: np.dot(o.oct_decode([(c[1] + 0.5) / N, (c[0] + 0.5) / N]), w))
+        assert np.allclose(T[best], L.astype(np.float64) * factor, rtol=1e-12), (frame, far)
+        seen[far] += 1
+    assert seen[True] >= 3 and seen[False] >= 3
