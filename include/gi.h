@@ -160,6 +160,7 @@ typedef struct gi_params {
     float m_cap;         /* temporal history cap, multiple of the current M */
     uint32_t unbiased;   /* 1: visibility-tested 1/Z normalisation, 0: 1/M */
     uint32_t M_light;    /* emitter-sampled candidates per pixel; M + M_light <= GI_MAX_M */
+    uint32_t subsample;  /* n >= 1: pixel (x, y) draws candidates in frame f iff (x + y + f) % n == 0 */
 } gi_params;
 
 /* Probe-update parameters. */
@@ -167,6 +168,7 @@ typedef struct gi_probe_params {
     uint32_t rays;       /* rays per probe, 1..GI_MAX_PROBE_RAYS */
     float hysteresis;    /* stored = h*old + (1-h)*new, in [0, 1] */
     float sharpness;     /* exponent of the depth-moment cosine lobe, > 0 */
+    float distance_slider; /* >= 0; 0 switches the emission distance heuristic off */
 } gi_probe_params;
 
 /* Human-readable name of a status code (static storage). */
@@ -187,6 +189,10 @@ gi_status gi_trace_gbuffer(const gi_scene *scene, const gi_camera *cam, gi_gbuff
  * min(bias_dist, t/2), a miss brings the sky; irradiance texels take the
  * cosine-weighted mean, depth texels the cos^sharpness-weighted mean of
  * (d, d^2) with d = min(t, d_max); stored = h*in + (1-h)*new; gutters filled.
+ * With distance_slider s > 0 (the distance heuristic of Sec. 3.2) emission
+ * reached at ray length t is scaled by (t / (t + s d_b))^2, d_b = the
+ * probe's own mean depth (input texture) in the backward direction, clipped
+ * to the distance from the probe to its cell boundary along that direction.
  * Reads only `in`, writes only `out` (same layout, must not alias). */
 gi_status gi_probe_update(const gi_scene *scene, const gi_probes *in, gi_probes *out,
                           const gi_probe_params *pp, uint64_t seed, uint32_t frame, void *stream);
@@ -208,7 +214,11 @@ gi_status gi_probe_query(const gi_probes *probes, uint32_t n, const float *p, co
  * emitter chosen uniformly from scene->emitters (u0 the emitter, u1, u2 the
  * point, u3 the decision); every candidate's weight is then p_hat over the
  * balance-heuristic mixture density (M p_A + M_light p_light)/(M + M_light)
- * and M + M_light candidates are counted.  resid (float4 plane, rgb used)
+ * and M + M_light candidates are counted.  With subsample n > 1 (the
+ * subsampling of Sec. 6) only pixels with (x + y + frame) % n == 0 draw
+ * candidates; the others get an empty reservoir (M = 0) and leave the
+ * resampling to temporal and spatial reuse, but still estimate the residual
+ * from candidate 0.  resid (float4 plane, rgb used)
  * receives the residual transport rho_x L(y_0) max(0, 1 - g_max/G_0) of
  * candidate 0 (Eq. 9).  Pixels that miss or have zero albedo get an empty
  * reservoir with M = 0. */

@@ -76,6 +76,8 @@ typedef struct {
     double cos_n;                   /* reuse normal threshold */
     double depth_rel;               /* reuse relative depth threshold */
     double m_cap;                   /* temporal history cap (multiple of current M) */
+    int32_t subsample;              /* n: pixel (x, y) draws candidates in frame f iff (x+y+f) % n == 0 */
+    int32_t pad;
 } o_params;
 
 enum { GB_POS = 0, GB_NRM = 3, GB_ALB = 6, GB_EMIT = 9, GB_DEPTH = 12, GB_PRIM = 13, GB_N = 14 };
@@ -799,7 +801,10 @@ void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *g
         double wsum = 0.0, p_sel = 0.0;
         int have = 0;
         res_empty(r, 0.0);
-        for (int i = 0; i < Mt; ++i) {
+        /* subsampling (Sec. 6): a pixel that draws no candidates this frame keeps an
+         * empty reservoir (M = 0) and only estimates the residual from candidate 0 */
+        const int draws = pp->subsample <= 1 || ((p % W) + (p / W) + (int64_t)frame) % pp->subsample == 0;
+        for (int i = 0; i < (draws ? Mt : 1); ++i) {
             double u[4], w[3];
             rand4(seed, (uint32_t)p, frame, PASS_INITIAL, (uint32_t)i, u);
             double y[3], ny[3] = {0, 0, 0}, L[3], phat = 0.0, wi = 0.0;
@@ -855,6 +860,7 @@ void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *g
                     wi = phat / (cx / O_PI) * ((double)Mt / Mb);
                 }
             }
+            if (!draws) break;
             wsum += wi;
             if (u_dec * wsum < wi) {
                 have = 1;
@@ -864,6 +870,7 @@ void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *g
                 r[R_PRIM] = (double)prim;
             }
         }
+        if (!draws) continue;
         r[R_WSUM] = wsum;
         r[R_M] = (double)Mt;
         r[R_W] = (have && p_sel > 0.0) ? wsum / (Mt * p_sel) : 0.0;

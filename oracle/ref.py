@@ -57,7 +57,8 @@ class OProbes(C.Structure):
 class OParams(C.Structure):
     _fields_ = [("M", C.c_int32), ("k", C.c_int32), ("unbiased", C.c_int32), ("M_light", C.c_int32),
                 ("radius", C.c_double), ("g_max", C.c_double), ("cos_n", C.c_double),
-                ("depth_rel", C.c_double), ("m_cap", C.c_double)]
+                ("depth_rel", C.c_double), ("m_cap", C.c_double), ("subsample", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -193,6 +194,7 @@ def _params(pr) -> OParams:
     o.cos_n = float(np.float32(pr.cos_n))
     o.depth_rel = float(np.float32(pr.depth_rel))
     o.m_cap = float(pr.m_cap)
+    o.subsample = int(getattr(pr, "subsample", 1))
     return o
 
 

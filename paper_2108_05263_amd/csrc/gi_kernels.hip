@@ -188,6 +188,18 @@ __global__ void __launch_bounds__(kProbeBlock)
             V3 n = hit_normal(sc, acc, P, w, h);
             V3 alb, emit;
             material(sc, h.prim, alb, emit);
+            if (pp.distance_slider > 0.0f && !is_zero(emit)) {
+                // distance heuristic: emission scaled by (t / (t + s d_b))^2, d_b the
+                // probe's backward mean depth clipped to its cell
+                const float2 m = fetch_dep(reinterpret_cast<const float4 *>(in.dep) + (size_t)pi * kDepProbeF4, -w);
+                float clip = kInf;
+                if (w.x != 0.0f) clip = fminf(clip, 0.5f * in.spacing[0] / fabsf(w.x));
+                if (w.y != 0.0f) clip = fminf(clip, 0.5f * in.spacing[1] / fabsf(w.y));
+                if (w.z != 0.0f) clip = fminf(clip, 0.5f * in.spacing[2] / fabsf(w.z));
+                const float db = fminf(fmaxf(m.x, 0.0f), clip);
+                const float ratio = h.t / (h.t + pp.distance_slider * db);
+                emit = (ratio * ratio) * emit;
+            }
             L = emit;
             if (!is_zero(alb)) {
                 V3 q = probe_query(in, view_bias(hp, P, in.bias_dist), n);
@@ -372,7 +384,9 @@ __global__ void __launch_bounds__(kBlock)
     Res r = empty_res(Mt);
     float wsum = 0.0f, p_sel = 0.0f;
     bool have = false;
-    for (uint32_t i = 0; i < Mt; ++i) {
+    // subsampling: a pixel off the pattern draws no candidates, only the residual's
+    const bool draws = pp.subsample <= 1u || ((uint64_t)px + py + frame) % pp.subsample == 0u;
+    for (uint32_t i = 0; i < (draws ? Mt : 1u); ++i) {
         uint4 rn = philox(seed, p, frame, kPassInitial, i);
         float u2 = u01(rn.z);
         V3 w, y, ny = v3(0.0f, 0.0f, 0.0f), L = v3(0.0f, 0.0f, 0.0f);
@@ -439,6 +453,7 @@ __global__ void __launch_bounds__(kBlock)
                 if (LIGHT) wi *= rcp(mixb);
             }
         }
+        if (!draws) break;
         wsum += wi;
         if (u2 * wsum < wi) {
             have = true;
@@ -451,6 +466,7 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
     r.wsum = wsum;
+    if (!draws) r = empty_res(0);
     r.W = (have && p_sel > 0.0f) ? wsum * rcp((float)Mt * p_sel) : 0.0f;
     store_res(out, p, r);
     resid[p] = make_float4(rs.x, rs.y, rs.z, 0.0f);
@@ -867,6 +883,7 @@ gi_status check_params(const gi_params *pp)
     if (!pp) return GI_ERR_NULL;
     if (pp->M < 1 || pp->M > GI_MAX_M || pp->k > GI_MAX_K) return GI_ERR_PARAM;
     if (pp->M_light > GI_MAX_M - pp->M) return GI_ERR_PARAM;
+    if (pp->subsample < 1) return GI_ERR_PARAM;
     if (!(pp->radius >= 0.0f) || !(pp->g_max > 0.0f) || !(pp->m_cap >= 0.0f) || !(pp->depth_rel >= 0.0f))
         return GI_ERR_PARAM;
     return GI_OK;
@@ -965,6 +982,7 @@ gi_status gi_probe_update(const gi_scene *scene, const gi_probes *in, gi_probes 
         return GI_ERR_ALIAS;
     if (pp->rays < 1 || pp->rays > GI_MAX_PROBE_RAYS) return GI_ERR_PARAM;
     if (!(pp->hysteresis >= 0.0f && pp->hysteresis <= 1.0f) || !(pp->sharpness > 0.0f)) return GI_ERR_PARAM;
+    if (!(pp->distance_slider >= 0.0f)) return GI_ERR_PARAM;
     uint32_t P = in->dims[0] * in->dims[1] * in->dims[2];
     uint32_t lds = scene_lds(scene, (uint32_t)sizeof(float) * (7u * GI_MAX_PROBE_RAYS + 64u * 3u + 256u * 2u));
     GI_LAUNCH_LDS(k_probe_update, P, kProbeBlock, lds, S(stream), *scene, *in, *out, *pp, seed, frame);

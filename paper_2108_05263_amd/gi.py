@@ -83,11 +83,12 @@ class GiReservoirs(C.Structure):
 class GiParams(C.Structure):
     _fields_ = [("M", C.c_uint32), ("k", C.c_uint32), ("radius", C.c_float), ("g_max", C.c_float),
                 ("cos_n", C.c_float), ("depth_rel", C.c_float), ("m_cap", C.c_float),
-                ("unbiased", C.c_uint32), ("M_light", C.c_uint32)]
+                ("unbiased", C.c_uint32), ("M_light", C.c_uint32), ("subsample", C.c_uint32)]
 
 
 class GiProbeParams(C.Structure):
-    _fields_ = [("rays", C.c_uint32), ("hysteresis", C.c_float), ("sharpness", C.c_float)]
+    _fields_ = [("rays", C.c_uint32), ("hysteresis", C.c_float), ("sharpness", C.c_float),
+                ("distance_slider", C.c_float)]
 
 
 class GiMlp(C.Structure):
@@ -398,6 +399,7 @@ def params_struct(p: sg.Params) -> GiParams:
     g.cos_n, g.depth_rel, g.m_cap = float(p.cos_n), float(p.depth_rel), float(p.m_cap)
     g.unbiased = int(p.unbiased)
     g.M_light = int(getattr(p, "M_light", 0))
+    g.subsample = int(getattr(p, "subsample", 1))
     return g
 
 
@@ -410,8 +412,8 @@ def trace_gbuffer(scene: DeviceScene, cam, gb: GBuffer, stream=None):
 
 
 def probe_update(scene: DeviceScene, pin: Probes, pout: Probes, rays, hysteresis, sharpness, seed,
-                 frame, stream=None):
-    pp = GiProbeParams(int(rays), float(hysteresis), float(sharpness))
+                 frame, stream=None, slider=0.0):
+    pp = GiProbeParams(int(rays), float(hysteresis), float(sharpness), float(slider))
     check(load().gi_probe_update(scene.ref, pin.ref, pout.ref, C.byref(pp), int(seed),
                                  int(frame) & 0xFFFFFFFF, _stream(stream)), "gi_probe_update")
 
@@ -672,7 +674,7 @@ class Renderer:
     def update_probes(self, rays, hysteresis, frame, stream=None):
         src, dst = self.probes[self.cur_probe], self.probes[1 - self.cur_probe]
         probe_update(self.dscene, src, dst, rays, hysteresis, self.cfg.probe_update.sharpness,
-                     self.seed, frame, stream)
+                     self.seed, frame, stream, slider=self.cfg.probe_update.distance_slider)
         self.cur_probe = 1 - self.cur_probe
 
     def fill_probes(self, stream=None):

@@ -112,6 +112,7 @@ class Params:
     unbiased: int = 1                 # 1: 1/Z normalisation with visibility, 0: 1/M
     temporal: bool = True
     M_light: int = 0                  # emitter-sampled candidates per pixel (M + M_light <= 32)
+    subsample: int = 1                # n: pixel (x, y) draws candidates in frame f iff (x + y + f) % n == 0
 
 
 @dataclasses.dataclass

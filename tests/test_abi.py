@@ -70,10 +70,27 @@ def test_validation_rejects_before_launch(gi):
     pr.irr, pr.dep = 80, 96
     pp = gi.GiParams()
     pp.M, pp.k, pp.radius, pp.g_max, pp.m_cap = 33, 1, 1.0, 1.0, 20.0
+    pp.subsample = 1
     resid = C.c_void_p(112)
     assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r),
                                    resid, 1, 0, None) == 3
     pp.M = 8
+    # emitter candidates beyond the 32-candidate limit, subsample 0
+    pp.M_light = 25
+    assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r),
+                                   resid, 1, 0, None) == 3
+    pp.M_light, pp.subsample = 24, 0
+    assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r),
+                                   resid, 1, 0, None) == 3
+    pp.subsample = 1
+    # emitter list: too long, or naming a primitive that does not exist
+    s.n_emitters = 33
+    assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r),
+                                   resid, 1, 0, None) == 2
+    s.n_emitters, s.emitters[0] = 1, 5
+    assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r),
+                                   resid, 1, 0, None) == 3
+    s.n_emitters = 0
     pr.irr_res = 4
     assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r),
                                    resid, 1, 0, None) == 2
@@ -82,11 +99,14 @@ def test_validation_rejects_before_launch(gi):
     assert lib.gi_resample_spatial(C.byref(s), C.byref(g), C.byref(r), C.byref(pp), 0, C.byref(r),
                                    1, 0, None) == 4
     # probe update: rays out of range, aliasing
-    pu = gi.GiProbeParams(0, 0.5, 50.0)
+    pu = gi.GiProbeParams(0, 0.5, 50.0, 0.0)
     pr2 = gi.GiProbes()
     C.pointer(pr2)[0] = pr
     pr2.irr, pr2.dep = 128, 144
     assert lib.gi_probe_update(C.byref(s), C.byref(pr), C.byref(pr2), C.byref(pu), 1, 0, None) == 3
+    pu.rays, pu.distance_slider = 64, -1.0
+    assert lib.gi_probe_update(C.byref(s), C.byref(pr), C.byref(pr2), C.byref(pu), 1, 0, None) == 3
+    pu.distance_slider = 0.0
     pu.rays = 64
     assert lib.gi_probe_update(C.byref(s), C.byref(pr), C.byref(pr), C.byref(pu), 1, 0, None) == 4
 

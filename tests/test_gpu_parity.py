@@ -162,15 +162,15 @@ def test_probe_update(gi, tiny):
     ds = gi.DeviceScene(sc, cfg.grid_res)
     pin, pout = gi.Probes(grid), gi.Probes(grid)
     pin.load(i2, d2)
-    for hyst in (0.0, 0.97):
-        gi.probe_update(ds, pin, pout, 64, hyst, 50.0, 1, 5)
+    for hyst, slider in ((0.0, 0.0), (0.97, 0.0), (0.0, 0.8)):
+        gi.probe_update(ds, pin, pout, 64, hyst, 50.0, 1, 5, slider=slider)
         gi_irr, gi_dep = pout.tiles()
         # every quad record agrees with the padded tile it encodes (gutters included)
         assert np.array_equal(pout.irr.cpu().numpy(), gi.tiles_to_quads(gi_irr, grid.irr_res))
         assert np.array_equal(pout.dep.cpu().numpy(), gi.tiles_to_quads(gi_dep, grid.dep_res))
-        ri, rd = o.probe_update(sc, grid, i2, d2, 64, hyst, 50.0, 1, 5)
+        ri, rd = o.probe_update(sc, grid, i2, d2, 64, hyst, 50.0, 1, 5, slider=slider)
         ei, ed = rel_err(gi_irr, ri), rel_err(gi_dep, rd)
-        log(f"probe update h={hyst}: irr mean {ei.mean():.2e} max {ei.max():.2e}; "
+        log(f"probe update h={hyst} slider={slider}: irr mean {ei.mean():.2e} max {ei.max():.2e}; "
             f"dep mean {ed.mean():.2e} max {ed.max():.2e}")
         assert ei.mean() < 1e-4 and ed.mean() < 1e-4
         assert np.mean(ei > 1e-2) < 1e-3 and np.mean(ed > 1e-2) < 1e-3
@@ -424,3 +424,29 @@ def test_emitter_candidates_closed_form(gi):
     z = (mean - exact) / (sd / np.sqrt(S) + 1e-12)
     log(f"emitter closed form on the device: max |z| {np.abs(z).max():.2f}")
     assert np.abs(z).max() < 5.0
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_subsampled_initial_shared_inputs(gi, tiny, n):
+    """Candidate subsampling: only pixels on the (x + y + f) % n pattern draw
+    candidates; against the oracle on its own G-buffer and probes."""
+    cfg, sc, grid, irr, dep = tiny
+    W, H = 64, 64
+    pr = dataclasses.replace(cfg.params, subsample=n)
+    ogb = o.gbuffer(sc, sg.make_camera(cfg, 0, W, H))
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    probes = gi.Probes(grid)
+    probes.load(irr, dep)
+    gb = gi.GBuffer(W, H)
+    gb.load_records(ogb)
+    out = gi.Reservoirs(W, H)
+    resid = torch.zeros(W * H, 4, device="cuda")
+    gi.resample_initial(ds, gb, probes, pr, out, resid, 1, 3)
+    ores, oresid = o.resample_initial(sc, W, H, ogb, grid, irr, dep, pr, 1, 3)
+    active = (ogb[:, 13] != o.MISS) & (ogb[:, 6:9].max(1) > 0)
+    g = out.to_records()
+    assert np.array_equal(g[:, 11], ores[:, 11])
+    st, _ = compare_reservoirs(g, ores, active, label=f"subsample {n}")
+    er = rel_err(resid.cpu().numpy()[:, :3], oresid)
+    log(f"subsample {n}: {st}; resid {er.mean():.2e}")
+    assert er.mean() < 1e-4

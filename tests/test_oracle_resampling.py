@@ -258,3 +258,23 @@ def test_emitter_candidates_unbiased_closed_form():
         # Bonferroni over the plane pixels and channels at family-wise 1e-3
         assert np.abs(z).max() < 5.0, (M, ml, np.abs(z).max())
     assert var[4] < 0.5 * var[0], var
+
+
+def test_subsampling_draws_on_the_pattern():
+    """Subsampling (Sec. 6): pixel (x, y) draws candidates in frame f iff
+    (x + y + f) % n == 0.  Drawing pixels get exactly the reservoirs of the
+    plain pass (same counters); the others an empty reservoir (M = 0, W = 0);
+    every pixel keeps its residual (candidate 0)."""
+    W, H = 12, 10
+    cfg, sc, cam, grid, irr, dep = _tiny_setup(W, H)
+    gb = o.gbuffer(sc, cam)
+    active = (gb[:, 13] != o.MISS) & (gb[:, 6:9].max(1) > 0)
+    for n, frame in ((2, 0), (3, 5), (1, 2)):
+        full, rfull = o.resample_initial(sc, W, H, gb, grid, irr, dep, _params(M=6), 4, frame)
+        sub, rsub = o.resample_initial(sc, W, H, gb, grid, irr, dep, _params(M=6, subsample=n), 4, frame)
+        x, y = np.arange(W * H) % W, np.arange(W * H) // W
+        draws = (x + y + frame) % n == 0
+        assert np.array_equal(sub[draws], full[draws])
+        assert np.all(sub[active & ~draws, 11] == 0) and np.all(sub[~draws, 10] == 0)
+        assert np.array_equal(rsub, rfull)
+        assert (active & ~draws).any() or n == 1
