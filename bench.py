@@ -250,11 +250,15 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
     del base
     out = {"config": cfg.name, "frames": frames, "eval_frames": [eval_frames[0], eval_frames[-1]],
            "seeds": n_seeds, "ref_spp": ref_spp, "ref_noise_mse": sum(noise) / len(noise), "forms": {}}
-    for form in ("probe", "bf16", "fp8"):
+    forms = (("probe", None, "f32"), ("bf16", "bf16", "f32"), ("fp8", "fp8", "f32"))
+    if cfg.name == "uhd":
+        # the precision sweep: half-precision G-buffer normals and albedo, alone and with FP8 inference
+        forms += (("probe, f16 G-buffer", None, "f16"), ("fp8, f16 G-buffer", "fp8", "f16"))
+    for form, mlp, gbf in forms:
         acc = {"mse": [], "relmse": [], "mape": []}
-        per_seed = []
+        per_seed, train = [], []
         for seed in range(1, n_seeds + 1):
-            r = gi.Renderer(cfg, seed=seed, mlp=None if form == "probe" else form, mlp_mode="always")
+            r = gi.Renderer(cfg, seed=seed, mlp=mlp, mlp_mode="always", gb_format=gbf)
             r.fill_probes()
             m = {"mse": 0.0, "relmse": 0.0, "mape": 0.0}
             for f in range(frames):
@@ -267,10 +271,15 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
             for k in acc:
                 acc[k].append(m[k])
             per_seed.append(m["mse"])
+            if mlp is not None:
+                st = r.mlp.state_words()
+                train.append({"loss": st["loss"], "ema_rel_err_vs_probe": st["ema_err"], "usable": st["usable"]})
             del r
             torch.cuda.empty_cache()
         rec = {k: sum(v) / len(v) for k, v in acc.items()}
         rec["mse_per_seed"] = per_seed
+        if train:
+            rec["train_at_end"] = train
         out["forms"][form] = rec
         print(f"form {form}: {rec}", file=sys.stderr, flush=True)
     return out
@@ -374,7 +383,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: {W}x{H} room, {cfg.n_spheres}+{cfg.n_boxes} primitives, "
+        "config": {"workload": f"{cfg.name}: {W}x{H} room, {cfg.n_spheres}+{cfg.n_boxes} primitives "
+                               f"({cfg.n_emitters} emitters), "
                                f"{cfg.probe_dims[0]}x{cfg.probe_dims[1]}x{cfg.probe_dims[2]} probes, "
                                f"M={cfg.params.M}, temporal, {cfg.params.n_spatial}x k={cfg.params.k} "
                                f"r={cfg.params.radius:g}",

@@ -100,9 +100,15 @@ typedef struct gi_camera {
     uint32_t width, height;
 } gi_camera;
 
-/* G-buffer of primary vertices, four float4 planes of width*height records:
- *   pos_depth = (x, y, z, view depth), nrm_prim = (n_x, n_y, n_z, prim id as
- *   uint32 bits), albedo = (r, g, b, 0), emit = (r, g, b, 0).
+/* G-buffer of primary vertices, four planes of width*height records.
+ * format GI_GB_F32: four float4 planes, pos_depth = (x, y, z, view depth),
+ *   nrm_prim = (n_x, n_y, n_z, prim id as uint32 bits), albedo = (r, g, b, 0),
+ *   emit = (r, g, b, 0).
+ * format GI_GB_F16 (normals and albedo in half precision, rounded to nearest
+ *   even): nrm_prim holds 8-byte records (half n_x, n_y, n_z; uint16 prim id,
+ *   0xFFFF = miss), albedo 8-byte records (half r, g, b, 0); pos_depth and
+ *   emit stay float4; readers renormalise the half-precision normal.  Scenes
+ *   must have fewer than 65535 - 6 primitives.
  * A pixel whose primary ray leaves the scene has prim = GI_MISS and emit = sky. */
 typedef struct gi_gbuffer {
     uint32_t width, height;
@@ -110,7 +116,12 @@ typedef struct gi_gbuffer {
     float *nrm_prim;
     float *albedo;
     float *emit;
+    uint32_t format;     /* GI_GB_F32 or GI_GB_F16 */
+    uint32_t pad;
 } gi_gbuffer;
+
+#define GI_GB_F32 0u
+#define GI_GB_F16 1u
 
 /* DDGI probe volume.  Probe (i, j, k), index i + dims[0]*(j + dims[1]*k),
  * sits at lo + (idx + 0.5) * spacing.  Each probe owns an octahedral

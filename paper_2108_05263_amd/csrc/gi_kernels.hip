@@ -71,12 +71,40 @@ struct GB {
     V3 alb;
 };
 
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ GB load_gb(const gi_gbuffer &g, uint32_t p)
 {
     float4 a = reinterpret_cast<const float4 *>(g.pos_depth)[p];
+    if (g.format == GI_GB_F16) {
+        const half4_t b = reinterpret_cast<const half4_t *>(g.nrm_prim)[p];
+        const half4_t c = reinterpret_cast<const half4_t *>(g.albedo)[p];
+        const uint32_t prim16 = __builtin_bit_cast(uint16_t, b[3]);
+        // a half-precision normal is renormalised: the sampling basis and the
+        // cosines assume unit length
+        V3 n = v3((float)b[0], (float)b[1], (float)b[2]);
+        const float nn = dot(n, n);
+        if (nn > 0.0f) n = frsq(nn) * n;
+        return GB{xyz(a), a.w, n, prim16 == 0xFFFFu ? GI_MISS : prim16, v3((float)c[0], (float)c[1], (float)c[2])};
+    }
     float4 b = reinterpret_cast<const float4 *>(g.nrm_prim)[p];
     float4 c = reinterpret_cast<const float4 *>(g.albedo)[p];
     return GB{xyz(a), a.w, xyz(b), __float_as_uint(b.w), xyz(c)};
+}
+
+// normal + primitive and albedo records of the G-buffer's format
+__device__ __forceinline__ void store_gb_na(const gi_gbuffer &g, uint32_t p, V3 n, uint32_t prim, V3 alb)
+{
+    if (g.format == GI_GB_F16) {
+        const uint16_t prim16 = prim == GI_MISS ? (uint16_t)0xFFFFu : (uint16_t)prim;
+        half4_t b = {(_Float16)n.x, (_Float16)n.y, (_Float16)n.z, __builtin_bit_cast(_Float16, prim16)};
+        half4_t c = {(_Float16)alb.x, (_Float16)alb.y, (_Float16)alb.z, (_Float16)0.0f};
+        reinterpret_cast<half4_t *>(g.nrm_prim)[p] = b;
+        reinterpret_cast<half4_t *>(g.albedo)[p] = c;
+        return;
+    }
+    reinterpret_cast<float4 *>(g.nrm_prim)[p] = make_float4(n.x, n.y, n.z, __uint_as_float(prim));
+    reinterpret_cast<float4 *>(g.albedo)[p] = make_float4(alb.x, alb.y, alb.z, 0.0f);
 }
 
 __device__ __forceinline__ bool active(const GB &g) { return g.prim != GI_MISS && !is_zero(g.alb); }
@@ -123,13 +151,11 @@ __global__ void __launch_bounds__(kBlock) k_gbuffer(gi_scene sc, gi_camera cam, 
     Hit h;
     const GeoGlobal acc(sc);
     float4 *pd = reinterpret_cast<float4 *>(gb.pos_depth);
-    float4 *np = reinterpret_cast<float4 *>(gb.nrm_prim);
-    float4 *al = reinterpret_cast<float4 *>(gb.albedo);
     float4 *em = reinterpret_cast<float4 *>(gb.emit);
+    const V3 zero = v3(0.0f, 0.0f, 0.0f);
     if (!cast<false>(sc, acc, o, d, kInf, h)) {
         pd[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        np[p] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(GI_MISS));
-        al[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        store_gb_na(gb, p, zero, GI_MISS, zero);
         em[p] = make_float4(sc.sky[0], sc.sky[1], sc.sky[2], 0.0f);
         return;
     }
@@ -138,8 +164,7 @@ __global__ void __launch_bounds__(kBlock) k_gbuffer(gi_scene sc, gi_camera cam, 
     V3 alb, emit;
     material(sc, h.prim, alb, emit);
     pd[p] = make_float4(x.x, x.y, x.z, h.t * dot(d, ld3(cam.fwd)));
-    np[p] = make_float4(n.x, n.y, n.z, __uint_as_float(h.prim));
-    al[p] = make_float4(alb.x, alb.y, alb.z, 0.0f);
+    store_gb_na(gb, p, n, h.prim, alb);
     em[p] = make_float4(emit.x, emit.y, emit.z, 0.0f);
 }
 
@@ -846,6 +871,7 @@ gi_status check_scene(const gi_scene *sc)
 gi_status check_gb(const gi_gbuffer *g, uint32_t W, uint32_t H)
 {
     if (!g || !g->pos_depth || !g->nrm_prim || !g->albedo || !g->emit) return GI_ERR_NULL;
+    if (g->format > GI_GB_F16) return GI_ERR_PARAM;
     if (g->width != W || g->height != H) return GI_ERR_SHAPE;
     return GI_OK;
 }
@@ -964,6 +990,7 @@ gi_status gi_trace_gbuffer(const gi_scene *scene, const gi_camera *cam, gi_gbuff
     if ((s = check_scene(scene)) != GI_OK) return s;
     if (cam->width == 0 || cam->height == 0) return GI_ERR_SHAPE;
     if ((s = check_gb(out, cam->width, cam->height)) != GI_OK) return s;
+    if (out->format == GI_GB_F16 && scene->n_prims + 6u >= 0xFFFFu) return GI_ERR_SHAPE;
     k_gbuffer<<<tile_grid(cam->width, cam->height), kBlock, 0, S(stream)>>>(*scene, *cam, *out);
     return launched();
 }

@@ -66,7 +66,11 @@ class GiCamera(C.Structure):
 
 class GiGBuffer(C.Structure):
     _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("pos_depth", C.c_void_p),
-                ("nrm_prim", C.c_void_p), ("albedo", C.c_void_p), ("emit", C.c_void_p)]
+                ("nrm_prim", C.c_void_p), ("albedo", C.c_void_p), ("emit", C.c_void_p),
+                ("format", C.c_uint32), ("pad", C.c_uint32)]
+
+
+GB_FORMAT = {"f32": 0, "f16": 1}
 
 
 class GiProbes(C.Structure):
@@ -234,17 +238,21 @@ def camera_struct(cam: sg.Camera) -> GiCamera:
 
 
 class GBuffer:
-    def __init__(self, W, H, device="cuda"):
-        self.W, self.H = W, H
+    """G-buffer planes; fmt 'f16' stores normals and albedo in half precision."""
+
+    def __init__(self, W, H, device="cuda", fmt="f32"):
+        self.W, self.H, self.fmt = W, H, fmt
         n = W * H
+        half = torch.float16 if fmt == "f16" else torch.float32
         self.pos_depth = torch.zeros(n, 4, dtype=torch.float32, device=device)
-        self.nrm_prim = torch.zeros(n, 4, dtype=torch.float32, device=device)
-        self.albedo = torch.zeros(n, 4, dtype=torch.float32, device=device)
+        self.nrm_prim = torch.zeros(n, 4, dtype=half, device=device)
+        self.albedo = torch.zeros(n, 4, dtype=half, device=device)
         self.emit = torch.zeros(n, 4, dtype=torch.float32, device=device)
         g = GiGBuffer()
         g.width, g.height = W, H
         g.pos_depth, g.nrm_prim = self.pos_depth.data_ptr(), self.nrm_prim.data_ptr()
         g.albedo, g.emit = self.albedo.data_ptr(), self.emit.data_ptr()
+        g.format = GB_FORMAT[fmt]
         self.c = g
 
     @property
@@ -259,7 +267,11 @@ class GBuffer:
         rec[:, 0:3], rec[:, 3:6] = pd[:, 0:3], npm[:, 0:3]
         rec[:, 6:9], rec[:, 9:12] = al[:, 0:3], em[:, 0:3]
         rec[:, 12] = pd[:, 3]
-        rec[:, 13] = npm[:, 3].view(np.uint32)
+        if self.fmt == "f16":
+            p16 = npm[:, 3].view(np.uint16).astype(np.uint64)
+            rec[:, 13] = np.where(p16 == 0xFFFF, MISS, p16)
+        else:
+            rec[:, 13] = npm[:, 3].view(np.uint32)
         return rec
 
     def load_records(self, rec, pixels=None):
@@ -268,13 +280,18 @@ class GBuffer:
         are written."""
         rec = np.asarray(rec, np.float64)
         n = len(rec) if pixels is not None else self.W * self.H
+        half = np.float16 if self.fmt == "f16" else np.float32
         pd = np.zeros((n, 4), np.float32)
-        npm = np.zeros((n, 4), np.float32)
-        al = np.zeros((n, 4), np.float32)
+        npm = np.zeros((n, 4), half)
+        al = np.zeros((n, 4), half)
         em = np.zeros((n, 4), np.float32)
         pd[:, 0:3], pd[:, 3] = rec[:, 0:3], rec[:, 12]
         npm[:, 0:3] = rec[:, 3:6]
-        npm.view(np.uint32)[:, 3] = rec[:, 13].astype(np.uint64).astype(np.uint32)
+        prim = rec[:, 13].astype(np.uint64)
+        if self.fmt == "f16":
+            npm.view(np.uint16)[:, 3] = np.where(prim == MISS, 0xFFFF, prim).astype(np.uint16)
+        else:
+            npm.view(np.uint32)[:, 3] = prim.astype(np.uint32)
         al[:, 0:3], em[:, 0:3] = rec[:, 6:9], rec[:, 9:12]
         idx = None if pixels is None else torch.as_tensor(np.asarray(pixels, np.int64), device=self.pos_depth.device)
         for t, a in ((self.pos_depth, pd), (self.nrm_prim, npm), (self.albedo, al), (self.emit, em)):
@@ -633,7 +650,7 @@ class Renderer:
     def __init__(self, cfg: sg.Config, seed: int = 1, width=None, height=None, use_grid=True,
                  device="cuda", scene=None, params=None, lds=True, mlp=None, mlp_mode="auto",
                  mlp_batch=1 << 16, mlp_steps=4, mlp_lr=1e-2, mlp_warmup=16, mlp_seed=7, mlp_ema=0.99,
-                 train=True):
+                 train=True, gb_format="f32"):
         self.cfg = cfg
         self.seed = seed
         self.W, self.H = int(width or cfg.width), int(height or cfg.height)
@@ -643,7 +660,7 @@ class Renderer:
         self.params = params if params is not None else cfg.params
         self.probes = [Probes(self.grid, device), Probes(self.grid, device)]
         self.cur_probe = 0
-        self.gb = [GBuffer(self.W, self.H, device), GBuffer(self.W, self.H, device)]
+        self.gb = [GBuffer(self.W, self.H, device, gb_format), GBuffer(self.W, self.H, device, gb_format)]
         self.res = [Reservoirs(self.W, self.H, device) for _ in range(4)]
         self.resid = torch.zeros(self.W * self.H, 4, dtype=torch.float32, device=device)
         self.img = torch.zeros(self.W * self.H, 4, dtype=torch.float32, device=device)

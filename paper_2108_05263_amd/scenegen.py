@@ -152,6 +152,7 @@ class Config:
     frames: int
     grid_res: tuple                   # uniform-grid accelerator resolution
     seeds: tuple = (1, 2, 3)
+    clear_emitters: bool = False      # redraw primitives that reach into an emitter
 
 
 # --------------------------------------------------------------------------
@@ -179,16 +180,18 @@ CONFIGS = {
         probe_update=ProbeUpdate(rays=256, hysteresis=0.0, fill_passes=4, fill_rays=256),
         frames=8, grid_res=(16, 4, 16)),
     # 3840x2160, same room with 512 + 512 primitives, 64x16x64 probes updated every
-    # frame with 256 rays at hysteresis 0.97.
+    # frame with 256 rays at hysteresis 0.97.  Four times the primitives of the
+    # 1920x1080 room at the same occupancy (sizes scaled by 4^(-1/3)) and with
+    # the same emitters per primitive (16), none of them reached into.
     "uhd": Config(
         name="uhd", width=3840, height=2160, scene_seed=103, n_spheres=512, n_boxes=512,
-        n_emitters=4, room_lo=(0, 0, 0), room_hi=(32, 8, 32), size_lo=0.2, size_hi=1.5,
+        n_emitters=16, room_lo=(0, 0, 0), room_hi=(32, 8, 32), size_lo=0.125, size_hi=0.95,
         emit_lo=10.0, emit_hi=50.0, eye=(16, 4, 1), look=(16, 3, 31), vfov_deg=60.0,
         pan=0.05, probe_dims=(64, 16, 64), probe_spacing=0.5,
         params=Params(M=32, k=5, n_spatial=2, radius=30.0, temporal=True),
         probe_update=ProbeUpdate(rays=256, hysteresis=0.97, fill_passes=4, fill_rays=256,
                                  per_frame=True),
-        frames=16, grid_res=(12, 3, 12)),
+        frames=16, grid_res=(24, 6, 24), clear_emitters=True),
 }
 
 
@@ -221,13 +224,16 @@ def _dist_point_segment(p, a, b):
 def make_scene(cfg: Config, max_frames: int = 32) -> Scene:
     """Seeded room: spheres first (the first n_emitters of them emit), then boxes.
     Primitives that would swallow the camera path (all frames up to max_frames)
-    are redrawn, so the eye is never inside geometry."""
+    are redrawn, so the eye is never inside geometry; with clear_emitters,
+    so are primitives whose bounding sphere reaches into an emitter's, so no
+    light is enclosed."""
     rng = np.random.default_rng(cfg.scene_seed)
     lo = np.asarray(cfg.room_lo, np.float64)
     hi = np.asarray(cfg.room_hi, np.float64)
     eye, _, r, _ = _camera_basis(cfg.eye, cfg.look)
     a, b = eye, eye + cfg.pan * max_frames * r
     types, centers, sizes, albedo, emit = [], [], [], [], []
+    lights = []                                    # (centre, radius) of the emitters drawn so far
     for i in range(cfg.n_spheres + cfg.n_boxes):
         is_sphere = i < cfg.n_spheres
         while True:
@@ -238,7 +244,9 @@ def make_scene(cfg: Config, max_frames: int = 32) -> Scene:
                 half = rng.uniform(cfg.size_lo, cfg.size_hi, 3)
             c = rng.uniform(lo + half, hi - half)
             reach = np.linalg.norm(half) if not is_sphere else half[0]
-            if _dist_point_segment(c, a, b) > reach + 0.3:
+            clear = not cfg.clear_emitters or all(
+                np.linalg.norm(c - ec) > reach + er for ec, er in lights)
+            if _dist_point_segment(c, a, b) > reach + 0.3 and clear:
                 break
         types.append(PRIM_SPHERE if is_sphere else PRIM_BOX)
         centers.append(c)
@@ -247,6 +255,7 @@ def make_scene(cfg: Config, max_frames: int = 32) -> Scene:
             albedo.append([0.0, 0.0, 0.0])
             le = rng.uniform(cfg.emit_lo, cfg.emit_hi)
             emit.append([le, le, le])
+            lights.append((c, half[0]))
         else:
             albedo.append(rng.uniform(0.1, 0.9, 3))
             emit.append([0.0, 0.0, 0.0])
