@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="hd")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
-    ap.add_argument("--cpu-crop", type=int, nargs=2, default=(320, 180))
+    ap.add_argument("--cpu-crop", type=int, nargs=2, default=(640, 360))
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-cache forms")
     ap.add_argument("--mlp-only", choices=["bf16", "fp8"], default=None,
                     help="time only this learned-cache form (for profiling)")
@@ -75,18 +75,42 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    runs (profiles/<kernel>_hd_traffic.json), if they were taken on the
-    current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_hd_traffic.json")
+def _profile(kernel, workload, what):
+    """A committed rocprofv3 counter summary (profiles/<kernel>_<workload>_<what>.json)
+    if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{what}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("source_sha") != source_sha():
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return rec
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE runs."""
+    rec = _profile(kernel, workload, "traffic")
+    return None if rec is None else rec.get("traffic_bytes_per_launch")
+
+
+# Vector-ALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction
+# per SIMD every 4 cycles (16 lanes per cycle; packed FP32 is not used).
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
+
+
+def alu_issue(kernel, workload, ms):
+    """Measured vector-ALU issue rate of `kernel`: its VALU wave-instructions
+    per launch (SQ_INSTS_VALU from the committed counter run) over the live
+    launch time, against the issue peak."""
+    rec = _profile(kernel, workload, "sq_counters")
+    if rec is None:
+        return None
+    insts = rec["SQ_INSTS_VALU"]
+    achieved = insts / (ms * 1e-3) / 1e9
+    return {"valu_insts_per_launch": insts, "achieved": achieved, "peak": VALU_PEAK_GINST,
+            "unit": "G wave-instr/s", "frac": achieved / VALU_PEAK_GINST,
+            "source": f"profiles/{kernel}_{workload}_sq_counters.json"}
 
 
 def cpu_baseline(cfg, crop):
@@ -395,9 +419,11 @@ def main():
         "path_hbm_frac": path_bytes / ((sum(avg.values())) * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"kernel": f"k_{dom_key}", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(f"k_{dom_key}"),
+                     "traffic": measured_traffic(f"k_{dom_key}", cfg.name),
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "kernel_source_sha": source_sha()},
+        # the dominant kernel is bound by vector-ALU issue, not HBM: its measured issue rate
+        "alu_issue": alu_issue(f"k_{dom_key}", cfg.name, avg[dom]),
     }
     if not args.no_mlp:
         del r

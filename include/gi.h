@@ -134,7 +134,9 @@ typedef struct gi_gbuffer {
  *        (cx+1,cy+1) in that order (3888 bytes per probe);
  *   dep: per probe (dep_res+1)^2 records of 8 floats, (mean, mean^2) of the
  *        same four padded texels (9248 bytes per probe).
- * irr_res must be 8 and dep_res 16.  bias_dist is the view-path bias d,
+ * irr_res must be 8 and dep_res 16; the volume holds at most 464,000
+ * probes (each texture then stays under 4 GiB, so kernels address it with
+ * 32-bit byte offsets; larger volumes return GI_ERR_SHAPE).  bias_dist is the view-path bias d,
  * var_floor the Chebyshev variance floor, d_max the probe-ray depth clamp. */
 typedef struct gi_probes {
     uint32_t dims[3];

@@ -55,8 +55,10 @@ __device__ __forceinline__ uint4 philox(uint64_t seed, uint32_t c0, uint32_t c1,
     uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        // one full 32x32->64 product per word (a single multiply instruction)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
@@ -133,12 +135,12 @@ __device__ __forceinline__ float isect_sphere(V3 o, V3 d, V3 c, float r)
     return kInf;
 }
 
-// slab test; on a hit returns t and the face axis
-__device__ __forceinline__ float isect_box(V3 o, V3 inv, V3 c, V3 h, int &axis)
+// slab test of the box [lo, hi]; on a hit returns t and the face axis
+__device__ __forceinline__ float isect_box(V3 o, V3 inv, V3 lo, V3 hi, int &axis)
 {
-    float ax = (c.x - h.x - o.x) * inv.x, bx = (c.x + h.x - o.x) * inv.x;
-    float ay = (c.y - h.y - o.y) * inv.y, by = (c.y + h.y - o.y) * inv.y;
-    float az = (c.z - h.z - o.z) * inv.z, bz = (c.z + h.z - o.z) * inv.z;
+    float ax = (lo.x - o.x) * inv.x, bx = (hi.x - o.x) * inv.x;
+    float ay = (lo.y - o.y) * inv.y, by = (hi.y - o.y) * inv.y;
+    float az = (lo.z - o.z) * inv.z, bz = (hi.z - o.z) * inv.z;
     float lx = fminf(ax, bx), hx = fmaxf(ax, bx);
     float ly = fminf(ay, by), hy = fmaxf(ay, by);
     float lz = fminf(az, bz), hz = fmaxf(az, bz);
@@ -176,11 +178,25 @@ __device__ __forceinline__ float isect_room(const gi_scene &sc, V3 o, V3 d, int 
     return best;
 }
 
+// Geometry as the intersection tests take it: a sphere as (centre, type)
+// and (radius, -, -); a box as (lo corner, type) and (hi corner), the
+// corners formed as centre -/+ half extent.
 struct PrimGeo {
-    V3 c;
+    V3 c;           // sphere centre, or box lo corner
     uint32_t type;
-    V3 s;
+    V3 s;           // sphere radius in s.x, or box hi corner
 };
+
+__device__ __forceinline__ void geo_records(float4 a, float4 b, float4 &ga, float4 &gb)
+{
+    if (__float_as_uint(a.w) == 0u) {
+        ga = a;
+        gb = b;
+    } else {
+        ga = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w);
+        gb = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, b.w);
+    }
+}
 
 __device__ __forceinline__ PrimGeo geo_of(float4 a, float4 b)
 {
@@ -190,7 +206,9 @@ __device__ __forceinline__ PrimGeo geo_of(float4 a, float4 b)
 __device__ __forceinline__ PrimGeo load_geo(const gi_prim *prims, uint32_t i)
 {
     const float4 *p = reinterpret_cast<const float4 *>(prims + i);
-    return geo_of(p[0], p[1]);
+    float4 ga, gb;
+    geo_records(p[0], p[1], ga, gb);
+    return geo_of(ga, gb);
 }
 
 // Scene access through the caller's device buffers.
@@ -207,7 +225,8 @@ struct GeoGlobal {
 };
 
 // Scene access through a workgroup-local copy in LDS (see stage_scene):
-// [2 float4 of geometry per primitive][cell_start: ncells+1][items]
+// [2 float4 of geometry per primitive, as geo_records forms them]
+// [cell_start: ncells+1][items]
 extern __shared__ float4 gi_lds[];
 
 struct GeoLds {
@@ -240,7 +259,7 @@ __device__ __forceinline__ void stage_scene(const gi_scene &sc)
 {
     const float4 *src = reinterpret_cast<const float4 *>(sc.prims);
     const uint32_t n2 = 2u * sc.n_prims, bs = blockDim.x;
-    for (uint32_t i = threadIdx.x; i < n2; i += bs) gi_lds[i] = src[(i >> 1) * 4u + (i & 1u)];
+    for (uint32_t i = threadIdx.x; i < sc.n_prims; i += bs) geo_records(src[4u * i], src[4u * i + 1u], gi_lds[2u * i], gi_lds[2u * i + 1u]);
     uint32_t *w = reinterpret_cast<uint32_t *>(gi_lds + n2);
     const uint32_t nc = sc.grid_res[0] * sc.grid_res[1] * sc.grid_res[2] + 1u;
     for (uint32_t i = threadIdx.x; i < nc; i += bs) w[i] = sc.cell_start[i];
@@ -248,20 +267,26 @@ __device__ __forceinline__ void stage_scene(const gi_scene &sc)
     __syncthreads();
 }
 
-// test one primitive; keep the lexicographically smallest (t, id)
+// keep the lexicographically smallest (t, id): equal distances go to the
+// lower id; a miss (t = inf) never counts, even when the running best is
+// still the initial tmax = inf
+__device__ __forceinline__ void take_hit(Hit &h, float t, uint32_t i, int axis)
+{
+    if (t < h.t || (t == h.t && t < kInf && i < h.prim)) {
+        h.t = t;
+        h.prim = i;
+        h.axis = axis;
+    }
+}
+
+// test one primitive of either type
 template <class G>
 __device__ __forceinline__ void test_prim(const G &acc, uint32_t i, V3 o, V3 d, V3 inv, Hit &h)
 {
     PrimGeo g = acc.geo(i);
     int axis = -1;
     float t = g.type == 0u ? isect_sphere(o, d, g.c, g.s.x) : isect_box(o, inv, g.c, g.s, axis);
-    // equal distances go to the lower id; a miss (t = inf) never counts,
-    // even when the running best is still the initial tmax = inf
-    if (t < h.t || (t == h.t && t < kInf && i < h.prim)) {
-        h.t = t;
-        h.prim = i;
-        h.axis = g.type == 0u ? -1 : axis;
-    }
+    take_hit(h, t, i, g.type == 0u ? -1 : axis);
 }
 
 // any surface crossing of a primitive in (0, tmax)?
@@ -321,6 +346,15 @@ __device__ __forceinline__ bool cast(const gi_scene &sc, const G &acc, V3 o, V3 
     int iy = min(max((int)floorf((ps.y - sc.grid_lo[1]) * ((float)ry / (sc.grid_hi[1] - sc.grid_lo[1]))), 0), ry - 1);
     int iz = min(max((int)floorf((ps.z - sc.grid_lo[2]) * ((float)rz / (sc.grid_hi[2] - sc.grid_lo[2]))), 0), rz - 1);
     const int sx = d.x >= 0.0f ? 1 : -1, sy = d.y >= 0.0f ? 1 : -1, sz = d.z >= 0.0f ? 1 : -1;
+    // ray parameter of the next cell face crossed on each axis, advanced by
+    // one cell's width per step; the accumulated rounding (a few ulps of t
+    // per step) stays far below the 1e-3-cell padding of the binned boxes
+    float nx = d.x == 0.0f ? kInf : (sc.grid_lo[0] + (float)(ix + (sx > 0)) * cxs - o.x) * inv.x;
+    float ny = d.y == 0.0f ? kInf : (sc.grid_lo[1] + (float)(iy + (sy > 0)) * cys - o.y) * inv.y;
+    float nz = d.z == 0.0f ? kInf : (sc.grid_lo[2] + (float)(iz + (sz > 0)) * czs - o.z) * inv.z;
+    const float dx = d.x == 0.0f ? kInf : cxs * fabsf(inv.x);
+    const float dy = d.y == 0.0f ? kInf : cys * fabsf(inv.y);
+    const float dz = d.z == 0.0f ? kInf : czs * fabsf(inv.z);
     const int max_steps = rx + ry + rz + 3;
     for (int step = 0; step < max_steps; ++step) {
         uint32_t cell = (uint32_t)(ix + rx * (iy + ry * iz));
@@ -333,19 +367,19 @@ __device__ __forceinline__ bool cast(const gi_scene &sc, const G &acc, V3 o, V3 
                 test_prim(acc, i, o, d, inv, h);
             }
         }
-        float nx = d.x == 0.0f ? kInf : (sc.grid_lo[0] + (float)(ix + (sx > 0)) * cxs - o.x) * inv.x;
-        float ny = d.y == 0.0f ? kInf : (sc.grid_lo[1] + (float)(iy + (sy > 0)) * cys - o.y) * inv.y;
-        float nz = d.z == 0.0f ? kInf : (sc.grid_lo[2] + (float)(iz + (sz > 0)) * czs - o.z) * inv.z;
         float texit = fminf(nx, fminf(ny, nz));
         if (texit >= fminf(t1, h.t)) break;
         if (nx <= ny && nx <= nz) {
             ix += sx;
+            nx += dx;
             if (ix < 0 || ix >= rx) break;
         } else if (ny <= nz) {
             iy += sy;
+            ny += dy;
             if (iy < 0 || iy >= ry) break;
         } else {
             iz += sz;
+            nz += dz;
             if (iz < 0 || iz >= rz) break;
         }
     }
@@ -408,7 +442,8 @@ __device__ __forceinline__ bool visible(const gi_scene &sc, const G &acc, V3 a, 
 // --------------------------------------------------------------------------
 __device__ __forceinline__ float sgnf(float v) { return v >= 0.0f ? 1.0f : -1.0f; }
 
-__device__ __forceinline__ void oct_encode(V3 v, float &u, float &w)
+// signed octahedral coordinates in [-1, 1]^2 of a direction of any length
+__device__ __forceinline__ void oct_encode_signed(V3 v, float &px_, float &py_)
 {
     float l1 = fabsf(v.x) + fabsf(v.y) + fabsf(v.z);
     float il = rcp(l1);
@@ -419,8 +454,8 @@ __device__ __forceinline__ void oct_encode(V3 v, float &u, float &w)
         px = fx;
         py = fy;
     }
-    u = 0.5f * (px + 1.0f);
-    w = 0.5f * (py + 1.0f);
+    px_ = px;
+    py_ = py;
 }
 
 __device__ __forceinline__ V3 oct_decode(float u, float w)
@@ -456,8 +491,10 @@ struct Bilin {
 __device__ __forceinline__ Bilin bilin(V3 dir, int N)
 {
     float u, w;
-    oct_encode(dir, u, w);
-    float fx = u * (float)N + 0.5f, fy = w * (float)N + 0.5f;
+    oct_encode_signed(dir, u, w);
+    // texel coordinate (u + 1)/2 * N + 1/2 of the signed octahedral coordinate u
+    const float h = 0.5f * (float)N;
+    float fx = fmaf(u, h, h + 0.5f), fy = fmaf(w, h, h + 0.5f);
     float x0 = floorf(fx), y0 = floorf(fy);
     Bilin b;
     // u, w lie in [0, 1] so x0, y0 lie in [0, N]; the clamp only guards
@@ -491,62 +528,101 @@ __device__ __forceinline__ float2 fetch_dep(const float4 *probe, V3 dir)
                        w00 * a.y + w10 * a.w + w01 * c.y + w11 * c.w);
 }
 
-// Q(p, n) = E(p, n)/pi: blend of the 8 probes of p's cell
+// Byte sizes of one probe's quad records; a volume of at most kMaxProbes
+// probes keeps both textures under 4 GiB, so the query addresses them with
+// 32-bit byte offsets from the (uniform) texture base.
+constexpr uint32_t kIrrProbeBytes = kIrrProbeF4 * 16u;    // 3888
+constexpr uint32_t kDepProbeBytes = kDepProbeF4 * 16u;    // 9248
+constexpr uint32_t kMaxProbes = 464000u;                  // kMaxProbes * kDepProbeBytes < 2^32
+
+__device__ __forceinline__ const float4 *at_bytes(const float *base, uint32_t off)
+{
+    return reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
+}
+
+// Per-axis quantities of the query cell's two corner layers: offsets of the
+// layers' probe coordinate from p, the trilinear fraction toward the upper
+// layer, and the probe-index step between the layers (0 on a one-probe axis).
+struct QueryAxis {
+    float d0, d1, fr;
+    uint32_t base, step;
+};
+
+__device__ __forceinline__ QueryAxis query_axis(float pv, float lo, float sp, int na, uint32_t stride)
+{
+    QueryAxis q;
+    float g = (pv - lo) / sp - 0.5f;
+    g = fminf(fmaxf(g, 0.0f), (float)(na - 1));
+    const int b = min(max((int)floorf(g), 0), max(na - 2, 0));
+    q.fr = na >= 2 ? g - (float)b : 0.0f;
+    const int i1 = min(b + 1, na - 1);
+    q.d0 = lo + ((float)b + 0.5f) * sp - pv;
+    q.d1 = lo + ((float)i1 + 0.5f) * sp - pv;
+    q.base = (uint32_t)b * stride;
+    q.step = (uint32_t)(i1 - b) * stride;
+    return q;
+}
+
+// Q(p, n) = E(p, n)/pi: blend of the 8 probes of p's cell.
+// The per-axis terms are formed once.  The direction toward p is
+// octahedral-encoded unnormalised (the encoding divides by its L1 norm).
+// Probe indices stay below 2^24, so byte offsets are 24-bit products.
 __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
 {
-    const float4 *irr = reinterpret_cast<const float4 *>(pr.irr);
-    const float4 *dep = reinterpret_cast<const float4 *>(pr.dep);
-    float pv[3] = {p.x, p.y, p.z};
-    int base[3];
-    float fr[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        int na = (int)pr.dims[a];
-        float g = (pv[a] - pr.lo[a]) / pr.spacing[a] - 0.5f;
-        g = fminf(fmaxf(g, 0.0f), (float)(na - 1));
-        int b = min(max((int)floorf(g), 0), max(na - 2, 0));
-        base[a] = b;
-        fr[a] = na >= 2 ? g - (float)b : 0.0f;
-    }
-    V3 sum = v3(0.0f, 0.0f, 0.0f);
-    float wsum = 0.0f;
-    const Bilin bn = bilin(n, kIrrN);   // the irradiance direction is the same for all 8 probes
+    const int nx = (int)pr.dims[0], ny = (int)pr.dims[1], nz = (int)pr.dims[2];
+    const QueryAxis ax = query_axis(p.x, pr.lo[0], pr.spacing[0], nx, 1u);
+    const QueryAxis ay = query_axis(p.y, pr.lo[1], pr.spacing[1], ny, (uint32_t)nx);
+    const QueryAxis az = query_axis(p.z, pr.lo[2], pr.spacing[2], nz, (uint32_t)(nx * ny));
+    const uint32_t base = ax.base + ay.base + az.base;
+    const Bilin bn = bilin(n, kIrrN);
+    const uint32_t irr_q = 48u * (uint32_t)bn.q;
+    const float w00 = (1.0f - bn.ax) * (1.0f - bn.ay), w10 = bn.ax * (1.0f - bn.ay);
+    const float w01 = (1.0f - bn.ax) * bn.ay, w11 = bn.ax * bn.ay;
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f, wsum = 0.0f;
 #ifndef GI_QUERY_UNROLL
 #define GI_QUERY_UNROLL 1
 #endif
 #pragma unroll GI_QUERY_UNROLL
-    for (int c = 0; c < 8; ++c) {
-        int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
-        int ix = min(base[0] + ox, (int)pr.dims[0] - 1);
-        int iy = min(base[1] + oy, (int)pr.dims[1] - 1);
-        int iz = min(base[2] + oz, (int)pr.dims[2] - 1);
-        float tri = (ox ? fr[0] : 1.0f - fr[0]) * (oy ? fr[1] : 1.0f - fr[1]) * (oz ? fr[2] : 1.0f - fr[2]);
-        uint32_t pi = (uint32_t)ix + pr.dims[0] * ((uint32_t)iy + pr.dims[1] * (uint32_t)iz);
-        V3 P = v3(pr.lo[0] + ((float)ix + 0.5f) * pr.spacing[0], pr.lo[1] + ((float)iy + 0.5f) * pr.spacing[1],
-                  pr.lo[2] + ((float)iz + 0.5f) * pr.spacing[2]);
-        V3 tp = P - p;
-        float r2 = dot(tp, tp);
-        float back = 0.45f, vis = 1.0f;
-        if (r2 > 0.0f) {
-            float ir = frsq(r2);
-            float r = r2 * ir;
-            V3 w = ir * tp;
-            float hh = 0.5f * (1.0f + dot(n, w));
-            back = hh * hh + 0.2f;
-            float2 m = fetch_dep(dep + (size_t)pi * kDepProbeF4, -w);
-            if (r > m.x) {
-                float var = fmaxf(fmaf(-m.x, m.x, m.y), pr.var_floor);
-                float dd = r - m.x;
-                float cheb = var * rcp(fmaf(dd, dd, var));
-                vis = cheb * cheb * cheb;
-            }
+    for (int c = 0; c < 4; ++c) {
+        const bool oy = (c & 1) != 0, oz = (c & 2) != 0;
+        const float dy = oy ? ay.d1 : ay.d0, dz = oz ? az.d1 : az.d0;
+        const float ty = oy ? ay.fr : 1.0f - ay.fr, tz = oz ? az.fr : 1.0f - az.fr;
+        const uint32_t pyz = base + (oy ? ay.step : 0u) + (oz ? az.step : 0u);
+#pragma unroll
+        for (int ox = 0; ox < 2; ++ox) {
+            const V3 tp = v3(ox ? ax.d1 : ax.d0, dy, dz);
+            const float tx = ox ? ax.fr : 1.0f - ax.fr;
+            const uint32_t pi = pyz + (ox ? ax.step : 0u);
+            const float r2 = dot(tp, tp);
+            const bool at_probe = !(r2 > 0.0f);
+            const float ir = frsq(r2);
+            const float r = r2 * ir;
+            const float hh = 0.5f * (1.0f + dot(n, tp) * ir);
+            // depth moments toward p (a probe sitting exactly at p reads any texel, unused)
+            const V3 dv = at_probe ? v3(0.0f, 0.0f, 1.0f) : -tp;
+            const Bilin bd = bilin(dv, kDepN);
+            const float4 *dr = at_bytes(pr.dep, __umul24(pi, kDepProbeBytes) + 32u * (uint32_t)bd.q);
+            const float4 da = dr[0], db = dr[1];
+            const float4 *qr = at_bytes(pr.irr, __umul24(pi, kIrrProbeBytes) + irr_q);
+            const float4 e0 = qr[0], e1 = qr[1], e2 = qr[2];
+            const float v00 = (1.0f - bd.ax) * (1.0f - bd.ay), v10 = bd.ax * (1.0f - bd.ay);
+            const float v01 = (1.0f - bd.ax) * bd.ay, v11 = bd.ax * bd.ay;
+            const float mu = v00 * da.x + v10 * da.z + v01 * db.x + v11 * db.z;
+            const float mu2 = v00 * da.y + v10 * da.w + v01 * db.y + v11 * db.w;
+            const float var = fmaxf(fmaf(-mu, mu, mu2), pr.var_floor);
+            const float dd = r - mu;
+            const float cheb = var * rcp(fmaf(dd, dd, var));
+            const float vis = (!at_probe && r > mu) ? cheb * cheb * cheb : 1.0f;
+            const float back = at_probe ? 0.45f : hh * hh + 0.2f;
+            const float wgt = tx * ty * tz * fmaxf(back * vis, 1e-6f);
+            sx = fmaf(wgt, w00 * e0.x + w10 * e0.w + w01 * e1.z + w11 * e2.y, sx);
+            sy = fmaf(wgt, w00 * e0.y + w10 * e1.x + w01 * e1.w + w11 * e2.z, sy);
+            sz = fmaf(wgt, w00 * e0.z + w10 * e1.y + w01 * e2.x + w11 * e2.w, sz);
+            wsum += wgt;
         }
-        float wgt = tri * fmaxf(back * vis, 1e-6f);
-        V3 e = fetch_irr(irr + (size_t)pi * kIrrProbeF4, bn);
-        sum = madd(sum, wgt, e);
-        wsum += wgt;
     }
-    return rcp(wsum) * sum;
+    const float iw = rcp(wsum);
+    return v3(iw * sx, iw * sy, iw * sz);
 }
 
 // view-path bias: move y toward x by min(d, |x - y|/2)

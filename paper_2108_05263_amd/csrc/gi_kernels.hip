@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(kBlock)
 // LIGHT: emitter candidates present (M_light > 0); without them the loop
 // compiles to the plain cosine-candidate form.
 template <bool LDS, bool WS, bool LIGHT>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, 4)
     k_initial(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_params pp, gi_reservoirs out, float4 *resid,
               uint64_t seed, uint32_t frame, CandWs ws, gi_mlp mlp)
 {
@@ -898,7 +898,8 @@ gi_status check_probes(const gi_probes *p)
     if (!p || !p->irr || !p->dep) return GI_ERR_NULL;
     if (p->irr_res != 8 || p->dep_res != 16) return GI_ERR_SHAPE;
     if (p->dims[0] == 0 || p->dims[1] == 0 || p->dims[2] == 0) return GI_ERR_SHAPE;
-    if ((uint64_t)p->dims[0] * p->dims[1] * p->dims[2] > (1u << 24)) return GI_ERR_SHAPE;
+    // the depth texture (the larger) must stay below 4 GiB: kernels use 32-bit byte offsets
+    if ((uint64_t)p->dims[0] * p->dims[1] * p->dims[2] > kMaxProbes) return GI_ERR_SHAPE;
     for (int a = 0; a < 3; ++a)
         if (!(p->spacing[a] > 0.0f)) return GI_ERR_PARAM;
     return GI_OK;
