@@ -42,6 +42,8 @@ typedef struct {
     double wall_albedo[3], wall_emit[3];
     double sky[3];
     double eps;                     /* ray-origin offset along the surface normal */
+    int32_t glossy;                 /* 1: primitives carry a specular layer (record slots 11, 15) */
+    int32_t pad;
 } o_scene;
 
 typedef struct {
@@ -78,6 +80,11 @@ typedef struct {
     double m_cap;                   /* temporal history cap (multiple of current M) */
     int32_t subsample;              /* n: pixel (x, y) draws candidates in frame f iff (x+y+f) % n == 0 */
     int32_t pad;
+    double eye[3];                  /* camera position of the current frame (glossy primary vertices) */
+    double eye_prev[3];             /* camera position of the previous frame (temporal history) */
+    double foot_c;                  /* footprint threshold c of the shading recursion (Eq. 8) */
+    int32_t glossy_depth;           /* most glossy vertices the shading recursion visits */
+    int32_t pad2;
 } o_params;
 
 enum { GB_POS = 0, GB_NRM = 3, GB_ALB = 6, GB_EMIT = 9, GB_DEPTH = 12, GB_PRIM = 13, GB_N = 14 };
@@ -129,7 +136,8 @@ static void rand4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t
     for (int i = 0; i < 4; ++i) u[i] = u01(out[i]);
 }
 
-enum { PASS_INITIAL = 0, PASS_TEMPORAL = 1, PASS_SPATIAL0 = 2, PASS_PROBE = 9 };
+enum { PASS_INITIAL = 0, PASS_TEMPORAL = 1, PASS_SPATIAL0 = 2, PASS_PROBE = 9,
+       PASS_GLOSSY_CAND = 14, PASS_GLOSSY_PROBE = 15, PASS_GLOSSY_SHADE = 16 };
 
 /* ---------------------------------------------------------------------------
  * Sampling
@@ -137,16 +145,99 @@ enum { PASS_INITIAL = 0, PASS_TEMPORAL = 1, PASS_SPATIAL0 = 2, PASS_PROBE = 9 };
 /* Cosine-weighted direction about n (the Lambertian BSDF sampling of step 1,
  * Sec. 3.1): disk point (sqrt(u1) cos 2pi u0, sqrt(u1) sin 2pi u0), lifted to
  * the hemisphere, expressed in the orthonormal basis of Duff et al. 2017. */
+static void onb(const double *n, double *t, double *bt)
+{
+    double s = n[2] >= 0.0 ? 1.0 : -1.0;
+    double a = -1.0 / (s + n[2]);
+    double b = n[0] * n[1] * a;
+    t[0] = 1.0 + s * n[0] * n[0] * a; t[1] = s * b; t[2] = -s * n[0];
+    bt[0] = b; bt[1] = s + n[1] * n[1] * a; bt[2] = -n[1];
+}
+
 void o_cosine_dir(const double *n, double u0, double u1, double *w)
 {
     double phi = 2.0 * O_PI * u0, r = sqrt(u1);
     double lx = r * cos(phi), ly = r * sin(phi), lz = sqrt(fmax(0.0, 1.0 - u1));
-    double s = n[2] >= 0.0 ? 1.0 : -1.0;
-    double a = -1.0 / (s + n[2]);
-    double b = n[0] * n[1] * a;
-    double t[3] = {1.0 + s * n[0] * n[0] * a, s * b, -s * n[0]};
-    double bt[3] = {b, s + n[1] * n[1] * a, -n[1]};
+    double t[3], bt[3];
+    onb(n, t, bt);
     for (int i = 0; i < 3; ++i) w[i] = lx * t[i] + ly * bt[i] + lz * n[i];
+}
+
+/* ---------------------------------------------------------------------------
+ * Glossy layer (Sec. 3.3: the glossy transport T_fg, "in our case microfacet
+ * models"): an isotropic GGX (Trowbridge-Reitz) lobe with separable Smith
+ * masking and a constant grey specular weight k_s (no Fresnel term):
+ *   f_g(wo, wi) = k_s D(h) G1(wo) G1(wi) / (4 (n.wo) (n.wi)),  h = (wo+wi)/|wo+wi|,
+ *   D(h) = a^2 / (pi ((n.h)^2 (a^2 - 1) + 1)^2),
+ *   G1(v) = 2 (n.v) / ((n.v) + sqrt(a^2 + (1 - a^2) (n.v)^2)).
+ * Sampling draws h with density D(h)(n.h) (Walter et al. 2007):
+ * cos^2(theta_h) = (1 - u0) / (1 + (a^2 - 1) u0), phi = 2 pi u1, and reflects
+ * wo about h; the solid-angle density of wi is D(h)(n.h) / (4 |wo.h|).
+ * ------------------------------------------------------------------------- */
+static double ggx_D(double nh, double a)
+{
+    double a2 = a * a, t = nh * nh * (a2 - 1.0) + 1.0;
+    return a2 / (O_PI * t * t);
+}
+
+static double smith_G1(double nv, double a)
+{
+    double a2 = a * a;
+    return 2.0 * nv / (nv + sqrt(a2 + (1.0 - a2) * nv * nv));
+}
+
+/* f_g / k_s; 0 unless both directions lie above the surface */
+static double ggx_eval(const double *n, const double *wo, const double *wi, double a)
+{
+    double no = dot3(n, wo), ni = dot3(n, wi);
+    if (no <= 0.0 || ni <= 0.0) return 0.0;
+    double h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
+    normalize3(h);
+    return ggx_D(dot3(n, h), a) * smith_G1(no, a) * smith_G1(ni, a) / (4.0 * no * ni);
+}
+
+/* solid-angle density of sampling wi from the lobe about wo */
+static double ggx_pdf(const double *n, const double *wo, const double *wi, double a)
+{
+    if (dot3(n, wi) <= 0.0 || dot3(n, wo) <= 0.0) return 0.0;
+    double h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
+    normalize3(h);
+    double nh = dot3(n, h), oh = fabs(dot3(wo, h));
+    return oh > 0.0 ? ggx_D(nh, a) * nh / (4.0 * oh) : 0.0;
+}
+
+/* a direction from the lobe about wo; returns 0 (and no direction) when the
+ * reflected direction falls below the surface */
+static int ggx_sample(const double *n, const double *wo, double a, double u0, double u1, double *wi)
+{
+    double c2 = (1.0 - u0) / (1.0 + (a * a - 1.0) * u0);
+    double ct = sqrt(c2), st = sqrt(fmax(0.0, 1.0 - c2)), phi = 2.0 * O_PI * u1;
+    double t[3], bt[3], h[3];
+    onb(n, t, bt);
+    for (int i = 0; i < 3; ++i) h[i] = st * cos(phi) * t[i] + st * sin(phi) * bt[i] + ct * n[i];
+    double oh = dot3(wo, h);
+    for (int i = 0; i < 3; ++i) wi[i] = 2.0 * oh * h[i] - wo[i];
+    return dot3(n, wi) > 0.0 && dot3(n, wo) > 0.0;
+}
+
+void o_ggx(const double *n, const double *wo, const double *wi, double a, double *out)
+{
+    out[0] = ggx_eval(n, wo, wi, a);
+    out[1] = ggx_pdf(n, wo, wi, a);
+}
+
+int o_ggx_sample(const double *n, const double *wo, double a, double u0, double u1, double *wi)
+{
+    return ggx_sample(n, wo, a, u0, u1, wi);
+}
+
+/* f_g / k_s and the sampling density for k directions wi (rows of 3) */
+void o_ggx_many(const double *n, const double *wo, const double *wi, int64_t k, double a, double *f, double *pdf)
+{
+    for (int64_t i = 0; i < k; ++i) {
+        f[i] = ggx_eval(n, wo, wi + 3 * i, a);
+        pdf[i] = ggx_pdf(n, wo, wi + 3 * i, a);
+    }
 }
 
 /* Uniform direction on the unit sphere (probe-update rays). */
@@ -265,6 +356,43 @@ static void material(const o_scene *sc, uint32_t prim, double *alb, double *emit
     } else {
         for (int i = 0; i < 3; ++i) { alb[i] = sc->wall_albedo[i]; emit[i] = sc->wall_emit[i]; }
     }
+}
+
+/* specular weight k_s and GGX roughness of a primitive (record slots 11 and
+ * 15); walls and diffuse scenes have none */
+static void spec_of(const o_scene *sc, uint32_t prim, double *ks, double *a)
+{
+    *ks = 0.0;
+    *a = 1.0;
+    if (sc->glossy && prim < (uint32_t)sc->n_prims) {
+        const double *rec = sc->prims + 16 * (size_t)prim;
+        *ks = rec[11];
+        *a = rec[15];
+    }
+}
+
+/* Primary-vertex sampling picks the glossy lobe with probability
+ * k_s / (k_s + lum(rho)) and the cosine lobe otherwise (one-sample mixture
+ * of the whole BSDF, Sec. 3.3: p_1 is proportional to the entire BSDF). */
+static double p_gloss(const double *rho, double ks)
+{
+    return ks > 0.0 ? ks / (ks + lum(rho)) : 0.0;
+}
+
+/* density of the mixture, solid angle */
+static double mix_pdf(const double *rho, double ks, double a, const double *n, const double *wo, const double *wi)
+{
+    double pg = p_gloss(rho, ks), c = dot3(n, wi);
+    double pd = c > 0.0 ? c / O_PI : 0.0;
+    return (1.0 - pg) * pd + (pg > 0.0 ? pg * ggx_pdf(n, wo, wi, a) : 0.0);
+}
+
+/* full BSDF f = rho/pi + k_s f_g(wo, wi) (RGB) */
+static void bsdf(const double *rho, double ks, double a, const double *n, const double *wo, const double *wi,
+                 double *f)
+{
+    double g = ks > 0.0 ? ks * ggx_eval(n, wo, wi, a) : 0.0;
+    for (int c = 0; c < 3; ++c) f[c] = rho[c] / O_PI + g;
 }
 
 /* Mutual visibility V(a, b) of two surface points (each lifted by eps along its
@@ -539,34 +667,72 @@ void o_mlp_forward(const double *params, int prec, const double *lo, const doubl
     for (int c = 0; c < 3; ++c) out[c] = a[c];
 }
 
+/* Glossy part of L_DDGI+ (Eq. 6) at a surface point: (1/2pi) times the
+ * integral of E(p, wi) f_g(wo, wi) cos(theta_i) over wi, estimated with one
+ * direction wi drawn from the glossy lobe (u0, u1): (1/2pi) E(p, wi) f_g cos / pdf.
+ * The probes store E/pi, so E(p, wi)/(2 pi) = Q(p, wi)/2, where Q(p, wi) is the
+ * probe query with the direction wi in place of the normal (the irradiance
+ * read as cosine-prefiltered radiance). */
+static void glossy_term(const o_probes *pr, const double *pb, const double *n, const double *wo, double ks,
+                        double a, double u0, double u1, double *out)
+{
+    out[0] = out[1] = out[2] = 0.0;
+    double wi[3];
+    if (!ggx_sample(n, wo, a, u0, u1, wi)) return;
+    double pdf = ggx_pdf(n, wo, wi, a);
+    if (!(pdf > 0.0)) return;
+    double w = ks * ggx_eval(n, wo, wi, a) * dot3(n, wi) / pdf;
+    double q[3];
+    probe_query(pr, pb, wi, 0, q);
+    for (int c = 0; c < 3; ++c) out[c] = 0.5 * w * q[c];
+}
+
+void o_glossy_term(const o_probes *pr, const double *pb, const double *n, const double *wo, double ks, double a,
+                   double u0, double u1, double *out)
+{
+    glossy_term(pr, pb, n, wo, ks, a, u0, u1, out);
+}
+
 /* Radiance leaving surface point y toward x: L_e(y) + rho_y * C(y), the
  * radiance L_DDGI+ of Eq. 4/5 (diffuse term rho/pi * E = rho * E/pi).  C is
  * the probe query Q(y_b, n_y) at the view-path-biased point, or, when a
  * learned cache is set and allowed, its output max(0, MLP(y, n_y)) at y
- * itself (the bias only guards the probes' visibility test). */
+ * itself (the bias only guards the probes' visibility test).  A surface with
+ * a specular layer adds the glossy part of Eq. 6 (one lobe sample, uniforms
+ * ug) at the same biased point; ug = NULL leaves it out. */
 static void radiance_toward_ex(const o_scene *sc, const o_probes *pr, uint32_t prim, const double *y,
-                               const double *ny, const double *x, int allow_mlp, double *L)
+                               const double *ny, const double *x, int allow_mlp, const double *ug, double *L)
 {
-    double alb[3], emit[3];
+    double alb[3], emit[3], ks, ra;
     material(sc, prim, alb, emit);
+    spec_of(sc, prim, &ks, &ra);
     for (int a = 0; a < 3; ++a) L[a] = emit[a];
-    if (alb[0] == 0.0 && alb[1] == 0.0 && alb[2] == 0.0) return;
-    double q[3];
-    if (allow_mlp && pr->mlp) {
-        o_mlp_forward(pr->mlp, pr->mlp_prec, pr->mlp_lo, pr->mlp_hi, y, ny, q);
-        for (int a = 0; a < 3; ++a) q[a] = fmax(q[a], 0.0);
-    } else {
-        double pb[3];
-        o_view_bias(y, x, pr->bias_dist, pb);
-        probe_query(pr, pb, ny, 0, q);
+    int diffuse = alb[0] != 0.0 || alb[1] != 0.0 || alb[2] != 0.0;
+    if (diffuse) {
+        double q[3];
+        if (allow_mlp && pr->mlp) {
+            o_mlp_forward(pr->mlp, pr->mlp_prec, pr->mlp_lo, pr->mlp_hi, y, ny, q);
+            for (int a = 0; a < 3; ++a) q[a] = fmax(q[a], 0.0);
+        } else {
+            double pb[3];
+            o_view_bias(y, x, pr->bias_dist, pb);
+            probe_query(pr, pb, ny, 0, q);
+        }
+        for (int a = 0; a < 3; ++a) L[a] += alb[a] * q[a];
     }
-    for (int a = 0; a < 3; ++a) L[a] += alb[a] * q[a];
+    if (ks > 0.0 && ug) {
+        double pb[3], wo[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]}, g[3];
+        normalize3(wo);
+        o_view_bias(y, x, pr->bias_dist, pb);
+        glossy_term(pr, pb, ny, wo, ks, ra, ug[0], ug[1], g);
+        for (int a = 0; a < 3; ++a) L[a] += g[a];
+    }
 }
 
 static void radiance_toward(const o_scene *sc, const o_probes *pr, uint32_t prim, const double *y,
                             const double *ny, const double *x, double *L)
 {
-    radiance_toward_ex(sc, pr, prim, y, ny, x, 1, L);
+    radiance_toward_ex(sc, pr, prim, y, ny, x, 1, NULL, L);
 }
 
 /* ---------------------------------------------------------------------------
@@ -626,6 +792,16 @@ void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, doub
                     o_view_bias(hp, Pp, in->bias_dist, hb);
                     probe_query(in, hb, h.n, 0, qv);
                     for (int a = 0; a < 3; ++a) Ls[r][a] += alb[a] * qv[a];
+                }
+                double ks, ra;
+                spec_of(sc, h.prim, &ks, &ra);
+                if (ks > 0.0) {
+                    /* L_DDGI+ with its glossy part (Eq. 6) toward the probe */
+                    double hb[3], ug[4], wo[3] = {-dirs[r][0], -dirs[r][1], -dirs[r][2]}, gq[3];
+                    o_view_bias(hp, Pp, in->bias_dist, hb);
+                    rand4(seed, (uint32_t)pi, frame, PASS_GLOSSY_PROBE, (uint32_t)r, ug);
+                    glossy_term(in, hb, h.n, wo, ks, ra, ug[0], ug[1], gq);
+                    for (int a = 0; a < 3; ++a) Ls[r][a] += gq[a];
                 }
                 ds[r] = fmin(h.t, in->d_max);
             } else {
@@ -699,8 +875,35 @@ static double target(const double *x, const double *nx, const double *rho, const
     return lum(f) * fmin(G, g_max);
 }
 
-static double res_target(const double *g, const double *r, double g_max)
+/* The same with the full BSDF of a glossy scene: f(x, wo, wi) = rho/pi +
+ * k_s f_g(wo, wi), wo toward the camera at eye, wi toward the sample. */
+static double target_glossy(const o_scene *sc, const double *g, const double *eye, const double *y,
+                            const double *ny, const double *L, double g_max)
 {
+    const double *x = g + GB_POS, *nx = g + GB_NRM, *rho = g + GB_ALB;
+    double ks, a, f[3], wo[3] = {eye[0] - x[0], eye[1] - x[1], eye[2] - x[2]};
+    spec_of(sc, (uint32_t)g[GB_PRIM], &ks, &a);
+    normalize3(wo);
+    if (ny[0] == 0.0 && ny[1] == 0.0 && ny[2] == 0.0) {
+        double cx = dot3(nx, y);
+        if (cx <= 0.0) return 0.0;
+        bsdf(rho, ks, a, nx, wo, y, f);
+        double fl[3] = {f[0] * L[0], f[1] * L[1], f[2] * L[2]};
+        return lum(fl) * cx;
+    }
+    double v[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+    double d2 = dot3(v, v), d = sqrt(d2);
+    double w[3] = {v[0] / d, v[1] / d, v[2] / d};
+    double cx = dot3(nx, w), cy = -dot3(ny, w);
+    if (cx <= 0.0 || cy <= 0.0) return 0.0;
+    bsdf(rho, ks, a, nx, wo, w, f);
+    double fl[3] = {f[0] * L[0], f[1] * L[1], f[2] * L[2]};
+    return lum(fl) * fmin(cx * cy / d2, g_max);
+}
+
+static double res_target(const o_scene *sc, const double *g, const double *eye, const double *r, double g_max)
+{
+    if (sc->glossy) return target_glossy(sc, g, eye, r + R_Y, r + R_NY, r + R_L, g_max);
     return target(g + GB_POS, g + GB_NRM, g + GB_ALB, r + R_Y, r + R_NY, r + R_L, g_max);
 }
 
@@ -709,10 +912,14 @@ static int res_is_sky(const double *r)
     return r[R_NY] == 0.0 && r[R_NY + 1] == 0.0 && r[R_NY + 2] == 0.0;
 }
 
-static int pixel_active(const double *g)
+/* a pixel is shaded when its surface reflects: diffuse albedo or a specular layer */
+static int pixel_active(const o_scene *sc, const double *g)
 {
-    return (uint32_t)g[GB_PRIM] != O_MISS &&
-           (g[GB_ALB] != 0.0 || g[GB_ALB + 1] != 0.0 || g[GB_ALB + 2] != 0.0);
+    if ((uint32_t)g[GB_PRIM] == O_MISS) return 0;
+    if (g[GB_ALB] != 0.0 || g[GB_ALB + 1] != 0.0 || g[GB_ALB + 2] != 0.0) return 1;
+    double ks, a;
+    spec_of(sc, (uint32_t)g[GB_PRIM], &ks, &a);
+    return ks > 0.0;
 }
 
 static void res_empty(double *r, double M)
@@ -794,10 +1001,18 @@ void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *g
         const double *g = gb + GB_N * p;
         double *r = res + R_N * p, *rs = resid + 3 * p;
         rs[0] = rs[1] = rs[2] = 0.0;
-        if (!pixel_active(g)) { res_empty(r, 0.0); continue; }
+        if (!pixel_active(sc, g)) { res_empty(r, 0.0); continue; }
         const double *x = g + GB_POS, *nx = g + GB_NRM, *rho = g + GB_ALB;
         double o[3];
         for (int a = 0; a < 3; ++a) o[a] = x[a] + sc->eps * nx[a];
+        /* glossy scene: the whole BSDF at x, wo toward the camera (Sec. 3.3) */
+        double ks_x = 0.0, a_x = 1.0, pg_x = 0.0, wo_x[3] = {0.0, 0.0, 1.0};
+        if (sc->glossy) {
+            spec_of(sc, (uint32_t)g[GB_PRIM], &ks_x, &a_x);
+            pg_x = p_gloss(rho, ks_x);
+            for (int a = 0; a < 3; ++a) wo_x[a] = pp->eye[a] - x[a];
+            normalize3(wo_x);
+        }
         double wsum = 0.0, p_sel = 0.0;
         int have = 0;
         res_empty(r, 0.0);
@@ -809,13 +1024,16 @@ void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *g
             rand4(seed, (uint32_t)p, frame, PASS_INITIAL, (uint32_t)i, u);
             double y[3], ny[3] = {0, 0, 0}, L[3], phat = 0.0, wi = 0.0;
             uint32_t prim = O_MISS;
-            int surface = 0;
+            int surface = 0, dir_ok = 1;
             double u_dec = u[2];
             if (i < Mb) {
-                /* BSDF (cosine) candidate: the first surface along the ray */
-                o_cosine_dir(nx, u[0], u[1], w);
+                /* BSDF candidate: the first surface along the ray; cosine-distributed,
+                 * or in a glossy scene drawn from the glossy lobe with probability
+                 * p_gloss (u3), a lobe sample below the surface giving no candidate */
+                if (pg_x > 0.0 && u[3] < pg_x) dir_ok = ggx_sample(nx, wo_x, a_x, u[0], u[1], w);
+                else o_cosine_dir(nx, u[0], u[1], w);
                 o_hit h;
-                if (closest_hit(sc, o, w, O_INF, &h)) {
+                if (dir_ok && closest_hit(sc, o, w, O_INF, &h)) {
                     for (int a = 0; a < 3; ++a) { y[a] = o[a] + h.t * w[a]; ny[a] = h.n[a]; }
                     prim = h.prim;
                     surface = 1;
@@ -839,25 +1057,52 @@ void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *g
                 double wv[3] = {v[0] / d, v[1] / d, v[2] / d};
                 double cx = dot3(nx, wv), cy = -dot3(ny, wv);
                 if (cx > 0.0 && cy > 0.0) {
-                    radiance_toward(sc, pr, prim, y, ny, x, L);
-                    double G = cx * cy / d2;
-                    double f[3] = {rho[0] / O_PI * L[0], rho[1] / O_PI * L[1], rho[2] / O_PI * L[2]};
+                    double G = cx * cy / d2, f[3], pA;
+                    if (sc->glossy) {
+                        /* f(x, wo, wi) L(y) with L_DDGI+ at y including its glossy part
+                         * (one lobe sample, counter (p, frame, 14, i)); p_A from the
+                         * BSDF mixture's solid-angle density */
+                        double ug[4], fb[3];
+                        rand4(seed, (uint32_t)p, frame, PASS_GLOSSY_CAND, (uint32_t)i, ug);
+                        radiance_toward_ex(sc, pr, prim, y, ny, x, 1, ug, L);
+                        bsdf(rho, ks_x, a_x, nx, wo_x, wv, fb);
+                        for (int a = 0; a < 3; ++a) f[a] = fb[a] * L[a];
+                        pA = mix_pdf(rho, ks_x, a_x, nx, wo_x, wv) * cy / d2;
+                    } else {
+                        radiance_toward(sc, pr, prim, y, ny, x, L);
+                        for (int a = 0; a < 3; ++a) f[a] = rho[a] / O_PI * L[a];
+                        pA = cx / O_PI * cy / d2;
+                    }
                     phat = lum(f) * fmin(G, pp->g_max);
                     /* balance heuristic: p_hat over the candidates' mixture density
                      * (Mb p_bsdf + Ml p_light) / Mt, area measure */
-                    double pA = cx / O_PI * cy / d2;
-                    if (Ml == 0) wi = phat / pA;
+                    if (!(pA > 0.0) && Ml == 0) wi = 0.0;
+                    else if (Ml == 0) wi = phat / pA;
                     else wi = phat * Mt / (Mb * pA + Ml * light_pdf(sc, em, n_em, prim));
-                    if (i == 0 && G > pp->g_max)
-                        for (int a = 0; a < 3; ++a) rs[a] = rho[a] * L[a] * (1.0 - pp->g_max / G);
+                    if (i == 0 && G > pp->g_max) {
+                        /* residual f L (G - G_max) / p_A: for the Lambertian BSDF
+                         * rho L (1 - G_max / G) */
+                        if (sc->glossy)
+                            for (int a = 0; a < 3; ++a) rs[a] = pA > 0.0 ? f[a] * (G - pp->g_max) / pA : 0.0;
+                        else
+                            for (int a = 0; a < 3; ++a) rs[a] = rho[a] * L[a] * (1.0 - pp->g_max / G);
+                    }
                 }
-            } else if (i < Mb) {
+            } else if (i < Mb && dir_ok) {
                 for (int a = 0; a < 3; ++a) { y[a] = w[a]; L[a] = sc->sky[a]; }
                 double cx = dot3(nx, w);
                 if (cx > 0.0) {
-                    double f[3] = {rho[0] / O_PI * L[0], rho[1] / O_PI * L[1], rho[2] / O_PI * L[2]};
-                    phat = lum(f) * cx;
-                    wi = phat / (cx / O_PI) * ((double)Mt / Mb);
+                    if (sc->glossy) {
+                        double fb[3], f[3], pd = mix_pdf(rho, ks_x, a_x, nx, wo_x, w);
+                        bsdf(rho, ks_x, a_x, nx, wo_x, w, fb);
+                        for (int a = 0; a < 3; ++a) f[a] = fb[a] * L[a];
+                        phat = lum(f) * cx;
+                        wi = pd > 0.0 ? phat / pd * ((double)Mt / Mb) : 0.0;
+                    } else {
+                        double f[3] = {rho[0] / O_PI * L[0], rho[1] / O_PI * L[1], rho[2] / O_PI * L[2]};
+                        phat = lum(f) * cx;
+                        wi = phat / (cx / O_PI) * ((double)Mt / Mb);
+                    }
                 }
             }
             if (!draws) break;
@@ -890,17 +1135,19 @@ typedef struct {
     const double *sel;
 } merge_state;
 
-static void merge_in(merge_state *s, const double *g, const double *rq, double Mq, double u, double g_max)
+static void merge_in(const o_scene *sc, merge_state *s, const double *g, const double *eye, const double *rq,
+                     double Mq, double u, double g_max)
 {
     double w = 0.0;
-    if (rq[R_W] > 0.0 && Mq > 0.0) w = res_target(g, rq, g_max) * rq[R_W] * Mq;
+    if (rq[R_W] > 0.0 && Mq > 0.0) w = res_target(sc, g, eye, rq, g_max) * rq[R_W] * Mq;
     s->wsum += w;
     s->Msum += Mq;
     if (u * s->wsum < w) s->sel = rq;
 }
 
 static void finish_merge(const o_scene *sc, const merge_state *s, const double *g, int ndom,
-                         const double *const *gdom, const double *Mdom, const o_params *pp, double *out)
+                         const double *const *gdom, const double *const *edom, const double *Mdom,
+                         const o_params *pp, double *out)
 {
     double tmp[R_N];
     if (!s->sel) {
@@ -910,7 +1157,7 @@ static void finish_merge(const o_scene *sc, const merge_state *s, const double *
         return;
     }
     memcpy(tmp, s->sel, sizeof tmp);
-    double ph = res_target(g, tmp, pp->g_max);
+    double ph = res_target(sc, g, edom[0], tmp, pp->g_max);
     double Z;
     int keep = 1;
     if (pp->unbiased) {
@@ -924,7 +1171,7 @@ static void finish_merge(const o_scene *sc, const merge_state *s, const double *
         for (int j = 0; j < ndom; ++j) {
             const double *gq = gdom[j];
             if (Mdom[j] <= 0.0) continue;
-            if (res_target(gq, tmp, pp->g_max) <= 0.0) continue;
+            if (res_target(sc, gq, edom[j], tmp, pp->g_max) <= 0.0) continue;
             int v = j == 0 ? vis_x : o_visible(sc, gq + GB_POS, gq + GB_NRM, tmp + R_Y, tmp + R_NY, sky);
             if (!v) continue;
             Z += Mdom[j];
@@ -970,23 +1217,23 @@ void o_resample_temporal(const o_scene *sc, int32_t W, int32_t H, const double *
         int64_t p = pix ? pix[q] : q;
         const double *g = gb + GB_N * p;
         const double *rc = cur + R_N * p;
-        if (!pixel_active(g)) { memcpy(out + R_N * p, rc, sizeof(double) * R_N); continue; }
+        if (!pixel_active(sc, g)) { memcpy(out + R_N * p, rc, sizeof(double) * R_N); continue; }
         merge_state s = {0.0, 0.0, NULL};
-        const double *gdom[2];
+        const double *gdom[2], *edom[2];
         double Mdom[2];
         int nd = 0;
-        merge_in(&s, g, rc, rc[R_M], 0.0, pp->g_max);
-        gdom[nd] = g; Mdom[nd] = rc[R_M]; ++nd;
+        merge_in(sc, &s, g, pp->eye, rc, rc[R_M], 0.0, pp->g_max);
+        gdom[nd] = g; edom[nd] = pp->eye; Mdom[nd] = rc[R_M]; ++nd;
         int64_t pp_idx = o_reproject(cam_prev, g + GB_POS);
         if (pp_idx >= 0 && similar(g, gb_prev + GB_N * pp_idx, pp)) {
             const double *rh = hist + R_N * pp_idx;
             double Mh = fmin(rh[R_M], pp->m_cap * rc[R_M]);
             double u[4];
             rand4(seed, (uint32_t)p, frame, PASS_TEMPORAL, 0u, u);
-            merge_in(&s, g, rh, Mh, u[0], pp->g_max);
-            gdom[nd] = gb_prev + GB_N * pp_idx; Mdom[nd] = Mh; ++nd;
+            merge_in(sc, &s, g, pp->eye, rh, Mh, u[0], pp->g_max);
+            gdom[nd] = gb_prev + GB_N * pp_idx; edom[nd] = pp->eye_prev; Mdom[nd] = Mh; ++nd;
         }
-        finish_merge(sc, &s, g, nd, gdom, Mdom, pp, out + R_N * p);
+        finish_merge(sc, &s, g, nd, gdom, edom, Mdom, pp, out + R_N * p);
     }
 }
 
@@ -1017,16 +1264,17 @@ void o_resample_spatial(const o_scene *sc, int32_t W, int32_t H, const double *g
                         int64_t npix, double *out)
 {
     int64_t n = pix ? npix : (int64_t)W * H;
-    const double *gdom[16];
+    const double *gdom[16], *edom[16];
     double Mdom[16];
+    for (int j = 0; j < 16; ++j) edom[j] = pp->eye;
     for (int64_t q = 0; q < n; ++q) {
         int64_t p = pix ? pix[q] : q;
         const double *g = gb + GB_N * p;
         const double *rc = in + R_N * p;
-        if (!pixel_active(g)) { memcpy(out + R_N * p, rc, sizeof(double) * R_N); continue; }
+        if (!pixel_active(sc, g)) { memcpy(out + R_N * p, rc, sizeof(double) * R_N); continue; }
         merge_state s = {0.0, 0.0, NULL};
         int nd = 0;
-        merge_in(&s, g, rc, rc[R_M], 0.0, pp->g_max);
+        merge_in(sc, &s, g, pp->eye, rc, rc[R_M], 0.0, pp->g_max);
         gdom[nd] = g; Mdom[nd] = rc[R_M]; ++nd;
         for (int j = 0; j < pp->k && j < 15; ++j) {
             double u2;
@@ -1035,10 +1283,10 @@ void o_resample_spatial(const o_scene *sc, int32_t W, int32_t H, const double *g
             const double *gq = gb + GB_N * qq;
             if (!similar(g, gq, pp)) continue;
             const double *rq = in + R_N * qq;
-            merge_in(&s, g, rq, rq[R_M], u2, pp->g_max);
+            merge_in(sc, &s, g, pp->eye, rq, rq[R_M], u2, pp->g_max);
             gdom[nd] = gq; Mdom[nd] = rq[R_M]; ++nd;
         }
-        finish_merge(sc, &s, g, nd, gdom, Mdom, pp, out + R_N * p);
+        finish_merge(sc, &s, g, nd, gdom, edom, Mdom, pp, out + R_N * p);
     }
 }
 
@@ -1048,9 +1296,64 @@ void o_resample_spatial(const o_scene *sc, int32_t W, int32_t H, const double *g
  * radiance query biased toward this x (the per-vertex query of Sec. 3.6) and
  * one shadow ray.  A primary ray that left the scene shows the sky.
  * ------------------------------------------------------------------------- */
+/* Specular recursion for shading (Sec. 3.3, Eq. 7-8), a glossy scene's
+ * radiance leaving surface point v (primitive prim, normal nv) toward the
+ * previous path vertex prev: L_e(v) + rho_v Q(v_b, n_v), the diffuse part
+ * always from the probes, plus the glossy part of one direction wi drawn from
+ * v's glossy lobe (counter (pixel, frame, 16, depth)), weighted by
+ * k_s f_g cos / pdf.  The path's footprint a(x_1 .. x_n) = (sum over its
+ * segments of sqrt(|x_i - x_{i+1}|^2 / (p_i cos_{i+1})))^2, with p_i the
+ * solid-angle density that chose segment i, decides: once it exceeds a_0 c,
+ * or at the depth limit, the glossy integral is estimated from the probes
+ * (Q(v_b, wi)/2, Eq. 6); below it the ray is traced and the recursion
+ * continues at the surface it hits (the sky if it leaves).  foot_sum holds the
+ * sum over the segments up to v. */
+static void shade_radiance(const o_scene *sc, const o_probes *pr, const o_params *pp, uint64_t seed,
+                           uint32_t pixel, uint32_t frame, uint32_t prim, const double *v, const double *nv,
+                           const double *prev, double foot_sum, double a0c, int depth, double *L)
+{
+    double alb[3], emit[3], ks, ra, pb[3], q[3];
+    material(sc, prim, alb, emit);
+    spec_of(sc, prim, &ks, &ra);
+    for (int a = 0; a < 3; ++a) L[a] = emit[a];
+    o_view_bias(v, prev, pr->bias_dist, pb);
+    if (alb[0] != 0.0 || alb[1] != 0.0 || alb[2] != 0.0) {
+        probe_query(pr, pb, nv, 0, q);
+        for (int a = 0; a < 3; ++a) L[a] += alb[a] * q[a];
+    }
+    if (!(ks > 0.0)) return;
+    double wo[3] = {prev[0] - v[0], prev[1] - v[1], prev[2] - v[2]}, wi[3], u[4];
+    normalize3(wo);
+    rand4(seed, pixel, frame, PASS_GLOSSY_SHADE, (uint32_t)depth, u);
+    if (!ggx_sample(nv, wo, ra, u[0], u[1], wi)) return;
+    double pdf = ggx_pdf(nv, wo, wi, ra);
+    if (!(pdf > 0.0)) return;
+    double wgt = ks * ggx_eval(nv, wo, wi, ra) * dot3(nv, wi) / pdf;
+    if (foot_sum * foot_sum > a0c || depth >= pp->glossy_depth) {
+        probe_query(pr, pb, wi, 0, q);
+        for (int a = 0; a < 3; ++a) L[a] += 0.5 * wgt * q[a];
+        return;
+    }
+    double o[3];
+    for (int a = 0; a < 3; ++a) o[a] = v[a] + sc->eps * nv[a];
+    o_hit h;
+    if (!closest_hit(sc, o, wi, O_INF, &h)) {
+        for (int a = 0; a < 3; ++a) L[a] += wgt * sc->sky[a];
+        return;
+    }
+    double z[3];
+    for (int a = 0; a < 3; ++a) z[a] = o[a] + h.t * wi[a];
+    double dz[3] = {z[0] - v[0], z[1] - v[1], z[2] - v[2]};
+    double cz = -dot3(h.n, wi);
+    double seg = cz > 0.0 ? sqrt(dot3(dz, dz) / (pdf * cz)) : O_INF;
+    double Lz[3];
+    shade_radiance(sc, pr, pp, seed, pixel, frame, h.prim, z, h.n, v, foot_sum + seg, a0c, depth + 1, Lz);
+    for (int a = 0; a < 3; ++a) L[a] += wgt * Lz[a];
+}
+
 void o_shade(const o_scene *sc, int32_t W, int32_t H, const double *gb, const o_probes *pr,
              const double *res, const double *resid, const o_params *pp, const int32_t *pix,
-             int64_t npix, double *img)
+             int64_t npix, double *img, uint64_t seed, uint32_t frame)
 {
     int64_t n = pix ? npix : (int64_t)W * H;
     for (int64_t q = 0; q < n; ++q) {
@@ -1078,7 +1381,31 @@ void o_shade(const o_scene *sc, int32_t W, int32_t H, const double *gb, const o_
             if (cx <= 0.0 || cy <= 0.0) continue;
             geo = fmin(cx * cy / d2, pp->g_max);
             if (!o_visible(sc, x, nx, y, ny, 0)) continue;
+            if (sc->glossy) {
+                /* x_1 = x, x_2 = y: the first segment's density is the BSDF mixture's
+                 * at x; a_0 = |x_0 - x_1|^2 / (4 pi cos) with x_0 the camera */
+                double ks, ra, wo[3] = {pp->eye[0] - x[0], pp->eye[1] - x[1], pp->eye[2] - x[2]}, f[3];
+                spec_of(sc, (uint32_t)g[GB_PRIM], &ks, &ra);
+                double dc2 = dot3(wo, wo);
+                normalize3(wo);
+                double c1 = dot3(nx, wo);
+                double a0c = c1 > 0.0 ? pp->foot_c * dc2 / (4.0 * O_PI * c1) : O_INF;
+                double p1 = mix_pdf(rho, ks, ra, nx, wo, w);
+                double foot = p1 > 0.0 ? sqrt(d2 / (p1 * cy)) : O_INF;
+                shade_radiance(sc, pr, pp, seed, (uint32_t)p, frame, (uint32_t)r[R_PRIM], y, ny, x, foot, a0c, 1, L);
+                bsdf(rho, ks, ra, nx, wo, w, f);
+                for (int a = 0; a < 3; ++a) o[a] += f[a] * L[a] * geo * r[R_W];
+                continue;
+            }
             radiance_toward(sc, pr, (uint32_t)r[R_PRIM], y, ny, x, L);
+        }
+        if (sc->glossy) {
+            double ks, ra, wo[3] = {pp->eye[0] - x[0], pp->eye[1] - x[1], pp->eye[2] - x[2]}, f[3];
+            spec_of(sc, (uint32_t)g[GB_PRIM], &ks, &ra);
+            normalize3(wo);
+            bsdf(rho, ks, ra, nx, wo, r + R_Y, f);
+            for (int a = 0; a < 3; ++a) o[a] += f[a] * L[a] * geo * r[R_W];
+            continue;
         }
         for (int a = 0; a < 3; ++a) o[a] += rho[a] / O_PI * L[a] * geo * r[R_W];
     }
@@ -1100,7 +1427,7 @@ void o_brute_force(const o_scene *sc, const o_probes *pr, const double *gb, int3
         const double *g = gb + GB_N * p;
         double *o = out + 3 * q;
         for (int a = 0; a < 3; ++a) o[a] = g[GB_EMIT + a];
-        if (!pixel_active(g)) continue;
+        if (!pixel_active(sc, g)) continue;
         const double *x = g + GB_POS, *nx = g + GB_NRM, *rho = g + GB_ALB;
         double org[3], acc[3] = {0, 0, 0};
         for (int a = 0; a < 3; ++a) org[a] = x[a] + sc->eps * nx[a];
@@ -1141,7 +1468,7 @@ void o_brute_force(const o_scene *sc, const o_probes *pr, const double *gb, int3
  * out[q] = mean over samples s0 .. s0+spp-1.
  * ------------------------------------------------------------------------- */
 void o_path_trace(const o_scene *sc, const double *gb, const int32_t *pix, int64_t npix, int32_t spp,
-                  uint32_t s0, uint64_t seed, double *out)
+                  uint32_t s0, uint64_t seed, const double *eye, double *out)
 {
     for (int64_t q = 0; q < npix; ++q) {
         const int64_t p = pix[q];
@@ -1154,6 +1481,54 @@ void o_path_trace(const o_scene *sc, const double *gb, const int32_t *pix, int64
                 n[a] = g[GB_NRM + a];
                 rho[a] = g[GB_ALB + a];
                 L[a] = g[GB_EMIT + a];
+            }
+            if (sc->glossy) {
+                /* glossy scene: at every vertex the BSDF mixture of the initial pass
+                 * (glossy lobe with probability p_gloss, chosen by u3), throughput
+                 * times f cos / pdf; roulette as below, after that product */
+                uint32_t prim = (uint32_t)g[GB_PRIM];
+                double wo[3] = {eye[0] - x[0], eye[1] - x[1], eye[2] - x[2]};
+                normalize3(wo);
+                for (uint32_t b = 1; b <= 32; ++b) {
+                    double ks, ra;
+                    spec_of(sc, prim, &ks, &ra);
+                    if (rho[0] == 0.0 && rho[1] == 0.0 && rho[2] == 0.0 && !(ks > 0.0)) break;
+                    double u[4], w[3], o[3], f[3];
+                    rand4(seed, (uint32_t)p, s0 + (uint32_t)s, 13u, b, u);
+                    double pg = p_gloss(rho, ks);
+                    if (pg > 0.0 && u[3] < pg) {
+                        if (!ggx_sample(n, wo, ra, u[0], u[1], w)) break;
+                    } else {
+                        o_cosine_dir(n, u[0], u[1], w);
+                    }
+                    double pd = mix_pdf(rho, ks, ra, n, wo, w);
+                    if (!(pd > 0.0)) break;
+                    bsdf(rho, ks, ra, n, wo, w, f);
+                    double c = dot3(n, w);
+                    for (int a = 0; a < 3; ++a) thr[a] *= f[a] * c / pd;
+                    if (b >= 4) {
+                        double P = fmin(1.0, fmax(thr[0], fmax(thr[1], thr[2])));
+                        if (!(u[2] < P)) break;
+                        for (int a = 0; a < 3; ++a) thr[a] /= P;
+                    }
+                    for (int a = 0; a < 3; ++a) o[a] = x[a] + sc->eps * n[a];
+                    o_hit h;
+                    if (!closest_hit(sc, o, w, O_INF, &h)) {
+                        for (int a = 0; a < 3; ++a) L[a] += thr[a] * sc->sky[a];
+                        break;
+                    }
+                    double emit[3];
+                    for (int a = 0; a < 3; ++a) {
+                        x[a] = o[a] + h.t * w[a];
+                        n[a] = h.n[a];
+                        wo[a] = -w[a];
+                    }
+                    prim = h.prim;
+                    material(sc, h.prim, rho, emit);
+                    for (int a = 0; a < 3; ++a) L[a] += thr[a] * emit[a];
+                }
+                for (int a = 0; a < 3; ++a) acc[a] += L[a];
+                continue;
             }
             for (uint32_t b = 1; b <= 32; ++b) {
                 if (rho[0] == 0.0 && rho[1] == 0.0 && rho[2] == 0.0) break;
@@ -1219,7 +1594,7 @@ void o_mlp_batch(const o_scene *sc, const o_probes *pr, int32_t W, int32_t H, co
         for (int a = 0; a < 3; ++a) {
             pos[3 * j + a] = 0.0; nrm[3 * j + a] = 0.0; target[3 * j + a] = 0.0; qprobe[3 * j + a] = 0.0;
         }
-        if (!pixel_active(g)) continue;
+        if (!pixel_active(sc, g)) continue;
         const double *x = g + GB_POS, *nx = g + GB_NRM;
         /* the candidate */
         double w[3], o[3];
@@ -1243,7 +1618,7 @@ void o_mlp_batch(const o_scene *sc, const o_probes *pr, int32_t W, int32_t H, co
         if (closest_hit(sc, ol, wl, O_INF, &h)) {
             double z[3];
             for (int a = 0; a < 3; ++a) z[a] = ol[a] + h.t * wl[a];
-            radiance_toward_ex(sc, pr, h.prim, z, h.n, y, 0, L);
+            radiance_toward_ex(sc, pr, h.prim, z, h.n, y, 0, NULL, L);
         } else {
             for (int a = 0; a < 3; ++a) L[a] = sc->sky[a];
         }

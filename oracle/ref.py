@@ -36,7 +36,7 @@ class OScene(C.Structure):
     _fields_ = [("n_prims", C.c_int32), ("has_room", C.c_int32), ("prims", C.c_void_p),
                 ("room_lo", C.c_double * 3), ("room_hi", C.c_double * 3),
                 ("wall_albedo", C.c_double * 3), ("wall_emit", C.c_double * 3),
-                ("sky", C.c_double * 3), ("eps", C.c_double)]
+                ("sky", C.c_double * 3), ("eps", C.c_double), ("glossy", C.c_int32), ("pad", C.c_int32)]
 
 
 class OCamera(C.Structure):
@@ -58,7 +58,8 @@ class OParams(C.Structure):
     _fields_ = [("M", C.c_int32), ("k", C.c_int32), ("unbiased", C.c_int32), ("M_light", C.c_int32),
                 ("radius", C.c_double), ("g_max", C.c_double), ("cos_n", C.c_double),
                 ("depth_rel", C.c_double), ("m_cap", C.c_double), ("subsample", C.c_int32),
-                ("pad", C.c_int32)]
+                ("pad", C.c_int32), ("eye", C.c_double * 3), ("eye_prev", C.c_double * 3),
+                ("foot_c", C.c_double), ("glossy_depth", C.c_int32), ("pad2", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -91,7 +92,12 @@ def _setup(L):
     L.o_spatial_candidate.restype = C.c_int64
     L.o_resample_spatial.argtypes = [_P, C.c_int32, C.c_int32, _P, _P, _P, C.c_int, C.c_uint64,
                                      C.c_uint32, _P, C.c_int64, _P]
-    L.o_shade.argtypes = [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P, C.c_int64, _P]
+    L.o_shade.argtypes = [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P, C.c_int64, _P, C.c_uint64,
+                          C.c_uint32]
+    L.o_ggx.argtypes = [_P, _P, _P, C.c_double, _P]
+    L.o_ggx_sample.argtypes = [_P, _P, C.c_double, C.c_double, C.c_double, _P]
+    L.o_ggx_sample.restype = C.c_int
+    L.o_glossy_term.argtypes = [_P, _P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_double, _P]
 
 
 def _ptr(a: np.ndarray):
@@ -119,6 +125,8 @@ class _Scene:
         for name in ("room_lo", "room_hi", "wall_albedo", "wall_emit", "sky"):
             getattr(s, name)[:] = [float(v) for v in np.asarray(getattr(scene, name), np.float32)]
         s.eps = float(np.float32(scene.eps))
+        # a specular layer on any primitive (slot 11 = k_s, slot 15 = GGX roughness)
+        s.glossy = 1 if len(rec) and np.any(rec[:, 11] > 0) else 0
         self.s = s
 
     @property
@@ -185,7 +193,9 @@ class _Probes:
         return C.byref(self.p)
 
 
-def _params(pr) -> OParams:
+def _params(pr, eye=None, eye_prev=None) -> OParams:
+    """Resampling parameters; eye / eye_prev are the camera positions of the
+    current and previous frame (the view direction of glossy primary vertices)."""
     o = OParams()
     o.M, o.k, o.unbiased = int(pr.M), int(pr.k), int(pr.unbiased)
     o.M_light = int(getattr(pr, "M_light", 0))
@@ -195,6 +205,11 @@ def _params(pr) -> OParams:
     o.depth_rel = float(np.float32(pr.depth_rel))
     o.m_cap = float(pr.m_cap)
     o.subsample = int(getattr(pr, "subsample", 1))
+    o.foot_c = float(np.float32(getattr(pr, "foot_c", 0.2)))
+    o.glossy_depth = int(getattr(pr, "glossy_depth", 8))
+    for name, v in (("eye", eye), ("eye_prev", eye_prev if eye_prev is not None else eye)):
+        if v is not None:
+            getattr(o, name)[:] = [float(t) for t in np.asarray(v, np.float32).reshape(3)]
     return o
 
 
@@ -309,8 +324,8 @@ def fill_probes(scene, grid, upd, seed, irr=None, dep=None):
 
 
 def resample_initial(scene, W, H, gb, grid, irr, dep, params, seed, frame, pixels=None,
-                     res=None, resid=None, mlp=None):
-    s, pr, pp = _scene(scene), _Probes(grid, irr, dep, mlp), _params(params)
+                     res=None, resid=None, mlp=None, eye=None):
+    s, pr, pp = _scene(scene), _Probes(grid, irr, dep, mlp), _params(params, eye)
     gb = _f64(gb)
     res = np.zeros((W * H, R_N)) if res is None else res
     resid = np.zeros((W * H, 3)) if resid is None else resid
@@ -334,8 +349,8 @@ def reproject(cam, x) -> int:
 
 
 def resample_temporal(scene, W, H, gb, gb_prev, cam_prev, cur, hist, params, seed, frame,
-                      pixels=None, out=None):
-    s, c, pp = _scene(scene), _camera(cam_prev), _params(params)
+                      pixels=None, out=None, eye=None, eye_prev=None):
+    s, c, pp = _scene(scene), _camera(cam_prev), _params(params, eye, eye_prev)
     gb, gb_prev, cur, hist = _f64(gb), _f64(gb_prev), _f64(cur), _f64(hist)
     out = np.zeros((W * H, R_N)) if out is None else out
     arr, n, px = _pix(pixels)
@@ -351,8 +366,8 @@ def spatial_candidate(W, H, p, j, radius, seed, frame, spass) -> int:
                                          int(frame) & 0xFFFFFFFF, int(spass), C.byref(u2)))
 
 
-def resample_spatial(scene, W, H, gb, res_in, params, spass, seed, frame, pixels=None, out=None):
-    s, pp = _scene(scene), _params(params)
+def resample_spatial(scene, W, H, gb, res_in, params, spass, seed, frame, pixels=None, out=None, eye=None):
+    s, pp = _scene(scene), _params(params, eye)
     gb, res_in = _f64(gb), _f64(res_in)
     out = np.zeros((W * H, R_N)) if out is None else out
     arr, n, px = _pix(pixels)
@@ -361,13 +376,15 @@ def resample_spatial(scene, W, H, gb, res_in, params, spass, seed, frame, pixels
     return out
 
 
-def shade(scene, W, H, gb, grid, irr, dep, res, resid, params, pixels=None, out=None, mlp=None):
-    s, pr, pp = _scene(scene), _Probes(grid, irr, dep, mlp), _params(params)
+def shade(scene, W, H, gb, grid, irr, dep, res, resid, params, pixels=None, out=None, mlp=None,
+          seed=0, frame=0, eye=None):
+    """Shading; seed / frame drive the specular recursion of a glossy scene."""
+    s, pr, pp = _scene(scene), _Probes(grid, irr, dep, mlp), _params(params, eye)
     gb, res, resid = _f64(gb), _f64(res), _f64(resid)
     out = np.zeros((W * H, 3)) if out is None else out
     arr, n, px = _pix(pixels)
     lib().o_shade(s.ref, W, H, _ptr(gb), pr.ref, _ptr(res), _ptr(resid), C.byref(pp), px, n,
-                  _ptr(out))
+                  _ptr(out), int(seed), int(frame) & 0xFFFFFFFF)
     return out
 
 
@@ -454,13 +471,52 @@ def mlp_forward(params, prec, lo, hi, pos, nrm) -> np.ndarray:
     return out
 
 
-def path_trace(scene, gb, pixels, spp, seed, s0=0) -> np.ndarray:
-    """Reference path tracer (o_path_trace) for the listed pixels: (n, 3)."""
+def path_trace(scene, gb, pixels, spp, seed, s0=0, eye=None) -> np.ndarray:
+    """Reference path tracer (o_path_trace) for the listed pixels: (n, 3);
+    eye (the camera position) is needed for a glossy scene."""
     s = _scene(scene)
     gb = _f64(gb)
     pix = np.ascontiguousarray(np.asarray(pixels, np.int32))
     out = np.zeros((len(pix), 3))
+    e = _f64(np.zeros(3) if eye is None else np.asarray(eye, np.float32))
     L = lib()
-    L.o_path_trace.argtypes = [_P, _P, _P, C.c_int64, C.c_int32, C.c_uint32, C.c_uint64, _P]
-    L.o_path_trace(s.ref, _ptr(gb), _ptr(pix), len(pix), int(spp), int(s0) & 0xFFFFFFFF, int(seed), _ptr(out))
+    L.o_path_trace.argtypes = [_P, _P, _P, C.c_int64, C.c_int32, C.c_uint32, C.c_uint64, _P, _P]
+    L.o_path_trace(s.ref, _ptr(gb), _ptr(pix), len(pix), int(spp), int(s0) & 0xFFFFFFFF, int(seed), _ptr(e),
+                   _ptr(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# glossy layer (test hooks)
+# --------------------------------------------------------------------------
+def ggx(n, wo, wi, a):
+    """(f_g / k_s, solid-angle sampling density) of the GGX lobe."""
+    out = np.zeros(2)
+    lib().o_ggx(_ptr(_f64(n)), _ptr(_f64(wo)), _ptr(_f64(wi)), float(a), _ptr(out))
+    return float(out[0]), float(out[1])
+
+
+def ggx_many(n, wo, wis, a):
+    """(f_g / k_s, density) of the GGX lobe for rows of directions wis."""
+    wis = _f64(np.asarray(wis).reshape(-1, 3))
+    f, pdf = np.zeros(len(wis)), np.zeros(len(wis))
+    L = lib()
+    L.o_ggx_many.argtypes = [_P, _P, _P, C.c_int64, C.c_double, _P, _P]
+    L.o_ggx_many(_ptr(_f64(n)), _ptr(_f64(wo)), _ptr(wis), len(wis), float(a), _ptr(f), _ptr(pdf))
+    return f, pdf
+
+
+def ggx_sample(n, wo, a, u0, u1):
+    """A direction from the GGX lobe about wo, or None below the surface."""
+    wi = np.zeros(3)
+    ok = lib().o_ggx_sample(_ptr(_f64(n)), _ptr(_f64(wo)), float(a), float(u0), float(u1), _ptr(wi))
+    return wi if ok else None
+
+
+def glossy_term(grid, irr, dep, pb, n, wo, ks, a, u0, u1):
+    """One-sample glossy part of L_DDGI+ (Eq. 6) at the biased point pb."""
+    pr = _Probes(grid, irr, dep)
+    out = np.zeros(3)
+    lib().o_glossy_term(pr.ref, _ptr(_f64(pb)), _ptr(_f64(n)), _ptr(_f64(wo)), float(ks), float(a), float(u0),
+                        float(u1), _ptr(out))
     return out

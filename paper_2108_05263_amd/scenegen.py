@@ -30,10 +30,11 @@ MISS = 0xFFFFFFFF
 # --------------------------------------------------------------------------
 # primitive records
 # --------------------------------------------------------------------------
-def prim_records(types, centers, sizes, albedo, emit) -> np.ndarray:
+def prim_records(types, centers, sizes, albedo, emit, spec=None, rough=None) -> np.ndarray:
     """Pack primitives into the 64-byte record layout used by the C ABI:
-    [cx cy cz type | sx sy sz 0 | ar ag ab 0 | er eg eb 0] (type as uint32 bits;
-    spheres keep their radius in sx)."""
+    [cx cy cz type | sx sy sz 0 | ar ag ab ks | er eg eb alpha] (type as uint32
+    bits; spheres keep their radius in sx; ks the grey weight of a GGX
+    specular layer of roughness alpha, 0 for a Lambertian surface)."""
     n = len(types)
     rec = np.zeros((n, PRIM_RECORD), dtype=np.float32)
     rec[:, 0:3] = np.asarray(centers, dtype=np.float32).reshape(n, 3)
@@ -41,6 +42,9 @@ def prim_records(types, centers, sizes, albedo, emit) -> np.ndarray:
     rec[:, 4:7] = np.asarray(sizes, dtype=np.float32).reshape(n, 3)
     rec[:, 8:11] = np.asarray(albedo, dtype=np.float32).reshape(n, 3)
     rec[:, 12:15] = np.asarray(emit, dtype=np.float32).reshape(n, 3)
+    if spec is not None:
+        rec[:, 11] = np.asarray(spec, dtype=np.float32).reshape(n)
+        rec[:, 15] = np.asarray(rough, dtype=np.float32).reshape(n)
     return rec
 
 
@@ -113,6 +117,8 @@ class Params:
     temporal: bool = True
     M_light: int = 0                  # emitter-sampled candidates per pixel (M + M_light <= 32)
     subsample: int = 1                # n: pixel (x, y) draws candidates in frame f iff (x + y + f) % n == 0
+    foot_c: float = 0.2               # footprint threshold c of the glossy shading recursion (Eq. 8)
+    glossy_depth: int = 8             # most glossy vertices the shading recursion visits
 
 
 @dataclasses.dataclass
@@ -153,6 +159,9 @@ class Config:
     grid_res: tuple                   # uniform-grid accelerator resolution
     seeds: tuple = (1, 2, 3)
     clear_emitters: bool = False      # redraw primitives that reach into an emitter
+    glossy_frac: float = 0.0          # fraction of non-emitting primitives with a GGX specular layer
+    spec_range: tuple = (0.3, 0.7)    # its weight ks, uniform (diffuse albedo scaled by 1 - ks)
+    rough_range: tuple = (0.02, 0.5)  # its roughness alpha, log-uniform
 
 
 # --------------------------------------------------------------------------
@@ -192,6 +201,26 @@ CONFIGS = {
         probe_update=ProbeUpdate(rays=256, hysteresis=0.97, fill_passes=4, fill_rays=256,
                                  per_frame=True),
         frames=16, grid_res=(24, 6, 24), clear_emitters=True),
+    # Glossy workloads (the glossy L_DDGI+ and the specular recursion): the
+    # tiny room with four boxes added, and the 1920x1080 room, with 60% / 50%
+    # of the non-emitting primitives given a GGX specular layer, ks
+    # U[0.3, 0.7], roughness log-uniform in [0.02, 0.5].
+    "glossy_tiny": Config(
+        name="glossy_tiny", width=64, height=64, scene_seed=111, n_spheres=8, n_boxes=4,
+        n_emitters=1, room_lo=(0, 0, 0), room_hi=(8, 8, 8), size_lo=0.3, size_hi=1.2,
+        emit_lo=20.0, emit_hi=20.0, eye=(4, 4, 0.5), look=(4, 3.5, 8), vfov_deg=60.0,
+        pan=0.0, probe_dims=(4, 4, 4), probe_spacing=2.0,
+        params=Params(M=8, k=3, n_spatial=1, radius=8.0, temporal=False),
+        probe_update=ProbeUpdate(rays=64, hysteresis=0.0, fill_passes=4, fill_rays=64),
+        frames=1, grid_res=(8, 8, 8), glossy_frac=0.6),
+    "glossy": Config(
+        name="glossy", width=1920, height=1080, scene_seed=102, n_spheres=128, n_boxes=128,
+        n_emitters=4, room_lo=(0, 0, 0), room_hi=(32, 8, 32), size_lo=0.2, size_hi=1.5,
+        emit_lo=10.0, emit_hi=50.0, eye=(16, 4, 1), look=(16, 3, 31), vfov_deg=60.0,
+        pan=0.05, probe_dims=(32, 8, 32), probe_spacing=1.0,
+        params=Params(M=32, k=5, n_spatial=2, radius=30.0, temporal=True),
+        probe_update=ProbeUpdate(rays=256, hysteresis=0.0, fill_passes=4, fill_rays=256),
+        frames=8, grid_res=(16, 4, 16), glossy_frac=0.5),
 }
 
 
@@ -259,7 +288,20 @@ def make_scene(cfg: Config, max_frames: int = 32) -> Scene:
         else:
             albedo.append(rng.uniform(0.1, 0.9, 3))
             emit.append([0.0, 0.0, 0.0])
-    prims = prim_records(types, centers, sizes, albedo, emit)
+    spec = rough = None
+    if cfg.glossy_frac > 0.0:
+        # the specular layers come from a stream of their own, so the geometry
+        # and albedo draws are those of the same room without them
+        grng = np.random.default_rng(cfg.scene_seed + 7919)
+        spec, rough = np.zeros(len(types)), np.ones(len(types))
+        for i in range(len(types)):
+            has = grng.random() < cfg.glossy_frac
+            ks = grng.uniform(*cfg.spec_range)
+            al = float(np.exp(grng.uniform(np.log(cfg.rough_range[0]), np.log(cfg.rough_range[1]))))
+            if has and not np.any(np.asarray(emit[i]) > 0):
+                spec[i], rough[i] = ks, al
+                albedo[i] = np.asarray(albedo[i]) * (1.0 - ks)
+    prims = prim_records(types, centers, sizes, albedo, emit, spec, rough)
     ext = float(np.max(hi - lo))
     return Scene(prims=prims, has_room=True, room_lo=lo.astype(np.float32),
                  room_hi=hi.astype(np.float32),
