@@ -50,16 +50,19 @@ typedef enum gi_status {
 #define GI_MAX_PROBE_RAYS 1024u      /* largest probe-update ray count */
 
 /* Primitive record, 64 bytes.  type 0 = sphere (size[0] = radius),
- * type 1 = axis-aligned box (size = half extents). */
+ * type 1 = axis-aligned box (size = half extents).  spec and rough describe
+ * an optional glossy layer (Sec. 3.3): f = albedo/pi + spec * D G1 G1 /
+ * (4 cos_o cos_i) with isotropic GGX D of roughness `rough` and separable
+ * Smith masking; they are read only in scenes with GI_OPT_GLOSSY. */
 typedef struct gi_prim {
     float center[3];
     uint32_t type;
     float size[3];
     float pad0;
     float albedo[3];     /* diffuse albedo rho */
-    float pad1;
+    float spec;          /* weight k_s of the GGX layer, 0 = Lambertian */
     float emit[3];       /* emitted radiance L_e */
-    float pad2;
+    float rough;         /* GGX roughness alpha in (0, 1] (with spec > 0) */
 } gi_prim;
 
 /* Analytic scene.  The room (if has_room) is the inside of the box
@@ -90,6 +93,9 @@ typedef struct gi_scene {
 #define GI_MAX_EMITTERS 32u
 
 #define GI_OPT_NO_LDS 1u             /* trace from global memory even when the scene fits LDS */
+#define GI_OPT_GLOSSY 2u             /* primitives may carry a glossy layer (gi_prim spec, rough): the
+                                        kernels with the glossy BSDF, glossy L_DDGI+ (Eq. 6) and the
+                                        shading recursion (Eq. 7-8) run; without it spec is ignored */
 
 /* Pinhole camera: the ray through pixel (i, j) has direction
  * normalize(fwd + sx*right + sy*up), sx = (2(i+.5)/W - 1) tan_half_fovy W/H,
@@ -118,6 +124,9 @@ typedef struct gi_gbuffer {
     float *emit;
     uint32_t format;     /* GI_GB_F32 or GI_GB_F16 */
     uint32_t pad;
+    float eye[3];        /* camera position the buffer was traced from (view direction of glossy
+                            primary vertices); gi_trace_gbuffer does not write it, the caller sets it */
+    float pad2;
 } gi_gbuffer;
 
 #define GI_GB_F32 0u
@@ -174,7 +183,11 @@ typedef struct gi_params {
     uint32_t unbiased;   /* 1: visibility-tested 1/Z normalisation, 0: 1/M */
     uint32_t M_light;    /* emitter-sampled candidates per pixel; M + M_light <= GI_MAX_M */
     uint32_t subsample;  /* n >= 1: pixel (x, y) draws candidates in frame f iff (x + y + f) % n == 0 */
+    float foot_c;        /* glossy scenes: footprint threshold c of the shading recursion (Eq. 8), >= 0 */
+    uint32_t glossy_depth; /* glossy scenes: most glossy vertices the recursion visits, 1..GI_MAX_GLOSSY_DEPTH */
 } gi_params;
+
+#define GI_MAX_GLOSSY_DEPTH 16u
 
 /* Probe-update parameters. */
 typedef struct gi_probe_params {
@@ -263,10 +276,15 @@ gi_status gi_resample_spatial(const gi_scene *scene, const gi_gbuffer *gb, const
 
 /* Shading (Sec. 3.1 steps 3-4, Eq. 9): L_o = L_e(x) + resid(x) +
  * rho_x/pi L(y; x) min(G, g_max) V(x, y) W with a fresh radiance query biased
- * toward this x and one shadow ray.  out_rgba: float4 plane (rgb, 1). */
+ * toward this x and one shadow ray.  out_rgba: float4 plane (rgb, 1).
+ * In a glossy scene f(x) replaces rho_x/pi and L(y; x) follows the specular
+ * recursion (Sec. 3.3, Eq. 7-8): glossy vertices draw one lobe direction each
+ * (counter (pixel, frame, 16, depth)) and trace it while the path footprint
+ * stays below a_0 * foot_c, else read the probes; seed and frame drive it
+ * (unused in Lambertian scenes). */
 gi_status gi_shade(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes,
                    const gi_reservoirs *res, const float *resid, const gi_params *params,
-                   float *out_rgba, void *stream);
+                   float *out_rgba, uint64_t seed, uint32_t frame, void *stream);
 
 /* ==========================================================================
  * Learned radiance cache (the paper treats the irradiance cache as
@@ -364,7 +382,9 @@ gi_status gi_mlp_infer(const gi_mlp *mlp, uint32_t n, const float *pos4, const f
  * valid 1/0), qprobe4 (Q(y_b, n_y) with y_b biased toward the pixel's x: the
  * probe value the cache replaces, 0).  A sample whose pixel has no surface,
  * whose candidate misses or lands on a zero-albedo surface is invalid (all
- * zero).  M in 1..GI_MAX_M (the initial pass's candidate count). */
+ * zero).  M in 1..GI_MAX_M (the initial pass's candidate count).
+ * Glossy scenes (GI_OPT_GLOSSY) return GI_ERR_PARAM: the cache serves Lambertian
+ * scenes. */
 gi_status gi_mlp_make_batch(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes, uint32_t M,
                             uint32_t n, uint64_t seed, uint32_t frame, float *pos4, float *nrm4,
                             float *target4, float *qprobe4, void *stream);
@@ -404,7 +424,9 @@ uint64_t gi_initial_mlp_workspace_bytes(uint32_t width, uint32_t height, uint32_
  * cache is evaluated for all of them, and the resampling uses
  * L(y) = L_e(y) + rho_y max(0, C(y, n_y)).  When the mode or the device state
  * rules the cache out, the same candidates take the probe query and the
- * result is bit-identical to gi_resample_initial. */
+ * result is bit-identical to gi_resample_initial.
+ * Glossy scenes (GI_OPT_GLOSSY) return GI_ERR_PARAM: the cache serves Lambertian
+ * scenes. */
 gi_status gi_resample_initial_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes,
                                   const gi_mlp *mlp, const gi_params *params, gi_reservoirs *out,
                                   float *resid, void *workspace, uint64_t workspace_bytes, uint64_t seed,
@@ -416,7 +438,9 @@ uint64_t gi_shade_mlp_workspace_bytes(uint32_t width, uint32_t height);
 /* gi_shade with the learned cache for the fresh radiance query at each
  * reservoir's sample (the cache needs no view-path bias); probe query when
  * the mode or the device state rules the cache out (then bit-identical to
- * gi_shade). */
+ * gi_shade).
+ * Glossy scenes (GI_OPT_GLOSSY) return GI_ERR_PARAM: the cache serves Lambertian
+ * scenes. */
 gi_status gi_shade_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes,
                        const gi_mlp *mlp, const gi_reservoirs *res, const float *resid,
                        const gi_params *params, float *out_rgba, void *workspace, uint64_t workspace_bytes,

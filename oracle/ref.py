@@ -403,17 +403,20 @@ class Sequence:
     def frame(self, cam, frame):
         W, H, pr = cam.width, cam.height, self.params
         gb = gbuffer(self.scene, cam)
+        eye = cam.eye
+        eye_prev = self.cam_prev.eye if self.cam_prev is not None else eye
         res, resid = resample_initial(self.scene, W, H, gb, self.grid, self.irr, self.dep, pr,
-                                      self.seed, frame, mlp=self.mlp)
+                                      self.seed, frame, mlp=self.mlp, eye=eye)
         stages = {"gbuffer": gb, "initial": res, "resid": resid}
         if pr.temporal and self.hist is not None:
             res = resample_temporal(self.scene, W, H, gb, self.gb_prev, self.cam_prev, res,
-                                    self.hist, pr, self.seed, frame)
+                                    self.hist, pr, self.seed, frame, eye=eye, eye_prev=eye_prev)
             stages["temporal"] = res
         for sp in range(pr.n_spatial):
-            res = resample_spatial(self.scene, W, H, gb, res, pr, sp, self.seed, frame)
+            res = resample_spatial(self.scene, W, H, gb, res, pr, sp, self.seed, frame, eye=eye)
             stages[f"spatial{sp}"] = res
-        img = shade(self.scene, W, H, gb, self.grid, self.irr, self.dep, res, resid, pr, mlp=self.mlp)
+        img = shade(self.scene, W, H, gb, self.grid, self.irr, self.dep, res, resid, pr, mlp=self.mlp,
+                    seed=self.seed, frame=frame, eye=eye)
         stages["image"] = img
         self.hist, self.gb_prev, self.cam_prev = res, gb, cam
         return img, stages

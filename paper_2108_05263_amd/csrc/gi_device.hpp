@@ -73,6 +73,7 @@ __device__ __forceinline__ uint4 philox(uint64_t seed, uint32_t c0, uint32_t c1,
 // 24-bit uniform in [0, 1): exact in FP32
 __device__ __forceinline__ float u01(uint32_t v) { return (float)(v >> 8) * 5.9604644775390625e-08f; }
 
+enum : uint32_t { kPassGlossyCand = 14, kPassGlossyProbe = 15, kPassGlossyShade = 16 };
 enum : uint32_t { kPassInitial = 0, kPassTemporal = 1, kPassSpatial0 = 2, kPassProbe = 9, kPassTrainBatch = 10,
                    kPassReference = 13 };
 
@@ -698,6 +699,146 @@ __device__ __forceinline__ Res empty_res(uint32_t M)
 }
 
 // target p_hat at (x, n_x, rho_x) for a sample with cached radiance L
+// --------------------------------------------------------------------------
+// glossy layer (Sec. 3.3, "microfacet models"): an isotropic GGX lobe with
+// separable Smith masking and a grey weight k_s, no Fresnel term:
+//   f = rho/pi + k_s D(h) G1(wo) G1(wi) / (4 (n.wo)(n.wi)),
+//   D(h) = a^2 / (pi t^2),  t = (n.h)^2 (a^2 - 1) + 1 = a^2 + (1 - a^2) |n x h|^2,
+//   G1(v) = 2 (n.v) / ((n.v) + sqrt(a^2 + (1 - a^2)(n.v)^2)).
+// t is formed from |n x h|^2, which keeps its precision near the lobe's peak
+// where (n.h)^2 is within rounding of 1.  The lobe is sampled by half vector
+// with density D(h)(n.h) (Walter et al. 2007) and wi reflected about h; the
+// density of wi is D(h)(n.h) / (4 |wo.h|).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ V3 cross(V3 a, V3 b)
+{
+    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+__device__ __forceinline__ float ggx_D(V3 n, V3 h, float a)
+{
+    const V3 c = cross(n, h);
+    const float a2 = a * a, t = fmaf(1.0f - a2, dot(c, c), a2);
+    return a2 * rcp(kPi * t * t);
+}
+
+__device__ __forceinline__ float smith_G1(float nv, float a)
+{
+    const float a2 = a * a;
+    return 2.0f * nv * rcp(nv + fsqrt(fmaf(1.0f - a2, nv * nv, a2)));
+}
+
+// f_g / k_s; 0 unless both directions lie above the surface
+__device__ __forceinline__ float ggx_eval(V3 n, V3 wo, V3 wi, float a)
+{
+    const float no = dot(n, wo), ni = dot(n, wi);
+    if (no <= 0.0f || ni <= 0.0f) return 0.0f;
+    V3 h = wo + wi;
+    h = frsq(dot(h, h)) * h;
+    return ggx_D(n, h, a) * smith_G1(no, a) * smith_G1(ni, a) * rcp(4.0f * no * ni);
+}
+
+__device__ __forceinline__ float ggx_pdf(V3 n, V3 wo, V3 wi, float a)
+{
+    if (dot(n, wi) <= 0.0f || dot(n, wo) <= 0.0f) return 0.0f;
+    V3 h = wo + wi;
+    h = frsq(dot(h, h)) * h;
+    const float oh = fabsf(dot(wo, h));
+    return oh > 0.0f ? ggx_D(n, h, a) * dot(n, h) * rcp(4.0f * oh) : 0.0f;
+}
+
+// a direction from the lobe about wo; false (no sample) below the surface
+__device__ __forceinline__ bool ggx_sample(V3 n, V3 wo, float a, float u0, float u1, V3 &wi)
+{
+    // cos^2 and sin^2 of theta_h: (1 - u0) / d and a^2 u0 / d, d = 1 - u0 + a^2 u0
+    const float a2 = a * a, om = 1.0f - u0, d = rcp(fmaf(a2, u0, om));
+    const float ct = fsqrt(om * d), st = fsqrt(a2 * u0 * d);
+    const float sp = sin_rev(u1), cp = cos_rev(u1);
+    const float sg = n.z >= 0.0f ? 1.0f : -1.0f;
+    const float aa = -rcp(sg + n.z);
+    const float b = n.x * n.y * aa;
+    const V3 t = v3(1.0f + sg * n.x * n.x * aa, sg * b, -sg * n.x);
+    const V3 bt = v3(b, sg + n.y * n.y * aa, -n.y);
+    const V3 h = v3(st * cp * t.x + st * sp * bt.x + ct * n.x, st * cp * t.y + st * sp * bt.y + ct * n.y,
+                    st * cp * t.z + st * sp * bt.z + ct * n.z);
+    const float oh = dot(wo, h);
+    wi = v3(2.0f * oh * h.x - wo.x, 2.0f * oh * h.y - wo.y, 2.0f * oh * h.z - wo.z);
+    return dot(n, wi) > 0.0f && dot(n, wo) > 0.0f;
+}
+
+// primary-vertex lobe choice: the glossy lobe with probability k_s / (k_s + lum(rho))
+__device__ __forceinline__ float p_gloss(V3 rho, float ks) { return ks > 0.0f ? ks * rcp(ks + lum(rho)) : 0.0f; }
+
+// solid-angle density of the BSDF mixture
+__device__ __forceinline__ float mix_pdf(V3 rho, float ks, float a, V3 n, V3 wo, V3 wi)
+{
+    const float pg = p_gloss(rho, ks), c = dot(n, wi);
+    const float pd = c > 0.0f ? c * kInvPi : 0.0f;
+    return (1.0f - pg) * pd + (pg > 0.0f ? pg * ggx_pdf(n, wo, wi, a) : 0.0f);
+}
+
+// f = rho/pi + k_s f_g(wo, wi)
+__device__ __forceinline__ V3 bsdf(V3 rho, float ks, float a, V3 n, V3 wo, V3 wi)
+{
+    const float g = ks > 0.0f ? ks * ggx_eval(n, wo, wi, a) : 0.0f;
+    return v3(fmaf(kInvPi, rho.x, g), fmaf(kInvPi, rho.y, g), fmaf(kInvPi, rho.z, g));
+}
+
+// material with the glossy layer (record slots albedo.w = k_s, emit.w = roughness)
+__device__ __forceinline__ void material_g(const gi_scene &sc, uint32_t prim, V3 &alb, V3 &emit, float &ks, float &a)
+{
+    if (prim < sc.n_prims) {
+        const float4 *p = reinterpret_cast<const float4 *>(sc.prims + prim);
+        const float4 c = p[2], e = p[3];
+        alb = xyz(c);
+        emit = xyz(e);
+        ks = c.w;
+        a = e.w;
+    } else {
+        alb = ld3(sc.wall_albedo);
+        emit = ld3(sc.wall_emit);
+        ks = 0.0f;
+        a = 1.0f;
+    }
+}
+
+// glossy part of L_DDGI+ (Eq. 6): one lobe sample wi, weighted k_s f_g cos / pdf,
+// times E(pb, wi)/(2 pi) = Q(pb, wi)/2 (the tiles hold E/pi; the query takes
+// wi in place of the normal)
+__device__ __forceinline__ V3 glossy_term(const gi_probes &pr, V3 pb, V3 n, V3 wo, float ks, float a, float u0, float u1)
+{
+    V3 wi;
+    if (!ggx_sample(n, wo, a, u0, u1, wi)) return v3(0.0f, 0.0f, 0.0f);
+    const float pdf = ggx_pdf(n, wo, wi, a);
+    if (!(pdf > 0.0f)) return v3(0.0f, 0.0f, 0.0f);
+    const float w = ks * ggx_eval(n, wo, wi, a) * dot(n, wi) * rcp(pdf);
+    return (0.5f * w) * probe_query(pr, pb, wi);
+}
+
+// L_DDGI+ leaving y toward x in a glossy scene: L_e + rho Q(y_b, n_y) + the
+// glossy part with uniforms (u0, u1)
+__device__ __forceinline__ V3 radiance_toward_g(const gi_scene &sc, const gi_probes &pr, uint32_t prim, V3 y, V3 ny,
+                                                V3 x, float u0, float u1)
+{
+    V3 alb, emit;
+    float ks, a;
+    material_g(sc, prim, alb, emit, ks, a);
+    V3 L = emit;
+    const bool diff = !is_zero(alb);
+    if (!diff && !(ks > 0.0f)) return L;
+    const V3 pb = view_bias(y, x, pr.bias_dist);
+    if (diff) {
+        const V3 q = probe_query(pr, pb, ny);
+        L = v3(fmaf(alb.x, q.x, L.x), fmaf(alb.y, q.y, L.y), fmaf(alb.z, q.z, L.z));
+    }
+    if (ks > 0.0f) {
+        V3 wo = x - y;
+        wo = frsq(dot(wo, wo)) * wo;
+        L = L + glossy_term(pr, pb, ny, wo, ks, a, u0, u1);
+    }
+    return L;
+}
+
 __device__ __forceinline__ float target(V3 x, V3 nx, V3 rho, V3 y, V3 ny, V3 L, float g_max)
 {
     float fl = kInvPi * lum(rho * L);

@@ -69,13 +69,20 @@ struct GB {
     V3 n;
     uint32_t prim;
     V3 alb;
+    float ks, rough;     // glossy layer (glossy loads only; else 0 and 1)
+    V3 wo;               // unit direction toward the camera (glossy loads only)
 };
 
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 
+// GLOSSY: also the glossy layer (k_s in albedo.w, roughness in emit.w) and
+// the direction toward the camera position the buffer was traced from
+template <bool GLOSSY = false>
 __device__ __forceinline__ GB load_gb(const gi_gbuffer &g, uint32_t p)
 {
     float4 a = reinterpret_cast<const float4 *>(g.pos_depth)[p];
+    GB r;
+    float ks = 0.0f;
     if (g.format == GI_GB_F16) {
         const half4_t b = reinterpret_cast<const half4_t *>(g.nrm_prim)[p];
         const half4_t c = reinterpret_cast<const half4_t *>(g.albedo)[p];
@@ -85,29 +92,45 @@ __device__ __forceinline__ GB load_gb(const gi_gbuffer &g, uint32_t p)
         V3 n = v3((float)b[0], (float)b[1], (float)b[2]);
         const float nn = dot(n, n);
         if (nn > 0.0f) n = frsq(nn) * n;
-        return GB{xyz(a), a.w, n, prim16 == 0xFFFFu ? GI_MISS : prim16, v3((float)c[0], (float)c[1], (float)c[2])};
+        r = GB{xyz(a), a.w, n, prim16 == 0xFFFFu ? GI_MISS : prim16, v3((float)c[0], (float)c[1], (float)c[2]),
+               0.0f, 1.0f, v3(0.0f, 0.0f, 1.0f)};
+        ks = (float)c[3];
+    } else {
+        float4 b = reinterpret_cast<const float4 *>(g.nrm_prim)[p];
+        float4 c = reinterpret_cast<const float4 *>(g.albedo)[p];
+        r = GB{xyz(a), a.w, xyz(b), __float_as_uint(b.w), xyz(c), 0.0f, 1.0f, v3(0.0f, 0.0f, 1.0f)};
+        ks = c.w;
     }
-    float4 b = reinterpret_cast<const float4 *>(g.nrm_prim)[p];
-    float4 c = reinterpret_cast<const float4 *>(g.albedo)[p];
-    return GB{xyz(a), a.w, xyz(b), __float_as_uint(b.w), xyz(c)};
+    if constexpr (GLOSSY) {
+        r.ks = ks;
+        r.rough = reinterpret_cast<const float4 *>(g.emit)[p].w;
+        V3 v = ld3(g.eye) - r.pos;
+        r.wo = frsq(dot(v, v)) * v;
+    }
+    return r;
 }
 
-// normal + primitive and albedo records of the G-buffer's format
-__device__ __forceinline__ void store_gb_na(const gi_gbuffer &g, uint32_t p, V3 n, uint32_t prim, V3 alb)
+// normal + primitive and albedo (+ glossy weight k_s) records of the G-buffer's format
+__device__ __forceinline__ void store_gb_na(const gi_gbuffer &g, uint32_t p, V3 n, uint32_t prim, V3 alb, float ks)
 {
     if (g.format == GI_GB_F16) {
         const uint16_t prim16 = prim == GI_MISS ? (uint16_t)0xFFFFu : (uint16_t)prim;
         half4_t b = {(_Float16)n.x, (_Float16)n.y, (_Float16)n.z, __builtin_bit_cast(_Float16, prim16)};
-        half4_t c = {(_Float16)alb.x, (_Float16)alb.y, (_Float16)alb.z, (_Float16)0.0f};
+        half4_t c = {(_Float16)alb.x, (_Float16)alb.y, (_Float16)alb.z, (_Float16)ks};
         reinterpret_cast<half4_t *>(g.nrm_prim)[p] = b;
         reinterpret_cast<half4_t *>(g.albedo)[p] = c;
         return;
     }
     reinterpret_cast<float4 *>(g.nrm_prim)[p] = make_float4(n.x, n.y, n.z, __uint_as_float(prim));
-    reinterpret_cast<float4 *>(g.albedo)[p] = make_float4(alb.x, alb.y, alb.z, 0.0f);
+    reinterpret_cast<float4 *>(g.albedo)[p] = make_float4(alb.x, alb.y, alb.z, ks);
 }
 
-__device__ __forceinline__ bool active(const GB &g) { return g.prim != GI_MISS && !is_zero(g.alb); }
+// a pixel is shaded when its surface reflects: diffuse albedo (or a glossy layer)
+template <bool GLOSSY = false>
+__device__ __forceinline__ bool active(const GB &g)
+{
+    return g.prim != GI_MISS && (!is_zero(g.alb) || (GLOSSY && g.ks > 0.0f));
+}
 
 __device__ __forceinline__ bool similar(const GB &g, const GB &q, const gi_params &pp)
 {
@@ -117,8 +140,27 @@ __device__ __forceinline__ bool similar(const GB &g, const GB &q, const gi_param
     return true;
 }
 
+// p_hat with the full BSDF of a glossy pixel: f(x, wo, wi) L min(G, G_max)
+// (sky samples: f L cos)
+__device__ __forceinline__ float target_glossy(const GB &g, V3 y, V3 ny, V3 L, float g_max)
+{
+    if (is_zero(ny)) {
+        const float cx = dot(g.n, y);
+        if (cx <= 0.0f) return 0.0f;
+        return lum(bsdf(g.alb, g.ks, g.rough, g.n, g.wo, y) * L) * cx;
+    }
+    V3 v = y - g.pos;
+    float d2 = dot(v, v);
+    V3 w = frsq(d2) * v;
+    float cx = dot(g.n, w), cy = -dot(ny, w);
+    if (cx <= 0.0f || cy <= 0.0f) return 0.0f;
+    return lum(bsdf(g.alb, g.ks, g.rough, g.n, g.wo, w) * L) * fminf(cx * cy * rcp(d2), g_max);
+}
+
+template <bool GLOSSY = false>
 __device__ __forceinline__ float res_target(const GB &g, const Res &r, float g_max)
 {
+    if constexpr (GLOSSY) return target_glossy(g, r.y, r.n, r.L, g_max);
     return target(g.pos, g.n, g.alb, r.y, r.n, r.L, g_max);
 }
 
@@ -155,17 +197,19 @@ __global__ void __launch_bounds__(kBlock) k_gbuffer(gi_scene sc, gi_camera cam, 
     const V3 zero = v3(0.0f, 0.0f, 0.0f);
     if (!cast<false>(sc, acc, o, d, kInf, h)) {
         pd[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        store_gb_na(gb, p, zero, GI_MISS, zero);
-        em[p] = make_float4(sc.sky[0], sc.sky[1], sc.sky[2], 0.0f);
+        store_gb_na(gb, p, zero, GI_MISS, zero, 0.0f);
+        em[p] = make_float4(sc.sky[0], sc.sky[1], sc.sky[2], 1.0f);
         return;
     }
     V3 x = madd(o, h.t, d);
     V3 n = hit_normal(sc, acc, o, d, h);
     V3 alb, emit;
-    material(sc, h.prim, alb, emit);
+    float ks = 0.0f, rough = 1.0f;
+    if (sc.options & GI_OPT_GLOSSY) material_g(sc, h.prim, alb, emit, ks, rough);
+    else material(sc, h.prim, alb, emit);
     pd[p] = make_float4(x.x, x.y, x.z, h.t * dot(d, ld3(cam.fwd)));
-    store_gb_na(gb, p, n, h.prim, alb);
-    em[p] = make_float4(emit.x, emit.y, emit.z, 0.0f);
+    store_gb_na(gb, p, n, h.prim, alb, ks);
+    em[p] = make_float4(emit.x, emit.y, emit.z, rough);
 }
 
 // --------------------------------------------------------------------------
@@ -185,7 +229,9 @@ __device__ __forceinline__ int gutter_source(int x, int y, int N)
     return (sy - 1) * N + (sx - 1);
 }
 
-template <bool LDS>
+// GLOSSY: a hit on a glossy surface adds the glossy part of L_DDGI+ toward the
+// probe (Eq. 6, one lobe sample, counter (probe, frame, 15, ray))
+template <bool LDS, bool GLOSSY>
 __global__ void __launch_bounds__(kProbeBlock)
     k_probe_update(gi_scene sc, gi_probes in, gi_probes out, gi_probe_params pp, uint64_t seed, uint32_t frame)
 {
@@ -212,7 +258,9 @@ __global__ void __launch_bounds__(kProbeBlock)
             V3 hp = madd(P, h.t, w);
             V3 n = hit_normal(sc, acc, P, w, h);
             V3 alb, emit;
-            material(sc, h.prim, alb, emit);
+            float ks = 0.0f, ra = 1.0f;
+            if (GLOSSY) material_g(sc, h.prim, alb, emit, ks, ra);
+            else material(sc, h.prim, alb, emit);
             if (pp.distance_slider > 0.0f && !is_zero(emit)) {
                 // distance heuristic: emission scaled by (t / (t + s d_b))^2, d_b the
                 // probe's backward mean depth clipped to its cell
@@ -229,6 +277,10 @@ __global__ void __launch_bounds__(kProbeBlock)
             if (!is_zero(alb)) {
                 V3 q = probe_query(in, view_bias(hp, P, in.bias_dist), n);
                 L = v3(fmaf(alb.x, q.x, emit.x), fmaf(alb.y, q.y, emit.y), fmaf(alb.z, q.z, emit.z));
+            }
+            if (GLOSSY && ks > 0.0f) {
+                const uint4 rg = philox(seed, pi, frame, kPassGlossyProbe, r);
+                L = L + glossy_term(in, view_bias(hp, P, in.bias_dist), n, -w, ks, ra, u01(rg.x), u01(rg.y));
             }
             dist = fminf(h.t, in.d_max);
         } else {
@@ -380,7 +432,12 @@ __global__ void __launch_bounds__(kBlock)
 // of the same candidates, through the same arithmetic as WS = false.
 // LIGHT: emitter candidates present (M_light > 0); without them the loop
 // compiles to the plain cosine-candidate form.
-template <bool LDS, bool WS, bool LIGHT>
+// GLOSSY: the whole BSDF at x (Sec. 3.3): candidate directions from the
+// mixture of the cosine and glossy lobes (lobe chosen by the candidate's
+// fourth uniform), L_DDGI+ at the candidates with its glossy part (one lobe
+// sample, counter (pixel, frame, 14, i)), weights p_hat over the mixture's
+// density in area measure, residual f L (G - G_max) / p_A.
+template <bool LDS, bool WS, bool LIGHT, bool GLOSSY>
 __global__ void __launch_bounds__(kBlock, 4)
     k_initial(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_params pp, gi_reservoirs out, float4 *resid,
               uint64_t seed, uint32_t frame, CandWs ws, gi_mlp mlp)
@@ -392,15 +449,16 @@ __global__ void __launch_bounds__(kBlock, 4)
     if (!inside) return;
     const Acc acc(sc);
     const uint32_t p = py * gb.width + px;
-    const GB g = load_gb(gb, p);
+    const GB g = load_gb<GLOSSY>(gb, p);
     V3 rs = v3(0.0f, 0.0f, 0.0f);
-    if (!active(g)) {
+    if (!active<GLOSSY>(g)) {
         store_res(out, p, empty_res(0));
         resid[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         return;
     }
     const V3 o = madd(g.pos, sc.eps, g.n);
     const V3 rho_pi = kInvPi * g.alb;
+    const float pg_x = GLOSSY ? p_gloss(g.alb, g.ks) : 0.0f;
     const bool use_cache = WS && mlp_selected(mlp);
     const size_t npx = (size_t)gb.width * gb.height;
     const uint32_t Mt = LIGHT ? pp.M + pp.M_light : pp.M;
@@ -441,14 +499,17 @@ __global__ void __launch_bounds__(kBlock, 4)
                 prim = __float_as_uint(a.w);
             }
         } else {
-            w = cosine_dir(g.n, u01(rn.x), u01(rn.y));
+            bool dir_ok = true;
+            if (GLOSSY && pg_x > 0.0f && u01(rn.w) < pg_x) dir_ok = ggx_sample(g.n, g.wo, g.rough, u01(rn.x), u01(rn.y), w);
+            else w = cosine_dir(g.n, u01(rn.x), u01(rn.y));
             Hit h;
-            hit = cast<false>(sc, acc, o, w, kInf, h);
+            hit = dir_ok && cast<false>(sc, acc, o, w, kInf, h);
             if (hit) {
                 y = madd(o, h.t, w);
                 ny = hit_normal(sc, acc, o, w, h);
                 prim = h.prim;
             }
+            if (GLOSSY && !dir_ok) w = v3(0.0f, 0.0f, 0.0f);   // no candidate: neither surface nor sky
         }
         if (hit) {
             V3 v = y - g.pos;
@@ -456,25 +517,45 @@ __global__ void __launch_bounds__(kBlock, 4)
             V3 wv = frsq(d2) * v;
             float cx = dot(g.n, wv), cy = -dot(ny, wv);
             if (cx > 0.0f && cy > 0.0f) {
-                L = (use_cache && i < pp.M) ? radiance_cached(sc, prim, ws.q[i * npx + p])
-                                            : radiance_toward(sc, pr, prim, y, ny, g.pos);
-                float G = cx * cy * rcp(d2);
-                float fl = lum(rho_pi * L);
-                float iG = rcp(G);
-                phat = fl * fminf(G, pp.g_max);
-                if (!LIGHT)
-                    wi = kPi * phat * iG;   // p_hat / p_A with p_A = G / pi
-                else
-                    wi = phat * rcp(mixb * kInvPi * G + mixl * light_pdf(sc, prim));
-                if (i == 0 && G > pp.g_max) rs = (1.0f - pp.g_max * iG) * (g.alb * L);
+                if constexpr (GLOSSY) {
+                    const uint4 rg = philox(seed, p, frame, kPassGlossyCand, i);
+                    L = radiance_toward_g(sc, pr, prim, y, ny, g.pos, u01(rg.x), u01(rg.y));
+                    const V3 f = bsdf(g.alb, g.ks, g.rough, g.n, g.wo, wv) * L;
+                    const float G = cx * cy * rcp(d2);
+                    const float pA = mix_pdf(g.alb, g.ks, g.rough, g.n, g.wo, wv) * cy * rcp(d2);
+                    phat = lum(f) * fminf(G, pp.g_max);
+                    if (!LIGHT)
+                        wi = pA > 0.0f ? phat * rcp(pA) : 0.0f;
+                    else
+                        wi = phat * rcp(mixb * pA + mixl * light_pdf(sc, prim));
+                    if (i == 0 && G > pp.g_max && pA > 0.0f) rs = ((G - pp.g_max) * rcp(pA)) * f;
+                } else {
+                    L = (use_cache && i < pp.M) ? radiance_cached(sc, prim, ws.q[i * npx + p])
+                                                : radiance_toward(sc, pr, prim, y, ny, g.pos);
+                    float G = cx * cy * rcp(d2);
+                    float fl = lum(rho_pi * L);
+                    float iG = rcp(G);
+                    phat = fl * fminf(G, pp.g_max);
+                    if (!LIGHT)
+                        wi = kPi * phat * iG;   // p_hat / p_A with p_A = G / pi
+                    else
+                        wi = phat * rcp(mixb * kInvPi * G + mixl * light_pdf(sc, prim));
+                    if (i == 0 && G > pp.g_max) rs = (1.0f - pp.g_max * iG) * (g.alb * L);
+                }
             }
-        } else if (!LIGHT || i < pp.M) {
+        } else if ((!LIGHT || i < pp.M) && (!GLOSSY || !is_zero(w))) {
             y = w;
             L = ld3(sc.sky);
             float cx = dot(g.n, w);
             if (cx > 0.0f) {
-                phat = lum(rho_pi * L) * cx;
-                wi = kPi * phat * rcp(cx);
+                if constexpr (GLOSSY) {
+                    phat = lum(bsdf(g.alb, g.ks, g.rough, g.n, g.wo, w) * L) * cx;
+                    const float pd = mix_pdf(g.alb, g.ks, g.rough, g.n, g.wo, w);
+                    wi = pd > 0.0f ? phat * rcp(pd) : 0.0f;
+                } else {
+                    phat = lum(rho_pi * L) * cx;
+                    wi = kPi * phat * rcp(cx);
+                }
                 if (LIGHT) wi *= rcp(mixb);
             }
         }
@@ -507,10 +588,11 @@ struct Merge {
     Res sel;
 };
 
+template <bool GLOSSY = false>
 __device__ __forceinline__ void merge_in(Merge &m, const GB &g, const Res &q, uint32_t Mq, float u, float g_max)
 {
     float w = 0.0f;
-    if (q.W > 0.0f && Mq > 0u) w = res_target(g, q, g_max) * q.W * (float)Mq;
+    if (q.W > 0.0f && Mq > 0u) w = res_target<GLOSSY>(g, q, g_max) * q.W * (float)Mq;
     m.wsum += w;
     m.Msum += Mq;
     if (u * m.wsum < w) {
@@ -525,7 +607,7 @@ constexpr int kMaxDom = GI_MAX_K + 1;
 // a neighbour that was rejected or never drawn) and is loaded by dom(j);
 // slot 0 is the pixel itself.  Slots are static so that the unrolled loop
 // keeps everything in registers.
-template <int ND, class DomFn, class G>
+template <bool GLOSSY, int ND, class DomFn, class G>
 __device__ __forceinline__ Res finish(const gi_scene &sc, const G &acc, const Merge &m, const GB &g,
                                       const uint32_t (&Mdom)[ND], DomFn dom, const gi_params &pp)
 {
@@ -535,7 +617,7 @@ __device__ __forceinline__ Res finish(const gi_scene &sc, const G &acc, const Me
         return e;
     }
     Res r = m.sel;
-    float ph = res_target(g, r, pp.g_max);
+    float ph = res_target<GLOSSY>(g, r, pp.g_max);
     float Z;
     bool keep = true;
     if (pp.unbiased) {
@@ -547,7 +629,7 @@ __device__ __forceinline__ Res finish(const gi_scene &sc, const G &acc, const Me
         for (int j = 1; j < ND; ++j) {
             if (Mdom[j] == 0u) continue;
             GB q = dom(j);
-            if (res_target(q, r, pp.g_max) <= 0.0f) continue;
+            if (res_target<GLOSSY>(q, r, pp.g_max) <= 0.0f) continue;
             if (visible(sc, acc, q.pos, q.n, r.y, r.n, sky)) z += Mdom[j];
         }
         Z = (float)z;
@@ -574,7 +656,7 @@ __device__ __forceinline__ int reproject(const gi_camera &c, V3 x)
     return (int)fy * (int)c.width + (int)fx;
 }
 
-template <bool LDS>
+template <bool LDS, bool GLOSSY>
 __global__ void __launch_bounds__(kBlock)
     k_temporal(gi_scene sc, gi_gbuffer gb, gi_gbuffer gbp, gi_camera cam_prev, gi_reservoirs cur,
                gi_reservoirs hist, gi_params pp, gi_reservoirs out, uint64_t seed, uint32_t frame)
@@ -586,33 +668,33 @@ __global__ void __launch_bounds__(kBlock)
     if (!inside) return;
     const Acc acc(sc);
     const uint32_t p = py * gb.width + px;
-    const GB g = load_gb(gb, p);
+    const GB g = load_gb<GLOSSY>(gb, p);
     const Res rc = load_res(cur, p);
-    if (!active(g)) {
+    if (!active<GLOSSY>(g)) {
         store_res(out, p, rc);
         return;
     }
     Merge m{0.0f, 0u, false, rc};
     uint32_t Mdom[2] = {rc.M, 0u};
     uint32_t qprev = 0u;
-    merge_in(m, g, rc, rc.M, 0.0f, pp.g_max);
+    merge_in<GLOSSY>(m, g, rc, rc.M, 0.0f, pp.g_max);
     int q = reproject(cam_prev, g.pos);
     if (q >= 0) {
-        GB gq = load_gb(gbp, (uint32_t)q);
+        GB gq = load_gb<GLOSSY>(gbp, (uint32_t)q);
         if (similar(g, gq, pp)) {
             Res rh = load_res(hist, (uint32_t)q);
             float cap = pp.m_cap * (float)rc.M;
             uint32_t Mh = (float)rh.M > cap ? (uint32_t)cap : rh.M;
             uint4 rn = philox(seed, p, frame, kPassTemporal, 0u);
-            merge_in(m, g, rh, Mh, u01(rn.x), pp.g_max);
+            merge_in<GLOSSY>(m, g, rh, Mh, u01(rn.x), pp.g_max);
             Mdom[1] = Mh;
             qprev = (uint32_t)q;
         }
     }
-    store_res(out, p, finish(sc, acc, m, g, Mdom, [&](int) { return load_gb(gbp, qprev); }, pp));
+    store_res(out, p, finish<GLOSSY>(sc, acc, m, g, Mdom, [&](int) { return load_gb<GLOSSY>(gbp, qprev); }, pp));
 }
 
-template <bool LDS>
+template <bool LDS, bool GLOSSY>
 __global__ void __launch_bounds__(kBlock)
     k_spatial(gi_scene sc, gi_gbuffer gb, gi_reservoirs in, gi_params pp, uint32_t pass, gi_reservoirs out,
               uint64_t seed, uint32_t frame)
@@ -625,9 +707,9 @@ __global__ void __launch_bounds__(kBlock)
     const Acc acc(sc);
     const uint32_t W = gb.width, H = gb.height;
     const uint32_t p = py * W + px;
-    const GB g = load_gb(gb, p);
+    const GB g = load_gb<GLOSSY>(gb, p);
     const Res rc = load_res(in, p);
-    if (!active(g)) {
+    if (!active<GLOSSY>(g)) {
         store_res(out, p, rc);
         return;
     }
@@ -635,7 +717,7 @@ __global__ void __launch_bounds__(kBlock)
     uint32_t Mdom[kMaxDom], qidx[kMaxDom];
     Mdom[0] = rc.M;
     qidx[0] = p;
-    merge_in(m, g, rc, rc.M, 0.0f, pp.g_max);
+    merge_in<GLOSSY>(m, g, rc, rc.M, 0.0f, pp.g_max);
 #pragma unroll
     for (uint32_t j = 0; j < GI_MAX_K; ++j) {
         Mdom[j + 1] = 0u;
@@ -649,25 +731,83 @@ __global__ void __launch_bounds__(kBlock)
         if (qx < 0 || qy < 0 || qx >= (int)W || qy >= (int)H) continue;
         if (qx == (int)px && qy == (int)py) continue;
         uint32_t q = (uint32_t)qy * W + (uint32_t)qx;
-        GB gq = load_gb(gb, q);
+        GB gq = load_gb<GLOSSY>(gb, q);
         if (!similar(g, gq, pp)) continue;
         Res rq = load_res(in, q);
-        merge_in(m, g, rq, rq.M, u01(rn.z), pp.g_max);
+        merge_in<GLOSSY>(m, g, rq, rq.M, u01(rn.z), pp.g_max);
         Mdom[j + 1] = rq.M;
         qidx[j + 1] = q;
     }
-    store_res(out, p, finish(sc, acc, m, g, Mdom, [&](int j) { return load_gb(gb, qidx[j]); }, pp));
+    store_res(out, p, finish<GLOSSY>(sc, acc, m, g, Mdom, [&](int j) { return load_gb<GLOSSY>(gb, qidx[j]); }, pp));
 }
 
 // --------------------------------------------------------------------------
 // shading
 // --------------------------------------------------------------------------
+// Specular recursion for shading (Sec. 3.3, Eq. 7-8) from the selected
+// sample v (primitive prim, normal nv) toward prev: at each vertex the
+// emission and the diffuse probe term rho Q(v_b, n_v), then one direction
+// from the glossy lobe (counter (pixel, frame, 16, depth)) weighted
+// k_s f_g cos / pdf.  While the footprint a = foot^2 stays within a_0 c and
+// below the depth limit the direction is traced (the sky if it leaves) and
+// the walk continues at the hit, adding sqrt(|z - v|^2 / (pdf cos_z)) to
+// foot; otherwise the probes estimate the glossy integral (Q(v_b, wi)/2).
+// The loop form carries the product of the weights so far (grey).
+template <class G>
+__device__ V3 shade_glossy(const gi_scene &sc, const G &acc, const gi_probes &pr, const gi_params &pp, uint64_t seed,
+                           uint32_t pixel, uint32_t frame, uint32_t prim, V3 v, V3 nv, V3 prev, float foot, float a0c)
+{
+    V3 L = v3(0.0f, 0.0f, 0.0f);
+    float thr = 1.0f;
+    for (uint32_t depth = 1; depth <= GI_MAX_GLOSSY_DEPTH; ++depth) {
+        V3 alb, emit;
+        float ks, a;
+        material_g(sc, prim, alb, emit, ks, a);
+        L = L + thr * emit;
+        const V3 pb = view_bias(v, prev, pr.bias_dist);
+        if (!is_zero(alb)) L = L + thr * (alb * probe_query(pr, pb, nv));
+        if (!(ks > 0.0f)) break;
+        V3 wo = prev - v;
+        wo = frsq(dot(wo, wo)) * wo;
+        const uint4 rn = philox(seed, pixel, frame, kPassGlossyShade, depth);
+        V3 wi;
+        if (!ggx_sample(nv, wo, a, u01(rn.x), u01(rn.y), wi)) break;
+        const float pdf = ggx_pdf(nv, wo, wi, a);
+        if (!(pdf > 0.0f)) break;
+        const float wgt = ks * ggx_eval(nv, wo, wi, a) * dot(nv, wi) * rcp(pdf);
+        if (foot * foot > a0c || depth >= pp.glossy_depth) {
+            L = L + (thr * 0.5f * wgt) * probe_query(pr, pb, wi);
+            break;
+        }
+        const V3 o = madd(v, sc.eps, nv);
+        Hit h;
+        if (!cast<false>(sc, acc, o, wi, kInf, h)) {
+            L = L + (thr * wgt) * ld3(sc.sky);
+            break;
+        }
+        const V3 z = madd(o, h.t, wi);
+        const V3 nz = hit_normal(sc, acc, o, wi, h);
+        const V3 dz = z - v;
+        const float cz = -dot(nz, wi);
+        foot += cz > 0.0f ? fsqrt(dot(dz, dz) * rcp(pdf * cz)) : kInf;
+        thr *= wgt;
+        prev = v;
+        v = z;
+        nv = nz;
+        prim = h.prim;
+    }
+    return L;
+}
+
 // WS = true: the fresh query is the cache value q[p] evaluated at the
 // reservoir's sample when the cache is selected (probe query otherwise).
-template <bool LDS, bool WS>
+// GLOSSY: f(x) replaces rho_x/pi and the fresh radiance follows the specular
+// recursion, started with the footprint of the segment x -> y (density of
+// the BSDF mixture at x) and a_0 c = c |x_0 - x|^2 / (4 pi cos) from the camera.
+template <bool LDS, bool WS, bool GLOSSY>
 __global__ void __launch_bounds__(kBlock)
     k_shade(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_reservoirs res, const float4 *resid, gi_params pp,
-            float4 *img, const float4 *q, gi_mlp mlp)
+            float4 *img, const float4 *q, gi_mlp mlp, uint64_t seed, uint32_t frame)
 {
     using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
     uint32_t px, py;
@@ -676,14 +816,14 @@ __global__ void __launch_bounds__(kBlock)
     if (!inside) return;
     const Acc acc(sc);
     const uint32_t p = py * gb.width + px;
-    const GB g = load_gb(gb, p);
+    const GB g = load_gb<GLOSSY>(gb, p);
     float4 e = reinterpret_cast<const float4 *>(gb.emit)[p];
     V3 o = xyz(e);
     if (g.prim != GI_MISS) {
         o = o + xyz(resid[p]);
         Res r = load_res(res, p);
         if (r.W > 0.0f) {
-            V3 L;
+            V3 L, wd = r.y;
             float geo = 0.0f;
             bool ok = false;
             if (is_zero(r.n)) {
@@ -696,17 +836,32 @@ __global__ void __launch_bounds__(kBlock)
                 V3 v = r.y - g.pos;
                 float d2 = dot(v, v);
                 V3 w = frsq(d2) * v;
+                wd = w;
                 float cx = dot(g.n, w), cy = -dot(r.n, w);
                 if (cx > 0.0f && cy > 0.0f) {
                     geo = fminf(cx * cy * rcp(d2), pp.g_max);
                     if (visible(sc, acc, g.pos, g.n, r.y, r.n, false)) {
-                        L = (WS && mlp_selected(mlp)) ? radiance_cached(sc, r.prim, q[p])
-                                                       : radiance_toward(sc, pr, r.prim, r.y, r.n, g.pos);
+                        if constexpr (GLOSSY) {
+                            const V3 vc = ld3(gb.eye) - g.pos;
+                            const float c1 = dot(g.n, g.wo);
+                            const float a0c = c1 > 0.0f ? pp.foot_c * dot(vc, vc) * rcp(4.0f * kPi * c1) : kInf;
+                            const float p1 = mix_pdf(g.alb, g.ks, g.rough, g.n, g.wo, w);
+                            const float foot = p1 > 0.0f ? fsqrt(d2 * rcp(p1 * cy)) : kInf;
+                            L = shade_glossy(sc, acc, pr, pp, seed, p, frame, r.prim, r.y, r.n, g.pos, foot, a0c);
+                        } else {
+                            L = (WS && mlp_selected(mlp)) ? radiance_cached(sc, r.prim, q[p])
+                                                           : radiance_toward(sc, pr, r.prim, r.y, r.n, g.pos);
+                        }
                         ok = true;
                     }
                 }
             }
-            if (ok) o = o + (kInvPi * geo * r.W) * (g.alb * L);
+            if (ok) {
+                if constexpr (GLOSSY)
+                    o = o + (geo * r.W) * (bsdf(g.alb, g.ks, g.rough, g.n, g.wo, wd) * L);
+                else
+                    o = o + (kInvPi * geo * r.W) * (g.alb * L);
+            }
         }
     }
     img[p] = make_float4(o.x, o.y, o.z, 1.0f);
@@ -770,7 +925,10 @@ __global__ void __launch_bounds__(kBlock)
 // --------------------------------------------------------------------------
 // reference path tracer (converged images for the error statements)
 // --------------------------------------------------------------------------
-template <bool LDS>
+// GLOSSY: at every vertex the BSDF mixture of the initial pass (glossy lobe
+// with probability k_s / (k_s + lum rho), chosen by u3), throughput times
+// f cos / pdf, roulette after that product
+template <bool LDS, bool GLOSSY>
 __global__ void __launch_bounds__(kBlock)
     k_path_trace(gi_scene sc, gi_gbuffer gb, uint32_t spp, uint32_t s0, uint64_t seed, float4 *out)
 {
@@ -781,11 +939,52 @@ __global__ void __launch_bounds__(kBlock)
     if (!inside) return;
     const Acc acc(sc);
     const uint32_t p = py * gb.width + px;
-    const GB g = load_gb(gb, p);
+    const GB g = load_gb<GLOSSY>(gb, p);
     const V3 e0 = xyz(reinterpret_cast<const float4 *>(gb.emit)[p]);
     V3 sum = v3(0.0f, 0.0f, 0.0f);
     for (uint32_t s = 0; s < spp; ++s) {
         V3 x = g.pos, n = g.n, rho = g.alb, L = e0, thr = v3(1.0f, 1.0f, 1.0f);
+        if constexpr (GLOSSY) {
+            if (g.prim == GI_MISS) {
+                sum = sum + L;
+                continue;
+            }
+            float ks = g.ks, ra = g.rough;
+            V3 wo = g.wo;
+            for (uint32_t b = 1; b <= 32; ++b) {
+                if (is_zero(rho) && !(ks > 0.0f)) break;
+                const uint4 rn = philox(seed, p, s0 + s, kPassReference, b);
+                const float pg = p_gloss(rho, ks);
+                V3 w;
+                if (pg > 0.0f && u01(rn.w) < pg) {
+                    if (!ggx_sample(n, wo, ra, u01(rn.x), u01(rn.y), w)) break;
+                } else {
+                    w = cosine_dir(n, u01(rn.x), u01(rn.y));
+                }
+                const float pd = mix_pdf(rho, ks, ra, n, wo, w);
+                if (!(pd > 0.0f)) break;
+                thr = thr * ((dot(n, w) * rcp(pd)) * bsdf(rho, ks, ra, n, wo, w));
+                if (b >= 4) {
+                    const float P = fminf(1.0f, fmaxf(thr.x, fmaxf(thr.y, thr.z)));
+                    if (!(u01(rn.z) < P)) break;
+                    thr = v3(thr.x / P, thr.y / P, thr.z / P);
+                }
+                const V3 o = madd(x, sc.eps, n);
+                Hit h;
+                if (!cast<false>(sc, acc, o, w, kInf, h)) {
+                    L = L + thr * ld3(sc.sky);
+                    break;
+                }
+                x = madd(o, h.t, w);
+                n = hit_normal(sc, acc, o, w, h);
+                wo = -w;
+                V3 emit;
+                material_g(sc, h.prim, rho, emit, ks, ra);
+                L = L + thr * emit;
+            }
+            sum = sum + L;
+            continue;
+        }
         for (uint32_t b = 1; b <= 32; ++b) {
             if (is_zero(rho)) break;
             const uint4 rn = philox(seed, p, s0 + s, kPassReference, b);
@@ -937,23 +1136,41 @@ uint32_t scene_lds(const gi_scene *sc, uint32_t static_lds = 0)
         if (lds) kernel<true><<<(grid), (block), (lds), (stream)>>>(__VA_ARGS__);             \
         else kernel<false><<<(grid), (block), 0, (stream)>>>(__VA_ARGS__);                   \
     } while (0)
-// k_initial with the scene staging (lds bytes, 0: none) and emitter candidates chosen at run time
-template <bool WS, class... A>
-void launch_initial(bool light, uint32_t lds, dim3 grid, hipStream_t st, A... a)
+// k_initial with the scene staging (lds bytes, 0: none), emitter candidates
+// and the glossy BSDF chosen at run time (the learned cache, WS, serves
+// Lambertian scenes only)
+template <bool WS, bool LIGHT, class... A>
+void launch_initial_l(bool glossy, uint32_t lds, dim3 grid, hipStream_t st, A... a)
 {
-    if (light) {
-        if (lds) k_initial<true, WS, true><<<grid, kBlock, lds, st>>>(a...);
-        else k_initial<false, WS, true><<<grid, kBlock, 0, st>>>(a...);
+    if (!WS && glossy) {
+        if (lds) k_initial<true, WS, LIGHT, !WS><<<grid, kBlock, lds, st>>>(a...);
+        else k_initial<false, WS, LIGHT, !WS><<<grid, kBlock, 0, st>>>(a...);
     } else {
-        if (lds) k_initial<true, WS, false><<<grid, kBlock, lds, st>>>(a...);
-        else k_initial<false, WS, false><<<grid, kBlock, 0, st>>>(a...);
+        if (lds) k_initial<true, WS, LIGHT, false><<<grid, kBlock, lds, st>>>(a...);
+        else k_initial<false, WS, LIGHT, false><<<grid, kBlock, 0, st>>>(a...);
     }
 }
+
+template <bool WS, class... A>
+void launch_initial(bool light, bool glossy, uint32_t lds, dim3 grid, hipStream_t st, A... a)
+{
+    if (light) launch_initial_l<WS, true>(glossy, lds, grid, st, a...);
+    else launch_initial_l<WS, false>(glossy, lds, grid, st, a...);
+}
+
+bool glossy_scene(const gi_scene *sc) { return (sc->options & GI_OPT_GLOSSY) != 0u; }
 
 #define GI_LAUNCH_LDS2(kernel, T2, grid, block, lds, stream, ...)                             \
     do {                                                                                      \
         if (lds) kernel<true, T2><<<(grid), (block), (lds), (stream)>>>(__VA_ARGS__);         \
         else kernel<false, T2><<<(grid), (block), 0, (stream)>>>(__VA_ARGS__);               \
+    } while (0)
+
+// kernel<LDS, GLOSSY> with both chosen at run time
+#define GI_LAUNCH_LDS_G(kernel, glossy, grid, block, lds, stream, ...)                          \
+    do {                                                                                      \
+        if (glossy) GI_LAUNCH_LDS2(kernel, true, grid, block, lds, stream, __VA_ARGS__);       \
+        else GI_LAUNCH_LDS2(kernel, false, grid, block, lds, stream, __VA_ARGS__);            \
     } while (0)
 
 }  // namespace
@@ -1013,7 +1230,8 @@ gi_status gi_probe_update(const gi_scene *scene, const gi_probes *in, gi_probes 
     if (!(pp->distance_slider >= 0.0f)) return GI_ERR_PARAM;
     uint32_t P = in->dims[0] * in->dims[1] * in->dims[2];
     uint32_t lds = scene_lds(scene, (uint32_t)sizeof(float) * (7u * GI_MAX_PROBE_RAYS + 64u * 3u + 256u * 2u));
-    GI_LAUNCH_LDS(k_probe_update, P, kProbeBlock, lds, S(stream), *scene, *in, *out, *pp, seed, frame);
+    GI_LAUNCH_LDS_G(k_probe_update, glossy_scene(scene), P, kProbeBlock, lds, S(stream), *scene, *in, *out, *pp,
+                    seed, frame);
     return launched();
 }
 
@@ -1041,7 +1259,8 @@ gi_status gi_resample_initial(const gi_scene *scene, const gi_gbuffer *gb, const
     if ((s = check_res(out, gb->width, gb->height)) != GI_OK) return s;
     if ((uint64_t)gb->width * gb->height > (1u << 23)) return GI_ERR_SHAPE;   // 23-bit tag origin
     if (gb->width == 0 || gb->height == 0) return GI_OK;
-    launch_initial<false>(params->M_light > 0, scene_lds(scene), tile_grid(gb->width, gb->height), S(stream),
+    launch_initial<false>(params->M_light > 0, glossy_scene(scene), scene_lds(scene),
+                          tile_grid(gb->width, gb->height), S(stream),
                           *scene, *gb, *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame,
                           CandWs{}, gi_mlp{});
     return launched();
@@ -1065,7 +1284,8 @@ gi_status gi_resample_temporal(const gi_scene *scene, const gi_gbuffer *gb, cons
     if ((s = check_res(out, W, H)) != GI_OK) return s;
     if (res_alias(out, cur_in) || res_alias(out, history)) return GI_ERR_ALIAS;
     if (W == 0 || H == 0) return GI_OK;
-    GI_LAUNCH_LDS(k_temporal, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *gb_prev,
+    GI_LAUNCH_LDS_G(k_temporal, glossy_scene(scene), tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene,
+                    *gb, *gb_prev,
                   *prev_cam, *cur_in, *history, *params, *out, seed, frame);
     return launched();
 }
@@ -1085,13 +1305,15 @@ gi_status gi_resample_spatial(const gi_scene *scene, const gi_gbuffer *gb, const
     if (res_alias(out, in)) return GI_ERR_ALIAS;
     if (pass > 5) return GI_ERR_PARAM;
     if (W == 0 || H == 0) return GI_OK;
-    GI_LAUNCH_LDS(k_spatial, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *in, *params,
+    GI_LAUNCH_LDS_G(k_spatial, glossy_scene(scene), tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene,
+                    *gb, *in, *params,
                   pass, *out, seed, frame);
     return launched();
 }
 
 gi_status gi_shade(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes, const gi_reservoirs *res,
-                   const float *resid, const gi_params *params, float *out_rgba, void *stream)
+                   const float *resid, const gi_params *params, float *out_rgba, uint64_t seed, uint32_t frame,
+                   void *stream)
 {
     gi_status s;
     if (!gb || !res || !resid || !out_rgba) return GI_ERR_NULL;
@@ -1101,10 +1323,25 @@ gi_status gi_shade(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes 
     if ((s = check_probes(probes)) != GI_OK) return s;
     if ((s = check_params(params)) != GI_OK) return s;
     if ((s = check_res(res, W, H)) != GI_OK) return s;
+    const bool glossy = glossy_scene(scene);
+    if (glossy && (!(params->foot_c >= 0.0f) || params->glossy_depth < 1u || params->glossy_depth > GI_MAX_GLOSSY_DEPTH))
+        return GI_ERR_PARAM;
     if (W == 0 || H == 0) return GI_OK;
-    GI_LAUNCH_LDS2(k_shade, false, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *probes,
-                   *res, reinterpret_cast<const float4 *>(resid), *params, reinterpret_cast<float4 *>(out_rgba),
-                   nullptr, gi_mlp{});
+    const uint32_t lds = scene_lds(scene);
+    const dim3 grid = tile_grid(W, H);
+    const float4 *rs = reinterpret_cast<const float4 *>(resid);
+    float4 *img = reinterpret_cast<float4 *>(out_rgba);
+    if (glossy) {
+        if (lds) k_shade<true, false, true><<<grid, kBlock, lds, S(stream)>>>(*scene, *gb, *probes, *res, rs, *params,
+                                                                           img, nullptr, gi_mlp{}, seed, frame);
+        else k_shade<false, false, true><<<grid, kBlock, 0, S(stream)>>>(*scene, *gb, *probes, *res, rs, *params, img,
+                                                                      nullptr, gi_mlp{}, seed, frame);
+    } else {
+        if (lds) k_shade<true, false, false><<<grid, kBlock, lds, S(stream)>>>(*scene, *gb, *probes, *res, rs, *params,
+                                                                            img, nullptr, gi_mlp{}, seed, frame);
+        else k_shade<false, false, false><<<grid, kBlock, 0, S(stream)>>>(*scene, *gb, *probes, *res, rs, *params, img,
+                                                                       nullptr, gi_mlp{}, seed, frame);
+    }
     return launched();
 }
 
@@ -1116,6 +1353,7 @@ gi_status gi_mlp_make_batch(const gi_scene *scene, const gi_gbuffer *gb, const g
     if (!gb) return GI_ERR_NULL;
     uint32_t W = gb->width, H = gb->height;
     if ((s = check_scene(scene)) != GI_OK) return s;
+    if (glossy_scene(scene)) return GI_ERR_PARAM;   // the learned cache serves Lambertian scenes
     if ((s = check_gb(gb, W, H)) != GI_OK) return s;
     if ((s = check_probes(probes)) != GI_OK) return s;
     if (M < 1 || M > GI_MAX_M) return GI_ERR_PARAM;
@@ -1143,6 +1381,7 @@ gi_status gi_resample_initial_mlp(const gi_scene *scene, const gi_gbuffer *gb, c
     if (!gb || !out || !resid || !workspace) return GI_ERR_NULL;
     uint32_t W = gb->width, H = gb->height;
     if ((s = check_scene(scene)) != GI_OK) return s;
+    if (glossy_scene(scene)) return GI_ERR_PARAM;   // the learned cache serves Lambertian scenes
     if ((s = check_gb(gb, W, H)) != GI_OK) return s;
     if ((s = check_probes(probes)) != GI_OK) return s;
     if ((s = check_mlp(mlp)) != GI_OK) return s;
@@ -1158,7 +1397,8 @@ gi_status gi_resample_initial_mlp(const gi_scene *scene, const gi_gbuffer *gb, c
                   frame);
     if ((s = launched()) != GI_OK) return s;
     if ((s = mlp_infer_launch(*mlp, (uint32_t)ncand, ws.pos, ws.nrm, ws.q, true, S(stream))) != GI_OK) return s;
-    launch_initial<true>(params->M_light > 0, 0u, tile_grid(W, H), S(stream), *scene, *gb, *probes, *params, *out,
+    launch_initial<true>(params->M_light > 0, false, 0u, tile_grid(W, H), S(stream), *scene, *gb, *probes, *params,
+                         *out,
                          reinterpret_cast<float4 *>(resid), seed, frame, ws, *mlp);
     return launched();
 }
@@ -1173,6 +1413,7 @@ gi_status gi_shade_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_pro
     if (!gb || !res || !resid || !out_rgba || !workspace) return GI_ERR_NULL;
     uint32_t W = gb->width, H = gb->height;
     if ((s = check_scene(scene)) != GI_OK) return s;
+    if (glossy_scene(scene)) return GI_ERR_PARAM;   // the learned cache serves Lambertian scenes
     if ((s = check_gb(gb, W, H)) != GI_OK) return s;
     if ((s = check_probes(probes)) != GI_OK) return s;
     if ((s = check_mlp(mlp)) != GI_OK) return s;
@@ -1184,9 +1425,15 @@ gi_status gi_shade_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_pro
     if ((s = mlp_infer_launch(*mlp, W * H, reinterpret_cast<const float4 *>(res->y_W),
                               reinterpret_cast<const float4 *>(res->n_wsum), q, true, S(stream))) != GI_OK)
         return s;
-    GI_LAUNCH_LDS2(k_shade, true, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *probes, *res,
-                   reinterpret_cast<const float4 *>(resid), *params, reinterpret_cast<float4 *>(out_rgba), q,
-                   *mlp);
+    {
+        const uint32_t lds = scene_lds(scene);
+        const float4 *rs = reinterpret_cast<const float4 *>(resid);
+        float4 *img = reinterpret_cast<float4 *>(out_rgba);
+        if (lds) k_shade<true, true, false><<<tile_grid(W, H), kBlock, lds, S(stream)>>>(*scene, *gb, *probes, *res, rs,
+                                                                                      *params, img, q, *mlp, 0ull, 0u);
+        else k_shade<false, true, false><<<tile_grid(W, H), kBlock, 0, S(stream)>>>(*scene, *gb, *probes, *res, rs,
+                                                                                 *params, img, q, *mlp, 0ull, 0u);
+    }
     return launched();
 }
 
@@ -1200,7 +1447,8 @@ gi_status gi_path_trace(const gi_scene *scene, const gi_gbuffer *gb, uint32_t sp
     if ((s = check_gb(gb, W, H)) != GI_OK) return s;
     if (spp < 1 || spp > 65536) return GI_ERR_PARAM;
     if (W == 0 || H == 0) return GI_OK;
-    GI_LAUNCH_LDS(k_path_trace, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, spp, sample0, seed,
+    GI_LAUNCH_LDS_G(k_path_trace, glossy_scene(scene), tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene,
+                    *gb, spp, sample0, seed,
                   reinterpret_cast<float4 *>(out_rgba));
     return launched();
 }

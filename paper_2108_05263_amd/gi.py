@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libgi.so")
 MISS = 0xFFFFFFFF
 EMPTY_TAG = 0xFFFFFFFF
 OPT_NO_LDS = 1
+OPT_GLOSSY = 2
 
 _lib = None
 
@@ -67,7 +68,7 @@ class GiCamera(C.Structure):
 class GiGBuffer(C.Structure):
     _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("pos_depth", C.c_void_p),
                 ("nrm_prim", C.c_void_p), ("albedo", C.c_void_p), ("emit", C.c_void_p),
-                ("format", C.c_uint32), ("pad", C.c_uint32)]
+                ("format", C.c_uint32), ("pad", C.c_uint32), ("eye", C.c_float * 3), ("pad2", C.c_float)]
 
 
 GB_FORMAT = {"f32": 0, "f16": 1}
@@ -87,7 +88,8 @@ class GiReservoirs(C.Structure):
 class GiParams(C.Structure):
     _fields_ = [("M", C.c_uint32), ("k", C.c_uint32), ("radius", C.c_float), ("g_max", C.c_float),
                 ("cos_n", C.c_float), ("depth_rel", C.c_float), ("m_cap", C.c_float),
-                ("unbiased", C.c_uint32), ("M_light", C.c_uint32), ("subsample", C.c_uint32)]
+                ("unbiased", C.c_uint32), ("M_light", C.c_uint32), ("subsample", C.c_uint32),
+                ("foot_c", C.c_float), ("glossy_depth", C.c_uint32)]
 
 
 class GiProbeParams(C.Structure):
@@ -125,7 +127,7 @@ def load():
         "gi_resample_initial": [_P, _P, _P, _P, _P, _P, C.c_uint64, C.c_uint32, _P],
         "gi_resample_temporal": [_P, _P, _P, _P, _P, _P, _P, _P, C.c_uint64, C.c_uint32, _P],
         "gi_resample_spatial": [_P, _P, _P, _P, C.c_uint32, _P, C.c_uint64, C.c_uint32, _P],
-        "gi_shade": [_P, _P, _P, _P, _P, _P, _P, _P],
+        "gi_shade": [_P, _P, _P, _P, _P, _P, _P, C.c_uint64, C.c_uint32, _P],
         "gi_accel_build_host": [_P, C.c_uint32, _P, _P, _P, _P, _P, C.c_uint32, _P],
         "gi_philox": [C.c_uint64, C.c_uint32, _P, _P, _P],
         "gi_trace_rays": [_P, C.c_uint32, _P, _P, _P, _P, _P],
@@ -164,8 +166,18 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def _ptr(t: torch.Tensor):
+def _ptr(t: torch.Tensor, dtype=None):
+    """Device pointer of a contiguous device tensor, of `dtype` when given (the
+    library reads and writes raw records: a buffer of another element type
+    would be misread, so it is refused)."""
+    if not (t.is_cuda and t.is_contiguous()):
+        raise GiError("buffers passed to the library must be contiguous device tensors")
+    if dtype is not None and t.dtype != dtype:
+        raise GiError(f"buffer of dtype {t.dtype} where {dtype} is required")
     return C.c_void_p(t.data_ptr())
+
+
+F32 = torch.float32
 
 
 def _f3(v):
@@ -191,6 +203,10 @@ class DeviceScene:
         s.sky = _f3(scene.sky)
         s.eps = float(scene.eps)
         s.options = 0 if lds else OPT_NO_LDS
+        # a glossy layer on any primitive (record slot 11 = k_s > 0) selects the glossy kernels
+        self.glossy = bool(len(rec) and np.any(rec[:, 11] > 0))
+        if self.glossy:
+            s.options |= OPT_GLOSSY
         # emitters light sampling draws from: the emissive spheres, in index order
         em = [i for i in range(len(rec)) if rec.view(np.uint32)[i, 3] == sg.PRIM_SPHERE and np.any(rec[i, 12:15] > 0)]
         if len(em) > 32:
@@ -274,10 +290,11 @@ class GBuffer:
             rec[:, 13] = npm[:, 3].view(np.uint32)
         return rec
 
-    def load_records(self, rec, pixels=None):
+    def load_records(self, rec, pixels=None, scene=None, eye=None):
         """Fill from (W*H, 14) oracle-layout records (rounded to float32); with
         `pixels`, rec holds one record per listed pixel and only those rows
-        are written."""
+        are written.  A glossy scene's layer (k_s, roughness) is looked up by
+        primitive id from `scene`; eye sets the camera position of the buffer."""
         rec = np.asarray(rec, np.float64)
         n = len(rec) if pixels is not None else self.W * self.H
         half = np.float16 if self.fmt == "f16" else np.float32
@@ -293,6 +310,15 @@ class GBuffer:
         else:
             npm.view(np.uint32)[:, 3] = prim.astype(np.uint32)
         al[:, 0:3], em[:, 0:3] = rec[:, 6:9], rec[:, 9:12]
+        em[:, 3] = 1.0
+        if scene is not None and len(scene.prims):
+            pr = np.asarray(scene.prims, np.float32)
+            own = prim < len(pr)
+            ids = np.where(own, prim, 0).astype(np.int64)
+            al[:, 3] = np.where(own, pr[ids, 11], 0.0)
+            em[:, 3] = np.where(own, pr[ids, 15], 1.0)
+        if eye is not None:
+            self.c.eye[:] = [float(v) for v in np.asarray(eye, np.float32).reshape(3)]
         idx = None if pixels is None else torch.as_tensor(np.asarray(pixels, np.int64), device=self.pos_depth.device)
         for t, a in ((self.pos_depth, pd), (self.nrm_prim, npm), (self.albedo, al), (self.emit, em)):
             if idx is None:
@@ -417,6 +443,8 @@ def params_struct(p: sg.Params) -> GiParams:
     g.unbiased = int(p.unbiased)
     g.M_light = int(getattr(p, "M_light", 0))
     g.subsample = int(getattr(p, "subsample", 1))
+    g.foot_c = float(getattr(p, "foot_c", 0.2))
+    g.glossy_depth = int(getattr(p, "glossy_depth", 8))
     return g
 
 
@@ -425,6 +453,7 @@ def params_struct(p: sg.Params) -> GiParams:
 # --------------------------------------------------------------------------
 def trace_gbuffer(scene: DeviceScene, cam, gb: GBuffer, stream=None):
     c = camera_struct(cam)
+    gb.c.eye[:] = [float(v) for v in np.asarray(cam.eye, np.float32).reshape(3)]
     check(load().gi_trace_gbuffer(scene.ref, C.byref(c), gb.ref, _stream(stream)), "gi_trace_gbuffer")
 
 
@@ -438,7 +467,7 @@ def probe_update(scene: DeviceScene, pin: Probes, pout: Probes, rays, hysteresis
 def probe_query(probes: Probes, p: torch.Tensor, n: torch.Tensor, stream=None) -> torch.Tensor:
     p, n = p.contiguous().float(), n.contiguous().float()
     out = torch.empty_like(p)
-    check(load().gi_probe_query(probes.ref, p.shape[0], _ptr(p), _ptr(n), _ptr(out), _stream(stream)),
+    check(load().gi_probe_query(probes.ref, p.shape[0], _ptr(p, F32), _ptr(n, F32), _ptr(out), _stream(stream)),
           "gi_probe_query")
     return out
 
@@ -446,7 +475,7 @@ def probe_query(probes: Probes, p: torch.Tensor, n: torch.Tensor, stream=None) -
 def resample_initial(scene, gb, probes, params, out: Reservoirs, resid: torch.Tensor, seed, frame,
                      stream=None):
     pp = params_struct(params)
-    check(load().gi_resample_initial(scene.ref, gb.ref, probes.ref, C.byref(pp), out.ref, _ptr(resid),
+    check(load().gi_resample_initial(scene.ref, gb.ref, probes.ref, C.byref(pp), out.ref, _ptr(resid, F32),
                                      int(seed), int(frame) & 0xFFFFFFFF, _stream(stream)),
           "gi_resample_initial")
 
@@ -466,10 +495,11 @@ def resample_spatial(scene, gb, res_in, params, spass, out, seed, frame, stream=
           "gi_resample_spatial")
 
 
-def shade(scene, gb, probes, res, resid, params, out_rgba: torch.Tensor, stream=None):
+def shade(scene, gb, probes, res, resid, params, out_rgba: torch.Tensor, stream=None, seed=0, frame=0):
+    """seed and frame drive the specular recursion of a glossy scene."""
     pp = params_struct(params)
-    check(load().gi_shade(scene.ref, gb.ref, probes.ref, res.ref, _ptr(resid), C.byref(pp),
-                          _ptr(out_rgba), _stream(stream)), "gi_shade")
+    check(load().gi_shade(scene.ref, gb.ref, probes.ref, res.ref, _ptr(resid, F32), C.byref(pp),
+                          _ptr(out_rgba, F32), int(seed), int(frame) & 0xFFFFFFFF, _stream(stream)), "gi_shade")
 
 
 def path_trace(scene: DeviceScene, gb: GBuffer, spp, seed, sample0=0, out_rgba=None, stream=None):
@@ -477,7 +507,7 @@ def path_trace(scene: DeviceScene, gb: GBuffer, spp, seed, sample0=0, out_rgba=N
     if out_rgba is None:
         out_rgba = torch.zeros(gb.W * gb.H, 4, dtype=torch.float32, device=gb.pos_depth.device)
     check(load().gi_path_trace(scene.ref, gb.ref, int(spp), int(sample0) & 0xFFFFFFFF, int(seed),
-                               _ptr(out_rgba), _stream(stream)), "gi_path_trace")
+                               _ptr(out_rgba, F32), _stream(stream)), "gi_path_trace")
     return out_rgba
 
 
@@ -493,7 +523,7 @@ def trace_rays(scene: DeviceScene, org: torch.Tensor, d: torch.Tensor, stream=No
     n = org.shape[0]
     out = torch.empty(n, 4, dtype=torch.float32, device=org.device)
     prim = torch.empty(n, dtype=torch.int32, device=org.device)
-    check(load().gi_trace_rays(scene.ref, n, _ptr(org), _ptr(d), _ptr(out), _ptr(prim),
+    check(load().gi_trace_rays(scene.ref, n, _ptr(org, F32), _ptr(d, F32), _ptr(out, F32), _ptr(prim, torch.int32),
                                _stream(stream)), "gi_trace_rays")
     return out, prim
 
@@ -566,7 +596,7 @@ class Mlp:
 def mlp_infer(mlp: Mlp, pos4: torch.Tensor, nrm4: torch.Tensor, stream=None) -> torch.Tensor:
     pos4, nrm4 = pos4.contiguous().float(), nrm4.contiguous().float()
     out = torch.empty(pos4.shape[0], 4, dtype=torch.float32, device=pos4.device)
-    check(load().gi_mlp_infer(mlp.ref, pos4.shape[0], _ptr(pos4), _ptr(nrm4), _ptr(out), _stream(stream)),
+    check(load().gi_mlp_infer(mlp.ref, pos4.shape[0], _ptr(pos4, F32), _ptr(nrm4, F32), _ptr(out), _stream(stream)),
           "gi_mlp_infer")
     return out
 
@@ -590,8 +620,8 @@ class MlpBatch:
 
 def mlp_make_batch(scene, gb, probes, M, batch: MlpBatch, seed, frame, stream=None):
     check(load().gi_mlp_make_batch(scene.ref, gb.ref, probes.ref, int(M), batch.n, int(seed),
-                                   int(frame) & 0xFFFFFFFF, _ptr(batch.pos), _ptr(batch.nrm),
-                                   _ptr(batch.target), _ptr(batch.qprobe), _stream(stream)), "gi_mlp_make_batch")
+                                   int(frame) & 0xFFFFFFFF, _ptr(batch.pos, F32), _ptr(batch.nrm, F32),
+                                   _ptr(batch.target, F32), _ptr(batch.qprobe, F32), _stream(stream)), "gi_mlp_make_batch")
 
 
 def train_workspace(n, device="cuda") -> torch.Tensor:
@@ -599,18 +629,18 @@ def train_workspace(n, device="cuda") -> torch.Tensor:
 
 
 def mlp_grad(mlp: Mlp, batch: MlpBatch, grad: torch.Tensor, ws: torch.Tensor, stream=None, qprobe=True):
-    check(load().gi_mlp_grad(mlp.ref, batch.n, _ptr(batch.pos), _ptr(batch.nrm), _ptr(batch.target),
-                             _ptr(batch.qprobe) if qprobe else None, _ptr(grad), _ptr(ws), ws.numel(),
+    check(load().gi_mlp_grad(mlp.ref, batch.n, _ptr(batch.pos, F32), _ptr(batch.nrm, F32), _ptr(batch.target, F32),
+                             _ptr(batch.qprobe, F32) if qprobe else None, _ptr(grad, F32), _ptr(ws), ws.numel(),
                              _stream(stream)), "gi_mlp_grad")
 
 
 def mlp_adam(mlp: Mlp, grad: torch.Tensor, t, lr=1e-2, stream=None):
-    check(load().gi_mlp_adam(mlp.ref, _ptr(grad), int(t), float(lr), _stream(stream)), "gi_mlp_adam")
+    check(load().gi_mlp_adam(mlp.ref, _ptr(grad, F32), int(t), float(lr), _stream(stream)), "gi_mlp_adam")
 
 
 def mlp_train_step(mlp: Mlp, batch: MlpBatch, t, lr, ws: torch.Tensor, stream=None):
-    check(load().gi_mlp_train_step(mlp.ref, batch.n, _ptr(batch.pos), _ptr(batch.nrm), _ptr(batch.target),
-                                   _ptr(batch.qprobe), int(t), float(lr), _ptr(ws), ws.numel(),
+    check(load().gi_mlp_train_step(mlp.ref, batch.n, _ptr(batch.pos, F32), _ptr(batch.nrm, F32), _ptr(batch.target, F32),
+                                   _ptr(batch.qprobe, F32), int(t), float(lr), _ptr(ws), ws.numel(),
                                    _stream(stream)), "gi_mlp_train_step")
 
 
@@ -626,14 +656,14 @@ def resample_initial_mlp(scene, gb, probes, mlp: Mlp, params, out: Reservoirs, r
                          stream=None):
     pp = params_struct(params)
     check(load().gi_resample_initial_mlp(scene.ref, gb.ref, probes.ref, mlp.ref, C.byref(pp), out.ref,
-                                         _ptr(resid), _ptr(ws), ws.numel(), int(seed), int(frame) & 0xFFFFFFFF,
+                                         _ptr(resid, F32), _ptr(ws), ws.numel(), int(seed), int(frame) & 0xFFFFFFFF,
                                          _stream(stream)), "gi_resample_initial_mlp")
 
 
 def shade_mlp(scene, gb, probes, mlp: Mlp, res, resid, params, out_rgba, ws, stream=None):
     pp = params_struct(params)
-    check(load().gi_shade_mlp(scene.ref, gb.ref, probes.ref, mlp.ref, res.ref, _ptr(resid), C.byref(pp),
-                              _ptr(out_rgba), _ptr(ws), ws.numel(), _stream(stream)), "gi_shade_mlp")
+    check(load().gi_shade_mlp(scene.ref, gb.ref, probes.ref, mlp.ref, res.ref, _ptr(resid, F32), C.byref(pp),
+                              _ptr(out_rgba, F32), _ptr(ws), ws.numel(), _stream(stream)), "gi_shade_mlp")
 
 
 # --------------------------------------------------------------------------
@@ -739,7 +769,7 @@ class Renderer:
             if self.train:
                 self.train_mlp(stream)
         else:
-            shade(self.dscene, gb, self.probe, cur, self.resid, pr, self.img, stream)
+            shade(self.dscene, gb, self.probe, cur, self.resid, pr, self.img, stream, seed=self.seed, frame=f)
         self.hist = cur
         self.cam_prev = cam
         self.frame_index = f + 1

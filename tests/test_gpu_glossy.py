@@ -1,0 +1,187 @@
+"""GPU parity of the glossy workload (glossy layer, glossy L_DDGI+ of Eq. 6,
+specular shading recursion of Eq. 7-8) against the FP64 oracle, and the
+Lambertian workloads' independence of it.
+
+Shared inputs as in the Lambertian parity tests: each pass reads the
+oracle's own inputs (G-buffer records with the primitives' glossy layer,
+probe textures, reservoirs).  Tolerances: the Lambertian bar (mean relative
+error <= 1e-4 over unflipped pixels, flips <= 1e-3) for the resampling
+passes and the probe update.  Shading traces the glossy samples of the
+recursion, so an FP32 and an FP64 ray can part at a grazing edge: pixels
+whose error exceeds 1e-3 are counted (<= 1% allowed) and the rest must meet
+the 1e-4 mean.  FP32 GGX forms its denominator from |n x h|^2 (no
+cancellation at the lobe's peak), so the lobe values keep FP32 precision
+down to roughness 0.02.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as o
+from paper_2108_05263_amd import scenegen as sg
+
+from helpers import compare_reservoirs, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gi():
+    from paper_2108_05263_amd import gi as m
+    m.load()
+    assert torch.cuda.is_available()
+    return m
+
+
+@pytest.fixture(scope="module")
+def gtiny():
+    cfg = sg.CONFIGS["glossy_tiny"]
+    sc = sg.make_scene(cfg)
+    grid = sg.make_probe_grid(cfg)
+    irr, dep = o.fill_probes(sc, grid, cfg.probe_update, seed=1)
+    return cfg, sc, grid, irr, dep
+
+
+@pytest.fixture(scope="module")
+def ghd_small():
+    """The glossy 1080p room at 250x141 (ragged tiles), probes filled by the
+    oracle with fewer rays."""
+    cfg = sg.CONFIGS["glossy"]
+    sc = sg.make_scene(cfg)
+    grid = sg.make_probe_grid(cfg)
+    irr, dep = o.fill_probes(sc, grid, sg.ProbeUpdate(rays=32, fill_passes=2, fill_rays=32), seed=1)
+    return cfg, sc, grid, irr, dep
+
+
+def _active(sc, gb):
+    prim = gb[:, 13].astype(np.int64)
+    own = (prim >= 0) & (prim < len(sc.prims)) & (gb[:, 13] != o.MISS)
+    ks = np.where(own, sc.prims[np.where(own, prim, 0), 11], 0.0)
+    return (gb[:, 13] != o.MISS) & ((gb[:, 6:9].max(1) > 0) | (ks > 0))
+
+
+def test_gbuffer_glossy_layer(gi, gtiny):
+    cfg, sc, grid, irr, dep = gtiny
+    W, H = 64, 64
+    cam = sg.make_camera(cfg, 0, W, H)
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    assert ds.glossy
+    g = gi.GBuffer(W, H)
+    gi.trace_gbuffer(ds, cam, g)
+    rec = g.to_records()
+    ref = o.gbuffer(sc, cam)
+    assert np.mean(rec[:, 13] == ref[:, 13]) > 0.999
+    hit = (rec[:, 13] == ref[:, 13]) & (ref[:, 13] != o.MISS)
+    prim = ref[hit, 13].astype(np.int64)
+    own = prim < len(sc.prims)
+    ks = g.albedo.cpu().numpy()[hit, 3]
+    ro = g.emit.cpu().numpy()[hit, 3]
+    assert np.array_equal(ks[own], sc.prims[prim[own], 11]) and np.all(ks[~own] == 0)
+    assert np.array_equal(ro[own], sc.prims[prim[own], 15]) and np.all(ro[~own] == 1)
+    assert np.allclose(np.asarray(g.c.eye), cam.eye)
+
+
+def test_probe_update_glossy(gi, gtiny):
+    cfg, sc, grid, irr, dep = gtiny
+    i2, d2 = o.fill_probes(sc, grid, sg.ProbeUpdate(fill_passes=2, fill_rays=64), seed=1)
+    i2, d2 = i2.astype(np.float32), d2.astype(np.float32)
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    pin, pout = gi.Probes(grid), gi.Probes(grid)
+    pin.load(i2, d2)
+    for hyst in (0.0, 0.97):
+        gi.probe_update(ds, pin, pout, 64, hyst, 50.0, 1, 5)
+        gi_irr, gi_dep = pout.tiles()
+        ri, rd = o.probe_update(sc, grid, i2, d2, 64, hyst, 50.0, 1, 5)
+        ei, ed = rel_err(gi_irr, ri), rel_err(gi_dep, rd)
+        log(f"glossy probe update h={hyst}: irr mean {ei.mean():.2e} max {ei.max():.2e}; dep mean {ed.mean():.2e}")
+        assert ei.mean() < 1e-4 and ed.mean() < 1e-4
+        assert np.mean(ei > 1e-2) < 1e-3 and np.mean(ed > 1e-2) < 1e-3
+
+
+@pytest.mark.parametrize("which", ["gtiny", "ghd_small"])
+def test_glossy_passes_shared_inputs(gi, request, which):
+    cfg, sc, grid, irr, dep = request.getfixturevalue(which)
+    W, H = (64, 64) if which == "gtiny" else (250, 141)
+    frames = 1 if which == "gtiny" else 2
+    seq = o.Sequence(sc, grid, irr, dep, cfg.params, 1)
+    st = []
+    for f in range(frames):
+        cam = sg.make_camera(cfg, f, W, H)
+        _, s = seq.frame(cam, f)
+        s["cam"] = cam
+        st.append(s)
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    probes = gi.Probes(grid)
+    probes.load(irr, dep)
+    pr = cfg.params
+    gb, gbp = gi.GBuffer(W, H), gi.GBuffer(W, H)
+    rin, rin2, rout = gi.Reservoirs(W, H), gi.Reservoirs(W, H), gi.Reservoirs(W, H)
+    resid = torch.empty(W * H, 4, device="cuda")
+    img = torch.empty(W * H, 4, device="cuda")
+    f = frames - 1
+    s = st[f]
+    gb.load_records(s["gbuffer"], scene=sc, eye=s["cam"].eye)
+    active = _active(sc, s["gbuffer"])
+    gi.resample_initial(ds, gb, probes, pr, rout, resid, 1, f)
+    res, _ = compare_reservoirs(rout.to_records(), s["initial"], active, label=f"{which} initial")
+    er = rel_err(resid.cpu().numpy()[:, :3], s["resid"])
+    log(f"{which} initial: {res}; resid mean {er.mean():.2e}")
+    assert er.mean() < 1e-4
+    if "temporal" in s:
+        gbp.load_records(st[f - 1]["gbuffer"], scene=sc, eye=st[f - 1]["cam"].eye)
+        rin.load_records(s["initial"])
+        rin2.load_records(st[f - 1][f"spatial{pr.n_spatial - 1}"])
+        gi.resample_temporal(ds, gb, gbp, st[f - 1]["cam"], rin, rin2, pr, rout, 1, f)
+        res, _ = compare_reservoirs(rout.to_records(), s["temporal"], active, label=f"{which} temporal")
+        log(f"{which} temporal: {res}")
+    src = s["temporal"] if "temporal" in s else s["initial"]
+    for sp in range(pr.n_spatial):
+        rin.load_records(src)
+        gi.resample_spatial(ds, gb, rin, pr, sp, rout, 1, f)
+        res, _ = compare_reservoirs(rout.to_records(), s[f"spatial{sp}"], active, label=f"{which} spatial{sp}")
+        log(f"{which} spatial{sp}: {res}")
+        src = s[f"spatial{sp}"]
+    rin.load_records(src)
+    resid.copy_(torch.from_numpy(np.concatenate([s["resid"], np.zeros((W * H, 1))], 1).astype(np.float32)))
+    gi.shade(ds, gb, probes, rin, resid, pr, img, seed=1, frame=f)
+    e = rel_err(img.cpu().numpy()[:, :3], s["image"], 1e-2).max(1)
+    parted = e > 1e-3
+    log(f"{which} shade: parted {parted.mean():.4f}, mean rel err of the rest {e[~parted].mean():.2e}")
+    assert parted.mean() <= 0.01
+    assert e[~parted].mean() < 1e-4
+
+
+def test_glossy_path_tracer(gi, gtiny):
+    cfg, sc, grid, irr, dep = gtiny
+    W, H = 48, 40
+    cam = sg.make_camera(cfg, 0, W, H)
+    gb_rec = o.gbuffer(sc, cam)
+    ref = o.path_trace(sc, gb_rec, np.arange(W * H), 4, 5, eye=cam.eye)
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    g = gi.GBuffer(W, H)
+    g.load_records(gb_rec, scene=sc, eye=cam.eye)
+    out = gi.path_trace(ds, g, 4, 5, 0).cpu().numpy()[:, :3]
+    e = rel_err(out, ref, 1e-2).max(1)
+    diverged = e > 1e-3
+    log(f"glossy path tracer: diverged {diverged.mean():.4f}, rest {e[~diverged].mean():.2e}")
+    assert diverged.mean() <= 0.03
+    assert e[~diverged].mean() <= 1e-4
+
+
+def test_mlp_entry_points_reject_glossy(gi, gtiny):
+    cfg, sc, grid, irr, dep = gtiny
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    g = gi.GBuffer(16, 16)
+    probes = gi.Probes(grid)
+    probes.load(irr, dep)
+    b = gi.MlpBatch(256)
+    with pytest.raises(gi.GiError):
+        gi.mlp_make_batch(ds, g, probes, 8, b, 1, 0)

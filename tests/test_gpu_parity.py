@@ -450,3 +450,19 @@ def test_subsampled_initial_shared_inputs(gi, tiny, n):
     er = rel_err(resid.cpu().numpy()[:, :3], oresid)
     log(f"subsample {n}: {st}; resid {er.mean():.2e}")
     assert er.mean() < 1e-4
+
+
+def test_binding_refuses_buffers_of_another_dtype(gi, tiny):
+    """The library writes float32 records: a float64 or strided output buffer
+    is refused before any launch instead of being misread."""
+    cfg, sc, grid, irr, dep = tiny
+    W = H = 16
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    probes = gi.Probes(grid)
+    probes.load(irr, dep)
+    g = gi.GBuffer(W, H)
+    out = gi.Reservoirs(W, H)
+    with pytest.raises(gi.GiError):
+        gi.resample_initial(ds, g, probes, cfg.params, out, torch.zeros(W * H, 4, dtype=torch.float64, device="cuda"), 1, 0)
+    with pytest.raises(gi.GiError):
+        gi.resample_initial(ds, g, probes, cfg.params, out, torch.zeros(W * H, 8, device="cuda")[:, ::2], 1, 0)

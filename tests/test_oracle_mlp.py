@@ -23,7 +23,16 @@ import oracle as o
 from oracle import mlp_ref as M
 from paper_2108_05263_amd import scenegen as sg
 
-torch.set_default_dtype(torch.float64)
+
+
+@pytest.fixture(autouse=True)
+def _float64_default():
+    """torch's default dtype is float64 inside this module's tests only (its
+    reference layers are built in FP64); other modules keep float32."""
+    old = torch.get_default_dtype()
+    torch.set_default_dtype(torch.float64)
+    yield
+    torch.set_default_dtype(old)
 
 
 def _batch(n=64, seed=0):
