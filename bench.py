@@ -15,6 +15,7 @@ inference kernel) and the FP64 oracle's rate on a bounded crop of the same
 frame (CPU baseline).
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -278,17 +279,34 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
     if cfg.name == "uhd":
         # the precision sweep: half-precision G-buffer normals and albedo, alone and with FP8 inference
         forms += (("probe, f16 G-buffer", None, "f16"), ("fp8, f16 G-buffer", "fp8", "f16"))
-    for form, mlp, gbf in forms:
+    forms = tuple((name, mlp, gbf, cfg) for name, mlp, gbf in forms)
+    if cfg.glossy_frac > 0.0:
+        # glossy workload: the specular recursion of shading at the workload's threshold,
+        # switched off (c = 0: every glossy sample read from the probes) and deeper (c = 1);
+        # the learned cache serves Lambertian scenes only
+        def with_c(c):
+            return dataclasses.replace(cfg, params=dataclasses.replace(cfg.params, foot_c=c))
+        forms = ((f"probe, recursion c={cfg.params.foot_c:g}", None, "f32", cfg),
+                 ("probe, no recursion (c=0)", None, "f32", with_c(0.0)),
+                 ("probe, recursion c=1", None, "f32", with_c(1.0)))
+    for form, mlp, gbf, fcfg in forms:
         acc = {"mse": [], "relmse": [], "mape": []}
         per_seed, train = [], []
+        # per evaluated frame: sum and sum of squares of the image over seeds, to
+        # split the error into the squared bias of the seed mean and the variance
+        s1 = {f: torch.zeros_like(refs[f]) for f in eval_frames}
+        s2 = {f: torch.zeros_like(refs[f]) for f in eval_frames}
         for seed in range(1, n_seeds + 1):
-            r = gi.Renderer(cfg, seed=seed, mlp=mlp, mlp_mode="always", gb_format=gbf)
+            r = gi.Renderer(fcfg, seed=seed, mlp=mlp, mlp_mode="always", gb_format=gbf)
             r.fill_probes()
             m = {"mse": 0.0, "relmse": 0.0, "mape": 0.0}
             for f in range(frames):
                 r.frame(f)
                 if f in refs:
-                    d = r.img[:, :3] - refs[f]
+                    img = r.img[:, :3]
+                    s1[f] += img
+                    s2[f] += img * img
+                    d = img - refs[f]
                     m["mse"] += float((d * d).mean()) / n_eval
                     m["relmse"] += float((d * d / (refs[f] ** 2 + 1e-2)).mean()) / n_eval
                     m["mape"] += float((d.abs() / (refs[f] + 1e-2)).mean()) / n_eval
@@ -302,6 +320,19 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
             torch.cuda.empty_cache()
         rec = {k: sum(v) / len(v) for k, v in acc.items()}
         rec["mse_per_seed"] = per_seed
+        if n_seeds >= 2:
+            # squared bias of the per-frame seed mean: its squared error minus the
+            # variance it still carries (sample variance / n_seeds) and the
+            # reference's own noise; plus the mean signed error (brightness bias)
+            b2, me = 0.0, 0.0
+            for f in eval_frames:
+                mean = s1[f] / n_seeds
+                var = (s2[f] - n_seeds * mean * mean) / (n_seeds - 1)
+                b2 += float(((mean - refs[f]) ** 2).mean() - var.mean() / n_seeds) / n_eval
+                me += float((mean - refs[f]).mean()) / n_eval
+            rec["bias2"] = b2 - out["ref_noise_mse"]
+            rec["variance"] = rec["mse"] - b2
+            rec["mean_signed_err"] = me
         if train:
             rec["train_at_end"] = train
         out["forms"][form] = rec
@@ -394,8 +425,9 @@ def main():
     achieved = bytes_launch / (avg[dom] * 1e-3) / 1e9
     path_bytes = sum(ALGO_BYTES[k if not k.startswith("spatial") else "spatial"] for k in names) * npx
     line = {
-        "metric": ("resampled pixels/s (1080p, M=32, 2xk=5)" if (W, H) == (1920, 1080) else
-                   f"resampled pixels/s ({W}x{H}, M={cfg.params.M}, {cfg.params.n_spatial}xk={cfg.params.k})"),
+        "metric": ("resampled pixels/s (1080p, M=32, 2xk=5)" if (W, H) == (1920, 1080) and cfg.glossy_frac == 0.0
+                   else f"resampled pixels/s ({W}x{H}{' glossy' if cfg.glossy_frac > 0.0 else ''}, "
+                        f"M={cfg.params.M}, {cfg.params.n_spatial}xk={cfg.params.k})"),
         "value": npx * args.steps / elapsed,
         "unit": "pixels/s",
         "n_gpus": 1,
@@ -408,7 +440,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {W}x{H} room, {cfg.n_spheres}+{cfg.n_boxes} primitives "
-                               f"({cfg.n_emitters} emitters), "
+                               f"({cfg.n_emitters} emitters"
+                               f"{f', {cfg.glossy_frac:.0%} with a GGX layer' if cfg.glossy_frac > 0.0 else ''}), "
                                f"{cfg.probe_dims[0]}x{cfg.probe_dims[1]}x{cfg.probe_dims[2]} probes, "
                                f"M={cfg.params.M}, temporal, {cfg.params.n_spatial}x k={cfg.params.k} "
                                f"r={cfg.params.radius:g}",
@@ -425,7 +458,7 @@ def main():
         # the dominant kernel is bound by vector-ALU issue, not HBM: its measured issue rate
         "alu_issue": alu_issue(f"k_{dom_key}", cfg.name, avg[dom]),
     }
-    if not args.no_mlp:
+    if not args.no_mlp and cfg.glossy_frac == 0.0:
         del r
         torch.cuda.empty_cache()
         forms = {}
