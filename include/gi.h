@@ -138,11 +138,12 @@ typedef struct gi_gbuffer {
  * texels of the mean and mean square hit distance), each with a one-texel
  * gutter that mirrors the interior along the tile edge (corners take the
  * diagonally opposite interior texel).  They are stored as bilinear quads:
- *   irr: per probe (irr_res+1)^2 records of 12 floats; record cy*(irr_res+1)+cx
+ *   irr: (irr_res+1)^2 records of 12 floats per probe, quad-major: record
+ *        q = cy*(irr_res+1)+cx of probe i is record q*P + i (P probes), and
  *        holds the RGB of padded texels (cx,cy), (cx+1,cy), (cx,cy+1),
- *        (cx+1,cy+1) in that order (3888 bytes per probe);
+ *        (cx+1,cy+1) in that order (3888 bytes per probe in all);
  *   dep: per probe (dep_res+1)^2 records of 8 floats, (mean, mean^2) of the
- *        same four padded texels (9248 bytes per probe).
+ *        same four padded texels, probe-major (9248 bytes per probe).
  * irr_res must be 8 and dep_res 16; the volume holds at most 464,000
  * probes (each texture then stays under 4 GiB, so kernels address it with
  * 32-bit byte offsets; larger volumes return GI_ERR_SHAPE).  bias_dist is the view-path bias d,

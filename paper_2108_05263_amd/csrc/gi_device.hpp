@@ -114,7 +114,7 @@ __device__ __forceinline__ V3 sphere_dir(float u0, float u1)
 struct Hit {
     float t;
     uint32_t prim;
-    int axis;        // box / wall face axis; -1 for spheres
+    int axis;        // face axis of a wall hit; a primitive's face comes from hit_normal
 };
 
 // nearest t > 0 of a sphere, in the cancellation-free form of Haines et al.
@@ -136,27 +136,37 @@ __device__ __forceinline__ float isect_sphere(V3 o, V3 d, V3 c, float r)
     return kInf;
 }
 
-// slab test of the box [lo, hi]; on a hit returns t and the face axis
-__device__ __forceinline__ float isect_box(V3 o, V3 inv, V3 lo, V3 hi, int &axis)
+// slab test of the box [lo, hi]: nearest t > 0 on its surface, kInf if none.
+// The face of the hit is not tracked here (box_axis recovers it for the one
+// hit a walk keeps), so a test is two 3-way min/max and a select.
+__device__ __forceinline__ float isect_box(V3 o, V3 inv, V3 lo, V3 hi)
 {
     float ax = (lo.x - o.x) * inv.x, bx = (hi.x - o.x) * inv.x;
     float ay = (lo.y - o.y) * inv.y, by = (hi.y - o.y) * inv.y;
     float az = (lo.z - o.z) * inv.z, bz = (hi.z - o.z) * inv.z;
-    float lx = fminf(ax, bx), hx = fmaxf(ax, bx);
-    float ly = fminf(ay, by), hy = fmaxf(ay, by);
-    float lz = fminf(az, bz), hz = fmaxf(az, bz);
-    int an = 0;
-    float tn = lx;
-    if (ly > tn) { tn = ly; an = 1; }
-    if (lz > tn) { tn = lz; an = 2; }
-    int af = 0;
-    float tf = hx;
-    if (hy < tf) { tf = hy; af = 1; }
-    if (hz < tf) { tf = hz; af = 2; }
-    if (tn > tf) return kInf;
-    if (tn > 0.0f) { axis = an; return tn; }
-    if (tf > 0.0f) { axis = af; return tf; }
-    return kInf;
+    float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz));
+    float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
+    float t = tn > 0.0f ? tn : tf;
+    return (tn <= tf && t > 0.0f) ? t : kInf;
+}
+
+// face axis of a box hit returned by isect_box: the entry face (the first
+// axis, in x, y, z order, whose slab entry equals the entry time), or the
+// exit face when the origin lies inside the box
+__device__ __forceinline__ int box_axis(V3 o, V3 inv, V3 lo, V3 hi)
+{
+    float ax = (lo.x - o.x) * inv.x, bx = (hi.x - o.x) * inv.x;
+    float ay = (lo.y - o.y) * inv.y, by = (hi.y - o.y) * inv.y;
+    float az = (lo.z - o.z) * inv.z, bz = (hi.z - o.z) * inv.z;
+    float lx = fminf(ax, bx), ly = fminf(ay, by), lz = fminf(az, bz);
+    float hx = fmaxf(ax, bx), hy = fmaxf(ay, by), hz = fmaxf(az, bz);
+    int an = ly > lx ? 1 : 0;
+    float tn = fmaxf(lx, ly);
+    if (lz > tn) an = 2;
+    tn = fmaxf(tn, lz);
+    int af = hy < hx ? 1 : 0;
+    if (hz < fminf(hx, hy)) af = 2;
+    return tn > 0.0f ? an : af;
 }
 
 __device__ __forceinline__ float comp(V3 v, int a) { return a == 0 ? v.x : (a == 1 ? v.y : v.z); }
@@ -271,12 +281,11 @@ __device__ __forceinline__ void stage_scene(const gi_scene &sc)
 // keep the lexicographically smallest (t, id): equal distances go to the
 // lower id; a miss (t = inf) never counts, even when the running best is
 // still the initial tmax = inf
-__device__ __forceinline__ void take_hit(Hit &h, float t, uint32_t i, int axis)
+__device__ __forceinline__ void take_hit(Hit &h, float t, uint32_t i)
 {
     if (t < h.t || (t == h.t && t < kInf && i < h.prim)) {
         h.t = t;
         h.prim = i;
-        h.axis = axis;
     }
 }
 
@@ -285,9 +294,8 @@ template <class G>
 __device__ __forceinline__ void test_prim(const G &acc, uint32_t i, V3 o, V3 d, V3 inv, Hit &h)
 {
     PrimGeo g = acc.geo(i);
-    int axis = -1;
-    float t = g.type == 0u ? isect_sphere(o, d, g.c, g.s.x) : isect_box(o, inv, g.c, g.s, axis);
-    take_hit(h, t, i, g.type == 0u ? -1 : axis);
+    float t = g.type == 0u ? isect_sphere(o, d, g.c, g.s.x) : isect_box(o, inv, g.c, g.s);
+    take_hit(h, t, i);
 }
 
 // any surface crossing of a primitive in (0, tmax)?
@@ -295,8 +303,7 @@ template <class G>
 __device__ __forceinline__ bool occludes_prim(const G &acc, uint32_t i, V3 o, V3 d, V3 inv, float tmax)
 {
     PrimGeo g = acc.geo(i);
-    int axis;
-    float t = g.type == 0u ? isect_sphere(o, d, g.c, g.s.x) : isect_box(o, inv, g.c, g.s, axis);
+    float t = g.type == 0u ? isect_sphere(o, d, g.c, g.s.x) : isect_box(o, inv, g.c, g.s);
     return t < tmax;
 }
 
@@ -392,11 +399,16 @@ template <class G>
 __device__ __forceinline__ V3 hit_normal(const gi_scene &sc, const G &acc, V3 o, V3 d, const Hit &h)
 {
     V3 n;
-    if (h.prim >= sc.n_prims || h.axis >= 0) {
-        float s = comp(d, h.axis) > 0.0f ? -1.0f : 1.0f;
-        n = v3(h.axis == 0 ? s : 0.0f, h.axis == 1 ? s : 0.0f, h.axis == 2 ? s : 0.0f);
+    int axis = h.axis;
+    PrimGeo g{};
+    if (h.prim < sc.n_prims) {
+        g = acc.geo(h.prim);
+        if (g.type != 0u) axis = box_axis(o, v3(rcp(d.x), rcp(d.y), rcp(d.z)), g.c, g.s);
+    }
+    if (h.prim >= sc.n_prims || g.type != 0u) {
+        float s = comp(d, axis) > 0.0f ? -1.0f : 1.0f;
+        n = v3(axis == 0 ? s : 0.0f, axis == 1 ? s : 0.0f, axis == 2 ? s : 0.0f);
     } else {
-        PrimGeo g = acc.geo(h.prim);
         V3 p = madd(o, h.t, d);
         float ir = rcp(g.s.x);
         n = ir * (p - g.c);
@@ -478,10 +490,13 @@ __device__ __forceinline__ V3 oct_decode(float u, float w)
 // (cx, cy+1), (cx+1, cy+1) that a bilinear fetch between them needs, so one
 // fetch is a single 48-byte (irradiance RGB) or 32-byte (depth moments)
 // record: 3 or 2 16-byte loads instead of 4 scattered texel loads.
+// Irradiance records are quad-major (record q of every probe, then record
+// q + 1): a query reads the same record q from all 8 probes of its cell, and
+// the x-neighbours' records then share cache lines.  Depth records, whose
+// direction differs per probe, stay probe-major.
 constexpr int kIrrN = 8, kDepN = 16;
 constexpr int kIrrQuads = (kIrrN + 1) * (kIrrN + 1);      // 81 records of 12 floats
 constexpr int kDepQuads = (kDepN + 1) * (kDepN + 1);      // 289 records of 8 floats
-constexpr int kIrrProbeF4 = kIrrQuads * 3;                 // float4 per probe
 constexpr int kDepProbeF4 = kDepQuads * 2;
 
 struct Bilin {
@@ -507,17 +522,6 @@ __device__ __forceinline__ Bilin bilin(V3 dir, int N)
     return b;
 }
 
-__device__ __forceinline__ V3 fetch_irr(const float4 *probe, const Bilin &b)
-{
-    const float4 *r = probe + 3 * b.q;
-    float4 a = r[0], c = r[1], d = r[2];
-    float w00 = (1.0f - b.ax) * (1.0f - b.ay), w10 = b.ax * (1.0f - b.ay);
-    float w01 = (1.0f - b.ax) * b.ay, w11 = b.ax * b.ay;
-    return v3(w00 * a.x + w10 * a.w + w01 * c.z + w11 * d.y,
-              w00 * a.y + w10 * c.x + w01 * c.w + w11 * d.z,
-              w00 * a.z + w10 * c.y + w01 * d.x + w11 * d.w);
-}
-
 __device__ __forceinline__ float2 fetch_dep(const float4 *probe, V3 dir)
 {
     Bilin b = bilin(dir, kDepN);
@@ -529,10 +533,10 @@ __device__ __forceinline__ float2 fetch_dep(const float4 *probe, V3 dir)
                        w00 * a.y + w10 * a.w + w01 * c.y + w11 * c.w);
 }
 
-// Byte sizes of one probe's quad records; a volume of at most kMaxProbes
-// probes keeps both textures under 4 GiB, so the query addresses them with
+// Byte sizes of the quad records; a volume of at most kMaxProbes probes
+// keeps both textures under 4 GiB, so the query addresses them with
 // 32-bit byte offsets from the (uniform) texture base.
-constexpr uint32_t kIrrProbeBytes = kIrrProbeF4 * 16u;    // 3888
+constexpr uint32_t kIrrRecBytes = 48u;
 constexpr uint32_t kDepProbeBytes = kDepProbeF4 * 16u;    // 9248
 constexpr uint32_t kMaxProbes = 464000u;                  // kMaxProbes * kDepProbeBytes < 2^32
 
@@ -576,7 +580,7 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
     const QueryAxis az = query_axis(p.z, pr.lo[2], pr.spacing[2], nz, (uint32_t)(nx * ny));
     const uint32_t base = ax.base + ay.base + az.base;
     const Bilin bn = bilin(n, kIrrN);
-    const uint32_t irr_q = 48u * (uint32_t)bn.q;
+    const uint32_t irr_q = kIrrRecBytes * (uint32_t)bn.q * (uint32_t)(nx * ny * nz);   // slice of record q
     const float w00 = (1.0f - bn.ax) * (1.0f - bn.ay), w10 = bn.ax * (1.0f - bn.ay);
     const float w01 = (1.0f - bn.ax) * bn.ay, w11 = bn.ax * bn.ay;
     float sx = 0.0f, sy = 0.0f, sz = 0.0f, wsum = 0.0f;
@@ -604,7 +608,7 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
             const Bilin bd = bilin(dv, kDepN);
             const float4 *dr = at_bytes(pr.dep, __umul24(pi, kDepProbeBytes) + 32u * (uint32_t)bd.q);
             const float4 da = dr[0], db = dr[1];
-            const float4 *qr = at_bytes(pr.irr, __umul24(pi, kIrrProbeBytes) + irr_q);
+            const float4 *qr = at_bytes(pr.irr, irr_q + __umul24(pi, kIrrRecBytes));
             const float4 e0 = qr[0], e1 = qr[1], e2 = qr[2];
             const float v00 = (1.0f - bd.ax) * (1.0f - bd.ay), v10 = bd.ax * (1.0f - bd.ay);
             const float v01 = (1.0f - bd.ax) * bd.ay, v11 = bd.ax * bd.ay;

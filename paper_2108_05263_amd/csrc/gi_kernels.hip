@@ -297,7 +297,9 @@ __global__ void __launch_bounds__(kProbeBlock)
     }
     __syncthreads();
     // old interior texel (i, j) = first texel of quad record (i+1, j+1)
-    const float4 *iold = reinterpret_cast<const float4 *>(in.irr) + (size_t)pi * kIrrProbeF4;
+    // irradiance records are quad-major: record q of probe pi is record q * nP + pi
+    const size_t nP = (size_t)in.dims[0] * in.dims[1] * in.dims[2];
+    const float4 *iold = reinterpret_cast<const float4 *>(in.irr) + 3 * (size_t)pi;
     const float4 *dold = reinterpret_cast<const float4 *>(in.dep) + (size_t)pi * kDepProbeF4;
     const float hy = pp.hysteresis;
     {   // depth texel t (16x16)
@@ -334,7 +336,7 @@ __global__ void __launch_bounds__(kProbeBlock)
                 den += c;
             }
         }
-        float4 old = iold[3 * ((ty + 1) * 9 + tx + 1)];
+        float4 old = iold[3 * nP * ((ty + 1) * 9 + tx + 1)];
         float id = 1.0f / den;
         V3 nv = den > 0.0f ? id * num : xyz(old);
         s_irr[t][0] = hy * old.x + (1.0f - hy) * nv.x;
@@ -344,7 +346,7 @@ __global__ void __launch_bounds__(kProbeBlock)
     __syncthreads();
     // write quad records: each corner is an interior texel or the interior
     // texel its gutter position mirrors
-    float4 *iout = reinterpret_cast<float4 *>(out.irr) + (size_t)pi * kIrrProbeF4;
+    float4 *iout = reinterpret_cast<float4 *>(out.irr) + 3 * (size_t)pi;
     float4 *dout = reinterpret_cast<float4 *>(out.dep) + (size_t)pi * kDepProbeF4;
     for (uint32_t q = threadIdx.x; q < (uint32_t)kDepQuads; q += kProbeBlock) {
         int cx = (int)(q % 17u), cy = (int)(q / 17u);
@@ -357,9 +359,10 @@ __global__ void __launch_bounds__(kProbeBlock)
         int cx = (int)(q % 9u), cy = (int)(q / 9u);
         int s0 = gutter_source(cx, cy, kIrrN), s1 = gutter_source(cx + 1, cy, kIrrN);
         int s2 = gutter_source(cx, cy + 1, kIrrN), s3 = gutter_source(cx + 1, cy + 1, kIrrN);
-        iout[3 * q] = make_float4(s_irr[s0][0], s_irr[s0][1], s_irr[s0][2], s_irr[s1][0]);
-        iout[3 * q + 1] = make_float4(s_irr[s1][1], s_irr[s1][2], s_irr[s2][0], s_irr[s2][1]);
-        iout[3 * q + 2] = make_float4(s_irr[s2][2], s_irr[s3][0], s_irr[s3][1], s_irr[s3][2]);
+        float4 *rec = iout + 3 * nP * q;
+        rec[0] = make_float4(s_irr[s0][0], s_irr[s0][1], s_irr[s0][2], s_irr[s1][0]);
+        rec[1] = make_float4(s_irr[s1][1], s_irr[s1][2], s_irr[s2][0], s_irr[s2][1]);
+        rec[2] = make_float4(s_irr[s2][2], s_irr[s3][0], s_irr[s3][1], s_irr[s3][2]);
     }
 }
 

@@ -402,12 +402,14 @@ def quads_to_tiles(quads, N, C_):
 
 
 class Probes:
-    """Probe textures in the library's quad-record layout (see gi.h)."""
+    """Probe textures in the library's quad-record layout (see gi.h):
+    irradiance records quad-major (record, probe, 12), depth records
+    probe-major (probe, record, 8)."""
 
     def __init__(self, grid: sg.ProbeGrid, device="cuda"):
         self.grid = grid
         P = grid.count
-        self.irr = torch.zeros(P, (grid.irr_res + 1) ** 2, 12, dtype=torch.float32, device=device)
+        self.irr = torch.zeros((grid.irr_res + 1) ** 2, P, 12, dtype=torch.float32, device=device)
         self.dep = torch.zeros(P, (grid.dep_res + 1) ** 2, 8, dtype=torch.float32, device=device)
         p = GiProbes()
         p.dims = (C.c_uint32 * 3)(*grid.dims)
@@ -426,14 +428,18 @@ class Probes:
         g = self.grid
         qi = tiles_to_quads(np.asarray(irr, np.float32)[..., :3], g.irr_res)
         qd = tiles_to_quads(np.asarray(dep, np.float32)[..., :2], g.dep_res)
-        self.irr.copy_(torch.from_numpy(np.ascontiguousarray(qi)))
+        self.irr.copy_(torch.from_numpy(np.ascontiguousarray(qi.swapaxes(0, 1))))
         self.dep.copy_(torch.from_numpy(np.ascontiguousarray(qd)))
 
     def tiles(self):
         """(irr (P, (N+2)^2, 3), dep (P, (Nd+2)^2, 2)) as gutter-padded tiles."""
         g = self.grid
-        return (quads_to_tiles(self.irr.cpu().numpy(), g.irr_res, 3),
+        return (quads_to_tiles(self.irr_quads(), g.irr_res, 3),
                 quads_to_tiles(self.dep.cpu().numpy(), g.dep_res, 2))
+
+    def irr_quads(self):
+        """Irradiance records probe-major, (P, (N+1)^2, 12), as tiles_to_quads makes them."""
+        return np.ascontiguousarray(self.irr.cpu().numpy().swapaxes(0, 1))
 
 
 def params_struct(p: sg.Params) -> GiParams:

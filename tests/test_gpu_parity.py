@@ -166,7 +166,7 @@ def test_probe_update(gi, tiny):
         gi.probe_update(ds, pin, pout, 64, hyst, 50.0, 1, 5, slider=slider)
         gi_irr, gi_dep = pout.tiles()
         # every quad record agrees with the padded tile it encodes (gutters included)
-        assert np.array_equal(pout.irr.cpu().numpy(), gi.tiles_to_quads(gi_irr, grid.irr_res))
+        assert np.array_equal(pout.irr_quads(), gi.tiles_to_quads(gi_irr, grid.irr_res))
         assert np.array_equal(pout.dep.cpu().numpy(), gi.tiles_to_quads(gi_dep, grid.dep_res))
         ri, rd = o.probe_update(sc, grid, i2, d2, 64, hyst, 50.0, 1, 5, slider=slider)
         ei, ed = rel_err(gi_irr, ri), rel_err(gi_dep, rd)
