@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kTile = 16;
 constexpr int kBlock = 256;
+constexpr uint32_t kSelBytes = 48u;   // k_initial's per-thread selected-candidate slot (3 float4)
 
 // Workgroups are dealt round-robin to the chip's 8 XCDs (each with its own
 // L2).  Workgroup L runs on XCD L % 8; it is given tile (L % 8) * chunk +
@@ -470,6 +471,11 @@ __global__ void __launch_bounds__(kBlock, 4)
     Res r = empty_res(Mt);
     float wsum = 0.0f, p_sel = 0.0f;
     bool have = false;
+    // The selected candidate so far, (y, tag), (n_y, prim), (L, -), waits in
+    // this thread's LDS slot past the staged scene: kept in registers across
+    // the probe query it would push the loop's invariants into scratch.
+    float4 *const sel = reinterpret_cast<float4 *>(reinterpret_cast<char *>(gi_lds) + (LDS ? lds_scene_bytes(sc) : 0u)) +
+                        3u * threadIdx.x;
     // subsampling: a pixel off the pattern draws no candidates, only the residual's
     const bool draws = pp.subsample <= 1u || ((uint64_t)px + py + frame) % pp.subsample == 0u;
     for (uint32_t i = 0; i < (draws ? Mt : 1u); ++i) {
@@ -567,12 +573,18 @@ __global__ void __launch_bounds__(kBlock, 4)
         if (u2 * wsum < wi) {
             have = true;
             p_sel = phat;
-            r.y = y;
-            r.n = ny;
-            r.L = L;
-            r.tag = ((p & 0x7FFFFFu) << 9) | ((i & 31u) << 4) | (frame & 15u);
-            r.prim = prim;
+            sel[0] = make_float4(y.x, y.y, y.z, __uint_as_float(((p & 0x7FFFFFu) << 9) | ((i & 31u) << 4) | (frame & 15u)));
+            sel[1] = make_float4(ny.x, ny.y, ny.z, __uint_as_float(prim));
+            sel[2] = make_float4(L.x, L.y, L.z, 0.0f);
         }
+    }
+    if (have) {
+        const float4 a = sel[0], b = sel[1], c = sel[2];
+        r.y = xyz(a);
+        r.tag = __float_as_uint(a.w);
+        r.n = xyz(b);
+        r.prim = __float_as_uint(b.w);
+        r.L = xyz(c);
     }
     r.wsum = wsum;
     if (!draws) r = empty_res(0);
@@ -1145,13 +1157,23 @@ uint32_t scene_lds(const gi_scene *sc, uint32_t static_lds = 0)
 template <bool WS, bool LIGHT, class... A>
 void launch_initial_l(bool glossy, uint32_t lds, dim3 grid, hipStream_t st, A... a)
 {
+    // past the staged scene: every thread's selected-candidate slot
+    const uint32_t extra = kBlock * kSelBytes;
     if (!WS && glossy) {
-        if (lds) k_initial<true, WS, LIGHT, !WS><<<grid, kBlock, lds, st>>>(a...);
-        else k_initial<false, WS, LIGHT, !WS><<<grid, kBlock, 0, st>>>(a...);
+        if (lds) k_initial<true, WS, LIGHT, !WS><<<grid, kBlock, lds + extra, st>>>(a...);
+        else k_initial<false, WS, LIGHT, !WS><<<grid, kBlock, extra, st>>>(a...);
     } else {
-        if (lds) k_initial<true, WS, LIGHT, false><<<grid, kBlock, lds, st>>>(a...);
-        else k_initial<false, WS, LIGHT, false><<<grid, kBlock, 0, st>>>(a...);
+        if (lds) k_initial<true, WS, LIGHT, false><<<grid, kBlock, lds + extra, st>>>(a...);
+        else k_initial<false, WS, LIGHT, false><<<grid, kBlock, extra, st>>>(a...);
     }
+}
+
+// scene bytes to stage for k_initial: the scene and the selected-candidate
+// slots together within kLdsScene, so that 4 workgroups share a CU
+uint32_t initial_scene_lds(const gi_scene *sc)
+{
+    const uint32_t b = scene_lds(sc);
+    return b && b + kBlock * kSelBytes <= kLdsScene ? b : 0u;
 }
 
 template <bool WS, class... A>
@@ -1262,7 +1284,7 @@ gi_status gi_resample_initial(const gi_scene *scene, const gi_gbuffer *gb, const
     if ((s = check_res(out, gb->width, gb->height)) != GI_OK) return s;
     if ((uint64_t)gb->width * gb->height > (1u << 23)) return GI_ERR_SHAPE;   // 23-bit tag origin
     if (gb->width == 0 || gb->height == 0) return GI_OK;
-    launch_initial<false>(params->M_light > 0, glossy_scene(scene), scene_lds(scene),
+    launch_initial<false>(params->M_light > 0, glossy_scene(scene), initial_scene_lds(scene),
                           tile_grid(gb->width, gb->height), S(stream),
                           *scene, *gb, *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame,
                           CandWs{}, gi_mlp{});
