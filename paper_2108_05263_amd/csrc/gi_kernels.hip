@@ -21,7 +21,7 @@ namespace {
 
 constexpr int kTile = 16;
 constexpr int kBlock = 256;
-constexpr uint32_t kSelBytes = 48u;   // k_initial's per-thread selected-candidate slot (3 float4)
+constexpr uint32_t kSelBytes = 64u;   // k_initial's per-thread slot: selected candidate (3 float4), residual
 
 // Workgroups are dealt round-robin to the chip's 8 XCDs (each with its own
 // L2).  Workgroup L runs on XCD L % 8; it is given tile (L % 8) * chunk +
@@ -454,7 +454,6 @@ __global__ void __launch_bounds__(kBlock, 4)
     const Acc acc(sc);
     const uint32_t p = py * gb.width + px;
     const GB g = load_gb<GLOSSY>(gb, p);
-    V3 rs = v3(0.0f, 0.0f, 0.0f);
     if (!active<GLOSSY>(g)) {
         store_res(out, p, empty_res(0));
         resid[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -471,11 +470,13 @@ __global__ void __launch_bounds__(kBlock, 4)
     Res r = empty_res(Mt);
     float wsum = 0.0f, p_sel = 0.0f;
     bool have = false;
-    // The selected candidate so far, (y, tag), (n_y, prim), (L, -), waits in
-    // this thread's LDS slot past the staged scene: kept in registers across
-    // the probe query it would push the loop's invariants into scratch.
+    // The selected candidate so far, (y, tag), (n_y, prim), (L, -), and
+    // candidate 0's residual wait in this thread's LDS slot past the staged
+    // scene: kept in registers across the probe query they would push the
+    // loop's invariants into scratch.
     float4 *const sel = reinterpret_cast<float4 *>(reinterpret_cast<char *>(gi_lds) + (LDS ? lds_scene_bytes(sc) : 0u)) +
-                        3u * threadIdx.x;
+                        4u * threadIdx.x;
+    sel[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     // subsampling: a pixel off the pattern draws no candidates, only the residual's
     const bool draws = pp.subsample <= 1u || ((uint64_t)px + py + frame) % pp.subsample == 0u;
     for (uint32_t i = 0; i < (draws ? Mt : 1u); ++i) {
@@ -537,7 +538,7 @@ __global__ void __launch_bounds__(kBlock, 4)
                         wi = pA > 0.0f ? phat * rcp(pA) : 0.0f;
                     else
                         wi = phat * rcp(mixb * pA + mixl * light_pdf(sc, prim));
-                    if (i == 0 && G > pp.g_max && pA > 0.0f) rs = ((G - pp.g_max) * rcp(pA)) * f;
+                    if (i == 0 && G > pp.g_max && pA > 0.0f) { const V3 q = ((G - pp.g_max) * rcp(pA)) * f; sel[3] = make_float4(q.x, q.y, q.z, 0.0f); }
                 } else {
                     L = (use_cache && i < pp.M) ? radiance_cached(sc, prim, ws.q[i * npx + p])
                                                 : radiance_toward(sc, pr, prim, y, ny, g.pos);
@@ -549,7 +550,7 @@ __global__ void __launch_bounds__(kBlock, 4)
                         wi = kPi * phat * iG;   // p_hat / p_A with p_A = G / pi
                     else
                         wi = phat * rcp(mixb * kInvPi * G + mixl * light_pdf(sc, prim));
-                    if (i == 0 && G > pp.g_max) rs = (1.0f - pp.g_max * iG) * (g.alb * L);
+                    if (i == 0 && G > pp.g_max) { const V3 q = (1.0f - pp.g_max * iG) * (g.alb * L); sel[3] = make_float4(q.x, q.y, q.z, 0.0f); }
                 }
             }
         } else if ((!LIGHT || i < pp.M) && (!GLOSSY || !is_zero(w))) {
@@ -590,7 +591,7 @@ __global__ void __launch_bounds__(kBlock, 4)
     if (!draws) r = empty_res(0);
     r.W = (have && p_sel > 0.0f) ? wsum * rcp((float)Mt * p_sel) : 0.0f;
     store_res(out, p, r);
-    resid[p] = make_float4(rs.x, rs.y, rs.z, 0.0f);
+    resid[p] = sel[3];
 }
 
 // --------------------------------------------------------------------------
