@@ -343,8 +343,8 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the path shards by screen "
-                                   "bands (see DESIGN.md), which is not built"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; the path would shard by screen "
+                                   "bands across GPUs, which is not implemented"}))
         sys.exit(2)
     import torch
 

@@ -1453,7 +1453,7 @@ void o_brute_force(const o_scene *sc, const o_probes *pr, const double *gb, int3
 }
 
 /* ---------------------------------------------------------------------------
- * Reference path tracer: the converged images the estimators are judged
+ * Reference path tracer: the converged images the estimators are scored
  * against (the paper's evaluation compares with an unbiased path tracer,
  * Sec. 4).  A path starts at the pixel's primary vertex x (G-buffer) with
  * L = L_e(x).  Bounce b = 1, 2, ...: leaving a surface of albedo rho, a

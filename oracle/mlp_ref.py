@@ -4,7 +4,7 @@ A small MLP stands in for the probe query in the target function: the paper
 notes that other caches, such as a neural radiance cache, can be targeted by
 the same resampling and are interchangeable with DDGI (Sec. 2, Sec. 5).  The
 network's shape and training follow the workload definition; everything the
-paper leaves open is a reading (listed in the design doc):
+paper leaves open is a reading, stated here:
 
 * input: the surface point y, normalised to [0,1]^3 by the room bounds, and
   its normal n (6 values); encoding per value v: [v, sin(2^j pi v),
