@@ -458,6 +458,14 @@ def main():
         # the dominant kernel is bound by vector-ALU issue, not HBM: its measured issue rate
         "alu_issue": alu_issue(f"k_{dom_key}", cfg.name, avg[dom]),
     }
+    if dom_key == "initial" and cfg.glossy_frac == 0.0:
+        # probe records the initial pass's queries read: 8 probes x (48 B irradiance + 32 B
+        # depth quad) per query, one query per candidate (with a glossy layer the count
+        # depends on how many candidates land on glossy surfaces, so it is not reported)
+        qb = 8 * (48 + 32) * cfg.params.M * npx
+        line["gather"] = {"kernel": "k_initial", "bytes_per_launch": qb, "unit": "GB/s",
+                          "achieved": qb / (avg[dom] * 1e-3) / 1e9,
+                          "note": "probe-record bytes read by the queries, served by L1, L2 and MALL"}
     if not args.no_mlp and cfg.glossy_frac == 0.0:
         del r
         torch.cuda.empty_cache()
