@@ -637,16 +637,20 @@ __device__ __forceinline__ Res finish(const gi_scene &sc, const G &acc, const Me
     float Z;
     bool keep = true;
     if (pp.unbiased) {
+        // W is zero unless x sees y and p_hat(y) > 0; the domains' rays only
+        // decide Z, so they are cast only then (the result is the same)
         bool sky = is_zero(r.n);
-        bool vis_x = visible(sc, acc, g.pos, g.n, r.y, r.n, sky);
+        bool vis_x = ph > 0.0f && visible(sc, acc, g.pos, g.n, r.y, r.n, sky);
         keep = vis_x;
         uint32_t z = vis_x ? Mdom[0] : 0u;     // the target at x supports y (it was chosen)
+        if (vis_x) {
 #pragma unroll
-        for (int j = 1; j < ND; ++j) {
-            if (Mdom[j] == 0u) continue;
-            GB q = dom(j);
-            if (res_target<GLOSSY>(q, r, pp.g_max) <= 0.0f) continue;
-            if (visible(sc, acc, q.pos, q.n, r.y, r.n, sky)) z += Mdom[j];
+            for (int j = 1; j < ND; ++j) {
+                if (Mdom[j] == 0u) continue;
+                GB q = dom(j);
+                if (res_target<GLOSSY>(q, r, pp.g_max) <= 0.0f) continue;
+                if (visible(sc, acc, q.pos, q.n, r.y, r.n, sky)) z += Mdom[j];
+            }
         }
         Z = (float)z;
     } else {
