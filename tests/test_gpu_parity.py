@@ -154,6 +154,38 @@ def test_probe_query(gi, tiny):
     assert e.mean() < 1e-5 and e.max() < 1e-3
 
 
+def test_probe_layout_odd_volume(gi, tiny):
+    """A 3x5x2 probe volume (no power-of-two extent, P = 30): the query on
+    points inside and around it, and the probe update's read-back, agree with
+    the oracle, which indexes probe-major tiles, through the library's
+    quad-major irradiance records."""
+    cfg, sc, _, _, _ = tiny
+    grid = sg.probe_grid((3, 5, 2), (0.5, 0.25, 1.0), 1.5)   # inside the 8-unit room
+    irr, dep = sg.random_probe_textures(grid, 5)
+    pr = gi.Probes(grid)
+    pr.load(irr, dep)
+    ti, td = pr.tiles()
+    assert np.array_equal(ti, irr.astype(np.float32)[..., :3]) and np.array_equal(td, dep.astype(np.float32)[..., :2])
+    rng = np.random.default_rng(4)
+    p = rng.uniform(-0.5, 8.0, (4000, 3)).astype(np.float32)
+    n = rng.normal(size=(4000, 3))
+    n = (n / np.linalg.norm(n, axis=1, keepdims=True)).astype(np.float32)
+    q = gi.probe_query(pr, torch.from_numpy(p).cuda(), torch.from_numpy(n).cuda()).cpu().numpy()
+    ref = o.probe_query(grid, irr.astype(np.float32), dep.astype(np.float32), p, n)
+    e = rel_err(q, ref)
+    log(f"odd volume query: mean rel err {e.mean():.2e} max {e.max():.2e}")
+    assert e.mean() < 1e-5 and e.max() < 1e-3
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    pout = gi.Probes(grid)
+    gi.probe_update(ds, pr, pout, 64, 0.5, 50.0, 1, 7)
+    gi_irr, gi_dep = pout.tiles()
+    assert np.array_equal(pout.irr_quads(), gi.tiles_to_quads(gi_irr, grid.irr_res))
+    ri, rd = o.probe_update(sc, grid, irr.astype(np.float32), dep.astype(np.float32), 64, 0.5, 50.0, 1, 7)
+    ei, ed = rel_err(gi_irr, ri), rel_err(gi_dep, rd)
+    log(f"odd volume update: irr mean {ei.mean():.2e}; dep mean {ed.mean():.2e}")
+    assert ei.mean() < 1e-4 and ed.mean() < 1e-4
+
+
 def test_probe_update(gi, tiny):
     cfg, sc, grid, irr, dep = tiny
     # start from the third fill pass so the recursion's Q_prev is non-trivial
