@@ -364,9 +364,11 @@ __device__ __forceinline__ bool cast(const gi_scene &sc, const G &acc, V3 o, V3 
     const float dy = d.y == 0.0f ? kInf : cys * fabsf(inv.y);
     const float dz = d.z == 0.0f ? kInf : czs * fabsf(inv.z);
     const int max_steps = rx + ry + rz + 3;
+    // cell index, advanced by the step of the axis crossed
+    int cell = ix + rx * (iy + ry * iz);
+    const int cx = sx, cy = sy * rx, cz = sz * rx * ry;
     for (int step = 0; step < max_steps; ++step) {
-        uint32_t cell = (uint32_t)(ix + rx * (iy + ry * iz));
-        uint32_t b = acc.cell(cell), e = acc.cell(cell + 1);
+        uint32_t b = acc.cell((uint32_t)cell), e = acc.cell((uint32_t)cell + 1u);
         for (uint32_t j = b; j < e; ++j) {
             uint32_t i = acc.item(j);
             if (ANY) {
@@ -377,19 +379,17 @@ __device__ __forceinline__ bool cast(const gi_scene &sc, const G &acc, V3 o, V3 
         }
         float texit = fminf(nx, fminf(ny, nz));
         if (texit >= fminf(t1, h.t)) break;
-        if (nx <= ny && nx <= nz) {
-            ix += sx;
-            nx += dx;
-            if (ix < 0 || ix >= rx) break;
-        } else if (ny <= nz) {
-            iy += sy;
-            ny += dy;
-            if (iy < 0 || iy >= ry) break;
-        } else {
-            iz += sz;
-            nz += dz;
-            if (iz < 0 || iz >= rz) break;
-        }
+        // the axis whose face is crossed first (x, then y, on ties), without
+        // branches: lanes stepping along different axes stay on one path
+        const bool ax = nx <= ny && nx <= nz, ay = !ax && ny <= nz, az = !ax && !ay;
+        ix += ax ? sx : 0;
+        iy += ay ? sy : 0;
+        iz += az ? sz : 0;
+        nx += ax ? dx : 0.0f;
+        ny += ay ? dy : 0.0f;
+        nz += az ? dz : 0.0f;
+        cell += ax ? cx : (ay ? cy : cz);
+        if ((unsigned)ix >= (unsigned)rx || (unsigned)iy >= (unsigned)ry || (unsigned)iz >= (unsigned)rz) break;
     }
     return h.prim != GI_MISS;
 }
