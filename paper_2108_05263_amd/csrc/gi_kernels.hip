@@ -676,8 +676,10 @@ __device__ __forceinline__ int reproject(const gi_camera &c, V3 x)
     return (int)fy * (int)c.width + (int)fx;
 }
 
+// 8 and 5 waves per SIMD for the reuse passes: their latency-bound gathers
+// and walks gain more from occupancy than they lose to a few spilled values
 template <bool LDS, bool GLOSSY>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, 8)
     k_temporal(gi_scene sc, gi_gbuffer gb, gi_gbuffer gbp, gi_camera cam_prev, gi_reservoirs cur,
                gi_reservoirs hist, gi_params pp, gi_reservoirs out, uint64_t seed, uint32_t frame)
 {
@@ -715,7 +717,7 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 template <bool LDS, bool GLOSSY>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, 5)
     k_spatial(gi_scene sc, gi_gbuffer gb, gi_reservoirs in, gi_params pp, uint32_t pass, gi_reservoirs out,
               uint64_t seed, uint32_t frame)
 {
