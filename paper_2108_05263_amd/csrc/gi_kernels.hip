@@ -676,7 +676,8 @@ __device__ __forceinline__ int reproject(const gi_camera &c, V3 x)
     return (int)fy * (int)c.width + (int)fx;
 }
 
-// 8 and 5 waves per SIMD for the reuse passes: their latency-bound gathers
+// 8 and 5 waves per SIMD for the reuse passes (4 for the glossy spatial
+// pass, whose extra state would spill more): their latency-bound gathers
 // and walks gain more from occupancy than they lose to a few spilled values
 template <bool LDS, bool GLOSSY>
 __global__ void __launch_bounds__(kBlock, 8)
@@ -717,7 +718,7 @@ __global__ void __launch_bounds__(kBlock, 8)
 }
 
 template <bool LDS, bool GLOSSY>
-__global__ void __launch_bounds__(kBlock, 5)
+__global__ void __launch_bounds__(kBlock, GLOSSY ? 4 : 5)
     k_spatial(gi_scene sc, gi_gbuffer gb, gi_reservoirs in, gi_params pp, uint32_t pass, gi_reservoirs out,
               uint64_t seed, uint32_t frame)
 {
