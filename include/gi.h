@@ -16,6 +16,10 @@
  *    Every call is asynchronous on that stream.
  *  - Arguments are validated on the host before anything is launched; a
  *    failed validation returns an error status and launches nothing.
+ *  - An empty image (width or height 0) or an empty batch (n = 0) passes the
+ *    same checks and then returns GI_OK without launching anything (except
+ *    gi_mlp_grad / gi_mlp_train_step, which still write the zero gradient of
+ *    an empty batch).
  *    GI_ERR_LAUNCH reports a failed launch; device faults surface at the
  *    caller's next synchronisation.
  *  - Pixel p = j*width + i, row 0 at the top.  Image planes are SoA arrays of

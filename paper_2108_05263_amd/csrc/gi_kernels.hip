@@ -1239,9 +1239,9 @@ gi_status gi_trace_gbuffer(const gi_scene *scene, const gi_camera *cam, gi_gbuff
     gi_status s;
     if (!cam || !out) return GI_ERR_NULL;
     if ((s = check_scene(scene)) != GI_OK) return s;
-    if (cam->width == 0 || cam->height == 0) return GI_ERR_SHAPE;
     if ((s = check_gb(out, cam->width, cam->height)) != GI_OK) return s;
     if (out->format == GI_GB_F16 && scene->n_prims + 6u >= 0xFFFFu) return GI_ERR_SHAPE;
+    if (cam->width == 0 || cam->height == 0) return GI_OK;
     k_gbuffer<<<tile_grid(cam->width, cam->height), kBlock, 0, S(stream)>>>(*scene, *cam, *out);
     return launched();
 }

@@ -151,3 +151,45 @@ def test_quad_layout_round_trip(gi):
         # record (cx, cy) corner 3 is padded texel (cx+1, cy+1)
         T = t.reshape(5, N + 2, N + 2, C_)
         assert np.array_equal(q.reshape(5, N + 1, N + 1, 4, C_)[:, 2, 5, 3], T[:, 3, 6])
+
+
+def test_empty_image_and_batch_are_no_ops(gi):
+    """Width 0 (or n = 0) with otherwise valid arguments returns GI_OK after the
+    checks and launches nothing (no device is touched: this runs without one)."""
+    lib = gi.load()
+    s = gi.GiScene()
+    cam = gi.GiCamera()
+    cam.width, cam.height = 0, 4
+    def gbuf(base):
+        g = gi.GiGBuffer()
+        g.width, g.height = 0, 4
+        g.pos_depth, g.nrm_prim, g.albedo, g.emit = base, base + 16, base + 32, base + 48
+        return g
+    def res(base):
+        r = gi.GiReservoirs()
+        r.width, r.height = 0, 4
+        r.y_W, r.n_wsum, r.L_M, r.tag_prim = base, base + 16, base + 32, base + 48
+        return r
+    g, gp = gbuf(1 << 12), gbuf(2 << 12)
+    r0, r1, r2 = res(3 << 12), res(4 << 12), res(5 << 12)
+    pr = gi.GiProbes()
+    pr.dims = (C.c_uint32 * 3)(2, 2, 2)
+    pr.irr_res, pr.dep_res = 8, 16
+    pr.spacing = gi.F3(1.0, 1.0, 1.0)
+    pr.irr, pr.dep = 6 << 12, 7 << 12
+    pp = gi.GiParams()
+    pp.M, pp.k, pp.radius, pp.g_max, pp.m_cap, pp.depth_rel, pp.subsample = 8, 2, 4.0, 1.0, 20.0, 0.1, 1
+    buf = C.c_void_p(8 << 12)
+    ok = 0
+    assert lib.gi_trace_gbuffer(C.byref(s), C.byref(cam), C.byref(g), None) == ok
+    assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r0),
+                                   buf, 1, 0, None) == ok
+    assert lib.gi_resample_temporal(C.byref(s), C.byref(g), C.byref(gp), C.byref(cam), C.byref(r0),
+                                    C.byref(r1), C.byref(pp), C.byref(r2), 1, 0, None) == ok
+    assert lib.gi_resample_spatial(C.byref(s), C.byref(g), C.byref(r0), C.byref(pp), 0, C.byref(r1),
+                                   1, 0, None) == ok
+    assert lib.gi_shade(C.byref(s), C.byref(g), C.byref(pr), C.byref(r0), buf, C.byref(pp),
+                        C.c_void_p(9 << 12), 1, 0, None) == ok
+    assert lib.gi_probe_query(C.byref(pr), 0, buf, buf, C.c_void_p(9 << 12), None) == ok
+    assert lib.gi_philox(1, 0, buf, C.c_void_p(9 << 12), None) == ok
+    assert lib.gi_trace_rays(C.byref(s), 0, buf, buf, C.c_void_p(9 << 12), C.c_void_p(10 << 12), None) == ok
