@@ -193,3 +193,18 @@ def test_empty_image_and_batch_are_no_ops(gi):
     assert lib.gi_probe_query(C.byref(pr), 0, buf, buf, C.c_void_p(9 << 12), None) == ok
     assert lib.gi_philox(1, 0, buf, C.c_void_p(9 << 12), None) == ok
     assert lib.gi_trace_rays(C.byref(s), 0, buf, buf, C.c_void_p(9 << 12), C.c_void_p(10 << 12), None) == ok
+
+
+def test_probe_volume_limit(gi):
+    """464,000 probes are accepted (the depth records stay under 4 GiB); one
+    more is refused before anything runs."""
+    lib = gi.load()
+    pr = gi.GiProbes()
+    pr.irr_res, pr.dep_res = 8, 16
+    pr.spacing = gi.F3(1.0, 1.0, 1.0)
+    pr.irr, pr.dep = 1 << 12, 2 << 12
+    buf = C.c_void_p(3 << 12)
+    pr.dims = (C.c_uint32 * 3)(80, 58, 100)
+    assert lib.gi_probe_query(C.byref(pr), 0, buf, buf, buf, None) == 0
+    pr.dims = (C.c_uint32 * 3)(3, 154667, 1)          # 464,001 probes
+    assert lib.gi_probe_query(C.byref(pr), 0, buf, buf, buf, None) == 2

@@ -149,3 +149,28 @@ def test_probe_update_uhd_sampled(gi):
             f"dep mean {ed.mean():.2e} max {ed.max():.2e}")
         assert ei.mean() < 1e-4 and ed.mean() < 1e-4
         assert np.mean(ei > 1e-2) < 1e-3 and np.mean(ed > 1e-2) < 1e-3
+
+
+def test_probe_query_at_the_volume_limit(gi):
+    """The largest probe volume the library accepts, 464,000 probes
+    (80 x 58 x 100): its depth records end 3.9 MB short of 4 GiB, the reach
+    of the query's 32-bit byte offsets.  Queries in the first and the last
+    cells, and anywhere in between, agree with the oracle."""
+    grid = sg.probe_grid((80, 58, 100), (0.0, 0.0, 0.0), 1.0)
+    assert grid.count == 464000
+    irr, dep = sg.random_probe_textures(grid, 9)
+    pr = gi.Probes(grid)
+    pr.load(irr, dep)
+    ext = np.array([80.0, 58.0, 100.0])
+    rng = np.random.default_rng(10)
+    p = np.concatenate([rng.uniform(0.5, 1.5, (100, 3)), ext - rng.uniform(0.5, 1.5, (100, 3)),
+                        rng.uniform(0.0, 1.0, (200, 3)) * ext]).astype(np.float32)
+    n = rng.normal(size=(400, 3))
+    n = (n / np.linalg.norm(n, axis=1, keepdims=True)).astype(np.float32)
+    q = gi.probe_query(pr, torch.from_numpy(p).cuda(), torch.from_numpy(n).cuda()).cpu().numpy()
+    del pr
+    torch.cuda.empty_cache()
+    ref = o.probe_query(grid, irr, dep, p, n)
+    e = rel_err(q, ref)
+    log(f"464,000 probes: mean rel err {e.mean():.2e} max {e.max():.2e} (last cell {e[100:200].max():.2e})")
+    assert e.mean() < 1e-5 and e.max() < 1e-3
