@@ -252,7 +252,8 @@ gi_status gi_probe_query(const gi_probes *probes, uint32_t n, const float *p, co
  * from candidate 0.  resid (float4 plane, rgb used)
  * receives the residual transport rho_x L(y_0) max(0, 1 - g_max/G_0) of
  * candidate 0 (Eq. 9).  Pixels that miss or have zero albedo get an empty
- * reservoir with M = 0. */
+ * reservoir with M = 0.  Images of more than 2^23 pixels return GI_ERR_SHAPE
+ * (a tag holds a 23-bit origin pixel). */
 gi_status gi_resample_initial(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes,
                               const gi_params *params, gi_reservoirs *out, float *resid,
                               uint64_t seed, uint32_t frame, void *stream);
@@ -431,7 +432,8 @@ uint64_t gi_initial_mlp_workspace_bytes(uint32_t width, uint32_t height, uint32_
  * rules the cache out, the same candidates take the probe query and the
  * result is bit-identical to gi_resample_initial.
  * Glossy scenes (GI_OPT_GLOSSY) return GI_ERR_PARAM: the cache serves Lambertian
- * scenes. */
+ * scenes.  Images of more than 2^23 pixels, or W*H*M >= 2^31 candidates,
+ * return GI_ERR_SHAPE. */
 gi_status gi_resample_initial_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes *probes,
                                   const gi_mlp *mlp, const gi_params *params, gi_reservoirs *out,
                                   float *resid, void *workspace, uint64_t workspace_bytes, uint64_t seed,

@@ -1420,6 +1420,7 @@ gi_status gi_resample_initial_mlp(const gi_scene *scene, const gi_gbuffer *gb, c
     if ((s = check_mlp(mlp)) != GI_OK) return s;
     if ((s = check_params(params)) != GI_OK) return s;
     if ((s = check_res(out, W, H)) != GI_OK) return s;
+    if ((uint64_t)W * H > (1u << 23)) return GI_ERR_SHAPE;   // 23-bit tag origin
     const uint64_t ncand = (uint64_t)W * H * params->M;
     if (ncand >= (1ull << 31)) return GI_ERR_SHAPE;
     if (workspace_bytes < gi_initial_mlp_workspace_bytes(W, H, params->M)) return GI_ERR_SHAPE;

@@ -208,3 +208,34 @@ def test_probe_volume_limit(gi):
     assert lib.gi_probe_query(C.byref(pr), 0, buf, buf, buf, None) == 0
     pr.dims = (C.c_uint32 * 3)(3, 154667, 1)          # 464,001 probes
     assert lib.gi_probe_query(C.byref(pr), 0, buf, buf, buf, None) == 2
+
+
+def test_image_size_limit_of_the_initial_pass(gi):
+    """Both forms of the initial pass refuse images of more than 2^23 pixels
+    (the reservoir tag holds a 23-bit origin pixel) before anything runs."""
+    lib = gi.load()
+    s = gi.GiScene()
+    W, H = 4097, 2048                               # 2^23 + 2048 pixels
+    g = gi.GiGBuffer()
+    g.width, g.height = W, H
+    g.pos_depth, g.nrm_prim, g.albedo, g.emit = 1 << 12, 2 << 12, 3 << 12, 4 << 12
+    r = gi.GiReservoirs()
+    r.width, r.height = W, H
+    r.y_W, r.n_wsum, r.L_M, r.tag_prim = 5 << 12, 6 << 12, 7 << 12, 8 << 12
+    pr = gi.GiProbes()
+    pr.dims = (C.c_uint32 * 3)(2, 2, 2)
+    pr.irr_res, pr.dep_res = 8, 16
+    pr.spacing = gi.F3(1.0, 1.0, 1.0)
+    pr.irr, pr.dep = 9 << 12, 10 << 12
+    pp = gi.GiParams()
+    pp.M, pp.k, pp.radius, pp.g_max, pp.m_cap, pp.depth_rel, pp.subsample = 1, 2, 4.0, 1.0, 20.0, 0.1, 1
+    resid = C.c_void_p(11 << 12)
+    assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r),
+                                   resid, 1, 0, None) == 2
+    m = gi.GiMlp()
+    m.params, m.adam_m, m.adam_v, m.weights, m.scales, m.state = [(12 + i) << 12 for i in range(6)]
+    m.pos_lo, m.pos_hi = gi.F3(0.0, 0.0, 0.0), gi.F3(1.0, 1.0, 1.0)
+    m.max_rel_err, m.ema_decay = 0.5, 0.0
+    ws = C.c_void_p(20 << 12)
+    assert lib.gi_resample_initial_mlp(C.byref(s), C.byref(g), C.byref(pr), C.byref(m), C.byref(pp),
+                                       C.byref(r), resid, ws, 1 << 40, 1, 0, None) == 2
