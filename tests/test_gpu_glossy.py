@@ -185,3 +185,48 @@ def test_mlp_entry_points_reject_glossy(gi, gtiny):
     b = gi.MlpBatch(256)
     with pytest.raises(gi.GiError):
         gi.mlp_make_batch(ds, g, probes, 8, b, 1, 0)
+
+
+def test_glossy_full_size_sampled(gi):
+    """The 1920x1080 glossy workload in the launch configuration the benchmark
+    times: the G-buffer, then the initial pass and the shading with its
+    specular recursion on the oracle's records, checked on 400 sampled pixels
+    (the probe volume is an input)."""
+    cfg = sg.CONFIGS["glossy"]
+    sc = sg.make_scene(cfg)
+    grid = sg.make_probe_grid(cfg)
+    irr, dep = sg.random_probe_textures(grid, 13)
+    W, H = cfg.width, cfg.height
+    n = W * H
+    pr = cfg.params
+    cam = sg.make_camera(cfg, 0)
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    probes = gi.Probes(grid)
+    probes.load(irr, dep)
+    gb = gi.GBuffer(W, H)
+    gi.trace_gbuffer(ds, cam, gb)
+    S = np.sort(np.random.default_rng(6).choice(n, 400, replace=False))
+    ogb = o.gbuffer(sc, cam, pixels=S, out=np.zeros((n, 14)))
+    g = gb.to_records()[S]
+    assert np.mean(g[:, 13] == ogb[S, 13]) > 0.995
+    gb.load_records(ogb[S], S, scene=sc, eye=cam.eye)
+    rin = gi.Reservoirs(W, H)
+    resid = torch.zeros(n, 4, device="cuda")
+    img = torch.zeros(n, 4, device="cuda")
+    gi.resample_initial(ds, gb, probes, pr, rin, resid, 1, 0)
+    ores, oresid = o.resample_initial(sc, W, H, ogb, grid, irr, dep, pr, 1, 0, pixels=S, eye=cam.eye)
+    active = _active(sc, ogb[S])
+    res, _ = compare_reservoirs(rin.to_records()[S], ores[S], active, tol_flip=5e-3, label="glossy 1080p initial")
+    er = rel_err(resid.cpu().numpy()[S, :3], oresid[S])
+    log(f"glossy 1080p initial (sampled): {res}; resid mean {er.mean():.2e}")
+    assert er.mean() < 1e-4
+    rin.load_records(ores[S], S)
+    resid[torch.as_tensor(S, device="cuda")] = torch.from_numpy(
+        np.concatenate([oresid[S], np.zeros((len(S), 1))], 1).astype(np.float32)).cuda()
+    gi.shade(ds, gb, probes, rin, resid, pr, img, seed=1, frame=0)
+    oimg = o.shade(sc, W, H, ogb, grid, irr, dep, ores, oresid, pr, pixels=S, seed=1, frame=0, eye=cam.eye)
+    e = rel_err(img.cpu().numpy()[S, :3], oimg[S], 1e-2).max(1)
+    parted = e > 1e-3
+    log(f"glossy 1080p shade (sampled): parted {parted.mean():.4f}, mean rel err of the rest {e[~parted].mean():.2e}")
+    assert parted.mean() <= 0.01
+    assert e[~parted].mean() < 1e-4
