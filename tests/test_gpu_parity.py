@@ -353,9 +353,12 @@ def test_furnace_full_hd(gi):
     assert np.array_equal(img[~on], np.broadcast_to(L.astype(np.float64), img[~on].shape))
 
 
-def test_initial_full_hd_sampled(gi):
+@pytest.mark.parametrize("variant", ["plain", "emitters", "subsample"])
+def test_initial_full_hd_sampled(gi, variant):
     """The 1920x1080 workload's G-buffer and initial pass in the launch
-    configuration the benchmark times, checked on 1500 sampled pixels."""
+    configuration the benchmark times, checked on 1500 sampled pixels; also
+    with emitter-sampled candidates (M = 28 + 4) and with candidate
+    subsampling (n = 2), the options of Sec. 3.1 step 1 and Sec. 6."""
     cfg = sg.CONFIGS["hd"]
     sc = sg.make_scene(cfg)
     grid = sg.make_probe_grid(cfg)
@@ -375,13 +378,17 @@ def test_initial_full_hd_sampled(gi):
     # initial reservoirs of the device run are gone (buffers rotate); rerun it
     rr = gi.Reservoirs(W, H)
     resid = torch.zeros(W * H, 4, device="cuda")
-    gi.resample_initial(r.dscene, r.gb[0], r.probe, cfg.params, rr, resid, 1, 0)
-    ores, oresid = o.resample_initial(sc, W, H, ogb, grid, irr, dep, cfg.params, 1, 0, pixels=pix)
+    pr = {"plain": cfg.params, "emitters": dataclasses.replace(cfg.params, M=28, M_light=4),
+          "subsample": dataclasses.replace(cfg.params, subsample=2)}[variant]
+    gi.resample_initial(r.dscene, r.gb[0], r.probe, pr, rr, resid, 1, 0)
+    ores, oresid = o.resample_initial(sc, W, H, ogb, grid, irr, dep, pr, 1, 0, pixels=pix)
     g = rr.to_records()[pix]
     ref = ores[pix]
     active = (ogb[pix, 13] != o.MISS) & (ogb[pix, 6:9].max(1) > 0) & (gb_g[pix, 13] == ogb[pix, 13])
-    res, _ = compare_reservoirs(g, ref, active, tol_flip=5e-3, label="1080p initial sampled")
-    log(f"1080p initial (sampled): {res}")
+    res, _ = compare_reservoirs(g, ref, active, tol_flip=5e-3, label=f"1080p initial sampled ({variant})")
+    er = rel_err(resid.cpu().numpy()[pix, :3], oresid[pix])
+    log(f"1080p initial (sampled, {variant}): {res}; resid mean {er.mean():.2e}")
+    assert er.mean() < 1e-4
 
 
 # --------------------------------------------------------------------------
