@@ -128,7 +128,8 @@ def test_passes_full_size_sampled(gi, name):
 def test_probe_update_uhd_sampled(gi):
     """The 4K probe volume (64x16x64 probes, 256 rays, 1024 primitives on the
     grid): a fill pass from zero textures, then a per-frame update at
-    hysteresis 0.97 from random textures, checked on 64 sampled probes."""
+    hysteresis 0.97 from random textures, and the same update with the
+    distance heuristic of Sec. 3.2 (slider 0.8), checked on 64 sampled probes."""
     cfg = sg.CONFIGS["uhd"]
     sc = sg.make_scene(cfg)
     grid = sg.make_probe_grid(cfg)
@@ -138,12 +139,15 @@ def test_probe_update_uhd_sampled(gi):
     sel = np.sort(np.random.default_rng(6).choice(grid.count, 64, replace=False))
     z_irr, z_dep = sg.empty_probe_textures(grid)
     r_irr, r_dep = sg.random_probe_textures(grid, 7)
-    for label, (irr, dep), hyst, frame in (("fill from zero", (z_irr, z_dep), 0.0, gi.FILL_FRAME_BASE),
-                                           ("update h=0.97", (r_irr, r_dep), u.hysteresis, 3)):
+    for label, (irr, dep), hyst, frame, slider in (
+            ("fill from zero", (z_irr, z_dep), 0.0, gi.FILL_FRAME_BASE, 0.0),
+            ("update h=0.97", (r_irr, r_dep), u.hysteresis, 3, 0.0),
+            ("update h=0.97, distance slider 0.8", (r_irr, r_dep), u.hysteresis, 4, 0.8)):
         pin.load(irr, dep)
-        gi.probe_update(ds, pin, pout, u.rays, hyst, u.sharpness, 1, frame)
+        gi.probe_update(ds, pin, pout, u.rays, hyst, u.sharpness, 1, frame, slider=slider)
         gi_irr, gi_dep = pout.tiles()
-        oi, od = o.probe_update(sc, grid, irr[..., :3], dep, u.rays, hyst, u.sharpness, 1, frame, probes=sel)
+        oi, od = o.probe_update(sc, grid, irr[..., :3], dep, u.rays, hyst, u.sharpness, 1, frame, probes=sel,
+                                slider=slider)
         ei, ed = rel_err(gi_irr[sel], oi[sel]), rel_err(gi_dep[sel], od[sel])
         log(f"uhd probe update ({label}): irr mean {ei.mean():.2e} max {ei.max():.2e}; "
             f"dep mean {ed.mean():.2e} max {ed.max():.2e}")
