@@ -353,6 +353,29 @@ def test_furnace_full_hd(gi):
     assert np.array_equal(img[~on], np.broadcast_to(L.astype(np.float64), img[~on].shape))
 
 
+@pytest.mark.parametrize("k", [0, 8])
+def test_spatial_neighbour_count_extremes(gi, tiny, k):
+    """Spatial reuse with no neighbour (k = 0: the pixel's own reservoir,
+    normalised again) and with the most the library takes (k = GI_MAX_K = 8),
+    both passes, on shared inputs."""
+    cfg, sc, grid, irr, dep = tiny
+    W, H = 64, 64
+    pr = dataclasses.replace(cfg.params, k=k)
+    ogb = o.gbuffer(sc, sg.make_camera(cfg, 0, W, H))
+    ores, _ = o.resample_initial(sc, W, H, ogb, grid, irr, dep, pr, 1, 0)
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    gb = gi.GBuffer(W, H)
+    gb.load_records(ogb)
+    rin, rout = gi.Reservoirs(W, H), gi.Reservoirs(W, H)
+    rin.load_records(ores)
+    active = (ogb[:, 13] != o.MISS) & (ogb[:, 6:9].max(1) > 0)
+    for sp in range(2):
+        gi.resample_spatial(ds, gb, rin, pr, sp, rout, 1, 0)
+        osp = o.resample_spatial(sc, W, H, ogb, ores, pr, sp, 1, 0)
+        res, _ = compare_reservoirs(rout.to_records(), osp, active, label=f"k={k} spatial{sp}")
+        log(f"k={k} spatial{sp}: {res}")
+
+
 @pytest.mark.parametrize("variant", ["plain", "emitters", "subsample"])
 def test_initial_full_hd_sampled(gi, variant):
     """The 1920x1080 workload's G-buffer and initial pass in the launch
