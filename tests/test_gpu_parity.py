@@ -353,6 +353,32 @@ def test_furnace_full_hd(gi):
     assert np.array_equal(img[~on], np.broadcast_to(L.astype(np.float64), img[~on].shape))
 
 
+@pytest.mark.parametrize("M", [1, 32])
+def test_initial_candidate_count_extremes(gi, tiny, M):
+    """The initial pass with a single candidate (M = 1: the selected sample is
+    the candidate, W = 1/p) and with the most the library takes (M =
+    GI_MAX_M = 32), on shared inputs."""
+    cfg, sc, grid, irr, dep = tiny
+    W, H = 64, 64
+    pr = dataclasses.replace(cfg.params, M=M)
+    ogb = o.gbuffer(sc, sg.make_camera(cfg, 0, W, H))
+    ores, oresid = o.resample_initial(sc, W, H, ogb, grid, irr, dep, pr, 1, 0)
+    ds = gi.DeviceScene(sc, cfg.grid_res)
+    probes = gi.Probes(grid)
+    probes.load(irr, dep)
+    gb = gi.GBuffer(W, H)
+    gb.load_records(ogb)
+    out = gi.Reservoirs(W, H)
+    resid = torch.zeros(W * H, 4, device="cuda")
+    gi.resample_initial(ds, gb, probes, pr, out, resid, 1, 0)
+    active = (ogb[:, 13] != o.MISS) & (ogb[:, 6:9].max(1) > 0)
+    res, _ = compare_reservoirs(out.to_records(), ores, active, label=f"M={M} initial")
+    er = rel_err(resid.cpu().numpy()[:, :3], oresid)
+    log(f"M={M} initial: {res}; resid mean {er.mean():.2e}")
+    assert er.mean() < 1e-4
+    assert np.all(out.to_records()[active, 11] == M)
+
+
 @pytest.mark.parametrize("k", [0, 8])
 def test_spatial_neighbour_count_extremes(gi, tiny, k):
     """Spatial reuse with no neighbour (k = 0: the pixel's own reservoir,
