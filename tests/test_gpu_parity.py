@@ -223,11 +223,9 @@ def _pass_inputs(sc, grid, irr, dep, cfg, W, H, frames=2):
     return out
 
 
-@pytest.mark.parametrize("which", ["tiny", "hd_small"])
-def test_passes_shared_inputs(gi, request, which):
-    cfg, sc, grid, irr, dep = request.getfixturevalue(which)
-    W, H = (64, 64) if which == "tiny" else (250, 141)
-    frames = 1 if which == "tiny" else 2
+def _check_chain(gi, cfg, sc, grid, irr, dep, W, H, frames, which):
+    """Each pass of the last of `frames` oracle frames, run on the GPU on the
+    oracle's own inputs (G-buffer, reservoirs, residual) and compared."""
     st = _pass_inputs(sc, grid, irr, dep, cfg, W, H, frames)
     ds = gi.DeviceScene(sc, cfg.grid_res)
     probes = gi.Probes(grid)
@@ -247,13 +245,12 @@ def test_passes_shared_inputs(gi, request, which):
     er = rel_err(resid.cpu().numpy()[:, :3], s["resid"])
     log(f"{which} initial: {res}; resid mean {er.mean():.2e}")
     assert er.mean() < 1e-4
+    dev_resid = resid.cpu().numpy()[:, :3].copy()
     # temporal
-    prev_final = None
     if "temporal" in s:
         gbp.load_records(st[f - 1]["gbuffer"])
         rin.load_records(s["initial"])
-        prev_final = st[f - 1][f"spatial{pr.n_spatial - 1}"]
-        rin2.load_records(prev_final)
+        rin2.load_records(st[f - 1][f"spatial{pr.n_spatial - 1}"])
         gi.resample_temporal(ds, gb, gbp, st[f - 1]["cam"], rin, rin2, pr, rout, 1, f)
         res, _ = compare_reservoirs(rout.to_records(), s["temporal"], active, label=f"{which} temporal")
         log(f"{which} temporal: {res}")
@@ -274,6 +271,30 @@ def test_passes_shared_inputs(gi, request, which):
     e = rel_err(gimg, s["image"], 1e-2)
     log(f"{which} shade: mean rel err {e.mean():.2e} max {e.max():.2e}")
     assert e.mean() < 1e-4
+    return dev_resid, s["resid"]
+
+
+@pytest.mark.parametrize("which", ["tiny", "hd_small"])
+def test_passes_shared_inputs(gi, request, which):
+    cfg, sc, grid, irr, dep = request.getfixturevalue(which)
+    W, H = (64, 64) if which == "tiny" else (250, 141)
+    _check_chain(gi, cfg, sc, grid, irr, dep, W, H, 1 if which == "tiny" else 2, which)
+
+
+@pytest.mark.parametrize("variant", ["biased", "no_bound", "tight_bound"])
+def test_chain_parameter_variants(gi, tiny, variant):
+    """The chain over two frames (initial, temporal, two spatial passes,
+    shading) on shared inputs with the biased 1/M normalisation, with a G_max
+    no geometry term reaches (nothing bounded, the residual exactly zero) and
+    with a tight G_max = 0.05 (the residual nonzero at six times as many pixels)."""
+    cfg, sc, grid, irr, dep = tiny
+    over = {"biased": dict(unbiased=0), "no_bound": dict(g_max=1e30), "tight_bound": dict(g_max=0.05)}[variant]
+    cfg = dataclasses.replace(cfg, params=dataclasses.replace(cfg.params, temporal=True, n_spatial=2, **over))
+    resid, oresid = _check_chain(gi, cfg, sc, grid, irr, dep, 64, 64, 2, f"tiny {variant}")
+    if variant == "no_bound":
+        assert np.all(resid == 0.0) and np.all(oresid == 0.0)
+    if variant == "tight_bound":
+        assert np.mean(oresid.max(1) > 0) > 0.2  # about 5% at the default G_max = 1
 
 
 # --------------------------------------------------------------------------
