@@ -252,7 +252,7 @@ __device__ __forceinline__ f32x16 bias_tile(const float *b, int h)
 }
 
 template <int P>
-__global__ void __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(P == GI_MLP_BF16 ? 2 : 1, 2)))
+__global__ void __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(P == GI_MLP_BF16 ? 3 : 4, P == GI_MLP_BF16 ? 3 : 4)))
 k_mlp_infer(gi_mlp m, uint32_t n, const float4 *pos,
                                                            const float4 *nrm, float4 *out, int gate)
 {
@@ -289,8 +289,8 @@ k_mlp_infer(gi_mlp m, uint32_t n, const float4 *pos,
         sb[i] = b;
     }
     // the fragments of layers 0 and 1 (18) stay in LDS and are re-read per
-    // tile; the other 20 live in registers for the whole kernel (two waves
-    // per SIMD without spills)
+    // tile; the other 20 live in registers for the whole kernel (3 waves per
+    // SIMD for BF16, 4 for FP8, without spills)
     constexpr int kLdsFrags = 18, kRegFrags = kFrags - kLdsFrags;
     __shared__ FT wls[kLdsFrags * 64];
     const FT *wsrc = reinterpret_cast<const FT *>(m.weights);
@@ -315,6 +315,10 @@ k_mlp_infer(gi_mlp m, uint32_t n, const float4 *pos,
     const uint32_t ntiles = (n + 31u) / 32u;
 
     for (uint32_t tile = wave; tile < ntiles; tile += nwaves) {
+        // the LDS fragments and biases are re-read every tile: hoisted out of
+        // the loop they would take 36 (FP8) to 72 (BF16) more registers
+        // plus the bias tiles, and cost waves (FP8: 341 registers, 1 wave)
+        asm volatile("" ::: "memory");
         const uint32_t idx = tile * 32u + (uint32_t)s;
         const bool ok = idx < n;
         const float4 in = ok ? src[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
