@@ -133,6 +133,43 @@ def test_mlp_infer_fp8(gi):
     assert mean <= 2e-3 and p99 <= 5e-2 and mx <= 0.2
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_mlp_infer_full_frame_sampled(gi, precision):
+    """One 1080p frame's candidates (1920 x 1080 x 32) plus a ragged last
+    tile of 7: every wave of the persistent grid loops over hundreds of
+    tiles, re-reading its LDS weights and biases each time.  4096 sampled
+    outputs (the last 64 included) against the oracle's forward, same bars
+    as the small cases."""
+    n = 1920 * 1080 * 32 + 7
+    params = _params(31)
+    rng = np.random.default_rng(32)
+    pos = rng.random((n, 4), dtype=np.float32) * np.float32(8.0)
+    nrm = rng.standard_normal((n, 4), dtype=np.float32)
+    pos[:, 3] = 0.0
+    nrm[:, 3] = 0.0
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    sel = np.unique(np.concatenate([rng.choice(n - 64, 4032, replace=False), np.arange(n - 64, n)]))
+    X = M.encode(pos[sel, :3].astype(np.float64), nrm[sel, :3].astype(np.float64), BOX_LO, BOX_HI)
+    m = _mlp(gi, params, precision)
+    sa = None
+    if precision == "fp8":
+        m.scales[5:10] = torch.tensor([a / 448.0 for a in M.act_amax(params, X)], dtype=torch.float32)
+        sa = [float(v) for v in m.scales[5:10].cpu().numpy()]
+    tp, tn = torch.from_numpy(pos).cuda(), torch.from_numpy(nrm).cuda()
+    del pos, nrm
+    out = gi.mlp_infer(m, tp, tn)[torch.as_tensor(sel, device="cuda")].cpu().numpy()
+    del tp, tn
+    torch.cuda.empty_cache()
+    assert np.all(out[:, 3] == 0)
+    ref, _ = M.forward(params, X, prec=precision, act_scales=sa)
+    mean, p99, mx = _err_stats(out[:, :3], ref)
+    log(f"{precision} n={n}: vs oracle {precision} mean {mean:.2e} p99 {p99:.2e} max {mx:.2e}")
+    if precision == "bf16":
+        assert mean <= 2e-4 and p99 <= 5e-3 and mx <= 3e-2
+    else:
+        assert mean <= 2e-3 and p99 <= 5e-2 and mx <= 0.2
+
+
 # --------------------------------------------------------------------------
 # training
 # --------------------------------------------------------------------------
