@@ -261,3 +261,129 @@ def test_glossy_path_reduces_to_lambertian():
     i1 = o.shade(sc, 24, 24, gb, grid, irr, dep, ref[0], ref[1], pr, eye=cam.eye)
     i2 = o.shade(forced, 24, 24, gb, grid, irr, dep, got[0], got[1], pr, eye=cam.eye)
     assert np.allclose(i1, i2, rtol=1e-10, atol=1e-14)
+
+
+def _u(v):
+    return (int(v) >> 8) * 2.0 ** -24
+
+
+def _recursion_setup(extra_prims=False):
+    """Shading point x on a Lambertian sphere (index 1), its reservoir sample y
+    on a glossy floor (index 0, no diffuse albedo), an emitting room; with
+    extra_prims a glossy slab (index 2) hangs below the ceiling."""
+    ks, a, L = 0.9, 0.2, np.array([1.5, 1.0, 0.5])
+    types = [sg.PRIM_BOX, sg.PRIM_SPHERE]
+    cen, size = [[4.0, 0.5, 4.0], [4.0, 5.0, 4.0]], [[3.5, 0.5, 3.5], [0.5, 0.0, 0.0]]
+    alb, spec, rough = [[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]], [ks, 0.0], [a, 1.0]
+    if extra_prims:
+        types.append(sg.PRIM_BOX)
+        cen.append([4.0, 7.25, 4.0])
+        size.append([3.9, 0.25, 3.9])
+        alb.append([0.0, 0.0, 0.0])
+        spec.append(0.9)
+        rough.append(0.3)
+    prims = sg.prim_records(types, cen, size, alb, [[0.0, 0.0, 0.0]] * len(types), spec=spec, rough=rough)
+    sc = sg.Scene(prims=prims, has_room=True, room_lo=np.zeros(3, np.float32), room_hi=np.full(3, 8.0, np.float32),
+                  wall_albedo=np.zeros(3, np.float32), sky=np.zeros(3, np.float32), eps=float(np.float32(8e-4)),
+                  wall_emit=np.asarray(L, np.float32))
+    x, nx = np.array([4.0, 4.5, 4.0]), np.array([0.0, -1.0, 0.0])
+    y, ny = (np.array([5.0, 1.0, 5.0]) if extra_prims else np.array([6.5, 1.0, 6.5])), np.array([0.0, 1.0, 0.0])
+    gb = np.zeros((1, 14))
+    gb[0, 0:3], gb[0, 3:6], gb[0, 6:9], gb[0, 12], gb[0, 13] = x, nx, [0.5, 0.5, 0.5], 3.0, 1
+    res = np.zeros((1, 14))
+    res[0, 0:3], res[0, 3:6], res[0, 10], res[0, 11], res[0, 13] = y, ny, 1.0, 1.0, 0
+    eye = np.array([2.0, 3.0, 2.0])                # below the sphere, facing x
+    grid = sg.make_probe_grid(sg.CONFIGS["tiny"])
+    q0 = np.array([0.4, 0.8, 1.2])                 # probe colour: red/blue = 1/3; walls: 3
+    irr, dep = _uniform_probes(grid, q0)
+    return sc, gb, res, eye, grid, irr, dep, x, nx, y, ny
+
+
+# red/blue ratios of the two outcomes, as stored (float32 textures and records)
+_PROBE_RB = float(np.float32(0.4)) / float(np.float32(1.2))
+_WALL_RB = float(np.float32(1.5)) / float(np.float32(0.5))
+
+
+def _a0(eye, x, nx):
+    """Eq. 8: |x_0 - x_1|^2 / (4 pi cos) with x_0 the camera."""
+    v = eye - x
+    return (v @ v) / (4 * np.pi * (nx @ (v / np.linalg.norm(v))))
+
+
+def _segment(a, b, nb, p):
+    """One term of Eq. 7: sqrt(|a - b|^2 / (p <n_b, -w>)), w = direction a -> b."""
+    v = b - a
+    w = v / np.linalg.norm(v)
+    return math.sqrt((v @ v) / (p * (-(nb @ w))))
+
+
+def _shade1(sc, gb, grid, irr, dep, res, c, seed, eye):
+    pr = dataclasses.replace(sg.CONFIGS["tiny"].params, foot_c=c, glossy_depth=8)
+    return o.shade(sc, 1, 1, gb, grid, irr, dep, res, np.zeros((1, 3)), pr, seed=seed, frame=0, eye=eye)[0]
+
+
+def test_shading_recursion_threshold_first_segment():
+    """Eq. 7-8 at the selected sample: the footprint of x -> y, with p_1 the
+    cosine density of the Lambertian x, against a_0 of the camera-x segment.
+    The threshold c* = a(x y) / a_0 is computed here by hand; just below it
+    every glossy sample at y is read from the probes (probe colour), just
+    above it every one is traced to the emitting walls (wall colour)."""
+    sc, gb, res, eye, grid, irr, dep, x, nx, y, ny = _recursion_setup()
+    w = (y - x) / np.linalg.norm(y - x)
+    p1 = (nx @ w) / np.pi
+    c_star = _segment(x, y, ny, p1) ** 2 / _a0(eye, x, nx)
+    assert 10.0 < c_star < 1000.0                  # far from 1: a missing square root shows
+    seen = {0.99: 0, 1.01: 0}
+    for f, ratio in ((0.99, _PROBE_RB), (1.01, _WALL_RB)):
+        for seed in range(40):
+            out = _shade1(sc, gb, grid, irr, dep, res, f * c_star, seed, eye)
+            if out[2] == 0.0:
+                continue                           # the lobe sample fell below the floor
+            seen[f] += 1
+            assert out[0] / out[2] == pytest.approx(ratio, rel=1e-9), (f, seed, out)
+    assert min(seen.values()) >= 20
+
+
+def test_shading_recursion_threshold_sums_segments():
+    """The footprint of a two-segment path x -> y -> z is the square of the
+    SUM of the segments' square roots (Eq. 7), the second segment's density
+    being the glossy lobe's at y.  z lies on a glossy slab; for each seed the
+    threshold c* = a(x y z) / a_0 is computed from that seed's own lobe sample
+    at y: just below it z reads the probes, just above it z's own lobe sample
+    is traced (to a wall, for the seeds used)."""
+    sc, gb, res, eye, grid, irr, dep, x, nx, y, ny = _recursion_setup(extra_prims=True)
+    w = (y - x) / np.linalg.norm(y - x)
+    s1 = _segment(x, y, ny, (nx @ w) / np.pi)
+    a0 = _a0(eye, x, nx)
+    wo_y = -w
+    a_y, a_z = 0.2, 0.3
+    used = 0
+    for seed in range(200):
+        u = o.philox(seed, [0, 0, 16, 1])                     # y is recursion depth 1
+        wi = o.ggx_sample(ny, wo_y, a_y, _u(u[0]), _u(u[1]))
+        if wi is None:
+            continue
+        hit, t, prim, nz = o.closest_hit(sc, y + float(np.float32(8e-4)) * ny, wi)
+        if not hit or prim != 2:
+            continue
+        z = y + float(np.float32(8e-4)) * ny + t * wi
+        s2 = _segment(y, z, nz, o.ggx(ny, wo_y, wi, a_y)[1])
+        # z's own lobe sample (depth 2) must reach a wall for the traced case to show the wall colour
+        u2 = o.philox(seed, [0, 0, 16, 2])
+        wo_z = (y - z) / np.linalg.norm(y - z)
+        wz = o.ggx_sample(nz, wo_z, a_z, _u(u2[0]), _u(u2[1]))
+        if wz is None:
+            continue
+        hit2, _, prim2, _ = o.closest_hit(sc, z + float(np.float32(8e-4)) * nz, wz)
+        if not hit2 or prim2 < 3:
+            continue
+        c_star = (s1 + s2) ** 2 / a0
+        assert c_star > 1.05 * s1 * s1 / a0                     # y itself traces at both c
+        below = _shade1(sc, gb, grid, irr, dep, res, 0.99 * c_star, seed, eye)
+        above = _shade1(sc, gb, grid, irr, dep, res, 1.01 * c_star, seed, eye)
+        assert below[0] / below[2] == pytest.approx(_PROBE_RB, rel=1e-9), (seed, below)
+        assert above[0] / above[2] == pytest.approx(_WALL_RB, rel=1e-9), (seed, above)
+        # the sum of squares (no cross term) would put the threshold elsewhere
+        assert abs((s1 * s1 + s2 * s2) / a0 / c_star - 1.0) > 0.02
+        used += 1
+    assert used >= 10, used

@@ -413,3 +413,70 @@ def test_distance_heuristic_reads_the_backward_direction():
         assert np.allclose(T[best], L.astype(np.float64) * factor, rtol=1e-12), (frame, far)
         seen[far] += 1
     assert seen[True] >= 3 and seen[False] >= 3
+
+
+def _lobe_means(nt, s, fn, nu=1000, nph=1000):
+    """Means of fn(direction) and fn(direction)^2 under the normalised lobe
+    max(0, nt.w)^s dw, by midpoint quadrature in (u, phi) with cos(theta) =
+    u^(1/(s+1)): the substitution makes the lobe's weight uniform in u."""
+    u = (np.arange(nu) + 0.5) / nu
+    ph = (np.arange(nph) + 0.5) / nph * 2 * np.pi
+    U, P = np.meshgrid(u, ph, indexing="ij")
+    c = U ** (1.0 / (s + 1.0))
+    sn = np.sqrt(np.maximum(0.0, 1.0 - c * c))
+    nt = np.asarray(nt, float)
+    t = np.cross(nt, [1.0, 0, 0] if abs(nt[0]) < 0.9 else [0, 1.0, 0])
+    t /= np.linalg.norm(t)
+    b = np.cross(nt, t)
+    w = (sn * np.cos(P))[..., None] * t + (sn * np.sin(P))[..., None] * b + c[..., None] * nt
+    f = fn(w.reshape(-1, 3))
+    return float(f.mean()), float((f * f).mean())
+
+
+@pytest.mark.parametrize("sharp", [2.0, 50.0])
+def test_update_depth_moments_above_plane(sharp):
+    """Both depth moments of Sec. 3.2's mean visibility (the Chebyshev test
+    reads their difference as a variance).  Probes at height h above an
+    infinite plane: a ray of direction w meets the plane at h / (-w_y), so the
+    stored moments must be the lobe means of d and d^2 with d = min(h / (-w_y),
+    d_max) below the horizon and d_max above it, computed here by quadrature.
+    At sharpness 2 the variance is large, so storing the squared mean in place
+    of the mean square fails."""
+    plane = g.prim_records([1], [[0.0, -1.0, 0.0]], [[1000.0, 1.0, 1000.0]], [[0.0, 0.0, 0.0]],
+                           [[0, 0, 0]])
+    sc = _open_scene(plane, sky=(0.0, 0.0, 0.0))
+    grid = g.probe_grid((8, 1, 8), (-4.0, 0.5, -4.0), 1.0)
+    h, D = 1.0, float(grid.d_max)
+    irr, dep = g.empty_probe_textures(grid)
+    _, d2 = o.probe_update(sc, grid, irr, dep, 4096, 0.0, sharp, 11, 0)
+    N = grid.dep_res
+
+    def depth(w):
+        down = w[:, 1] < 0
+        d = np.full(len(w), D)
+        d[down] = np.minimum(h / -w[down, 1], D)
+        return d
+
+    worst = 0.0
+    for ty in range(0, N, 3):
+        for tx in range(0, N, 3):
+            nt = o.oct_decode([(tx + 0.5) / N, (ty + 0.5) / N])
+            want1, want2 = _lobe_means(nt, sharp, depth)
+            got = d2[:, (ty + 1) * (N + 2) + tx + 1, :]          # 64 independent probes
+            for k, want in ((0, want1), (1, want2)):
+                m = got[:, k].mean()
+                se = got[:, k].std(ddof=1) / math.sqrt(len(got))
+                if se < 1e-12:                                   # all sky: exactly d_max^k
+                    assert m == pytest.approx(want, rel=1e-9), (nt, k, m, want)
+                    continue
+                # quadrature error at this resolution is below 1e-5 relative
+                z = (m - want) / se
+                worst = max(worst, abs(z))
+                assert abs(m - want) < 5.0 * se + 1e-5 * want, (nt, k, m, want, se)
+    assert worst > 0.0
+    if sharp == 2.0:
+        # the downward texels see a real spread of depths: E[d^2] - E[d]^2 > 0
+        nt = np.array([0.0, -1.0, 0.0])
+        m1, m2 = _lobe_means(nt, sharp, depth)
+        var = m2 - m1 * m1
+        assert var > 0.05
