@@ -184,7 +184,8 @@ typedef struct gi_params {
     float g_max;         /* geometry-term bound G_max (Sec. 3.5), > 0 */
     float cos_n;         /* reuse normal threshold (cosine) */
     float depth_rel;     /* reuse relative depth threshold */
-    float m_cap;         /* temporal history cap, multiple of the current M */
+    float m_cap;         /* temporal history cap: the history's M is capped at
+                            floor(m_cap * (M + M_light)), computed in double */
     uint32_t unbiased;   /* 1: visibility-tested 1/Z normalisation, 0: 1/M */
     uint32_t M_light;    /* emitter-sampled candidates per pixel; M + M_light <= GI_MAX_M */
     uint32_t subsample;  /* n >= 1: pixel (x, y) draws candidates in frame f iff (x + y + f) % n == 0 */
@@ -247,8 +248,9 @@ gi_status gi_probe_query(const gi_probes *probes, uint32_t n, const float *p, co
  * balance-heuristic mixture density (M p_A + M_light p_light)/(M + M_light)
  * and M + M_light candidates are counted.  With subsample n > 1 (the
  * subsampling of Sec. 6) only pixels with (x + y + frame) % n == 0 draw
- * candidates; the others get an empty reservoir (M = 0) and leave the
- * resampling to temporal and spatial reuse, but still estimate the residual
+ * candidates; the others get an empty reservoir (M = 0) and take their
+ * samples from temporal reuse (the history cap does not depend on the
+ * pixel's own M) and spatial reuse, but still estimate the residual
  * from candidate 0.  resid (float4 plane, rgb used)
  * receives the residual transport rho_x L(y_0) max(0, 1 - g_max/G_0) of
  * candidate 0 (Eq. 9).  Pixels that miss or have zero albedo get an empty
@@ -261,7 +263,9 @@ gi_status gi_resample_initial(const gi_scene *scene, const gi_gbuffer *gb, const
 /* Temporal reuse (Sec. 3.1 step 2, Sec. 3.6): x is projected with prev_cam;
  * if the previous pixel is a hit with n.n_prev >= cos_n and |depth -
  * depth_prev| <= depth_rel*depth, the history reservoir (M capped at
- * m_cap*M) is merged after the pixel's own, with weights p_hat_x(y)W M using
+ * floor(m_cap*(M + M_light)), the per-frame candidate count, so that a pixel
+ * that drew no candidates this frame still takes over its history) is
+ * merged after the pixel's own, with weights p_hat_x(y)W M using
  * the cached L.  Unbiased mode: Z counts the domains whose target supports y
  * and that see y (one visibility ray each, the history domain from its
  * previous-frame vertex); a sample x cannot see is dropped.

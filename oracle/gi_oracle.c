@@ -77,7 +77,7 @@ typedef struct {
     double g_max;                   /* geometry-term bound */
     double cos_n;                   /* reuse normal threshold */
     double depth_rel;               /* reuse relative depth threshold */
-    double m_cap;                   /* temporal history cap (multiple of current M) */
+    double m_cap;                   /* temporal history cap (multiple of the per-frame candidate count) */
     int32_t subsample;              /* n: pixel (x, y) draws candidates in frame f iff (x+y+f) % n == 0 */
     int32_t pad;
     double eye[3];                  /* camera position of the current frame (glossy primary vertices) */
@@ -1205,7 +1205,8 @@ int64_t o_reproject(const o_camera *c, const double *x)
  * Temporal reuse (Sec. 3.1 step 2, "among previous frames"; Sec. 3.6 for the
  * cached radiance): merge the current reservoir with the history reservoir
  * of the pixel x lands on in the previous camera, if that pixel passes the
- * normal/depth test; the history's M is capped at m_cap x the current M.
+ * normal/depth test; the history's M is capped at floor(m_cap (M + M_light)),
+ * a multiple of the per-frame candidate count.
  * ------------------------------------------------------------------------- */
 void o_resample_temporal(const o_scene *sc, int32_t W, int32_t H, const double *gb, const double *gb_prev,
                          const o_camera *cam_prev, const double *cur, const double *hist,
@@ -1227,7 +1228,10 @@ void o_resample_temporal(const o_scene *sc, int32_t W, int32_t H, const double *
         int64_t pp_idx = o_reproject(cam_prev, g + GB_POS);
         if (pp_idx >= 0 && similar(g, gb_prev + GB_N * pp_idx, pp)) {
             const double *rh = hist + R_N * pp_idx;
-            double Mh = fmin(rh[R_M], pp->m_cap * rc[R_M]);
+            /* the cap is a multiple of the candidates a drawing pixel takes per
+             * frame, so a pixel that drew none this frame (candidate
+             * subsampling, Sec. 6) still takes over its history */
+            double Mh = fmin(rh[R_M], floor(pp->m_cap * (double)(pp->M + pp->M_light)));
             double u[4];
             rand4(seed, (uint32_t)p, frame, PASS_TEMPORAL, 0u, u);
             merge_in(sc, &s, g, pp->eye, rh, Mh, u[0], pp->g_max);

@@ -203,7 +203,7 @@ def _params(pr, eye=None, eye_prev=None) -> OParams:
     o.g_max = float(np.float32(pr.g_max))
     o.cos_n = float(np.float32(pr.cos_n))
     o.depth_rel = float(np.float32(pr.depth_rel))
-    o.m_cap = float(pr.m_cap)
+    o.m_cap = float(np.float32(pr.m_cap))
     o.subsample = int(getattr(pr, "subsample", 1))
     o.foot_c = float(np.float32(getattr(pr, "foot_c", 0.2)))
     o.glossy_depth = int(getattr(pr, "glossy_depth", 8))

@@ -682,7 +682,8 @@ __device__ __forceinline__ int reproject(const gi_camera &c, V3 x)
 template <bool LDS, bool GLOSSY>
 __global__ void __launch_bounds__(kBlock, 8)
     k_temporal(gi_scene sc, gi_gbuffer gb, gi_gbuffer gbp, gi_camera cam_prev, gi_reservoirs cur,
-               gi_reservoirs hist, gi_params pp, gi_reservoirs out, uint64_t seed, uint32_t frame)
+               gi_reservoirs hist, gi_params pp, uint32_t m_hist_cap, gi_reservoirs out, uint64_t seed,
+               uint32_t frame)
 {
     using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
     uint32_t px, py;
@@ -706,8 +707,7 @@ __global__ void __launch_bounds__(kBlock, 8)
         GB gq = load_gb<GLOSSY>(gbp, (uint32_t)q);
         if (similar(g, gq, pp)) {
             Res rh = load_res(hist, (uint32_t)q);
-            float cap = pp.m_cap * (float)rc.M;
-            uint32_t Mh = (float)rh.M > cap ? (uint32_t)cap : rh.M;
+            const uint32_t Mh = min(rh.M, m_hist_cap);
             uint4 rn = philox(seed, p, frame, kPassTemporal, 0u);
             merge_in<GLOSSY>(m, g, rh, Mh, u01(rn.x), pp.g_max);
             Mdom[1] = Mh;
@@ -1317,9 +1317,13 @@ gi_status gi_resample_temporal(const gi_scene *scene, const gi_gbuffer *gb, cons
     if ((s = check_res(out, W, H)) != GI_OK) return s;
     if (res_alias(out, cur_in) || res_alias(out, history)) return GI_ERR_ALIAS;
     if (W == 0 || H == 0) return GI_OK;
+    // the history's M is capped at a multiple of the candidates a drawing pixel
+    // takes per frame, so pixels that drew none this frame (candidate
+    // subsampling, Sec. 6) still take over their history
+    const double capd = floor((double)params->m_cap * (double)(params->M + params->M_light));
+    const uint32_t m_hist_cap = capd >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)capd;
     GI_LAUNCH_LDS_G(k_temporal, glossy_scene(scene), tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene,
-                    *gb, *gb_prev,
-                  *prev_cam, *cur_in, *history, *params, *out, seed, frame);
+                    *gb, *gb_prev, *prev_cam, *cur_in, *history, *params, m_hist_cap, *out, seed, frame);
     return launched();
 }
 

@@ -80,13 +80,17 @@ def test_view_bias_segment_and_never_inside():
     assert np.all(_sdf(sc, np.array(pts)) > 0.0)
 
 
-def test_temporal_history_cap():
+@pytest.mark.parametrize("m_cap", [3.0, 2.3])
+def test_temporal_history_cap(m_cap):
+    """The history's M is capped at floor(m_cap (M + M_light)), a multiple of
+    the per-frame candidate count (a non-integer multiple rounds down)."""
     cfg = g.CONFIGS["tiny"]
     sc = g.make_scene(cfg)
     cam = g.make_camera(cfg, width=16, height=16)
     grid = g.make_probe_grid(cfg)
     irr, dep = o.fill_probes(sc, grid, cfg.probe_update, seed=1)
-    pr = g.Params(M=4, k=3, n_spatial=2, radius=3.0, temporal=True, m_cap=3)
+    pr = g.Params(M=4, k=3, n_spatial=2, radius=3.0, temporal=True, m_cap=m_cap)
+    cap = math.floor(m_cap * pr.M)
     seq = o.Sequence(sc, grid, irr, dep, pr, 5)
     hist = None
     for f in range(3):
@@ -94,10 +98,43 @@ def test_temporal_history_cap():
         if f > 0:
             cur, out = st["initial"], st["temporal"]
             active = (st["gbuffer"][:, 13] != o.MISS) & (st["gbuffer"][:, 6:9].max(1) > 0)
-            expect = cur[:, 11] + np.minimum(hist[:, 11], pr.m_cap * cur[:, 11])
+            # static camera: every active pixel's history is its own previous reservoir
+            expect = cur[:, 11] + np.minimum(hist[:, 11], cap)
             assert np.array_equal(out[active, 11], expect[active])
-            assert np.any(hist[active, 11] > pr.m_cap * pr.M)
+            assert np.any(hist[active, 11] > cap)
         hist = st["spatial1"]
+
+
+def test_subsampled_pixels_take_over_their_history():
+    """Candidate subsampling (Sec. 6): a pixel that draws no candidates this
+    frame has M = 0 after the initial pass, and temporal reuse fills it from
+    its history (capped at the per-frame candidate count, not at its own M)."""
+    cfg = g.CONFIGS["tiny"]
+    sc = g.make_scene(cfg)
+    cam = g.make_camera(cfg, width=16, height=16)
+    grid = g.make_probe_grid(cfg)
+    irr, dep = o.fill_probes(sc, grid, cfg.probe_update, seed=1)
+    pr = g.Params(M=4, k=0, n_spatial=0, temporal=True, m_cap=3, subsample=2)
+    seq = o.Sequence(sc, grid, irr, dep, pr, 5)
+    _, st0 = seq.frame(cam, 0)
+    _, st1 = seq.frame(cam, 1)
+    gb = st1["gbuffer"]
+    active = (gb[:, 13] != o.MISS) & (gb[:, 6:9].max(1) > 0)
+    p = np.arange(16 * 16)
+    off = active & (((p % 16) + (p // 16) + 1) % 2 != 0)        # drew nothing in frame 1
+    on0 = active & (((p % 16) + (p // 16) + 0) % 2 == 0)        # drew in frame 0
+    assert off.sum() > 20 and np.array_equal(off, on0 & active)
+    assert np.all(st1["initial"][off, 11] == 0)
+    hist = st0["temporal"] if "temporal" in st0 else st0["initial"]
+    # the history of these pixels (static camera: their own previous reservoir)
+    out = st1["temporal"]
+    assert np.array_equal(out[off, 11], np.minimum(hist[off, 11], 3 * pr.M))
+    assert np.all(out[off, 11] > 0)
+    held = off & (hist[:, 10] > 0)
+    assert held.sum() > 10
+    # the sample is taken over: same tag, and W = wsum / (Z p_hat) > 0 where visible
+    assert np.array_equal(out[held, 12], hist[held, 12])
+    assert np.mean(out[held, 10] > 0) > 0.9
 
 
 def _single_pixel_camera(eye, look):
