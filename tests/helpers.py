@@ -40,7 +40,7 @@ def compare_reservoirs(gpu, ref, active=None, tol_mean=1e-4, tol_flip=1e-3, labe
     zero_mismatch = same & ((gpu[:, 10] > 0) != (ref[:, 10] > 0))
     out["zeroW_mismatch"] = float(zero_mismatch.mean())
     assert flips <= tol_flip, f"{label} flips {flips:.2e} > {tol_flip:g} ({out})"
-    for name in ("L", "wsum", "W"):
+    for name in ("y", "n", "L", "wsum", "W"):
         if name in out:
             assert out[name] <= tol_mean, f"{label} {name} mean rel err {out[name]:.2e} ({out})"
     assert out["zeroW_mismatch"] <= tol_flip, f"{label} W=0 mismatch ({out})"

@@ -62,7 +62,7 @@ def test_passes_full_size_sampled(gi, name):
     gb1, gb0 = r.gb[1], r.gb[0]
 
     rng = np.random.default_rng(5)
-    S = np.sort(rng.choice(W * H, 500, replace=False))
+    S = np.sort(rng.choice(W * H, 2000, replace=False))
     # pixels the spatial passes at S read, from the passes' own counters
     neigh = {int(o.spatial_candidate(W, H, p, j, pr.radius, 1, 1, s))
              for p in S for s in range(pr.n_spatial) for j in range(pr.k)}
@@ -94,7 +94,7 @@ def test_passes_full_size_sampled(gi, name):
     rin, rhist, rout = gi.Reservoirs(W, H), gi.Reservoirs(W, H), gi.Reservoirs(W, H)
     resid = torch.zeros(n, 4, device="cuda")
     img = torch.zeros(n, 4, device="cuda")
-    tol_flip = 5e-3
+    tol_flip = 1e-3
     # initial
     gi.resample_initial(r.dscene, gb1, r.probe, pr, rin, resid, 1, 1)
     st, _ = compare_reservoirs(rin.to_records()[S], ores[S], active, tol_flip=tol_flip, label=f"{name} initial")

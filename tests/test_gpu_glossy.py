@@ -205,7 +205,7 @@ def test_glossy_full_size_sampled(gi):
     probes.load(irr, dep)
     gb = gi.GBuffer(W, H)
     gi.trace_gbuffer(ds, cam, gb)
-    S = np.sort(np.random.default_rng(6).choice(n, 400, replace=False))
+    S = np.sort(np.random.default_rng(6).choice(n, 2000, replace=False))
     ogb = o.gbuffer(sc, cam, pixels=S, out=np.zeros((n, 14)))
     g = gb.to_records()[S]
     assert np.mean(g[:, 13] == ogb[S, 13]) > 0.995
@@ -216,7 +216,7 @@ def test_glossy_full_size_sampled(gi):
     gi.resample_initial(ds, gb, probes, pr, rin, resid, 1, 0)
     ores, oresid = o.resample_initial(sc, W, H, ogb, grid, irr, dep, pr, 1, 0, pixels=S, eye=cam.eye)
     active = _active(sc, ogb[S])
-    res, _ = compare_reservoirs(rin.to_records()[S], ores[S], active, tol_flip=5e-3, label="glossy 1080p initial")
+    res, _ = compare_reservoirs(rin.to_records()[S], ores[S], active, tol_flip=1e-3, label="glossy 1080p initial")
     er = rel_err(resid.cpu().numpy()[S, :3], oresid[S])
     log(f"glossy 1080p initial (sampled): {res}; resid mean {er.mean():.2e}")
     assert er.mean() < 1e-4

@@ -117,7 +117,7 @@ def test_storage_error_uhd_sampled(gi):
     n = W * H
     pr = cfg.params
     cam = sg.make_camera(cfg, 0)
-    S = np.sort(np.random.default_rng(8).choice(n, 400, replace=False))
+    S = np.sort(np.random.default_rng(8).choice(n, 2000, replace=False))
     ogb = o.gbuffer(sc, cam, pixels=S, out=np.zeros((n, 14)))
     ores, oresid = o.resample_initial(sc, W, H, ogb, grid, irr, dep, pr, 1, 0, pixels=S)
     oimg = o.shade(sc, W, H, ogb, grid, irr, dep, ores, oresid, pr, pixels=S)
@@ -144,5 +144,5 @@ def test_storage_error_uhd_sampled(gi):
             f"flips {flips:.2e}")
         del g, out, resid, img
         torch.cuda.empty_cache()
-    assert errs["f32"][0] < 1e-4 and errs["f32"][1] <= 5e-3
+    assert errs["f32"][0] < 1e-4 and errs["f32"][1] <= 1e-3
     assert errs["f16"][0] < 1e-2 and errs["f16"][1] <= 5e-2
