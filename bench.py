@@ -349,7 +349,7 @@ def main():
     import torch
 
     from paper_2108_05263_amd import build as libbuild
-    if not os.path.exists(libbuild.LIB):
+    if libbuild.is_stale():
         libbuild.build()
     from paper_2108_05263_amd import gi
     from paper_2108_05263_amd import scenegen as sg

@@ -209,6 +209,11 @@ const char *gi_status_string(gi_status s);
 /* Number of the HIP device the calling thread uses, or -1 (host query). */
 int gi_device(void);
 
+/* Hash of the sources and compiler flags this library was built from (16
+ * hex digits, static storage): build provenance, compared by the loader with
+ * the sources it ships with. */
+const char *gi_build_hash(void);
+
 /* Primary vertices (Sec. 3.1: the primary vertex x, with L_e(x) of Eq. 9):
  * one pinhole ray per pixel centre, closest hit, written to `out`.
  * out->width/height must equal the camera's. */

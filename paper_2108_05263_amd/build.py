@@ -1,5 +1,7 @@
 """Build libgi.so (HIP kernels for gfx950 + the C ABI) in-tree with hipcc."""
+import hashlib
 import os
+import re
 import subprocess
 import sys
 
@@ -24,8 +26,35 @@ def hipcc():
     return "hipcc"
 
 
+def source_hash(extra=()) -> str:
+    """SHA-256 (16 hex digits) of every source and header the library is
+    built from and of the compiler flags: the library embeds it, and loading
+    refuses a library whose hash differs from that of the sources in the tree."""
+    h = hashlib.sha256()
+    for d in sorted(DEPS):
+        with open(d, "rb") as fh:
+            h.update(os.path.basename(d).encode() + b"\0" + fh.read())
+    # flags without the tree's absolute include paths (the box copies the tree elsewhere)
+    flags = [os.path.relpath(f, ROOT) if os.path.isabs(f) else f for f in HIPCC_FLAGS + list(extra)]
+    h.update(" ".join(flags).encode())
+    return h.hexdigest()[:16]
+
+
+MARKER = b"GI_BUILD_HASH="
+
+
+def built_hash():
+    """The source hash embedded in the built library, or None."""
+    if not os.path.exists(LIB):
+        return None
+    with open(LIB, "rb") as fh:
+        m = re.search(re.escape(MARKER) + rb"([0-9a-f]{16})", fh.read())
+    return m.group(1).decode() if m else None
+
+
 def build(verbose: bool = False, extra=()) -> str:
-    cmd = [hipcc()] + HIPCC_FLAGS + list(extra) + ["-o", LIB + ".tmp"] + SOURCES
+    tag = source_hash(extra)
+    cmd = [hipcc()] + HIPCC_FLAGS + list(extra) + [f'-DGI_BUILD_HASH="{tag}"', "-o", LIB + ".tmp"] + SOURCES
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -34,10 +63,8 @@ def build(verbose: bool = False, extra=()) -> str:
 
 
 def is_stale() -> bool:
-    if not os.path.exists(LIB):
-        return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(d) > t for d in DEPS if os.path.exists(d))
+    """True when the library is missing or was built from other sources or flags."""
+    return built_hash() != source_hash()
 
 
 if __name__ == "__main__":

@@ -12,6 +12,16 @@
 
 #include "gi.h"
 
+#ifndef GI_BUILD_HASH
+#define GI_BUILD_HASH "unknown"
+#endif
+
+// provenance: the build script passes the hash of the sources and flags; the
+// loader finds it in the file by its marker and compares it with the tree's
+extern "C" __attribute__((used)) const char gi_build_id[] = "GI_BUILD_HASH=" GI_BUILD_HASH;
+
+extern "C" const char *gi_build_hash(void) { return gi_build_id + 14; }
+
 namespace {
 
 void cell_range(const gi_prim &p, const float lo[3], const float cs[3], const uint32_t res[3], int c0[3], int c1[3])

@@ -25,7 +25,7 @@ OPT_GLOSSY = 2
 _lib = None
 
 # every symbol include/gi.h declares
-EXPORTS = ["gi_status_string", "gi_device", "gi_trace_gbuffer", "gi_probe_update", "gi_probe_query",
+EXPORTS = ["gi_status_string", "gi_device", "gi_build_hash", "gi_trace_gbuffer", "gi_probe_update", "gi_probe_query",
            "gi_resample_initial", "gi_resample_temporal", "gi_resample_spatial", "gi_shade",
            "gi_accel_build_host", "gi_philox", "gi_trace_rays",
            "gi_mlp_init", "gi_mlp_prepare", "gi_mlp_infer", "gi_mlp_make_batch", "gi_mlp_train_workspace_bytes",
@@ -116,7 +116,13 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise GiError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                       "python paper_2108_05263_amd/build.py")
+    from . import build as _build
+    have, want = _build.built_hash(), _build.source_hash()
+    if have != want:
+        raise GiError(f"{LIB_PATH} was built from other sources (hash {have}, tree {want}); "
+                      "run __graft_entry__.build() or python paper_2108_05263_amd/build.py")
     L = C.CDLL(LIB_PATH)
+    L.gi_build_hash.restype = C.c_char_p
     L.gi_status_string.restype = C.c_char_p
     L.gi_status_string.argtypes = [C.c_int]
     L.gi_device.restype = C.c_int

@@ -33,6 +33,13 @@ def test_exports_every_declared_symbol(gi):
     assert declared == set(gi.EXPORTS)
 
 
+def test_library_built_from_these_sources(gi):
+    """The library carries the hash of the sources and flags it was built
+    from; loading refuses a library built from others."""
+    from paper_2108_05263_amd import build
+    assert gi.load().gi_build_hash().decode() == build.source_hash() == build.built_hash()
+
+
 def test_status_strings(gi):
     lib = gi.load()
     for s in range(7):
