@@ -25,7 +25,24 @@
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 #include <string.h>
+
+/* Optional OpenMP pixel loops (build with -fopenmp): every pixel or probe
+ * iteration reads shared inputs and writes only its own outputs, so the
+ * results are bitwise identical for any thread count.  One thread unless
+ * o_set_threads says otherwise. */
+static int o_threads = 1;
+void o_set_threads(int n) { o_threads = n < 1 ? 1 : n; }
+int o_openmp(void)
+{
+#ifdef _OPENMP
+    return 1;
+#else
+    return 0;
+#endif
+}
+#define O_PARALLEL _Pragma("omp parallel for schedule(dynamic, 16) num_threads(o_threads) if(o_threads > 1)")
 
 #define O_MISS 0xFFFFFFFFu
 #define O_PI 3.14159265358979323846
@@ -431,6 +448,7 @@ void o_gbuffer(const o_scene *sc, const o_camera *cam, const int32_t *pix, int64
 {
     int64_t total = (int64_t)cam->width * cam->height;
     int64_t n = pix ? npix : total;
+    O_PARALLEL
     for (int64_t q = 0; q < n; ++q) {
         int64_t p = pix ? pix[q] : q;
         int i = (int)(p % cam->width), j = (int)(p / cam->width);
@@ -753,9 +771,12 @@ void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, doub
     int64_t P = (int64_t)in->dims[0] * in->dims[1] * in->dims[2];
     size_t irr_tile = (size_t)(Ni + 2) * (Ni + 2) * 3, dep_tile = (size_t)(Nd + 2) * (Nd + 2) * 2;
     int64_t n = plist ? nlist : P;
-    double dirs[4096][3], Ls[4096][3], ds[4096];
     if (rays > 4096) rays = 4096;
+    O_PARALLEL
     for (int64_t q = 0; q < n; ++q) {
+        double (*dirs)[3] = malloc(sizeof(double) * 3 * (size_t)rays);
+        double (*Ls)[3] = malloc(sizeof(double) * 3 * (size_t)rays);
+        double *ds = malloc(sizeof(double) * (size_t)rays);
         int64_t pi = plist ? plist[q] : q;
         int idx[3] = {(int)(pi % in->dims[0]), (int)((pi / in->dims[0]) % in->dims[1]),
                       (int)(pi / ((int64_t)in->dims[0] * in->dims[1]))};
@@ -848,6 +869,9 @@ void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, doub
             }
         fill_gutter(inew, Ni, 3);
         fill_gutter(dnew, Nd, 2);
+        free(dirs);
+        free(Ls);
+        free(ds);
     }
 }
 
@@ -996,6 +1020,7 @@ void o_resample_initial(const o_scene *sc, int32_t W, int32_t H, const double *g
     const int n_em = pp->M_light > 0 ? emitter_list(sc, em, 256) : 0;
     const int Mb = pp->M, Ml = pp->M_light, Mt = Mb + Ml;
     int64_t n = pix ? npix : (int64_t)W * H;
+    O_PARALLEL
     for (int64_t q = 0; q < n; ++q) {
         int64_t p = pix ? pix[q] : q;
         const double *g = gb + GB_N * p;
@@ -1214,6 +1239,7 @@ void o_resample_temporal(const o_scene *sc, int32_t W, int32_t H, const double *
                          int64_t npix, double *out)
 {
     int64_t n = pix ? npix : (int64_t)W * H;
+    O_PARALLEL
     for (int64_t q = 0; q < n; ++q) {
         int64_t p = pix ? pix[q] : q;
         const double *g = gb + GB_N * p;
@@ -1268,10 +1294,11 @@ void o_resample_spatial(const o_scene *sc, int32_t W, int32_t H, const double *g
                         int64_t npix, double *out)
 {
     int64_t n = pix ? npix : (int64_t)W * H;
-    const double *gdom[16], *edom[16];
-    double Mdom[16];
-    for (int j = 0; j < 16; ++j) edom[j] = pp->eye;
+    O_PARALLEL
     for (int64_t q = 0; q < n; ++q) {
+        const double *gdom[16], *edom[16];
+        double Mdom[16];
+        for (int j = 0; j < 16; ++j) edom[j] = pp->eye;
         int64_t p = pix ? pix[q] : q;
         const double *g = gb + GB_N * p;
         const double *rc = in + R_N * p;
@@ -1360,6 +1387,7 @@ void o_shade(const o_scene *sc, int32_t W, int32_t H, const double *gb, const o_
              int64_t npix, double *img, uint64_t seed, uint32_t frame)
 {
     int64_t n = pix ? npix : (int64_t)W * H;
+    O_PARALLEL
     for (int64_t q = 0; q < n; ++q) {
         int64_t p = pix ? pix[q] : q;
         const double *g = gb + GB_N * p;
@@ -1426,6 +1454,7 @@ void o_shade(const o_scene *sc, int32_t W, int32_t H, const double *gb, const o_
 void o_brute_force(const o_scene *sc, const o_probes *pr, const double *gb, int32_t W, int32_t H,
                    const int32_t *pix, int64_t npix, int64_t nsamples, uint64_t seed, double *out)
 {
+    O_PARALLEL
     for (int64_t q = 0; q < npix; ++q) {
         int64_t p = pix[q];
         const double *g = gb + GB_N * p;
@@ -1474,6 +1503,7 @@ void o_brute_force(const o_scene *sc, const o_probes *pr, const double *gb, int3
 void o_path_trace(const o_scene *sc, const double *gb, const int32_t *pix, int64_t npix, int32_t spp,
                   uint32_t s0, uint64_t seed, const double *eye, double *out)
 {
+    O_PARALLEL
     for (int64_t q = 0; q < npix; ++q) {
         const int64_t p = pix[q];
         const double *g = gb + GB_N * p;

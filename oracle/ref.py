@@ -66,6 +66,8 @@ _P = C.c_void_p
 
 
 def _setup(L):
+    L.o_set_threads.argtypes = [C.c_int]
+    L.o_openmp.restype = C.c_int
     L.o_philox.argtypes = [C.c_uint32, C.c_uint32, _P, _P]
     L.o_cosine_dir.argtypes = [_P, C.c_double, C.c_double, _P]
     L.o_sphere_dir.argtypes = [C.c_double, C.c_double, _P]
@@ -98,6 +100,15 @@ def _setup(L):
     L.o_ggx_sample.argtypes = [_P, _P, C.c_double, C.c_double, C.c_double, _P]
     L.o_ggx_sample.restype = C.c_int
     L.o_glossy_term.argtypes = [_P, _P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_double, _P]
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's pixel and probe loops (1 by default).  Every
+    iteration writes only its own outputs, so results do not depend on it.
+    Returns the count in effect (1 when the library was built without OpenMP)."""
+    n = max(1, int(n)) if lib().o_openmp() else 1
+    lib().o_set_threads(n)
+    return n
 
 
 def _ptr(a: np.ndarray):
