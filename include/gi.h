@@ -10,8 +10,9 @@
  * Conventions shared by every entry point
  *  - Every buffer pointer is DEVICE memory owned by the caller.  The library
  *    allocates nothing, keeps no pointer after a call returns, and has no
- *    mutable global state; buffers must stay valid until the stream's work
- *    has completed.
+ *    mutable global state besides the per-GPU scratch of
+ *    gi_mlp_train_step_noalloc; buffers must stay valid until the stream's
+ *    work has completed.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Every call is asynchronous on that stream.
  *  - Arguments are validated on the host before anything is launched; a
@@ -430,6 +431,26 @@ gi_status gi_mlp_adam(const gi_mlp *mlp, const float *grad, uint32_t t, float lr
 gi_status gi_mlp_train_step(const gi_mlp *mlp, uint32_t n, const float *pos4, const float *nrm4,
                             const float *target4, const float *qprobe4, uint32_t t, float lr,
                             void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Largest batch of gi_mlp_train_step_noalloc, and the bytes of device memory
+ * its scratch takes on every GPU the library runs on (from the code object's
+ * load until the process ends). */
+#define GI_MLP_NOALLOC_MAX_BATCH 16384u
+#define GI_MLP_NOALLOC_SCRATCH_BYTES 36509440ull
+
+/* gi_mlp_train_step without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid allocation): the same kernels and
+ * results, with the workspace in a scratch array inside the library, one
+ * per GPU (its address is looked up once per device, on the first call with
+ * that device current).  Allocates nothing.  n <= GI_MLP_NOALLOC_MAX_BATCH,
+ * else GI_ERR_SHAPE; GI_ERR_DEVICE when the scratch cannot be located.
+ * Every call on a GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (on different streams, or from several threads) race and must be
+ * serialised by the caller.  Nothing carries over from one call to the next. */
+gi_status gi_mlp_train_step_noalloc(const gi_mlp *mlp, uint32_t n, const float *pos4, const float *nrm4,
+                                    const float *target4, const float *qprobe4, uint32_t t, float lr,
+                                    void *stream);
 
 /* Device workspace bytes of gi_resample_initial_mlp: 48 bytes per candidate. */
 uint64_t gi_initial_mlp_workspace_bytes(uint32_t width, uint32_t height, uint32_t M);

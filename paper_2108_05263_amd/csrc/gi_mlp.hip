@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "gi.h"
 #include "gi_device.hpp"
@@ -704,9 +705,39 @@ __global__ void __launch_bounds__(256) k_mlp_state(gi_mlp m, uint32_t t)
     }
 }
 
-uint32_t train_wgs(uint32_t n) { return (n + kTrainS - 1) / kTrainS; }
+constexpr uint32_t train_wgs(uint32_t n) { return (n + kTrainS - 1) / kTrainS; }
 
-uint64_t train_bytes(uint32_t n) { return 4ull * (kHdr + (uint64_t)kPartStride * (1ull + train_wgs(n))); }
+constexpr uint64_t train_bytes(uint32_t n) { return 4ull * (kHdr + (uint64_t)kPartStride * (1ull + train_wgs(n))); }
+
+// Scratch of the allocation-free training step (gi_mlp_train_step_noalloc):
+// the workspace of a GI_MLP_NOALLOC_MAX_BATCH-sample step, one copy per GPU,
+// held from the code object's load until the process ends.  Every word the
+// step reads is written earlier in the same step (count, partial gradients,
+// reductions), so nothing needs clearing between calls; calls that overlap
+// on one GPU share it and race.
+constexpr uint64_t kNoallocBytes = train_bytes(GI_MLP_NOALLOC_MAX_BATCH);
+static_assert(kNoallocBytes == GI_MLP_NOALLOC_SCRATCH_BYTES, "gi.h states the scratch size");
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+// device address of `scratch` on each GPU (the host-side symbol is only a
+// stand-in), looked up once per device with that device current
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+gi_status scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GI_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GI_ERR_DEVICE;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return GI_OK;
+}
 
 gi_status prepare(const gi_mlp &m, hipStream_t st)
 {
@@ -854,6 +885,22 @@ gi_status gi_mlp_train_step(const gi_mlp *mlp, uint32_t n, const float *pos4, co
     if (t < 1 || !(lr > 0.0f)) return GI_ERR_PARAM;
     float *grad = reinterpret_cast<float *>(workspace) + kHdr;
     if ((s = grad_launch(*mlp, n, pos4, nrm4, target4, qprobe4, grad, workspace, S(stream))) != GI_OK) return s;
+    return adam_launch(*mlp, grad, t, lr, S(stream));
+}
+
+gi_status gi_mlp_train_step_noalloc(const gi_mlp *mlp, uint32_t n, const float *pos4, const float *nrm4,
+                                    const float *target4, const float *qprobe4, uint32_t t, float lr,
+                                    void *stream)
+{
+    gi_status s;
+    if ((s = check_mlp(mlp)) != GI_OK) return s;
+    if ((s = check_batch(n, pos4, nrm4, target4)) != GI_OK) return s;
+    if (n > GI_MLP_NOALLOC_MAX_BATCH) return GI_ERR_SHAPE;
+    if (t < 1 || !(lr > 0.0f)) return GI_ERR_PARAM;
+    void *ws = nullptr;
+    if ((s = scratch_address(&ws)) != GI_OK) return s;
+    float *grad = reinterpret_cast<float *>(ws) + kHdr;
+    if ((s = grad_launch(*mlp, n, pos4, nrm4, target4, qprobe4, grad, ws, S(stream))) != GI_OK) return s;
     return adam_launch(*mlp, grad, t, lr, S(stream));
 }
 

@@ -29,7 +29,7 @@ EXPORTS = ["gi_status_string", "gi_device", "gi_build_hash", "gi_trace_gbuffer",
            "gi_resample_initial", "gi_resample_temporal", "gi_resample_spatial", "gi_shade",
            "gi_accel_build_host", "gi_philox", "gi_trace_rays",
            "gi_mlp_init", "gi_mlp_prepare", "gi_mlp_infer", "gi_mlp_make_batch", "gi_mlp_train_workspace_bytes",
-           "gi_mlp_grad", "gi_mlp_adam", "gi_mlp_train_step", "gi_initial_mlp_workspace_bytes",
+           "gi_mlp_grad", "gi_mlp_adam", "gi_mlp_train_step", "gi_mlp_train_step_noalloc", "gi_initial_mlp_workspace_bytes",
            "gi_resample_initial_mlp", "gi_shade_mlp_workspace_bytes", "gi_shade_mlp", "gi_path_trace"]
 
 MLP_N_PARAMS = 17731
@@ -144,6 +144,7 @@ def load():
         "gi_mlp_grad": [_P, C.c_uint32, _P, _P, _P, _P, _P, _P, C.c_uint64, _P],
         "gi_mlp_adam": [_P, _P, C.c_uint32, C.c_float, _P],
         "gi_mlp_train_step": [_P, C.c_uint32, _P, _P, _P, _P, C.c_uint32, C.c_float, _P, C.c_uint64, _P],
+        "gi_mlp_train_step_noalloc": [_P, C.c_uint32, _P, _P, _P, _P, C.c_uint32, C.c_float, _P],
         "gi_resample_initial_mlp": [_P, _P, _P, _P, _P, _P, _P, _P, C.c_uint64, C.c_uint64, C.c_uint32, _P],
         "gi_shade_mlp": [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_uint64, _P],
         "gi_path_trace": [_P, _P, C.c_uint32, C.c_uint32, C.c_uint64, _P, _P],
@@ -654,6 +655,13 @@ def mlp_train_step(mlp: Mlp, batch: MlpBatch, t, lr, ws: torch.Tensor, stream=No
     check(load().gi_mlp_train_step(mlp.ref, batch.n, _ptr(batch.pos, F32), _ptr(batch.nrm, F32), _ptr(batch.target, F32),
                                    _ptr(batch.qprobe, F32), int(t), float(lr), _ptr(ws), ws.numel(),
                                    _stream(stream)), "gi_mlp_train_step")
+
+
+def mlp_train_step_noalloc(mlp: Mlp, batch: MlpBatch, t, lr, stream=None):
+    """gi_mlp_train_step with the library's per-GPU scratch (no workspace)."""
+    check(load().gi_mlp_train_step_noalloc(mlp.ref, batch.n, _ptr(batch.pos, F32), _ptr(batch.nrm, F32),
+                                           _ptr(batch.target, F32), _ptr(batch.qprobe, F32), int(t), float(lr),
+                                           _stream(stream)), "gi_mlp_train_step_noalloc")
 
 
 def initial_mlp_workspace(W, H, M, device="cuda") -> torch.Tensor:
