@@ -53,6 +53,43 @@ __device__ __forceinline__ bool tile_pixel(uint32_t W, uint32_t H, uint32_t &px,
     return px < W && py < H;
 }
 
+// Reuse passes gather from neighbours within the spatial radius: their
+// workgroups are given tiles in XCD stripes, so that a pixel's neighbours
+// are mostly read through one XCD's L2.  Workgroup L runs on XCD L % 8 and
+// takes tile L / 8 (row-major) of stripe L % 8, a band of ceil(tx / 8) tile
+// columns.
+#ifndef GI_XCD_STRIPES
+#define GI_XCD_STRIPES 1
+#endif
+__device__ __forceinline__ bool tile_pixel_striped(uint32_t W, uint32_t H, uint32_t &px, uint32_t &py)
+{
+#if GI_XCD_STRIPES
+    const uint32_t t = threadIdx.x, w = t >> 6, l = t & 63u;
+    const uint32_t tiles_x = (W + kTile - 1) / kTile;
+    const uint32_t sw = (tiles_x + kXcds - 1) / kXcds;
+    const uint32_t xcd = blockIdx.x % kXcds, m = blockIdx.x / kXcds;
+    const uint32_t tx = xcd * sw + m % sw, ty = m / sw;
+    px = tx * kTile + (w & 1u) * 8u + (l & 7u);
+    py = ty * kTile + (w >> 1) * 8u + (l >> 3);
+    return tx < tiles_x && px < W && py < H;
+#else
+    return tile_pixel(W, H, px, py);
+#endif
+}
+
+dim3 tile_grid(uint32_t W, uint32_t H);
+
+dim3 striped_grid(uint32_t W, uint32_t H)
+{
+#if GI_XCD_STRIPES
+    const uint32_t tx = (W + kTile - 1) / kTile, ty = (H + kTile - 1) / kTile;
+    const uint32_t sw = (tx + kXcds - 1) / kXcds;
+    return dim3(kXcds * sw * ty);
+#else
+    return tile_grid(W, H);
+#endif
+}
+
 dim3 tile_grid(uint32_t W, uint32_t H)
 {
     uint32_t tx = (W + kTile - 1) / kTile, ty = (H + kTile - 1) / kTile;
@@ -717,14 +754,22 @@ __global__ void __launch_bounds__(kBlock, 8)
     store_res(out, p, finish<GLOSSY>(sc, acc, m, g, Mdom, [&](int) { return load_gb<GLOSSY>(gbp, qprev); }, pp));
 }
 
-template <bool LDS, bool GLOSSY>
-__global__ void __launch_bounds__(kBlock, GLOSSY ? 4 : 5)
+// Neighbour slots are static (KM of them, KM >= k): a slot that draws no
+// pixel (off-screen, the pixel itself, j >= k) points at the pixel itself,
+// so every neighbour load is in bounds and unconditional, and the loads of
+// all slots can be in flight together instead of one neighbour after the
+// other (the pass is bound by the latency of these gathers).
+#ifndef GI_SPATIAL_WAVES
+#define GI_SPATIAL_WAVES 5
+#endif
+template <bool LDS, bool GLOSSY, int KM>
+__global__ void __launch_bounds__(kBlock, GLOSSY ? 4 : GI_SPATIAL_WAVES)
     k_spatial(gi_scene sc, gi_gbuffer gb, gi_reservoirs in, gi_params pp, uint32_t pass, gi_reservoirs out,
               uint64_t seed, uint32_t frame)
 {
     using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
     uint32_t px, py;
-    const bool inside = tile_pixel(gb.width, gb.height, px, py);
+    const bool inside = tile_pixel_striped(gb.width, gb.height, px, py);
     if (LDS) stage_scene(sc);
     if (!inside) return;
     const Acc acc(sc);
@@ -736,30 +781,57 @@ __global__ void __launch_bounds__(kBlock, GLOSSY ? 4 : 5)
         store_res(out, p, rc);
         return;
     }
-    Merge m{0.0f, 0u, false, rc};
-    uint32_t Mdom[kMaxDom], qidx[kMaxDom];
-    Mdom[0] = rc.M;
+    // neighbour pixels: uniform in the disk (counter (pixel, frame, 2+pass, j))
+    uint32_t qidx[KM + 1];
+    bool drawn[KM];
+    float uq[KM];
     qidx[0] = p;
-    merge_in<GLOSSY>(m, g, rc, rc.M, 0.0f, pp.g_max);
 #pragma unroll
-    for (uint32_t j = 0; j < GI_MAX_K; ++j) {
-        Mdom[j + 1] = 0u;
+    for (int j = 0; j < KM; ++j) {
         qidx[j + 1] = p;
-        if (j >= pp.k) continue;
-        uint4 rn = philox(seed, p, frame, kPassSpatial0 + pass, j);
-        float rad = pp.radius * fsqrt(u01(rn.x));
-        float s_ = sin_rev(u01(rn.y)), c_ = cos_rev(u01(rn.y));
-        int qx = (int)px + (int)floorf(rad * c_ + 0.5f);
-        int qy = (int)py + (int)floorf(rad * s_ + 0.5f);
+        drawn[j] = false;
+        uq[j] = 0.0f;
+        if ((uint32_t)j >= pp.k) continue;
+        const uint4 rn = philox(seed, p, frame, kPassSpatial0 + pass, (uint32_t)j);
+        const float rad = pp.radius * fsqrt(u01(rn.x));
+        const float s_ = sin_rev(u01(rn.y)), c_ = cos_rev(u01(rn.y));
+        const int qx = (int)px + (int)floorf(rad * c_ + 0.5f);
+        const int qy = (int)py + (int)floorf(rad * s_ + 0.5f);
+        uq[j] = u01(rn.z);
         if (qx < 0 || qy < 0 || qx >= (int)W || qy >= (int)H) continue;
         if (qx == (int)px && qy == (int)py) continue;
-        uint32_t q = (uint32_t)qy * W + (uint32_t)qx;
-        GB gq = load_gb<GLOSSY>(gb, q);
-        if (!similar(g, gq, pp)) continue;
-        Res rq = load_res(in, q);
-        merge_in<GLOSSY>(m, g, rq, rq.M, u01(rn.z), pp.g_max);
-        Mdom[j + 1] = rq.M;
-        qidx[j + 1] = q;
+        drawn[j] = true;
+        qidx[j + 1] = (uint32_t)qy * W + (uint32_t)qx;
+    }
+    // geometric validation of every drawn neighbour (its normal and depth)
+    bool use[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        const uint32_t q = qidx[j + 1];
+        const float4 a = reinterpret_cast<const float4 *>(gb.pos_depth)[q];
+        GB gq;
+        gq.depth = a.w;
+        if (gb.format == GI_GB_F16) {
+            const GB full = load_gb<false>(gb, q);
+            gq.n = full.n;
+            gq.prim = full.prim;
+        } else {
+            const float4 b = reinterpret_cast<const float4 *>(gb.nrm_prim)[q];
+            gq.n = xyz(b);
+            gq.prim = __float_as_uint(b.w);
+        }
+        use[j] = drawn[j] && similar(g, gq, pp);
+    }
+    // merge the pixel's own reservoir, then the neighbours in order
+    Merge m{0.0f, 0u, false, rc};
+    uint32_t Mdom[KM + 1];
+    Mdom[0] = rc.M;
+    merge_in<GLOSSY>(m, g, rc, rc.M, 0.0f, pp.g_max);
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        const Res rq = load_res(in, qidx[j + 1]);
+        Mdom[j + 1] = use[j] ? rq.M : 0u;
+        if (use[j]) merge_in<GLOSSY>(m, g, rq, rq.M, uq[j], pp.g_max);
     }
     store_res(out, p, finish<GLOSSY>(sc, acc, m, g, Mdom, [&](int j) { return load_gb<GLOSSY>(gb, qidx[j]); }, pp));
 }
@@ -1200,6 +1272,18 @@ bool glossy_scene(const gi_scene *sc) { return (sc->options & GI_OPT_GLOSSY) != 
     } while (0)
 
 // kernel<LDS, GLOSSY> with both chosen at run time
+template <int KM, class... A>
+void launch_spatial(bool glossy, uint32_t lds, dim3 grid, hipStream_t st, A... a)
+{
+    if (glossy) {
+        if (lds) k_spatial<true, true, KM><<<grid, kBlock, lds, st>>>(a...);
+        else k_spatial<false, true, KM><<<grid, kBlock, 0, st>>>(a...);
+    } else {
+        if (lds) k_spatial<true, false, KM><<<grid, kBlock, lds, st>>>(a...);
+        else k_spatial<false, false, KM><<<grid, kBlock, 0, st>>>(a...);
+    }
+}
+
 #define GI_LAUNCH_LDS_G(kernel, glossy, grid, block, lds, stream, ...)                          \
     do {                                                                                      \
         if (glossy) GI_LAUNCH_LDS2(kernel, true, grid, block, lds, stream, __VA_ARGS__);       \
@@ -1342,9 +1426,13 @@ gi_status gi_resample_spatial(const gi_scene *scene, const gi_gbuffer *gb, const
     if (res_alias(out, in)) return GI_ERR_ALIAS;
     if (pass > 5) return GI_ERR_PARAM;
     if (W == 0 || H == 0) return GI_OK;
-    GI_LAUNCH_LDS_G(k_spatial, glossy_scene(scene), tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene,
-                    *gb, *in, *params,
-                  pass, *out, seed, frame);
+    // neighbour slots: 5 (the workloads' k) or GI_MAX_K
+    if (params->k <= 5u)
+        launch_spatial<5>(glossy_scene(scene), scene_lds(scene), striped_grid(W, H), S(stream), *scene, *gb, *in,
+                          *params, pass, *out, seed, frame);
+    else
+        launch_spatial<(int)GI_MAX_K>(glossy_scene(scene), scene_lds(scene), striped_grid(W, H), S(stream), *scene,
+                                      *gb, *in, *params, pass, *out, seed, frame);
     return launched();
 }
 
