@@ -28,6 +28,13 @@
  *  - Identical inputs, seed and frame give bit-identical outputs.
  *  - All arithmetic is FP32.  Random numbers come from Philox4x32-10 keyed
  *    by (seed) with counter (pixel or probe, frame, pass, block).
+ *  - Against a single-entry-point design with optional arguments, the
+ *    learned cache has its own entry points (gi_resample_initial_mlp,
+ *    gi_shade_mlp) with a caller workspace, the probe update reads one
+ *    volume and writes another (each probe reads its neighbours' previous
+ *    textures), shading takes seed and frame (the glossy recursion samples),
+ *    and precisions are chosen per buffer (G-buffer format, cache precision)
+ *    rather than by a general dtype argument.
  */
 #ifndef GI_H
 #define GI_H
@@ -436,7 +443,7 @@ gi_status gi_mlp_train_step(const gi_mlp *mlp, uint32_t n, const float *pos4, co
  * its scratch takes on every GPU the library runs on (from the code object's
  * load until the process ends). */
 #define GI_MLP_NOALLOC_MAX_BATCH 16384u
-#define GI_MLP_NOALLOC_SCRATCH_BYTES 36509440ull
+#define GI_MLP_NOALLOC_SCRATCH_BYTES 18355968ull
 
 /* gi_mlp_train_step without a workspace argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving or

@@ -2,18 +2,18 @@
 // operands, MFMA inference (BF16 and FP8 E4M3) and BF16 training (forward,
 // backward, ordered gradient reduction, Adam, usability state).
 //
-// Inference keeps the whole network in registers: each wave loads the 38
-// weight fragments of the 32x32x16 MFMA once and then streams tiles of 32
-// samples, the samples on the N side of every product, so a layer's
-// accumulators become the next layer's B operand without leaving the
-// registers (see the slot permutation in gi_mlp.hpp).
+// Inference keeps the network in registers and LDS: each wave loads the
+// weight fragments once and then streams tiles of 32 samples, the samples
+// on the N side of every product, so a layer's accumulators become the next
+// layer's B operand without leaving the registers (see the slot permutation
+// in gi_mlp.hpp).  BF16 runs on the 32x32x16 instruction, FP8 on the
+// 32x32x64 one.
 //
-// Training (2^14..2^16 samples per step, ~0.6 GFLOP) runs on the vector ALUs
-// with the operands in LDS: one workgroup per 32 samples computes the
-// forward pass, the loss gradient and the backward pass, and writes its
-// partial gradient; two more kernels sum the partials in a fixed order
-// (groups of 16 workgroups, then the groups), so the result does not depend
-// on scheduling.
+// Training (2^14..2^16 samples per step, ~0.6 GFLOP) runs on the matrix cores
+// as well: one workgroup per 64 samples computes the forward pass, the loss
+// gradient, the backward pass and its partial weight gradient; two more
+// kernels sum the partials in a fixed order (groups of 16 workgroups, then
+// the groups), so the result does not depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -33,8 +33,6 @@ typedef float f32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kInferBlock = 256;
-constexpr int kTrainS = 32;            // samples per training workgroup
-constexpr int kTrainBlock = 256;
 constexpr int kStats = 16;             // per-workgroup statistics after the gradient
 constexpr int kPartStride = 17792;     // >= kParams + kStats, multiple of 64
 constexpr int kHdr = 64;               // workspace header words
@@ -143,17 +141,46 @@ __device__ __forceinline__ uint32_t fp8_byte(float x)
     return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFFu;
 }
 
-// FP8 fragments: byte i = (f * 64 + lane) * 8 + v
+// FP8 operands for the K = 64 instruction (v_mfma_f32_32x32x64_f8f6f4):
+// lane l of a fragment holds row l % 32 of a 32-row output tile and the 32
+// consecutive K slots 32 (l / 32) + b, one byte each.  Nine such fragments
+// (byte (f * 64 + l) * 32 + b): f = 0, 1 layer 0's two tiles (slots = the
+// half-wave's features 0..31), f = 2 + 2 (L - 1) + t hidden layer L tile t,
+// f = 8 the output layer.  Then two K = 16 fragments of layer 0's tiles (byte
+// kFp8K16Off + (g * 64 + l) * 8 + v: features 32..38 of half l / 32, slot 7
+// zero).  Hidden slot k = 32 h + b takes unit 32 (b >> 4) + 8 ((b >> 2) & 3)
+// + 4 h + (b & 3): the previous layer's accumulator 4a + b' of tile t sits in
+// lane half h as unit 32 t + 8 a + 4 h + b', so byte b of a lane's operand is
+// simply accumulator b of the first tile, then of the second.
+constexpr int kFp8K64Frags = 9;
+constexpr int kFp8K16Off = kFp8K64Frags * 64 * 32;
+static_assert(kFp8K16Off + 2 * 64 * 8 <= kBiasOff, "FP8 operands fit the fragment area");
+
+__host__ __device__ constexpr int k64_unit(int h, int b)
+{
+    return 32 * (b >> 4) + 8 * ((b >> 2) & 3) + 4 * h + (b & 3);
+}
+
 __global__ void __launch_bounds__(256) k_mlp_prepare_fp8(gi_mlp m)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const InferSrc src = infer_src(m);
     if (i < kBiasSlots) write_bias(m, src, i);
-    if (i >= kFrags * 64 * 8) return;
-    const int f = i >> 9, l = (i >> 3) & 63, v = i & 7;
-    const int L = layer_of_frag(f), r = f - kFrag0[L];
-    const int t = r / kSteps[L], c = r % kSteps[L];
-    const int row = 32 * t + (l & 31), k = frag_column(L, c, l >> 5, v);
+    int L, row, k;
+    if (i < kFp8K16Off) {
+        const int f = i >> 11, l = (i >> 5) & 63, b = i & 31, h = l >> 5;
+        const int t = f < 2 ? f : (f < 8 ? (f - 2) & 1 : 0);
+        L = f < 2 ? 0 : (f < 8 ? 1 + ((f - 2) >> 1) : 4);
+        row = 32 * t + (l & 31);
+        k = L == 0 ? 39 * h + b : k64_unit(h, b);
+    } else if (i < kFp8K16Off + 2 * 64 * 8) {
+        const int j = i - kFp8K16Off, g = j >> 9, l = (j >> 3) & 63, v = j & 7;
+        L = 0;
+        row = 32 * g + (l & 31);
+        k = v < 7 ? 39 * (l >> 5) + 32 + v : -1;
+    } else {
+        return;
+    }
     float w = 0.0f;
     if (row < kOut[L] && k >= 0 && k < kIn[L]) w = src.p[kOffW[L] + row * kIn[L] + k] * src.scale / m.scales[L];
     reinterpret_cast<uint8_t *>(m.weights)[i] = (uint8_t)fp8_byte(w);
@@ -162,17 +189,6 @@ __global__ void __launch_bounds__(256) k_mlp_prepare_fp8(gi_mlp m)
 // --------------------------------------------------------------------------
 // inference
 // --------------------------------------------------------------------------
-template <int P>
-struct Frag;
-template <>
-struct Frag<GI_MLP_BF16> {
-    using T = bf16x8;
-};
-template <>
-struct Frag<GI_MLP_FP8> {
-    using T = long;
-};
-
 __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c)
 {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -221,22 +237,6 @@ __device__ __forceinline__ bf16x8 relu_operand(const f32x16 &a, int part)
     return __builtin_bit_cast(bf16x8, r);
 }
 
-// eight floats already within +-448 -> eight E4M3FN bytes
-__device__ __forceinline__ long to_fp8(f32x8 x)
-{
-    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
-    lo = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], lo, true);
-    int hi = __builtin_amdgcn_cvt_pk_fp8_f32(x[4], x[5], 0, false);
-    hi = __builtin_amdgcn_cvt_pk_fp8_f32(x[6], x[7], hi, true);
-    return (long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
-__device__ __forceinline__ f32x8 half_of(const f32x16 &a, int part)
-{
-    return part ? __builtin_shufflevector(a, a, 8, 9, 10, 11, 12, 13, 14, 15)
-                : __builtin_shufflevector(a, a, 0, 1, 2, 3, 4, 5, 6, 7);
-}
-
 // accumulators of a 32-row tile initialised with the bias of rows 8a+4h+b
 __device__ __forceinline__ f32x16 bias_tile(const float *b, int h)
 {
@@ -252,46 +252,18 @@ __device__ __forceinline__ f32x16 bias_tile(const float *b, int h)
     return c;
 }
 
-template <int P>
-__global__ void __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(P == GI_MLP_BF16 ? 3 : 4, P == GI_MLP_BF16 ? 3 : 4)))
-k_mlp_infer(gi_mlp m, uint32_t n, const float4 *pos,
-                                                           const float4 *nrm, float4 *out, int gate)
+__global__ void __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(3, 3)))
+k_mlp_infer_bf16(gi_mlp m, uint32_t n, const float4 *pos, const float4 *nrm, float4 *out, int gate)
 {
-    using FT = typename Frag<P>::T;
+    using FT = bf16x8;
     if (gate && !mlp_selected(m)) return;   // uniform over the grid
-    // FP8 scales (a non-positive or non-finite activation scale counts as 1):
-    // layer L's accumulator holds sum a8 w8 = z / (s_w s_a); its bias enters
-    // as b / (s_w s_a) and the next layer's operand is acc * (s_w s_a / s_a')
-    float kq[kLayers - 1];
-    float smul4 = 1.0f, in0 = 1.0f;
-    if (P == GI_MLP_FP8) {
-        float sa[kLayers];
-#pragma unroll
-        for (int L = 0; L < kLayers; ++L) {
-            sa[L] = m.scales[5 + L];
-            if (!(sa[L] > 0.0f && sa[L] < kInf)) sa[L] = 1.0f;
-        }
-#pragma unroll
-        for (int L = 0; L + 1 < kLayers; ++L) kq[L] = m.scales[L] * sa[L] / sa[L + 1];
-        in0 = 1.0f / sa[0];
-        smul4 = m.scales[4] * sa[4];
-    }
-    // biases (accumulator units): layers 0-3 at 64 L, layer 4 at 256 padded to 32 rows
+    // biases: layers 0-3 at 64 L, layer 4 at 256 padded to 32 rows
     __shared__ __attribute__((aligned(16))) float sb[kBiasSlots];
     const float *bias = reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(m.weights) + kBiasOff);
-    for (int i = threadIdx.x; i < kBiasSlots; i += kInferBlock) {
-        const int L = i < 256 ? i >> 6 : 4;
-        float b = bias[i];
-        if (P == GI_MLP_FP8) {
-            float sa = m.scales[5 + L];
-            if (!(sa > 0.0f && sa < kInf)) sa = 1.0f;
-            b = b / (m.scales[L] * sa);
-        }
-        sb[i] = b;
-    }
+    for (int i = threadIdx.x; i < kBiasSlots; i += kInferBlock) sb[i] = bias[i];
     // the fragments of layers 0 and 1 (18) stay in LDS and are re-read per
     // tile; the other 20 live in registers for the whole kernel (3 waves per
-    // SIMD for BF16, 4 for FP8, without spills)
+    // SIMD without spills)
     constexpr int kLdsFrags = 18, kRegFrags = kFrags - kLdsFrags;
     __shared__ FT wls[kLdsFrags * 64];
     const FT *wsrc = reinterpret_cast<const FT *>(m.weights);
@@ -317,8 +289,8 @@ k_mlp_infer(gi_mlp m, uint32_t n, const float4 *pos,
 
     for (uint32_t tile = wave; tile < ntiles; tile += nwaves) {
         // the LDS fragments and biases are re-read every tile: hoisted out of
-        // the loop they would take 36 (FP8) to 72 (BF16) more registers
-        // plus the bias tiles, and cost waves (FP8: 341 registers, 1 wave)
+        // the loop they would take 72 more registers plus the bias tiles,
+        // and cost waves (238 registers, 2 waves)
         asm volatile("" ::: "memory");
         const uint32_t idx = tile * 32u + (uint32_t)s;
         const bool ok = idx < n;
@@ -345,14 +317,7 @@ k_mlp_infer(gi_mlp m, uint32_t n, const float4 *pos,
             f32x8 x;
 #pragma unroll
             for (int v = 0; v < 8; ++v) x[v] = feat[8 * c + v];
-            FT b;
-            if constexpr (P == GI_MLP_BF16) {
-                b = to_bf16(x);
-            } else {
-#pragma unroll
-                for (int v = 0; v < 8; ++v) x[v] = __builtin_amdgcn_fmed3f(x[v] * in0, -kFp8Max, kFp8Max);
-                b = to_fp8(x);
-            }
+            const FT b = to_bf16(x);
             acc0 = mfma(frag(c), b, acc0);
             acc1 = mfma(frag(5 + c), b, acc1);
         }
@@ -361,17 +326,7 @@ k_mlp_infer(gi_mlp m, uint32_t n, const float4 *pos,
         for (int L = 1; L < kLayers; ++L) {
             FT bop[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if constexpr (P == GI_MLP_BF16) {
-                    bop[c] = relu_operand(c >> 1 ? acc1 : acc0, c & 1);
-                } else {
-                    f32x8 x = half_of(c >> 1 ? acc1 : acc0, c & 1);
-                    // ReLU, rescale to the next layer's input scale, saturate
-#pragma unroll
-                    for (int v = 0; v < 8; ++v) x[v] = __builtin_amdgcn_fmed3f(x[v] * kq[L - 1], 0.0f, kFp8Max);
-                    bop[c] = to_fp8(x);
-                }
-            }
+            for (int c = 0; c < 4; ++c) bop[c] = relu_operand(c >> 1 ? acc1 : acc0, c & 1);
             const int f0 = kFrag0[L];
             if (L < kLayers - 1) {
                 acc0 = bias_tile(sb + 64 * L, h);
@@ -389,51 +344,150 @@ k_mlp_infer(gi_mlp m, uint32_t n, const float4 *pos,
         }
         // output rows 0..2 sit in accumulators 0..2 of the lower half-wave
         if (ok && h == 0) {
-            out[idx] = make_float4(acc0[0] * smul4, acc0[1] * smul4, acc0[2] * smul4, 0.0f);
+            out[idx] = make_float4(acc0[0], acc0[1], acc0[2], 0.0f);
         }
+    }
+}
+
+// FP8 inference on the K = 64 instruction (twice the K = 16 instruction's
+// rate): per 32-sample tile, layer 0 is one K = 64 product (features 0..31 of
+// each half-wave) plus one K = 16 product (features 32..38) per output tile,
+// hidden layers one K = 64 product per tile, the output layer one.  Operands
+// are E4M3FN x / s with the per-layer scales of the generic kernel.  Layer
+// 0's fragments stay in LDS, the seven others in registers.
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x16 mfma64(i32x8 a, i32x8 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+}
+
+// 16 floats (already scaled and clamped to [-448, 448]) -> 16 E4M3FN bytes
+__device__ __forceinline__ void pack_fp8x16(const float *x, int *dst)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[4 * q], x[4 * q + 1], 0, false);
+        dst[q] = __builtin_amdgcn_cvt_pk_fp8_f32(x[4 * q + 2], x[4 * q + 3], w, true);
+    }
+}
+
+// accumulators of both tiles -> the next layer's K = 64 operand: ReLU, scale
+// to the next layer's input scale, saturate
+__device__ __forceinline__ i32x8 relu_fp8_operand(const f32x16 &a0, const f32x16 &a1, float kq)
+{
+    float x[16];
+    i32x8 r;
+    int *rp = reinterpret_cast<int *>(&r);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) x[v] = __builtin_amdgcn_fmed3f(a0[v] * kq, 0.0f, kFp8Max);
+    pack_fp8x16(x, rp);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) x[v] = __builtin_amdgcn_fmed3f(a1[v] * kq, 0.0f, kFp8Max);
+    pack_fp8x16(x, rp + 4);
+    return r;
+}
+
+__global__ void __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_mlp_infer_fp8(gi_mlp m, uint32_t n, const float4 *pos, const float4 *nrm, float4 *out, int gate)
+{
+    if (gate && !mlp_selected(m)) return;   // uniform over the grid
+    float sa[kLayers];
+#pragma unroll
+    for (int L = 0; L < kLayers; ++L) {
+        sa[L] = m.scales[5 + L];
+        if (!(sa[L] > 0.0f && sa[L] < kInf)) sa[L] = 1.0f;
+    }
+    float kq[kLayers - 1];
+#pragma unroll
+    for (int L = 0; L + 1 < kLayers; ++L) kq[L] = m.scales[L] * sa[L] / sa[L + 1];
+    const float in0 = 1.0f / sa[0], smul4 = m.scales[4] * sa[4];
+    __shared__ __attribute__((aligned(16))) float sb[kBiasSlots];
+    const float *bias = reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(m.weights) + kBiasOff);
+    for (int i = threadIdx.x; i < kBiasSlots; i += kInferBlock) {
+        const int L = i < 256 ? i >> 6 : 4;
+        sb[i] = bias[i] / (m.scales[L] * sa[L]);
+    }
+    // layer 0's fragments in LDS: two K = 64 (32 B per lane), two K = 16 (8 B)
+    __shared__ i32x8 w0[2 * 64];
+    __shared__ long w0b[2 * 64];
+    const i32x8 *w64 = reinterpret_cast<const i32x8 *>(m.weights);
+    const long *w16 = reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(m.weights) + kFp8K16Off);
+    for (int i = threadIdx.x; i < 2 * 64; i += kInferBlock) {
+        w0[i] = w64[i];
+        w0b[i] = w16[i];
+    }
+    __syncthreads();
+    const int l = threadIdx.x & 63, s = l & 31, h = l >> 5;
+    i32x8 wf[kFp8K64Frags - 2];
+#pragma unroll
+    for (int f = 0; f < kFp8K64Frags - 2; ++f) wf[f] = w64[(2 + f) * 64 + l];
+
+    float lo[3], ext[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = h ? 0.0f : m.pos_lo[a];
+        ext[a] = h ? 1.0f : m.pos_hi[a] - m.pos_lo[a];
+    }
+    const float4 *src = h ? nrm : pos;
+    const uint32_t wave = (blockIdx.x * kInferBlock + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * kInferBlock) >> 6;
+    const uint32_t ntiles = (n + 31u) / 32u;
+
+    for (uint32_t tile = wave; tile < ntiles; tile += nwaves) {
+        asm volatile("" ::: "memory");   // re-read layer 0's fragments and the biases per tile
+        const uint32_t idx = tile * 32u + (uint32_t)s;
+        const bool ok = idx < n;
+        const float4 in = ok ? src[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float feat[40];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float v = (comp(in, a) - lo[a]) / ext[a];
+            feat[13 * a] = v;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                const float x = __builtin_amdgcn_fractf(v * (float)(1 << j) * 0.5f);
+                feat[13 * a + 1 + 2 * j] = sin_rev(x);
+                feat[13 * a + 2 + 2 * j] = cos_rev(x);
+            }
+        }
+        feat[39] = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 40; ++v) feat[v] = __builtin_amdgcn_fmed3f(feat[v] * in0, -kFp8Max, kFp8Max);
+        i32x8 b64;
+        int *bp = reinterpret_cast<int *>(&b64);
+        pack_fp8x16(feat, bp);
+        pack_fp8x16(feat + 16, bp + 4);
+        long b16;
+        {
+            int lo2 = __builtin_amdgcn_cvt_pk_fp8_f32(feat[32], feat[33], 0, false);
+            lo2 = __builtin_amdgcn_cvt_pk_fp8_f32(feat[34], feat[35], lo2, true);
+            int hi2 = __builtin_amdgcn_cvt_pk_fp8_f32(feat[36], feat[37], 0, false);
+            hi2 = __builtin_amdgcn_cvt_pk_fp8_f32(feat[38], feat[39], hi2, true);
+            b16 = (long)(((uint64_t)(uint32_t)hi2 << 32) | (uint32_t)lo2);
+        }
+        f32x16 acc0 = bias_tile(sb, h), acc1 = bias_tile(sb + 32, h);
+        acc0 = mfma64(w0[l], b64, acc0);
+        acc1 = mfma64(w0[64 + l], b64, acc1);
+        acc0 = mfma(w0b[l], b16, acc0);
+        acc1 = mfma(w0b[64 + l], b16, acc1);
+#pragma unroll
+        for (int L = 1; L < kLayers; ++L) {
+            const i32x8 bop = relu_fp8_operand(acc0, acc1, kq[L - 1]);
+            if (L < kLayers - 1) {
+                acc0 = mfma64(wf[2 * (L - 1)], bop, bias_tile(sb + 64 * L, h));
+                acc1 = mfma64(wf[2 * (L - 1) + 1], bop, bias_tile(sb + 64 * L + 32, h));
+            } else {
+                acc0 = mfma64(wf[6], bop, bias_tile(sb + 256, h));
+            }
+        }
+        if (ok && h == 0) out[idx] = make_float4(acc0[0] * smul4, acc0[1] * smul4, acc0[2] * smul4, 0.0f);
     }
 }
 
 // --------------------------------------------------------------------------
 // training
 // --------------------------------------------------------------------------
-// LDS weights: row-major [u][k] with row stride in+1 (conflict-free both for
-// lanes along u and along k); the layer offsets coincide with the flat
-// parameter offsets of the weights.
-constexpr int kWStride[kLayers] = {79, 65, 65, 65, 65};
-// layer inputs: [s][k] with stride 80 (layer 0) or 64
-constexpr int kAOff[kLayers] = {0, 32 * 80, 32 * 80 + 2048, 32 * 80 + 4096, 32 * 80 + 6144};
-constexpr int kAStride[kLayers] = {80, 64, 64, 64, 64};
-constexpr int kASize = 32 * 80 + 4 * 2048;
-
-__device__ __forceinline__ float block_sum(float v, float *red)
-{
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-    for (int o = kTrainBlock / 2; o > 0; o >>= 1) {
-        if (t < o) red[t] += red[t + o];
-        __syncthreads();
-    }
-    float r = red[0];
-    __syncthreads();
-    return r;
-}
-
-__device__ __forceinline__ float block_max(float v, float *red)
-{
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-    for (int o = kTrainBlock / 2; o > 0; o >>= 1) {
-        if (t < o) red[t] = fmaxf(red[t], red[t + o]);
-        __syncthreads();
-    }
-    float r = red[0];
-    __syncthreads();
-    return r;
-}
-
 // number of valid samples (target.w != 0) -> hdr[0]
 __global__ void __launch_bounds__(1024) k_mlp_count(uint32_t n, const float4 *tgt, uint32_t *hdr)
 {
@@ -450,161 +504,320 @@ __global__ void __launch_bounds__(1024) k_mlp_count(uint32_t n, const float4 *tg
     if (t == 0) hdr[0] = red[0];
 }
 
-__global__ void __launch_bounds__(kTrainBlock) k_mlp_fwdbwd(gi_mlp m, uint32_t n, const float4 *pos,
-                                                            const float4 *nrm, const float4 *tgt,
-                                                            const float4 *qp, const uint32_t *hdr, float *part)
+// --------------------------------------------------------------------------
+// training on the matrix cores
+// --------------------------------------------------------------------------
+// One workgroup of two waves takes kMS = 64 samples, each wave a tile of 32
+// samples on the N side of the 32x32x16 BF16 product, as in inference:
+// forward products W x (weight fragments of the master parameters as the A
+// operand), the activations handed from layer to layer in registers, and
+// each layer's input also written to LDS unit-major ([unit][sample]); the
+// backward products dA = W^T g take the transposed fragments, g handed down
+// in registers the same way (the ReLU masks kept as bits from the forward
+// pass); the weight gradients dW = g^T a sum over the 64 samples with the
+// samples on the K side, both operands read from LDS.  Every operand is
+// rounded to BF16 and products accumulate in FP32, as in the VALU form.
+constexpr int kMS = 64;                 // samples per workgroup
+constexpr int kMBlock = 128;            // two waves
+constexpr int kFwdFrags = kFrags;       // 38 forward fragments (inference layout, master parameters)
+constexpr int kBwdFrag0[kLayers] = {0, 0, 8, 16, 24};   // backward fragments of layers 1..4 (W^T)
+constexpr int kBwdFrags = 26;
+constexpr int kTrainFragBytes = (kFwdFrags + kBwdFrags) * 64 * 16;
+
+// backward fragment f of layer L (1..3: 2 row tiles x 4 k-steps; 4: 2 x 1):
+// lane l holds rows k = 32 t + l % 32 of W_L^T, K slots 16 c + 8 h + v
+// taking output unit swap23(16 c + 8 h + v) (the layout the previous
+// backward product leaves in its accumulators); layer 4 takes unit v of
+// the lower half-wave (its 3 outputs) and zero elsewhere
+__device__ __forceinline__ float bwd_weight(const float *P, int f, int l, int v)
 {
-    __shared__ float sW[kParams];
-    __shared__ float sA[kASize];
-    __shared__ float sG[2][kTrainS * 64];
-    __shared__ float sGr[kTrainS * 64];
-    __shared__ float sO[kTrainS * 4], sT[kTrainS * 4], sQ[kTrainS * 4];
-    __shared__ float sX[kTrainS * 8];
-    __shared__ int sValid[kTrainS];
-    __shared__ float red[kTrainBlock];
+    const int L = f < 8 ? 1 : (f < 16 ? 2 : (f < 24 ? 3 : 4));
+    const int r = f - kBwdFrag0[L];
+    const int t = L < 4 ? r >> 2 : r, c = L < 4 ? r & 3 : 0, h = l >> 5;
+    const int k = 32 * t + (l & 31);
+    const int u = L < 4 ? swap23(16 * c + 8 * h + v) : (h == 0 && v < 3 ? v : -1);
+    if (u < 0 || u >= kOut[L] || k >= kIn[L]) return 0.0f;
+    return P[kOffW[L] + u * kIn[L] + k];
+}
 
-    const int t = threadIdx.x;
-    const uint32_t s0 = blockIdx.x * kTrainS;
+// forward and backward BF16 fragments of the master parameters, one element per thread
+__global__ void __launch_bounds__(256) k_mlp_train_frags(gi_mlp m, __bf16 *frags)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= (kFwdFrags + kBwdFrags) * 64 * 8) return;
+    const int f = i >> 9, l = (i >> 3) & 63, v = i & 7;
+    float w = 0.0f;
+    if (f < kFwdFrags) {
+        const int L = layer_of_frag(f), r = f - kFrag0[L];
+        const int t = r / kSteps[L], c = r % kSteps[L];
+        const int row = 32 * t + (l & 31), k = frag_column(L, c, l >> 5, v);
+        if (row < kOut[L] && k >= 0 && k < kIn[L]) w = m.params[kOffW[L] + row * kIn[L] + k];
+    } else {
+        w = bwd_weight(m.params, f - kFwdFrags, l, v);
+    }
+    frags[i] = (__bf16)w;
+}
+
+// sum over the 32 lanes of each half-wave (fixed butterfly order)
+__device__ __forceinline__ float half_sum(float v)
+{
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float half_max(float v)
+{
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// the 16 accumulators of a tile as BF16 operand halves (no ReLU)
+__device__ __forceinline__ bf16x8 bf16_operand(const f32x16 &a, int part)
+{
+    u32x4 r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] = pk_bf16(a[8 * part + 2 * i], a[8 * part + 2 * i + 1]);
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+__global__ void __launch_bounds__(kMBlock) k_mlp_fwdbwd_mfma(gi_mlp m, uint32_t n, const float4 *pos,
+                                                            const float4 *nrm, const float4 *tgt,
+                                                            const float4 *qp, const uint32_t *hdr,
+                                                            const bf16x8 *frags, float *part)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 sX[80 * kMS];       // layer 0 input [feature][sample]
+    __shared__ __attribute__((aligned(16))) __bf16 sA[4 * 64 * kMS];   // layer 1..4 inputs [unit][sample]
+    __shared__ __attribute__((aligned(16))) __bf16 sG[64 * kMS];       // BF16 gradient [unit][sample]
+    __shared__ float sDb[2][64];                                       // bias gradient per wave
+    __shared__ float sSt[2][kStats];
+
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, s = l & 31, h = l >> 5;
+    const int sl = 32 * wv + s;                                        // sample within the workgroup
+    const uint32_t idx = blockIdx.x * kMS + sl;
     float *pw = part + (size_t)blockIdx.x * kPartStride;
+    const bf16x8 *bfr = frags + kFwdFrags * 64;
 
-    // weights, rounded to BF16
-    for (int L = 0; L < kLayers; ++L) {
-        const int in = kIn[L], cnt = in * kOut[L];
-        for (int r = t; r < cnt; r += kTrainBlock) {
-            const int u = r / in, k = r - u * in;
-            sW[kOffW[L] + u * kWStride[L] + k] = bf16_round(m.params[kOffW[L] + r]);
-        }
-    }
-    // per-sample inputs
-    if (t < kTrainS) {
-        const uint32_t i = s0 + t;
-        const bool in_range = i < n;
-        const float4 tg = in_range ? tgt[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        const bool valid = in_range && tg.w != 0.0f;
-        sValid[t] = valid ? 1 : 0;
-        const float4 p = valid ? pos[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        const float4 nn = valid ? nrm[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        const float4 q = (valid && qp) ? qp[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        for (int a = 0; a < 3; ++a) {
-            sX[8 * t + a] = (comp(p, a) - m.pos_lo[a]) / (m.pos_hi[a] - m.pos_lo[a]);
-            sX[8 * t + 3 + a] = comp(nn, a);
-            sT[4 * t + a] = comp(tg, a);
-            sQ[4 * t + a] = comp(q, a);
-        }
-    }
-    __syncthreads();
+    // inputs and encoding: lanes 0-31 the position's 39 features, 32-63 the normal's
+    const float4 tg = idx < n ? tgt[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const bool valid = idx < n && tg.w != 0.0f;
+    const float4 in = valid ? (h ? nrm[idx] : pos[idx]) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float feat[40];
     float amax[kLayers] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    // encoding (precise sin(pi x) / cos(pi x), exact range reduction)
-    for (int e = t; e < kTrainS * 80; e += kTrainBlock) {
-        const int s = e / 80, f = e - s * 80;
-        float x = 0.0f;
-        if (f < 78 && sValid[s]) {
-            const int i = f / 13, ee = f - 13 * i;
-            const float v = sX[8 * s + i];
-            if (ee == 0) x = v;
-            else if (ee & 1) x = sinpif(ldexpf(v, (ee - 1) >> 1));
-            else x = cospif(ldexpf(v, (ee - 2) >> 1));
-            amax[0] = fmaxf(amax[0], fabsf(x));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float v = h ? comp(in, a) : (comp(in, a) - m.pos_lo[a]) / (m.pos_hi[a] - m.pos_lo[a]);
+        feat[13 * a] = v;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            feat[13 * a + 1 + 2 * j] = sinpif(ldexpf(v, j));
+            feat[13 * a + 2 + 2 * j] = cospif(ldexpf(v, j));
         }
-        sA[s * 80 + f] = bf16_round(x);
     }
-    __syncthreads();
+    feat[39] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 39; ++j) {
+        if (!valid) feat[j] = 0.0f;
+        amax[0] = fmaxf(amax[0], fabsf(feat[j]));
+        sX[(39 * h + j) * kMS + sl] = (__bf16)feat[j];
+    }
+    if (h) {
+        sX[78 * kMS + sl] = (__bf16)0.0f;
+        sX[79 * kMS + sl] = (__bf16)0.0f;
+    }
 
-    // forward, hidden layers: thread (unit u, samples sg + 4i)
-    const int u = t & 63, sg = t >> 6;
-    for (int L = 0; L < kLayers - 1; ++L) {
-        const int in = kIn[L];
-        const float *A = sA + kAOff[L];
-        const float *Wr = sW + kOffW[L] + u * kWStride[L];
-        float acc[8];
+    // forward
+    uint32_t mask[kLayers - 1];
+    f32x16 acc0, acc1;
+    {
+        acc0 = f32x16{};
+        acc1 = f32x16{};
 #pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
-        for (int k = 0; k < in; ++k) {
-            const float w = Wr[k];
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int i = 0; i < 8; ++i) acc[i] = fmaf(A[(sg + 4 * i) * kAStride[L] + k], w, acc[i]);
+            for (int b = 0; b < 4; ++b) {
+                acc0[4 * a + b] = m.params[kOffB[0] + 8 * a + 4 * h + b];
+                acc1[4 * a + b] = m.params[kOffB[0] + 32 + 8 * a + 4 * h + b];
+            }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            f32x8 x;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) x[v] = feat[8 * c + v];
+            const bf16x8 b = to_bf16(x);
+            acc0 = mfma(frags[c * 64 + l], b, acc0);
+            acc1 = mfma(frags[(5 + c) * 64 + l], b, acc1);
         }
-        const float b = m.params[kOffB[L] + u];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int s = sg + 4 * i;
-            const float a = fmaxf(acc[i] + b, 0.0f);
-            if (sValid[s]) amax[L + 1] = fmaxf(amax[L + 1], a);
-            sA[kAOff[L + 1] + s * 64 + u] = bf16_round(a);
-        }
-        __syncthreads();
     }
-    // output layer and loss gradient: thread (sample s, channel c)
+#pragma unroll
+    for (int L = 1; L < kLayers; ++L) {
+        // layer L-1's ReLU output: kept as the ReLU mask and written to LDS as layer L's input
+        uint32_t mk = 0u;
+        float mx = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const float z = t ? acc1[i] : acc0[i];
+                const float a = fmaxf(z, 0.0f);
+                mk |= (z > 0.0f ? 1u : 0u) << (16 * t + i);
+                mx = fmaxf(mx, a);
+                const int k = 32 * t + 8 * (i >> 2) + 4 * h + (i & 3);
+                sA[((L - 1) * 64 + k) * kMS + sl] = (__bf16)a;
+            }
+        mask[L - 1] = mk;
+        if (valid) amax[L] = mx;
+        bf16x8 bop[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bop[c] = relu_operand(c >> 1 ? acc1 : acc0, c & 1);
+        const int f0 = kFrag0[L];
+        if (L < kLayers - 1) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    acc0[4 * a + b] = m.params[kOffB[L] + 8 * a + 4 * h + b];
+                    acc1[4 * a + b] = m.params[kOffB[L] + 32 + 8 * a + 4 * h + b];
+                }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                acc0 = mfma(frags[(f0 + c) * 64 + l], bop[c], acc0);
+                acc1 = mfma(frags[(f0 + 4 + c) * 64 + l], bop[c], acc1);
+            }
+        } else {
+            acc0 = f32x16{};
+#pragma unroll
+            for (int b = 0; b < 3; ++b) acc0[b] = h ? 0.0f : m.params[kOffB[4] + b];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc0 = mfma(frags[(f0 + c) * 64 + l], bop[c], acc0);
+        }
+    }
+    // loss gradient (lower half-wave: outputs 0..2 in accumulators 0..2)
     const float ntot = (float)max(hdr[0], 1u) * 3.0f;
     float loss = 0.0f, enum_ = 0.0f, eden = 0.0f, nonfinite = 0.0f;
-    if (t < kTrainS * 3) {
-        const int s = t / 3, c = t - 3 * s;
-        const float *A = sA + kAOff[4] + s * 64;
-        const float *Wr = sW + kOffW[4] + c * kWStride[4];
-        float z = 0.0f;
-        for (int k = 0; k < 64; ++k) z = fmaf(A[k], Wr[k], z);
-        z += m.params[kOffB[4] + c];
-        sO[4 * s + c] = z;
-        float g = 0.0f;
-        if (sValid[s]) {
-            const float den = z * z + 0.01f, d = z - sT[4 * s + c];
-            g = 2.0f * d / den / ntot;
-            loss = d * d / den;
-            const float q = sQ[4 * s + c];
-            enum_ = fabsf(fmaxf(z, 0.0f) - q);
-            eden = q + 0.01f;
-            nonfinite = __builtin_isfinite(z) ? 0.0f : 1.0f;
-        }
-        sG[0][s * 64 + c] = g;
-        sGr[s * 64 + c] = bf16_round(g);
-    }
-    {
-        const float st[4] = {loss, enum_, eden, nonfinite};
-        for (int j = 0; j < 4; ++j) {
-            const float r = block_sum(st[j], red);
-            if (t == 0) pw[kParams + j] = r;
-        }
-        for (int L = 0; L < kLayers; ++L) {
-            const float r = block_max(amax[L], red);
-            if (t == 0) pw[kParams + kStAmax0 + L] = r;
-        }
-    }
-    __syncthreads();
-
-    // backward
-    int cur = 0;
-    for (int L = kLayers - 1; L >= 0; --L) {
-        const int in = kIn[L], out = kOut[L];
-        const float *A = sA + kAOff[L];
-        const int as = kAStride[L];
-        if (t < out) {
-            float db = 0.0f;
-            for (int s = 0; s < kTrainS; ++s) db += sG[cur][s * 64 + t];
-            pw[kOffB[L] + t] = db;
-        }
-        for (int r = t; r < in * out; r += kTrainBlock) {
-            const int uu = r / in, k = r - uu * in;
-            float dw = 0.0f;
-            for (int s = 0; s < kTrainS; ++s) dw = fmaf(sGr[s * 64 + uu], A[s * as + k], dw);
-            pw[kOffW[L] + r] = dw;
-        }
-        if (L == 0) break;
-        // gradient w.r.t. this layer's input (64 units), masked by the ReLU of the previous layer
-        {
-            const int k = t & 63;
-            const float *Wc = sW + kOffW[L] + k;
+    float g[3] = {0.0f, 0.0f, 0.0f};
+    if (h == 0) {
+        const float4 q = (valid && qp) ? qp[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int s = sg + 4 * i;
-                float g = 0.0f;
-                for (int uu = 0; uu < out; ++uu) g = fmaf(sGr[s * 64 + uu], Wc[uu * kWStride[L]], g);
-                sG[cur ^ 1][s * 64 + k] = A[s * 64 + k] > 0.0f ? g : 0.0f;
+        for (int c = 0; c < 3; ++c) {
+            const float z = acc0[c];
+            if (valid) {
+                const float den = z * z + 0.01f, d = z - comp(tg, c);
+                g[c] = 2.0f * d / den / ntot;
+                loss += d * d / den;
+                enum_ += fabsf(fmaxf(z, 0.0f) - comp(q, c));
+                eden += comp(q, c) + 0.01f;
+                nonfinite += __builtin_isfinite(z) ? 0.0f : 1.0f;
             }
         }
+    }
+    // statistics of the workgroup: per half-wave, then the two waves in order
+    {
+        float st[4 + kLayers] = {loss, enum_, eden, nonfinite};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) st[j] = half_sum(st[j]);
+#pragma unroll
+        for (int L = 0; L < kLayers; ++L) st[4 + L] = half_max(amax[L]);
+#pragma unroll
+        for (int j = 0; j < 4 + kLayers; ++j) {
+            // lane 0 holds the lower half's value, lane 32 the upper half's
+            const float o = __shfl(st[j], 32, 64);
+            if (l == 0) sSt[wv][j] = j < 4 ? st[j] + o : fmaxf(st[j], o);
+        }
+    }
+
+    // backward: layer 4 first (3 output units)
+    f32x16 g0, g1;     // this lane's gradient of the current layer's pre-activation
+    for (int L = kLayers - 1; L >= 0; --L) {
+        const int out = kOut[L], in = kIn[L];
+        // bias gradient (unrounded FP32 g) and the BF16 gradient in LDS [unit][sample]
+        if (L == kLayers - 1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float sum = half_sum(g[c]);
+                if (l == 0) sDb[wv][c] = sum;
+            }
+            if (h == 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sG[c * kMS + sl] = (__bf16)g[c];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const float v = t ? g1[i] : g0[i];
+                    const int u = 32 * t + 8 * (i >> 2) + 4 * h + (i & 3);
+                    const float sum = half_sum(v);
+                    if (s == 0) sDb[wv][u] = sum;
+                    sG[u * kMS + sl] = (__bf16)v;
+                }
+        }
         __syncthreads();
-        for (int e = t; e < kTrainS * 64; e += kTrainBlock) sGr[e] = bf16_round(sG[cur ^ 1][e]);
-        __syncthreads();
-        cur ^= 1;
+        if (threadIdx.x < out) pw[kOffB[L] + threadIdx.x] = sDb[0][threadIdx.x] + sDb[1][threadIdx.x];
+        // dW = g^T a over the workgroup's 64 samples: output tiles (unit tile i, input tile j)
+        const __bf16 *Ain = L == 0 ? sX : sA + (L - 1) * 64 * kMS;
+        const int ti = (out + 31) / 32, tj = (in + 31) / 32;
+        for (int tile = wv; tile < ti * tj; tile += 2) {
+            const int i0 = 32 * (tile / tj), j0 = 32 * (tile % tj);
+            const int ur = i0 + (l & 31), kr = j0 + (l & 31);
+            f32x16 d = f32x16{};
+#pragma unroll
+            for (int c = 0; c < kMS / 16; ++c) {
+                const int s0 = 16 * c + 8 * h;
+                const bf16x8 a = ur < out ? *reinterpret_cast<const bf16x8 *>(sG + ur * kMS + s0) : bf16x8{};
+                const bf16x8 b = kr < (L == 0 ? 80 : in) ? *reinterpret_cast<const bf16x8 *>(Ain + kr * kMS + s0)
+                                                         : bf16x8{};
+                d = mfma(a, b, d);
+            }
+            // accumulator 4a + b: row (unit) i0 + 8a + 4h + b, column (input) kr
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int u = i0 + 8 * (i >> 2) + 4 * h + (i & 3);
+                if (u < out && kr < in) pw[kOffW[L] + u * in + kr] = d[i];
+            }
+        }
+        if (L == 0) break;
+        // dA = W^T g: the BF16 gradient from registers as the B operand
+        bf16x8 bop[4];
+        int nc;
+        if (L == kLayers - 1) {
+            f32x8 x = f32x8{};
+            if (h == 0) {
+                x[0] = g[0];
+                x[1] = g[1];
+                x[2] = g[2];
+            }
+            bop[0] = to_bf16(x);
+            nc = 1;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) bop[c] = bf16_operand(c >> 1 ? g1 : g0, c & 1);
+            nc = 4;
+        }
+        f32x16 d0 = f32x16{}, d1 = f32x16{};
+        const int fb = kBwdFrag0[L];
+        for (int c = 0; c < nc; ++c) {
+            const int f0 = L == kLayers - 1 ? fb : fb + c, f1 = L == kLayers - 1 ? fb + 1 : fb + 4 + c;
+            d0 = mfma(bfr[f0 * 64 + l], bop[c], d0);
+            d1 = mfma(bfr[f1 * 64 + l], bop[c], d1);
+        }
+        // ReLU mask of layer L-1's output
+        const uint32_t mk = mask[L - 1];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            g0[i] = (mk >> i) & 1u ? d0[i] : 0.0f;
+            g1[i] = (mk >> (16 + i)) & 1u ? d1[i] : 0.0f;
+        }
+        __syncthreads();     // sG and sDb are rewritten by the next layer
+    }
+    __syncthreads();
+    if (threadIdx.x < kStats) {
+        // slots 0-3 sums (loss, error numerator and denominator, non-finite outputs), 4-8 the
+        // activation amax of every layer input, the rest unused (zero)
+        const int j = threadIdx.x;
+        const float v = j < 4 ? sSt[0][j] + sSt[1][j] : (j < 4 + kLayers ? fmaxf(sSt[0][j], sSt[1][j]) : 0.0f);
+        pw[kParams + j] = v;
     }
 }
 
@@ -705,9 +918,12 @@ __global__ void __launch_bounds__(256) k_mlp_state(gi_mlp m, uint32_t t)
     }
 }
 
-constexpr uint32_t train_wgs(uint32_t n) { return (n + kTrainS - 1) / kTrainS; }
+constexpr uint32_t train_wgs(uint32_t n) { return (n + kMS - 1) / kMS; }
 
-constexpr uint64_t train_bytes(uint32_t n) { return 4ull * (kHdr + (uint64_t)kPartStride * (1ull + train_wgs(n))); }
+// workspace: header, gradient, one partial gradient per workgroup, then the
+// BF16 fragments of the master parameters the matrix-core kernel reads
+constexpr uint64_t train_frag_off(uint32_t n) { return 4ull * (kHdr + (uint64_t)kPartStride * (1ull + train_wgs(n))); }
+constexpr uint64_t train_bytes(uint32_t n) { return train_frag_off(n) + kTrainFragBytes; }
 
 // Scratch of the allocation-free training step (gi_mlp_train_step_noalloc):
 // the workspace of a GI_MLP_NOALLOC_MAX_BATCH-sample step, one copy per GPU,
@@ -765,11 +981,15 @@ gi_status grad_launch(const gi_mlp &m, uint32_t n, const float *pos4, const floa
     float *part = reinterpret_cast<float *>(ws) + kHdr + kPartStride;
     const uint32_t nwg = train_wgs(n);
     k_mlp_count<<<1, 1024, 0, st>>>(n, reinterpret_cast<const float4 *>(target4), hdr);
-    if (nwg)
-        k_mlp_fwdbwd<<<nwg, kTrainBlock, 0, st>>>(m, n, reinterpret_cast<const float4 *>(pos4),
-                                                  reinterpret_cast<const float4 *>(nrm4),
-                                                  reinterpret_cast<const float4 *>(target4),
-                                                  reinterpret_cast<const float4 *>(qprobe4), hdr, part);
+    __bf16 *frags = reinterpret_cast<__bf16 *>(reinterpret_cast<uint8_t *>(ws) + train_frag_off(n));
+    if (nwg) {
+        k_mlp_train_frags<<<((kFwdFrags + kBwdFrags) * 64 * 8 + 255) / 256, 256, 0, st>>>(m, frags);
+        k_mlp_fwdbwd_mfma<<<nwg, kMBlock, 0, st>>>(m, n, reinterpret_cast<const float4 *>(pos4),
+                                                   reinterpret_cast<const float4 *>(nrm4),
+                                                   reinterpret_cast<const float4 *>(target4),
+                                                   reinterpret_cast<const float4 *>(qprobe4), hdr,
+                                                   reinterpret_cast<const bf16x8 *>(frags), part);
+    }
     const uint32_t cols = (kParams + kStats + 255) / 256;
     if (nwg) k_mlp_reduce1<<<dim3(cols, (nwg + kGroup - 1) / kGroup), 256, 0, st>>>(nwg, part);
     k_mlp_reduce<<<cols, 256, 0, st>>>(m, nwg, part, grad, hdr);
@@ -810,9 +1030,9 @@ gi_status mlp_infer_launch(const gi_mlp &m, uint32_t n, const float4 *pos, const
     const uint32_t tiles = (n + 31u) / 32u;
     const uint32_t blocks = std::min<uint32_t>((tiles + 3u) / 4u, 2048u);
     if (m.precision == GI_MLP_BF16)
-        k_mlp_infer<GI_MLP_BF16><<<blocks, kInferBlock, 0, st>>>(m, n, pos, nrm, out, gate ? 1 : 0);
+        k_mlp_infer_bf16<<<blocks, kInferBlock, 0, st>>>(m, n, pos, nrm, out, gate ? 1 : 0);
     else
-        k_mlp_infer<GI_MLP_FP8><<<blocks, kInferBlock, 0, st>>>(m, n, pos, nrm, out, gate ? 1 : 0);
+        k_mlp_infer_fp8<<<blocks, kInferBlock, 0, st>>>(m, n, pos, nrm, out, gate ? 1 : 0);
     return launched_mlp();
 }
 
