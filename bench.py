@@ -46,8 +46,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="hd")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
-    ap.add_argument("--cpu-crop", type=int, nargs=2, default=(640, 360))
+    ap.add_argument("--cpu-crop", type=int, nargs=2, default=(320, 180))
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-cache forms")
+    ap.add_argument("--mlp-train-frames", type=int, default=64,
+                    help="untimed frames of online training before the learned-cache forms are timed")
     ap.add_argument("--mlp-only", choices=["bf16", "fp8"], default=None,
                     help="time only this learned-cache form (for profiling)")
     ap.add_argument("--quality", action="store_true",
@@ -60,17 +62,27 @@ def parse():
     ap.add_argument("--profile-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device-to-device once (a known-size "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--profile-commands", metavar="DIR", default=None,
+                    help="print the rocprofv3 commands behind profiles/ (results under DIR) and exit")
+    ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
+                    help="write the profiles/ summaries from those runs' results under DIR and exit")
     return ap.parse_args()
 
 
-KERNEL_SOURCES = ["paper_2108_05263_amd/csrc/gi_kernels.hip", "paper_2108_05263_amd/csrc/gi_device.hpp",
-                  "paper_2108_05263_amd/csrc/gi_mlp.hip", "paper_2108_05263_amd/csrc/gi_mlp.hpp", "include/gi.h"]
+# sources a committed profile depends on: the resampling kernels, or the learned cache's
+KERNEL_SOURCES = {
+    "resampling": ["paper_2108_05263_amd/csrc/gi_kernels.hip", "paper_2108_05263_amd/csrc/gi_device.hpp",
+                   "include/gi.h"],
+    "mlp": ["paper_2108_05263_amd/csrc/gi_mlp.hip", "paper_2108_05263_amd/csrc/gi_mlp.hpp",
+            "paper_2108_05263_amd/csrc/gi_device.hpp", "include/gi.h"],
+}
 
 
-def source_sha():
+def source_sha(family="resampling"):
+    """SHA-256 prefix of the kernel sources of one family (profiles record it)."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[family]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -84,7 +96,7 @@ def _profile(kernel, workload, what):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_sha") != source_sha():
+    if rec.get("source_sha") != source_sha("mlp" if kernel.startswith("k_mlp") else "resampling"):
         return None
     return rec
 
@@ -114,41 +126,95 @@ def alu_issue(kernel, workload, ms):
             "source": f"profiles/{kernel}_{workload}_sq_counters.json"}
 
 
+def _host():
+    """Host CPU: model name, logical CPUs, CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def _oracle_frame(o, sg, cfg, sc, grid, irr, dep, pix, f, prev=None):
+    """One frame of the oracle on the listed pixels (all pixels: None); per-pass
+    seconds.  prev = (G-buffer, history reservoirs, camera) of the frame before."""
+    import numpy as np
+    W, H = cfg.width, cfg.height
+    pr = cfg.params
+    cam = sg.make_camera(cfg, f)
+    t = {}
+    t0 = time.perf_counter()
+    gb = o.gbuffer(sc, cam, pixels=pix, out=np.zeros((W * H, 14)) if pix is not None else None)
+    t["gbuffer"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res, resid = o.resample_initial(sc, W, H, gb, grid, irr, dep, pr, 1, f, pixels=pix)
+    t["initial"] = time.perf_counter() - t0
+    if prev is not None and pr.temporal:
+        t0 = time.perf_counter()
+        res = o.resample_temporal(sc, W, H, gb, prev[0], prev[2], res, prev[1], pr, 1, f, pixels=pix)
+        t["temporal"] = time.perf_counter() - t0
+    for sp in range(pr.n_spatial):
+        t0 = time.perf_counter()
+        res = o.resample_spatial(sc, W, H, gb, res, pr, sp, 1, f, pixels=pix)
+        t[f"spatial{sp}"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.shade(sc, W, H, gb, grid, irr, dep, res, resid, pr, pixels=pix)
+    t["shade"] = time.perf_counter() - t0
+    return t, (gb, res, cam)
+
+
 def cpu_baseline(cfg, crop):
-    """FP64 oracle, single thread, on a centred crop of the same frame: two
-    frames (the second with temporal reuse), the second one timed."""
+    """The FP64 oracle on the host: the 1920x1080 workload's frame 0 in full on
+    the oracle's OpenMP pixel loops (all usable CPUs, at most 16: the host share
+    of one GPU), the 64x64 room's frame in full on one thread, and a centred
+    crop of the 1920x1080 workload's second frame (with temporal reuse) on one
+    thread.  The probe volume is filled once beforehand with fewer rays (it is
+    an input of the timed passes, not timed)."""
     import numpy as np
     import oracle as o
     from paper_2108_05263_amd import scenegen as sg
 
+    host = _host()
+    threads = o.set_threads(min(16, host["usable_cpus"] or 1))
     sc = sg.make_scene(cfg)
     grid = sg.make_probe_grid(cfg)
-    upd = sg.ProbeUpdate(rays=32, fill_passes=1, fill_rays=32)
-    irr, dep = o.fill_probes(sc, grid, upd, seed=1)
+    irr, dep = o.fill_probes(sc, grid, sg.ProbeUpdate(rays=32, fill_passes=1, fill_rays=32), seed=1)
     W, H = cfg.width, cfg.height
+    tf, _ = _oracle_frame(o, sg, cfg, sc, grid, irr, dep, None, 0)
+    full_s = sum(tf.values())
+    o.set_threads(1)
+    # the 64x64 room, one frame in full, one thread
+    tcfg = sg.CONFIGS["tiny"]
+    tsc, tgrid = sg.make_scene(tcfg), sg.make_probe_grid(tcfg)
+    tirr, tdep = o.fill_probes(tsc, tgrid, tcfg.probe_update, seed=1)
+    tt, _ = _oracle_frame(o, sg, tcfg, tsc, tgrid, tirr, tdep, None, 0)
+    tiny_s = sum(tt.values())
+    # single-thread rate on the 1080p frame: a centred crop of frame 1 (temporal reuse on)
     cw, ch = crop
     x0, y0 = (W - cw) // 2, (H - ch) // 2
     pix = np.array([(y0 + j) * W + x0 + i for j in range(ch) for i in range(cw)], np.int32)
-    pr = cfg.params
-    n = W * H
-    gb_prev = hist = None
-    cam_prev = None
-    t_frame = 0.0
-    for f in range(2):
-        cam = sg.make_camera(cfg, f)
-        t0 = time.perf_counter()
-        gb = o.gbuffer(sc, cam, pixels=pix, out=np.zeros((n, 14)))
-        res, resid = o.resample_initial(sc, W, H, gb, grid, irr, dep, pr, 1, f, pixels=pix)
-        if hist is not None:
-            res = o.resample_temporal(sc, W, H, gb, gb_prev, cam_prev, res, hist, pr, 1, f, pixels=pix)
-        for sp in range(pr.n_spatial):
-            res = o.resample_spatial(sc, W, H, gb, res, pr, sp, 1, f, pixels=pix)
-        o.shade(sc, W, H, gb, grid, irr, dep, res, resid, pr, pixels=pix)
-        t_frame = time.perf_counter() - t0
-        gb_prev, hist, cam_prev = gb, res, cam
-    return {"value": len(pix) / t_frame, "unit": "pixels/s", "cores": 1, "kind": "oracle",
-            "sample": f"{cw}x{ch} centre crop of the {W}x{H} frame, second frame (with temporal "
-                      f"reuse), {t_frame:.1f} s single-threaded FP64"}
+    _, prev = _oracle_frame(o, sg, cfg, sc, grid, irr, dep, pix, 0)
+    tc, _ = _oracle_frame(o, sg, cfg, sc, grid, irr, dep, pix, 1, prev)
+    crop_s = sum(tc.values())
+    return {"value": W * H / full_s, "unit": "pixels/s", "cores": threads, "kind": "oracle",
+            "sample": f"{W}x{H} workload, frame 0 in full (G-buffer, initial, {cfg.params.n_spatial} spatial "
+                      f"passes, shading; no temporal pass in frame 0), FP64, {threads} OpenMP threads, "
+                      f"{full_s:.1f} s",
+            "pass_s": {k: round(v, 3) for k, v in tf.items()},
+            "host": host,
+            "single_thread": {
+                "tiny_64x64_frame_s": round(tiny_s, 3), "tiny_pixels_per_s": 64 * 64 / tiny_s,
+                "hd_crop": f"{cw}x{ch} centre crop of frame 1 (with temporal reuse)",
+                "hd_crop_pixels_per_s": len(pix) / crop_s, "hd_crop_s": round(crop_s, 3)}}
 
 
 # Algorithmic FLOP of one network evaluation: 2 * (78*64 + 3*64*64 + 64*3)
@@ -156,13 +222,15 @@ MLP_FLOP = 34944
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0}
 
 
-def mlp_form(gi, sg, torch, cfg, precision, steps, warmup):
+def mlp_form(gi, sg, torch, cfg, precision, steps, warmup, mode="always", train_frames=0):
     """Frames of the learned-cache form (cache target in the initial pass and
     in shading, online training after each frame), timed like the probe form,
-    plus the inference kernel alone on one frame's candidates."""
-    # the cache is always the target here (the usability test could hand
-    # frames back to the probe query and leave the inference untimed)
-    r = gi.Renderer(cfg, seed=1, mlp=precision, mlp_mode="always")
+    plus the inference kernel alone on one frame's candidates.  mode "always"
+    makes the cache the target in every frame; "auto" lets the cache's own
+    judge (its error against the probe query) decide per frame, falling back
+    to the probe query.  train_frames untimed frames of online training run
+    before the warm-up (the cache in steady state)."""
+    r = gi.Renderer(cfg, seed=1, mlp=precision, mlp_mode=mode)
     r.fill_probes()
     stream = torch.cuda.current_stream()
     keys = {"trace_gbuffer": "gbuffer", "resample_initial_mlp": "initial", "resample_temporal": "temporal",
@@ -185,12 +253,13 @@ def mlp_form(gi, sg, torch, cfg, precision, steps, warmup):
     orig_train = r.train_mlp
     r.train_mlp = timed(lambda a: "train", orig_train)
     try:
-        for f in range(warmup):
+        f0 = train_frames + warmup
+        for f in range(f0):
             r.frame(f)
         torch.cuda.synchronize()
         pending.clear()
         t0 = time.perf_counter()
-        for f in range(warmup, warmup + steps):
+        for f in range(f0, f0 + steps):
             r.frame(f)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
@@ -227,6 +296,8 @@ def mlp_form(gi, sg, torch, cfg, precision, steps, warmup):
     npx = r.W * r.H
     res_ms = sum(v for k, v in avg.items() if k not in ("gbuffer", "batch", "train"))
     return {
+        "mode": mode,
+        "trained_frames_before_timing": f0,
         "ms_per_step": elapsed * 1e3 / steps,
         "pixels_per_s": npx * steps / elapsed,
         "resampling_only_pixels_per_s": npx / (res_ms * 1e-3),
@@ -340,8 +411,169 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
     return out
 
 
+# --------------------------------------------------------------------------
+# rocprofv3 runs behind the committed profiles/ summaries
+# --------------------------------------------------------------------------
+PROBE_INITIAL = "k_initial<true, false, false, false>"       # the probe form's initial pass (scene in LDS)
+SQ_SETS = {"sq1": "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU "
+                  "SQ_ACTIVE_INST_LDS SQ_INSTS_VMEM_RD",
+           "sq2": "SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_ACTIVE_INST_ANY SQ_THREAD_CYCLES_VALU TCC_HIT_sum "
+                  "TCC_MISS_sum GRBM_GUI_ACTIVE"}
+MFMA_SET = ("SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES SQ_INSTS_VALU SQ_INSTS_MFMA SQ_VALU_MFMA_COEXEC_CYCLES "
+            "GRBM_GUI_ACTIVE")
+
+
+def profile_commands(outdir):
+    """The rocprofv3 runs (one shell command each) whose results
+    summarize_profiles() turns into profiles/: kernel-trace statistics of
+    the default benchmark, HBM traffic (FETCH_SIZE, then WRITE_SIZE, each
+    scaled by a 1 GiB copy in the same run), SQ counters of the probe form's
+    initial pass, MFMA counters of the inference kernels."""
+    bench = f"python3 -u {os.path.join(ROOT, 'bench.py')}"
+    pre = "cd /tmp && TMPDIR=/tmp timeout -s KILL 240 rocprofv3"
+    probe = f"{bench} --steps 2 --warmup 1 --no-cpu --no-mlp"
+    cmds = {"kt": f"{pre} --kernel-trace --stats --output-format csv -d {outdir}/kt -o hd -- "
+                  f"{bench} --steps 5 --warmup 2 --no-cpu --mlp-train-frames 8",
+            "fetch": f"{pre} --pmc FETCH_SIZE --output-format csv -d {outdir}/fetch -o hd -- {probe} --profile-copy",
+            "write": f"{pre} --pmc WRITE_SIZE --output-format csv -d {outdir}/write -o hd -- {probe} --profile-copy"}
+    for k, v in SQ_SETS.items():
+        cmds[k] = f"{pre} --pmc {v} --output-format csv -d {outdir}/{k} -o hd -- {probe}"
+    for prec in ("bf16", "fp8"):
+        cmds[f"mfma_{prec}"] = (f"{pre} --pmc {MFMA_SET} --output-format csv -d {outdir}/mfma_{prec} -o mlp -- "
+                                f"{bench} --mlp-only {prec} --steps 2 --warmup 1 --mlp-train-frames 0")
+    return cmds
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _counters(d, kernel_sub):
+    """Per-dispatch counter values (summed over the chip) of the dispatches
+    whose kernel name contains kernel_sub: {counter: [value per dispatch]}."""
+    per = {}
+    for r in _csv_rows(d, "counter_collection.csv"):
+        if kernel_sub not in r["Kernel_Name"]:
+            continue
+        key = (r["Dispatch_Id"], r["Counter_Name"])
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for (_, c), v in sorted(per.items(), key=lambda kv: int(kv[0][0])):
+        out.setdefault(c, []).append(v)
+    return out
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "").replace("(anonymous namespace)::", "")
+
+
+def summarize_profiles(outdir, ms_initial=None):
+    """Write the profiles/ summaries from the runs of profile_commands()."""
+    cmds = {k: v.replace(ROOT, "<repo>").replace(outdir, "<out>") for k, v in profile_commands(outdir).items()}
+    prof = os.path.join(ROOT, "profiles")
+    sha_r, sha_m = source_sha("resampling"), source_sha("mlp")
+    written = []
+    # kernel-trace statistics
+    rows = _csv_rows(os.path.join(outdir, "kt"), "kernel_stats.csv")
+    if rows:
+        for fname, fam, keep in (("k_initial_hd_kernel_stats.txt", "resampling", lambda n: "k_mlp" not in n),
+                                 ("k_mlp_infer_hd_kernel_stats.txt", "mlp", lambda n: "k_mlp" in n or "k_cand" in n)):
+            lines = [f"# rocprofv3 kernel-trace statistics, 1920x1080 workload (hd), {fam} kernels of the run",
+                     f"# command: {cmds['kt']}",
+                     f"# kernel sources: {source_sha(fam)} (sha256 prefix of {', '.join(KERNEL_SOURCES[fam])})",
+                     "# the run covers the probe form and the learned-cache forms (BF16, FP8; always and auto)",
+                     "# columns: kernel, calls, average ns, min ns, max ns, total ns"]
+            for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+                if keep(r["Name"]):
+                    lines.append(f'{_short(r["Name"])}, {r["Calls"]}, {float(r["AverageNs"]):.0f}, '
+                                 f'{float(r["MinNs"]):.0f}, {float(r["MaxNs"]):.0f}, {float(r["TotalDurationNs"]):.0f}')
+            with open(os.path.join(prof, fname), "w") as fh:
+                fh.write("\n".join(lines) + "\n")
+            written.append(fname)
+    # HBM traffic of the probe form's initial pass, scaled by the copy reference
+    fetch = _counters(os.path.join(outdir, "fetch"), PROBE_INITIAL).get("FETCH_SIZE", [])
+    write = _counters(os.path.join(outdir, "write"), PROBE_INITIAL).get("WRITE_SIZE", [])
+    cf = _counters(os.path.join(outdir, "fetch"), "copyBuffer").get("FETCH_SIZE", [])
+    cw = _counters(os.path.join(outdir, "write"), "copyBuffer").get("WRITE_SIZE", [])
+    if fetch and write and cf and cw:
+        gib = float(1 << 30)
+        fs, ws = gib / (max(cf) * 1024.0), gib / (max(cw) * 1024.0)
+        f_kib, w_kib = sum(fetch) / len(fetch), sum(write) / len(write)
+        rec = {"kernel": "k_initial", "workload": "hd 1920x1080, M=32", "source_sha": sha_r,
+               "fetch_size_kib_per_dispatch": f_kib, "write_size_kib_per_dispatch": w_kib,
+               "dispatches": [len(fetch), len(write)],
+               "copy_reference": {"bytes": int(gib), "fetch_size_kib": max(cf), "write_size_kib": max(cw),
+                                  "fetch_scale": fs, "write_scale": ws},
+               "traffic_bytes_per_launch": int(f_kib * 1024 * fs + w_kib * 1024 * ws),
+               "algorithmic_bytes_per_launch": ALGO_BYTES["initial"] * 1920 * 1080,
+               "commands": [cmds["fetch"], cmds["write"]],
+               "note": "FETCH_SIZE/WRITE_SIZE count L2-to-fabric bytes (MALL or HBM); each is scaled by what "
+                       "the same counter reads for a 1 GiB device-to-device copy in the same run"}
+        with open(os.path.join(prof, "k_initial_hd_traffic.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        written.append("k_initial_hd_traffic.json")
+    # SQ counters of the probe form's initial pass
+    rec = {"kernel": "k_initial", "workload": "hd", "source_sha": sha_r}
+    for k in SQ_SETS:
+        for c, v in _counters(os.path.join(outdir, k), PROBE_INITIAL).items():
+            rec[c] = sum(v) / len(v)
+            rec[c + "_dispatches"] = len(v)
+    if "SQ_INSTS_VALU" in rec:
+        rec["commands"] = [cmds[k] for k in SQ_SETS]
+        rec["note"] = ("per-dispatch averages summed over the chip; the SQ_*CYCLES / SQ_WAIT* / SQ_ACTIVE* counters "
+                       "count quad-cycles (4 clocks), SQ_INSTS_* count wave-level instructions")
+        if "SQ_THREAD_CYCLES_VALU" in rec and "SQ_ACTIVE_INST_VALU" in rec:
+            rec["active_lanes_per_valu_instruction"] = rec["SQ_THREAD_CYCLES_VALU"] / rec["SQ_ACTIVE_INST_VALU"]
+        if "TCC_HIT_sum" in rec:
+            rec["l2_hit_rate"] = rec["TCC_HIT_sum"] / (rec["TCC_HIT_sum"] + rec["TCC_MISS_sum"])
+        with open(os.path.join(prof, "k_initial_hd_sq_counters.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        written.append("k_initial_hd_sq_counters.json")
+    # MFMA counters of the inference kernels (full-frame dispatches: the most MFMA instructions)
+    lines = ["# rocprofv3 counters of the inference kernels, 1920x1080 workload (hd): one frame's candidates",
+             f"# kernel sources: {sha_m} (sha256 prefix of {', '.join(KERNEL_SOURCES['mlp'])})",
+             "# averages over the full-frame dispatches; counters summed over the chip"]
+    have = False
+    for prec, kname in (("bf16", "k_mlp_infer_bf16"), ("fp8", "k_mlp_infer_fp8")):
+        c = _counters(os.path.join(outdir, f"mfma_{prec}"), kname)
+        if not c.get("SQ_INSTS_MFMA"):
+            continue
+        have = True
+        top = max(c["SQ_INSTS_MFMA"])
+        sel = [i for i, v in enumerate(c["SQ_INSTS_MFMA"]) if v == top]
+        avg = {k: sum(v[i] for i in sel) / len(sel) for k, v in c.items() if len(v) == len(c["SQ_INSTS_MFMA"])}
+        tiles = 1920 * 1080 * 32 / 32
+        lines += ["", f"## {prec.upper()} ({kname})", f"# command: {cmds['mfma_' + prec]}",
+                  f"# {len(sel)} full-frame dispatches"]
+        lines += [f"{k:<40s} {v:>18.0f}" for k, v in sorted(avg.items())]
+        lines += ["derived:",
+                  f"MFMA instructions per 32-sample tile     {avg['SQ_INSTS_MFMA'] / tiles:10.2f}",
+                  f"MFMA busy cycles per MFMA instruction    {avg['SQ_VALU_MFMA_BUSY_CYCLES'] / avg['SQ_INSTS_MFMA']:10.2f}",
+                  f"VALU instructions per tile (incl. MFMA)  {avg['SQ_INSTS_VALU'] / tiles:10.1f}",
+                  f"MFMA cycles overlapped with VALU         "
+                  f"{avg['SQ_VALU_MFMA_COEXEC_CYCLES'] / max(avg['SQ_VALU_MFMA_BUSY_CYCLES'], 1.0):10.3f}"]
+    if have:
+        with open(os.path.join(prof, "k_mlp_infer_hd_mfma_counters.txt"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        written.append("k_mlp_infer_hd_mfma_counters.txt")
+    return written
+
+
 def main():
     args = parse()
+    if args.profile_commands:
+        for k, v in profile_commands(os.path.abspath(args.profile_commands)).items():
+            print(v)
+        return
+    if args.summarize_profiles:
+        print("\n".join(summarize_profiles(os.path.abspath(args.summarize_profiles))))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py runs on one GPU only; the path would shard by screen "
                                    "bands across GPUs, which is not implemented"}))
@@ -362,7 +594,8 @@ def main():
         return
     if args.mlp_only:
         print(json.dumps({"mlp_form": args.mlp_only,
-                          **mlp_form(gi, sg, torch, cfg, args.mlp_only, args.steps, args.warmup)}), flush=True)
+                          **mlp_form(gi, sg, torch, cfg, args.mlp_only, args.steps, args.warmup, "always",
+                                     args.mlp_train_frames)}), flush=True)
         if args.profile_copy:
             src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
             torch.empty_like(src).copy_(src)
@@ -454,7 +687,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(f"k_{dom_key}", cfg.name),
                      "algorithmic_bytes_per_launch": bytes_launch,
-                     "kernel_source_sha": source_sha()},
+                     "kernel_source_sha": source_sha("resampling")},
         # the dominant kernel is bound by vector-ALU issue, not HBM: its measured issue rate
         "alu_issue": alu_issue(f"k_{dom_key}", cfg.name, avg[dom]),
     }
@@ -471,10 +704,11 @@ def main():
         torch.cuda.empty_cache()
         forms = {}
         for prec in ("bf16", "fp8"):
-            f = mlp_form(gi, sg, torch, cfg, prec, args.steps, args.warmup)
-            f["speed_ratio_vs_probe"] = ms_step / f["ms_per_step"]
-            forms[prec] = f
-            torch.cuda.empty_cache()
+            for mode in ("always", "auto"):
+                f = mlp_form(gi, sg, torch, cfg, prec, args.steps, args.warmup, mode, args.mlp_train_frames)
+                f["speed_ratio_vs_probe"] = ms_step / f["ms_per_step"]
+                forms[f"{prec}_{mode}"] = f
+                torch.cuda.empty_cache()
         line["mlp_forms"] = forms
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg, tuple(args.cpu_crop))

@@ -24,13 +24,14 @@ def test_committed_profiles_match_the_kernel_sources():
     silently turning the bench line's traffic into null."""
     sys.path.insert(0, ROOT)
     import bench
-    sha = bench.source_sha()
+    sha, sha_m = bench.source_sha("resampling"), bench.source_sha("mlp")
     for what in ("traffic", "sq_counters"):
         with open(os.path.join(ROOT, "profiles", f"k_initial_hd_{what}.json")) as fh:
             assert json.load(fh)["source_sha"] == sha, what
-    for name in ("k_initial_hd_kernel_stats.txt", "k_mlp_infer_hd_kernel_stats.txt"):
+    for name, h in (("k_initial_hd_kernel_stats.txt", sha), ("k_mlp_infer_hd_kernel_stats.txt", sha_m),
+                    ("k_mlp_infer_hd_mfma_counters.txt", sha_m)):
         with open(os.path.join(ROOT, "profiles", name)) as fh:
-            assert f"kernel sources: {sha}" in fh.read(), name
+            assert f"kernel sources: {h}" in fh.read(), name
     # the bench line's algorithmic bytes: 104 B per pixel of the 1920x1080 frame
     assert bench.measured_traffic("k_initial", "hd") > 104 * 1920 * 1080
     issue = bench.alu_issue("k_initial", "hd", 6.0)
