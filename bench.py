@@ -470,7 +470,9 @@ def _counters(d, kernel_sub):
 
 
 def _short(name):
-    return name.split("(")[0].replace("void ", "").replace("(anonymous namespace)::", "")
+    """Kernel name without namespace, parameter list and return type."""
+    n = name.replace("(anonymous namespace)::", "").replace("void ", "", 1)
+    return n.split("(")[0].strip()
 
 
 def summarize_profiles(outdir, ms_initial=None):
