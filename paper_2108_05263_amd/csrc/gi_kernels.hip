@@ -424,15 +424,27 @@ struct CandWs {
     float4 *pos;
     float4 *nrm;
     float4 *q;
+    uint32_t gate;   // kRunAlways, or run only when the cache is (kRunIfCache) / is not (kRunIfProbe) selected
 };
+
+// Gates of the learned cache's kernels in AUTO mode: the device decides per
+// frame, so both forms are launched and the one not selected returns at once
+// (a uniform exit before any barrier).
+enum : uint32_t { kRunAlways = 0u, kRunIfCache = 1u, kRunIfProbe = 2u };
+
+__device__ __forceinline__ bool gated_off(const CandWs &ws, const gi_mlp &mlp)
+{
+    return ws.gate != kRunAlways && (ws.gate == kRunIfCache) != mlp_selected(mlp);
+}
 
 // Traces the M candidates of every pixel into the candidate planes (the
 // directions and hits k_initial computes itself in the probe form).
 template <bool LDS>
 __global__ void __launch_bounds__(kBlock)
-    k_cand(gi_scene sc, gi_gbuffer gb, gi_params pp, CandWs ws, uint64_t seed, uint32_t frame)
+    k_cand(gi_scene sc, gi_gbuffer gb, gi_params pp, CandWs ws, uint64_t seed, uint32_t frame, gi_mlp mlp)
 {
     using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
+    if (gated_off(ws, mlp)) return;
     uint32_t px, py;
     const bool inside = tile_pixel(gb.width, gb.height, px, py);
     if (LDS) stage_scene(sc);
@@ -484,6 +496,7 @@ __global__ void __launch_bounds__(kBlock, 4)
               uint64_t seed, uint32_t frame, CandWs ws, gi_mlp mlp)
 {
     using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
+    if (gated_off(ws, mlp)) return;
     uint32_t px, py;
     const bool inside = tile_pixel(gb.width, gb.height, px, py);
     if (LDS) stage_scene(sc);
@@ -1518,14 +1531,28 @@ gi_status gi_resample_initial_mlp(const gi_scene *scene, const gi_gbuffer *gb, c
     if (workspace_bytes < gi_initial_mlp_workspace_bytes(W, H, params->M)) return GI_ERR_SHAPE;
     if (W == 0 || H == 0) return GI_OK;
     float4 *base = reinterpret_cast<float4 *>(workspace);
-    CandWs ws{base, base + ncand, base + 2 * ncand};
-    GI_LAUNCH_LDS(k_cand, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *params, ws, seed,
-                  frame);
-    if ((s = launched()) != GI_OK) return s;
-    if ((s = mlp_infer_launch(*mlp, (uint32_t)ncand, ws.pos, ws.nrm, ws.q, true, S(stream))) != GI_OK) return s;
-    launch_initial<true>(params->M_light > 0, false, 0u, tile_grid(W, H), S(stream), *scene, *gb, *probes, *params,
-                         *out,
-                         reinterpret_cast<float4 *>(resid), seed, frame, ws, *mlp);
+    // NEVER: the probe form alone.  ALWAYS: the cache form (candidates traced
+    // into the workspace, the cache evaluated on all of them, resampling with
+    // the cached values).  AUTO: both, each gated on the device's usability
+    // word, so that a frame the cache is not used in costs the probe form
+    // (bit-identical to gi_resample_initial) and not the cache form's trace.
+    if (mlp->mode != GI_MLP_NEVER) {
+        const uint32_t gate = mlp->mode == GI_MLP_AUTO ? kRunIfCache : kRunAlways;
+        CandWs ws{base, base + ncand, base + 2 * ncand, gate};
+        GI_LAUNCH_LDS(k_cand, tile_grid(W, H), kBlock, scene_lds(scene), S(stream), *scene, *gb, *params, ws, seed,
+                      frame, *mlp);
+        if ((s = launched()) != GI_OK) return s;
+        if ((s = mlp_infer_launch(*mlp, (uint32_t)ncand, ws.pos, ws.nrm, ws.q, true, S(stream))) != GI_OK) return s;
+        launch_initial<true>(params->M_light > 0, false, 0u, tile_grid(W, H), S(stream), *scene, *gb, *probes,
+                             *params, *out, reinterpret_cast<float4 *>(resid), seed, frame, ws, *mlp);
+        if ((s = launched()) != GI_OK) return s;
+    }
+    if (mlp->mode != GI_MLP_ALWAYS) {
+        const uint32_t gate = mlp->mode == GI_MLP_AUTO ? kRunIfProbe : kRunAlways;
+        launch_initial<false>(params->M_light > 0, false, initial_scene_lds(scene), tile_grid(W, H), S(stream),
+                              *scene, *gb, *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame,
+                              CandWs{nullptr, nullptr, nullptr, gate}, *mlp);
+    }
     return launched();
 }
 

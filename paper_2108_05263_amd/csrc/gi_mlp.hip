@@ -489,19 +489,33 @@ k_mlp_infer_fp8(gi_mlp m, uint32_t n, const float4 *pos, const float4 *nrm, floa
 // training
 // --------------------------------------------------------------------------
 // number of valid samples (target.w != 0) -> hdr[0]
+// sum of a value over a 1024-thread workgroup: wave sums by shuffles, then
+// the 16 wave sums in order (integer-valued here, so exact)
+__device__ __forceinline__ uint32_t block_sum_1024(uint32_t v, uint32_t *red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t r = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) r += red[w];
+    return r;
+}
+
 __global__ void __launch_bounds__(1024) k_mlp_count(uint32_t n, const float4 *tgt, uint32_t *hdr)
 {
-    __shared__ uint32_t red[1024];
-    const int t = threadIdx.x;
+    __shared__ uint32_t red[16];
     uint32_t c = 0;
-    for (uint32_t i = t; i < n; i += 1024) c += tgt[i].w != 0.0f ? 1u : 0u;
-    red[t] = c;
-    __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-        if (t < o) red[t] += red[t + o];
-        __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += 4096) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t j = i + 1024u * k;
+            if (j < n) c += tgt[j].w != 0.0f ? 1u : 0u;
+        }
     }
-    if (t == 0) hdr[0] = red[0];
+    const uint32_t r = block_sum_1024(c, red);
+    if (threadIdx.x == 0) hdr[0] = r;
 }
 
 // --------------------------------------------------------------------------
@@ -893,25 +907,19 @@ __global__ void __launch_bounds__(256) k_mlp_adam(gi_mlp m, const float *grad, f
     if (m.ema) m.ema[p] = m.ema_decay * m.ema[p] + (1.0f - m.ema_decay) * np;
 }
 
-// usability after step t (one workgroup)
-__global__ void __launch_bounds__(256) k_mlp_state(gi_mlp m, uint32_t t)
+// usability after step t (one workgroup of 1024 threads)
+__global__ void __launch_bounds__(1024) k_mlp_state(gi_mlp m, uint32_t t)
 {
-    __shared__ float red[256];
-    const int tid = threadIdx.x;
-    float bad = 0.0f;
-    for (int p = tid; p < kParams; p += 256) bad += __builtin_isfinite(m.params[p]) ? 0.0f : 1.0f;
-    red[tid] = bad;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) red[tid] += red[tid + o];
-        __syncthreads();
-    }
-    if (tid == 0) {
+    __shared__ uint32_t red[16];
+    uint32_t bad = 0;
+    for (int p = threadIdx.x; p < kParams; p += 1024) bad += __builtin_isfinite(m.params[p]) ? 0u : 1u;
+    const uint32_t nonfinite = block_sum_1024(bad, red);
+    if (threadIdx.x == 0) {
         const float be = __uint_as_float(m.state[GI_MLP_STATE_BATCH_ERR]);
         const float old = __uint_as_float(m.state[GI_MLP_STATE_EMA_ERR]);
         const float ema = t <= 1u ? be : 0.9f * old + 0.1f * be;
         const bool ok = t >= m.warmup_steps && m.state[GI_MLP_STATE_NONFINITE] == 0u && ema <= m.max_rel_err &&
-                        red[0] == 0.0f;
+                        nonfinite == 0u;
         m.state[GI_MLP_STATE_STEPS] = t;
         m.state[GI_MLP_STATE_EMA_ERR] = __float_as_uint(ema);
         m.state[GI_MLP_STATE_USABLE] = ok ? 1u : 0u;
@@ -1001,7 +1009,7 @@ gi_status adam_launch(const gi_mlp &m, const float *grad, uint32_t t, float lr, 
     const double c1 = 1.0 / (1.0 - std::pow(0.9, (double)t));
     const double c2 = 1.0 / (1.0 - std::pow(0.99, (double)t));
     k_mlp_adam<<<(kParams + 255) / 256, 256, 0, st>>>(m, grad, lr, (float)c1, (float)c2);
-    k_mlp_state<<<1, 256, 0, st>>>(m, t);
+    k_mlp_state<<<1, 1024, 0, st>>>(m, t);
     gi_status s = launched_mlp();
     if (s != GI_OK) return s;
     return prepare(m, st);
