@@ -6,10 +6,11 @@ Shared inputs as in the Lambertian parity tests: each pass reads the
 oracle's own inputs (G-buffer records with the primitives' glossy layer,
 probe textures, reservoirs).  Tolerances: the Lambertian bar (mean relative
 error <= 1e-4 over unflipped pixels, flips <= 1e-3) for the resampling
-passes and the probe update.  Shading traces the glossy samples of the
-recursion, so an FP32 and an FP64 ray can part at a grazing edge: pixels
-whose error exceeds 1e-3 are counted (<= 1% allowed) and the rest must meet
-the 1e-4 mean.  FP32 GGX forms its denominator from |n x h|^2 (no
+passes and the probe update; shading (which traces the glossy samples of
+the recursion) and the glossy path tracer are held to a mean relative error
+of 1e-4 over every compared pixel (the pixels above 1e-3 are logged: an
+FP32 and an FP64 ray could part at a grazing edge, and none does on these
+inputs).  FP32 GGX forms its denominator from |n x h|^2 (no
 cancellation at the lobe's peak), so the lobe values keep FP32 precision
 down to roughness 0.02.
 """
@@ -153,10 +154,8 @@ def test_glossy_passes_shared_inputs(gi, request, which):
     resid.copy_(torch.from_numpy(np.concatenate([s["resid"], np.zeros((W * H, 1))], 1).astype(np.float32)))
     gi.shade(ds, gb, probes, rin, resid, pr, img, seed=1, frame=f)
     e = rel_err(img.cpu().numpy()[:, :3], s["image"], 1e-2).max(1)
-    parted = e > 1e-3
-    log(f"{which} shade: parted {parted.mean():.4f}, mean rel err of the rest {e[~parted].mean():.2e}")
-    assert parted.mean() <= 0.01
-    assert e[~parted].mean() < 1e-4
+    log(f"{which} shade: mean rel err {e.mean():.2e}, pixels above 1e-3 {np.mean(e > 1e-3):.4f}")
+    assert e.mean() <= 1e-4
 
 
 def test_glossy_path_tracer(gi, gtiny):
@@ -170,10 +169,8 @@ def test_glossy_path_tracer(gi, gtiny):
     g.load_records(gb_rec, scene=sc, eye=cam.eye)
     out = gi.path_trace(ds, g, 4, 5, 0).cpu().numpy()[:, :3]
     e = rel_err(out, ref, 1e-2).max(1)
-    diverged = e > 1e-3
-    log(f"glossy path tracer: diverged {diverged.mean():.4f}, rest {e[~diverged].mean():.2e}")
-    assert diverged.mean() <= 0.03
-    assert e[~diverged].mean() <= 1e-4
+    log(f"glossy path tracer: mean rel err {e.mean():.2e}, pixels above 1e-3 {np.mean(e > 1e-3):.4f}")
+    assert e.mean() <= 1e-4
 
 
 def test_mlp_entry_points_reject_glossy(gi, gtiny):
@@ -226,7 +223,5 @@ def test_glossy_full_size_sampled(gi):
     gi.shade(ds, gb, probes, rin, resid, pr, img, seed=1, frame=0)
     oimg = o.shade(sc, W, H, ogb, grid, irr, dep, ores, oresid, pr, pixels=S, seed=1, frame=0, eye=cam.eye)
     e = rel_err(img.cpu().numpy()[S, :3], oimg[S], 1e-2).max(1)
-    parted = e > 1e-3
-    log(f"glossy 1080p shade (sampled): parted {parted.mean():.4f}, mean rel err of the rest {e[~parted].mean():.2e}")
-    assert parted.mean() <= 0.01
-    assert e[~parted].mean() < 1e-4
+    log(f"glossy 1080p shade (sampled): mean rel err {e.mean():.2e}, pixels above 1e-3 {np.mean(e > 1e-3):.4f}")
+    assert e.mean() <= 1e-4

@@ -85,8 +85,5 @@ def test_parity_with_oracle(gi):
     for grid_res in (None, cfg.grid_res):
         out = _run(gi, sc, gb, W, H, spp, 5, grid_res)
         e = rel_err(out, ref, 1e-2).max(1)
-        diverged = e > 1e-3
-        log(f"path tracer grid={grid_res}: diverged {diverged.mean():.4f}, mean rel err of the rest "
-            f"{e[~diverged].mean():.2e}")
-        assert diverged.mean() <= 0.02
-        assert e[~diverged].mean() <= 1e-4
+        log(f"path tracer grid={grid_res}: mean rel err {e.mean():.2e}, pixels above 1e-3 {np.mean(e > 1e-3):.4f}")
+        assert e.mean() <= 1e-4
