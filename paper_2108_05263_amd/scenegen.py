@@ -187,7 +187,7 @@ CONFIGS = {
         pan=0.05, probe_dims=(32, 8, 32), probe_spacing=1.0,
         params=Params(M=32, k=5, n_spatial=2, radius=30.0, temporal=True),
         probe_update=ProbeUpdate(rays=256, hysteresis=0.0, fill_passes=4, fill_rays=256),
-        frames=8, grid_res=(16, 4, 16)),
+        frames=8, grid_res=(12, 3, 12)),
     # 3840x2160, same room with 512 + 512 primitives, 64x16x64 probes updated every
     # frame with 256 rays at hysteresis 0.97.  Four times the primitives of the
     # 1920x1080 room at the same occupancy (sizes scaled by 4^(-1/3)) and with
@@ -220,7 +220,7 @@ CONFIGS = {
         pan=0.05, probe_dims=(32, 8, 32), probe_spacing=1.0,
         params=Params(M=32, k=5, n_spatial=2, radius=30.0, temporal=True),
         probe_update=ProbeUpdate(rays=256, hysteresis=0.0, fill_passes=4, fill_rays=256),
-        frames=8, grid_res=(16, 4, 16), glossy_frac=0.5),
+        frames=8, grid_res=(12, 3, 12), glossy_frac=0.5),
 }
 
 
