@@ -326,9 +326,10 @@ gi_status gi_shade(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes 
  * Precision: BF16 inference rounds every GEMM operand (encoded input,
  * weights, hidden activations) to BF16, nearest even, and accumulates in
  * FP32 (biases FP32).  FP8 inference stores operands as OCP E4M3FN values
- * x/s, with s = amax|W_l|/448 per weight matrix and s = (activation scale of
- * layer l) per layer input, saturating at +-448; products accumulate in FP32
- * and are scaled back by s_w*s_a.  Training is BF16 (gradients that enter a
+ * x/s, saturating at +-448, with power-of-two scales: per weight matrix the
+ * smallest power of two s with amax|W_l| <= 448 s, per layer input the
+ * activation scale of layer l (scales[5 + l]) rounded up to a power of two;
+ * products accumulate in FP32 and are scaled back by s_w*s_a.  Training is BF16 (gradients that enter a
  * product are rounded to BF16 too) with FP32 master weights and Adam moments.
  * ========================================================================== */
 #define GI_MLP_N_PARAMS 17731u
@@ -420,7 +421,8 @@ uint64_t gi_mlp_train_workspace_bytes(uint32_t n);
  * (GI_MLP_N_PARAMS floats, caller-owned) and, into state, LOSS, VALID,
  * NONFINITE and BATCH_ERR = sum |max(0,C) - q| / sum (q + 0.01) over valid
  * samples and channels (q from qprobe4, which may be NULL: error 0); writes
- * the activation amax/448 of every layer input into scales[5..9].  The sums
+ * the FP8 scale of every layer input, the smallest power of two s with
+ * activation amax <= 448 s (1 when the amax is 0), into scales[5..9].  The sums
  * are reduced in a fixed order (deterministic). */
 gi_status gi_mlp_grad(const gi_mlp *mlp, uint32_t n, const float *pos4, const float *nrm4,
                       const float *target4, const float *qprobe4, float *grad, void *workspace,

@@ -17,10 +17,11 @@ paper leaves open is a reading, stated here:
 * BF16 precision: every GEMM operand (encoded input, weights, hidden
   activations, back-propagated gradients) is rounded to BF16 (nearest even,
   via FP32); accumulation and biases stay FP32/FP64;
-* FP8 (inference only): per-layer scales s_w = amax|W|/448 and s_a =
-  amax|input|/448 (activation amax calibrated on a batch); operands are
-  x / s rounded to OCP E4M3FN (saturated at 448), products accumulate
-  exactly and are scaled back by s_w s_a;
+* FP8 (inference only): per-layer scales, each the smallest power of two s
+  with amax <= 448 s (s_w from amax|W|, s_a from the activation amax
+  calibrated on a batch; given activation scales are rounded up to powers
+  of two); operands are x / s rounded to OCP E4M3FN (saturated at 448),
+  products accumulate exactly and are scaled back by s_w s_a;
 * loss: relative L2, mean over samples and channels of
   (y_hat - t)^2 / (sg(y_hat)^2 + 0.01), sg = stop-gradient;
 * optimiser: Adam, lr 1e-2, betas (0.9, 0.99), eps 1e-8, FP32/FP64 master
@@ -135,9 +136,39 @@ def encode(pos, nrm, lo, hi) -> np.ndarray:
     return np.stack(feats, axis=1)                                       # (B, 78)
 
 
+def pow2_at_least(x) -> float:
+    """The smallest power of two >= x (x > 0 finite); 1 otherwise.  Exact:
+    the candidate exponent from log2 is corrected by exact comparisons."""
+    x = float(x)
+    if not (x > 0.0 and math.isfinite(x)):
+        return 1.0
+    e = math.ceil(math.log2(x))
+    while x > math.ldexp(1.0, e):
+        e += 1
+    while x <= math.ldexp(1.0, e - 1):
+        e -= 1
+    return math.ldexp(1.0, e)
+
+
+def fp8_scale(amax) -> float:
+    """Per-layer FP8 scale: the smallest power of two s with amax <= 448 s (1
+    for an all-zero tensor, which has no range).  Powers of two make the
+    ratio of consecutive layers' scales a power of two as well, an exponent
+    the matrix instruction applies."""
+    amax = float(amax)
+    if not (amax > 0.0 and math.isfinite(amax)):
+        return 1.0
+    e = math.ceil(math.log2(amax / 448.0))
+    while amax > 448.0 * math.ldexp(1.0, e):
+        e += 1
+    while amax <= 448.0 * math.ldexp(1.0, e - 1):
+        e -= 1
+    return math.ldexp(1.0, e)
+
+
 def fp8_weight_scales(params):
-    """amax|W| / 448 per layer (1 for an all-zero matrix, which has no range)."""
-    return [float(np.max(np.abs(W))) / 448.0 or 1.0 for W, _ in split(params)]
+    """fp8_scale of amax|W| per layer."""
+    return [fp8_scale(np.max(np.abs(W))) for W, _ in split(params)]
 
 
 def forward(params, X, prec="f64", act_scales=None):
@@ -151,7 +182,8 @@ def forward(params, X, prec="f64", act_scales=None):
             a_in, W_used = round_bf16(h), round_bf16(W)
             z = a_in @ W_used.T + b
         elif prec == "fp8":
-            sa, sw = act_scales[li], w_scales[li]
+            # activation scales as given, rounded up to powers of two
+            sa, sw = pow2_at_least(act_scales[li]), w_scales[li]
             a_in = round_fp8_e4m3(h / sa)
             W_used = round_fp8_e4m3(W / sw)
             z = (a_in @ W_used.T) * (sw * sa) + b

@@ -48,6 +48,48 @@ __device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; 
 
 __device__ __forceinline__ float comp(float4 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
 
+// a lane's input point of tile t (zero past the end)
+__device__ __forceinline__ float4 tile_input(const float4 *src, uint32_t t, uint32_t ntiles, int s, uint32_t n)
+{
+    if (t < ntiles) {
+        const uint32_t idx = t * 32u + (uint32_t)s;
+        if (idx < n) return src[idx];
+    }
+    return make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// sin and cos of the doubled angle
+__device__ __forceinline__ void double_angle(float s, float c, float &s2, float &c2)
+{
+    s2 = (s + s) * c;
+    c2 = __builtin_fmaf(c, c, -(s * s));
+}
+
+// The 13 features of one coordinate v: v, then sin and cos of 2^j pi v for
+// j = 0..5.  j = 0 and j = 3 come from the hardware sine and cosine (argument
+// in revolutions, v 2^(j-1) reduced exactly to [0, 1) by fract), the others
+// by one or two angle doublings each, which at most quadruples the sine's
+// own error: a few 1e-7, far below a BF16 or FP8 operand's spacing.
+__device__ __forceinline__ void encode13(float v, float *f)
+{
+    float sn[6], cs[6];
+    const float x0 = __builtin_amdgcn_fractf(v * 0.5f), x3 = __builtin_amdgcn_fractf(v * 4.0f);
+    sn[0] = sin_rev(x0);
+    cs[0] = cos_rev(x0);
+    sn[3] = sin_rev(x3);
+    cs[3] = cos_rev(x3);
+    double_angle(sn[0], cs[0], sn[1], cs[1]);
+    double_angle(sn[1], cs[1], sn[2], cs[2]);
+    double_angle(sn[3], cs[3], sn[4], cs[4]);
+    double_angle(sn[4], cs[4], sn[5], cs[5]);
+    f[0] = v;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        f[1 + 2 * j] = sn[j];
+        f[2 + 2 * j] = cs[j];
+    }
+}
+
 __device__ __forceinline__ int layer_of_frag(int f)
 {
     return f < kFrag0[1] ? 0 : (f < kFrag0[2] ? 1 : (f < kFrag0[3] ? 2 : (f < kFrag0[4] ? 3 : 4)));
@@ -119,6 +161,42 @@ __global__ void __launch_bounds__(256) k_mlp_prepare_bf16(gi_mlp m)
 }
 
 // FP8 weight scales: amax|W_L| / 448 (1 for an all-zero matrix)
+// FP8 per-layer scale: the smallest power of two s with amax <= 448 s (1 for
+// a tensor without range).  The candidate from the quotient's exponent is
+// corrected by exact comparisons (448 s is exact), so the rule does not
+// depend on how amax / 448 rounds.  Powers of two make the ratio of two
+// layers' scales an exponent the scaled matrix instruction applies.
+__device__ __forceinline__ float fp8_scale(float amax)
+{
+    if (!(amax > 0.0f && amax < kInf)) return 1.0f;
+    int e;
+    frexpf(amax / kFp8Max, &e);
+    float s = ldexpf(1.0f, e);
+    while (amax > kFp8Max * s) s *= 2.0f;
+    while (amax <= 0.5f * kFp8Max * s) s *= 0.5f;
+    return s;
+}
+
+// the smallest power of two >= x (x > 0 finite), else 1
+__device__ __forceinline__ float pow2_at_least(float x)
+{
+    if (!(x > 0.0f && x < kInf)) return 1.0f;
+    int e;
+    frexpf(x, &e);
+    float s = ldexpf(1.0f, e);
+    while (x > s) s *= 2.0f;
+    while (x <= 0.5f * s) s *= 0.5f;
+    return s;
+}
+
+// log2 of a power of two
+__device__ __forceinline__ int exp2_of(float pow2)
+{
+    int e;
+    frexpf(pow2, &e);
+    return e - 1;
+}
+
 __global__ void __launch_bounds__(256) k_mlp_wscale(gi_mlp m)
 {
     __shared__ float red[256];
@@ -132,7 +210,7 @@ __global__ void __launch_bounds__(256) k_mlp_wscale(gi_mlp m)
         if (t < o) red[t] = fmaxf(red[t], red[t + o]);
         __syncthreads();
     }
-    if (t == 0) m.scales[L] = red[0] > 0.0f ? red[0] / kFp8Max : 1.0f;
+    if (t == 0) m.scales[L] = fp8_scale(red[0]);
 }
 
 __device__ __forceinline__ uint32_t fp8_byte(float x)
@@ -141,20 +219,19 @@ __device__ __forceinline__ uint32_t fp8_byte(float x)
     return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFFu;
 }
 
-// FP8 operands for the K = 64 instruction (v_mfma_f32_32x32x64_f8f6f4):
+// FP8 operands for the K = 64 instruction (v_mfma_scale_f32_32x32x64_f8f6f4):
 // lane l of a fragment holds row l % 32 of a 32-row output tile and the 32
-// consecutive K slots 32 (l / 32) + b, one byte each.  Nine such fragments
-// (byte (f * 64 + l) * 32 + b): f = 0, 1 layer 0's two tiles (slots = the
-// half-wave's features 0..31), f = 2 + 2 (L - 1) + t hidden layer L tile t,
-// f = 8 the output layer.  Then two K = 16 fragments of layer 0's tiles (byte
-// kFp8K16Off + (g * 64 + l) * 8 + v: features 32..38 of half l / 32, slot 7
-// zero).  Hidden slot k = 32 h + b takes unit 32 (b >> 4) + 8 ((b >> 2) & 3)
-// + 4 h + (b & 3): the previous layer's accumulator 4a + b' of tile t sits in
-// lane half h as unit 32 t + 8 a + 4 h + b', so byte b of a lane's operand is
-// simply accumulator b of the first tile, then of the second.
-constexpr int kFp8K64Frags = 9;
-constexpr int kFp8K16Off = kFp8K64Frags * 64 * 32;
-static_assert(kFp8K16Off + 2 * 64 * 8 <= kBiasOff, "FP8 operands fit the fragment area");
+// consecutive K slots 32 (l / 32) + b, one byte each.  Eleven fragments
+// (byte (f * 64 + l) * 32 + b): f = 2 p + t layer 0's tile t, part p (part
+// 0: slots b = features 39 h + b of the half-wave h = l / 32; part 1: slots
+// b < 7 = features 39 h + 32 + b, the rest zero), f = 4 + 2 (L - 1) + t
+// hidden layer L tile t, f = 10 the output layer.  Hidden slot k = 32 h + b
+// takes unit 32 (b >> 4) + 8 ((b >> 2) & 3) + 4 h + (b & 3): the previous
+// layer's accumulator 4a + b' of tile t sits in lane half h as unit 32 t +
+// 8 a + 4 h + b', so byte b of a lane's operand is simply accumulator b of
+// the first tile, then of the second.
+constexpr int kFp8Frags = 11;
+static_assert(kFp8Frags * 64 * 32 <= kBiasOff, "FP8 operands fit the fragment area");
 
 __host__ __device__ constexpr int k64_unit(int h, int b)
 {
@@ -166,21 +243,19 @@ __global__ void __launch_bounds__(256) k_mlp_prepare_fp8(gi_mlp m)
     const int i = blockIdx.x * 256 + threadIdx.x;
     const InferSrc src = infer_src(m);
     if (i < kBiasSlots) write_bias(m, src, i);
-    int L, row, k;
-    if (i < kFp8K16Off) {
-        const int f = i >> 11, l = (i >> 5) & 63, b = i & 31, h = l >> 5;
-        const int t = f < 2 ? f : (f < 8 ? (f - 2) & 1 : 0);
-        L = f < 2 ? 0 : (f < 8 ? 1 + ((f - 2) >> 1) : 4);
-        row = 32 * t + (l & 31);
-        k = L == 0 ? 39 * h + b : k64_unit(h, b);
-    } else if (i < kFp8K16Off + 2 * 64 * 8) {
-        const int j = i - kFp8K16Off, g = j >> 9, l = (j >> 3) & 63, v = j & 7;
+    if (i >= kFp8Frags * 64 * 32) return;
+    const int f = i >> 11, l = (i >> 5) & 63, b = i & 31, h = l >> 5;
+    int L, t, k;
+    if (f < 4) {
         L = 0;
-        row = 32 * g + (l & 31);
-        k = v < 7 ? 39 * (l >> 5) + 32 + v : -1;
+        t = f & 1;
+        k = (f >> 1) == 0 ? 39 * h + b : (b < 7 ? 39 * h + 32 + b : -1);
     } else {
-        return;
+        L = f < 10 ? 1 + ((f - 4) >> 1) : 4;
+        t = f < 10 ? (f - 4) & 1 : 0;
+        k = k64_unit(h, b);
     }
+    const int row = 32 * t + (l & 31);
     float w = 0.0f;
     if (row < kOut[L] && k >= 0 && k < kIn[L]) w = src.p[kOffW[L] + row * kIn[L] + k] * src.scale / m.scales[L];
     reinterpret_cast<uint8_t *>(m.weights)[i] = (uint8_t)fp8_byte(w);
@@ -276,11 +351,11 @@ k_mlp_infer_bf16(gi_mlp m, uint32_t n, const float4 *pos, const float4 *nrm, flo
     auto frag = [&](int f) -> FT { return f < kLdsFrags ? wls[f * 64 + l] : wf[f - kLdsFrags]; };
 
     // lanes 0-31 encode the normalised position, lanes 32-63 the normal
-    float lo[3], ext[3];
+    float lo[3], rext[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         lo[a] = h ? 0.0f : m.pos_lo[a];
-        ext[a] = h ? 1.0f : m.pos_hi[a] - m.pos_lo[a];
+        rext[a] = h ? 1.0f : 1.0f / (m.pos_hi[a] - m.pos_lo[a]);
     }
     const float4 *src = h ? nrm : pos;
     const uint32_t wave = (blockIdx.x * kInferBlock + threadIdx.x) >> 6;
@@ -288,26 +363,16 @@ k_mlp_infer_bf16(gi_mlp m, uint32_t n, const float4 *pos, const float4 *nrm, flo
     const uint32_t ntiles = (n + 31u) / 32u;
 
     for (uint32_t tile = wave; tile < ntiles; tile += nwaves) {
+        const float4 in = tile_input(src, tile, ntiles, s, n);
         // the LDS fragments and biases are re-read every tile: hoisted out of
         // the loop they would take 72 more registers plus the bias tiles,
         // and cost waves (238 registers, 2 waves)
         asm volatile("" ::: "memory");
         const uint32_t idx = tile * 32u + (uint32_t)s;
         const bool ok = idx < n;
-        const float4 in = ok ? src[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         float feat[40];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const float v = (comp(in, a) - lo[a]) / ext[a];
-            feat[13 * a] = v;
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                // sin(2^j pi v) = sin of 2^(j-1) v revolutions, reduced exactly to [0, 1)
-                const float x = __builtin_amdgcn_fractf(v * (float)(1 << j) * 0.5f);
-                feat[13 * a + 1 + 2 * j] = sin_rev(x);
-                feat[13 * a + 2 + 2 * j] = cos_rev(x);
-            }
-        }
+        for (int a = 0; a < 3; ++a) encode13((comp(in, a) - lo[a]) * rext[a], feat + 13 * a);
         feat[39] = 0.0f;
 
         // layer 0: K = 80 (5 k-steps), two output tiles
@@ -350,138 +415,190 @@ k_mlp_infer_bf16(gi_mlp m, uint32_t n, const float4 *pos, const float4 *nrm, flo
 }
 
 // FP8 inference on the K = 64 instruction (twice the K = 16 instruction's
-// rate): per 32-sample tile, layer 0 is one K = 64 product (features 0..31 of
-// each half-wave) plus one K = 16 product (features 32..38) per output tile,
-// hidden layers one K = 64 product per tile, the output layer one.  Operands
-// are E4M3FN x / s with the per-layer scales of the generic kernel.  Layer
-// 0's fragments stay in LDS, the seven others in registers.
+// rate): per 32-sample tile, layer 0 is two scaled K = 64 products per
+// output tile (features 0..31, then 32..38, of each half-wave), every other
+// layer one.  Operands are E4M3FN x / s with power-of-two per-layer scales:
+// the factor s_w s_a / s_a' that takes a layer's sums to the next layer's
+// input scale is then a power of two 2^k, applied by the instruction's E8M0
+// operand scales (the bias, pre-divided by s_a', initialises the
+// accumulators), so handing an activation on costs a ReLU-and-saturate and
+// a conversion.  The fragments stay in LDS.
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ f32x16 mfma64(i32x8 a, i32x8 b, f32x16 c)
+// 2^k (A B) + C; the exponent is split over the two E8M0 operand scales
+// (both run-time values: a constant scale would be read as an FP32 constant)
+__device__ __forceinline__ f32x16 mfma64(i32x8 a, i32x8 b, f32x16 c, int k)
 {
-    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+    const int ka = k >> 1, kb = k - ka;
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127 + ka, 0, 127 + kb);
 }
 
-// 16 floats (already scaled and clamped to [-448, 448]) -> 16 E4M3FN bytes
-__device__ __forceinline__ void pack_fp8x16(const float *x, int *dst)
+// four floats (already clamped to [-448, 448]) -> one register of four
+// E4M3FN bytes.  Each conversion replaces one half of its third operand; the
+// first one's other half is overwritten by the second, so any value serves
+// as the first one's (here a's bits: no register has to be zeroed).
+__device__ __forceinline__ int pack_fp8x4(float a, float b, float c, float d)
 {
+    const int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, __builtin_bit_cast(int, a), false);
+    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+}
+
+// the same for x / scale, scale a power of two (with a, b, c, d clamped to
+// [-448 scale, 448 scale]): the conversion applies the scale exactly
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int pack_fp8x4_scaled(float a, float b, float c, float d, float scale)
+{
+    i16x2 w = __builtin_bit_cast(i16x2, a);
+    w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w, a, b, scale, false);
+    w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w, c, d, scale, true);
+    return __builtin_bit_cast(int, w);
+}
+
+// one half-wave lane's 39 features (its sample's position or normal) -> the
+// two layer-0 operands, at input scale sa0 with saturation at 448 sa0 = lim.
+// The sines and cosines need the clamp only when lim < 1 (kClampAll).
+template <bool kClampAll>
+__device__ __forceinline__ void encode_fp8(float4 in, const float *lo, const float *rext, float sa0, float lim,
+                                           i32x8 &b0, i32x8 &b1)
+{
+    float f[40];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[4 * q], x[4 * q + 1], 0, false);
-        dst[q] = __builtin_amdgcn_cvt_pk_fp8_f32(x[4 * q + 2], x[4 * q + 3], w, true);
+    for (int a = 0; a < 3; ++a) encode13((comp(in, a) - lo[a]) * rext[a], f + 13 * a);
+#pragma unroll
+    for (int v = 0; v < 39; ++v)
+        if (kClampAll || v % 13 == 0) f[v] = __builtin_amdgcn_fmed3f(f[v], -lim, lim);
+    f[39] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        b0[q] = pack_fp8x4_scaled(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3], sa0);
+        b1[q] = q < 2 ? pack_fp8x4_scaled(f[32 + 4 * q], f[33 + 4 * q], f[34 + 4 * q], f[35 + 4 * q], sa0) : 0;
     }
 }
 
-// accumulators of both tiles -> the next layer's K = 64 operand: ReLU, scale
-// to the next layer's input scale, saturate
-__device__ __forceinline__ i32x8 relu_fp8_operand(const f32x16 &a0, const f32x16 &a1, float kq)
+// accumulators of both tiles (already at the next layer's input scale) ->
+// the next layer's K = 64 operand: ReLU and saturation, then conversion
+__device__ __forceinline__ i32x8 relu_fp8_operand(const f32x16 &a0, const f32x16 &a1)
 {
-    float x[16];
     i32x8 r;
-    int *rp = reinterpret_cast<int *>(&r);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) x[v] = __builtin_amdgcn_fmed3f(a0[v] * kq, 0.0f, kFp8Max);
-    pack_fp8x16(x, rp);
-#pragma unroll
-    for (int v = 0; v < 16; ++v) x[v] = __builtin_amdgcn_fmed3f(a1[v] * kq, 0.0f, kFp8Max);
-    pack_fp8x16(x, rp + 4);
+    for (int q = 0; q < 4; ++q) {
+        r[q] = pack_fp8x4(__builtin_amdgcn_fmed3f(a0[4 * q], 0.0f, kFp8Max),
+                          __builtin_amdgcn_fmed3f(a0[4 * q + 1], 0.0f, kFp8Max),
+                          __builtin_amdgcn_fmed3f(a0[4 * q + 2], 0.0f, kFp8Max),
+                          __builtin_amdgcn_fmed3f(a0[4 * q + 3], 0.0f, kFp8Max));
+        r[4 + q] = pack_fp8x4(__builtin_amdgcn_fmed3f(a1[4 * q], 0.0f, kFp8Max),
+                              __builtin_amdgcn_fmed3f(a1[4 * q + 1], 0.0f, kFp8Max),
+                              __builtin_amdgcn_fmed3f(a1[4 * q + 2], 0.0f, kFp8Max),
+                              __builtin_amdgcn_fmed3f(a1[4 * q + 3], 0.0f, kFp8Max));
+    }
     return r;
 }
 
-__global__ void __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_mlp_infer_fp8(gi_mlp m, uint32_t n, const float4 *pos, const float4 *nrm, float4 *out, int gate)
 {
     if (gate && !mlp_selected(m)) return;   // uniform over the grid
+    // activation scales as stored, rounded up to powers of two; layer L's
+    // sums reach the next layer's input scale (the output's for L = 4)
+    // through the exponent kx[L]
     float sa[kLayers];
 #pragma unroll
-    for (int L = 0; L < kLayers; ++L) {
-        sa[L] = m.scales[5 + L];
-        if (!(sa[L] > 0.0f && sa[L] < kInf)) sa[L] = 1.0f;
-    }
-    float kq[kLayers - 1];
+    for (int L = 0; L < kLayers; ++L) sa[L] = pow2_at_least(m.scales[5 + L]);
+    int kx[kLayers];
 #pragma unroll
-    for (int L = 0; L + 1 < kLayers; ++L) kq[L] = m.scales[L] * sa[L] / sa[L + 1];
-    const float in0 = 1.0f / sa[0], smul4 = m.scales[4] * sa[4];
+    for (int L = 0; L < kLayers; ++L)
+        kx[L] = __builtin_amdgcn_readfirstlane(
+            min(max(exp2_of(m.scales[L]) + exp2_of(sa[L]) - (L + 1 < kLayers ? exp2_of(sa[L + 1]) : 0), -120), 120));
+    const float sa0 = sa[0], lim = kFp8Max * sa0;
+    const bool clamp_all = lim < 1.0f;   // uniform
     __shared__ __attribute__((aligned(16))) float sb[kBiasSlots];
     const float *bias = reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(m.weights) + kBiasOff);
     for (int i = threadIdx.x; i < kBiasSlots; i += kInferBlock) {
         const int L = i < 256 ? i >> 6 : 4;
-        sb[i] = bias[i] / (m.scales[L] * sa[L]);
+        sb[i] = L + 1 < kLayers ? bias[i] / sa[L + 1] : bias[i];
     }
-    // layer 0's fragments in LDS: two K = 64 (32 B per lane), two K = 16 (8 B)
-    __shared__ i32x8 w0[2 * 64];
-    __shared__ long w0b[2 * 64];
+    // all eleven fragments in LDS (32 B per lane each), read per tile
+    __shared__ i32x8 wl[kFp8Frags * 64];
     const i32x8 *w64 = reinterpret_cast<const i32x8 *>(m.weights);
-    const long *w16 = reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(m.weights) + kFp8K16Off);
-    for (int i = threadIdx.x; i < 2 * 64; i += kInferBlock) {
-        w0[i] = w64[i];
-        w0b[i] = w16[i];
-    }
+    for (int i = threadIdx.x; i < kFp8Frags * 64; i += kInferBlock) wl[i] = w64[i];
     __syncthreads();
     const int l = threadIdx.x & 63, s = l & 31, h = l >> 5;
-    i32x8 wf[kFp8K64Frags - 2];
-#pragma unroll
-    for (int f = 0; f < kFp8K64Frags - 2; ++f) wf[f] = w64[(2 + f) * 64 + l];
 
-    float lo[3], ext[3];
+    float lo[3], rext[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         lo[a] = h ? 0.0f : m.pos_lo[a];
-        ext[a] = h ? 1.0f : m.pos_hi[a] - m.pos_lo[a];
+        rext[a] = h ? 1.0f : 1.0f / (m.pos_hi[a] - m.pos_lo[a]);
     }
     const float4 *src = h ? nrm : pos;
     const uint32_t wave = (blockIdx.x * kInferBlock + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * kInferBlock) >> 6;
     const uint32_t ntiles = (n + 31u) / 32u;
 
-    for (uint32_t tile = wave; tile < ntiles; tile += nwaves) {
-        asm volatile("" ::: "memory");   // re-read layer 0's fragments and the biases per tile
-        const uint32_t idx = tile * 32u + (uint32_t)s;
-        const bool ok = idx < n;
-        const float4 in = ok ? src[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        float feat[40];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const float v = (comp(in, a) - lo[a]) / ext[a];
-            feat[13 * a] = v;
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                const float x = __builtin_amdgcn_fractf(v * (float)(1 << j) * 0.5f);
-                feat[13 * a + 1 + 2 * j] = sin_rev(x);
-                feat[13 * a + 2 + 2 * j] = cos_rev(x);
-            }
+    // Two adjacent tiles per iteration: the fragments and biases read from
+    // LDS serve both, and one tile's activations are converted while the
+    // other's products run.  A layer's fragments and biases are read where
+    // it runs, through an offset the compiler cannot see through (hoisted
+    // to the top of the iteration, all eleven fragments would be spilled to
+    // scratch).  The operands of a scaled product stay allocated until its
+    // sums have been read: written while the instruction is in flight, they
+    // would reach it corrupted, so each layer's empty asm takes the previous
+    // layer's operands next to the new activation operands.
+    for (uint32_t tile = 2 * wave; tile < ntiles; tile += 2 * nwaves) {
+        const float4 inA = tile_input(src, tile, ntiles, s, n), inB = tile_input(src, tile + 1, ntiles, s, n);
+        const uint32_t idxA = tile * 32u + (uint32_t)s, idxB = idxA + 32u;
+        const bool okA = idxA < n, okB = tile + 1 < ntiles && idxB < n;
+        i32x8 a0, a1, b0, b1;
+        if (clamp_all) {
+            encode_fp8<true>(inA, lo, rext, sa0, lim, a0, a1);
+            encode_fp8<true>(inB, lo, rext, sa0, lim, b0, b1);
+        } else {
+            encode_fp8<false>(inA, lo, rext, sa0, lim, a0, a1);
+            encode_fp8<false>(inB, lo, rext, sa0, lim, b0, b1);
         }
-        feat[39] = 0.0f;
+        uint32_t o = 0;
+        asm volatile("" : "+v"(o) : "v"(a0[0]), "v"(b0[0]));
+        const i32x8 fa = wl[o + l], fb = wl[o + 64 + l], fc = wl[o + 128 + l], fd = wl[o + 192 + l];
+        const f32x16 c0 = bias_tile(sb + o, h), c1 = bias_tile(sb + o + 32, h);
+        f32x16 A0 = mfma64(fa, a0, c0, kx[0]);
+        f32x16 A1 = mfma64(fb, a0, c1, kx[0]);
+        f32x16 B0 = mfma64(fa, b0, c0, kx[0]);
+        f32x16 B1 = mfma64(fb, b0, c1, kx[0]);
+        A0 = mfma64(fc, a1, A0, kx[0]);
+        A1 = mfma64(fd, a1, A1, kx[0]);
+        B0 = mfma64(fc, b1, B0, kx[0]);
+        B1 = mfma64(fd, b1, B1, kx[0]);
+        i32x8 opA = relu_fp8_operand(A0, A1);
+        i32x8 opB = relu_fp8_operand(B0, B1);
+        o = 0;
+        asm volatile("" : "+v"(o) : "v"(opA), "v"(opB), "v"(a0), "v"(a1), "v"(b0), "v"(b1), "v"(fa), "v"(fb), "v"(fc),
+                     "v"(fd));
 #pragma unroll
-        for (int v = 0; v < 40; ++v) feat[v] = __builtin_amdgcn_fmed3f(feat[v] * in0, -kFp8Max, kFp8Max);
-        i32x8 b64;
-        int *bp = reinterpret_cast<int *>(&b64);
-        pack_fp8x16(feat, bp);
-        pack_fp8x16(feat + 16, bp + 4);
-        long b16;
-        {
-            int lo2 = __builtin_amdgcn_cvt_pk_fp8_f32(feat[32], feat[33], 0, false);
-            lo2 = __builtin_amdgcn_cvt_pk_fp8_f32(feat[34], feat[35], lo2, true);
-            int hi2 = __builtin_amdgcn_cvt_pk_fp8_f32(feat[36], feat[37], 0, false);
-            hi2 = __builtin_amdgcn_cvt_pk_fp8_f32(feat[38], feat[39], hi2, true);
-            b16 = (long)(((uint64_t)(uint32_t)hi2 << 32) | (uint32_t)lo2);
+        for (int L = 1; L < kLayers - 1; ++L) {
+            const i32x8 f0 = wl[o + (2 + 2 * L) * 64 + l], f1 = wl[o + (3 + 2 * L) * 64 + l];
+            const f32x16 d0 = bias_tile(sb + o + 64 * L, h), d1 = bias_tile(sb + o + 64 * L + 32, h);
+            A0 = mfma64(f0, opA, d0, kx[L]);
+            A1 = mfma64(f1, opA, d1, kx[L]);
+            B0 = mfma64(f0, opB, d0, kx[L]);
+            B1 = mfma64(f1, opB, d1, kx[L]);
+            const i32x8 nA = relu_fp8_operand(A0, A1);
+            const i32x8 nB = relu_fp8_operand(B0, B1);
+            o = 0;
+            asm volatile("" : "+v"(o) : "v"(nA), "v"(nB), "v"(opA), "v"(opB), "v"(f0), "v"(f1));
+            opA = nA;
+            opB = nB;
         }
-        f32x16 acc0 = bias_tile(sb, h), acc1 = bias_tile(sb + 32, h);
-        acc0 = mfma64(w0[l], b64, acc0);
-        acc1 = mfma64(w0[64 + l], b64, acc1);
-        acc0 = mfma(w0b[l], b16, acc0);
-        acc1 = mfma(w0b[64 + l], b16, acc1);
-#pragma unroll
-        for (int L = 1; L < kLayers; ++L) {
-            const i32x8 bop = relu_fp8_operand(acc0, acc1, kq[L - 1]);
-            if (L < kLayers - 1) {
-                acc0 = mfma64(wf[2 * (L - 1)], bop, bias_tile(sb + 64 * L, h));
-                acc1 = mfma64(wf[2 * (L - 1) + 1], bop, bias_tile(sb + 64 * L + 32, h));
-            } else {
-                acc0 = mfma64(wf[6], bop, bias_tile(sb + 256, h));
-            }
+        const i32x8 f4 = wl[o + 10 * 64 + l];
+        const f32x16 d4 = bias_tile(sb + o + 256, h);
+        A0 = mfma64(f4, opA, d4, kx[kLayers - 1]);
+        B0 = mfma64(f4, opB, d4, kx[kLayers - 1]);
+        const float touched = A0[0] + B0[0];
+        asm volatile("" ::"v"(touched), "v"(opA), "v"(opB), "v"(f4));
+        // output rows 0..2 sit in accumulators 0..2 of the lower half-wave
+        if (h == 0) {
+            if (okA) out[idxA] = make_float4(A0[0], A0[1], A0[2], 0.0f);
+            if (okB) out[idxB] = make_float4(B0[0], B0[1], B0[2], 0.0f);
         }
-        if (ok && h == 0) out[idx] = make_float4(acc0[0] * smul4, acc0[1] * smul4, acc0[2] * smul4, 0.0f);
     }
 }
 
@@ -889,7 +1006,7 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(gi_mlp m, uint32_t nwg, cons
     } else if (j == kStNonFinite) {
         m.state[GI_MLP_STATE_NONFINITE] = (uint32_t)acc;
     } else if (is_max) {
-        m.scales[5 + (j - kStAmax0)] = acc > 0.0f ? acc / kFp8Max : 1.0f;
+        m.scales[5 + (j - kStAmax0)] = fp8_scale(acc);
     }
 }
 
@@ -965,12 +1082,11 @@ gi_status scratch_address(void **out)
 
 gi_status prepare(const gi_mlp &m, hipStream_t st)
 {
-    const int blocks = (kFrags * 64 * 8 + 255) / 256;
     if (m.precision == GI_MLP_BF16) {
-        k_mlp_prepare_bf16<<<blocks, 256, 0, st>>>(m);
+        k_mlp_prepare_bf16<<<(kFrags * 64 * 8 + 255) / 256, 256, 0, st>>>(m);
     } else {
         k_mlp_wscale<<<kLayers, 256, 0, st>>>(m);
-        k_mlp_prepare_fp8<<<blocks, 256, 0, st>>>(m);
+        k_mlp_prepare_fp8<<<(kFp8Frags * 64 * 32 + 255) / 256, 256, 0, st>>>(m);
     }
     return launched_mlp();
 }

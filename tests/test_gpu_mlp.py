@@ -15,6 +15,7 @@
   untrained network's.
 """
 import dataclasses
+import math
 import sys
 
 import numpy as np
@@ -220,10 +221,13 @@ def test_mlp_grad(gi, n):
     relu_out = np.maximum(out, 0.0)
     be = np.abs(relu_out - q)[valid].sum() / (q[valid] + 0.01).sum()
     assert st["batch_err"] == pytest.approx(be, rel=2e-3)
-    # activation amax of every layer input (valid samples), FP8 scales
+    # activation amax of every layer input (valid samples) -> FP8 scales:
+    # the smallest power of two s with amax <= 448 s (the kernel's amax comes
+    # from its own BF16 forward, hence the 2 % slack at both ends)
     amax = M.act_amax(params, X[valid])
-    sa = m.scales[5:10].cpu().numpy() * 448.0
-    assert np.allclose(sa, amax, rtol=2e-2), (sa, amax)
+    sa = m.scales[5:10].cpu().numpy().astype(np.float64)
+    assert all(math.frexp(float(v))[0] == 0.5 for v in sa), sa
+    assert np.all(amax <= 448.0 * sa * 1.02) and np.all(amax > 224.0 * sa * 0.98), (sa, amax)
 
 
 def test_mlp_adam(gi):

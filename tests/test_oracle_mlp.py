@@ -198,6 +198,19 @@ def test_bf16_training_semantics_match_torch():
     assert np.max(np.abs(out - ref)) < 0.05 * (np.max(np.abs(ref)) + 1e-3)
 
 
+def test_fp8_scales_are_powers_of_two_covering_the_range():
+    rng = np.random.default_rng(12)
+    for amax in list(rng.uniform(1e-6, 1e4, 200)) + [448.0, 224.0, 448.0 * 2 ** -20, 3.0 * 2 ** -130]:
+        s = M.fp8_scale(amax)
+        m, e = math.frexp(s)
+        assert m == 0.5                                  # a power of two
+        assert amax <= 448.0 * s and amax > 224.0 * s    # the smallest that covers amax
+    assert M.fp8_scale(0.0) == 1.0 and M.fp8_scale(float("inf")) == 1.0
+    for x in list(rng.uniform(1e-8, 1e3, 200)) + [1.0, 0.5, 2.0 ** -40]:
+        p = M.pow2_at_least(x)
+        assert math.frexp(p)[0] == 0.5 and x <= p < 2 * x
+
+
 def test_fp8_forward_matches_torch_casts():
     params = M.init_params(9)
     X = _batch(40, 7)
@@ -207,10 +220,12 @@ def test_fp8_forward_matches_torch_casts():
     h = torch.tensor(X)
     f8 = torch.float8_e4m3fn
     for li, (W, b) in enumerate(M.split(params)):
-        sw = float(np.max(np.abs(W))) / 448.0
-        a8 = (h / sa[li]).clamp(-448, 448).to(torch.float32).to(f8).to(torch.float64)
+        # power-of-two scales: weights from amax|W|, activations rounded up
+        sw = 2.0 ** math.ceil(math.log2(float(np.max(np.abs(W))) / 448.0))
+        sa_l = 2.0 ** math.ceil(math.log2(sa[li]))
+        a8 = (h / sa_l).clamp(-448, 448).to(torch.float32).to(f8).to(torch.float64)
         w8 = (torch.tensor(W) / sw).to(torch.float32).to(f8).to(torch.float64)
-        h = (a8 @ w8.T) * (sw * sa[li]) + torch.tensor(b)
+        h = (a8 @ w8.T) * (sw * sa_l) + torch.tensor(b)
         if li < 4:
             h = torch.relu(h)
     assert np.allclose(out, h.numpy(), rtol=1e-12, atol=1e-12)
