@@ -623,10 +623,11 @@ __device__ __forceinline__ uint32_t block_sum_1024(uint32_t v, uint32_t *red)
 __global__ void __launch_bounds__(1024) k_mlp_count(uint32_t n, const float4 *tgt, uint32_t *hdr)
 {
     __shared__ uint32_t red[16];
+    // 16 independent loads in flight per thread and round
     uint32_t c = 0;
-    for (uint32_t i = threadIdx.x; i < n; i += 4096) {
+    for (uint32_t i = threadIdx.x; i < n; i += 16384) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 16; ++k) {
             const uint32_t j = i + 1024u * k;
             if (j < n) c += tgt[j].w != 0.0f ? 1u : 0u;
         }
@@ -696,6 +697,24 @@ __device__ __forceinline__ float half_sum(float v)
     for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+// The same sum by DPP moves (no LDS round trips), in a fixed order: pairs,
+// quads, mirrored halves of each row of 16 lanes, mirrored rows, then row 0's
+// total broadcast into row 1 and row 2's into row 3.  The half-wave's total
+// lands in its upper 16 lanes (16-31 and 48-63).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_add(float v)
+{
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl, kRowMask,
+                                                                     0xF, false));
+}
+__device__ __forceinline__ float half_sum_dpp(float v)
+{
+    v = dpp_add<0xB1, 0xF>(v);     // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4E, 0xF>(v);     // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x141, 0xF>(v);    // row_half_mirror
+    v = dpp_add<0x140, 0xF>(v);    // row_mirror
+    return dpp_add<0x142, 0xA>(v); // row_bcast:15 into rows 1 and 3
+}
 __device__ __forceinline__ float half_max(float v)
 {
 #pragma unroll
@@ -722,12 +741,22 @@ __global__ void __launch_bounds__(kMBlock) k_mlp_fwdbwd_mfma(gi_mlp m, uint32_t 
     __shared__ __attribute__((aligned(16))) __bf16 sG[64 * kMS];       // BF16 gradient [unit][sample]
     __shared__ float sDb[2][64];                                       // bias gradient per wave
     __shared__ float sSt[2][kStats];
+    // all 64 forward and backward fragments staged in LDS (64 KB): each
+    // layer's operands are then an LDS read away instead of an L2 round trip
+    __shared__ bf16x8 sF[(kFwdFrags + kBwdFrags) * 64];
+    for (int i = threadIdx.x; i < (kFwdFrags + kBwdFrags) * 64; i += kMBlock) sF[i] = frags[i];
+    // the biases too (layer L's at 64 L, the output layer's at 256)
+    __shared__ float sBias[kBiasSlots];
+    for (int i = threadIdx.x; i < kBiasSlots; i += kMBlock) {
+        const int L = i < 256 ? i >> 6 : 4, u = i < 256 ? i & 63 : i - 256;
+        sBias[i] = u < kOut[L] ? m.params[kOffB[L] + u] : 0.0f;
+    }
 
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, s = l & 31, h = l >> 5;
     const int sl = 32 * wv + s;                                        // sample within the workgroup
     const uint32_t idx = blockIdx.x * kMS + sl;
     float *pw = part + (size_t)blockIdx.x * kPartStride;
-    const bf16x8 *bfr = frags + kFwdFrags * 64;
+    const bf16x8 *bfr = sF + kFwdFrags * 64;
 
     // inputs and encoding: lanes 0-31 the position's 39 features, 32-63 the normal's
     const float4 tg = idx < n ? tgt[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -736,15 +765,8 @@ __global__ void __launch_bounds__(kMBlock) k_mlp_fwdbwd_mfma(gi_mlp m, uint32_t 
     float feat[40];
     float amax[kLayers] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float v = h ? comp(in, a) : (comp(in, a) - m.pos_lo[a]) / (m.pos_hi[a] - m.pos_lo[a]);
-        feat[13 * a] = v;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            feat[13 * a + 1 + 2 * j] = sinpif(ldexpf(v, j));
-            feat[13 * a + 2 + 2 * j] = cospif(ldexpf(v, j));
-        }
-    }
+    for (int a = 0; a < 3; ++a)
+        encode13(h ? comp(in, a) : (comp(in, a) - m.pos_lo[a]) / (m.pos_hi[a] - m.pos_lo[a]), feat + 13 * a);
     feat[39] = 0.0f;
 #pragma unroll
     for (int j = 0; j < 39; ++j) {
@@ -757,6 +779,8 @@ __global__ void __launch_bounds__(kMBlock) k_mlp_fwdbwd_mfma(gi_mlp m, uint32_t 
         sX[79 * kMS + sl] = (__bf16)0.0f;
     }
 
+    __syncthreads();   // sF
+
     // forward
     uint32_t mask[kLayers - 1];
     f32x16 acc0, acc1;
@@ -767,8 +791,8 @@ __global__ void __launch_bounds__(kMBlock) k_mlp_fwdbwd_mfma(gi_mlp m, uint32_t 
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                acc0[4 * a + b] = m.params[kOffB[0] + 8 * a + 4 * h + b];
-                acc1[4 * a + b] = m.params[kOffB[0] + 32 + 8 * a + 4 * h + b];
+                acc0[4 * a + b] = sBias[8 * a + 4 * h + b];
+                acc1[4 * a + b] = sBias[32 + 8 * a + 4 * h + b];
             }
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
@@ -776,8 +800,8 @@ __global__ void __launch_bounds__(kMBlock) k_mlp_fwdbwd_mfma(gi_mlp m, uint32_t 
 #pragma unroll
             for (int v = 0; v < 8; ++v) x[v] = feat[8 * c + v];
             const bf16x8 b = to_bf16(x);
-            acc0 = mfma(frags[c * 64 + l], b, acc0);
-            acc1 = mfma(frags[(5 + c) * 64 + l], b, acc1);
+            acc0 = mfma(sF[c * 64 + l], b, acc0);
+            acc1 = mfma(sF[(5 + c) * 64 + l], b, acc1);
         }
     }
 #pragma unroll
@@ -807,20 +831,20 @@ __global__ void __launch_bounds__(kMBlock) k_mlp_fwdbwd_mfma(gi_mlp m, uint32_t 
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    acc0[4 * a + b] = m.params[kOffB[L] + 8 * a + 4 * h + b];
-                    acc1[4 * a + b] = m.params[kOffB[L] + 32 + 8 * a + 4 * h + b];
+                    acc0[4 * a + b] = sBias[64 * L + 8 * a + 4 * h + b];
+                    acc1[4 * a + b] = sBias[64 * L + 32 + 8 * a + 4 * h + b];
                 }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                acc0 = mfma(frags[(f0 + c) * 64 + l], bop[c], acc0);
-                acc1 = mfma(frags[(f0 + 4 + c) * 64 + l], bop[c], acc1);
+                acc0 = mfma(sF[(f0 + c) * 64 + l], bop[c], acc0);
+                acc1 = mfma(sF[(f0 + 4 + c) * 64 + l], bop[c], acc1);
             }
         } else {
             acc0 = f32x16{};
 #pragma unroll
-            for (int b = 0; b < 3; ++b) acc0[b] = h ? 0.0f : m.params[kOffB[4] + b];
+            for (int b = 0; b < 3; ++b) acc0[b] = h ? 0.0f : sBias[256 + b];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc0 = mfma(frags[(f0 + c) * 64 + l], bop[c], acc0);
+            for (int c = 0; c < 4; ++c) acc0 = mfma(sF[(f0 + c) * 64 + l], bop[c], acc0);
         }
     }
     // loss gradient (lower half-wave: outputs 0..2 in accumulators 0..2)
@@ -859,14 +883,16 @@ __global__ void __launch_bounds__(kMBlock) k_mlp_fwdbwd_mfma(gi_mlp m, uint32_t 
 
     // backward: layer 4 first (3 output units)
     f32x16 g0, g1;     // this lane's gradient of the current layer's pre-activation
+    // unrolled: every layer's sizes and offsets are constants
+#pragma unroll
     for (int L = kLayers - 1; L >= 0; --L) {
         const int out = kOut[L], in = kIn[L];
         // bias gradient (unrounded FP32 g) and the BF16 gradient in LDS [unit][sample]
         if (L == kLayers - 1) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const float sum = half_sum(g[c]);
-                if (l == 0) sDb[wv][c] = sum;
+                const float sum = half_sum_dpp(g[c]);
+                if (l == 31) sDb[wv][c] = sum;
             }
             if (h == 0) {
 #pragma unroll
@@ -879,8 +905,8 @@ __global__ void __launch_bounds__(kMBlock) k_mlp_fwdbwd_mfma(gi_mlp m, uint32_t 
                 for (int i = 0; i < 16; ++i) {
                     const float v = t ? g1[i] : g0[i];
                     const int u = 32 * t + 8 * (i >> 2) + 4 * h + (i & 3);
-                    const float sum = half_sum(v);
-                    if (s == 0) sDb[wv][u] = sum;
+                    const float sum = half_sum_dpp(v);
+                    if (s == 31) sDb[wv][u] = sum;
                     sG[u * kMS + sl] = (__bf16)v;
                 }
         }
@@ -969,11 +995,14 @@ __global__ void __launch_bounds__(256) k_mlp_reduce1(uint32_t nwg, float *part)
     if (p >= kParams + kStats) return;
     const uint32_t w0 = blockIdx.y * kGroup, w1 = min(w0 + kGroup, nwg);
     const bool is_max = stat_is_max(p);
+    // the group's loads are all issued before the first add; the order of
+    // the adds is the partials' order
+    float x[kGroup];
+#pragma unroll
+    for (uint32_t k = 0; k < kGroup; ++k) x[k] = w0 + k < w1 ? part[(size_t)(w0 + k) * kPartStride + p] : 0.0f;
     float acc = 0.0f;
-    for (uint32_t w = w0; w < w1; ++w) {
-        const float x = part[(size_t)w * kPartStride + p];
-        acc = is_max ? fmaxf(acc, x) : acc + x;
-    }
+#pragma unroll
+    for (uint32_t k = 0; k < kGroup; ++k) acc = is_max ? fmaxf(acc, x[k]) : acc + x[k];
     part[(size_t)w0 * kPartStride + p] = acc;
 }
 
@@ -985,10 +1014,17 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(gi_mlp m, uint32_t nwg, cons
     if (p >= kParams + kStats) return;
     const int j = p - kParams;
     const bool is_max = stat_is_max(p);
+    // group sums in group order, 16 loads in flight per round
     float acc = 0.0f;
-    for (uint32_t w = 0; w < nwg; w += kGroup) {
-        const float x = part[(size_t)w * kPartStride + p];
-        acc = is_max ? fmaxf(acc, x) : acc + x;
+    for (uint32_t w = 0; w < nwg; w += 16 * kGroup) {
+        float x[16];
+#pragma unroll
+        for (uint32_t k = 0; k < 16; ++k) {
+            const uint32_t wk = w + k * kGroup;
+            x[k] = wk < nwg ? part[(size_t)wk * kPartStride + p] : 0.0f;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 16; ++k) acc = is_max ? fmaxf(acc, x[k]) : acc + x[k];
     }
     if (j < 0) {
         grad[p] = acc;
@@ -1028,8 +1064,14 @@ __global__ void __launch_bounds__(256) k_mlp_adam(gi_mlp m, const float *grad, f
 __global__ void __launch_bounds__(1024) k_mlp_state(gi_mlp m, uint32_t t)
 {
     __shared__ uint32_t red[16];
+    // all of a thread's loads in flight at once
     uint32_t bad = 0;
-    for (int p = threadIdx.x; p < kParams; p += 1024) bad += __builtin_isfinite(m.params[p]) ? 0u : 1u;
+    constexpr int kPer = (kParams + 1023) / 1024;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int p = threadIdx.x + 1024 * k;
+        if (p < kParams) bad += __builtin_isfinite(m.params[p]) ? 0u : 1u;
+    }
     const uint32_t nonfinite = block_sum_1024(bad, red);
     if (threadIdx.x == 0) {
         const float be = __uint_as_float(m.state[GI_MLP_STATE_BATCH_ERR]);
