@@ -425,12 +425,22 @@ k_mlp_infer_bf16(gi_mlp m, uint32_t n, const float4 *pos, const float4 *nrm, flo
 // a conversion.  The fragments stay in LDS.
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-// 2^k (A B) + C; the exponent is split over the two E8M0 operand scales
-// (both run-time values: a constant scale would be read as an FP32 constant)
-__device__ __forceinline__ f32x16 mfma64(i32x8 a, i32x8 b, f32x16 c, int k)
+// The exponent k of 2^k (A B) + C, split over the instruction's two E8M0
+// operand scales.  Both are run-time values (a constant scale operand would
+// be read as an FP32 constant), passed through an empty asm so that they sit
+// in registers the layer's liveness asm can name.
+struct E8M0Pair {
+    int a, b;
+};
+__device__ __forceinline__ E8M0Pair e8m0_pair(int k)
 {
-    const int ka = k >> 1, kb = k - ka;
-    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127 + ka, 0, 127 + kb);
+    int a = 127 + (k >> 1), b = 127 + k - (k >> 1);
+    asm volatile("" : "+v"(a), "+v"(b));
+    return {a, b};
+}
+__device__ __forceinline__ f32x16 mfma64(i32x8 a, i32x8 b, f32x16 c, E8M0Pair q)
+{
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, q.a, 0, q.b);
 }
 
 // four floats (already clamped to [-448, 448]) -> one register of four
@@ -540,10 +550,11 @@ k_mlp_infer_fp8(gi_mlp m, uint32_t n, const float4 *pos, const float4 *nrm, floa
     // other's products run.  A layer's fragments and biases are read where
     // it runs, through an offset the compiler cannot see through (hoisted
     // to the top of the iteration, all eleven fragments would be spilled to
-    // scratch).  The operands of a scaled product stay allocated until its
-    // sums have been read: written while the instruction is in flight, they
-    // would reach it corrupted, so each layer's empty asm takes the previous
-    // layer's operands next to the new activation operands.
+    // scratch).  The operands of a scaled product (A, B and the two scale
+    // registers) stay allocated until its sums have been read: written while
+    // the instruction is in flight, A and B reached it corrupted, so each
+    // layer's empty asm takes the layer's operands next to the new activation
+    // operands.
     for (uint32_t tile = 2 * wave; tile < ntiles; tile += 2 * nwaves) {
         const float4 inA = tile_input(src, tile, ntiles, s, n), inB = tile_input(src, tile + 1, ntiles, s, n);
         const uint32_t idxA = tile * 32u + (uint32_t)s, idxB = idxA + 32u;
@@ -560,40 +571,43 @@ k_mlp_infer_fp8(gi_mlp m, uint32_t n, const float4 *pos, const float4 *nrm, floa
         asm volatile("" : "+v"(o) : "v"(a0[0]), "v"(b0[0]));
         const i32x8 fa = wl[o + l], fb = wl[o + 64 + l], fc = wl[o + 128 + l], fd = wl[o + 192 + l];
         const f32x16 c0 = bias_tile(sb + o, h), c1 = bias_tile(sb + o + 32, h);
-        f32x16 A0 = mfma64(fa, a0, c0, kx[0]);
-        f32x16 A1 = mfma64(fb, a0, c1, kx[0]);
-        f32x16 B0 = mfma64(fa, b0, c0, kx[0]);
-        f32x16 B1 = mfma64(fb, b0, c1, kx[0]);
-        A0 = mfma64(fc, a1, A0, kx[0]);
-        A1 = mfma64(fd, a1, A1, kx[0]);
-        B0 = mfma64(fc, b1, B0, kx[0]);
-        B1 = mfma64(fd, b1, B1, kx[0]);
+        const E8M0Pair q0 = e8m0_pair(kx[0]);
+        f32x16 A0 = mfma64(fa, a0, c0, q0);
+        f32x16 A1 = mfma64(fb, a0, c1, q0);
+        f32x16 B0 = mfma64(fa, b0, c0, q0);
+        f32x16 B1 = mfma64(fb, b0, c1, q0);
+        A0 = mfma64(fc, a1, A0, q0);
+        A1 = mfma64(fd, a1, A1, q0);
+        B0 = mfma64(fc, b1, B0, q0);
+        B1 = mfma64(fd, b1, B1, q0);
         i32x8 opA = relu_fp8_operand(A0, A1);
         i32x8 opB = relu_fp8_operand(B0, B1);
         o = 0;
         asm volatile("" : "+v"(o) : "v"(opA), "v"(opB), "v"(a0), "v"(a1), "v"(b0), "v"(b1), "v"(fa), "v"(fb), "v"(fc),
-                     "v"(fd));
+                     "v"(fd), "v"(q0.a), "v"(q0.b));
 #pragma unroll
         for (int L = 1; L < kLayers - 1; ++L) {
             const i32x8 f0 = wl[o + (2 + 2 * L) * 64 + l], f1 = wl[o + (3 + 2 * L) * 64 + l];
             const f32x16 d0 = bias_tile(sb + o + 64 * L, h), d1 = bias_tile(sb + o + 64 * L + 32, h);
-            A0 = mfma64(f0, opA, d0, kx[L]);
-            A1 = mfma64(f1, opA, d1, kx[L]);
-            B0 = mfma64(f0, opB, d0, kx[L]);
-            B1 = mfma64(f1, opB, d1, kx[L]);
+            const E8M0Pair q = e8m0_pair(kx[L]);
+            A0 = mfma64(f0, opA, d0, q);
+            A1 = mfma64(f1, opA, d1, q);
+            B0 = mfma64(f0, opB, d0, q);
+            B1 = mfma64(f1, opB, d1, q);
             const i32x8 nA = relu_fp8_operand(A0, A1);
             const i32x8 nB = relu_fp8_operand(B0, B1);
             o = 0;
-            asm volatile("" : "+v"(o) : "v"(nA), "v"(nB), "v"(opA), "v"(opB), "v"(f0), "v"(f1));
+            asm volatile("" : "+v"(o) : "v"(nA), "v"(nB), "v"(opA), "v"(opB), "v"(f0), "v"(f1), "v"(q.a), "v"(q.b));
             opA = nA;
             opB = nB;
         }
         const i32x8 f4 = wl[o + 10 * 64 + l];
         const f32x16 d4 = bias_tile(sb + o + 256, h);
-        A0 = mfma64(f4, opA, d4, kx[kLayers - 1]);
-        B0 = mfma64(f4, opB, d4, kx[kLayers - 1]);
+        const E8M0Pair q4 = e8m0_pair(kx[kLayers - 1]);
+        A0 = mfma64(f4, opA, d4, q4);
+        B0 = mfma64(f4, opB, d4, q4);
         const float touched = A0[0] + B0[0];
-        asm volatile("" ::"v"(touched), "v"(opA), "v"(opB), "v"(f4));
+        asm volatile("" ::"v"(touched), "v"(opA), "v"(opB), "v"(f4), "v"(q4.a), "v"(q4.b));
         // output rows 0..2 sit in accumulators 0..2 of the lower half-wave
         if (h == 0) {
             if (okA) out[idxA] = make_float4(A0[0], A0[1], A0[2], 0.0f);
