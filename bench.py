@@ -303,7 +303,7 @@ def mlp_form(gi, sg, torch, cfg, precision, steps, warmup, mode="always", train_
         "resampling_only_pixels_per_s": npx / (res_ms * 1e-3),
         "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
         "train": {"samples_per_frame": r.batch.n, "adam_steps_per_frame": r.mlp_steps,
-                  "loss": st["loss"], "ema_rel_err_vs_probe": st["ema_err"], "usable": st["usable"]},
+                  "loss": st["loss"], "ema_sq_err_ratio_vs_probe": st["ema_err"], "usable": st["usable"]},
         "infer_kernel": {"samples": n, "ms": t_inf, "bound": "mfma", "achieved": tflops,
                          "peak": MFMA_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
                          "frac": tflops / MFMA_PEAK_TFLOPS[precision], "flop_per_sample": MLP_FLOP},
@@ -386,7 +386,7 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
             per_seed.append(m["mse"])
             if mlp is not None:
                 st = r.mlp.state_words()
-                train.append({"loss": st["loss"], "ema_rel_err_vs_probe": st["ema_err"], "usable": st["usable"]})
+                train.append({"loss": st["loss"], "ema_sq_err_ratio_vs_probe": st["ema_err"], "usable": st["usable"]})
             del r
             torch.cuda.empty_cache()
         rec = {k: sum(v) / len(v) for k, v in acc.items()}

@@ -349,10 +349,10 @@ typedef enum gi_mlp_mode {
 #define GI_MLP_STATE_USABLE 0     /* 1 when AUTO mode uses the cache */
 #define GI_MLP_STATE_STEPS 1      /* Adam steps taken */
 #define GI_MLP_STATE_NONFINITE 2  /* non-finite outputs in the last training batch */
-#define GI_MLP_STATE_EMA_ERR 3    /* EMA of the relative error vs the probe query (float) */
+#define GI_MLP_STATE_EMA_ERR 3    /* EMA of BATCH_ERR (float) */
 #define GI_MLP_STATE_LOSS 4       /* loss of the last training batch (float) */
 #define GI_MLP_STATE_VALID 5      /* valid samples in the last training batch */
-#define GI_MLP_STATE_BATCH_ERR 6  /* relative error of the last batch (float) */
+#define GI_MLP_STATE_BATCH_ERR 6  /* cache / probe squared-error ratio of the last batch (float) */
 #define GI_MLP_STATE_WORDS 16
 
 typedef struct gi_mlp {
@@ -371,7 +371,8 @@ typedef struct gi_mlp {
     uint32_t precision;   /* gi_mlp_precision of inference */
     uint32_t mode;        /* gi_mlp_mode */
     uint32_t warmup_steps;/* AUTO: Adam steps before the cache may be used */
-    float max_rel_err;    /* AUTO: largest EMA relative error vs the probe query, > 0 */
+    float max_rel_err;    /* AUTO: largest EMA of the cache / probe squared-error ratio, > 0 (1: the
+                             cache is used while it predicts the labels no worse than the probes) */
     float ema_decay;      /* decay of the parameter average, in [0, 1) */
     uint32_t pad;
 } gi_mlp;
@@ -419,8 +420,11 @@ uint64_t gi_mlp_train_workspace_bytes(uint32_t n);
 /* Gradient of the relative-L2 loss, mean over valid samples and channels of
  * (C - t)^2 / (sg(C)^2 + 0.01), with BF16 operands as above; writes grad
  * (GI_MLP_N_PARAMS floats, caller-owned) and, into state, LOSS, VALID,
- * NONFINITE and BATCH_ERR = sum |max(0,C) - q| / sum (q + 0.01) over valid
- * samples and channels (q from qprobe4, which may be NULL: error 0); writes
+ * NONFINITE and BATCH_ERR = sum (max(0,C) - t)^2 / sum (q - t)^2 over valid
+ * samples and channels: the squared error of the cache, as the target uses
+ * it, against the batch's labels t relative to that of the probe query q
+ * (qprobe4; NULL gives 0; a zero denominator gives FLT_MAX unless the
+ * numerator is zero too); writes
  * the FP8 scale of every layer input, the smallest power of two s with
  * activation amax <= 448 s (1 when the amax is 0), into scales[5..9].  The sums
  * are reduced in a fixed order (deterministic). */

@@ -33,6 +33,7 @@ typedef float f32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kInferBlock = 256;
+constexpr float kFltMax = 3.40282347e38f;
 constexpr int kStats = 16;             // per-workgroup statistics after the gradient
 constexpr int kPartStride = 17792;     // >= kParams + kStats, multiple of 64
 constexpr int kHdr = 64;               // workspace header words
@@ -874,8 +875,13 @@ __global__ void __launch_bounds__(kMBlock) k_mlp_fwdbwd_mfma(gi_mlp m, uint32_t 
                 const float den = z * z + 0.01f, d = z - comp(tg, c);
                 g[c] = 2.0f * d / den / ntot;
                 loss += d * d / den;
-                enum_ += fabsf(fmaxf(z, 0.0f) - comp(q, c));
-                eden += comp(q, c) + 0.01f;
+                // squared errors of the cache (as the target uses it) and of
+                // the probe query against the label (none without probe values)
+                if (qp) {
+                    const float ec = fmaxf(z, 0.0f) - comp(tg, c), ep = comp(q, c) - comp(tg, c);
+                    enum_ += ec * ec;
+                    eden += ep * ep;
+                }
                 nonfinite += __builtin_isfinite(z) ? 0.0f : 1.0f;
             }
         }
@@ -1052,7 +1058,7 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(gi_mlp m, uint32_t nwg, cons
     } else if (j == kStErrNum) {
         float den = 0.0f;
         for (uint32_t w = 0; w < nwg; w += kGroup) den += part[(size_t)w * kPartStride + kParams + kStErrDen];
-        m.state[GI_MLP_STATE_BATCH_ERR] = __float_as_uint(den > 0.0f ? acc / den : 0.0f);
+        m.state[GI_MLP_STATE_BATCH_ERR] = __float_as_uint(den > 0.0f ? acc / den : (acc > 0.0f ? kFltMax : 0.0f));
     } else if (j == kStNonFinite) {
         m.state[GI_MLP_STATE_NONFINITE] = (uint32_t)acc;
     } else if (is_max) {

@@ -548,7 +548,7 @@ class Mlp:
     """Device state of the learned cache: FP32 master parameters, Adam
     moments, inference operands, FP8 scales and the usability state words."""
 
-    def __init__(self, lo, hi, precision="bf16", mode="auto", warmup_steps=16, max_rel_err=0.5,
+    def __init__(self, lo, hi, precision="bf16", mode="auto", warmup_steps=16, max_rel_err=1.0,
                  ema_decay=None, device="cuda"):
         f32 = dict(dtype=torch.float32, device=device)
         self.params = torch.zeros(MLP_N_PARAMS, **f32)

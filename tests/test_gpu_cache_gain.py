@@ -79,6 +79,6 @@ def test_cache_target_beats_probe_target(gi):
             torch.cuda.empty_cache()
         score[form] = (float(np.mean(mse)), float(np.mean(mape)))
         log(f"{form}: MSE {score[form][0]:.5f} (per seed {', '.join(f'{v:.5f}' for v in mse)}), "
-            f"MAPE {score[form][1]:.4f}" + (f"; own judge (usable, EMA error vs probes) {judged}" if judged else ""))
+            f"MAPE {score[form][1]:.4f}" + (f"; own judge (usable, EMA cache/probe squared-error ratio) {judged}" if judged else ""))
     log(f"cache / probe: MSE {score['cache'][0] / score['probe'][0]:.3f}, MAPE {score['cache'][1] / score['probe'][1]:.3f}")
     assert score["cache"][0] <= score["probe"][0]

@@ -134,6 +134,31 @@ def test_mlp_infer_fp8(gi):
     assert mean <= 2e-3 and p99 <= 5e-2 and mx <= 0.2
 
 
+@pytest.mark.parametrize("factor", [1.0 / 16.0, 64.0])
+def test_mlp_infer_fp8_scale_extremes(gi, factor):
+    """Activation scales 16x too small (layer 0's saturation bound 448 s_0
+    drops below 1, so every feature is clamped, and hidden activations
+    saturate at 448 s) or 64x too large (operands deep in E4M3's subnormal
+    range): the kernel still matches the oracle's FP8 forward on the same
+    stored scales."""
+    params = _params(23)
+    n = 2500
+    pos, nrm = _points(n, 24)
+    X = M.encode(pos.astype(np.float64), nrm.astype(np.float64), BOX_LO, BOX_HI)
+    amax = M.act_amax(params, X)
+    m = _mlp(gi, params, "fp8")
+    m.scales[5:10] = torch.tensor([a / 448.0 * factor for a in amax], dtype=torch.float32)
+    out = gi.mlp_infer(m, _f4(pos), _f4(nrm)).cpu().numpy()[:, :3]
+    sa = [float(v) for v in m.scales[5:10].cpu().numpy()]
+    if factor < 1.0:
+        assert 448.0 * M.pow2_at_least(sa[0]) < 1.0      # the clamp-everything encoding path
+    ref, _ = M.forward(params, X, prec="fp8", act_scales=sa)
+    mean, p99, mx = _err_stats(out, ref)
+    log(f"fp8 scales x{factor:g}: vs oracle fp8 mean {mean:.2e} p99 {p99:.2e} max {mx:.2e}")
+    assert np.all(np.isfinite(out))
+    assert mean <= 2e-3 and p99 <= 5e-2 and mx <= 0.2
+
+
 @pytest.mark.parametrize("precision", ["bf16", "fp8"])
 def test_mlp_infer_full_frame_sampled(gi, precision):
     """One 1080p frame's candidates (1920 x 1080 x 32) plus a ragged last
@@ -218,8 +243,9 @@ def test_mlp_grad(gi, n):
     assert st["valid"] == int(valid.sum())
     assert st["loss"] == pytest.approx(loss, rel=2e-3)
     assert st["nonfinite"] == 0
+    # the cache's squared error against the labels over the probe query's
     relu_out = np.maximum(out, 0.0)
-    be = np.abs(relu_out - q)[valid].sum() / (q[valid] + 0.01).sum()
+    be = ((relu_out - tgt) ** 2)[valid].sum() / ((q - tgt) ** 2)[valid].sum()
     assert st["batch_err"] == pytest.approx(be, rel=2e-3)
     # activation amax of every layer input (valid samples) -> FP8 scales:
     # the smallest power of two s with amax <= 448 s (the kernel's amax comes
