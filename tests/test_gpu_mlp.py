@@ -134,6 +134,37 @@ def test_mlp_infer_fp8(gi):
     assert mean <= 2e-3 and p99 <= 5e-2 and mx <= 0.2
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_mlp_infer_tiny_batches(gi, precision):
+    """Batches of 1, 31, 33, 64 and 65 points: a single partial tile, a
+    partial second tile of the FP8 kernel's tile pair, an exact pair and one
+    point past it; every output row matches the oracle and nothing is written
+    past n."""
+    params = _params(25)
+    m = _mlp(gi, params, precision)
+    sa = None
+    if precision == "fp8":
+        pos, nrm = _points(512, 26)
+        X = M.encode(pos.astype(np.float64), nrm.astype(np.float64), BOX_LO, BOX_HI)
+        m.scales[5:10] = torch.tensor([a / 448.0 for a in M.act_amax(params, X)], dtype=torch.float32)
+        sa = [float(v) for v in m.scales[5:10].cpu().numpy()]
+    for n in (1, 31, 33, 64, 65):
+        pos, nrm = _points(n, 27 + n)
+        X = M.encode(pos.astype(np.float64), nrm.astype(np.float64), BOX_LO, BOX_HI)
+        out = torch.full((n + 40, 4), 7.0, device="cuda")
+        p4, n4 = _f4(pos), _f4(nrm)
+        gi.check(gi.load().gi_mlp_infer(m.ref, n, gi._ptr(p4, gi.F32), gi._ptr(n4, gi.F32), gi._ptr(out),
+                                        gi._stream(None)), "gi_mlp_infer")
+        o = out.cpu().numpy()
+        assert np.all(o[n:] == 7.0), n          # rows past n untouched
+        ref, _ = M.forward(params, X, prec=precision, act_scales=sa)
+        mean, p99, mx = _err_stats(o[:n, :3], ref)
+        log(f"{precision} n={n}: mean {mean:.2e} max {mx:.2e}")
+        bar = (2e-4, 3e-2) if precision == "bf16" else (2e-3, 0.2)
+        # a single rounding-boundary flip dominates the mean of a handful of rows
+        assert mx <= bar[1] and mean <= (bar[0] if n >= 32 else bar[1]), n
+
+
 @pytest.mark.parametrize("factor", [1.0 / 16.0, 64.0])
 def test_mlp_infer_fp8_scale_extremes(gi, factor):
     """Activation scales 16x too small (layer 0's saturation bound 448 s_0
