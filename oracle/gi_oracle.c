@@ -18,7 +18,10 @@
  * Record layouts (all double):
  *   G-buffer pixel  [14]: pos[3] nrm[3] albedo[3] emit[3] view_depth prim
  *   reservoir       [14]: y[3] n_y[3] L[3] wsum W M tag prim
- *   probe textures : irr[P][(Ni+2)^2][3] (E/pi), dep[P][(Nd+2)^2][2] (mean, mean^2)
+ *   probe textures : irr[P][(Ni+2)^2][3] (E/pi), dep[P][(Nd+2)^2][2] (mean, mean^2);
+ *                    irradiance texels are binary16 values (o_round_half):
+ *                    rounded when the update stores them, read at that
+ *                    precision by the query
  * A reservoir whose sample left the scene stores the direction in y and a
  * zero normal in n_y.
  */
@@ -502,6 +505,23 @@ void o_oct_decode(const double *uv, double *v)
     normalize3(v);
 }
 
+/* IEEE binary16 rounding (nearest, ties to even) of a double, returned as a
+ * double: the storage precision of the probe irradiance texels.  11
+ * significant bits for |x| >= 2^-14, steps of 2^-24 below (subnormals),
+ * infinity from 65520 up (the tie between 65504 and 2^16 goes to the even
+ * 2^16, which overflows). */
+double o_round_half(double x)
+{
+    if (!(fabs(x) > 0.0) || !isfinite(x)) return x;
+    double a = fabs(x);
+    int e;
+    frexp(a, &e);                                     /* a in [2^(e-1), 2^e) */
+    double ulp = a >= ldexp(1.0, -14) ? ldexp(1.0, e - 11) : ldexp(1.0, -24);
+    double r = nearbyint(a / ulp) * ulp;              /* exact scaling; ties to even */
+    if (r > 65504.0) r = INFINITY;
+    return copysign(r, x);
+}
+
 /* bilinear fetch of a padded tile with C channels at the direction v */
 static void tile_fetch(const double *tile, int N, int C, const double *v, double *out)
 {
@@ -523,6 +543,25 @@ static void tile_fetch(const double *tile, int N, int C, const double *v, double
 void o_tile_fetch(const double *tile, int N, int C, const double *v, double *out)
 {
     tile_fetch(tile, N, C, v, out);
+}
+
+/* the same fetch of an irradiance tile, whose texels are read at the
+ * storage precision (binary16) whatever the caller's tile holds */
+static void irr_fetch(const double *tile, int N, const double *v, double *out)
+{
+    double uv[2];
+    o_oct_encode(v, uv);
+    int P = N + 2;
+    double fx = uv[0] * N + 0.5, fy = uv[1] * N + 0.5;
+    int x0 = (int)floor(fx), y0 = (int)floor(fy);
+    double ax = fx - x0, ay = fy - y0;
+    for (int c = 0; c < 3; ++c) out[c] = 0.0;
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+            double w = (dx ? ax : 1.0 - ax) * (dy ? ay : 1.0 - ay);
+            const double *t = tile + 3 * ((size_t)(y0 + dy) * P + (x0 + dx));
+            for (int c = 0; c < 3; ++c) out[c] += w * o_round_half(t[c]);
+        }
 }
 
 /* Gutter fill: a border texel repeats the interior texel mirrored along its
@@ -608,7 +647,7 @@ static void probe_query(const o_probes *pr, const double *p, const double *n, in
         if (flags & 2) vis = 1.0;
         double w = tri * fmax(back * vis, 1e-6);
         double irr[3];
-        tile_fetch(pr->irr + pi * irr_tile, Ni, 3, n, irr);
+        irr_fetch(pr->irr + pi * irr_tile, Ni, n, irr);
         for (int a = 0; a < 3; ++a) sum[a] += w * irr[a];
         wsum += w;
     }
@@ -846,8 +885,9 @@ void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, doub
                 }
                 size_t o = 3 * ((size_t)(ty + 1) * (Ni + 2) + (tx + 1));
                 for (int a = 0; a < 3; ++a) {
-                    double nv = den > 0.0 ? num[a] / den : iold[o + a];
-                    inew[o + a] = hysteresis * iold[o + a] + (1.0 - hysteresis) * nv;
+                    double nv = den > 0.0 ? num[a] / den : o_round_half(iold[o + a]);
+                    /* stored at binary16, blended from the stored (rounded) old texel */
+                    inew[o + a] = o_round_half(hysteresis * o_round_half(iold[o + a]) + (1.0 - hysteresis) * nv);
                 }
             }
         for (int ty = 0; ty < Nd; ++ty)

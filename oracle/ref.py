@@ -80,6 +80,8 @@ def _setup(L):
     L.o_oct_decode.argtypes = [_P, _P]
     L.o_tile_fetch.argtypes = [_P, C.c_int, C.c_int, _P, _P]
     L.o_fill_gutter.argtypes = [_P, C.c_int, C.c_int]
+    L.o_round_half.argtypes = [C.c_double]
+    L.o_round_half.restype = C.c_double
     L.o_probe_query.argtypes = [_P, C.c_int64, _P, _P, C.c_int, _P]
     L.o_probe_update.argtypes = [_P, _P, _P, _P, C.c_int, C.c_double, C.c_double, C.c_double, C.c_uint64,
                                  C.c_uint32, _P, C.c_int64]
@@ -284,6 +286,12 @@ def tile_fetch(tile, N, v) -> np.ndarray:
     vv, out = _f64(v), np.zeros(Cc)
     lib().o_tile_fetch(_ptr(t), int(N), int(Cc), _ptr(vv), _ptr(out))
     return out
+
+
+def round_half(x) -> float:
+    """IEEE binary16 rounding of x (nearest, ties to even), as a float: the
+    storage precision of probe irradiance texels."""
+    return lib().o_round_half(float(x))
 
 
 def fill_gutter(tile, N) -> np.ndarray:

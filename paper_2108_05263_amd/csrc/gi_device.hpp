@@ -488,8 +488,9 @@ __device__ __forceinline__ V3 oct_decode(float u, float w)
 // Probe textures are stored as bilinear quads: record (cx, cy), cx, cy in
 // [0, N], holds the four gutter-padded texels (cx, cy), (cx+1, cy),
 // (cx, cy+1), (cx+1, cy+1) that a bilinear fetch between them needs, so one
-// fetch is a single 48-byte (irradiance RGB) or 32-byte (depth moments)
-// record: 3 or 2 16-byte loads instead of 4 scattered texel loads.
+// fetch is a single 24-byte (irradiance RGB, binary16) or 32-byte (depth
+// moments, FP32) record: 3 8-byte or 2 16-byte loads instead of 4 scattered
+// texel loads.
 // Irradiance records are quad-major (record q of every probe, then record
 // q + 1): a query reads the same record q from all 8 probes of its cell, and
 // the x-neighbours' records then share cache lines.  Depth records, whose
@@ -536,9 +537,23 @@ __device__ __forceinline__ float2 fetch_dep(const float4 *probe, V3 dir)
 // Byte sizes of the quad records; a volume of at most kMaxProbes probes
 // keeps both textures under 4 GiB, so the query addresses them with
 // 32-bit byte offsets from the (uniform) texture base.
-constexpr uint32_t kIrrRecBytes = 48u;
+constexpr uint32_t kIrrRecBytes = 24u;                    // 12 binary16 values
 constexpr uint32_t kDepProbeBytes = kDepProbeF4 * 16u;    // 9248
 constexpr uint32_t kMaxProbes = 464000u;                  // kMaxProbes * kDepProbeBytes < 2^32
+
+// binary16 <-> FP32 (the irradiance records' storage precision; conversions
+// to binary16 round to nearest even)
+__device__ __forceinline__ float half_lo(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu)); }
+__device__ __forceinline__ float half_hi(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
+__device__ __forceinline__ float4 half4_to_float4(uint2 q)
+{
+    return make_float4(half_lo(q.x), half_hi(q.x), half_lo(q.y), half_hi(q.y));
+}
+__device__ __forceinline__ uint32_t pack_half2(float a, float b)
+{
+    const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)a), hi = __builtin_bit_cast(uint16_t, (_Float16)b);
+    return lo | (hi << 16);
+}
 
 __device__ __forceinline__ const float4 *at_bytes(const float *base, uint32_t off)
 {
@@ -608,8 +623,9 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
             const Bilin bd = bilin(dv, kDepN);
             const float4 *dr = at_bytes(pr.dep, __umul24(pi, kDepProbeBytes) + 32u * (uint32_t)bd.q);
             const float4 da = dr[0], db = dr[1];
-            const float4 *qr = at_bytes(pr.irr, irr_q + __umul24(pi, kIrrRecBytes));
-            const float4 e0 = qr[0], e1 = qr[1], e2 = qr[2];
+            const uint2 *qr = reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(pr.irr) + irr_q +
+                                                              __umul24(pi, kIrrRecBytes));
+            const float4 e0 = half4_to_float4(qr[0]), e1 = half4_to_float4(qr[1]), e2 = half4_to_float4(qr[2]);
             const float v00 = (1.0f - bd.ax) * (1.0f - bd.ay), v10 = bd.ax * (1.0f - bd.ay);
             const float v01 = (1.0f - bd.ax) * bd.ay, v11 = bd.ax * bd.ay;
             const float mu = v00 * da.x + v10 * da.z + v01 * db.x + v11 * db.z;

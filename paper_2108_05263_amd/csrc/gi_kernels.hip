@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(kProbeBlock)
     // old interior texel (i, j) = first texel of quad record (i+1, j+1)
     // irradiance records are quad-major: record q of probe pi is record q * nP + pi
     const size_t nP = (size_t)in.dims[0] * in.dims[1] * in.dims[2];
-    const float4 *iold = reinterpret_cast<const float4 *>(in.irr) + 3 * (size_t)pi;
+    const uint2 *iold = reinterpret_cast<const uint2 *>(in.irr) + 3 * (size_t)pi;
     const float4 *dold = reinterpret_cast<const float4 *>(in.dep) + (size_t)pi * kDepProbeF4;
     const float hy = pp.hysteresis;
     {   // depth texel t (16x16)
@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(kProbeBlock)
                 den += c;
             }
         }
-        float4 old = iold[3 * nP * ((ty + 1) * 9 + tx + 1)];
+        const float4 old = half4_to_float4(iold[3 * nP * ((ty + 1) * 9 + tx + 1)]);
         float id = 1.0f / den;
         V3 nv = den > 0.0f ? id * num : xyz(old);
         s_irr[t][0] = hy * old.x + (1.0f - hy) * nv.x;
@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(kProbeBlock)
     __syncthreads();
     // write quad records: each corner is an interior texel or the interior
     // texel its gutter position mirrors
-    float4 *iout = reinterpret_cast<float4 *>(out.irr) + 3 * (size_t)pi;
+    uint2 *iout = reinterpret_cast<uint2 *>(out.irr) + 3 * (size_t)pi;
     float4 *dout = reinterpret_cast<float4 *>(out.dep) + (size_t)pi * kDepProbeF4;
     for (uint32_t q = threadIdx.x; q < (uint32_t)kDepQuads; q += kProbeBlock) {
         int cx = (int)(q % 17u), cy = (int)(q / 17u);
@@ -397,10 +397,11 @@ __global__ void __launch_bounds__(kProbeBlock)
         int cx = (int)(q % 9u), cy = (int)(q / 9u);
         int s0 = gutter_source(cx, cy, kIrrN), s1 = gutter_source(cx + 1, cy, kIrrN);
         int s2 = gutter_source(cx, cy + 1, kIrrN), s3 = gutter_source(cx + 1, cy + 1, kIrrN);
-        float4 *rec = iout + 3 * nP * q;
-        rec[0] = make_float4(s_irr[s0][0], s_irr[s0][1], s_irr[s0][2], s_irr[s1][0]);
-        rec[1] = make_float4(s_irr[s1][1], s_irr[s1][2], s_irr[s2][0], s_irr[s2][1]);
-        rec[2] = make_float4(s_irr[s2][2], s_irr[s3][0], s_irr[s3][1], s_irr[s3][2]);
+        // binary16 (nearest even), in the order of the FP32 corners
+        uint2 *rec = iout + 3 * nP * q;
+        rec[0] = make_uint2(pack_half2(s_irr[s0][0], s_irr[s0][1]), pack_half2(s_irr[s0][2], s_irr[s1][0]));
+        rec[1] = make_uint2(pack_half2(s_irr[s1][1], s_irr[s1][2]), pack_half2(s_irr[s2][0], s_irr[s2][1]));
+        rec[2] = make_uint2(pack_half2(s_irr[s2][2], s_irr[s3][0]), pack_half2(s_irr[s3][1], s_irr[s3][2]));
     }
 }
 
@@ -1353,8 +1354,8 @@ gi_status gi_probe_update(const gi_scene *scene, const gi_probes *in, gi_probes 
     if ((s = check_probes(out)) != GI_OK) return s;
     for (int a = 0; a < 3; ++a)
         if (in->dims[a] != out->dims[a]) return GI_ERR_SHAPE;
-    if (in->irr == out->irr || in->dep == out->dep || in->irr == out->dep || in->dep == out->irr)
-        return GI_ERR_ALIAS;
+    const void *ii = in->irr, *id = in->dep, *oi = out->irr, *od = out->dep;
+    if (ii == oi || id == od || ii == od || id == oi) return GI_ERR_ALIAS;
     if (pp->rays < 1 || pp->rays > GI_MAX_PROBE_RAYS) return GI_ERR_PARAM;
     if (!(pp->hysteresis >= 0.0f && pp->hysteresis <= 1.0f) || !(pp->sharpness > 0.0f)) return GI_ERR_PARAM;
     if (!(pp->distance_slider >= 0.0f)) return GI_ERR_PARAM;

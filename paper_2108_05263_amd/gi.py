@@ -410,13 +410,13 @@ def quads_to_tiles(quads, N, C_):
 
 class Probes:
     """Probe textures in the library's quad-record layout (see gi.h):
-    irradiance records quad-major (record, probe, 12), depth records
-    probe-major (probe, record, 8)."""
+    irradiance records quad-major (record, probe, 12) in binary16, depth
+    records probe-major (probe, record, 8) in FP32."""
 
     def __init__(self, grid: sg.ProbeGrid, device="cuda"):
         self.grid = grid
         P = grid.count
-        self.irr = torch.zeros((grid.irr_res + 1) ** 2, P, 12, dtype=torch.float32, device=device)
+        self.irr = torch.zeros((grid.irr_res + 1) ** 2, P, 12, dtype=torch.float16, device=device)
         self.dep = torch.zeros(P, (grid.dep_res + 1) ** 2, 8, dtype=torch.float32, device=device)
         p = GiProbes()
         p.dims = (C.c_uint32 * 3)(*grid.dims)
@@ -433,7 +433,8 @@ class Probes:
     def load(self, irr, dep):
         """Fill from gutter-padded tiles: irr (P, (N+2)^2, >=3), dep (P, (Nd+2)^2, 2)."""
         g = self.grid
-        qi = tiles_to_quads(np.asarray(irr, np.float32)[..., :3], g.irr_res)
+        # binary16 straight from the caller's values (one rounding, nearest even)
+        qi = tiles_to_quads(np.asarray(irr, np.float64)[..., :3], g.irr_res).astype(np.float16)
         qd = tiles_to_quads(np.asarray(dep, np.float32)[..., :2], g.dep_res)
         self.irr.copy_(torch.from_numpy(np.ascontiguousarray(qi.swapaxes(0, 1))))
         self.dep.copy_(torch.from_numpy(np.ascontiguousarray(qd)))
@@ -446,7 +447,7 @@ class Probes:
 
     def irr_quads(self):
         """Irradiance records probe-major, (P, (N+1)^2, 12), as tiles_to_quads makes them."""
-        return np.ascontiguousarray(self.irr.cpu().numpy().swapaxes(0, 1))
+        return np.ascontiguousarray(self.irr.cpu().numpy().astype(np.float32).swapaxes(0, 1))
 
 
 def params_struct(p: sg.Params) -> GiParams:

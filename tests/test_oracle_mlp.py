@@ -300,7 +300,7 @@ def test_constant_mlp_target_equals_constant_probes():
     W, H = 32, 24
     cam = sg.make_camera(cfg, 0, W, H)
     grid = sg.make_probe_grid(cfg)
-    c = np.array([0.3, 0.55, 0.8], np.float32).astype(np.float64)   # exact in the FP32 texels
+    c = np.array([0.25, 0.5625, 0.8125])            # exact in the binary16 texels
     params = np.zeros(M.N_PARAMS)
     params[-3:] = c
     lo, hi = sc.bounds()

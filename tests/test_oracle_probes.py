@@ -81,6 +81,12 @@ def test_gutters_make_fetch_continuous():
         assert np.allclose(o.tile_fetch(tile, N, v), o.tile_fetch(tile, N, w), atol=1e-6)
 
 
+def _f16(x):
+    """binary16 rounding (numpy's float16 conversion), the precision of the
+    stored irradiance texels, back in float64"""
+    return np.asarray(x, np.float64).astype(np.float16).astype(np.float64)
+
+
 def _grid(dims=(4, 3, 5), spacing=1.5):
     return g.probe_grid(dims, (0.0, 0.0, 0.0), spacing)
 
@@ -95,7 +101,8 @@ def test_query_equals_trilinear_when_weights_off():
     nx, ny, nz = grid.dims
     s = float(grid.spacing[0])
     axes = [(np.arange(n) + 0.5) * s for n in (nx, ny, nz)]
-    grid_vals = vals.reshape(nz, ny, nx, 3).transpose(2, 1, 0, 3)
+    # irradiance texels are read at binary16 (numpy's float16 conversion)
+    grid_vals = _f16(vals).reshape(nz, ny, nx, 3).transpose(2, 1, 0, 3)
     interp = RegularGridInterpolator(axes, grid_vals)
     pts = np.stack([rng.uniform(a[0], a[-1], 400) for a in axes], axis=1)
     nrm = _dirs(400, 9)
@@ -117,7 +124,8 @@ def test_query_constant_textures_give_constant():
     dep = np.concatenate([dep, dep ** 2 + rng.uniform(0, 0.5, dep.shape)], axis=2)
     pts = rng.uniform(0.0, 7.0, (300, 3))
     q = o.probe_query(grid, irr, dep, pts, _dirs(300, 3))
-    assert np.allclose(q, [0.7, 1.1, 2.3], atol=1e-12)
+    assert np.allclose(q, _f16([0.7, 1.1, 2.3]), atol=1e-12)
+    assert not np.allclose(q, [0.7, 1.1, 2.3], atol=1e-6)   # the texels' precision shows
 
 
 def test_query_visibility_limits():
@@ -185,11 +193,14 @@ def test_update_plane_fixed_point_gives_pi_L():
     dep[..., 0], dep[..., 1] = 1.0, 1.0
     i2, d2 = o.probe_update(sc, grid, irr, dep, rays=64, hysteresis=0.0, sharpness=50.0, seed=1,
                             frame=0)
-    assert np.allclose(i2, L.astype(np.float64), rtol=1e-12)
-    # query on the plane: Q = E/pi = L, i.e. E = pi L
+    # the stored texels are L at binary16: the sky rays bring L, the plane
+    # rays the stored value, and every mean of the two rounds back to it
+    Lh = _f16(L)
+    assert np.allclose(i2, Lh, rtol=1e-12)
+    # query on the plane: Q = E/pi = L (as stored), i.e. E = pi L
     pts = np.array([[0.1, 0.0, 0.2], [-0.7, 0.0, 0.4]])
     q = o.probe_query(grid, i2, d2, pts, [[0, 1.0, 0]] * 2)
-    assert np.allclose(math.pi * q, math.pi * L.astype(np.float64), rtol=1e-12)
+    assert np.allclose(math.pi * q, math.pi * Lh, rtol=1e-12)
 
 
 def test_update_hysteresis_geometric():
@@ -200,10 +211,13 @@ def test_update_hysteresis_geometric():
     irr = irr[..., :3].astype(np.float64) + 0.5
     dep = dep.astype(np.float64)
     a = 0.9
+    expect = 0.5
     for k in range(1, 6):
         irr, dep = o.probe_update(sc, grid, irr, dep, 64, a, 50.0, 1, k)
-        expect = a ** k * 0.5 + (1 - a ** k) * 2.0
+        # a^k 0.5 + (1 - a^k) 2, each step's blend stored at binary16
+        expect = float(_f16(a * expect + (1 - a) * 2.0))
         assert np.allclose(irr, expect, rtol=1e-12)
+    assert abs(expect - (a ** 5 * 0.5 + (1 - a ** 5) * 2.0)) < 2e-3
 
 
 def test_update_texel_converges_to_analytic_irradiance():
@@ -371,7 +385,7 @@ def test_distance_heuristic_single_ray():
                 for tx in range(N):
                     nt = o.oct_decode([(tx + 0.5) / N, (ty + 0.5) / N])
                     if np.dot(nt, w) > 1e-9:
-                        assert np.allclose(T[ty, tx], Ld * factor, rtol=1e-12), (frame, mu_b, s)
+                        assert np.allclose(T[ty, tx], _f16(Ld * factor), rtol=1e-12), (frame, mu_b, s)
                         facing += 1
                     elif np.dot(nt, w) < -1e-9:
                         assert np.all(T[ty, tx] == 0.0)
@@ -410,7 +424,7 @@ def test_distance_heuristic_reads_the_backward_direction():
         T = i2.reshape(N + 2, N + 2, 3)[1:N + 1, 1:N + 1]
         best = max(((ty, tx) for ty in range(N) for tx in range(N)),
                    key=lambda c: np.dot(o.oct_decode([(c[1] + 0.5) / N, (c[0] + 0.5) / N]), w))
-        assert np.allclose(T[best], L.astype(np.float64) * factor, rtol=1e-12), (frame, far)
+        assert np.allclose(T[best], _f16(L.astype(np.float64) * factor), rtol=1e-12), (frame, far)
         seen[far] += 1
     assert seen[True] >= 3 and seen[False] >= 3
 
@@ -480,3 +494,38 @@ def test_update_depth_moments_above_plane(sharp):
         m1, m2 = _lobe_means(nt, sharp, depth)
         var = m2 - m1 * m1
         assert var > 0.05
+
+
+# --------------------------------------------------------------------------
+# binary16 irradiance texels
+# --------------------------------------------------------------------------
+def test_round_half_matches_numpy_float16():
+    """o_round_half against numpy's float64 -> float16 conversion: normal and
+    subnormal ranges, ties (to even), the largest finite value and overflow."""
+    rng = np.random.default_rng(31)
+    xs = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-9, 6, 20000),
+                         [0.0, -0.0, 65504.0, 65519.99, 65520.0, -65520.0, 1e6, 2.0 ** -24, 2.0 ** -25,
+                          3 * 2.0 ** -26, 2.0 ** -14, 2.0 ** -14 * (1 - 2.0 ** -11), 1 + 2.0 ** -11,
+                          1 + 3 * 2.0 ** -11, 2049.0, 2051.0]])
+    with np.errstate(over="ignore"):
+        want = xs.astype(np.float16).astype(np.float64)
+    got = np.array([o.round_half(x) for x in xs])
+    assert np.array_equal(got, want)
+
+
+def test_update_stores_binary16_and_query_reads_binary16():
+    """The update stores irradiance texels that are binary16 values; the
+    query reads a caller's arbitrary tile at that precision (a tile of
+    1 + 2^-12, which rounds to 1, queries as exactly 1)."""
+    sky = np.array([0.3, 0.7, 1.9], np.float32)
+    sc = _open_scene(sky=sky)
+    grid = _grid((2, 2, 2), 1.0)
+    irr, dep = g.empty_probe_textures(grid)
+    i2, d2 = o.probe_update(sc, grid, irr, dep, rays=32, hysteresis=0.25, sharpness=50.0, seed=5, frame=0)
+    # empty space under the sky: every texel is 0.75 L, stored at binary16
+    want = 0.75 * sky.astype(np.float64)
+    assert np.array_equal(i2, _f16(i2))
+    assert np.allclose(i2, want, rtol=1e-3) and not np.allclose(i2, want, rtol=1e-6)
+    tile = np.full_like(i2, 1.0 + 2.0 ** -12)
+    q = o.probe_query(grid, tile, d2, [[0.7, 0.6, 0.8]], [[0.0, 1.0, 0.0]])
+    assert np.array_equal(q, [[1.0, 1.0, 1.0]])
