@@ -149,16 +149,19 @@ typedef struct gi_gbuffer {
  * irradiance tile (irr_res^2 texels of E/pi, RGB) and depth tile (dep_res^2
  * texels of the mean and mean square hit distance), each with a one-texel
  * gutter that mirrors the interior along the tile edge (corners take the
- * diagonally opposite interior texel).  Irradiance texels are IEEE binary16
- * values (gi_probe_update rounds to nearest even), depth texels FP32.  They
- * are stored as bilinear quads:
+ * diagonally opposite interior texel).  Texels are stored as IEEE binary16
+ * values (gi_probe_update rounds to nearest even): irradiance as RGB, depth
+ * as the mean and the variance (mean square minus squared mean; the query
+ * rebuilds the mean square as variance + mean^2).  They are stored as
+ * bilinear quads:
  *   irr: (irr_res+1)^2 records of 12 binary16 values (24 bytes) per probe,
  *        quad-major: record q = cy*(irr_res+1)+cx of probe i is record
  *        q*P + i (P probes), and holds the RGB of padded texels (cx,cy),
  *        (cx+1,cy), (cx,cy+1), (cx+1,cy+1) in that order (1944 bytes per
  *        probe in all);
- *   dep: per probe (dep_res+1)^2 records of 8 floats, (mean, mean^2) of the
- *        same four padded texels, probe-major (9248 bytes per probe).
+ *   dep: per probe (dep_res+1)^2 records of 8 binary16 values (16 bytes),
+ *        (mean, variance) of the same four padded texels, probe-major (4624
+ *        bytes per probe).
  * irr_res must be 8 and dep_res 16; the volume holds at most 464,000
  * probes (each texture then stays under 4 GiB, so kernels address it with
  * 32-bit byte offsets; larger volumes return GI_ERR_SHAPE).  bias_dist is the view-path bias d,
@@ -169,7 +172,7 @@ typedef struct gi_probes {
     float lo[3], spacing[3];
     float bias_dist, var_floor, d_max;
     uint16_t *irr;        /* binary16 bits */
-    float *dep;
+    uint16_t *dep;        /* binary16 bits */
 } gi_probes;
 
 /* Reservoirs, SoA planes of width*height records:

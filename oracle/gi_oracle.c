@@ -19,9 +19,11 @@
  *   G-buffer pixel  [14]: pos[3] nrm[3] albedo[3] emit[3] view_depth prim
  *   reservoir       [14]: y[3] n_y[3] L[3] wsum W M tag prim
  *   probe textures : irr[P][(Ni+2)^2][3] (E/pi), dep[P][(Nd+2)^2][2] (mean, mean^2);
- *                    irradiance texels are binary16 values (o_round_half):
- *                    rounded when the update stores them, read at that
- *                    precision by the query
+ *                    texels are kept at their storage precision: binary16
+ *                    (o_round_half) irradiance, and for depth a binary16 mean
+ *                    and variance with the mean square rebuilt from them
+ *                    (dep_texel); the update stores them so, the query
+ *                    reads a caller's tile so
  * A reservoir whose sample left the scene stores the direction in y and a
  * zero normal in n_y.
  */
@@ -545,6 +547,37 @@ void o_tile_fetch(const double *tile, int N, int C, const double *v, double *out
     tile_fetch(tile, N, C, v, out);
 }
 
+/* A depth texel (mean, mean square) at its storage precision: the mean and
+ * the variance (mean square minus squared mean) as binary16 values, the mean
+ * square rebuilt from them.  The variance is rounded, not the mean square,
+ * because at 11 bits the difference of two rounded squares of similar size
+ * would lose the variance. */
+static void dep_texel(const double *t, double *m)
+{
+    double mu = o_round_half(t[0]), var = o_round_half(t[1] - t[0] * t[0]);
+    m[0] = mu;
+    m[1] = var + mu * mu;
+}
+
+/* bilinear fetch of a depth tile, texels read at their storage precision */
+static void dep_fetch(const double *tile, int N, const double *v, double *out)
+{
+    double uv[2];
+    o_oct_encode(v, uv);
+    int P = N + 2;
+    double fx = uv[0] * N + 0.5, fy = uv[1] * N + 0.5;
+    int x0 = (int)floor(fx), y0 = (int)floor(fy);
+    double ax = fx - x0, ay = fy - y0;
+    out[0] = out[1] = 0.0;
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+            double w = (dx ? ax : 1.0 - ax) * (dy ? ay : 1.0 - ay), m[2];
+            dep_texel(tile + 2 * ((size_t)(y0 + dy) * P + (x0 + dx)), m);
+            out[0] += w * m[0];
+            out[1] += w * m[1];
+        }
+}
+
 /* the same fetch of an irradiance tile, whose texels are read at the
  * storage precision (binary16) whatever the caller's tile holds */
 static void irr_fetch(const double *tile, int N, const double *v, double *out)
@@ -635,7 +668,7 @@ static void probe_query(const o_probes *pr, const double *p, const double *n, in
             double h = 0.5 * (1.0 + dot3(n, w));
             back = h * h + 0.2;
             double from_probe[3] = {-w[0], -w[1], -w[2]}, mom[2];
-            tile_fetch(pr->dep + pi * dep_tile, Nd, 2, from_probe, mom);
+            dep_fetch(pr->dep + pi * dep_tile, Nd, from_probe, mom);
             if (r > mom[0]) {
                 double var = fmax(mom[1] - mom[0] * mom[0], pr->var_floor);
                 double dd = r - mom[0];
@@ -838,7 +871,7 @@ void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, doub
                      * inverse square of that total relative to t, with the backward
                      * part weighted by the per-scene slider */
                     double back[3] = {-dirs[r][0], -dirs[r][1], -dirs[r][2]}, mom[2];
-                    tile_fetch(in->dep + pi * dep_tile, Nd, 2, back, mom);
+                    dep_fetch(in->dep + pi * dep_tile, Nd, back, mom);
                     double clip = O_INF;
                     for (int a = 0; a < 3; ++a)
                         if (back[a] != 0.0) clip = fmin(clip, 0.5 * in->spacing[a] / fabs(back[a]));
@@ -902,10 +935,15 @@ void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, doub
                     den += w;
                 }
                 size_t o = 2 * ((size_t)(ty + 1) * (Nd + 2) + (tx + 1));
-                double n1 = den > 0.0 ? m1 / den : dold[o];
-                double n2 = den > 0.0 ? m2 / den : dold[o + 1];
-                dnew[o] = hysteresis * dold[o] + (1.0 - hysteresis) * n1;
-                dnew[o + 1] = hysteresis * dold[o + 1] + (1.0 - hysteresis) * n2;
+                /* blended from the stored old texel, stored at binary16 as
+                 * (mean, variance) and kept here as (mean, mean square) */
+                double old[2], b[2];
+                dep_texel(dold + o, old);
+                double n1 = den > 0.0 ? m1 / den : old[0];
+                double n2 = den > 0.0 ? m2 / den : old[1];
+                b[0] = hysteresis * old[0] + (1.0 - hysteresis) * n1;
+                b[1] = hysteresis * old[1] + (1.0 - hysteresis) * n2;
+                dep_texel(b, dnew + o);
             }
         fill_gutter(inew, Ni, 3);
         fill_gutter(dnew, Nd, 2);

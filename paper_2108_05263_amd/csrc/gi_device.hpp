@@ -488,9 +488,9 @@ __device__ __forceinline__ V3 oct_decode(float u, float w)
 // Probe textures are stored as bilinear quads: record (cx, cy), cx, cy in
 // [0, N], holds the four gutter-padded texels (cx, cy), (cx+1, cy),
 // (cx, cy+1), (cx+1, cy+1) that a bilinear fetch between them needs, so one
-// fetch is a single 24-byte (irradiance RGB, binary16) or 32-byte (depth
-// moments, FP32) record: 3 8-byte or 2 16-byte loads instead of 4 scattered
-// texel loads.
+// fetch is a single 24-byte (irradiance RGB) or 16-byte (depth mean and
+// variance) record of binary16 values: 3 8-byte or 1 16-byte loads instead
+// of 4 scattered texel loads.
 // Irradiance records are quad-major (record q of every probe, then record
 // q + 1): a query reads the same record q from all 8 probes of its cell, and
 // the x-neighbours' records then share cache lines.  Depth records, whose
@@ -498,7 +498,28 @@ __device__ __forceinline__ V3 oct_decode(float u, float w)
 constexpr int kIrrN = 8, kDepN = 16;
 constexpr int kIrrQuads = (kIrrN + 1) * (kIrrN + 1);      // 81 records of 12 floats
 constexpr int kDepQuads = (kDepN + 1) * (kDepN + 1);      // 289 records of 8 floats
-constexpr int kDepProbeF4 = kDepQuads * 2;
+constexpr int kDepRecBytes = 16;                          // 4 texels x binary16 (mean, variance)
+
+// binary16 <-> FP32 (the probe records' storage precision; conversions to
+// binary16 round to nearest even)
+__device__ __forceinline__ float half_lo(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu)); }
+__device__ __forceinline__ float half_hi(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
+__device__ __forceinline__ float4 half4_to_float4(uint2 q)
+{
+    return make_float4(half_lo(q.x), half_hi(q.x), half_lo(q.y), half_hi(q.y));
+}
+__device__ __forceinline__ uint32_t pack_half2(float a, float b)
+{
+    const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)a), hi = __builtin_bit_cast(uint16_t, (_Float16)b);
+    return lo | (hi << 16);
+}
+
+// a depth texel stored as binary16 (mean, variance) -> (mean, mean square)
+__device__ __forceinline__ float2 dep_texel(uint32_t w)
+{
+    const float mu = half_lo(w);
+    return make_float2(mu, fmaf(mu, mu, half_hi(w)));
+}
 
 struct Bilin {
     int q;          // quad record index cy * (N + 1) + cx
@@ -523,37 +544,24 @@ __device__ __forceinline__ Bilin bilin(V3 dir, int N)
     return b;
 }
 
-__device__ __forceinline__ float2 fetch_dep(const float4 *probe, V3 dir)
+// bilinear (mean, mean square) of a probe's depth records (uint4 per quad)
+__device__ __forceinline__ float2 fetch_dep(const uint4 *probe, V3 dir)
 {
     Bilin b = bilin(dir, kDepN);
-    const float4 *r = probe + 2 * b.q;
-    float4 a = r[0], c = r[1];
+    const uint4 r = probe[b.q];
+    const float2 t0 = dep_texel(r.x), t1 = dep_texel(r.y), t2 = dep_texel(r.z), t3 = dep_texel(r.w);
     float w00 = (1.0f - b.ax) * (1.0f - b.ay), w10 = b.ax * (1.0f - b.ay);
     float w01 = (1.0f - b.ax) * b.ay, w11 = b.ax * b.ay;
-    return make_float2(w00 * a.x + w10 * a.z + w01 * c.x + w11 * c.z,
-                       w00 * a.y + w10 * a.w + w01 * c.y + w11 * c.w);
+    return make_float2(w00 * t0.x + w10 * t1.x + w01 * t2.x + w11 * t3.x,
+                       w00 * t0.y + w10 * t1.y + w01 * t2.y + w11 * t3.y);
 }
 
 // Byte sizes of the quad records; a volume of at most kMaxProbes probes
 // keeps both textures under 4 GiB, so the query addresses them with
 // 32-bit byte offsets from the (uniform) texture base.
 constexpr uint32_t kIrrRecBytes = 24u;                    // 12 binary16 values
-constexpr uint32_t kDepProbeBytes = kDepProbeF4 * 16u;    // 9248
+constexpr uint32_t kDepProbeBytes = kDepQuads * kDepRecBytes;   // 4624
 constexpr uint32_t kMaxProbes = 464000u;                  // kMaxProbes * kDepProbeBytes < 2^32
-
-// binary16 <-> FP32 (the irradiance records' storage precision; conversions
-// to binary16 round to nearest even)
-__device__ __forceinline__ float half_lo(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu)); }
-__device__ __forceinline__ float half_hi(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
-__device__ __forceinline__ float4 half4_to_float4(uint2 q)
-{
-    return make_float4(half_lo(q.x), half_hi(q.x), half_lo(q.y), half_hi(q.y));
-}
-__device__ __forceinline__ uint32_t pack_half2(float a, float b)
-{
-    const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)a), hi = __builtin_bit_cast(uint16_t, (_Float16)b);
-    return lo | (hi << 16);
-}
 
 __device__ __forceinline__ const float4 *at_bytes(const float *base, uint32_t off)
 {
@@ -621,15 +629,17 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
             // depth moments toward p (a probe sitting exactly at p reads any texel, unused)
             const V3 dv = at_probe ? v3(0.0f, 0.0f, 1.0f) : -tp;
             const Bilin bd = bilin(dv, kDepN);
-            const float4 *dr = at_bytes(pr.dep, __umul24(pi, kDepProbeBytes) + 32u * (uint32_t)bd.q);
-            const float4 da = dr[0], db = dr[1];
+            const uint4 dq = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(pr.dep) +
+                                                             __umul24(pi, kDepProbeBytes) +
+                                                             (uint32_t)kDepRecBytes * (uint32_t)bd.q);
+            const float2 d0 = dep_texel(dq.x), d1 = dep_texel(dq.y), d2 = dep_texel(dq.z), d3 = dep_texel(dq.w);
             const uint2 *qr = reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(pr.irr) + irr_q +
                                                               __umul24(pi, kIrrRecBytes));
             const float4 e0 = half4_to_float4(qr[0]), e1 = half4_to_float4(qr[1]), e2 = half4_to_float4(qr[2]);
             const float v00 = (1.0f - bd.ax) * (1.0f - bd.ay), v10 = bd.ax * (1.0f - bd.ay);
             const float v01 = (1.0f - bd.ax) * bd.ay, v11 = bd.ax * bd.ay;
-            const float mu = v00 * da.x + v10 * da.z + v01 * db.x + v11 * db.z;
-            const float mu2 = v00 * da.y + v10 * da.w + v01 * db.y + v11 * db.w;
+            const float mu = v00 * d0.x + v10 * d1.x + v01 * d2.x + v11 * d3.x;
+            const float mu2 = v00 * d0.y + v10 * d1.y + v01 * d2.y + v11 * d3.y;
             const float var = fmaxf(fmaf(-mu, mu, mu2), pr.var_floor);
             const float dd = r - mu;
             const float cheb = var * rcp(fmaf(dd, dd, var));

@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(kProbeBlock)
             if (pp.distance_slider > 0.0f && !is_zero(emit)) {
                 // distance heuristic: emission scaled by (t / (t + s d_b))^2, d_b the
                 // probe's backward mean depth clipped to its cell
-                const float2 m = fetch_dep(reinterpret_cast<const float4 *>(in.dep) + (size_t)pi * kDepProbeF4, -w);
+                const float2 m = fetch_dep(reinterpret_cast<const uint4 *>(in.dep) + (size_t)pi * kDepQuads, -w);
                 float clip = kInf;
                 if (w.x != 0.0f) clip = fminf(clip, 0.5f * in.spacing[0] / fabsf(w.x));
                 if (w.y != 0.0f) clip = fminf(clip, 0.5f * in.spacing[1] / fabsf(w.y));
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(kProbeBlock)
     // irradiance records are quad-major: record q of probe pi is record q * nP + pi
     const size_t nP = (size_t)in.dims[0] * in.dims[1] * in.dims[2];
     const uint2 *iold = reinterpret_cast<const uint2 *>(in.irr) + 3 * (size_t)pi;
-    const float4 *dold = reinterpret_cast<const float4 *>(in.dep) + (size_t)pi * kDepProbeF4;
+    const uint4 *dold = reinterpret_cast<const uint4 *>(in.dep) + (size_t)pi * kDepQuads;
     const float hy = pp.hysteresis;
     {   // depth texel t (16x16)
         uint32_t t = threadIdx.x;
@@ -355,11 +355,14 @@ __global__ void __launch_bounds__(kProbeBlock)
                 den += w;
             }
         }
-        float4 old = dold[2 * ((ty + 1) * 17 + tx + 1)];
+        // the stored old texel (first of quad (tx+1, ty+1)) as (mean, mean square);
+        // the blend is stored as its mean and variance
+        const float2 old = dep_texel(dold[(ty + 1) * 17 + tx + 1].x);
         float n1 = den > 0.0f ? m1 / den : old.x;
         float n2 = den > 0.0f ? m2 / den : old.y;
-        s_dep[t][0] = hy * old.x + (1.0f - hy) * n1;
-        s_dep[t][1] = hy * old.y + (1.0f - hy) * n2;
+        const float b1 = hy * old.x + (1.0f - hy) * n1, b2 = hy * old.y + (1.0f - hy) * n2;
+        s_dep[t][0] = b1;
+        s_dep[t][1] = fmaf(-b1, b1, b2);
     }
     if (threadIdx.x < 64) {   // irradiance texel t (8x8)
         uint32_t t = threadIdx.x;
@@ -385,13 +388,13 @@ __global__ void __launch_bounds__(kProbeBlock)
     // write quad records: each corner is an interior texel or the interior
     // texel its gutter position mirrors
     uint2 *iout = reinterpret_cast<uint2 *>(out.irr) + 3 * (size_t)pi;
-    float4 *dout = reinterpret_cast<float4 *>(out.dep) + (size_t)pi * kDepProbeF4;
+    uint4 *dout = reinterpret_cast<uint4 *>(out.dep) + (size_t)pi * kDepQuads;
     for (uint32_t q = threadIdx.x; q < (uint32_t)kDepQuads; q += kProbeBlock) {
         int cx = (int)(q % 17u), cy = (int)(q / 17u);
         int s0 = gutter_source(cx, cy, kDepN), s1 = gutter_source(cx + 1, cy, kDepN);
         int s2 = gutter_source(cx, cy + 1, kDepN), s3 = gutter_source(cx + 1, cy + 1, kDepN);
-        dout[2 * q] = make_float4(s_dep[s0][0], s_dep[s0][1], s_dep[s1][0], s_dep[s1][1]);
-        dout[2 * q + 1] = make_float4(s_dep[s2][0], s_dep[s2][1], s_dep[s3][0], s_dep[s3][1]);
+        dout[q] = make_uint4(pack_half2(s_dep[s0][0], s_dep[s0][1]), pack_half2(s_dep[s1][0], s_dep[s1][1]),
+                             pack_half2(s_dep[s2][0], s_dep[s2][1]), pack_half2(s_dep[s3][0], s_dep[s3][1]));
     }
     for (uint32_t q = threadIdx.x; q < (uint32_t)kIrrQuads; q += kProbeBlock) {
         int cx = (int)(q % 9u), cy = (int)(q / 9u);

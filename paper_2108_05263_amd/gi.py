@@ -410,14 +410,15 @@ def quads_to_tiles(quads, N, C_):
 
 class Probes:
     """Probe textures in the library's quad-record layout (see gi.h):
-    irradiance records quad-major (record, probe, 12) in binary16, depth
-    records probe-major (probe, record, 8) in FP32."""
+    irradiance records quad-major (record, probe, 12), depth records
+    probe-major (probe, record, 8) as (mean, variance) per texel, all
+    binary16."""
 
     def __init__(self, grid: sg.ProbeGrid, device="cuda"):
         self.grid = grid
         P = grid.count
         self.irr = torch.zeros((grid.irr_res + 1) ** 2, P, 12, dtype=torch.float16, device=device)
-        self.dep = torch.zeros(P, (grid.dep_res + 1) ** 2, 8, dtype=torch.float32, device=device)
+        self.dep = torch.zeros(P, (grid.dep_res + 1) ** 2, 8, dtype=torch.float16, device=device)
         p = GiProbes()
         p.dims = (C.c_uint32 * 3)(*grid.dims)
         p.irr_res, p.dep_res = grid.irr_res, grid.dep_res
@@ -435,7 +436,10 @@ class Probes:
         g = self.grid
         # binary16 straight from the caller's values (one rounding, nearest even)
         qi = tiles_to_quads(np.asarray(irr, np.float64)[..., :3], g.irr_res).astype(np.float16)
-        qd = tiles_to_quads(np.asarray(dep, np.float32)[..., :2], g.dep_res)
+        # depth texels stored as binary16 (mean, variance) from (mean, mean square)
+        d = np.asarray(dep, np.float64)[..., :2]
+        mv = np.stack([d[..., 0], d[..., 1] - d[..., 0] * d[..., 0]], axis=-1)
+        qd = tiles_to_quads(mv, g.dep_res).astype(np.float16)
         self.irr.copy_(torch.from_numpy(np.ascontiguousarray(qi.swapaxes(0, 1))))
         self.dep.copy_(torch.from_numpy(np.ascontiguousarray(qd)))
 
@@ -443,7 +447,14 @@ class Probes:
         """(irr (P, (N+2)^2, 3), dep (P, (Nd+2)^2, 2)) as gutter-padded tiles."""
         g = self.grid
         return (quads_to_tiles(self.irr_quads(), g.irr_res, 3),
-                quads_to_tiles(self.dep.cpu().numpy(), g.dep_res, 2))
+                quads_to_tiles(self.dep_quads(), g.dep_res, 2))
+
+    def dep_quads(self):
+        """Depth records (P, (Nd+1)^2, 8) as (mean, mean square) per texel, the
+        mean square rebuilt from the stored binary16 mean and variance."""
+        q = self.dep.cpu().numpy().astype(np.float64).reshape(self.grid.count, -1, 4, 2)
+        out = np.stack([q[..., 0], q[..., 1] + q[..., 0] * q[..., 0]], axis=-1)
+        return out.reshape(self.grid.count, -1, 8)
 
     def irr_quads(self):
         """Irradiance records probe-major, (P, (N+1)^2, 12), as tiles_to_quads makes them."""

@@ -165,9 +165,12 @@ def test_probe_layout_odd_volume(gi, tiny):
     pr = gi.Probes(grid)
     pr.load(irr, dep)
     ti, td = pr.tiles()
-    # irradiance texels come back at binary16, depth at FP32
+    # texels come back at binary16: irradiance, and depth as (mean, variance)
     assert np.array_equal(ti, irr[..., :3].astype(np.float16).astype(np.float32))
-    assert np.array_equal(td, dep.astype(np.float32)[..., :2])
+    d = dep[..., :2].astype(np.float64)
+    mu = d[..., 0].astype(np.float16).astype(np.float64)
+    var = (d[..., 1] - d[..., 0] * d[..., 0]).astype(np.float16).astype(np.float64)
+    assert np.array_equal(td[..., 0], mu) and np.array_equal(td[..., 1], var + mu * mu)
     rng = np.random.default_rng(4)
     p = rng.uniform(-0.5, 8.0, (4000, 3)).astype(np.float32)
     n = rng.normal(size=(4000, 3))
@@ -201,7 +204,7 @@ def test_probe_update(gi, tiny):
         gi_irr, gi_dep = pout.tiles()
         # every quad record agrees with the padded tile it encodes (gutters included)
         assert np.array_equal(pout.irr_quads(), gi.tiles_to_quads(gi_irr, grid.irr_res))
-        assert np.array_equal(pout.dep.cpu().numpy(), gi.tiles_to_quads(gi_dep, grid.dep_res))
+        assert np.array_equal(pout.dep_quads(), gi.tiles_to_quads(gi_dep, grid.dep_res))
         ri, rd = o.probe_update(sc, grid, i2, d2, 64, hyst, 50.0, 1, 5, slider=slider)
         ei, ed = rel_err(gi_irr, ri), rel_err(gi_dep, rd)
         log(f"probe update h={hyst} slider={slider}: irr mean {ei.mean():.2e} max {ei.max():.2e}; "
