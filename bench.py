@@ -694,10 +694,10 @@ def main():
         "alu_issue": alu_issue(f"k_{dom_key}", cfg.name, avg[dom]),
     }
     if dom_key == "initial" and cfg.glossy_frac == 0.0:
-        # probe records the initial pass's queries read: 8 probes x (24 B binary16 irradiance
-        # + 32 B depth quad) per query, one query per candidate (with a glossy layer the count
-        # depends on how many candidates land on glossy surfaces, so it is not reported)
-        qb = 8 * (24 + 32) * cfg.params.M * npx
+        # probe records the initial pass's queries read: 8 probes x (24 B irradiance + 16 B
+        # depth quad, binary16) per query, one query per candidate (with a glossy layer the
+        # count depends on how many candidates land on glossy surfaces, so it is not reported)
+        qb = 8 * (24 + 16) * cfg.params.M * npx
         line["gather"] = {"kernel": "k_initial", "bytes_per_launch": qb, "unit": "GB/s",
                           "achieved": qb / (avg[dom] * 1e-3) / 1e9,
                           "note": "probe-record bytes read by the queries, served by L1, L2 and MALL"}
