@@ -496,8 +496,8 @@ __device__ __forceinline__ V3 oct_decode(float u, float w)
 // the x-neighbours' records then share cache lines.  Depth records, whose
 // direction differs per probe, stay probe-major.
 constexpr int kIrrN = 8, kDepN = 16;
-constexpr int kIrrQuads = (kIrrN + 1) * (kIrrN + 1);      // 81 records of 12 floats
-constexpr int kDepQuads = (kDepN + 1) * (kDepN + 1);      // 289 records of 8 floats
+constexpr int kIrrQuads = (kIrrN + 1) * (kIrrN + 1);      // 81 records of 12 binary16 values
+constexpr int kDepQuads = (kDepN + 1) * (kDepN + 1);      // 289 records of 8 binary16 values
 constexpr int kDepRecBytes = 16;                          // 4 texels x binary16 (mean, variance)
 
 // binary16 <-> FP32 (the probe records' storage precision; conversions to
@@ -568,6 +568,25 @@ __device__ __forceinline__ const float4 *at_bytes(const float *base, uint32_t of
     return reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
 }
 
+// Raw buffer view of a probe texture of `bytes` bytes: a load takes a 32-bit
+// byte offset in a VGPR against the descriptor's base in SGPRs, so the query
+// forms no 64-bit addresses; a load at or past `bytes` returns zeros.  The
+// last word is the gfx9 raw-buffer format (32-bit data, no swizzle).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tex_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ uint4 tex_load16(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return make_uint4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ uint2 tex_load8(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    return make_uint2(v[0], v[1]);
+}
+
 // Per-axis quantities of the query cell's two corner layers: offsets of the
 // layers' probe coordinate from p, the trilinear fraction toward the upper
 // layer, and the probe-index step between the layers (0 on a one-probe axis).
@@ -595,6 +614,9 @@ __device__ __forceinline__ QueryAxis query_axis(float pv, float lo, float sp, in
 // The per-axis terms are formed once.  The direction toward p is
 // octahedral-encoded unnormalised (the encoding divides by its L1 norm).
 // Probe indices stay below 2^24, so byte offsets are 24-bit products.
+// kUnroll: how many of the four (y, z) corner pairs one loop iteration
+// covers (a code-size / register trade made per kernel).
+template <int kUnroll = 1>
 __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
 {
     const int nx = (int)pr.dims[0], ny = (int)pr.dims[1], nz = (int)pr.dims[2];
@@ -603,14 +625,14 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
     const QueryAxis az = query_axis(p.z, pr.lo[2], pr.spacing[2], nz, (uint32_t)(nx * ny));
     const uint32_t base = ax.base + ay.base + az.base;
     const Bilin bn = bilin(n, kIrrN);
-    const uint32_t irr_q = kIrrRecBytes * (uint32_t)bn.q * (uint32_t)(nx * ny * nz);   // slice of record q
+    const uint32_t np = (uint32_t)(nx * ny * nz);
+    const uint32_t irr_q = kIrrRecBytes * (uint32_t)bn.q * np;   // slice of record q
+    const __amdgpu_buffer_rsrc_t dep_r = tex_rsrc(pr.dep, np * kDepProbeBytes);
+    const __amdgpu_buffer_rsrc_t irr_r = tex_rsrc(pr.irr, np * (uint32_t)kIrrQuads * kIrrRecBytes);
     const float w00 = (1.0f - bn.ax) * (1.0f - bn.ay), w10 = bn.ax * (1.0f - bn.ay);
     const float w01 = (1.0f - bn.ax) * bn.ay, w11 = bn.ax * bn.ay;
     float sx = 0.0f, sy = 0.0f, sz = 0.0f, wsum = 0.0f;
-#ifndef GI_QUERY_UNROLL
-#define GI_QUERY_UNROLL 1
-#endif
-#pragma unroll GI_QUERY_UNROLL
+#pragma unroll kUnroll
     for (int c = 0; c < 4; ++c) {
         const bool oy = (c & 1) != 0, oz = (c & 2) != 0;
         const float dy = oy ? ay.d1 : ay.d0, dz = oz ? az.d1 : az.d0;
@@ -629,13 +651,13 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
             // depth moments toward p (a probe sitting exactly at p reads any texel, unused)
             const V3 dv = at_probe ? v3(0.0f, 0.0f, 1.0f) : -tp;
             const Bilin bd = bilin(dv, kDepN);
-            const uint4 dq = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(pr.dep) +
-                                                             __umul24(pi, kDepProbeBytes) +
-                                                             (uint32_t)kDepRecBytes * (uint32_t)bd.q);
+            const uint4 dq = tex_load16(dep_r, __umul24(pi, kDepProbeBytes) + (uint32_t)kDepRecBytes * (uint32_t)bd.q);
             const float2 d0 = dep_texel(dq.x), d1 = dep_texel(dq.y), d2 = dep_texel(dq.z), d3 = dep_texel(dq.w);
-            const uint2 *qr = reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(pr.irr) + irr_q +
-                                                              __umul24(pi, kIrrRecBytes));
-            const float4 e0 = half4_to_float4(qr[0]), e1 = half4_to_float4(qr[1]), e2 = half4_to_float4(qr[2]);
+            const uint32_t io = irr_q + __umul24(pi, kIrrRecBytes);
+            const uint4 ia = tex_load16(irr_r, io);
+            const uint2 ib = tex_load8(irr_r, io + 16u);
+            const float4 e0 = half4_to_float4(make_uint2(ia.x, ia.y)), e1 = half4_to_float4(make_uint2(ia.z, ia.w));
+            const float4 e2 = half4_to_float4(ib);
             const float v00 = (1.0f - bd.ax) * (1.0f - bd.ay), v10 = bd.ax * (1.0f - bd.ay);
             const float v01 = (1.0f - bd.ax) * bd.ay, v11 = bd.ax * bd.ay;
             const float mu = v00 * d0.x + v10 * d1.x + v01 * d2.x + v11 * d3.x;
@@ -667,12 +689,13 @@ __device__ __forceinline__ V3 view_bias(V3 y, V3 x, float d)
 }
 
 // L_e(y) + rho_y Q(y_b, n_y), y_b biased toward x
+template <int kUnroll = 1>
 __device__ __forceinline__ V3 radiance_toward(const gi_scene &sc, const gi_probes &pr, uint32_t prim, V3 y, V3 ny, V3 x)
 {
     V3 alb, emit;
     material(sc, prim, alb, emit);
     if (is_zero(alb)) return emit;
-    V3 q = probe_query(pr, view_bias(y, x, pr.bias_dist), ny);
+    V3 q = probe_query<kUnroll>(pr, view_bias(y, x, pr.bias_dist), ny);
     return v3(fmaf(alb.x, q.x, emit.x), fmaf(alb.y, q.y, emit.y), fmaf(alb.z, q.z, emit.z));
 }
 

@@ -594,8 +594,9 @@ __global__ void __launch_bounds__(kBlock, 4)
                         wi = phat * rcp(mixb * pA + mixl * light_pdf(sc, prim));
                     if (i == 0 && G > pp.g_max && pA > 0.0f) { const V3 q = ((G - pp.g_max) * rcp(pA)) * f; sel[3] = make_float4(q.x, q.y, q.z, 0.0f); }
                 } else {
+                    // (the query unrolled over two corner pairs is the faster form here)
                     L = (use_cache && i < pp.M) ? radiance_cached(sc, prim, ws.q[i * npx + p])
-                                                : radiance_toward(sc, pr, prim, y, ny, g.pos);
+                                                : radiance_toward<2>(sc, pr, prim, y, ny, g.pos);
                     float G = cx * cy * rcp(d2);
                     float fl = lum(rho_pi * L);
                     float iG = rcp(G);
