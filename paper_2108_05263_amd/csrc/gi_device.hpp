@@ -233,49 +233,86 @@ struct GeoGlobal {
     __device__ __forceinline__ uint32_t cell(uint32_t c) const { return cells[c]; }
     __device__ __forceinline__ uint32_t item(uint32_t j) const { return items[j]; }
     __device__ __forceinline__ bool has_grid() const { return cells != nullptr; }
+    static constexpr bool kSplit = false;   // a cell's items in id order, types mixed
+    __device__ __forceinline__ uint32_t mid(uint32_t) const { return 0u; }
 };
 
 // Scene access through a workgroup-local copy in LDS (see stage_scene):
 // [2 float4 of geometry per primitive, as geo_records forms them]
-// [cell_start: ncells+1][items]
+// [cell_start: ncells+1][cell_mid: ncells][items]
+// With kSplit, each cell's items are reordered in LDS so that its spheres
+// come first: cell c lists spheres at [cell_start[c], cell_mid[c]) and boxes
+// at [cell_mid[c], cell_start[c+1]), and a walk tests each run with one
+// intersection routine instead of branching per item on its type.  The
+// closest hit is the smallest (t, id) pair, so the order does not change it.
+// The reordering costs a pass over the items per workgroup; it pays off in
+// kernels that cast many rays per pixel.
 extern __shared__ float4 gi_lds[];
 
-struct GeoLds {
+template <bool kSplitCells>
+struct GeoLdsT {
     uint32_t n_prims, n_cells;
-    __device__ __forceinline__ explicit GeoLds(const gi_scene &sc)
+    __device__ __forceinline__ explicit GeoLdsT(const gi_scene &sc)
         : n_prims(sc.n_prims), n_cells(sc.grid_res[0] * sc.grid_res[1] * sc.grid_res[2]) {}
     __device__ __forceinline__ PrimGeo geo(uint32_t i) const { return geo_of(gi_lds[2 * i], gi_lds[2 * i + 1]); }
     __device__ __forceinline__ uint32_t cell(uint32_t c) const
     {
         return reinterpret_cast<const uint32_t *>(gi_lds + 2 * n_prims)[c];
     }
+    __device__ __forceinline__ uint32_t mid(uint32_t c) const
+    {
+        return reinterpret_cast<const uint32_t *>(gi_lds + 2 * n_prims)[n_cells + 1 + c];
+    }
     __device__ __forceinline__ uint32_t item(uint32_t j) const
     {
-        return reinterpret_cast<const uint32_t *>(gi_lds + 2 * n_prims)[n_cells + 1 + j];
+        return reinterpret_cast<const uint32_t *>(gi_lds + 2 * n_prims)[2 * n_cells + 1 + j];
     }
     __device__ __forceinline__ bool has_grid() const { return true; }
+    static constexpr bool kSplit = kSplitCells;
 };
+using GeoLds = GeoLdsT<false>;
 
 // Bytes of LDS the staged scene needs (host and device agree on this layout).
 __host__ __device__ __forceinline__ uint32_t lds_scene_bytes(const gi_scene &sc)
 {
     uint32_t nc = sc.grid_res[0] * sc.grid_res[1] * sc.grid_res[2];
-    uint32_t words = nc + 1 + sc.n_items;
+    uint32_t words = 2 * nc + 1 + sc.n_items;
     return 32u * sc.n_prims + ((4u * words + 15u) & ~15u);
 }
 
-// Cooperative copy of primitive geometry and the grid into LDS; every
-// thread of the workgroup must call it (it ends with a barrier).
+// Cooperative copy of primitive geometry and the grid into LDS (with
+// kSplit, then the per-cell partition of the items by type); every thread
+// of the workgroup must call it (it ends with a barrier).
+template <bool kSplit = false>
 __device__ __forceinline__ void stage_scene(const gi_scene &sc)
 {
     const float4 *src = reinterpret_cast<const float4 *>(sc.prims);
     const uint32_t n2 = 2u * sc.n_prims, bs = blockDim.x;
     for (uint32_t i = threadIdx.x; i < sc.n_prims; i += bs) geo_records(src[4u * i], src[4u * i + 1u], gi_lds[2u * i], gi_lds[2u * i + 1u]);
     uint32_t *w = reinterpret_cast<uint32_t *>(gi_lds + n2);
-    const uint32_t nc = sc.grid_res[0] * sc.grid_res[1] * sc.grid_res[2] + 1u;
+    const uint32_t ncell = sc.grid_res[0] * sc.grid_res[1] * sc.grid_res[2], nc = ncell + 1u;
+    uint32_t *mids = w + nc, *items = w + nc + ncell;
     for (uint32_t i = threadIdx.x; i < nc; i += bs) w[i] = sc.cell_start[i];
-    for (uint32_t i = threadIdx.x; i < sc.n_items; i += bs) w[nc + i] = sc.cell_items[i];
+    for (uint32_t i = threadIdx.x; i < sc.n_items; i += bs) items[i] = sc.cell_items[i];
     __syncthreads();
+    if constexpr (kSplit) {
+        // one thread per cell: swap boxes to the back of the cell's run
+        for (uint32_t c = threadIdx.x; c < ncell; c += bs) {
+            uint32_t j = w[c], k = w[c + 1u];
+            while (j < k) {
+                const uint32_t it = items[j];
+                if (__float_as_uint(gi_lds[2u * it].w) == 0u) {
+                    ++j;
+                } else {
+                    --k;
+                    items[j] = items[k];
+                    items[k] = it;
+                }
+            }
+            mids[c] = j;
+        }
+        __syncthreads();
+    }
 }
 
 // keep the lexicographically smallest (t, id): equal distances go to the
@@ -369,12 +406,37 @@ __device__ __forceinline__ bool cast(const gi_scene &sc, const G &acc, V3 o, V3 
     const int cx = sx, cy = sy * rx, cz = sz * rx * ry;
     for (int step = 0; step < max_steps; ++step) {
         uint32_t b = acc.cell((uint32_t)cell), e = acc.cell((uint32_t)cell + 1u);
-        for (uint32_t j = b; j < e; ++j) {
-            uint32_t i = acc.item(j);
-            if (ANY) {
-                if (occludes_prim(acc, i, o, d, inv, tmax)) { h.prim = i; return true; }
-            } else {
-                test_prim(acc, i, o, d, inv, h);
+        if constexpr (G::kSplit) {
+            // the cell's spheres, then its boxes (see GeoLdsT)
+            const uint32_t m = acc.mid((uint32_t)cell);
+            for (uint32_t j = b; j < m; ++j) {
+                const uint32_t i = acc.item(j);
+                const PrimGeo g = acc.geo(i);
+                const float t = isect_sphere(o, d, g.c, g.s.x);
+                if (ANY) {
+                    if (t < tmax) { h.prim = i; return true; }
+                } else {
+                    take_hit(h, t, i);
+                }
+            }
+            for (uint32_t j = m; j < e; ++j) {
+                const uint32_t i = acc.item(j);
+                const PrimGeo g = acc.geo(i);
+                const float t = isect_box(o, inv, g.c, g.s);
+                if (ANY) {
+                    if (t < tmax) { h.prim = i; return true; }
+                } else {
+                    take_hit(h, t, i);
+                }
+            }
+        } else {
+            for (uint32_t j = b; j < e; ++j) {
+                uint32_t i = acc.item(j);
+                if (ANY) {
+                    if (occludes_prim(acc, i, o, d, inv, tmax)) { h.prim = i; return true; }
+                } else {
+                    test_prim(acc, i, o, d, inv, h);
+                }
             }
         }
         float texit = fminf(nx, fminf(ny, nz));

@@ -499,11 +499,11 @@ __global__ void __launch_bounds__(kBlock, 4)
     k_initial(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_params pp, gi_reservoirs out, float4 *resid,
               uint64_t seed, uint32_t frame, CandWs ws, gi_mlp mlp)
 {
-    using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
+    using Acc = typename std::conditional<LDS, GeoLdsT<true>, GeoGlobal>::type;
     if (gated_off(ws, mlp)) return;
     uint32_t px, py;
     const bool inside = tile_pixel(gb.width, gb.height, px, py);
-    if (LDS) stage_scene(sc);
+    if (LDS) stage_scene<true>(sc);
     if (!inside) return;
     const Acc acc(sc);
     const uint32_t p = py * gb.width + px;
