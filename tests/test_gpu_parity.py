@@ -330,11 +330,7 @@ def test_free_running(gi, request, which, frames):
         assert flips <= 1e-3
 
 
-@pytest.mark.parametrize("which", ["tiny", "hd_small"])
-def test_lds_staging_matches_global(gi, request, which):
-    """Tracing from the LDS copy of the scene gives bit-identical frames."""
-    cfg, sc, grid, irr, dep = request.getfixturevalue(which)
-    W, H = (64, 64) if which == "tiny" else (250, 141)
+def _lds_vs_global(gi, cfg, sc, irr, dep, W, H):
     out = []
     for lds in (True, False):
         r = gi.Renderer(cfg, seed=2, width=W, height=H, scene=sc, lds=lds)
@@ -345,6 +341,29 @@ def test_lds_staging_matches_global(gi, request, which):
         out.append((r.img.cpu().numpy().copy(), r.hist.to_records()))
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("which", ["tiny", "hd_small"])
+def test_lds_staging_matches_global(gi, request, which):
+    """Tracing from the LDS copy of the scene gives bit-identical frames."""
+    cfg, sc, grid, irr, dep = request.getfixturevalue(which)
+    W, H = (64, 64) if which == "tiny" else (250, 141)
+    _lds_vs_global(gi, cfg, sc, irr, dep, W, H)
+
+
+def test_lds_staging_matches_global_interleaved_types(gi, hd_small):
+    """The initial pass reorders each staged cell's items (spheres, then
+    boxes).  With the room's primitives renumbered in a shuffled order the
+    types interleave in id order, so the reordering swaps items in most
+    cells; the frames stay bit-identical to the walk over the caller's
+    id-ordered lists (the closest hit is the smallest (t, id) pair)."""
+    cfg, sc, grid, irr, dep = hd_small
+    perm = np.random.default_rng(5).permutation(sc.n_prims)
+    sc2 = dataclasses.replace(sc, prims=np.ascontiguousarray(sc.prims[perm]))
+    types = sc2.prims.view(np.uint32)[:, 3]
+    assert np.sum(np.diff(types.astype(np.int64)) != 0) > sc.n_prims // 4
+    log(f"interleaved types: {int(np.sum(np.diff(types.astype(np.int64)) != 0))} type changes in id order")
+    _lds_vs_global(gi, cfg, sc2, irr, dep, 250, 141)
 
 
 def test_determinism(gi, tiny):
