@@ -37,6 +37,8 @@ HBM_PEAK_GBS = 8000.0
 #            records are re-reads of the same buffer)
 #   shade    reads G-buffer 52 + reservoir 56 + resid 12; writes 12 = 132
 ALGO_BYTES = {"gbuffer": 56, "initial": 104, "temporal": 236, "spatial": 152, "shade": 132}
+# probe-record bytes one probe fetch reads (irradiance + depth quad) per texel format
+PROBE_RECORD_BYTES = {"f32": 48 + 32, "f16": 24 + 16}
 
 
 def parse():
@@ -48,6 +50,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-crop", type=int, nargs=2, default=(320, 180))
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-cache forms")
+    ap.add_argument("--probe-texel", choices=["f32", "f16"], default="f32",
+                    help="probe texel storage of the timed probe form (the workloads specify FP32)")
+    ap.add_argument("--no-f16-form", action="store_true",
+                    help="skip the extra timing of the same frames from binary16 probe textures")
     ap.add_argument("--mlp-train-frames", type=int, default=64,
                     help="untimed frames of online training before the learned-cache forms are timed")
     ap.add_argument("--mlp-only", choices=["bf16", "fp8"], default=None,
@@ -414,7 +420,7 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
 # --------------------------------------------------------------------------
 # rocprofv3 runs behind the committed profiles/ summaries
 # --------------------------------------------------------------------------
-PROBE_INITIAL = "k_initial<true, false, false, false>"       # the probe form's initial pass (scene in LDS)
+PROBE_INITIAL = "k_initial<true, false, false, false, 0>"    # the probe form's initial pass (scene in LDS, FP32 texels)
 SQ_SETS = {"sq1": "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU "
                   "SQ_ACTIVE_INST_LDS SQ_INSTS_VMEM_RD",
            "sq2": "SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_ACTIVE_INST_ANY SQ_THREAD_CYCLES_VALU TCC_HIT_sum "
@@ -431,7 +437,7 @@ def profile_commands(outdir):
     initial pass, MFMA counters of the inference kernels."""
     bench = f"python3 -u {os.path.join(ROOT, 'bench.py')}"
     pre = "cd /tmp && TMPDIR=/tmp timeout -s KILL 240 rocprofv3"
-    probe = f"{bench} --steps 2 --warmup 1 --no-cpu --no-mlp"
+    probe = f"{bench} --steps 2 --warmup 1 --no-cpu --no-mlp --no-f16-form"
     cmds = {"kt": f"{pre} --kernel-trace --stats --output-format csv -d {outdir}/kt -o hd -- "
                   f"{bench} --steps 5 --warmup 2 --no-cpu --mlp-train-frames 8",
             "fetch": f"{pre} --pmc FETCH_SIZE --output-format csv -d {outdir}/fetch -o hd -- {probe} --profile-copy",
@@ -567,6 +573,62 @@ def summarize_profiles(outdir, ms_initial=None):
     return written
 
 
+def time_frames(gi, torch, cfg, steps, warmup, profile_copy=False):
+    """Render warm-up + timed frames of a workload with the probe target;
+    per-pass HIP-event times recorded on the launch stream."""
+    r = gi.Renderer(cfg, seed=1)
+    r.fill_probes()
+    stream = torch.cuda.current_stream()
+    names = ["gbuffer", "initial", "temporal", "spatial0", "spatial1", "shade"]
+
+    # wrap the entry points with HIP events recorded on the launch stream
+    times = {k: [] for k in names}
+    orig = {k: getattr(gi, k) for k in ("trace_gbuffer", "resample_initial", "resample_temporal",
+                                        "resample_spatial", "shade")}
+    pending = []
+
+    def timed(key_fn, fn):
+        def wrapper(*a, **kw):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn(*a, **kw)
+            e1.record(stream)
+            pending.append((key_fn(a), e0, e1))
+        return wrapper
+
+    gi.trace_gbuffer = timed(lambda a: "gbuffer", orig["trace_gbuffer"])
+    gi.resample_initial = timed(lambda a: "initial", orig["resample_initial"])
+    gi.resample_temporal = timed(lambda a: "temporal", orig["resample_temporal"])
+    gi.resample_spatial = timed(lambda a: f"spatial{a[4]}", orig["resample_spatial"])
+    gi.shade = timed(lambda a: "shade", orig["shade"])
+    try:
+        for f in range(warmup):
+            r.frame(f)
+        torch.cuda.synchronize()
+        pending.clear()
+        t0 = time.perf_counter()
+        for f in range(warmup, warmup + steps):
+            r.frame(f)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+    finally:
+        for k, v in orig.items():
+            setattr(gi, k, v)
+    for key, e0, e1 in pending:
+        times[key].append(e0.elapsed_time(e1))
+    if profile_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    W, H = r.W, r.H
+    del r
+    torch.cuda.empty_cache()
+    return {"elapsed": elapsed, "avg": {k: (sum(v) / len(v) if v else 0.0) for k, v in times.items()},
+            "W": W, "H": H}
+
+
 def main():
     args = parse()
     if args.profile_commands:
@@ -603,62 +665,19 @@ def main():
             torch.empty_like(src).copy_(src)
             torch.cuda.synchronize()
         return
-    r = gi.Renderer(cfg, seed=1)
-    r.fill_probes()
-    stream = torch.cuda.current_stream()
-    names = ["gbuffer", "initial", "temporal", "spatial0", "spatial1", "shade"]
-
-    # wrap the entry points with HIP events recorded on the launch stream
-    times = {k: [] for k in names}
-    orig = {k: getattr(gi, k) for k in ("trace_gbuffer", "resample_initial", "resample_temporal",
-                                        "resample_spatial", "shade")}
-    pending = []
-
-    def timed(key_fn, fn):
-        def wrapper(*a, **kw):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            fn(*a, **kw)
-            e1.record(stream)
-            pending.append((key_fn(a), e0, e1))
-        return wrapper
-
-    gi.trace_gbuffer = timed(lambda a: "gbuffer", orig["trace_gbuffer"])
-    gi.resample_initial = timed(lambda a: "initial", orig["resample_initial"])
-    gi.resample_temporal = timed(lambda a: "temporal", orig["resample_temporal"])
-    gi.resample_spatial = timed(lambda a: f"spatial{a[4]}", orig["resample_spatial"])
-    gi.shade = timed(lambda a: "shade", orig["shade"])
-
-    for f in range(args.warmup):
-        r.frame(f)
-    torch.cuda.synchronize()
-    pending.clear()
-    t0 = time.perf_counter()
-    for f in range(args.warmup, args.warmup + args.steps):
-        r.frame(f)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for key, e0, e1 in pending:
-        times[key].append(e0.elapsed_time(e1))
-    for k, v in orig.items():
-        setattr(gi, k, v)
-    if args.profile_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    W, H = r.W, r.H
+    if args.probe_texel != cfg.probe_texel:
+        cfg = dataclasses.replace(cfg, probe_texel=args.probe_texel)
+    run = time_frames(gi, torch, cfg, args.steps, args.warmup, args.profile_copy)
+    elapsed, avg = run["elapsed"], run["avg"]
+    W, H = run["W"], run["H"]
     npx = W * H
     ms_step = elapsed * 1e3 / args.steps
-    avg = {k: (sum(v) / len(v) if v else 0.0) for k, v in times.items()}
     resampling_ms = avg["initial"] + avg["temporal"] + avg["spatial0"] + avg["spatial1"] + avg["shade"]
     dom = max(avg, key=avg.get)
     dom_key = "spatial" if dom.startswith("spatial") else dom
     bytes_launch = ALGO_BYTES[dom_key] * npx
     achieved = bytes_launch / (avg[dom] * 1e-3) / 1e9
-    path_bytes = sum(ALGO_BYTES[k if not k.startswith("spatial") else "spatial"] for k in names) * npx
+    path_bytes = sum(ALGO_BYTES[k if not k.startswith("spatial") else "spatial"] for k in avg) * npx
     line = {
         "metric": ("resampled pixels/s (1080p, M=32, 2xk=5)" if (W, H) == (1920, 1080) and cfg.glossy_frac == 0.0
                    else f"resampled pixels/s ({W}x{H}{' glossy' if cfg.glossy_frac > 0.0 else ''}, "
@@ -694,16 +713,24 @@ def main():
         "alu_issue": alu_issue(f"k_{dom_key}", cfg.name, avg[dom]),
     }
     if dom_key == "initial" and cfg.glossy_frac == 0.0:
-        # probe records the initial pass's queries read: 8 probes x (24 B irradiance + 16 B
-        # depth quad, binary16) per query, one query per candidate (with a glossy layer the
-        # count depends on how many candidates land on glossy surfaces, so it is not reported)
-        qb = 8 * (24 + 16) * cfg.params.M * npx
+        # probe records the initial pass's queries read: 8 probes x (irradiance + depth
+        # quad: 48 + 32 B in FP32, 24 + 16 B in binary16) per query, one query per candidate
+        # (with a glossy layer the count depends on how many candidates land on glossy
+        # surfaces, so it is not reported)
+        qb = 8 * PROBE_RECORD_BYTES[cfg.probe_texel] * cfg.params.M * npx
         line["gather"] = {"kernel": "k_initial", "bytes_per_launch": qb, "unit": "GB/s",
                           "achieved": qb / (avg[dom] * 1e-3) / 1e9,
                           "note": "probe-record bytes read by the queries, served by L1, L2 and MALL"}
+    line["config"]["probe_texel"] = cfg.probe_texel
+    if cfg.probe_texel == "f32" and not args.no_f16_form:
+        # the same frames from binary16 probe textures (a storage-precision option)
+        h = time_frames(gi, torch, dataclasses.replace(cfg, probe_texel="f16"), args.steps, args.warmup)
+        h_ms = h["elapsed"] * 1e3 / args.steps
+        line["probe_f16_form"] = {"ms_per_step": h_ms, "pixels_per_s": npx * args.steps / h["elapsed"],
+                                  "kernel_ms": {k: round(v, 4) for k, v in h["avg"].items()},
+                                  "speed_ratio_vs_f32": ms_step / h_ms,
+                                  "note": "probe texels stored as IEEE binary16 (depth as mean and variance)"}
     if not args.no_mlp and cfg.glossy_frac == 0.0:
-        del r
-        torch.cuda.empty_cache()
         forms = {}
         for prec in ("bf16", "fp8"):
             for mode in ("always", "auto"):

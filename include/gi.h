@@ -144,35 +144,45 @@ typedef struct gi_gbuffer {
 #define GI_GB_F32 0u
 #define GI_GB_F16 1u
 
+/* Texel formats of a probe volume (gi_probes.texel) */
+#define GI_TEXEL_F32 0u   /* FP32 texels */
+#define GI_TEXEL_F16 1u   /* IEEE binary16 texels */
+
 /* DDGI probe volume.  Probe (i, j, k), index i + dims[0]*(j + dims[1]*k),
  * sits at lo + (idx + 0.5) * spacing.  Each probe owns an octahedral
  * irradiance tile (irr_res^2 texels of E/pi, RGB) and depth tile (dep_res^2
  * texels of the mean and mean square hit distance), each with a one-texel
  * gutter that mirrors the interior along the tile edge (corners take the
- * diagonally opposite interior texel).  Texels are stored as IEEE binary16
- * values (gi_probe_update rounds to nearest even): irradiance as RGB, depth
- * as the mean and the variance (mean square minus squared mean; the query
- * rebuilds the mean square as variance + mean^2).  They are stored as
- * bilinear quads:
- *   irr: (irr_res+1)^2 records of 12 binary16 values (24 bytes) per probe,
- *        quad-major: record q = cy*(irr_res+1)+cx of probe i is record
- *        q*P + i (P probes), and holds the RGB of padded texels (cx,cy),
- *        (cx+1,cy), (cx,cy+1), (cx+1,cy+1) in that order (1944 bytes per
- *        probe in all);
- *   dep: per probe (dep_res+1)^2 records of 8 binary16 values (16 bytes),
- *        (mean, variance) of the same four padded texels, probe-major (4624
- *        bytes per probe).
+ * diagonally opposite interior texel).  Texels are stored in the volume's
+ * texel format:
+ *   GI_TEXEL_F32: FP32 values, depth texels as (mean, mean square);
+ *   GI_TEXEL_F16: IEEE binary16 values (gi_probe_update rounds to nearest
+ *        even), depth texels as (mean, variance), the variance being the mean
+ *        square minus the squared mean (the query rebuilds the mean square as
+ *        variance + mean^2).
+ * They are stored as bilinear quads:
+ *   irr: (irr_res+1)^2 records of 12 values per probe (48 bytes in FP32, 24
+ *        in binary16), quad-major: record q = cy*(irr_res+1)+cx of probe i is
+ *        record q*P + i (P probes), and holds the RGB of padded texels
+ *        (cx,cy), (cx+1,cy), (cx,cy+1), (cx+1,cy+1) in that order (3888 or
+ *        1944 bytes per probe in all);
+ *   dep: per probe (dep_res+1)^2 records of 8 values (32 or 16 bytes), the
+ *        two depth values of the same four padded texels, probe-major (9248
+ *        or 4624 bytes per probe).
  * irr_res must be 8 and dep_res 16; the volume holds at most 464,000
  * probes (each texture then stays under 4 GiB, so kernels address it with
- * 32-bit byte offsets; larger volumes return GI_ERR_SHAPE).  bias_dist is the view-path bias d,
- * var_floor the Chebyshev variance floor, d_max the probe-ray depth clamp. */
+ * 32-bit byte offsets; larger volumes return GI_ERR_SHAPE); texel must be
+ * one of the formats above (else GI_ERR_PARAM).  bias_dist is the view-path
+ * bias d, var_floor the Chebyshev variance floor, d_max the probe-ray depth
+ * clamp. */
 typedef struct gi_probes {
     uint32_t dims[3];
     uint32_t irr_res, dep_res;
     float lo[3], spacing[3];
     float bias_dist, var_floor, d_max;
-    uint16_t *irr;        /* binary16 bits */
-    uint16_t *dep;        /* binary16 bits */
+    uint32_t texel;       /* GI_TEXEL_F32 or GI_TEXEL_F16 */
+    void *irr;            /* device, records as above */
+    void *dep;            /* device, records as above */
 } gi_probes;
 
 /* Reservoirs, SoA planes of width*height records:
@@ -244,7 +254,10 @@ gi_status gi_trace_gbuffer(const gi_scene *scene, const gi_camera *cam, gi_gbuff
  * reached at ray length t is scaled by (t / (t + s d_b))^2, d_b = the
  * probe's own mean depth (input texture) in the backward direction, clipped
  * to the distance from the probe to its cell boundary along that direction.
- * Reads only `in`, writes only `out` (same layout, must not alias). */
+ * The blend reads the old texels and stores the new ones in the volume's
+ * texel format (binary16: each stored value rounded to nearest even).
+ * Reads only `in`, writes only `out` (same layout and texel format, else
+ * GI_ERR_SHAPE / GI_ERR_PARAM; must not alias). */
 gi_status gi_probe_update(const gi_scene *scene, const gi_probes *in, gi_probes *out,
                           const gi_probe_params *pp, uint64_t seed, uint32_t frame, void *stream);
 

@@ -19,11 +19,12 @@
  *   G-buffer pixel  [14]: pos[3] nrm[3] albedo[3] emit[3] view_depth prim
  *   reservoir       [14]: y[3] n_y[3] L[3] wsum W M tag prim
  *   probe textures : irr[P][(Ni+2)^2][3] (E/pi), dep[P][(Nd+2)^2][2] (mean, mean^2);
- *                    texels are kept at their storage precision: binary16
- *                    (o_round_half) irradiance, and for depth a binary16 mean
- *                    and variance with the mean square rebuilt from them
- *                    (dep_texel); the update stores them so, the query
- *                    reads a caller's tile so
+ *                    texels are kept at their storage precision: with
+ *                    o_probes.texel = 0 at full precision, with texel = 1
+ *                    as binary16 (o_round_half) irradiance, and for depth a
+ *                    binary16 mean and variance with the mean square rebuilt
+ *                    from them (dep_texel); the update stores them so, the
+ *                    query reads a caller's tile so
  * A reservoir whose sample left the scene stores the direction in y and a
  * zero normal in n_y.
  */
@@ -86,7 +87,7 @@ typedef struct {
     /* learned cache used as the target instead of the probe query (NULL: probes) */
     const double *mlp;              /* 17731 parameters, layout of oracle/mlp_ref.py */
     int32_t mlp_prec;               /* 0: FP64, 1: BF16 operands */
-    int32_t mlp_pad;
+    int32_t texel;                  /* texel storage: 0 full precision, 1 binary16 */
     double mlp_lo[3], mlp_hi[3];    /* position normalisation box */
 } o_probes;
 
@@ -547,20 +548,29 @@ void o_tile_fetch(const double *tile, int N, int C, const double *v, double *out
     tile_fetch(tile, N, C, v, out);
 }
 
-/* A depth texel (mean, mean square) at its storage precision: the mean and
- * the variance (mean square minus squared mean) as binary16 values, the mean
- * square rebuilt from them.  The variance is rounded, not the mean square,
- * because at 11 bits the difference of two rounded squares of similar size
- * would lose the variance. */
-static void dep_texel(const double *t, double *m)
+/* A depth texel (mean, mean square) at its storage precision.  Binary16
+ * (half != 0): the mean and the variance (mean square minus squared mean) as
+ * binary16 values, the mean square rebuilt from them.  The variance is
+ * rounded, not the mean square, because at 11 bits the difference of two
+ * rounded squares of similar size would lose the variance.  Full precision:
+ * the texel as it is. */
+static void dep_texel(const double *t, double *m, int half)
 {
+    if (!half) {
+        m[0] = t[0];
+        m[1] = t[1];
+        return;
+    }
     double mu = o_round_half(t[0]), var = o_round_half(t[1] - t[0] * t[0]);
     m[0] = mu;
     m[1] = var + mu * mu;
 }
 
+/* an irradiance texel channel at its storage precision */
+static double irr_texel(double v, int half) { return half ? o_round_half(v) : v; }
+
 /* bilinear fetch of a depth tile, texels read at their storage precision */
-static void dep_fetch(const double *tile, int N, const double *v, double *out)
+static void dep_fetch(const double *tile, int N, const double *v, int half, double *out)
 {
     double uv[2];
     o_oct_encode(v, uv);
@@ -572,15 +582,15 @@ static void dep_fetch(const double *tile, int N, const double *v, double *out)
     for (int dy = 0; dy < 2; ++dy)
         for (int dx = 0; dx < 2; ++dx) {
             double w = (dx ? ax : 1.0 - ax) * (dy ? ay : 1.0 - ay), m[2];
-            dep_texel(tile + 2 * ((size_t)(y0 + dy) * P + (x0 + dx)), m);
+            dep_texel(tile + 2 * ((size_t)(y0 + dy) * P + (x0 + dx)), m, half);
             out[0] += w * m[0];
             out[1] += w * m[1];
         }
 }
 
 /* the same fetch of an irradiance tile, whose texels are read at the
- * storage precision (binary16) whatever the caller's tile holds */
-static void irr_fetch(const double *tile, int N, const double *v, double *out)
+ * storage precision whatever the caller's tile holds */
+static void irr_fetch(const double *tile, int N, const double *v, int half, double *out)
 {
     double uv[2];
     o_oct_encode(v, uv);
@@ -593,7 +603,7 @@ static void irr_fetch(const double *tile, int N, const double *v, double *out)
         for (int dx = 0; dx < 2; ++dx) {
             double w = (dx ? ax : 1.0 - ax) * (dy ? ay : 1.0 - ay);
             const double *t = tile + 3 * ((size_t)(y0 + dy) * P + (x0 + dx));
-            for (int c = 0; c < 3; ++c) out[c] += w * o_round_half(t[c]);
+            for (int c = 0; c < 3; ++c) out[c] += w * irr_texel(t[c], half);
         }
 }
 
@@ -668,7 +678,7 @@ static void probe_query(const o_probes *pr, const double *p, const double *n, in
             double h = 0.5 * (1.0 + dot3(n, w));
             back = h * h + 0.2;
             double from_probe[3] = {-w[0], -w[1], -w[2]}, mom[2];
-            dep_fetch(pr->dep + pi * dep_tile, Nd, from_probe, mom);
+            dep_fetch(pr->dep + pi * dep_tile, Nd, from_probe, pr->texel, mom);
             if (r > mom[0]) {
                 double var = fmax(mom[1] - mom[0] * mom[0], pr->var_floor);
                 double dd = r - mom[0];
@@ -680,7 +690,7 @@ static void probe_query(const o_probes *pr, const double *p, const double *n, in
         if (flags & 2) vis = 1.0;
         double w = tri * fmax(back * vis, 1e-6);
         double irr[3];
-        irr_fetch(pr->irr + pi * irr_tile, Ni, n, irr);
+        irr_fetch(pr->irr + pi * irr_tile, Ni, n, pr->texel, irr);
         for (int a = 0; a < 3; ++a) sum[a] += w * irr[a];
         wsum += w;
     }
@@ -871,7 +881,7 @@ void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, doub
                      * inverse square of that total relative to t, with the backward
                      * part weighted by the per-scene slider */
                     double back[3] = {-dirs[r][0], -dirs[r][1], -dirs[r][2]}, mom[2];
-                    dep_fetch(in->dep + pi * dep_tile, Nd, back, mom);
+                    dep_fetch(in->dep + pi * dep_tile, Nd, back, in->texel, mom);
                     double clip = O_INF;
                     for (int a = 0; a < 3; ++a)
                         if (back[a] != 0.0) clip = fmin(clip, 0.5 * in->spacing[a] / fabs(back[a]));
@@ -918,9 +928,10 @@ void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, doub
                 }
                 size_t o = 3 * ((size_t)(ty + 1) * (Ni + 2) + (tx + 1));
                 for (int a = 0; a < 3; ++a) {
-                    double nv = den > 0.0 ? num[a] / den : o_round_half(iold[o + a]);
-                    /* stored at binary16, blended from the stored (rounded) old texel */
-                    inew[o + a] = o_round_half(hysteresis * o_round_half(iold[o + a]) + (1.0 - hysteresis) * nv);
+                    const double old = irr_texel(iold[o + a], in->texel);
+                    double nv = den > 0.0 ? num[a] / den : old;
+                    /* stored at the storage precision, blended from the stored old texel */
+                    inew[o + a] = irr_texel(hysteresis * old + (1.0 - hysteresis) * nv, in->texel);
                 }
             }
         for (int ty = 0; ty < Nd; ++ty)
@@ -935,15 +946,16 @@ void o_probe_update(const o_scene *sc, const o_probes *in, double *irr_out, doub
                     den += w;
                 }
                 size_t o = 2 * ((size_t)(ty + 1) * (Nd + 2) + (tx + 1));
-                /* blended from the stored old texel, stored at binary16 as
-                 * (mean, variance) and kept here as (mean, mean square) */
+                /* blended from the stored old texel, stored at the storage
+                 * precision (binary16: as (mean, variance)) and kept here as
+                 * (mean, mean square) */
                 double old[2], b[2];
-                dep_texel(dold + o, old);
+                dep_texel(dold + o, old, in->texel);
                 double n1 = den > 0.0 ? m1 / den : old[0];
                 double n2 = den > 0.0 ? m2 / den : old[1];
                 b[0] = hysteresis * old[0] + (1.0 - hysteresis) * n1;
                 b[1] = hysteresis * old[1] + (1.0 - hysteresis) * n2;
-                dep_texel(b, dnew + o);
+                dep_texel(b, dnew + o, in->texel);
             }
         fill_gutter(inew, Ni, 3);
         fill_gutter(dnew, Nd, 2);

@@ -50,7 +50,7 @@ class OProbes(C.Structure):
                 ("lo", C.c_double * 3), ("spacing", C.c_double * 3), ("bias_dist", C.c_double),
                 ("var_floor", C.c_double), ("d_max", C.c_double),
                 ("irr", C.c_void_p), ("dep", C.c_void_p), ("mlp", C.c_void_p),
-                ("mlp_prec", C.c_int32), ("mlp_pad", C.c_int32),
+                ("mlp_prec", C.c_int32), ("texel", C.c_int32),
                 ("mlp_lo", C.c_double * 3), ("mlp_hi", C.c_double * 3)]
 
 
@@ -180,6 +180,16 @@ class MlpTarget:
         self.prec = 1 if prec == "bf16" else 0
 
 
+def texel_code(grid) -> int:
+    """The oracle's texel-precision switch for a probe grid: 0 keeps texels
+    at full precision (the FP32 textures), 1 rounds them as the binary16
+    textures store them."""
+    t = getattr(grid, "texel", "f32")
+    if t not in ("f32", "f16"):
+        raise ValueError(f"unknown probe texel format {t!r}")
+    return 1 if t == "f16" else 0
+
+
 class _Probes:
     def __init__(self, grid, irr, dep, mlp: "MlpTarget" = None):
         self.irr = _f64(np.asarray(irr)[..., :3])
@@ -194,6 +204,7 @@ class _Probes:
         p.d_max = float(np.float32(grid.d_max))
         p.irr = self.irr.ctypes.data
         p.dep = self.dep.ctypes.data
+        p.texel = texel_code(grid)
         self.mlp = mlp
         if mlp is not None:
             p.mlp = mlp.params.ctypes.data

@@ -550,20 +550,32 @@ __device__ __forceinline__ V3 oct_decode(float u, float w)
 // Probe textures are stored as bilinear quads: record (cx, cy), cx, cy in
 // [0, N], holds the four gutter-padded texels (cx, cy), (cx+1, cy),
 // (cx, cy+1), (cx+1, cy+1) that a bilinear fetch between them needs, so one
-// fetch is a single 24-byte (irradiance RGB) or 16-byte (depth mean and
-// variance) record of binary16 values: 3 8-byte or 1 16-byte loads instead
-// of 4 scattered texel loads.
+// fetch is a single record instead of 4 scattered texel loads.  Two texel
+// formats (gi_probes.texel):
+//   FP32:     irradiance 12 floats (48 B: RGB of the 4 texels), depth
+//             8 floats (32 B: mean and mean square of the 4 texels);
+//   binary16: irradiance 12 halves (24 B), depth 8 halves (16 B: mean and
+//             variance of the 4 texels; the mean square is rebuilt).
 // Irradiance records are quad-major (record q of every probe, then record
 // q + 1): a query reads the same record q from all 8 probes of its cell, and
 // the x-neighbours' records then share cache lines.  Depth records, whose
 // direction differs per probe, stay probe-major.
 constexpr int kIrrN = 8, kDepN = 16;
-constexpr int kIrrQuads = (kIrrN + 1) * (kIrrN + 1);      // 81 records of 12 binary16 values
-constexpr int kDepQuads = (kDepN + 1) * (kDepN + 1);      // 289 records of 8 binary16 values
-constexpr int kDepRecBytes = 16;                          // 4 texels x binary16 (mean, variance)
+constexpr int kIrrQuads = (kIrrN + 1) * (kIrrN + 1);      // 81 irradiance records per probe
+constexpr int kDepQuads = (kDepN + 1) * (kDepN + 1);      // 289 depth records per probe
 
-// binary16 <-> FP32 (the probe records' storage precision; conversions to
-// binary16 round to nearest even)
+// Record sizes of a texel format (kF16: binary16, else FP32).  A volume of
+// at most kMaxProbes probes keeps both textures under 4 GiB in either
+// format, so kernels address them with 32-bit byte offsets.
+template <bool kF16>
+struct ProbeFmt {
+    static constexpr uint32_t kIrrRec = kF16 ? 24u : 48u;
+    static constexpr uint32_t kDepRec = kF16 ? 16u : 32u;
+    static constexpr uint32_t kDepProbe = kDepQuads * kDepRec;     // 4624 or 9248
+};
+constexpr uint32_t kMaxProbes = 464000u;      // kMaxProbes * ProbeFmt<false>::kDepProbe < 2^32
+
+// binary16 <-> FP32 (conversions to binary16 round to nearest even)
 __device__ __forceinline__ float half_lo(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu)); }
 __device__ __forceinline__ float half_hi(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
 __device__ __forceinline__ float4 half4_to_float4(uint2 q)
@@ -581,6 +593,11 @@ __device__ __forceinline__ float2 dep_texel(uint32_t w)
 {
     const float mu = half_lo(w);
     return make_float2(mu, fmaf(mu, mu, half_hi(w)));
+}
+
+__device__ __forceinline__ float4 as_float4(uint4 v)
+{
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
 }
 
 struct Bilin {
@@ -606,24 +623,33 @@ __device__ __forceinline__ Bilin bilin(V3 dir, int N)
     return b;
 }
 
-// bilinear (mean, mean square) of a probe's depth records (uint4 per quad)
-__device__ __forceinline__ float2 fetch_dep(const uint4 *probe, V3 dir)
+// The four (mean, mean square) texels of a depth record in memory
+template <bool kF16>
+__device__ __forceinline__ void dep_texels(const void *rec, float2 (&t)[4])
 {
-    Bilin b = bilin(dir, kDepN);
-    const uint4 r = probe[b.q];
-    const float2 t0 = dep_texel(r.x), t1 = dep_texel(r.y), t2 = dep_texel(r.z), t3 = dep_texel(r.w);
-    float w00 = (1.0f - b.ax) * (1.0f - b.ay), w10 = b.ax * (1.0f - b.ay);
-    float w01 = (1.0f - b.ax) * b.ay, w11 = b.ax * b.ay;
-    return make_float2(w00 * t0.x + w10 * t1.x + w01 * t2.x + w11 * t3.x,
-                       w00 * t0.y + w10 * t1.y + w01 * t2.y + w11 * t3.y);
+    const uint4 *r = reinterpret_cast<const uint4 *>(rec);
+    if constexpr (kF16) {
+        const uint4 q = r[0];
+        t[0] = dep_texel(q.x); t[1] = dep_texel(q.y); t[2] = dep_texel(q.z); t[3] = dep_texel(q.w);
+    } else {
+        const float4 a = as_float4(r[0]), b = as_float4(r[1]);
+        t[0] = make_float2(a.x, a.y); t[1] = make_float2(a.z, a.w);
+        t[2] = make_float2(b.x, b.y); t[3] = make_float2(b.z, b.w);
+    }
 }
 
-// Byte sizes of the quad records; a volume of at most kMaxProbes probes
-// keeps both textures under 4 GiB, so the query addresses them with
-// 32-bit byte offsets from the (uniform) texture base.
-constexpr uint32_t kIrrRecBytes = 24u;                    // 12 binary16 values
-constexpr uint32_t kDepProbeBytes = kDepQuads * kDepRecBytes;   // 4624
-constexpr uint32_t kMaxProbes = 464000u;                  // kMaxProbes * kDepProbeBytes < 2^32
+// bilinear (mean, mean square) of the depth records of one probe
+template <bool kF16>
+__device__ __forceinline__ float2 fetch_dep(const void *probe, V3 dir)
+{
+    Bilin b = bilin(dir, kDepN);
+    float2 t[4];
+    dep_texels<kF16>(reinterpret_cast<const char *>(probe) + ProbeFmt<kF16>::kDepRec * (uint32_t)b.q, t);
+    float w00 = (1.0f - b.ax) * (1.0f - b.ay), w10 = b.ax * (1.0f - b.ay);
+    float w01 = (1.0f - b.ax) * b.ay, w11 = b.ax * b.ay;
+    return make_float2(w00 * t[0].x + w10 * t[1].x + w01 * t[2].x + w11 * t[3].x,
+                       w00 * t[0].y + w10 * t[1].y + w01 * t[2].y + w11 * t[3].y);
+}
 
 __device__ __forceinline__ const float4 *at_bytes(const float *base, uint32_t off)
 {
@@ -649,6 +675,38 @@ __device__ __forceinline__ uint2 tex_load8(__amdgpu_buffer_rsrc_t r, uint32_t of
     return make_uint2(v[0], v[1]);
 }
 
+// The depth record at byte offset off as four (mean, mean square) texels
+template <bool kF16>
+__device__ __forceinline__ void dep_record(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 (&t)[4])
+{
+    if constexpr (kF16) {
+        const uint4 q = tex_load16(r, off);
+        t[0] = dep_texel(q.x); t[1] = dep_texel(q.y); t[2] = dep_texel(q.z); t[3] = dep_texel(q.w);
+    } else {
+        const float4 a = as_float4(tex_load16(r, off)), b = as_float4(tex_load16(r, off + 16u));
+        t[0] = make_float2(a.x, a.y); t[1] = make_float2(a.z, a.w);
+        t[2] = make_float2(b.x, b.y); t[3] = make_float2(b.z, b.w);
+    }
+}
+
+// The irradiance record at byte offset off as 12 floats (RGB of the four
+// texels in order) in e0, e1, e2
+template <bool kF16>
+__device__ __forceinline__ void irr_record(__amdgpu_buffer_rsrc_t r, uint32_t off, float4 &e0, float4 &e1, float4 &e2)
+{
+    if constexpr (kF16) {
+        const uint4 ia = tex_load16(r, off);
+        const uint2 ib = tex_load8(r, off + 16u);
+        e0 = half4_to_float4(make_uint2(ia.x, ia.y));
+        e1 = half4_to_float4(make_uint2(ia.z, ia.w));
+        e2 = half4_to_float4(ib);
+    } else {
+        e0 = as_float4(tex_load16(r, off));
+        e1 = as_float4(tex_load16(r, off + 16u));
+        e2 = as_float4(tex_load16(r, off + 32u));
+    }
+}
+
 // Per-axis quantities of the query cell's two corner layers: offsets of the
 // layers' probe coordinate from p, the trilinear fraction toward the upper
 // layer, and the probe-index step between the layers (0 on a one-probe axis).
@@ -672,15 +730,16 @@ __device__ __forceinline__ QueryAxis query_axis(float pv, float lo, float sp, in
     return q;
 }
 
-// Q(p, n) = E(p, n)/pi: blend of the 8 probes of p's cell.
-// The per-axis terms are formed once.  The direction toward p is
-// octahedral-encoded unnormalised (the encoding divides by its L1 norm).
-// Probe indices stay below 2^24, so byte offsets are 24-bit products.
-// kUnroll: how many of the four (y, z) corner pairs one loop iteration
-// covers (a code-size / register trade made per kernel).
-template <int kUnroll = 1>
-__device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
+// Q(p, n) = E(p, n)/pi: blend of the 8 probes of p's cell, from textures
+// of one texel format.  The per-axis terms are formed once.  The direction
+// toward p is octahedral-encoded unnormalised (the encoding divides by its
+// L1 norm).  Probe indices stay below 2^24, so byte offsets are 24-bit
+// products.  kUnroll: how many of the four (y, z) corner pairs one loop
+// iteration covers (a code-size / register trade made per kernel).
+template <int kUnroll, bool kF16>
+__device__ __forceinline__ V3 probe_query_fmt(const gi_probes &pr, V3 p, V3 n)
 {
+    using F = ProbeFmt<kF16>;
     const int nx = (int)pr.dims[0], ny = (int)pr.dims[1], nz = (int)pr.dims[2];
     const QueryAxis ax = query_axis(p.x, pr.lo[0], pr.spacing[0], nx, 1u);
     const QueryAxis ay = query_axis(p.y, pr.lo[1], pr.spacing[1], ny, (uint32_t)nx);
@@ -688,9 +747,9 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
     const uint32_t base = ax.base + ay.base + az.base;
     const Bilin bn = bilin(n, kIrrN);
     const uint32_t np = (uint32_t)(nx * ny * nz);
-    const uint32_t irr_q = kIrrRecBytes * (uint32_t)bn.q * np;   // slice of record q
-    const __amdgpu_buffer_rsrc_t dep_r = tex_rsrc(pr.dep, np * kDepProbeBytes);
-    const __amdgpu_buffer_rsrc_t irr_r = tex_rsrc(pr.irr, np * (uint32_t)kIrrQuads * kIrrRecBytes);
+    const uint32_t irr_q = F::kIrrRec * (uint32_t)bn.q * np;   // slice of record q
+    const __amdgpu_buffer_rsrc_t dep_r = tex_rsrc(pr.dep, np * F::kDepProbe);
+    const __amdgpu_buffer_rsrc_t irr_r = tex_rsrc(pr.irr, np * (uint32_t)kIrrQuads * F::kIrrRec);
     const float w00 = (1.0f - bn.ax) * (1.0f - bn.ay), w10 = bn.ax * (1.0f - bn.ay);
     const float w01 = (1.0f - bn.ax) * bn.ay, w11 = bn.ax * bn.ay;
     float sx = 0.0f, sy = 0.0f, sz = 0.0f, wsum = 0.0f;
@@ -713,17 +772,14 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
             // depth moments toward p (a probe sitting exactly at p reads any texel, unused)
             const V3 dv = at_probe ? v3(0.0f, 0.0f, 1.0f) : -tp;
             const Bilin bd = bilin(dv, kDepN);
-            const uint4 dq = tex_load16(dep_r, __umul24(pi, kDepProbeBytes) + (uint32_t)kDepRecBytes * (uint32_t)bd.q);
-            const float2 d0 = dep_texel(dq.x), d1 = dep_texel(dq.y), d2 = dep_texel(dq.z), d3 = dep_texel(dq.w);
-            const uint32_t io = irr_q + __umul24(pi, kIrrRecBytes);
-            const uint4 ia = tex_load16(irr_r, io);
-            const uint2 ib = tex_load8(irr_r, io + 16u);
-            const float4 e0 = half4_to_float4(make_uint2(ia.x, ia.y)), e1 = half4_to_float4(make_uint2(ia.z, ia.w));
-            const float4 e2 = half4_to_float4(ib);
+            float2 d[4];
+            dep_record<kF16>(dep_r, __umul24(pi, F::kDepProbe) + F::kDepRec * (uint32_t)bd.q, d);
+            float4 e0, e1, e2;
+            irr_record<kF16>(irr_r, irr_q + __umul24(pi, F::kIrrRec), e0, e1, e2);
             const float v00 = (1.0f - bd.ax) * (1.0f - bd.ay), v10 = bd.ax * (1.0f - bd.ay);
             const float v01 = (1.0f - bd.ax) * bd.ay, v11 = bd.ax * bd.ay;
-            const float mu = v00 * d0.x + v10 * d1.x + v01 * d2.x + v11 * d3.x;
-            const float mu2 = v00 * d0.y + v10 * d1.y + v01 * d2.y + v11 * d3.y;
+            const float mu = v00 * d[0].x + v10 * d[1].x + v01 * d[2].x + v11 * d[3].x;
+            const float mu2 = v00 * d[0].y + v10 * d[1].y + v01 * d[2].y + v11 * d[3].y;
             const float var = fmaxf(fmaf(-mu, mu, mu2), pr.var_floor);
             const float dd = r - mu;
             const float cheb = var * rcp(fmaf(dd, dd, var));
@@ -740,6 +796,25 @@ __device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
     return v3(iw * sx, iw * sy, iw * sz);
 }
 
+// Texel format a kernel is compiled for: one of the two, or either (read
+// from the volume at run time: a uniform branch, both forms in the code).
+// The hot kernels take it as a template argument, so that only one form
+// competes for their registers.
+enum : int { kTexF32 = 0, kTexF16 = 1, kTexAny = 2 };
+template <bool kF16>
+constexpr int kTexOf = kF16 ? kTexF16 : kTexF32;
+
+// Q(p, n) from the volume's textures
+template <int kUnroll = 1, int kTex = kTexAny>
+__device__ __forceinline__ V3 probe_query(const gi_probes &pr, V3 p, V3 n)
+{
+    if constexpr (kTex == kTexAny)
+        return pr.texel == GI_TEXEL_F16 ? probe_query_fmt<kUnroll, true>(pr, p, n)
+                                        : probe_query_fmt<kUnroll, false>(pr, p, n);
+    else
+        return probe_query_fmt<kUnroll, kTex == kTexF16>(pr, p, n);
+}
+
 // view-path bias: move y toward x by min(d, |x - y|/2)
 __device__ __forceinline__ V3 view_bias(V3 y, V3 x, float d)
 {
@@ -751,13 +826,13 @@ __device__ __forceinline__ V3 view_bias(V3 y, V3 x, float d)
 }
 
 // L_e(y) + rho_y Q(y_b, n_y), y_b biased toward x
-template <int kUnroll = 1>
+template <int kUnroll = 1, int kTex = kTexAny>
 __device__ __forceinline__ V3 radiance_toward(const gi_scene &sc, const gi_probes &pr, uint32_t prim, V3 y, V3 ny, V3 x)
 {
     V3 alb, emit;
     material(sc, prim, alb, emit);
     if (is_zero(alb)) return emit;
-    V3 q = probe_query<kUnroll>(pr, view_bias(y, x, pr.bias_dist), ny);
+    V3 q = probe_query<kUnroll, kTex>(pr, view_bias(y, x, pr.bias_dist), ny);
     return v3(fmaf(alb.x, q.x, emit.x), fmaf(alb.y, q.y, emit.y), fmaf(alb.z, q.z, emit.z));
 }
 
@@ -920,6 +995,7 @@ __device__ __forceinline__ void material_g(const gi_scene &sc, uint32_t prim, V3
 // glossy part of L_DDGI+ (Eq. 6): one lobe sample wi, weighted k_s f_g cos / pdf,
 // times E(pb, wi)/(2 pi) = Q(pb, wi)/2 (the tiles hold E/pi; the query takes
 // wi in place of the normal)
+template <int kTex = kTexAny>
 __device__ __forceinline__ V3 glossy_term(const gi_probes &pr, V3 pb, V3 n, V3 wo, float ks, float a, float u0, float u1)
 {
     V3 wi;
@@ -927,11 +1003,12 @@ __device__ __forceinline__ V3 glossy_term(const gi_probes &pr, V3 pb, V3 n, V3 w
     const float pdf = ggx_pdf(n, wo, wi, a);
     if (!(pdf > 0.0f)) return v3(0.0f, 0.0f, 0.0f);
     const float w = ks * ggx_eval(n, wo, wi, a) * dot(n, wi) * rcp(pdf);
-    return (0.5f * w) * probe_query(pr, pb, wi);
+    return (0.5f * w) * probe_query<1, kTex>(pr, pb, wi);
 }
 
 // L_DDGI+ leaving y toward x in a glossy scene: L_e + rho Q(y_b, n_y) + the
 // glossy part with uniforms (u0, u1)
+template <int kTex = kTexAny>
 __device__ __forceinline__ V3 radiance_toward_g(const gi_scene &sc, const gi_probes &pr, uint32_t prim, V3 y, V3 ny,
                                                 V3 x, float u0, float u1)
 {
@@ -943,13 +1020,13 @@ __device__ __forceinline__ V3 radiance_toward_g(const gi_scene &sc, const gi_pro
     if (!diff && !(ks > 0.0f)) return L;
     const V3 pb = view_bias(y, x, pr.bias_dist);
     if (diff) {
-        const V3 q = probe_query(pr, pb, ny);
+        const V3 q = probe_query<1, kTex>(pr, pb, ny);
         L = v3(fmaf(alb.x, q.x, L.x), fmaf(alb.y, q.y, L.y), fmaf(alb.z, q.z, L.z));
     }
     if (ks > 0.0f) {
         V3 wo = x - y;
         wo = frsq(dot(wo, wo)) * wo;
-        L = L + glossy_term(pr, pb, ny, wo, ks, a, u0, u1);
+        L = L + glossy_term<kTex>(pr, pb, ny, wo, ks, a, u0, u1);
     }
     return L;
 }

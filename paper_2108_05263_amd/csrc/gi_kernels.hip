@@ -269,11 +269,13 @@ __device__ __forceinline__ int gutter_source(int x, int y, int N)
 
 // GLOSSY: a hit on a glossy surface adds the glossy part of L_DDGI+ toward the
 // probe (Eq. 6, one lobe sample, counter (probe, frame, 15, ray))
-template <bool LDS, bool GLOSSY>
+// F16: the volume's texel format is binary16 (else FP32)
+template <bool LDS, bool GLOSSY, bool F16>
 __global__ void __launch_bounds__(kProbeBlock)
     k_probe_update(gi_scene sc, gi_probes in, gi_probes out, gi_probe_params pp, uint64_t seed, uint32_t frame)
 {
     using Acc = typename std::conditional<LDS, GeoLds, GeoGlobal>::type;
+    using F = ProbeFmt<F16>;
     if (LDS) stage_scene(sc);
     const Acc acc(sc);
     __shared__ float s_dir[GI_MAX_PROBE_RAYS][3];
@@ -302,7 +304,7 @@ __global__ void __launch_bounds__(kProbeBlock)
             if (pp.distance_slider > 0.0f && !is_zero(emit)) {
                 // distance heuristic: emission scaled by (t / (t + s d_b))^2, d_b the
                 // probe's backward mean depth clipped to its cell
-                const float2 m = fetch_dep(reinterpret_cast<const uint4 *>(in.dep) + (size_t)pi * kDepQuads, -w);
+                const float2 m = fetch_dep<F16>(reinterpret_cast<const char *>(in.dep) + (size_t)pi * F::kDepProbe, -w);
                 float clip = kInf;
                 if (w.x != 0.0f) clip = fminf(clip, 0.5f * in.spacing[0] / fabsf(w.x));
                 if (w.y != 0.0f) clip = fminf(clip, 0.5f * in.spacing[1] / fabsf(w.y));
@@ -313,12 +315,12 @@ __global__ void __launch_bounds__(kProbeBlock)
             }
             L = emit;
             if (!is_zero(alb)) {
-                V3 q = probe_query(in, view_bias(hp, P, in.bias_dist), n);
+                V3 q = probe_query_fmt<1, F16>(in, view_bias(hp, P, in.bias_dist), n);
                 L = v3(fmaf(alb.x, q.x, emit.x), fmaf(alb.y, q.y, emit.y), fmaf(alb.z, q.z, emit.z));
             }
             if (GLOSSY && ks > 0.0f) {
                 const uint4 rg = philox(seed, pi, frame, kPassGlossyProbe, r);
-                L = L + glossy_term(in, view_bias(hp, P, in.bias_dist), n, -w, ks, ra, u01(rg.x), u01(rg.y));
+                L = L + glossy_term<kTexOf<F16>>(in, view_bias(hp, P, in.bias_dist), n, -w, ks, ra, u01(rg.x), u01(rg.y));
             }
             dist = fminf(h.t, in.d_max);
         } else {
@@ -337,8 +339,8 @@ __global__ void __launch_bounds__(kProbeBlock)
     // old interior texel (i, j) = first texel of quad record (i+1, j+1)
     // irradiance records are quad-major: record q of probe pi is record q * nP + pi
     const size_t nP = (size_t)in.dims[0] * in.dims[1] * in.dims[2];
-    const uint2 *iold = reinterpret_cast<const uint2 *>(in.irr) + 3 * (size_t)pi;
-    const uint4 *dold = reinterpret_cast<const uint4 *>(in.dep) + (size_t)pi * kDepQuads;
+    const char *iold = reinterpret_cast<const char *>(in.irr) + F::kIrrRec * (size_t)pi;
+    const char *dold = reinterpret_cast<const char *>(in.dep) + F::kDepProbe * (size_t)pi;
     const float hy = pp.hysteresis;
     {   // depth texel t (16x16)
         uint32_t t = threadIdx.x;
@@ -356,13 +358,15 @@ __global__ void __launch_bounds__(kProbeBlock)
             }
         }
         // the stored old texel (first of quad (tx+1, ty+1)) as (mean, mean square);
-        // the blend is stored as its mean and variance
-        const float2 old = dep_texel(dold[(ty + 1) * 17 + tx + 1].x);
+        // the blend is kept as the format stores it (binary16: mean and variance)
+        float2 ot[4];
+        dep_texels<F16>(dold + F::kDepRec * (uint32_t)((ty + 1) * 17 + tx + 1), ot);
+        const float2 old = ot[0];
         float n1 = den > 0.0f ? m1 / den : old.x;
         float n2 = den > 0.0f ? m2 / den : old.y;
         const float b1 = hy * old.x + (1.0f - hy) * n1, b2 = hy * old.y + (1.0f - hy) * n2;
         s_dep[t][0] = b1;
-        s_dep[t][1] = fmaf(-b1, b1, b2);
+        s_dep[t][1] = F16 ? fmaf(-b1, b1, b2) : b2;
     }
     if (threadIdx.x < 64) {   // irradiance texel t (8x8)
         uint32_t t = threadIdx.x;
@@ -377,7 +381,9 @@ __global__ void __launch_bounds__(kProbeBlock)
                 den += c;
             }
         }
-        const float4 old = half4_to_float4(iold[3 * nP * ((ty + 1) * 9 + tx + 1)]);
+        const char *orec = iold + F::kIrrRec * nP * (size_t)((ty + 1) * 9 + tx + 1);
+        const float4 old = F16 ? half4_to_float4(*reinterpret_cast<const uint2 *>(orec))
+                               : *reinterpret_cast<const float4 *>(orec);
         float id = 1.0f / den;
         V3 nv = den > 0.0f ? id * num : xyz(old);
         s_irr[t][0] = hy * old.x + (1.0f - hy) * nv.x;
@@ -387,24 +393,39 @@ __global__ void __launch_bounds__(kProbeBlock)
     __syncthreads();
     // write quad records: each corner is an interior texel or the interior
     // texel its gutter position mirrors
-    uint2 *iout = reinterpret_cast<uint2 *>(out.irr) + 3 * (size_t)pi;
-    uint4 *dout = reinterpret_cast<uint4 *>(out.dep) + (size_t)pi * kDepQuads;
+    char *iout = reinterpret_cast<char *>(out.irr) + F::kIrrRec * (size_t)pi;
+    char *dout = reinterpret_cast<char *>(out.dep) + F::kDepProbe * (size_t)pi;
     for (uint32_t q = threadIdx.x; q < (uint32_t)kDepQuads; q += kProbeBlock) {
         int cx = (int)(q % 17u), cy = (int)(q / 17u);
         int s0 = gutter_source(cx, cy, kDepN), s1 = gutter_source(cx + 1, cy, kDepN);
         int s2 = gutter_source(cx, cy + 1, kDepN), s3 = gutter_source(cx + 1, cy + 1, kDepN);
-        dout[q] = make_uint4(pack_half2(s_dep[s0][0], s_dep[s0][1]), pack_half2(s_dep[s1][0], s_dep[s1][1]),
-                             pack_half2(s_dep[s2][0], s_dep[s2][1]), pack_half2(s_dep[s3][0], s_dep[s3][1]));
+        if constexpr (F16) {
+            *reinterpret_cast<uint4 *>(dout + F::kDepRec * q) =
+                make_uint4(pack_half2(s_dep[s0][0], s_dep[s0][1]), pack_half2(s_dep[s1][0], s_dep[s1][1]),
+                           pack_half2(s_dep[s2][0], s_dep[s2][1]), pack_half2(s_dep[s3][0], s_dep[s3][1]));
+        } else {
+            float4 *rec = reinterpret_cast<float4 *>(dout + F::kDepRec * q);
+            rec[0] = make_float4(s_dep[s0][0], s_dep[s0][1], s_dep[s1][0], s_dep[s1][1]);
+            rec[1] = make_float4(s_dep[s2][0], s_dep[s2][1], s_dep[s3][0], s_dep[s3][1]);
+        }
     }
     for (uint32_t q = threadIdx.x; q < (uint32_t)kIrrQuads; q += kProbeBlock) {
         int cx = (int)(q % 9u), cy = (int)(q / 9u);
         int s0 = gutter_source(cx, cy, kIrrN), s1 = gutter_source(cx + 1, cy, kIrrN);
         int s2 = gutter_source(cx, cy + 1, kIrrN), s3 = gutter_source(cx + 1, cy + 1, kIrrN);
-        // binary16 (nearest even), in the order of the FP32 corners
-        uint2 *rec = iout + 3 * nP * q;
-        rec[0] = make_uint2(pack_half2(s_irr[s0][0], s_irr[s0][1]), pack_half2(s_irr[s0][2], s_irr[s1][0]));
-        rec[1] = make_uint2(pack_half2(s_irr[s1][1], s_irr[s1][2]), pack_half2(s_irr[s2][0], s_irr[s2][1]));
-        rec[2] = make_uint2(pack_half2(s_irr[s2][2], s_irr[s3][0]), pack_half2(s_irr[s3][1], s_irr[s3][2]));
+        char *rb = iout + F::kIrrRec * nP * q;
+        if constexpr (F16) {
+            // binary16 (nearest even), in the order of the FP32 corners
+            uint2 *rec = reinterpret_cast<uint2 *>(rb);
+            rec[0] = make_uint2(pack_half2(s_irr[s0][0], s_irr[s0][1]), pack_half2(s_irr[s0][2], s_irr[s1][0]));
+            rec[1] = make_uint2(pack_half2(s_irr[s1][1], s_irr[s1][2]), pack_half2(s_irr[s2][0], s_irr[s2][1]));
+            rec[2] = make_uint2(pack_half2(s_irr[s2][2], s_irr[s3][0]), pack_half2(s_irr[s3][1], s_irr[s3][2]));
+        } else {
+            float4 *rec = reinterpret_cast<float4 *>(rb);
+            rec[0] = make_float4(s_irr[s0][0], s_irr[s0][1], s_irr[s0][2], s_irr[s1][0]);
+            rec[1] = make_float4(s_irr[s1][1], s_irr[s1][2], s_irr[s2][0], s_irr[s2][1]);
+            rec[2] = make_float4(s_irr[s2][2], s_irr[s3][0], s_irr[s3][1], s_irr[s3][2]);
+        }
     }
 }
 
@@ -494,7 +515,7 @@ __global__ void __launch_bounds__(kBlock)
 // fourth uniform), L_DDGI+ at the candidates with its glossy part (one lobe
 // sample, counter (pixel, frame, 14, i)), weights p_hat over the mixture's
 // density in area measure, residual f L (G - G_max) / p_A.
-template <bool LDS, bool WS, bool LIGHT, bool GLOSSY>
+template <bool LDS, bool WS, bool LIGHT, bool GLOSSY, int TEX>
 __global__ void __launch_bounds__(kBlock, 4)
     k_initial(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_params pp, gi_reservoirs out, float4 *resid,
               uint64_t seed, uint32_t frame, CandWs ws, gi_mlp mlp)
@@ -583,7 +604,7 @@ __global__ void __launch_bounds__(kBlock, 4)
             if (cx > 0.0f && cy > 0.0f) {
                 if constexpr (GLOSSY) {
                     const uint4 rg = philox(seed, p, frame, kPassGlossyCand, i);
-                    L = radiance_toward_g(sc, pr, prim, y, ny, g.pos, u01(rg.x), u01(rg.y));
+                    L = radiance_toward_g<TEX>(sc, pr, prim, y, ny, g.pos, u01(rg.x), u01(rg.y));
                     const V3 f = bsdf(g.alb, g.ks, g.rough, g.n, g.wo, wv) * L;
                     const float G = cx * cy * rcp(d2);
                     const float pA = mix_pdf(g.alb, g.ks, g.rough, g.n, g.wo, wv) * cy * rcp(d2);
@@ -596,7 +617,7 @@ __global__ void __launch_bounds__(kBlock, 4)
                 } else {
                     // (the query unrolled over two corner pairs is the faster form here)
                     L = (use_cache && i < pp.M) ? radiance_cached(sc, prim, ws.q[i * npx + p])
-                                                : radiance_toward<2>(sc, pr, prim, y, ny, g.pos);
+                                                : radiance_toward<2, TEX>(sc, pr, prim, y, ny, g.pos);
                     float G = cx * cy * rcp(d2);
                     float fl = lum(rho_pi * L);
                     float iG = rcp(G);
@@ -866,7 +887,7 @@ __global__ void __launch_bounds__(kBlock, GLOSSY ? 4 : GI_SPATIAL_WAVES)
 // the walk continues at the hit, adding sqrt(|z - v|^2 / (pdf cos_z)) to
 // foot; otherwise the probes estimate the glossy integral (Q(v_b, wi)/2).
 // The loop form carries the product of the weights so far (grey).
-template <class G>
+template <int TEX, class G>
 __device__ V3 shade_glossy(const gi_scene &sc, const G &acc, const gi_probes &pr, const gi_params &pp, uint64_t seed,
                            uint32_t pixel, uint32_t frame, uint32_t prim, V3 v, V3 nv, V3 prev, float foot, float a0c)
 {
@@ -878,7 +899,7 @@ __device__ V3 shade_glossy(const gi_scene &sc, const G &acc, const gi_probes &pr
         material_g(sc, prim, alb, emit, ks, a);
         L = L + thr * emit;
         const V3 pb = view_bias(v, prev, pr.bias_dist);
-        if (!is_zero(alb)) L = L + thr * (alb * probe_query(pr, pb, nv));
+        if (!is_zero(alb)) L = L + thr * (alb * probe_query<1, TEX>(pr, pb, nv));
         if (!(ks > 0.0f)) break;
         V3 wo = prev - v;
         wo = frsq(dot(wo, wo)) * wo;
@@ -889,7 +910,7 @@ __device__ V3 shade_glossy(const gi_scene &sc, const G &acc, const gi_probes &pr
         if (!(pdf > 0.0f)) break;
         const float wgt = ks * ggx_eval(nv, wo, wi, a) * dot(nv, wi) * rcp(pdf);
         if (foot * foot > a0c || depth >= pp.glossy_depth) {
-            L = L + (thr * 0.5f * wgt) * probe_query(pr, pb, wi);
+            L = L + (thr * 0.5f * wgt) * probe_query<1, TEX>(pr, pb, wi);
             break;
         }
         const V3 o = madd(v, sc.eps, nv);
@@ -917,7 +938,7 @@ __device__ V3 shade_glossy(const gi_scene &sc, const G &acc, const gi_probes &pr
 // GLOSSY: f(x) replaces rho_x/pi and the fresh radiance follows the specular
 // recursion, started with the footprint of the segment x -> y (density of
 // the BSDF mixture at x) and a_0 c = c |x_0 - x|^2 / (4 pi cos) from the camera.
-template <bool LDS, bool WS, bool GLOSSY>
+template <bool LDS, bool WS, bool GLOSSY, int TEX>
 __global__ void __launch_bounds__(kBlock)
     k_shade(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_reservoirs res, const float4 *resid, gi_params pp,
             float4 *img, const float4 *q, gi_mlp mlp, uint64_t seed, uint32_t frame)
@@ -960,10 +981,10 @@ __global__ void __launch_bounds__(kBlock)
                             const float a0c = c1 > 0.0f ? pp.foot_c * dot(vc, vc) * rcp(4.0f * kPi * c1) : kInf;
                             const float p1 = mix_pdf(g.alb, g.ks, g.rough, g.n, g.wo, w);
                             const float foot = p1 > 0.0f ? fsqrt(d2 * rcp(p1 * cy)) : kInf;
-                            L = shade_glossy(sc, acc, pr, pp, seed, p, frame, r.prim, r.y, r.n, g.pos, foot, a0c);
+                            L = shade_glossy<TEX>(sc, acc, pr, pp, seed, p, frame, r.prim, r.y, r.n, g.pos, foot, a0c);
                         } else {
                             L = (WS && mlp_selected(mlp)) ? radiance_cached(sc, r.prim, q[p])
-                                                           : radiance_toward(sc, pr, r.prim, r.y, r.n, g.pos);
+                                                           : radiance_toward<1, TEX>(sc, pr, r.prim, r.y, r.n, g.pos);
                         }
                         ok = true;
                     }
@@ -1214,6 +1235,7 @@ gi_status check_probes(const gi_probes *p)
     if ((uint64_t)p->dims[0] * p->dims[1] * p->dims[2] > kMaxProbes) return GI_ERR_SHAPE;
     for (int a = 0; a < 3; ++a)
         if (!(p->spacing[a] > 0.0f)) return GI_ERR_PARAM;
+    if (p->texel != GI_TEXEL_F32 && p->texel != GI_TEXEL_F16) return GI_ERR_PARAM;
     return GI_OK;
 }
 
@@ -1249,20 +1271,31 @@ uint32_t scene_lds(const gi_scene *sc, uint32_t static_lds = 0)
         if (lds) kernel<true><<<(grid), (block), (lds), (stream)>>>(__VA_ARGS__);             \
         else kernel<false><<<(grid), (block), 0, (stream)>>>(__VA_ARGS__);                   \
     } while (0)
-// k_initial with the scene staging (lds bytes, 0: none), emitter candidates
-// and the glossy BSDF chosen at run time (the learned cache, WS, serves
-// Lambertian scenes only)
-template <bool WS, bool LIGHT, class... A>
-void launch_initial_l(bool glossy, uint32_t lds, dim3 grid, hipStream_t st, A... a)
+// k_initial with the scene staging (lds bytes, 0: none), emitter candidates,
+// the glossy BSDF and the probes' texel format chosen at run time (the
+// learned cache, WS, serves Lambertian scenes only and reads the texel format
+// at run time: its probe queries are the emitter candidates' alone)
+template <bool WS, bool LIGHT, int TEX, class... A>
+void launch_initial_t(bool glossy, uint32_t lds, dim3 grid, hipStream_t st, A... a)
 {
     // past the staged scene: every thread's selected-candidate slot
     const uint32_t extra = kBlock * kSelBytes;
     if (!WS && glossy) {
-        if (lds) k_initial<true, WS, LIGHT, !WS><<<grid, kBlock, lds + extra, st>>>(a...);
-        else k_initial<false, WS, LIGHT, !WS><<<grid, kBlock, extra, st>>>(a...);
+        if (lds) k_initial<true, WS, LIGHT, !WS, TEX><<<grid, kBlock, lds + extra, st>>>(a...);
+        else k_initial<false, WS, LIGHT, !WS, TEX><<<grid, kBlock, extra, st>>>(a...);
     } else {
-        if (lds) k_initial<true, WS, LIGHT, false><<<grid, kBlock, lds + extra, st>>>(a...);
-        else k_initial<false, WS, LIGHT, false><<<grid, kBlock, extra, st>>>(a...);
+        if (lds) k_initial<true, WS, LIGHT, false, TEX><<<grid, kBlock, lds + extra, st>>>(a...);
+        else k_initial<false, WS, LIGHT, false, TEX><<<grid, kBlock, extra, st>>>(a...);
+    }
+}
+template <bool WS, bool LIGHT, class... A>
+void launch_initial_l(bool glossy, bool f16, uint32_t lds, dim3 grid, hipStream_t st, A... a)
+{
+    if constexpr (WS) {
+        launch_initial_t<WS, LIGHT, kTexAny>(glossy, lds, grid, st, a...);
+    } else {
+        if (f16) launch_initial_t<WS, LIGHT, kTexF16>(glossy, lds, grid, st, a...);
+        else launch_initial_t<WS, LIGHT, kTexF32>(glossy, lds, grid, st, a...);
     }
 }
 
@@ -1275,10 +1308,10 @@ uint32_t initial_scene_lds(const gi_scene *sc)
 }
 
 template <bool WS, class... A>
-void launch_initial(bool light, bool glossy, uint32_t lds, dim3 grid, hipStream_t st, A... a)
+void launch_initial(bool light, bool glossy, bool f16, uint32_t lds, dim3 grid, hipStream_t st, A... a)
 {
-    if (light) launch_initial_l<WS, true>(glossy, lds, grid, st, a...);
-    else launch_initial_l<WS, false>(glossy, lds, grid, st, a...);
+    if (light) launch_initial_l<WS, true>(glossy, f16, lds, grid, st, a...);
+    else launch_initial_l<WS, false>(glossy, f16, lds, grid, st, a...);
 }
 
 bool glossy_scene(const gi_scene *sc) { return (sc->options & GI_OPT_GLOSSY) != 0u; }
@@ -1358,6 +1391,7 @@ gi_status gi_probe_update(const gi_scene *scene, const gi_probes *in, gi_probes 
     if ((s = check_probes(out)) != GI_OK) return s;
     for (int a = 0; a < 3; ++a)
         if (in->dims[a] != out->dims[a]) return GI_ERR_SHAPE;
+    if (in->texel != out->texel) return GI_ERR_PARAM;
     const void *ii = in->irr, *id = in->dep, *oi = out->irr, *od = out->dep;
     if (ii == oi || id == od || ii == od || id == oi) return GI_ERR_ALIAS;
     if (pp->rays < 1 || pp->rays > GI_MAX_PROBE_RAYS) return GI_ERR_PARAM;
@@ -1365,8 +1399,17 @@ gi_status gi_probe_update(const gi_scene *scene, const gi_probes *in, gi_probes 
     if (!(pp->distance_slider >= 0.0f)) return GI_ERR_PARAM;
     uint32_t P = in->dims[0] * in->dims[1] * in->dims[2];
     uint32_t lds = scene_lds(scene, (uint32_t)sizeof(float) * (7u * GI_MAX_PROBE_RAYS + 64u * 3u + 256u * 2u));
-    GI_LAUNCH_LDS_G(k_probe_update, glossy_scene(scene), P, kProbeBlock, lds, S(stream), *scene, *in, *out, *pp,
-                    seed, frame);
+    const bool glossy = glossy_scene(scene), f16 = in->texel == GI_TEXEL_F16;
+    const dim3 grid(P);
+#define GI_PU(L, G, H) k_probe_update<L, G, H><<<grid, kProbeBlock, (L) ? lds : 0u, S(stream)>>>(*scene, *in, *out, *pp, seed, frame)
+    if (lds) {
+        if (glossy) { if (f16) GI_PU(true, true, true); else GI_PU(true, true, false); }
+        else { if (f16) GI_PU(true, false, true); else GI_PU(true, false, false); }
+    } else {
+        if (glossy) { if (f16) GI_PU(false, true, true); else GI_PU(false, true, false); }
+        else { if (f16) GI_PU(false, false, true); else GI_PU(false, false, false); }
+    }
+#undef GI_PU
     return launched();
 }
 
@@ -1394,7 +1437,7 @@ gi_status gi_resample_initial(const gi_scene *scene, const gi_gbuffer *gb, const
     if ((s = check_res(out, gb->width, gb->height)) != GI_OK) return s;
     if ((uint64_t)gb->width * gb->height > (1u << 23)) return GI_ERR_SHAPE;   // 23-bit tag origin
     if (gb->width == 0 || gb->height == 0) return GI_OK;
-    launch_initial<false>(params->M_light > 0, glossy_scene(scene), initial_scene_lds(scene),
+    launch_initial<false>(params->M_light > 0, glossy_scene(scene), probes->texel == GI_TEXEL_F16, initial_scene_lds(scene),
                           tile_grid(gb->width, gb->height), S(stream),
                           *scene, *gb, *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame,
                           CandWs{}, gi_mlp{});
@@ -1474,17 +1517,18 @@ gi_status gi_shade(const gi_scene *scene, const gi_gbuffer *gb, const gi_probes 
     const dim3 grid = tile_grid(W, H);
     const float4 *rs = reinterpret_cast<const float4 *>(resid);
     float4 *img = reinterpret_cast<float4 *>(out_rgba);
+    const bool f16 = probes->texel == GI_TEXEL_F16;
+#define GI_SH(L, G, T)                                                                                   \
+    k_shade<L, false, G, T><<<grid, kBlock, (L) ? lds : 0u, S(stream)>>>(*scene, *gb, *probes, *res, rs, *params, \
+                                                                          img, nullptr, gi_mlp{}, seed, frame)
     if (glossy) {
-        if (lds) k_shade<true, false, true><<<grid, kBlock, lds, S(stream)>>>(*scene, *gb, *probes, *res, rs, *params,
-                                                                           img, nullptr, gi_mlp{}, seed, frame);
-        else k_shade<false, false, true><<<grid, kBlock, 0, S(stream)>>>(*scene, *gb, *probes, *res, rs, *params, img,
-                                                                      nullptr, gi_mlp{}, seed, frame);
+        if (lds) { if (f16) GI_SH(true, true, kTexF16); else GI_SH(true, true, kTexF32); }
+        else { if (f16) GI_SH(false, true, kTexF16); else GI_SH(false, true, kTexF32); }
     } else {
-        if (lds) k_shade<true, false, false><<<grid, kBlock, lds, S(stream)>>>(*scene, *gb, *probes, *res, rs, *params,
-                                                                            img, nullptr, gi_mlp{}, seed, frame);
-        else k_shade<false, false, false><<<grid, kBlock, 0, S(stream)>>>(*scene, *gb, *probes, *res, rs, *params, img,
-                                                                       nullptr, gi_mlp{}, seed, frame);
+        if (lds) { if (f16) GI_SH(true, false, kTexF16); else GI_SH(true, false, kTexF32); }
+        else { if (f16) GI_SH(false, false, kTexF16); else GI_SH(false, false, kTexF32); }
     }
+#undef GI_SH
     return launched();
 }
 
@@ -1548,13 +1592,13 @@ gi_status gi_resample_initial_mlp(const gi_scene *scene, const gi_gbuffer *gb, c
                       frame, *mlp);
         if ((s = launched()) != GI_OK) return s;
         if ((s = mlp_infer_launch(*mlp, (uint32_t)ncand, ws.pos, ws.nrm, ws.q, true, S(stream))) != GI_OK) return s;
-        launch_initial<true>(params->M_light > 0, false, 0u, tile_grid(W, H), S(stream), *scene, *gb, *probes,
+        launch_initial<true>(params->M_light > 0, false, probes->texel == GI_TEXEL_F16, 0u, tile_grid(W, H), S(stream), *scene, *gb, *probes,
                              *params, *out, reinterpret_cast<float4 *>(resid), seed, frame, ws, *mlp);
         if ((s = launched()) != GI_OK) return s;
     }
     if (mlp->mode != GI_MLP_ALWAYS) {
         const uint32_t gate = mlp->mode == GI_MLP_AUTO ? kRunIfProbe : kRunAlways;
-        launch_initial<false>(params->M_light > 0, false, initial_scene_lds(scene), tile_grid(W, H), S(stream),
+        launch_initial<false>(params->M_light > 0, false, probes->texel == GI_TEXEL_F16, initial_scene_lds(scene), tile_grid(W, H), S(stream),
                               *scene, *gb, *probes, *params, *out, reinterpret_cast<float4 *>(resid), seed, frame,
                               CandWs{nullptr, nullptr, nullptr, gate}, *mlp);
     }
@@ -1587,9 +1631,9 @@ gi_status gi_shade_mlp(const gi_scene *scene, const gi_gbuffer *gb, const gi_pro
         const uint32_t lds = scene_lds(scene);
         const float4 *rs = reinterpret_cast<const float4 *>(resid);
         float4 *img = reinterpret_cast<float4 *>(out_rgba);
-        if (lds) k_shade<true, true, false><<<tile_grid(W, H), kBlock, lds, S(stream)>>>(*scene, *gb, *probes, *res, rs,
+        if (lds) k_shade<true, true, false, kTexAny><<<tile_grid(W, H), kBlock, lds, S(stream)>>>(*scene, *gb, *probes, *res, rs,
                                                                                       *params, img, q, *mlp, 0ull, 0u);
-        else k_shade<false, true, false><<<tile_grid(W, H), kBlock, 0, S(stream)>>>(*scene, *gb, *probes, *res, rs,
+        else k_shade<false, true, false, kTexAny><<<tile_grid(W, H), kBlock, 0, S(stream)>>>(*scene, *gb, *probes, *res, rs,
                                                                                  *params, img, q, *mlp, 0ull, 0u);
     }
     return launched();

@@ -74,10 +74,13 @@ class GiGBuffer(C.Structure):
 GB_FORMAT = {"f32": 0, "f16": 1}
 
 
+TEXEL_FORMAT = {"f32": 0, "f16": 1}
+
+
 class GiProbes(C.Structure):
     _fields_ = [("dims", U3), ("irr_res", C.c_uint32), ("dep_res", C.c_uint32), ("lo", F3),
                 ("spacing", F3), ("bias_dist", C.c_float), ("var_floor", C.c_float),
-                ("d_max", C.c_float), ("irr", C.c_void_p), ("dep", C.c_void_p)]
+                ("d_max", C.c_float), ("texel", C.c_uint32), ("irr", C.c_void_p), ("dep", C.c_void_p)]
 
 
 class GiReservoirs(C.Structure):
@@ -411,15 +414,21 @@ def quads_to_tiles(quads, N, C_):
 class Probes:
     """Probe textures in the library's quad-record layout (see gi.h):
     irradiance records quad-major (record, probe, 12), depth records
-    probe-major (probe, record, 8) as (mean, variance) per texel, all
-    binary16."""
+    probe-major (probe, record, 8), in the grid's texel format: FP32 with
+    depth texels as (mean, mean square), or binary16 with depth texels as
+    (mean, variance)."""
 
     def __init__(self, grid: sg.ProbeGrid, device="cuda"):
         self.grid = grid
+        self.texel = getattr(grid, "texel", "f32")
+        if self.texel not in TEXEL_FORMAT:
+            raise GiError(f"unknown probe texel format {self.texel!r}")
+        dt = torch.float16 if self.texel == "f16" else torch.float32
         P = grid.count
-        self.irr = torch.zeros((grid.irr_res + 1) ** 2, P, 12, dtype=torch.float16, device=device)
-        self.dep = torch.zeros(P, (grid.dep_res + 1) ** 2, 8, dtype=torch.float16, device=device)
+        self.irr = torch.zeros((grid.irr_res + 1) ** 2, P, 12, dtype=dt, device=device)
+        self.dep = torch.zeros(P, (grid.dep_res + 1) ** 2, 8, dtype=dt, device=device)
         p = GiProbes()
+        p.texel = TEXEL_FORMAT[self.texel]
         p.dims = (C.c_uint32 * 3)(*grid.dims)
         p.irr_res, p.dep_res = grid.irr_res, grid.dep_res
         p.lo, p.spacing = _f3(grid.lo), _f3(grid.spacing)
@@ -434,12 +443,16 @@ class Probes:
     def load(self, irr, dep):
         """Fill from gutter-padded tiles: irr (P, (N+2)^2, >=3), dep (P, (Nd+2)^2, 2)."""
         g = self.grid
-        # binary16 straight from the caller's values (one rounding, nearest even)
-        qi = tiles_to_quads(np.asarray(irr, np.float64)[..., :3], g.irr_res).astype(np.float16)
-        # depth texels stored as binary16 (mean, variance) from (mean, mean square)
         d = np.asarray(dep, np.float64)[..., :2]
-        mv = np.stack([d[..., 0], d[..., 1] - d[..., 0] * d[..., 0]], axis=-1)
-        qd = tiles_to_quads(mv, g.dep_res).astype(np.float16)
+        if self.texel == "f16":
+            # binary16 straight from the caller's values (one rounding, nearest even)
+            qi = tiles_to_quads(np.asarray(irr, np.float64)[..., :3], g.irr_res).astype(np.float16)
+            # depth texels stored as binary16 (mean, variance) from (mean, mean square)
+            mv = np.stack([d[..., 0], d[..., 1] - d[..., 0] * d[..., 0]], axis=-1)
+            qd = tiles_to_quads(mv, g.dep_res).astype(np.float16)
+        else:
+            qi = tiles_to_quads(np.asarray(irr, np.float64)[..., :3], g.irr_res).astype(np.float32)
+            qd = tiles_to_quads(d, g.dep_res).astype(np.float32)
         self.irr.copy_(torch.from_numpy(np.ascontiguousarray(qi.swapaxes(0, 1))))
         self.dep.copy_(torch.from_numpy(np.ascontiguousarray(qd)))
 
@@ -450,11 +463,12 @@ class Probes:
                 quads_to_tiles(self.dep_quads(), g.dep_res, 2))
 
     def dep_quads(self):
-        """Depth records (P, (Nd+1)^2, 8) as (mean, mean square) per texel, the
-        mean square rebuilt from the stored binary16 mean and variance."""
+        """Depth records (P, (Nd+1)^2, 8) as (mean, mean square) per texel (a
+        binary16 volume's mean square rebuilt from its stored mean and variance)."""
         q = self.dep.cpu().numpy().astype(np.float64).reshape(self.grid.count, -1, 4, 2)
-        out = np.stack([q[..., 0], q[..., 1] + q[..., 0] * q[..., 0]], axis=-1)
-        return out.reshape(self.grid.count, -1, 8)
+        if self.texel == "f16":
+            q = np.stack([q[..., 0], q[..., 1] + q[..., 0] * q[..., 0]], axis=-1)
+        return q.reshape(self.grid.count, -1, 8)
 
     def irr_quads(self):
         """Irradiance records probe-major, (P, (N+1)^2, 12), as tiles_to_quads makes them."""

@@ -96,6 +96,7 @@ class ProbeGrid:
     bias_dist: float = 0.0            # view-path bias distance d (0.3 x min spacing)
     var_floor: float = 0.0            # Chebyshev variance floor (1e-4 x min spacing^2)
     d_max: float = 0.0                # depth clamp for probe rays (1.5 x cell diagonal)
+    texel: str = "f32"                # texel storage: "f32" or "f16" (IEEE binary16)
 
     @property
     def count(self) -> int:
@@ -162,6 +163,7 @@ class Config:
     glossy_frac: float = 0.0          # fraction of non-emitting primitives with a GGX specular layer
     spec_range: tuple = (0.3, 0.7)    # its weight ks, uniform (diffuse albedo scaled by 1 - ks)
     rough_range: tuple = (0.02, 0.5)  # its roughness alpha, log-uniform
+    probe_texel: str = "f32"          # probe texel storage: "f32" (the workloads) or "f16"
 
 
 # --------------------------------------------------------------------------
@@ -311,17 +313,17 @@ def make_scene(cfg: Config, max_frames: int = 32) -> Scene:
 
 def make_probe_grid(cfg: Config) -> ProbeGrid:
     s = float(cfg.probe_spacing)
-    return probe_grid(cfg.probe_dims, cfg.room_lo, s)
+    return probe_grid(cfg.probe_dims, cfg.room_lo, s, texel=cfg.probe_texel)
 
 
-def probe_grid(dims, lo, spacing, irr_res=8, dep_res=16) -> ProbeGrid:
+def probe_grid(dims, lo, spacing, irr_res=8, dep_res=16, texel="f32") -> ProbeGrid:
     s = float(spacing)
     return ProbeGrid(dims=tuple(int(v) for v in dims),
                      lo=np.asarray(lo, np.float32).reshape(3),
                      spacing=np.full(3, s, np.float32), irr_res=irr_res, dep_res=dep_res,
                      bias_dist=float(np.float32(0.3 * s)),
                      var_floor=float(np.float32(1e-4 * s * s)),
-                     d_max=float(np.float32(1.5 * s * math.sqrt(3.0))))
+                     d_max=float(np.float32(1.5 * s * math.sqrt(3.0))), texel=texel)
 
 
 def empty_probe_textures(grid: ProbeGrid):

@@ -102,6 +102,12 @@ def test_validation_rejects_before_launch(gi):
     assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r),
                                    resid, 1, 0, None) == 2
     pr.irr_res = 8
+    # an unknown texel format
+    pr.texel = 2
+    assert lib.gi_resample_initial(C.byref(s), C.byref(g), C.byref(pr), C.byref(pp), C.byref(r),
+                                   resid, 1, 0, None) == 3
+    assert lib.gi_probe_query(C.byref(pr), 0, resid, resid, resid, None) == 3
+    pr.texel = 0
     # aliasing output and input reservoirs
     assert lib.gi_resample_spatial(C.byref(s), C.byref(g), C.byref(r), C.byref(pp), 0, C.byref(r),
                                    1, 0, None) == 4
@@ -116,6 +122,10 @@ def test_validation_rejects_before_launch(gi):
     pu.distance_slider = 0.0
     pu.rays = 64
     assert lib.gi_probe_update(C.byref(s), C.byref(pr), C.byref(pr), C.byref(pu), 1, 0, None) == 4
+    # input and output volumes of different texel formats
+    pr2.texel = 1
+    assert lib.gi_probe_update(C.byref(s), C.byref(pr), C.byref(pr2), C.byref(pu), 1, 0, None) == 3
+    pr2.texel = 0
 
 
 def test_accel_builder_lists_overlapping_cells(gi):
@@ -215,6 +225,10 @@ def test_probe_volume_limit(gi):
     assert lib.gi_probe_query(C.byref(pr), 0, buf, buf, buf, None) == 0
     pr.dims = (C.c_uint32 * 3)(3, 154667, 1)          # 464,001 probes
     assert lib.gi_probe_query(C.byref(pr), 0, buf, buf, buf, None) == 2
+    pr.texel = 1                                      # the same limit for binary16 volumes
+    assert lib.gi_probe_query(C.byref(pr), 0, buf, buf, buf, None) == 2
+    pr.dims = (C.c_uint32 * 3)(80, 58, 100)
+    assert lib.gi_probe_query(C.byref(pr), 0, buf, buf, buf, None) == 0
 
 
 def test_image_size_limit_of_the_initial_pass(gi):

@@ -139,8 +139,13 @@ def test_gbuffer(gi, W, H):
     assert np.max(rel_err(g[same, 12], r[same, 12])) < 1e-5
 
 
-def test_probe_query(gi, tiny):
+TEXELS = pytest.mark.parametrize("texel", ["f32", "f16"])
+
+
+@TEXELS
+def test_probe_query(gi, tiny, texel):
     cfg, sc, grid, irr, dep = tiny
+    grid = dataclasses.replace(grid, texel=texel)
     pr = gi.Probes(grid)
     pr.load(irr, dep)
     rng = np.random.default_rng(2)
@@ -150,27 +155,33 @@ def test_probe_query(gi, tiny):
     q = gi.probe_query(pr, torch.from_numpy(p).cuda(), torch.from_numpy(n).cuda()).cpu().numpy()
     ref = o.probe_query(grid, irr.astype(np.float32), dep.astype(np.float32), p, n)
     e = rel_err(q, ref)
-    log(f"probe query: mean rel err {e.mean():.2e} max {e.max():.2e}")
+    log(f"probe query ({texel}): mean rel err {e.mean():.2e} max {e.max():.2e}")
     assert e.mean() < 1e-5 and e.max() < 1e-3
 
 
-def test_probe_layout_odd_volume(gi, tiny):
+@TEXELS
+def test_probe_layout_odd_volume(gi, tiny, texel):
     """A 3x5x2 probe volume (no power-of-two extent, P = 30): the query on
     points inside and around it, and the probe update's read-back, agree with
     the oracle, which indexes probe-major tiles, through the library's
     quad-major irradiance records."""
     cfg, sc, _, _, _ = tiny
-    grid = sg.probe_grid((3, 5, 2), (0.5, 0.25, 1.0), 1.5)   # inside the 8-unit room
+    grid = sg.probe_grid((3, 5, 2), (0.5, 0.25, 1.0), 1.5, texel=texel)   # inside the 8-unit room
     irr, dep = sg.random_probe_textures(grid, 5)
     pr = gi.Probes(grid)
     pr.load(irr, dep)
     ti, td = pr.tiles()
-    # texels come back at binary16: irradiance, and depth as (mean, variance)
-    assert np.array_equal(ti, irr[..., :3].astype(np.float16).astype(np.float32))
-    d = dep[..., :2].astype(np.float64)
-    mu = d[..., 0].astype(np.float16).astype(np.float64)
-    var = (d[..., 1] - d[..., 0] * d[..., 0]).astype(np.float16).astype(np.float64)
-    assert np.array_equal(td[..., 0], mu) and np.array_equal(td[..., 1], var + mu * mu)
+    if texel == "f16":
+        # texels come back at binary16: irradiance, and depth as (mean, variance)
+        assert np.array_equal(ti, irr[..., :3].astype(np.float16).astype(np.float32))
+        d = dep[..., :2].astype(np.float64)
+        mu = d[..., 0].astype(np.float16).astype(np.float64)
+        var = (d[..., 1] - d[..., 0] * d[..., 0]).astype(np.float16).astype(np.float64)
+        assert np.array_equal(td[..., 0], mu) and np.array_equal(td[..., 1], var + mu * mu)
+    else:
+        # FP32 texels come back as loaded
+        assert np.array_equal(ti, irr[..., :3].astype(np.float32))
+        assert np.array_equal(td, dep[..., :2].astype(np.float32).astype(np.float64))
     rng = np.random.default_rng(4)
     p = rng.uniform(-0.5, 8.0, (4000, 3)).astype(np.float32)
     n = rng.normal(size=(4000, 3))
@@ -178,7 +189,7 @@ def test_probe_layout_odd_volume(gi, tiny):
     q = gi.probe_query(pr, torch.from_numpy(p).cuda(), torch.from_numpy(n).cuda()).cpu().numpy()
     ref = o.probe_query(grid, irr.astype(np.float32), dep.astype(np.float32), p, n)
     e = rel_err(q, ref)
-    log(f"odd volume query: mean rel err {e.mean():.2e} max {e.max():.2e}")
+    log(f"odd volume query ({texel}): mean rel err {e.mean():.2e} max {e.max():.2e}")
     assert e.mean() < 1e-5 and e.max() < 1e-3
     ds = gi.DeviceScene(sc, cfg.grid_res)
     pout = gi.Probes(grid)
@@ -187,15 +198,17 @@ def test_probe_layout_odd_volume(gi, tiny):
     assert np.array_equal(pout.irr_quads(), gi.tiles_to_quads(gi_irr, grid.irr_res))
     ri, rd = o.probe_update(sc, grid, irr.astype(np.float32), dep.astype(np.float32), 64, 0.5, 50.0, 1, 7)
     ei, ed = rel_err(gi_irr, ri), rel_err(gi_dep, rd)
-    log(f"odd volume update: irr mean {ei.mean():.2e}; dep mean {ed.mean():.2e}")
+    log(f"odd volume update ({texel}): irr mean {ei.mean():.2e}; dep mean {ed.mean():.2e}")
     assert ei.mean() < 1e-4 and ed.mean() < 1e-4
 
 
-def test_probe_update(gi, tiny):
+@TEXELS
+def test_probe_update(gi, tiny, texel):
     cfg, sc, grid, irr, dep = tiny
     # start from the third fill pass so the recursion's Q_prev is non-trivial
     i2, d2 = o.fill_probes(sc, grid, sg.ProbeUpdate(fill_passes=2, fill_rays=64), seed=1)
     i2, d2 = i2.astype(np.float32), d2.astype(np.float32)
+    grid = dataclasses.replace(grid, texel=texel)
     ds = gi.DeviceScene(sc, cfg.grid_res)
     pin, pout = gi.Probes(grid), gi.Probes(grid)
     pin.load(i2, d2)
@@ -207,7 +220,7 @@ def test_probe_update(gi, tiny):
         assert np.array_equal(pout.dep_quads(), gi.tiles_to_quads(gi_dep, grid.dep_res))
         ri, rd = o.probe_update(sc, grid, i2, d2, 64, hyst, 50.0, 1, 5, slider=slider)
         ei, ed = rel_err(gi_irr, ri), rel_err(gi_dep, rd)
-        log(f"probe update h={hyst} slider={slider}: irr mean {ei.mean():.2e} max {ei.max():.2e}; "
+        log(f"probe update ({texel}) h={hyst} slider={slider}: irr mean {ei.mean():.2e} max {ei.max():.2e}; "
             f"dep mean {ed.mean():.2e} max {ed.max():.2e}")
         assert ei.mean() < 1e-4 and ed.mean() < 1e-4
         assert np.mean(ei > 1e-2) < 1e-3 and np.mean(ed > 1e-2) < 1e-3
@@ -279,11 +292,15 @@ def _check_chain(gi, cfg, sc, grid, irr, dep, W, H, frames, which):
     return dev_resid, s["resid"]
 
 
-@pytest.mark.parametrize("which", ["tiny", "hd_small"])
-def test_passes_shared_inputs(gi, request, which):
+@pytest.mark.parametrize("which,texel", [("tiny", "f32"), ("hd_small", "f32"), ("tiny", "f16"), ("hd_small", "f16")])
+def test_passes_shared_inputs(gi, request, which, texel):
+    """Every pass on the oracle's inputs, with the FP32 probe volume of the
+    workloads and with a binary16 one (each side reading the textures at that
+    precision)."""
     cfg, sc, grid, irr, dep = request.getfixturevalue(which)
+    grid = dataclasses.replace(grid, texel=texel)
     W, H = (64, 64) if which == "tiny" else (250, 141)
-    _check_chain(gi, cfg, sc, grid, irr, dep, W, H, 1 if which == "tiny" else 2, which)
+    _check_chain(gi, cfg, sc, grid, irr, dep, W, H, 1 if which == "tiny" else 2, f"{which} {texel}")
 
 
 @pytest.mark.parametrize("variant", ["biased", "no_bound", "tight_bound", "subsample", "fractional_cap"])

@@ -83,16 +83,26 @@ def test_gutters_make_fetch_continuous():
 
 def _f16(x):
     """binary16 rounding (numpy's float16 conversion), the precision of the
-    stored irradiance texels, back in float64"""
+    stored texels of a binary16 probe volume, back in float64"""
     return np.asarray(x, np.float64).astype(np.float16).astype(np.float64)
 
 
-def _grid(dims=(4, 3, 5), spacing=1.5):
-    return g.probe_grid(dims, (0.0, 0.0, 0.0), spacing)
+def _store(x, texel):
+    """a texel value as a probe volume of the given format stores it (the
+    FP32 volume: as given, the oracle keeping full precision)"""
+    return _f16(x) if texel == "f16" else np.asarray(x, np.float64)
 
 
-def test_query_equals_trilinear_when_weights_off():
-    grid = _grid()
+TEXELS = pytest.mark.parametrize("texel", ["f32", "f16"])
+
+
+def _grid(dims=(4, 3, 5), spacing=1.5, texel="f32"):
+    return g.probe_grid(dims, (0.0, 0.0, 0.0), spacing, texel=texel)
+
+
+@TEXELS
+def test_query_equals_trilinear_when_weights_off(texel):
+    grid = _grid(texel=texel)
     P = grid.count
     rng = np.random.default_rng(8)
     vals = rng.uniform(0.1, 3.0, (P, 3))
@@ -101,8 +111,8 @@ def test_query_equals_trilinear_when_weights_off():
     nx, ny, nz = grid.dims
     s = float(grid.spacing[0])
     axes = [(np.arange(n) + 0.5) * s for n in (nx, ny, nz)]
-    # irradiance texels are read at binary16 (numpy's float16 conversion)
-    grid_vals = _f16(vals).reshape(nz, ny, nx, 3).transpose(2, 1, 0, 3)
+    # irradiance texels are read at their storage precision
+    grid_vals = _store(vals, texel).reshape(nz, ny, nx, 3).transpose(2, 1, 0, 3)
     interp = RegularGridInterpolator(axes, grid_vals)
     pts = np.stack([rng.uniform(a[0], a[-1], 400) for a in axes], axis=1)
     nrm = _dirs(400, 9)
@@ -115,8 +125,9 @@ def test_query_equals_trilinear_when_weights_off():
     assert np.allclose(q_out, interp(clamp), atol=1e-12)
 
 
-def test_query_constant_textures_give_constant():
-    grid = _grid()
+@TEXELS
+def test_query_constant_textures_give_constant(texel):
+    grid = _grid(texel=texel)
     P = grid.count
     rng = np.random.default_rng(10)
     irr = np.zeros((P, (grid.irr_res + 2) ** 2, 3)) + np.array([0.7, 1.1, 2.3])
@@ -124,8 +135,9 @@ def test_query_constant_textures_give_constant():
     dep = np.concatenate([dep, dep ** 2 + rng.uniform(0, 0.5, dep.shape)], axis=2)
     pts = rng.uniform(0.0, 7.0, (300, 3))
     q = o.probe_query(grid, irr, dep, pts, _dirs(300, 3))
-    assert np.allclose(q, _f16([0.7, 1.1, 2.3]), atol=1e-12)
-    assert not np.allclose(q, [0.7, 1.1, 2.3], atol=1e-6)   # the texels' precision shows
+    assert np.allclose(q, _store([0.7, 1.1, 2.3], texel), atol=1e-12)
+    if texel == "f16":
+        assert not np.allclose(q, [0.7, 1.1, 2.3], atol=1e-6)   # the texels' precision shows
 
 
 def test_query_visibility_limits():
@@ -170,33 +182,37 @@ def _open_scene(prims=None, sky=(1.5, 0.5, 2.0)):
                    sky=np.asarray(sky, np.float32), eps=1e-3)
 
 
-def test_update_empty_space_under_sky():
+@TEXELS
+def test_update_empty_space_under_sky(texel):
     sky = np.array([1.5, 0.5, 2.0], np.float32)
     sc = _open_scene(sky=sky)
-    grid = _grid((2, 2, 2), 1.0)
+    grid = _grid((2, 2, 2), 1.0, texel)
     irr, dep = g.empty_probe_textures(grid)
     i2, d2 = o.probe_update(sc, grid, irr, dep, rays=128, hysteresis=0.0, sharpness=50.0, seed=3,
                             frame=0)
     assert np.allclose(i2, sky.astype(np.float64), rtol=1e-14, atol=0)
-    # depth texels: binary16 mean d_max and variance 0, mean square rebuilt
-    assert np.allclose(d2[..., 0], _f16(grid.d_max), rtol=1e-14)
-    assert np.allclose(d2[..., 1], _f16(grid.d_max) ** 2, rtol=1e-13)
+    # depth texels: mean d_max and variance 0 (binary16: mean square rebuilt
+    # from the stored mean)
+    assert np.allclose(d2[..., 0], _store(grid.d_max, texel), rtol=1e-14)
+    assert np.allclose(d2[..., 1], _store(grid.d_max, texel) ** 2, rtol=1e-13)
 
 
-def test_update_plane_fixed_point_gives_pi_L():
+@TEXELS
+def test_update_plane_fixed_point_gives_pi_L(texel):
     L = np.array([0.8, 1.3, 2.1], np.float32)
     plane = g.prim_records([1], [[0.0, -1.0, 0.0]], [[1000.0, 1.0, 1000.0]], [[1.0, 1.0, 1.0]],
                            [[0, 0, 0]])
     sc = _open_scene(plane, sky=L)
-    grid = g.probe_grid((3, 3, 3), (-1.5, 0.0, -1.5), 1.0)
+    grid = g.probe_grid((3, 3, 3), (-1.5, 0.0, -1.5), 1.0, texel=texel)
     irr, dep = g.empty_probe_textures(grid)
     irr[..., :3] = L
     dep[..., 0], dep[..., 1] = 1.0, 1.0
     i2, d2 = o.probe_update(sc, grid, irr, dep, rays=64, hysteresis=0.0, sharpness=50.0, seed=1,
                             frame=0)
-    # the stored texels are L at binary16: the sky rays bring L, the plane
-    # rays the stored value, and every mean of the two rounds back to it
-    Lh = _f16(L)
+    # the stored texels are L at the storage precision: the sky rays bring
+    # L, the plane rays the stored value, and every mean of the two rounds
+    # back to it
+    Lh = _store(L, texel)
     assert np.allclose(i2, Lh, rtol=1e-12)
     # query on the plane: Q = E/pi = L (as stored), i.e. E = pi L
     pts = np.array([[0.1, 0.0, 0.2], [-0.7, 0.0, 0.4]])
@@ -204,10 +220,11 @@ def test_update_plane_fixed_point_gives_pi_L():
     assert np.allclose(math.pi * q, math.pi * Lh, rtol=1e-12)
 
 
-def test_update_hysteresis_geometric():
+@TEXELS
+def test_update_hysteresis_geometric(texel):
     sky = np.array([2.0, 2.0, 2.0], np.float32)
     sc = _open_scene(sky=sky)
-    grid = _grid((2, 2, 2), 1.0)
+    grid = _grid((2, 2, 2), 1.0, texel)
     irr, dep = g.empty_probe_textures(grid)
     irr = irr[..., :3].astype(np.float64) + 0.5
     dep = dep.astype(np.float64)
@@ -215,8 +232,8 @@ def test_update_hysteresis_geometric():
     expect = 0.5
     for k in range(1, 6):
         irr, dep = o.probe_update(sc, grid, irr, dep, 64, a, 50.0, 1, k)
-        # a^k 0.5 + (1 - a^k) 2, each step's blend stored at binary16
-        expect = float(_f16(a * expect + (1 - a) * 2.0))
+        # a^k 0.5 + (1 - a^k) 2, each step's blend stored at the storage precision
+        expect = float(_store(a * expect + (1 - a) * 2.0, texel))
         assert np.allclose(irr, expect, rtol=1e-12)
     assert abs(expect - (a ** 5 * 0.5 + (1 - a ** 5) * 2.0)) < 2e-3
 
@@ -334,12 +351,13 @@ def test_query_backface_prefers_probes_in_front():
         assert q_back == pytest.approx(w[-1] / sum(w), rel=1e-12)
 
 
-def test_query_chebyshev_weight():
+@TEXELS
+def test_query_chebyshev_weight(texel):
     # two probes along x; probe 0 stores depth moments (mu, mu^2 + s2) in every
     # texel, probe 1 sees far.  The query's value recovers probe 0's
     # visibility weight, which must be the cubed one-sided Chebyshev bound
     # s2 / (s2 + (r - mu)^2) when r > mu, and 1 when r <= mu.
-    grid = g.probe_grid((2, 1, 1), (0, 0, 0), 2.0)
+    grid = g.probe_grid((2, 1, 1), (0, 0, 0), 2.0, texel=texel)
     nd = (grid.dep_res + 2) ** 2
     irr = np.zeros((2, (grid.irr_res + 2) ** 2, 3))
     irr[1] = 1.0
@@ -355,13 +373,14 @@ def test_query_chebyshev_weight():
         t0 = 1.0 - t1
         v0 = t1 * (1.0 - q) / (t0 * q)
         r = xq - 1.0
-        # the texels hold the mean and the variance at binary16
-        mu, s2 = float(_f16(mu)), float(_f16((mu * mu + s2) - mu * mu))
+        # the texels hold the mean and the variance at the storage precision
+        mu, s2 = float(_store(mu, texel)), float(_store((mu * mu + s2) - mu * mu, texel))
         cheb = 1.0 if r <= mu else (s2 / (s2 + (r - mu) ** 2)) ** 3
         assert v0 == pytest.approx(max(cheb, 1e-6), rel=1e-9), (mu, s2, xq)
 
 
-def test_distance_heuristic_single_ray():
+@TEXELS
+def test_distance_heuristic_single_ray(texel):
     """Emission heuristic of the probe update (Sec. 3.2): a probe at the
     centre of a cube room whose walls emit L and reflect nothing, one update
     ray of length t: every irradiance texel facing the ray holds L (t / (t +
@@ -372,7 +391,7 @@ def test_distance_heuristic_single_ray():
     sc = g.Scene(prims=np.zeros((0, 16), np.float32), has_room=True, room_lo=np.zeros(3, np.float32),
                  room_hi=np.full(3, 8.0, np.float32), wall_albedo=np.zeros(3, np.float32),
                  sky=np.zeros(3, np.float32), eps=8e-4, wall_emit=L)
-    grid = g.probe_grid((1, 1, 1), (0.0, 0.0, 0.0), 8.0)
+    grid = g.probe_grid((1, 1, 1), (0.0, 0.0, 0.0), 8.0, texel=texel)
     N = grid.irr_res
     Ld = L.astype(np.float64)
     for frame in range(6):
@@ -390,7 +409,7 @@ def test_distance_heuristic_single_ray():
                 for tx in range(N):
                     nt = o.oct_decode([(tx + 0.5) / N, (ty + 0.5) / N])
                     if np.dot(nt, w) > 1e-9:
-                        assert np.allclose(T[ty, tx], _f16(Ld * factor), rtol=1e-12), (frame, mu_b, s)
+                        assert np.allclose(T[ty, tx], _store(Ld * factor, texel), rtol=1e-12), (frame, mu_b, s)
                         facing += 1
                     elif np.dot(nt, w) < -1e-9:
                         assert np.all(T[ty, tx] == 0.0)
@@ -398,7 +417,8 @@ def test_distance_heuristic_single_ray():
             assert facing > 10
 
 
-def test_distance_heuristic_reads_the_backward_direction():
+@TEXELS
+def test_distance_heuristic_reads_the_backward_direction(texel):
     """Same room; the probe's depth tile says 'far' (beyond the cell) for
     directions with z > 0 and 1.5 for z < 0, so the factor tells which
     direction was read: the backward one, -w."""
@@ -406,7 +426,7 @@ def test_distance_heuristic_reads_the_backward_direction():
     sc = g.Scene(prims=np.zeros((0, 16), np.float32), has_room=True, room_lo=np.zeros(3, np.float32),
                  room_hi=np.full(3, 8.0, np.float32), wall_albedo=np.zeros(3, np.float32),
                  sky=np.zeros(3, np.float32), eps=8e-4, wall_emit=L)
-    grid = g.probe_grid((1, 1, 1), (0.0, 0.0, 0.0), 8.0)
+    grid = g.probe_grid((1, 1, 1), (0.0, 0.0, 0.0), 8.0, texel=texel)
     N, Nd = grid.irr_res, grid.dep_res
     irr, dep = g.empty_probe_textures(grid)
     tile = np.zeros((Nd + 2, Nd + 2, 2))
@@ -429,7 +449,7 @@ def test_distance_heuristic_reads_the_backward_direction():
         T = i2.reshape(N + 2, N + 2, 3)[1:N + 1, 1:N + 1]
         best = max(((ty, tx) for ty in range(N) for tx in range(N)),
                    key=lambda c: np.dot(o.oct_decode([(c[1] + 0.5) / N, (c[0] + 0.5) / N]), w))
-        assert np.allclose(T[best], _f16(L.astype(np.float64) * factor), rtol=1e-12), (frame, far)
+        assert np.allclose(T[best], _store(L.astype(np.float64) * factor, texel), rtol=1e-12), (frame, far)
         seen[far] += 1
     assert seen[True] >= 3 and seen[False] >= 3
 
@@ -452,8 +472,9 @@ def _lobe_means(nt, s, fn, nu=1000, nph=1000):
     return float(f.mean()), float((f * f).mean())
 
 
+@TEXELS
 @pytest.mark.parametrize("sharp", [2.0, 50.0])
-def test_update_depth_moments_above_plane(sharp):
+def test_update_depth_moments_above_plane(sharp, texel):
     """Both depth moments of Sec. 3.2's mean visibility (the Chebyshev test
     reads their difference as a variance).  Probes at height h above an
     infinite plane: a ray of direction w meets the plane at h / (-w_y), so the
@@ -464,7 +485,7 @@ def test_update_depth_moments_above_plane(sharp):
     plane = g.prim_records([1], [[0.0, -1.0, 0.0]], [[1000.0, 1.0, 1000.0]], [[0.0, 0.0, 0.0]],
                            [[0, 0, 0]])
     sc = _open_scene(plane, sky=(0.0, 0.0, 0.0))
-    grid = g.probe_grid((8, 1, 8), (-4.0, 0.5, -4.0), 1.0)
+    grid = g.probe_grid((8, 1, 8), (-4.0, 0.5, -4.0), 1.0, texel=texel)
     h, D = 1.0, float(grid.d_max)
     irr, dep = g.empty_probe_textures(grid)
     _, d2 = o.probe_update(sc, grid, irr, dep, 4096, 0.0, sharp, 11, 0)
@@ -486,10 +507,10 @@ def test_update_depth_moments_above_plane(sharp):
                 m = got[:, k].mean()
                 se = got[:, k].std(ddof=1) / math.sqrt(len(got))
                 if se < 1e-12:                                   # all sky: d_max^k, stored as
-                    assert m == pytest.approx(_f16(D) ** (k + 1), rel=1e-9), (nt, k, m, want)
+                    assert m == pytest.approx(_store(D, texel) ** (k + 1), rel=1e-9), (nt, k, m, want)
                     continue
-                # quadrature error at this resolution is below 1e-5 relative; the
-                # stored mean and variance are binary16 (relative step 2^-11)
+                # quadrature error at this resolution is below 1e-5 relative; a
+                # binary16 volume stores the mean and variance to a relative step of 2^-11
                 z = (m - want) / se
                 worst = max(worst, abs(z))
                 assert abs(m - want) < 5.0 * se + (1e-5 + 2.0 ** -10) * want, (nt, k, m, want, se)
@@ -520,12 +541,12 @@ def test_round_half_matches_numpy_float16():
 
 
 def test_update_stores_binary16_and_query_reads_binary16():
-    """The update stores irradiance texels that are binary16 values; the
-    query reads a caller's arbitrary tile at that precision (a tile of
-    1 + 2^-12, which rounds to 1, queries as exactly 1)."""
+    """In a binary16 volume the update stores irradiance texels that are
+    binary16 values; the query reads a caller's arbitrary tile at that
+    precision (a tile of 1 + 2^-12, which rounds to 1, queries as exactly 1)."""
     sky = np.array([0.3, 0.7, 1.9], np.float32)
     sc = _open_scene(sky=sky)
-    grid = _grid((2, 2, 2), 1.0)
+    grid = _grid((2, 2, 2), 1.0, "f16")
     irr, dep = g.empty_probe_textures(grid)
     i2, d2 = o.probe_update(sc, grid, irr, dep, rays=32, hysteresis=0.25, sharpness=50.0, seed=5, frame=0)
     # empty space under the sky: every texel is 0.75 L, stored at binary16
@@ -535,3 +556,20 @@ def test_update_stores_binary16_and_query_reads_binary16():
     tile = np.full_like(i2, 1.0 + 2.0 ** -12)
     q = o.probe_query(grid, tile, d2, [[0.7, 0.6, 0.8]], [[0.0, 1.0, 0.0]])
     assert np.array_equal(q, [[1.0, 1.0, 1.0]])
+
+
+def test_fp32_volume_keeps_full_precision():
+    """In an FP32 volume the oracle keeps texels at full precision: the
+    same update stores 0.75 L (to the rounding of its ray sums), and the
+    tile of 1 + 2^-12 queries as itself."""
+    sky = np.array([0.3, 0.7, 1.9], np.float32)
+    sc = _open_scene(sky=sky)
+    grid = _grid((2, 2, 2), 1.0, "f32")
+    irr, dep = g.empty_probe_textures(grid)
+    i2, d2 = o.probe_update(sc, grid, irr, dep, rays=32, hysteresis=0.25, sharpness=50.0, seed=5, frame=0)
+    want = 0.75 * sky.astype(np.float64)
+    assert np.allclose(i2, want, rtol=1e-14, atol=0)
+    assert not np.allclose(i2, _f16(want), rtol=1e-6)
+    tile = np.full_like(i2, 1.0 + 2.0 ** -12)
+    q = o.probe_query(grid, tile, d2, [[0.7, 0.6, 0.8]], [[0.0, 1.0, 0.0]])
+    assert np.allclose(q, 1.0 + 2.0 ** -12, rtol=1e-15, atol=0)
