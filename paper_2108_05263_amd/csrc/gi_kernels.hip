@@ -615,9 +615,10 @@ __global__ void __launch_bounds__(kBlock, 4)
                         wi = phat * rcp(mixb * pA + mixl * light_pdf(sc, prim));
                     if (i == 0 && G > pp.g_max && pA > 0.0f) { const V3 q = ((G - pp.g_max) * rcp(pA)) * f; sel[3] = make_float4(q.x, q.y, q.z, 0.0f); }
                 } else {
-                    // (the query unrolled over two corner pairs is the faster form here)
+                    // (binary16 records: the query unrolled over two corner pairs is the
+                    // faster form here; FP32 records: one pair, which needs no spills)
                     L = (use_cache && i < pp.M) ? radiance_cached(sc, prim, ws.q[i * npx + p])
-                                                : radiance_toward<2, TEX>(sc, pr, prim, y, ny, g.pos);
+                                                : radiance_toward<TEX == kTexF16 ? 2 : 1, TEX>(sc, pr, prim, y, ny, g.pos);
                     float G = cx * cy * rcp(d2);
                     float fl = lum(rho_pi * L);
                     float iG = rcp(G);
@@ -938,8 +939,9 @@ __device__ V3 shade_glossy(const gi_scene &sc, const G &acc, const gi_probes &pr
 // GLOSSY: f(x) replaces rho_x/pi and the fresh radiance follows the specular
 // recursion, started with the footprint of the segment x -> y (density of
 // the BSDF mixture at x) and a_0 c = c |x_0 - x|^2 / (4 pi cos) from the camera.
+// The Lambertian kernel is held to 5 waves per SIMD (no spills).
 template <bool LDS, bool WS, bool GLOSSY, int TEX>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, GLOSSY ? 1 : 5)
     k_shade(gi_scene sc, gi_gbuffer gb, gi_probes pr, gi_reservoirs res, const float4 *resid, gi_params pp,
             float4 *img, const float4 *q, gi_mlp mlp, uint64_t seed, uint32_t frame)
 {
