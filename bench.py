@@ -330,8 +330,9 @@ def reference_image(gi, torch, r, gb, spp, seed, chunk=32):
 
 
 def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
-    """Frames 0..frames-1 of each form (probe target; learned cache in BF16 /
-    FP8, always the target, trained online from frame 0) for render seeds
+    """Frames 0..frames-1 of each form (probe target from FP32 and from
+    binary16 texels; learned cache in BF16 / FP8, always the target, trained
+    online from frame 0) for render seeds
     1..n_seeds; the last n_eval frames are scored against path-traced
     references of the same camera: MSE over pixels and channels, relative
     MSE (err^2 / (ref^2 + 0.01)) and MAPE (|err| / (ref + 0.01)), averaged
@@ -357,6 +358,8 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
         # the precision sweep: half-precision G-buffer normals and albedo, alone and with FP8 inference
         forms += (("probe, f16 G-buffer", None, "f16"), ("fp8, f16 G-buffer", "fp8", "f16"))
     forms = tuple((name, mlp, gbf, cfg) for name, mlp, gbf in forms)
+    # storage precision of the probe textures: the same probe target from binary16 texels
+    forms += (("probe, binary16 texels", None, "f32", dataclasses.replace(cfg, probe_texel="f16")),)
     if cfg.glossy_frac > 0.0:
         # glossy workload: the specular recursion of shading at the workload's threshold,
         # switched off (c = 0: every glossy sample read from the probes) and deeper (c = 1);
