@@ -125,12 +125,14 @@ def test_passes_full_size_sampled(gi, name):
     assert e.mean() < 1e-4
 
 
-def test_probe_update_uhd_sampled(gi):
+@pytest.mark.parametrize("texel", ["f32", "f16"])
+def test_probe_update_uhd_sampled(gi, texel):
     """The 4K probe volume (64x16x64 probes, 256 rays, 1024 primitives on the
     grid): a fill pass from zero textures, then a per-frame update at
     hysteresis 0.97 from random textures, and the same update with the
-    distance heuristic of Sec. 3.2 (slider 0.8), checked on 64 sampled probes."""
-    cfg = sg.CONFIGS["uhd"]
+    distance heuristic of Sec. 3.2 (slider 0.8), checked on 64 sampled probes
+    (FP32 and binary16 texels)."""
+    cfg = dataclasses.replace(sg.CONFIGS["uhd"], probe_texel=texel)
     sc = sg.make_scene(cfg)
     grid = sg.make_probe_grid(cfg)
     u = cfg.probe_update
@@ -149,7 +151,7 @@ def test_probe_update_uhd_sampled(gi):
         oi, od = o.probe_update(sc, grid, irr[..., :3], dep, u.rays, hyst, u.sharpness, 1, frame, probes=sel,
                                 slider=slider)
         ei, ed = rel_err(gi_irr[sel], oi[sel]), rel_err(gi_dep[sel], od[sel])
-        log(f"uhd probe update ({label}): irr mean {ei.mean():.2e} max {ei.max():.2e}; "
+        log(f"uhd probe update ({texel}, {label}): irr mean {ei.mean():.2e} max {ei.max():.2e}; "
             f"dep mean {ed.mean():.2e} max {ed.max():.2e}")
         assert ei.mean() < 1e-4 and ed.mean() < 1e-4
         assert np.mean(ei > 1e-2) < 1e-3 and np.mean(ed > 1e-2) < 1e-3

@@ -467,13 +467,16 @@ def test_spatial_neighbour_count_extremes(gi, tiny, k):
         log(f"k={k} spatial{sp}: {res}")
 
 
-@pytest.mark.parametrize("variant", ["plain", "emitters", "subsample"])
+@pytest.mark.parametrize("variant", ["plain", "emitters", "subsample", "binary16"])
 def test_initial_full_hd_sampled(gi, variant):
     """The 1920x1080 workload's G-buffer and initial pass in the launch
     configuration the benchmark times, checked on 1500 sampled pixels; also
     with emitter-sampled candidates (M = 28 + 4) and with candidate
-    subsampling (n = 2), the options of Sec. 3.1 step 1 and Sec. 6."""
+    subsampling (n = 2), the options of Sec. 3.1 step 1 and Sec. 6, and
+    from binary16 probe textures."""
     cfg = sg.CONFIGS["hd"]
+    if variant == "binary16":
+        cfg = dataclasses.replace(cfg, probe_texel="f16")
     sc = sg.make_scene(cfg)
     grid = sg.make_probe_grid(cfg)
     upd = sg.ProbeUpdate(rays=32, fill_passes=2, fill_rays=32)
@@ -493,7 +496,7 @@ def test_initial_full_hd_sampled(gi, variant):
     rr = gi.Reservoirs(W, H)
     resid = torch.zeros(W * H, 4, device="cuda")
     pr = {"plain": cfg.params, "emitters": dataclasses.replace(cfg.params, M=28, M_light=4),
-          "subsample": dataclasses.replace(cfg.params, subsample=2)}[variant]
+          "subsample": dataclasses.replace(cfg.params, subsample=2), "binary16": cfg.params}[variant]
     gi.resample_initial(r.dscene, r.gb[0], r.probe, pr, rr, resid, 1, 0)
     ores, oresid = o.resample_initial(sc, W, H, ogb, grid, irr, dep, pr, 1, 0, pixels=pix)
     g = rr.to_records()[pix]
