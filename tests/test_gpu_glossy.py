@@ -90,10 +90,12 @@ def test_gbuffer_glossy_layer(gi, gtiny):
     assert np.allclose(np.asarray(g.c.eye), cam.eye)
 
 
-def test_probe_update_glossy(gi, gtiny):
+@pytest.mark.parametrize("texel", ["f32", "f16"])
+def test_probe_update_glossy(gi, gtiny, texel):
     cfg, sc, grid, irr, dep = gtiny
     i2, d2 = o.fill_probes(sc, grid, sg.ProbeUpdate(fill_passes=2, fill_rays=64), seed=1)
     i2, d2 = i2.astype(np.float32), d2.astype(np.float32)
+    grid = dataclasses.replace(grid, texel=texel)
     ds = gi.DeviceScene(sc, cfg.grid_res)
     pin, pout = gi.Probes(grid), gi.Probes(grid)
     pin.load(i2, d2)
@@ -102,14 +104,17 @@ def test_probe_update_glossy(gi, gtiny):
         gi_irr, gi_dep = pout.tiles()
         ri, rd = o.probe_update(sc, grid, i2, d2, 64, hyst, 50.0, 1, 5)
         ei, ed = rel_err(gi_irr, ri), rel_err(gi_dep, rd)
-        log(f"glossy probe update h={hyst}: irr mean {ei.mean():.2e} max {ei.max():.2e}; dep mean {ed.mean():.2e}")
+        log(f"glossy probe update ({texel}) h={hyst}: irr mean {ei.mean():.2e} max {ei.max():.2e}; dep mean {ed.mean():.2e}")
         assert ei.mean() < 1e-4 and ed.mean() < 1e-4
         assert np.mean(ei > 1e-2) < 1e-3 and np.mean(ed > 1e-2) < 1e-3
 
 
-@pytest.mark.parametrize("which", ["gtiny", "ghd_small"])
-def test_glossy_passes_shared_inputs(gi, request, which):
+@pytest.mark.parametrize("which,texel", [("gtiny", "f32"), ("ghd_small", "f32"), ("gtiny", "f16")])
+def test_glossy_passes_shared_inputs(gi, request, which, texel):
+    """Every glossy pass on the oracle's inputs, with FP32 probe textures and
+    (on the small room) binary16 ones."""
     cfg, sc, grid, irr, dep = request.getfixturevalue(which)
+    grid = dataclasses.replace(grid, texel=texel)
     W, H = (64, 64) if which == "gtiny" else (250, 141)
     frames = 1 if which == "gtiny" else 2
     seq = o.Sequence(sc, grid, irr, dep, cfg.params, 1)
