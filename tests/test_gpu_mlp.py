@@ -356,10 +356,10 @@ def test_mlp_make_batch(gi, tiny):
     assert et[~far].mean() <= 1e-4 and eq.mean() <= 1e-4
 
 
-def _cache_setup(gi, tiny, precision="bf16", mode="always"):
+def _cache_setup(gi, tiny, precision="bf16", mode="always", texel="f32"):
     cfg, sc, grid, irr, dep, W, H, gb, res, resid = tiny
     ds = gi.DeviceScene(sc, cfg.grid_res)
-    probes = gi.Probes(grid)
+    probes = gi.Probes(dataclasses.replace(grid, texel=texel))
     probes.load(irr, dep)
     g = gi.GBuffer(W, H)
     g.load_records(gb)
@@ -369,10 +369,13 @@ def _cache_setup(gi, tiny, precision="bf16", mode="always"):
     return ds, probes, g, m, params, lo, hi
 
 
-@pytest.mark.parametrize("m_light", [0, 3])
-def test_initial_and_shade_with_cache(gi, tiny, m_light):
+@pytest.mark.parametrize("m_light,texel", [(0, "f32"), (3, "f32"), (3, "f16")])
+def test_initial_and_shade_with_cache(gi, tiny, m_light, texel):
+    """The cache as the target; with emitter candidates, whose radiance the
+    probes still give (also from binary16 probe textures)."""
     cfg, sc, grid, irr, dep, W, H, gb, res, resid = tiny
-    ds, probes, g, m, params, lo, hi = _cache_setup(gi, tiny)
+    ds, probes, g, m, params, lo, hi = _cache_setup(gi, tiny, texel=texel)
+    grid = dataclasses.replace(grid, texel=texel)
     pr = dataclasses.replace(cfg.params, M_light=m_light)
     out = gi.Reservoirs(W, H)
     gresid = torch.zeros(W * H, 4, device="cuda")
