@@ -509,7 +509,7 @@ void o_oct_decode(const double *uv, double *v)
 }
 
 /* IEEE binary16 rounding (nearest, ties to even) of a double, returned as a
- * double: the storage precision of the probe irradiance texels.  11
+ * double: the storage precision of a binary16 probe volume's texels.  11
  * significant bits for |x| >= 2^-14, steps of 2^-24 below (subnormals),
  * infinity from 65520 up (the tie between 65504 and 2^16 goes to the even
  * 2^16, which overflows). */

@@ -301,7 +301,7 @@ def tile_fetch(tile, N, v) -> np.ndarray:
 
 def round_half(x) -> float:
     """IEEE binary16 rounding of x (nearest, ties to even), as a float: the
-    storage precision of probe irradiance texels."""
+    storage precision of a binary16 probe volume's texels."""
     return lib().o_round_half(float(x))
 
 
