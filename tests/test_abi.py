@@ -40,6 +40,23 @@ def test_library_built_from_these_sources(gi):
     assert gi.load().gi_build_hash().decode() == build.source_hash() == build.built_hash()
 
 
+def test_binding_fails_loudly_without_the_library(gi, monkeypatch):
+    """No fallback: with the library missing, or built from other sources,
+    loading raises instead of running anything else."""
+    from paper_2108_05263_amd import build
+    monkeypatch.setattr(gi, "_lib", None)
+    monkeypatch.setattr(gi, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libgi.so"))
+    with pytest.raises(gi.GiError, match="not built"):
+        gi.load()
+    monkeypatch.undo()
+    monkeypatch.setattr(gi, "_lib", None)
+    monkeypatch.setattr(build, "source_hash", lambda *a, **k: "0" * 16)
+    with pytest.raises(gi.GiError, match="other sources"):
+        gi.load()
+    monkeypatch.undo()
+    assert gi.load() is not None
+
+
 def test_status_strings(gi):
     lib = gi.load()
     for s in range(7):
