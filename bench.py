@@ -37,6 +37,8 @@ HBM_PEAK_GBS = 8000.0
 #            records are re-reads of the same buffer)
 #   shade    reads G-buffer 52 + reservoir 56 + resid 12; writes 12 = 132
 ALGO_BYTES = {"gbuffer": 56, "initial": 104, "temporal": 236, "spatial": 152, "shade": 132}
+# learned-cache training options set from the command line (empty: the binding's defaults)
+MLP_OPTS = {}
 # probe-record bytes one probe fetch reads (irradiance + depth quad) per texel format
 PROBE_RECORD_BYTES = {"f32": 48 + 32, "f16": 24 + 16}
 
@@ -56,6 +58,10 @@ def parse():
                     help="skip the extra timing of the same frames from binary16 probe textures")
     ap.add_argument("--mlp-train-frames", type=int, default=64,
                     help="untimed frames of online training before the learned-cache forms are timed")
+    ap.add_argument("--mlp-ema", type=float, default=None,
+                    help="decay of the parameter average the cache's inference uses (default: the binding's)")
+    ap.add_argument("--mlp-steps", type=int, default=None,
+                    help="Adam steps per frame over the frame's training batch (default: the binding's)")
     ap.add_argument("--mlp-only", choices=["bf16", "fp8"], default=None,
                     help="time only this learned-cache form (for profiling)")
     ap.add_argument("--quality", action="store_true",
@@ -236,7 +242,7 @@ def mlp_form(gi, sg, torch, cfg, precision, steps, warmup, mode="always", train_
     judge (its error against the probe query) decide per frame, falling back
     to the probe query.  train_frames untimed frames of online training run
     before the warm-up (the cache in steady state)."""
-    r = gi.Renderer(cfg, seed=1, mlp=precision, mlp_mode=mode)
+    r = gi.Renderer(cfg, seed=1, mlp=precision, mlp_mode=mode, **MLP_OPTS)
     r.fill_probes()
     stream = torch.cuda.current_stream()
     keys = {"trace_gbuffer": "gbuffer", "resample_initial_mlp": "initial", "resample_temporal": "temporal",
@@ -352,7 +358,8 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
         print(f"reference frame {f} done", file=sys.stderr, flush=True)
     del base
     out = {"config": cfg.name, "frames": frames, "eval_frames": [eval_frames[0], eval_frames[-1]],
-           "seeds": n_seeds, "ref_spp": ref_spp, "ref_noise_mse": sum(noise) / len(noise), "forms": {}}
+           "seeds": n_seeds, "ref_spp": ref_spp, "ref_noise_mse": sum(noise) / len(noise),
+           "mlp_options": dict(MLP_OPTS), "forms": {}}
     forms = (("probe", None, "f32"), ("bf16", "bf16", "f32"), ("fp8", "fp8", "f32"))
     if cfg.name == "uhd":
         # the precision sweep: half-precision G-buffer normals and albedo, alone and with FP8 inference
@@ -377,7 +384,8 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
         s1 = {f: torch.zeros_like(refs[f]) for f in eval_frames}
         s2 = {f: torch.zeros_like(refs[f]) for f in eval_frames}
         for seed in range(1, n_seeds + 1):
-            r = gi.Renderer(fcfg, seed=seed, mlp=mlp, mlp_mode="always", gb_format=gbf)
+            r = gi.Renderer(fcfg, seed=seed, mlp=mlp, mlp_mode="always", gb_format=gbf,
+                            **(MLP_OPTS if mlp is not None else {}))
             r.fill_probes()
             m = {"mse": 0.0, "relmse": 0.0, "mape": 0.0}
             for f in range(frames):
@@ -656,6 +664,10 @@ def main():
     from paper_2108_05263_amd import scenegen as sg
 
     cfg = sg.CONFIGS[args.config]
+    if args.mlp_ema is not None:
+        MLP_OPTS["mlp_ema"] = args.mlp_ema
+    if args.mlp_steps is not None:
+        MLP_OPTS["mlp_steps"] = args.mlp_steps
     torch.cuda.set_device(0)
     if args.quality:
         print(json.dumps({"quality": quality(gi, sg, torch, cfg, args.quality_frames, args.quality_eval,
