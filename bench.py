@@ -432,6 +432,8 @@ def quality(gi, sg, torch, cfg, frames, n_eval, ref_spp, n_seeds):
 # rocprofv3 runs behind the committed profiles/ summaries
 # --------------------------------------------------------------------------
 PROBE_INITIAL = "k_initial<true, false, false, false, 0>"    # the probe form's initial pass (scene in LDS, FP32 texels)
+# the probe form's other resampling kernels of the 1080p workload (scene in LDS, FP32 texels)
+REUSE_KERNELS = ("k_temporal<true, false>", "k_spatial<true, false, 5>", "k_shade<true, false, false, 0>")
 SQ_SETS = {"sq1": "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU "
                   "SQ_ACTIVE_INST_LDS SQ_INSTS_VMEM_RD",
            "sq2": "SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_ACTIVE_INST_ANY SQ_THREAD_CYCLES_VALU TCC_HIT_sum "
@@ -554,6 +556,35 @@ def summarize_profiles(outdir, ms_initial=None):
         with open(os.path.join(prof, "k_initial_hd_sq_counters.json"), "w") as fh:
             json.dump(rec, fh, indent=1)
         written.append("k_initial_hd_sq_counters.json")
+    # SQ counters of the reuse passes and shading from the same runs (what bounds them)
+    kt_avg = {}
+    for r in _csv_rows(os.path.join(outdir, "kt"), "kernel_stats.csv"):
+        kt_avg[_short(r["Name"])] = float(r["AverageNs"]) * 1e-6
+    reuse = {"kernel_sources": sha_r, "workload": "hd 1920x1080, FP32 probe texels",
+             "commands": [cmds[k] for k in SQ_SETS],
+             "note": "per-dispatch averages summed over the chip; issue fraction = SQ_INSTS_VALU over the "
+                     "kernel-trace average duration x 614.4 G wave-instructions/s; active lanes = "
+                     "SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU", "kernels": {}}
+    for kname in REUSE_KERNELS:
+        rec_k = {}
+        for k in SQ_SETS:
+            for c, v in _counters(os.path.join(outdir, k), kname).items():
+                rec_k[c] = sum(v) / len(v)
+        if "SQ_INSTS_VALU" not in rec_k:
+            continue
+        ms = kt_avg.get(kname)
+        if ms:
+            rec_k["kernel_trace_avg_ms"] = ms
+            rec_k["valu_issue_frac"] = rec_k["SQ_INSTS_VALU"] / (ms * 1e-3) / (VALU_PEAK_GINST * 1e9)
+        if "SQ_ACTIVE_INST_VALU" in rec_k:
+            rec_k["active_lanes_per_valu_instruction"] = rec_k["SQ_THREAD_CYCLES_VALU"] / rec_k["SQ_ACTIVE_INST_VALU"]
+        if "TCC_HIT_sum" in rec_k:
+            rec_k["l2_hit_rate"] = rec_k["TCC_HIT_sum"] / (rec_k["TCC_HIT_sum"] + rec_k["TCC_MISS_sum"])
+        reuse["kernels"][kname] = rec_k
+    if reuse["kernels"]:
+        with open(os.path.join(prof, "k_reuse_hd_sq_counters.json"), "w") as fh:
+            json.dump(reuse, fh, indent=1)
+        written.append("k_reuse_hd_sq_counters.json")
     # MFMA counters of the inference kernels (full-frame dispatches: the most MFMA instructions)
     lines = ["# rocprofv3 counters of the inference kernels, 1920x1080 workload (hd): one frame's candidates",
              f"# kernel sources: {sha_m} (sha256 prefix of {', '.join(KERNEL_SOURCES['mlp'])})",

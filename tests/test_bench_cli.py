@@ -28,6 +28,10 @@ def test_committed_profiles_match_the_kernel_sources():
     for what in ("traffic", "sq_counters"):
         with open(os.path.join(ROOT, "profiles", f"k_initial_hd_{what}.json")) as fh:
             assert json.load(fh)["source_sha"] == sha, what
+    with open(os.path.join(ROOT, "profiles", "k_reuse_hd_sq_counters.json")) as fh:
+        reuse = json.load(fh)
+    assert reuse["kernel_sources"] == sha
+    assert set(reuse["kernels"]) == set(bench.REUSE_KERNELS)
     for name, h in (("k_initial_hd_kernel_stats.txt", sha), ("k_mlp_infer_hd_kernel_stats.txt", sha_m),
                     ("k_mlp_infer_hd_mfma_counters.txt", sha_m)):
         with open(os.path.join(ROOT, "profiles", name)) as fh:
