@@ -573,3 +573,22 @@ def test_fp32_volume_keeps_full_precision():
     tile = np.full_like(i2, 1.0 + 2.0 ** -12)
     q = o.probe_query(grid, tile, d2, [[0.7, 0.6, 0.8]], [[0.0, 1.0, 0.0]])
     assert np.allclose(q, 1.0 + 2.0 ** -12, rtol=1e-15, atol=0)
+
+
+def test_binary16_blend_below_half_a_step_is_lost():
+    """The cost of binary16 texels under hysteresis: a stored irradiance of 1
+    blended at h = 0.97 toward 1.01 moves by 3e-4, less than half the binary16
+    step at 1 (2^-11), so a binary16 volume keeps 1 while an FP32 volume
+    stores 0.97 + 0.03 x 1.01."""
+    sky = np.array([1.01, 1.01, 1.01], np.float32)
+    sc = _open_scene(sky=sky)
+    for texel in ("f32", "f16"):
+        grid = _grid((2, 2, 2), 1.0, texel)
+        irr, dep = g.empty_probe_textures(grid)
+        irr = irr[..., :3].astype(np.float64) + 1.0
+        i2, _ = o.probe_update(sc, grid, irr, dep.astype(np.float64), 64, 0.97, 50.0, 1, 0)
+        want = 0.97 + 0.03 * float(sky[0])
+        if texel == "f16":
+            assert np.all(i2 == 1.0)
+        else:
+            assert np.allclose(i2, want, rtol=1e-12) and np.all(i2 > 1.0)
